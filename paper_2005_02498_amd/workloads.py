@@ -1,0 +1,218 @@
+"""Seeded synthetic inputs: FCC glide-loop ensembles.
+
+This module only *draws* inputs. It holds none of the force, mobility or
+slip-rate arithmetic, so that the FP64 CPU oracle (``oracle/``) and the HIP
+library can both be fed from it without sharing any of the method's code.
+
+The paper's DD boxes were built by a third-party code from boundary-to-boundary
+segments (Sec. "Construction of initial microstructure"); those files are not
+available, so closed planar glide loops stand in for them:
+
+* every loop is a regular 32-gon inscribed in a circle of radius R, lying in a
+  {111} plane through its centre, first vertex at a random in-plane angle, nodes
+  numbered counter-clockwise about the plane normal n (so the line sense t and
+  the radial direction r satisfy r x t = +n);
+* each loop draws one of the 4 {111} planes, one of the 3 in-plane 1/2<110>
+  Burgers directions and a random sign;
+* lengths are in units of the Burgers vector magnitude (|b| = 1), the core
+  width is a = 1 b, stresses are in Pa, the drag B in Pa s and dt in s.
+
+Material (FCC Cu): mu = 48 GPa, nu = 0.34, |b| = 0.2556 nm, a = 1 b,
+B = 1e-4 Pa s.  The paper's table lists mu = 48 GPa and b = 2.55e-10 m.
+
+Array layout (what the C ABI takes): positions ``x`` as SoA ``[3][n_nodes]``
+float64, ``seg_nodes`` as ``[2][n_segs]`` int32 (node 1 -> node 2 gives the line
+sense), ``burgers`` and ``normal`` as ``[3][n_segs]`` float64, ``pinned`` as
+``[n_nodes]`` uint8, ``sigma_app`` as Voigt ``(xx, yy, zz, yz, xz, xy)``.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# material and run constants
+# ---------------------------------------------------------------------------
+MU = 48.0e9            # shear modulus, Pa
+NU = 0.34              # Poisson ratio
+B_SI = 0.2556e-9       # |b| in metres (length unit of every instance)
+CORE_A = 1.0           # core width a, in b
+DRAG_B = 1.0e-4        # drag coefficient, Pa s
+DT = 2.0e-14           # forward-Euler step, s
+SEGS_PER_LOOP = 32
+
+# FCC {111} plane normals (crystal frame), and for each the three in-plane
+# 1/2<110> directions.  Ordering convention of the 12 slip systems: system
+# alpha = 3*p + d for plane p and direction d below.
+_PLANES = np.array([[1, 1, 1], [-1, 1, 1], [1, -1, 1], [1, 1, -1]], float)
+_DIRS = np.array([
+    [[0, 1, -1], [1, 0, -1], [1, -1, 0]],
+    [[0, 1, -1], [1, 0, 1], [1, 1, 0]],
+    [[0, 1, 1], [1, 0, -1], [1, 1, 0]],
+    [[0, 1, 1], [1, 0, 1], [1, -1, 0]],
+], float)
+PLANE_NORMALS = _PLANES / math.sqrt(3.0)
+SLIP_DIRS = _DIRS / math.sqrt(2.0)
+
+
+@dataclass
+class Instance:
+    """One DD volume: fixed topology, planar loops."""
+    x: np.ndarray            # [3][n_nodes] float64, in b
+    seg_nodes: np.ndarray    # [2][n_segs] int32
+    burgers: np.ndarray      # [3][n_segs] float64, in b
+    normal: np.ndarray       # [3][n_segs] float64, unit
+    pinned: np.ndarray       # [n_nodes] uint8
+    sigma_app: np.ndarray    # [6] float64 Voigt, Pa
+    volume: float            # b^3
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.x.shape[1])
+
+    @property
+    def n_segs(self) -> int:
+        return int(self.seg_nodes.shape[1])
+
+
+def material() -> dict:
+    return {"mu": MU, "nu": NU, "a": CORE_A, "B": DRAG_B}
+
+
+def _loops(rng, n_loops, box, rmin, rmax, log_radius=False, nseg=SEGS_PER_LOOP):
+    """Draw n_loops regular nseg-gons; returns arrays for an Instance."""
+    planes = rng.integers(0, 4, n_loops)
+    dirs = rng.integers(0, 3, n_loops)
+    signs = rng.integers(0, 2, n_loops) * 2 - 1
+    if log_radius:
+        radii = np.exp(rng.uniform(math.log(rmin), math.log(rmax), n_loops))
+    else:
+        radii = rng.uniform(rmin, rmax, n_loops)
+    centres = rng.uniform(0.0, box, (n_loops, 3))
+    phi0 = rng.uniform(0.0, 2.0 * math.pi, n_loops)
+
+    n_nodes = n_loops * nseg
+    x = np.empty((3, n_nodes))
+    seg = np.empty((2, n_nodes), np.int32)
+    bur = np.empty((3, n_nodes))
+    nor = np.empty((3, n_nodes))
+    k = np.arange(nseg)
+    for i in range(n_loops):
+        n = PLANE_NORMALS[planes[i]]
+        # in-plane orthonormal pair (e1, e2) with e1 x e2 = n
+        e1 = SLIP_DIRS[planes[i], 0].copy()
+        e2 = np.cross(n, e1)
+        ang = phi0[i] + 2.0 * math.pi * k / nseg
+        pts = centres[i][:, None] + radii[i] * (np.cos(ang)[None, :] * e1[:, None]
+                                                + np.sin(ang)[None, :] * e2[:, None])
+        base = i * nseg
+        x[:, base:base + nseg] = pts
+        seg[0, base:base + nseg] = base + k
+        seg[1, base:base + nseg] = base + (k + 1) % nseg
+        bur[:, base:base + nseg] = (signs[i] * SLIP_DIRS[planes[i], dirs[i]])[:, None]
+        nor[:, base:base + nseg] = n[:, None]
+    meta = {"planes": planes, "dirs": dirs, "signs": signs, "radii": radii,
+            "centres": centres, "phi0": phi0}
+    return x, seg, bur, nor, meta
+
+
+def uniaxial_001(stress_pa: float) -> np.ndarray:
+    return np.array([0.0, 0.0, stress_pa, 0.0, 0.0, 0.0])
+
+
+def volume_instance(seed, n_loops, box, rmin=100.0, rmax=500.0, log_radius=False,
+                    sigma_app=None) -> Instance:
+    rng = np.random.default_rng(seed)
+    x, seg, bur, nor, meta = _loops(rng, n_loops, box, rmin, rmax, log_radius)
+    if sigma_app is None:
+        sigma_app = uniaxial_001(50.0e6)
+    return Instance(x, seg, bur, nor, np.zeros(x.shape[1], np.uint8),
+                    np.asarray(sigma_app, float), float(box) ** 3,
+                    dict(meta, seed=seed, box=box))
+
+
+# --- the five workloads ------------------------------------------------------
+
+def config0() -> Instance:
+    """8 loops (256 segments) in a 2000 b cube, 50 MPa along [001]."""
+    return volume_instance(0, 8, 2000.0)
+
+
+def config1() -> Instance:
+    """512 loops (16,384 segments) in a 10,000 b cube, 50 MPa along [001]."""
+    return volume_instance(1, 512, 10000.0)
+
+
+def config3() -> Instance:
+    """8192 loops (262,144 segments), radii log-uniform 50-2000 b, 50,000 b cube."""
+    return volume_instance(3, 8192, 50000.0, 50.0, 2000.0, log_radius=True)
+
+
+def burst_instance(seed, box=2000.0, kmin=8, kmax=128) -> Instance:
+    """A PTA-style burst volume: k ~ U{kmin..kmax} loops, a random applied
+    stress (6 Voigt entries ~ U[-100, 100] MPa) and a mobile loop fraction
+    f ~ U[0.1, 0.9]; the first round(f k) loops are mobile, the others have
+    every node pinned (sessile)."""
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(kmin, kmax + 1))
+    f = float(rng.uniform(0.1, 0.9))
+    sig = rng.uniform(-100e6, 100e6, 6)
+    x, seg, bur, nor, meta = _loops(rng, k, box, 100.0, 500.0)
+    n_mob = int(round(f * k))
+    pinned = np.zeros(x.shape[1], np.uint8)
+    pinned[n_mob * SEGS_PER_LOOP:] = 1
+    return Instance(x, seg, bur, nor, pinned, sig, float(box) ** 3,
+                    dict(meta, seed=seed, box=box, k=k, f=f, n_mobile_loops=n_mob))
+
+
+def config2(n_inst=512, seed0=1_000_000, **kw) -> list[Instance]:
+    return [burst_instance(seed0 + i, **kw) for i in range(n_inst)]
+
+
+@dataclass
+class Batch:
+    """Instances packed back to back; seg_nodes stay instance-local."""
+    node_off: np.ndarray     # [n_inst+1] int64
+    seg_off: np.ndarray      # [n_inst+1] int64
+    x: np.ndarray            # [3][total nodes]
+    seg_nodes: np.ndarray    # [2][total segs] int32, local to the instance
+    burgers: np.ndarray
+    normal: np.ndarray
+    pinned: np.ndarray
+    sigma_app: np.ndarray    # [n_inst][6]
+    volume: np.ndarray       # [n_inst]
+
+    @property
+    def n_inst(self) -> int:
+        return int(self.node_off.shape[0] - 1)
+
+
+def pack(instances: list[Instance]) -> Batch:
+    nn = np.array([0] + [i.n_nodes for i in instances], np.int64)
+    ns = np.array([0] + [i.n_segs for i in instances], np.int64)
+    return Batch(np.cumsum(nn), np.cumsum(ns),
+                 np.ascontiguousarray(np.concatenate([i.x for i in instances], 1)),
+                 np.ascontiguousarray(np.concatenate([i.seg_nodes for i in instances], 1)),
+                 np.ascontiguousarray(np.concatenate([i.burgers for i in instances], 1)),
+                 np.ascontiguousarray(np.concatenate([i.normal for i in instances], 1)),
+                 np.ascontiguousarray(np.concatenate([i.pinned for i in instances])),
+                 np.stack([i.sigma_app for i in instances]),
+                 np.array([i.volume for i in instances]))
+
+
+def subset(inst: Instance, n_loops: int) -> Instance:
+    """The first n_loops loops of an instance (for small parity cases)."""
+    n = n_loops * SEGS_PER_LOOP
+    return Instance(inst.x[:, :n].copy(), inst.seg_nodes[:, :n].copy(),
+                    inst.burgers[:, :n].copy(), inst.normal[:, :n].copy(),
+                    inst.pinned[:n].copy(), inst.sigma_app.copy(),
+                    inst.volume, dict(inst.meta, subset=n_loops))
+
+
+def surrogate_state(seed) -> Instance:
+    """One training/inference state for the slip-rate surrogate: a burst volume
+    drawn like ``burst_instance`` from its own seed stream."""
+    return burst_instance(seed)
