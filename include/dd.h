@@ -1,0 +1,231 @@
+/*
+ * dd.h -- C ABI of libdd.so, the MI355X (gfx950) library for the all-pairs
+ * dislocation-segment force path of "Plasticity without phenomenology: a
+ * first step" (Chatterjee, Po, Zhang, Acharya, Ghoniem).
+ *
+ * The paper runs Discrete Dislocation Dynamics (DD) only in short bursts at
+ * frozen load (Sec. "Application of PTA for coarse-graining DD simulation",
+ * Eq. fast_dd) and averages their output in time (Eq. R_lambda_t).  Inside a
+ * burst the time goes to the interaction of every straight segment with every
+ * other: the stress of one segment (Sec. "Discrete Dislocation Dynamics": a
+ * differential operator on R = x - x' convolved with the dislocation density;
+ * here its isotropic, non-singular line-integral form with R_a =
+ * sqrt(R.R + a^2), integrated in closed form along the segment) evaluated at
+ * Gauss points of every other segment, contracted into Peach-Koehler forces
+ * df_k = eps_kjm sigma_ji b_i dl_m, integrated to nodal forces, then the glide
+ * velocity of Eq. DD_evol and the node update x(t + dt) = x(t) + w dt.
+ *
+ * Conventions common to every call
+ * --------------------------------
+ * Memory.   Array arguments are DEVICE pointers (hipMalloc or a PyTorch-ROCm
+ *           tensor's data_ptr) unless marked "host".  The caller owns them;
+ *           the library never frees them.  The library keeps a per-device
+ *           workspace (grown on demand with hipMalloc, released by
+ *           dd_shutdown).  Calls that share a device must not overlap in
+ *           time (issue them on one stream, or synchronise between them).
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = the default
+ *           stream).  Work is enqueued on it; outputs are valid once the
+ *           stream has been synchronised.  With validation on (the default)
+ *           each call also synchronises the stream before returning so that
+ *           it can report input errors (see dd_set_validation).
+ * Layouts.  Structure of arrays: positions x[3][n_nodes] (all x, then all y,
+ *           then all z), burgers[3][n_segs], normal[3][n_segs], forces
+ *           [3][n_nodes], float64.  seg_nodes[2][n_segs] int32: segment s
+ *           runs from node seg_nodes[s] to node seg_nodes[n_segs + s]; that
+ *           order is its line sense t.  pinned[n_nodes] uint8 (non-zero =
+ *           immobile node).  sigma_app: Voigt (xx, yy, zz, yz, xz, xy).
+ * Units.    Any consistent set: positions, Burgers vectors and the core width
+ *           a in one length unit; mu and every stress in one stress unit;
+ *           the drag B in stress*time; dt in time.  Forces are returned in
+ *           stress*length^2, velocities in length/time.  Internally lengths
+ *           are divided by a and stresses by mu, so FP32 work never
+ *           underflows whatever the caller's unit.
+ * Slip systems.  FCC, 12 systems alpha = 3 p + d: plane normals
+ *           p = 0..3: (1,1,1), (-1,1,1), (1,-1,1), (1,1,-1) over sqrt(3); in
+ *           plane p the three <110> directions normal to it, d = 0 the one
+ *           with zero x component, d = 1 zero y, d = 2 zero z, first non-zero
+ *           entry positive, over sqrt(2).
+ * Errors.   Every int-returning call returns DD_OK (0) or a negative code and
+ *           then dd_last_error() (per thread) says why.  No C++ exception
+ *           crosses this interface.  Kernels never read out of bounds, even
+ *           on invalid input: bad node indices are clamped on the device and
+ *           reported as DD_EINVAL when validation is on.
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DD_OK          0
+#define DD_EINVAL     (-1)   /* invalid argument or input array contents  */
+#define DD_EHIP       (-2)   /* a HIP runtime call failed                 */
+#define DD_ENOMEM     (-3)   /* device workspace allocation failed        */
+#define DD_ENONFINITE (-4)   /* a NaN or Inf reached an output            */
+
+#define DD_MAX_GAUSS  16
+#define DD_N_SYSTEMS  12
+#define DD_N_FEATURES 36
+
+/* Isotropic material: shear modulus mu, Poisson ratio nu, core width a,
+ * scalar drag B (Eq. DD_evol with B = B 1).  Valid: mu > 0, -1 < nu < 0.5,
+ * a > 0, B > 0 (B is only read by the mobility calls). */
+typedef struct { double mu, nu, a, B; } dd_material;
+
+/* DD_FP64: every pair in float64.
+ * DD_MIXED: pairs whose minimum distance from the target Gauss point to the
+ * source segment is below near_cutoff_a * a are evaluated in float64, all
+ * others in float32 (a cancellation-free arrangement of the closed form) with
+ * float32 accumulation over a source tile; tile sums, nodal sums and the
+ * mobility step stay float64. */
+typedef enum { DD_FP64 = 0, DD_MIXED = 1 } dd_precision;
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *dd_last_error(void);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int dd_version(void);
+
+/* Turn host-side reporting of input errors and non-finite outputs on (1,
+ * default) or off (0).  Off: no synchronisation inside calls; invalid input
+ * still cannot make a kernel read out of bounds, but it yields unspecified
+ * results instead of an error code.  Returns the previous setting. */
+int dd_set_validation(int on);
+
+/* Release the workspace of every device this thread's process used. */
+int dd_shutdown(void);
+
+/* Nodal forces (internal + applied) on every node.
+ *  For every segment j and Gauss-Legendre point q of an n_gauss-point rule
+ *  on [0, 1] (points s_q, weights w_q):
+ *    sigma(x_jq) = sigma_app + sum_{i != j} sigma^i(x_jq)
+ *    f_jq = (sigma(x_jq) b_j) x t_j                      (Peach-Koehler)
+ *    F[n1(j)] += L_j w_q (1 - s_q) f_jq,  F[n2(j)] += L_j w_q s_q f_jq
+ *  where sigma^i is the closed-form non-singular stress of segment i.  A
+ *  segment's own field is excluded (it only redistributes force between its
+ *  two nodes: its net force vanishes by symmetry).
+ * Arguments: x [3][n_nodes], seg_nodes [2][n_segs], burgers [3][n_segs];
+ *  normal [3][n_segs] is validated (unit length) but unused by the force;
+ *  sigma_app host [6]; m host; 1 <= n_gauss <= DD_MAX_GAUSS; precision a
+ *  dd_precision; near_cutoff_a > 0 (in units of a, mixed only; the
+ *  workload value is 20); force_out [3][n_nodes] (overwritten).
+ * Errors: DD_EINVAL for null pointers, counts < 0, bad material, n_gauss out
+ *  of range, a node index outside [0, n_nodes), a zero-length segment or a
+ *  normal of length differing from 1 by more than 1e-6 (validation on);
+ *  DD_ENONFINITE if a force is NaN/Inf (validation on). */
+int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
+                    const int32_t *seg_nodes, const double *burgers,
+                    const double *normal, const double *sigma_app,
+                    const dd_material *m, int n_gauss, int precision,
+                    double near_cutoff_a, double *force_out, void *stream);
+
+/* One glide-constrained forward-Euler step (Eq. DD_evol, lumped, scalar B):
+ *    ell_n = 1/2 sum_{s attached to n} L_s
+ *    v_n   = P_n F_n / (B ell_n),   x_n <- x_n + v_n dt
+ *  P_n projects out the component along the slip-plane normal shared by the
+ *  node's segments; with two distinct normals (up to sign) v is projected on
+ *  the line n1 x n2; with three or more, or when pinned or unattached, v = 0.
+ * Arguments: x [3][n_nodes] updated in place; force [3][n_nodes];
+ *  seg_nodes, normal as above; pinned [n_nodes] (nullable = none pinned);
+ *  m host (B used); dt > 0; vel_out [3][n_nodes] (nullable).
+ * Errors: as dd_nodal_forces. */
+int dd_glide_step(int64_t n_nodes, double *x, const double *force,
+                  int64_t n_segs, const int32_t *seg_nodes,
+                  const double *normal, const uint8_t *pinned,
+                  const dd_material *m, double dt, double *vel_out,
+                  void *stream);
+
+/* Independent DD bursts at frozen applied stress, all advanced together.
+ *  Instance i owns nodes [node_off[i], node_off[i+1]) and segments
+ *  [seg_off[i], seg_off[i+1]) of the packed arrays; its seg_nodes are local
+ *  to it (0 .. its node count - 1) and instances never interact.  Every step
+ *  k = 0 .. n_steps-1 of every instance does: nodal forces of X_k (as
+ *  dd_nodal_forces, with that instance's sigma_app), glide velocities v_k,
+ *  the per-system slip rate
+ *    gdot_alpha(k) = (1/V) sum_{s in alpha} (b_s . m_alpha) L_s
+ *                    ((t_s x (v_n1 + v_n2)/2) . n_alpha)
+ *  (the segment distortion rate b/A (x) (l x V) times l A, Sec. "Thermal
+ *  activation", summed over the volume and resolved on system alpha; s in
+ *  alpha when its normal and Burgers direction match the system up to sign),
+ *  then X_{k+1} = X_k + v_k dt.  Output: rate_avg_out[i][alpha] =
+ *  (1/n_steps) sum_k gdot_alpha(k), the running time average of
+ *  Eq. R_lambda_t with equal steps.  x is advanced in place, so a second
+ *  call resumes the burst.
+ *  features_out (nullable) [n_inst][36]: of the initial state, per system:
+ *  [0..11] resolved shear stress m_alpha . sigma_app n_alpha (numerator of
+ *  Eq. schmid), [12..23] mobile and [24..35] sessile line length per volume
+ *  (a segment is sessile when both its nodes are pinned).
+ * Arguments: node_off, seg_off HOST [n_inst+1] int64, non-decreasing, from 0;
+ *  x, seg_nodes, burgers, normal, pinned (nullable) packed as above;
+ *  sigma_app [n_inst][6] and volume [n_inst] device; m host; n_gauss,
+ *  precision, near_cutoff_a as dd_nodal_forces; n_steps >= 0; dt > 0;
+ *  rate_avg_out [n_inst][12].  The step loop is captured once into a HIP
+ *  graph and launched as one graph.
+ * Errors: as dd_nodal_forces, also for inconsistent offsets. */
+int dd_burst_batch(int32_t n_inst, const int64_t *node_off,
+                   const int64_t *seg_off, double *x,
+                   const int32_t *seg_nodes, const double *burgers,
+                   const double *normal, const uint8_t *pinned,
+                   const double *sigma_app, const double *volume,
+                   const dd_material *m, int n_gauss, int precision,
+                   double near_cutoff_a, int n_steps, double dt,
+                   double *rate_avg_out, double *features_out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Slip-rate surrogate (not in the paper): a 4-member ensemble of MLPs     */
+/* 36 -> 256 -> 256 -> 256 -> 12, ReLU hidden layers, that maps the 36     */
+/* features above to the 12 burst-averaged slip rates.  bfloat16 weights   */
+/* and activations on the matrix cores, float32 accumulation, float32      */
+/* master weights and Adam moments.                                        */
+/* ---------------------------------------------------------------------- */
+#define DD_MLP_IN      36
+#define DD_MLP_HIDDEN  256
+#define DD_MLP_OUT     12
+/* Parameters of one member, flat float32, in this order: W1[256][36],
+ * b1[256], W2[256][256], b2[256], W3[256][256], b3[256], W4[12][256], b4[12]
+ * (W[out][in]). */
+#define DD_MLP_PARAMS  144140
+
+typedef struct dd_mlp dd_mlp;
+
+/* Create an ensemble of n_members (1..8) on the current device with
+ * He-uniform weights drawn on the host from `seed` (member k uses seed + k),
+ * zero biases, identity input/output scaling.  *out receives the handle. */
+int dd_mlp_create(int n_members, uint64_t seed, dd_mlp **out);
+int dd_mlp_destroy(dd_mlp *model);
+
+/* Copy one member's parameters in (host float32 [DD_MLP_PARAMS]); resets the
+ * Adam state of that member. */
+int dd_mlp_set_params(dd_mlp *model, int member, const float *host_params);
+/* Copy one member's float32 master parameters out to host memory. */
+int dd_mlp_get_params(const dd_mlp *model, int member, float *host_params);
+
+/* Feature and target standardisation (host arrays): the network sees
+ * (feat - in_shift) * in_scale and predicts (rate - out_shift) / out_scale. */
+int dd_mlp_set_scaling(dd_mlp *model, const float *in_shift, const float *in_scale,
+                       const float *out_shift, const float *out_scale);
+
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) of
+ * every member on the same mini-batch: feat [n][36], target rates [n][12]
+ * (device float32, unstandardised); loss_out (device float32
+ * [n_members], nullable) receives each member's mean squared error in
+ * standardised units before the step.  1 <= n <= 65536. */
+int dd_mlp_train_step(dd_mlp *model, int64_t n, const float *feat,
+                      const float *target, float lr, float *loss_out,
+                      void *stream);
+
+/* Ensemble inference: rates [n][12] = member mean (unstandardised), spread
+ * [n] = ||population std over members||_2 / max(||mean||_2, 1e-30),
+ * needs_dd [n] = spread > spread_tol (DD is the fallback for those points).
+ * feat [n][36] device float32; rates, spread, needs_dd device. */
+int dd_surrogate_rates(const dd_mlp *model, int64_t n, const float *feat,
+                       float *rates, float *spread, uint8_t *needs_dd,
+                       float spread_tol, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DD_H */

@@ -1,0 +1,299 @@
+"""Python binding of libdd.so: argument marshalling only.
+
+Every function here has the name of the C entry point it wraps
+(``include/dd.h``) and takes PyTorch-ROCm tensors that already live on the GPU;
+it checks dtype, device, contiguity and shapes, passes raw device pointers and
+the current HIP stream to the library, and raises ``DDError`` on a non-zero
+return code.  No arithmetic of the method happens in Python and there is no
+CPU fallback: if ``libdd.so`` is missing, importing the binding's functions
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdd.so")
+
+DD_FP64, DD_MIXED = 0, 1
+N_SYSTEMS, N_FEATURES = 12, 36
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
+
+EXPORTS = [
+    "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
+    "dd_nodal_forces", "dd_glide_step", "dd_burst_batch",
+    "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
+    "dd_mlp_set_scaling", "dd_mlp_train_step", "dd_surrogate_rates",
+]
+
+
+class DDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdd error {code}: {msg}")
+        self.code = code
+
+
+class Material(C.Structure):
+    _fields_ = [("mu", C.c_double), ("nu", C.c_double), ("a", C.c_double), ("B", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libdd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2005_02498_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _declare(L):
+    i64, i32, vp, dbl = C.c_int64, C.c_int32, C.c_void_p, C.c_double
+    fp = C.POINTER(C.c_float)
+    sig = {
+        "dd_last_error": (C.c_char_p, []),
+        "dd_version": (C.c_int, []),
+        "dd_set_validation": (C.c_int, [C.c_int]),
+        "dd_shutdown": (C.c_int, []),
+        "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
+                                      C.POINTER(Material), C.c_int, C.c_int, dbl, vp, vp]),
+        "dd_glide_step": (C.c_int, [i64, vp, vp, i64, vp, vp, vp, C.POINTER(Material), dbl,
+                                    vp, vp]),
+        "dd_burst_batch": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp,
+                                     vp, vp, vp, vp, vp, C.POINTER(Material), C.c_int, C.c_int,
+                                     dbl, C.c_int, dbl, vp, vp, vp]),
+        "dd_mlp_create": (C.c_int, [C.c_int, C.c_uint64, C.POINTER(vp)]),
+        "dd_mlp_destroy": (C.c_int, [vp]),
+        "dd_mlp_set_params": (C.c_int, [vp, C.c_int, fp]),
+        "dd_mlp_get_params": (C.c_int, [vp, C.c_int, fp]),
+        "dd_mlp_set_scaling": (C.c_int, [vp, fp, fp, fp, fp]),
+        "dd_mlp_train_step": (C.c_int, [vp, i64, vp, vp, C.c_float, vp, vp]),
+        "dd_surrogate_rates": (C.c_int, [vp, i64, vp, vp, vp, vp, C.c_float, vp]),
+    }
+    for name, (res, args) in sig.items():
+        if hasattr(L, name):
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+
+
+def _check(rc):
+    if rc != 0:
+        raise DDError(rc, lib().dd_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, shape=None, name="tensor", nullable=False):
+    if t is None:
+        if nullable:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def material(mu, nu, a, B=1.0):
+    return Material(float(mu), float(nu), float(a), float(B))
+
+
+def _mat(m):
+    if isinstance(m, Material):
+        return m
+    if isinstance(m, dict):
+        return material(m["mu"], m["nu"], m["a"], m.get("B", 1.0))
+    return material(*m)
+
+
+def _prec(p):
+    if p in (DD_FP64, "fp64", "f64"):
+        return DD_FP64
+    if p in (DD_MIXED, "mixed"):
+        return DD_MIXED
+    raise ValueError(f"unknown precision {p!r}")
+
+
+# ----------------------------------------------------------------- general --
+def dd_version() -> int:
+    return lib().dd_version()
+
+
+def dd_set_validation(on: bool) -> bool:
+    return bool(lib().dd_set_validation(1 if on else 0))
+
+
+def dd_shutdown():
+    _check(lib().dd_shutdown())
+
+
+def dd_last_error() -> str:
+    return lib().dd_last_error().decode()
+
+
+# -------------------------------------------------------------- force path --
+def dd_nodal_forces(x, seg_nodes, burgers, normal, sigma_app, mat, n_gauss=2,
+                    precision=DD_FP64, near_cutoff_a=20.0, force_out=None, stream=None):
+    """Nodal forces [3][n_nodes] (float64) of the volume; see dd.h."""
+    nn = x.shape[1] if x.dim() == 2 else -1
+    ns = seg_nodes.shape[1] if seg_nodes.dim() == 2 else -1
+    px = _dev(x, torch.float64, (3, nn), "x")
+    psn = _dev(seg_nodes, torch.int32, (2, ns), "seg_nodes")
+    pb = _dev(burgers, torch.float64, (3, ns), "burgers")
+    pn = _dev(normal, torch.float64, (3, ns), "normal")
+    if force_out is None:
+        force_out = torch.empty((3, nn), dtype=torch.float64, device=x.device)
+    pf = _dev(force_out, torch.float64, (3, nn), "force_out")
+    sig = (C.c_double * 6)(*[float(v) for v in sigma_app])
+    m = _mat(mat)
+    _check(lib().dd_nodal_forces(nn, px, ns, psn, pb, pn, sig, C.byref(m), int(n_gauss),
+                                 _prec(precision), float(near_cutoff_a), pf, _stream(stream)))
+    return force_out
+
+
+def dd_glide_step(x, force, seg_nodes, normal, pinned, mat, dt, vel_out=None, stream=None):
+    """Advance x in place by one glide step; returns the velocities."""
+    nn = x.shape[1]
+    ns = seg_nodes.shape[1]
+    px = _dev(x, torch.float64, (3, nn), "x")
+    pf = _dev(force, torch.float64, (3, nn), "force")
+    psn = _dev(seg_nodes, torch.int32, (2, ns), "seg_nodes")
+    pn = _dev(normal, torch.float64, (3, ns), "normal")
+    pp = _dev(pinned, torch.uint8, (nn,), "pinned", nullable=True)
+    if vel_out is None:
+        vel_out = torch.empty((3, nn), dtype=torch.float64, device=x.device)
+    pv = _dev(vel_out, torch.float64, (3, nn), "vel_out")
+    m = _mat(mat)
+    _check(lib().dd_glide_step(nn, px, pf, ns, psn, pn, pp, C.byref(m), float(dt), pv,
+                               _stream(stream)))
+    return vel_out
+
+
+def dd_burst_batch(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app,
+                   volume, mat, n_gauss=2, precision=DD_MIXED, near_cutoff_a=20.0,
+                   n_steps=200, dt=2e-14, rate_avg_out=None, features_out=None,
+                   want_features=False, stream=None):
+    """Batched bursts; node_off/seg_off are host sequences (length n_inst+1).
+    Returns (rate_avg [n_inst][12], features [n_inst][36] or None); x advances."""
+    no = (C.c_int64 * len(node_off))(*[int(v) for v in node_off])
+    so = (C.c_int64 * len(seg_off))(*[int(v) for v in seg_off])
+    n_inst = len(node_off) - 1
+    if len(seg_off) != n_inst + 1:
+        raise ValueError("node_off and seg_off must have the same length")
+    nn, ns = int(node_off[-1]), int(seg_off[-1])
+    dev = x.device
+    px = _dev(x, torch.float64, (3, nn), "x")
+    psn = _dev(seg_nodes, torch.int32, (2, ns), "seg_nodes")
+    pb = _dev(burgers, torch.float64, (3, ns), "burgers")
+    pn = _dev(normal, torch.float64, (3, ns), "normal")
+    pp = _dev(pinned, torch.uint8, (nn,), "pinned", nullable=True)
+    ps = _dev(sigma_app, torch.float64, (n_inst, 6), "sigma_app")
+    pv = _dev(volume, torch.float64, (n_inst,), "volume")
+    if rate_avg_out is None:
+        rate_avg_out = torch.empty((n_inst, 12), dtype=torch.float64, device=dev)
+    pr = _dev(rate_avg_out, torch.float64, (n_inst, 12), "rate_avg_out")
+    if features_out is None and want_features:
+        features_out = torch.empty((n_inst, 36), dtype=torch.float64, device=dev)
+    pfe = _dev(features_out, torch.float64, (n_inst, 36), "features_out", nullable=True)
+    m = _mat(mat)
+    _check(lib().dd_burst_batch(n_inst, no, so, px, psn, pb, pn, pp, ps, pv, C.byref(m),
+                                int(n_gauss), _prec(precision), float(near_cutoff_a),
+                                int(n_steps), float(dt), pr, pfe, _stream(stream)))
+    return rate_avg_out, features_out
+
+
+# --------------------------------------------------------------- surrogate --
+def _host_f32(a, n, name):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32).reshape(-1)
+    if a.size != n:
+        raise ValueError(f"{name} must have {n} entries")
+    return a, a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class SurrogateModel:
+    """Owns a dd_mlp handle (ensemble of MLPs on the current device)."""
+
+    def __init__(self, n_members=4, seed=0):
+        h = C.c_void_p()
+        _check(lib().dd_mlp_create(int(n_members), C.c_uint64(int(seed)), C.byref(h)))
+        self.handle = h
+        self.n_members = n_members
+
+    def close(self):
+        if self.handle:
+            _check(lib().dd_mlp_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, member, params):
+        import numpy as np
+        a, p = _host_f32(params, MLP_PARAMS, "params")
+        _check(lib().dd_mlp_set_params(self.handle, int(member), p))
+
+    def get_params(self, member):
+        import numpy as np
+        out = np.zeros(MLP_PARAMS, np.float32)
+        _check(lib().dd_mlp_get_params(self.handle, int(member),
+                                       out.ctypes.data_as(C.POINTER(C.c_float))))
+        return out
+
+    def set_scaling(self, in_shift, in_scale, out_shift, out_scale):
+        a, p1 = _host_f32(in_shift, MLP_IN, "in_shift")
+        b, p2 = _host_f32(in_scale, MLP_IN, "in_scale")
+        c, p3 = _host_f32(out_shift, MLP_OUT, "out_shift")
+        d, p4 = _host_f32(out_scale, MLP_OUT, "out_scale")
+        _check(lib().dd_mlp_set_scaling(self.handle, p1, p2, p3, p4))
+
+
+def dd_mlp_train_step(model: SurrogateModel, feat, target, lr=1e-3, loss_out=None, stream=None):
+    n = feat.shape[0]
+    pf = _dev(feat, torch.float32, (n, MLP_IN), "feat")
+    pt = _dev(target, torch.float32, (n, MLP_OUT), "target")
+    if loss_out is None:
+        loss_out = torch.empty(model.n_members, dtype=torch.float32, device=feat.device)
+    pl = _dev(loss_out, torch.float32, (model.n_members,), "loss_out")
+    _check(lib().dd_mlp_train_step(model.handle, n, pf, pt, C.c_float(lr), pl, _stream(stream)))
+    return loss_out
+
+
+def dd_surrogate_rates(model: SurrogateModel, feat, spread_tol=0.05, rates=None, spread=None,
+                       needs_dd=None, stream=None):
+    n = feat.shape[0]
+    dev = feat.device
+    pf = _dev(feat, torch.float32, (n, MLP_IN), "feat")
+    if rates is None:
+        rates = torch.empty((n, MLP_OUT), dtype=torch.float32, device=dev)
+    if spread is None:
+        spread = torch.empty((n,), dtype=torch.float32, device=dev)
+    if needs_dd is None:
+        needs_dd = torch.empty((n,), dtype=torch.uint8, device=dev)
+    pr = _dev(rates, torch.float32, (n, MLP_OUT), "rates")
+    ps = _dev(spread, torch.float32, (n,), "spread")
+    pn = _dev(needs_dd, torch.uint8, (n,), "needs_dd")
+    _check(lib().dd_surrogate_rates(model.handle, n, pf, pr, ps, pn, C.c_float(spread_tol),
+                                    _stream(stream)))
+    return rates, spread, needs_dd

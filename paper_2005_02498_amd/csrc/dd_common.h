@@ -1,0 +1,106 @@
+// Internal declarations of libdd.so (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "dd.h"
+
+namespace dd {
+
+// ---------------------------------------------------------------- errors --
+int set_error(int code, const char *fmt, ...);
+void clear_error();
+bool validation_on();
+
+#define DD_HIP(call)                                                           \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess)                                                  \
+            return ::dd::set_error(DD_EHIP, "%s failed: %s (%s:%d)", #call,    \
+                                   hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+// Flags raised by device-side checks (OR-ed into one word).
+enum : unsigned {
+    FLAG_BAD_INDEX = 1u,
+    FLAG_ZERO_LENGTH = 2u,
+    FLAG_BAD_NORMAL = 4u,
+    FLAG_NONFINITE = 8u,
+};
+
+// -------------------------------------------------------------- workspace --
+// Per-device scratch: named slots, grown on demand, freed by dd_shutdown().
+enum Slot {
+    WS_SEG64 = 0,      // FP64 segment records
+    WS_SEG32,          // FP32 segment records (mixed path)
+    WS_PARTIAL,        // per work item partial sums
+    WS_SEGF,           // per-segment end forces [6][n_segs]
+    WS_CSR_PTR,        // node -> incident (segment, end) list: offsets
+    WS_CSR_LIST,       //   ... and entries
+    WS_CSR_CNT,        //   ... counters
+    WS_TILES,          // tile table
+    WS_ITEMS,          // work-item table
+    WS_SEG_INST,       // segment -> instance
+    WS_OFFS,           // device copies of instance offsets
+    WS_VEL,            // node velocities
+    WS_FORCE,          // node forces (bursts)
+    WS_RATE,           // running slip-rate sums
+    WS_INST_OFFS,      // instance node and segment offsets
+    WS_MISC,
+    WS_NSLOTS
+};
+
+struct Workspace {
+    int device = -1;
+    void *ptr[WS_NSLOTS] = {};
+    size_t cap[WS_NSLOTS] = {};
+    unsigned *flags_dev = nullptr;   // one word
+    unsigned *flags_host = nullptr;  // pinned mirror
+    hipStream_t capture_stream = nullptr;
+};
+
+// Returns the workspace of the current device (creating it on first use).
+int workspace(Workspace **out);
+// Makes slot s at least `bytes` large.  Growing synchronises the device first.
+int ensure(Workspace *ws, Slot s, size_t bytes, void **out);
+
+// --------------------------------------------------------------- kernels --
+// Work decomposition of the pair kernel: a tile is up to TILE consecutive
+// target Gauss points of one instance; an item is one tile against one
+// contiguous range of that instance's sources.
+constexpr int TILE = 256;
+
+struct Tile {
+    int64_t point_begin;   // global Gauss-point index (segment * Q + q)
+    int32_t n_points;      // <= TILE
+    int32_t n_chunks;      // items covering this tile, slots slot_begin..+n_chunks
+    int64_t slot_begin;
+};
+
+struct Item {
+    int32_t tile;
+    int32_t pad;
+    int64_t src_begin;     // global segment indices [src_begin, src_end)
+    int64_t src_end;
+    int64_t slot;          // partial-sum slot
+};
+
+struct GaussRule {
+    double s[DD_MAX_GAUSS];
+    double w[DD_MAX_GAUSS];
+    int n;
+};
+
+// FP64 segment record, structure of arrays with stride n_segs:
+//  0..2 x1/a, 3..5 t, 6 L/a, 7..9 b/a, 10..12 c = (b/a) x t, 13 unused.
+constexpr int REC64 = 14;
+// FP32 segment record: 0..2 t, 3 L/a, 4..6 b/a, 7..9 c.
+constexpr int REC32 = 10;
+
+GaussRule gauss_rule(int n);
+
+}  // namespace dd

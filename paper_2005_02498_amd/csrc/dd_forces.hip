@@ -1,0 +1,1145 @@
+// Pair-force path of libdd.so: segment preparation, the all-pairs kernels,
+// the per-segment quadrature epilogue, node gathers, glide + Euler, slip
+// rates, and the public entry points dd_nodal_forces / dd_glide_step /
+// dd_burst_batch.
+//
+// Units inside the kernels: lengths are divided by the core width a and
+// stresses by mu, so the non-singular closed form is evaluated with a = 1 and
+// mu = 1; forces are multiplied back by mu a^2.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dd_common.h"
+#include "dd_pair.h"
+
+namespace dd {
+
+// ---------------------------------------------------------------- helpers --
+__global__ void k_fill_u32(unsigned *p, int64_t n, unsigned v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_f64(double *p, int64_t n, double v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_check_finite(const double *p, int64_t n, unsigned *flags)
+{
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(p[i]);
+    if (bad) atomicOr(flags, FLAG_NONFINITE);
+}
+
+static inline unsigned grid_for(int64_t n, int block = 256, int64_t cap = 4096)
+{
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// Instance lookup helpers: node_off / seg_off / seg_inst may be null for a
+// single volume (instance 0 owns everything).
+struct Layout {
+    const int64_t *node_off;   // device [n_inst+1] or null
+    const int64_t *seg_off;    // device [n_inst+1] or null
+    const int32_t *seg_inst;   // device [n_segs] or null
+    const int64_t *tile_begin; // device [n_inst+1] or null
+    int64_t nn, ns;            // totals
+};
+
+__device__ __forceinline__ int seg_instance(const Layout &L, int64_t s)
+{
+    return L.seg_inst ? L.seg_inst[s] : 0;
+}
+__device__ __forceinline__ int64_t node_begin(const Layout &L, int inst)
+{
+    return L.node_off ? L.node_off[inst] : 0;
+}
+__device__ __forceinline__ int64_t node_count(const Layout &L, int inst)
+{
+    return L.node_off ? L.node_off[inst + 1] - L.node_off[inst] : L.nn;
+}
+__device__ __forceinline__ int64_t seg_begin(const Layout &L, int inst)
+{
+    return L.seg_off ? L.seg_off[inst] : 0;
+}
+
+// Global node ids of segment s (instance-local indices clamped into range on
+// the device, flagged when they were not).
+__device__ __forceinline__ bool seg_ends(const Layout &L, const int32_t *seg_nodes, int64_t s,
+                                         int64_t &g1, int64_t &g2)
+{
+    int inst = seg_instance(L, s);
+    int64_t n0 = node_begin(L, inst), nn = node_count(L, inst);
+    int64_t i1 = seg_nodes[s], i2 = seg_nodes[L.ns + s];
+    bool ok = nn > 0 && i1 >= 0 && i1 < nn && i2 >= 0 && i2 < nn;
+    if (!ok) {
+        i1 = 0;
+        i2 = 0;
+        if (nn <= 0) n0 = 0;   // only reachable when nn_total > 0 is checked on host
+    }
+    g1 = n0 + i1;
+    g2 = n0 + i2;
+    return ok;
+}
+
+// FCC slip systems, alpha = 3 p + d (see dd.h).
+__device__ __forceinline__ void fcc(int alpha, double n[3], double m[3])
+{
+    const double r3 = 0.57735026918962576451, r2 = 0.70710678118654752440;
+    // plane normals
+    const signed char P[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
+    // directions, per plane: zero x, zero y, zero z
+    const signed char D[4][3][3] = {
+        {{0, 1, -1}, {1, 0, -1}, {1, -1, 0}},
+        {{0, 1, -1}, {1, 0, 1}, {1, 1, 0}},
+        {{0, 1, 1}, {1, 0, -1}, {1, 1, 0}},
+        {{0, 1, 1}, {1, 0, 1}, {1, -1, 0}},
+    };
+    int p = alpha / 3, d = alpha % 3;
+    for (int k = 0; k < 3; ++k) {
+        n[k] = P[p][k] * r3;
+        m[k] = D[p][d][k] * r2;
+    }
+}
+
+// -------------------------------------------------------- a1: preparation --
+struct PrepArgs {
+    Layout L;
+    const double *x;
+    const int32_t *seg_nodes;
+    const double *burgers;
+    const double *normal;
+    double inv_a;
+    double *rec64;        // [REC64][ns]
+    float *rec32;         // [REC32][ns] or null
+    int32_t *sys;         // [ns] slip system or -1, or null
+    unsigned *flags;
+};
+
+__global__ void k_seg_prep(PrepArgs A)
+{
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t ns = A.L.ns, nn = A.L.nn;
+    if (s >= ns) return;
+    unsigned fl = 0;
+    int64_t g1, g2;
+    if (!seg_ends(A.L, A.seg_nodes, s, g1, g2)) fl |= FLAG_BAD_INDEX;
+    double x1[3], d[3], b[3], t[3], c[3];
+    for (int k = 0; k < 3; ++k) {
+        x1[k] = A.x[k * nn + g1] * A.inv_a;
+        d[k] = A.x[k * nn + g2] * A.inv_a - x1[k];
+        b[k] = A.burgers[k * ns + s] * A.inv_a;
+    }
+    double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(L > 0.0) || !isfinite(L)) fl |= FLAG_ZERO_LENGTH;
+    double iL = 1.0 / L;
+    for (int k = 0; k < 3; ++k) t[k] = d[k] * iL;
+    c[0] = b[1] * t[2] - b[2] * t[1];
+    c[1] = b[2] * t[0] - b[0] * t[2];
+    c[2] = b[0] * t[1] - b[1] * t[0];
+    double nv[3] = {A.normal[s], A.normal[ns + s], A.normal[2 * ns + s]};
+    double nl = nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2];
+    if (!(fabs(nl - 1.0) <= 2e-6)) fl |= FLAG_BAD_NORMAL;
+    double *r = A.rec64;
+    r[0 * ns + s] = x1[0]; r[1 * ns + s] = x1[1]; r[2 * ns + s] = x1[2];
+    r[3 * ns + s] = t[0];  r[4 * ns + s] = t[1];  r[5 * ns + s] = t[2];
+    r[6 * ns + s] = L;
+    r[7 * ns + s] = b[0];  r[8 * ns + s] = b[1];  r[9 * ns + s] = b[2];
+    r[10 * ns + s] = c[0]; r[11 * ns + s] = c[1]; r[12 * ns + s] = c[2];
+    r[13 * ns + s] = 0.0;
+    if (A.rec32) {
+        float *q = A.rec32;
+        q[0 * ns + s] = (float)t[0]; q[1 * ns + s] = (float)t[1]; q[2 * ns + s] = (float)t[2];
+        q[3 * ns + s] = (float)L;
+        q[4 * ns + s] = (float)b[0]; q[5 * ns + s] = (float)b[1]; q[6 * ns + s] = (float)b[2];
+        q[7 * ns + s] = (float)c[0]; q[8 * ns + s] = (float)c[1]; q[9 * ns + s] = (float)c[2];
+    }
+    if (A.sys) {
+        int found = -1;
+        double bl = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+        for (int al = 0; al < 12 && found < 0; ++al) {
+            double n[3], m[3];
+            fcc(al, n, m);
+            double cn = fabs(n[0] * nv[0] + n[1] * nv[1] + n[2] * nv[2]);
+            double cb = fabs(m[0] * b[0] + m[1] * b[1] + m[2] * b[2]);
+            if (cn > 1.0 - 1e-6 && bl > 0.0 && cb > (1.0 - 1e-6) * bl) found = al;
+        }
+        A.sys[s] = found;
+    }
+    if (fl) atomicOr(A.flags, fl);
+}
+
+// ------------------------------------------- node -> (segment, end) lists --
+__global__ void k_csr_count(Layout L, const int32_t *seg_nodes, int32_t *cnt)
+{
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= L.ns) return;
+    int64_t g1, g2;
+    if (!seg_ends(L, seg_nodes, s, g1, g2)) return;   // bad segment: attached to nothing
+    atomicAdd(&cnt[g1], 1);
+    atomicAdd(&cnt[g2], 1);
+}
+
+// Exclusive scan of cnt[0..n) into ptr[0..n] by one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *cnt, int64_t n, int32_t *ptr)
+{
+    __shared__ int32_t part[1024];
+    const int T = 1024, tid = threadIdx.x;
+    int64_t per = (n + T - 1) / T;
+    int64_t b = tid * per, e = min(n, b + per);
+    int32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += cnt[i];
+    part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < T; off <<= 1) {
+        int32_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    int32_t run = tid ? part[tid - 1] : 0;
+    for (int64_t i = b; i < e; ++i) {
+        ptr[i] = run;
+        run += cnt[i];
+    }
+    if (tid == T - 1) ptr[n] = part[T - 1];
+}
+
+__global__ void k_csr_fill(Layout L, const int32_t *seg_nodes, const int32_t *ptr,
+                           int32_t *cursor, int32_t *list)
+{
+    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= L.ns) return;
+    int64_t g[2];
+    if (!seg_ends(L, seg_nodes, s, g[0], g[1])) return;
+    for (int e = 0; e < 2; ++e) {
+        int32_t k = atomicAdd(&cursor[g[e]], 1);
+        list[ptr[g[e]] + k] = (int32_t)(2 * s + e);
+    }
+}
+
+// Sort each node's list by (segment, end) so that every later gather sums in
+// a fixed order (results do not depend on the atomics above).
+__global__ void k_csr_sort(const int32_t *ptr, int64_t nn, int32_t *list)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    int32_t b = ptr[n], e = ptr[n + 1];
+    for (int32_t i = b + 1; i < e; ++i) {
+        int32_t v = list[i], k = i - 1;
+        while (k >= b && list[k] > v) {
+            list[k + 1] = list[k];
+            --k;
+        }
+        list[k + 1] = v;
+    }
+}
+
+// ------------------------------------------ a2: the all-pairs FP64 kernel --
+// One workgroup = one work item: up to TILE target Gauss points (one per
+// lane) against a contiguous source range, staged through LDS TILE sources at
+// a time.  Each lane accumulates sigma b_j (3 values) over the range; the
+// item's partial sums go to their own slot, reduced in a fixed order later.
+__global__ __launch_bounds__(TILE) void k_pair64(const Item *__restrict__ items,
+                                                 const Tile *__restrict__ tiles,
+                                                 const double *__restrict__ rec, int64_t ns,
+                                                 GaussRule g, double k1, double k2,
+                                                 double *__restrict__ partial)
+{
+    __shared__ double sh[13][TILE];
+    const Item it = items[blockIdx.x];
+    const Tile tl = tiles[it.tile];
+    const int lane = threadIdx.x;
+    const bool valid = lane < tl.n_points;
+    const int64_t p = tl.point_begin + (valid ? lane : 0);
+    const int Q = g.n;
+    const int64_t j = p / Q;
+    const int q = (int)(p - j * Q);
+    double sq = g.s[0];
+    for (int k = 1; k < DD_MAX_GAUSS; ++k)
+        if (k == q) sq = g.s[k];
+    const double L = rec[6 * ns + j];
+    const double xq0 = rec[0 * ns + j] + sq * L * rec[3 * ns + j];
+    const double xq1 = rec[1 * ns + j] + sq * L * rec[4 * ns + j];
+    const double xq2 = rec[2 * ns + j] + sq * L * rec[5 * ns + j];
+    const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+
+    for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
+        const int n = (int)min<int64_t>(TILE, it.src_end - base);
+        __syncthreads();
+        if (lane < n) {
+#pragma unroll
+            for (int k = 0; k < 13; ++k) sh[k][lane] = rec[k * ns + base + lane];
+        }
+        __syncthreads();
+        for (int m = 0; m < n; ++m) {
+            double c0, c1, c2;
+            pair_sigma_b_f64(xq0, xq1, xq2, bj0, bj1, bj2,
+                             sh[0][m], sh[1][m], sh[2][m], sh[3][m], sh[4][m], sh[5][m],
+                             sh[6][m], sh[7][m], sh[8][m], sh[9][m], sh[10][m], sh[11][m],
+                             sh[12][m], k1, k2, c0, c1, c2);
+            const bool self = (base + m) == j;
+            a0 += self ? 0.0 : c0;
+            a1 += self ? 0.0 : c1;
+            a2 += self ? 0.0 : c2;
+        }
+    }
+    if (valid) {
+        double *o = partial + it.slot * 3 * TILE;
+        o[lane] = a0;
+        o[TILE + lane] = a1;
+        o[2 * TILE + lane] = a2;
+    }
+}
+
+// Mixed precision: far pairs in FP32 (cancellation-free arrangement, FP32
+// accumulation over one LDS stage), near pairs (minimum distance from the
+// Gauss point to the closed source segment below the cutoff) in FP64.  The
+// target-source offset, its axial part y and its perpendicular part rho are
+// formed in FP64 and rounded once, so nearly collinear far pairs keep rho.
+__global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ items,
+                                                     const Tile *__restrict__ tiles,
+                                                     const double *__restrict__ rec,
+                                                     const float *__restrict__ rec32,
+                                                     int64_t ns, GaussRule g, double k1,
+                                                     double k2, float cut2,
+                                                     double *__restrict__ partial)
+{
+    __shared__ double shx[6][TILE];    // x1, t (FP64)
+    __shared__ float shf[7][TILE];     // L, b, c (FP32)
+    const Item it = items[blockIdx.x];
+    const Tile tl = tiles[it.tile];
+    const int lane = threadIdx.x;
+    const bool valid = lane < tl.n_points;
+    const int64_t p = tl.point_begin + (valid ? lane : 0);
+    const int Q = g.n;
+    const int64_t j = p / Q;
+    const int q = (int)(p - j * Q);
+    double sq = g.s[0];
+    for (int k = 1; k < DD_MAX_GAUSS; ++k)
+        if (k == q) sq = g.s[k];
+    const double L = rec[6 * ns + j];
+    const double xq0 = rec[0 * ns + j] + sq * L * rec[3 * ns + j];
+    const double xq1 = rec[1 * ns + j] + sq * L * rec[4 * ns + j];
+    const double xq2 = rec[2 * ns + j] + sq * L * rec[5 * ns + j];
+    const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
+    const float fb0 = (float)bj0, fb1 = (float)bj1, fb2 = (float)bj2;
+    const float fk1 = (float)k1, fk2 = (float)k2;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+
+    for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
+        const int n = (int)min<int64_t>(TILE, it.src_end - base);
+        __syncthreads();
+        if (lane < n) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) shx[k][lane] = rec[k * ns + base + lane];
+            shf[0][lane] = rec32[3 * ns + base + lane];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) shf[1 + k][lane] = rec32[(4 + k) * ns + base + lane];
+        }
+        __syncthreads();
+        float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+        for (int m = 0; m < n; ++m) {
+            const int64_t i = base + m;
+            const double T0 = shx[3][m], T1 = shx[4][m], T2 = shx[5][m];
+            const double R0 = xq0 - shx[0][m], R1 = xq1 - shx[1][m], R2 = xq2 - shx[2][m];
+            const double yd = R0 * T0 + R1 * T1 + R2 * T2;
+            const float y = (float)yd;
+            const float h0 = (float)(R0 - yd * T0), h1 = (float)(R1 - yd * T1), h2 = (float)(R2 - yd * T2);
+            const float Ls = shf[0][m];
+            const float ya = y - fminf(fmaxf(y, 0.f), Ls);
+            const float dmin2 = h0 * h0 + h1 * h1 + h2 * h2 + ya * ya;
+            if (dmin2 < cut2) {
+                if (i != j) {
+                    double c0, c1, c2;
+                    pair_sigma_b_f64(xq0, xq1, xq2, bj0, bj1, bj2, shx[0][m], shx[1][m], shx[2][m],
+                                     T0, T1, T2, rec[6 * ns + i], rec[7 * ns + i], rec[8 * ns + i],
+                                     rec[9 * ns + i], rec[10 * ns + i], rec[11 * ns + i],
+                                     rec[12 * ns + i], k1, k2, c0, c1, c2);
+                    a0 += c0;
+                    a1 += c1;
+                    a2 += c2;
+                }
+            } else {
+                float c0, c1, c2;
+                pair_sigma_b_f32(y, h0, h1, h2, fb0, fb1, fb2, (float)T0, (float)T1, (float)T2, Ls,
+                                 shf[1][m], shf[2][m], shf[3][m], shf[4][m], shf[5][m], shf[6][m],
+                                 fk1, fk2, c0, c1, c2);
+                f0 += c0;
+                f1 += c1;
+                f2 += c2;
+            }
+        }
+        a0 += (double)f0;
+        a1 += (double)f1;
+        a2 += (double)f2;
+    }
+    if (valid) {
+        double *o = partial + it.slot * 3 * TILE;
+        o[lane] = a0;
+        o[TILE + lane] = a1;
+        o[2 * TILE + lane] = a2;
+    }
+}
+
+// ------------------------------ a3 + a4: Peach-Koehler and the quadrature --
+struct Sig6 { double v[6]; };
+
+__global__ void k_segment_ends(Layout L, const Tile *__restrict__ tiles,
+                               const double *__restrict__ partial,
+                               const double *__restrict__ rec, GaussRule g,
+                               const double *__restrict__ sig_dev, Sig6 sig_val,
+                               double inv_mu, double fscale, double *__restrict__ segF)
+{
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t ns = L.ns;
+    if (j >= ns) return;
+    const int inst = seg_instance(L, j);
+    const int Q = g.n;
+    const int64_t lp0 = (j - seg_begin(L, inst)) * Q;
+    const int64_t tb = L.tile_begin ? L.tile_begin[inst] : 0;
+    double S[6];
+    for (int k = 0; k < 6; ++k) S[k] = (sig_dev ? sig_dev[6 * inst + k] : sig_val.v[k]) * inv_mu;
+    const double t0 = rec[3 * ns + j], t1 = rec[4 * ns + j], t2 = rec[5 * ns + j];
+    const double Ls = rec[6 * ns + j];
+    const double b0 = rec[7 * ns + j], b1 = rec[8 * ns + j], b2 = rec[9 * ns + j];
+    // applied part: sigma_app b (Voigt xx yy zz yz xz xy)
+    const double ab0 = S[0] * b0 + S[5] * b1 + S[4] * b2;
+    const double ab1 = S[5] * b0 + S[1] * b1 + S[3] * b2;
+    const double ab2 = S[4] * b0 + S[3] * b1 + S[2] * b2;
+    double F1[3] = {0, 0, 0}, F2[3] = {0, 0, 0};
+    for (int q = 0; q < Q; ++q) {
+        const int64_t lp = lp0 + q;
+        const Tile T = tiles[tb + lp / TILE];
+        const int lane = (int)(lp % TILE);
+        double s0 = 0, s1 = 0, s2 = 0;
+        for (int c = 0; c < T.n_chunks; ++c) {
+            const double *o = partial + (T.slot_begin + c) * 3 * TILE;
+            s0 += o[lane];
+            s1 += o[TILE + lane];
+            s2 += o[2 * TILE + lane];
+        }
+        s0 += ab0;
+        s1 += ab1;
+        s2 += ab2;
+        // f = (sigma b) x t
+        const double f0 = s1 * t2 - s2 * t1;
+        const double f1 = s2 * t0 - s0 * t2;
+        const double f2 = s0 * t1 - s1 * t0;
+        const double w1 = Ls * g.w[q] * (1.0 - g.s[q]), w2 = Ls * g.w[q] * g.s[q];
+        F1[0] += w1 * f0; F1[1] += w1 * f1; F1[2] += w1 * f2;
+        F2[0] += w2 * f0; F2[1] += w2 * f1; F2[2] += w2 * f2;
+    }
+    for (int k = 0; k < 3; ++k) {
+        segF[k * ns + j] = F1[k] * fscale;
+        segF[(3 + k) * ns + j] = F2[k] * fscale;
+    }
+}
+
+// F_n = sum over the node's (segment, end) list in sorted order.
+__global__ void k_node_gather(const int32_t *__restrict__ ptr, const int32_t *__restrict__ list,
+                              int64_t nn, int64_t ns, const double *__restrict__ segF,
+                              double *__restrict__ F)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    double f0 = 0, f1 = 0, f2 = 0;
+    for (int32_t k = ptr[n]; k < ptr[n + 1]; ++k) {
+        const int32_t e = list[k];
+        const int64_t s = e >> 1;
+        const int end = e & 1;
+        f0 += segF[(3 * end + 0) * ns + s];
+        f1 += segF[(3 * end + 1) * ns + s];
+        f2 += segF[(3 * end + 2) * ns + s];
+    }
+    F[n] = f0;
+    F[nn + n] = f1;
+    F[2 * nn + n] = f2;
+}
+
+// ---------------------------------------------- a5 + a6: glide and Euler --
+// Per node: ell = 1/2 sum L_s over attached segments, v = P F / (B ell), with
+// P from the distinct slip-plane normals among them.  FROM_REC: lengths from
+// the segment records (x unchanged since they were made), so the node can be
+// advanced in the same pass; otherwise lengths come from x and the Euler
+// update is a separate kernel.
+template <bool FROM_REC>
+__global__ void k_glide(Layout L, const int32_t *__restrict__ ptr, const int32_t *__restrict__ list,
+                        const int32_t *__restrict__ seg_nodes, const double *__restrict__ normal,
+                        const double *__restrict__ rec, double a, double *x,
+                        const double *__restrict__ F, const uint8_t *__restrict__ pinned,
+                        double invB, double dt, double *__restrict__ vel)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nn = L.nn, ns = L.ns;
+    if (n >= nn) return;
+    double ell = 0.0;
+    double nrm[3][3];
+    int cnt = 0;
+    for (int32_t k = ptr[n]; k < ptr[n + 1]; ++k) {
+        const int64_t s = list[k] >> 1;
+        double Ls;
+        if (FROM_REC) {
+            Ls = rec[6 * ns + s] * a;
+        } else {
+            int64_t g1, g2;
+            seg_ends(L, seg_nodes, s, g1, g2);
+            double d0 = x[g2] - x[g1], d1 = x[nn + g2] - x[nn + g1], d2 = x[2 * nn + g2] - x[2 * nn + g1];
+            Ls = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+        }
+        ell += 0.5 * Ls;
+        const double ns0 = normal[s], ns1 = normal[ns + s], ns2 = normal[2 * ns + s];
+        bool dup = false;
+        for (int c = 0; c < 3; ++c)
+            if (c < cnt && fabs(nrm[c][0] * ns0 + nrm[c][1] * ns1 + nrm[c][2] * ns2) > 1.0 - 1e-12)
+                dup = true;
+        if (!dup) {
+            if (cnt < 3) {
+                nrm[cnt][0] = ns0; nrm[cnt][1] = ns1; nrm[cnt][2] = ns2;
+            }
+            ++cnt;
+        }
+    }
+    double v0 = 0, v1 = 0, v2 = 0;
+    const bool fixed = (pinned && pinned[n]) || !(ell > 0.0) || cnt == 0 || cnt >= 3;
+    if (!fixed) {
+        const double sc = invB / ell;
+        v0 = F[n] * sc;
+        v1 = F[nn + n] * sc;
+        v2 = F[2 * nn + n] * sc;
+        if (cnt == 1) {
+            const double vn = v0 * nrm[0][0] + v1 * nrm[0][1] + v2 * nrm[0][2];
+            v0 -= vn * nrm[0][0];
+            v1 -= vn * nrm[0][1];
+            v2 -= vn * nrm[0][2];
+        } else {
+            double l0 = nrm[0][1] * nrm[1][2] - nrm[0][2] * nrm[1][1];
+            double l1 = nrm[0][2] * nrm[1][0] - nrm[0][0] * nrm[1][2];
+            double l2 = nrm[0][0] * nrm[1][1] - nrm[0][1] * nrm[1][0];
+            const double il = 1.0 / sqrt(l0 * l0 + l1 * l1 + l2 * l2);
+            l0 *= il; l1 *= il; l2 *= il;
+            const double vl = v0 * l0 + v1 * l1 + v2 * l2;
+            v0 = vl * l0; v1 = vl * l1; v2 = vl * l2;
+        }
+    }
+    if (vel) {
+        vel[n] = v0;
+        vel[nn + n] = v1;
+        vel[2 * nn + n] = v2;
+    }
+    if (FROM_REC) {
+        x[n] += v0 * dt;
+        x[nn + n] += v1 * dt;
+        x[2 * nn + n] += v2 * dt;
+    }
+}
+
+__global__ void k_euler(int64_t nn, double *x, const double *__restrict__ vel, double dt)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= 3 * nn) return;
+    x[i] += vel[i] * dt;
+}
+
+// ---------------------------------------------- a7: slip-rate accumulation --
+// One workgroup per instance; 12 sums per lane, reduced in a fixed tree order
+// and added to acc[inst][12].  mode 0: gdot_alpha(k) from velocities;
+// mode 1: features (resolved shear, mobile and sessile densities).
+__global__ __launch_bounds__(256) void k_instance_sums(Layout L, int mode,
+                                                       const int32_t *__restrict__ seg_nodes,
+                                                       const double *__restrict__ rec,
+                                                       const int32_t *__restrict__ sys,
+                                                       const double *__restrict__ vel,
+                                                       const uint8_t *__restrict__ pinned,
+                                                       const double *__restrict__ volume,
+                                                       const double *__restrict__ sig_dev,
+                                                       double a, double *__restrict__ out)
+{
+    __shared__ double red[24][256];
+    const int inst = blockIdx.x;
+    const int64_t s0 = L.seg_off ? L.seg_off[inst] : 0;
+    const int64_t s1 = L.seg_off ? L.seg_off[inst + 1] : L.ns;
+    const int64_t nn = L.nn, ns = L.ns;
+    const double invV = 1.0 / volume[inst];
+    double acc[24];
+    for (int k = 0; k < 24; ++k) acc[k] = 0.0;
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x) {
+        const int al = sys[s];
+        if (al < 0) continue;
+        double n[3], m[3];
+        fcc(al, n, m);
+        const double Ls = rec[6 * ns + s] * a;
+        if (mode == 0) {
+            int64_t g1, g2;
+            seg_ends(L, seg_nodes, s, g1, g2);
+            const double t0 = rec[3 * ns + s], t1 = rec[4 * ns + s], t2 = rec[5 * ns + s];
+            const double vb0 = 0.5 * (vel[g1] + vel[g2]);
+            const double vb1 = 0.5 * (vel[nn + g1] + vel[nn + g2]);
+            const double vb2 = 0.5 * (vel[2 * nn + g1] + vel[2 * nn + g2]);
+            const double c0 = t1 * vb2 - t2 * vb1, c1 = t2 * vb0 - t0 * vb2, c2 = t0 * vb1 - t1 * vb0;
+            const double bm = (rec[7 * ns + s] * m[0] + rec[8 * ns + s] * m[1] + rec[9 * ns + s] * m[2]) * a;
+            const double val = bm * Ls * (c0 * n[0] + c1 * n[1] + c2 * n[2]) * invV;
+            for (int k = 0; k < 12; ++k)
+                if (k == al) acc[k] += val;
+        } else {
+            int64_t g1, g2;
+            seg_ends(L, seg_nodes, s, g1, g2);
+            const bool ses = pinned && pinned[g1] && pinned[g2];
+            for (int k = 0; k < 12; ++k)
+                if (k == al) {
+                    if (ses) acc[12 + k] += Ls * invV;
+                    else acc[k] += Ls * invV;
+                }
+        }
+    }
+    const int nv = mode == 0 ? 12 : 24;
+    for (int k = 0; k < nv; ++k) red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int k = 0; k < nv; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (mode == 0) {
+            for (int k = 0; k < 12; ++k) out[12 * inst + k] += red[k][0];
+        } else {
+            double S[3][3];
+            const double *sv = sig_dev + 6 * inst;
+            S[0][0] = sv[0]; S[1][1] = sv[1]; S[2][2] = sv[2];
+            S[1][2] = S[2][1] = sv[3];
+            S[0][2] = S[2][0] = sv[4];
+            S[0][1] = S[1][0] = sv[5];
+            for (int al = 0; al < 12; ++al) {
+                double n[3], m[3];
+                fcc(al, n, m);
+                double tau = 0.0;
+                for (int r = 0; r < 3; ++r)
+                    for (int c = 0; c < 3; ++c) tau += m[r] * S[r][c] * n[c];
+                out[36 * inst + al] = tau;
+                out[36 * inst + 12 + al] = red[al][0];
+                out[36 * inst + 24 + al] = red[12 + al][0];
+            }
+        }
+    }
+}
+
+__global__ void k_scale_rates(double *acc, int64_t n, double inv_steps)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) acc[i] *= inv_steps;
+}
+
+// =================================================================== host ==
+namespace {
+
+int check_material(const dd_material *m, bool need_B)
+{
+    if (!m) return set_error(DD_EINVAL, "material is null");
+    if (!(m->mu > 0.0) || !std::isfinite(m->mu)) return set_error(DD_EINVAL, "mu must be > 0");
+    if (!(m->nu > -1.0 && m->nu < 0.5)) return set_error(DD_EINVAL, "nu must lie in (-1, 0.5)");
+    if (!(m->a > 0.0) || !std::isfinite(m->a)) return set_error(DD_EINVAL, "core width a must be > 0");
+    if (need_B && (!(m->B > 0.0) || !std::isfinite(m->B))) return set_error(DD_EINVAL, "drag B must be > 0");
+    return DD_OK;
+}
+
+int read_flags(Workspace *ws, hipStream_t st)
+{
+    DD_HIP(hipMemcpyAsync(ws->flags_host, ws->flags_dev, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    unsigned f = *ws->flags_host;
+    if (f & FLAG_BAD_INDEX) return set_error(DD_EINVAL, "a segment references a node index outside its instance");
+    if (f & FLAG_ZERO_LENGTH) return set_error(DD_EINVAL, "zero-length (or non-finite) segment");
+    if (f & FLAG_BAD_NORMAL) return set_error(DD_EINVAL, "slip-plane normal is not of unit length");
+    if (f & FLAG_NONFINITE) return set_error(DD_ENONFINITE, "non-finite value in an output");
+    return DD_OK;
+}
+
+// Work decomposition for a set of instances (host tables).
+struct Plan {
+    std::vector<Tile> tiles;
+    std::vector<Item> items;
+    std::vector<int64_t> tile_begin;   // [n_inst+1]
+    int64_t chunk_len = 0;
+};
+
+// chunk_len <= 0: choose so that a single large volume fills the chip.
+void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Plan &P)
+{
+    const int n_inst = (int)seg_off.size() - 1;
+    P.tiles.clear();
+    P.items.clear();
+    P.tile_begin.assign(n_inst + 1, 0);
+    if (chunk_len <= 0) {
+        int64_t total_tiles = 0, max_src = 0;
+        for (int i = 0; i < n_inst; ++i) {
+            int64_t N = seg_off[i + 1] - seg_off[i];
+            total_tiles += (N * Q + TILE - 1) / TILE;
+            max_src = std::max(max_src, N);
+        }
+        const int64_t want_items = 2048;
+        int64_t chunks = total_tiles > 0 ? (want_items + total_tiles - 1) / total_tiles : 1;
+        chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, (max_src + TILE - 1) / TILE));
+        chunk_len = (max_src + chunks - 1) / chunks;
+        chunk_len = std::max<int64_t>(TILE, (chunk_len + TILE - 1) / TILE * TILE);
+    }
+    P.chunk_len = chunk_len;
+    int64_t slot = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const int64_t s0 = seg_off[i], N = seg_off[i + 1] - s0;
+        P.tile_begin[i] = (int64_t)P.tiles.size();
+        const int64_t npts = N * Q;
+        const int nchunks = N > 0 ? (int)((N + chunk_len - 1) / chunk_len) : 0;
+        for (int64_t pb = 0; pb < npts; pb += TILE) {
+            Tile t;
+            t.point_begin = s0 * Q + pb;
+            t.n_points = (int32_t)std::min<int64_t>(TILE, npts - pb);
+            t.n_chunks = nchunks;
+            t.slot_begin = slot;
+            const int32_t tidx = (int32_t)P.tiles.size();
+            P.tiles.push_back(t);
+            for (int c = 0; c < nchunks; ++c) {
+                Item it;
+                it.tile = tidx;
+                it.pad = 0;
+                it.src_begin = s0 + c * chunk_len;
+                it.src_end = std::min(s0 + N, it.src_begin + chunk_len);
+                it.slot = slot++;
+                P.items.push_back(it);
+            }
+        }
+    }
+    P.tile_begin[n_inst] = (int64_t)P.tiles.size();
+    // longest items first: the dispatcher hands out workgroups in index order,
+    // which makes this a longest-processing-time-first schedule
+    std::stable_sort(P.items.begin(), P.items.end(), [&](const Item &a, const Item &b) {
+        const int64_t ca = (int64_t)P.tiles[a.tile].n_points * (a.src_end - a.src_begin);
+        const int64_t cb = (int64_t)P.tiles[b.tile].n_points * (b.src_end - b.src_begin);
+        return ca > cb;
+    });
+}
+
+template <class T>
+int upload(Workspace *ws, Slot s, const std::vector<T> &v, T **dev, hipStream_t st)
+{
+    void *p;
+    int rc = ensure(ws, s, v.size() * sizeof(T), &p);
+    if (rc) return rc;
+    if (!v.empty()) {
+        DD_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        DD_HIP(hipStreamSynchronize(st));   // v is pageable and short-lived
+    }
+    *dev = (T *)p;
+    return DD_OK;
+}
+
+// Device state of one force evaluation set-up.
+struct ForceCtx {
+    Layout L{};
+    double *rec64 = nullptr;
+    float *rec32 = nullptr;
+    int32_t *sys = nullptr;
+    double *partial = nullptr;
+    double *segF = nullptr;
+    int32_t *csr_ptr = nullptr, *csr_list = nullptr, *csr_cnt = nullptr;
+    Tile *tiles = nullptr;
+    Item *items = nullptr;
+    int64_t n_items = 0;
+    GaussRule g{};
+    double k1 = 0, k2 = 0, inv_a = 0, inv_mu = 0, fscale = 0, a = 0;
+    int precision = DD_FP64;
+    float cut2 = 0.f;
+};
+
+// Cache of the last uploaded plan (the tables depend only on sizes).
+struct PlanKey {
+    std::vector<int64_t> seg_off;
+    int Q = 0;
+    int64_t chunk_len = -1;
+    bool operator==(const PlanKey &o) const
+    {
+        return Q == o.Q && chunk_len == o.chunk_len && seg_off == o.seg_off;
+    }
+};
+PlanKey g_plan_key;   // guarded by the single-caller-per-device rule
+int g_plan_dev = -1;
+int64_t g_plan_items = 0;
+int64_t g_plan_chunk = 0;
+
+int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, int64_t nn,
+          const int32_t *seg_nodes, const dd_material *m, int n_gauss, int precision,
+          double near_cut, int64_t chunk_len, bool need_sys, ForceCtx &C)
+{
+    const int64_t ns = seg_off_h.back();
+    const int n_inst = (int)seg_off_h.size() - 1;
+    C.g = gauss_rule(n_gauss);
+    C.k1 = 1.0 / (8.0 * M_PI);
+    C.k2 = 1.0 / (4.0 * M_PI * (1.0 - m->nu));
+    C.a = m->a;
+    C.inv_a = 1.0 / m->a;
+    C.inv_mu = 1.0 / m->mu;
+    C.fscale = m->mu * m->a * m->a;
+    C.precision = precision;
+    C.cut2 = (float)(near_cut * near_cut);
+    C.L.nn = nn;
+    C.L.ns = ns;
+    void *p;
+    int rc;
+    if ((rc = ensure(ws, WS_SEG64, sizeof(double) * REC64 * std::max<int64_t>(ns, 1), &p))) return rc;
+    C.rec64 = (double *)p;
+    if (precision == DD_MIXED) {
+        if ((rc = ensure(ws, WS_SEG32, sizeof(float) * REC32 * std::max<int64_t>(ns, 1), &p))) return rc;
+        C.rec32 = (float *)p;
+    }
+    if (need_sys) {
+        if ((rc = ensure(ws, WS_MISC, sizeof(int32_t) * std::max<int64_t>(ns, 1), &p))) return rc;
+        C.sys = (int32_t *)p;
+    }
+    if ((rc = ensure(ws, WS_SEGF, sizeof(double) * 6 * std::max<int64_t>(ns, 1), &p))) return rc;
+    C.segF = (double *)p;
+    if ((rc = ensure(ws, WS_CSR_PTR, sizeof(int32_t) * (nn + 1), &p))) return rc;
+    C.csr_ptr = (int32_t *)p;
+    if ((rc = ensure(ws, WS_CSR_LIST, sizeof(int32_t) * std::max<int64_t>(2 * ns, 1), &p))) return rc;
+    C.csr_list = (int32_t *)p;
+    if ((rc = ensure(ws, WS_CSR_CNT, sizeof(int32_t) * std::max<int64_t>(nn, 1), &p))) return rc;
+    C.csr_cnt = (int32_t *)p;
+
+    // plan tables (cached by size)
+    PlanKey key;
+    key.seg_off = seg_off_h;
+    key.Q = n_gauss;
+    key.chunk_len = chunk_len;
+    if (!(key == g_plan_key) || g_plan_dev != ws->device || !ws->ptr[WS_TILES]) {
+        Plan P;
+        make_plan(seg_off_h, n_gauss, chunk_len, P);
+        Tile *dt;
+        Item *di;
+        int64_t *dtb;
+        if ((rc = upload(ws, WS_TILES, P.tiles, &dt, st))) return rc;
+        if ((rc = upload(ws, WS_ITEMS, P.items, &di, st))) return rc;
+        std::vector<int64_t> offs;   // [tile_begin (n_inst+1)]
+        offs = P.tile_begin;
+        if ((rc = upload(ws, WS_OFFS, offs, &dtb, st))) return rc;
+        g_plan_key = key;
+        g_plan_dev = ws->device;
+        g_plan_items = (int64_t)P.items.size();
+        g_plan_chunk = P.chunk_len;
+    }
+    C.tiles = (Tile *)ws->ptr[WS_TILES];
+    C.items = (Item *)ws->ptr[WS_ITEMS];
+    C.L.tile_begin = n_inst > 1 ? (const int64_t *)ws->ptr[WS_OFFS] : nullptr;
+    C.n_items = g_plan_items;
+    if ((rc = ensure(ws, WS_PARTIAL, sizeof(double) * 3 * TILE * std::max<int64_t>(C.n_items, 1), &p)))
+        return rc;
+    C.partial = (double *)p;
+    (void)seg_nodes;
+    return DD_OK;
+}
+
+// Topology-only work: CSR of node -> (segment, end).
+void launch_csr(const ForceCtx &C, const int32_t *seg_nodes, hipStream_t st)
+{
+    const int64_t nn = C.L.nn, ns = C.L.ns;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nn)), dim3(256), 0, st, (unsigned *)C.csr_cnt, nn, 0u);
+    hipLaunchKernelGGL(k_csr_count, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L, seg_nodes,
+                       C.csr_cnt);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, C.csr_cnt, nn, C.csr_ptr);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nn)), dim3(256), 0, st, (unsigned *)C.csr_cnt, nn, 0u);
+    hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L, seg_nodes,
+                       C.csr_ptr, C.csr_cnt, C.csr_list);
+    hipLaunchKernelGGL(k_csr_sort, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, st, C.csr_ptr, nn,
+                       C.csr_list);
+}
+
+// a1..a4 for positions x: segment records, pair kernel, epilogue, gather.
+void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int32_t *seg_nodes,
+                   const double *burgers, const double *normal, const double *sig_dev, Sig6 sig_val,
+                   double *F, hipStream_t st)
+{
+    const int64_t nn = C.L.nn, ns = C.L.ns;
+    if (ns > 0) {
+        PrepArgs A;
+        A.L = C.L;
+        A.x = x;
+        A.seg_nodes = seg_nodes;
+        A.burgers = burgers;
+        A.normal = normal;
+        A.inv_a = C.inv_a;
+        A.rec64 = C.rec64;
+        A.rec32 = C.rec32;
+        A.sys = C.sys;
+        A.flags = ws->flags_dev;
+        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
+        if (C.n_items > 0) {
+            if (C.precision == DD_MIXED)
+                hipLaunchKernelGGL(k_pair_mixed, dim3((unsigned)C.n_items), dim3(TILE), 0, st, C.items,
+                                   C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut2, C.partial);
+            else
+                hipLaunchKernelGGL(k_pair64, dim3((unsigned)C.n_items), dim3(TILE), 0, st, C.items,
+                                   C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial);
+        }
+        hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
+                           C.tiles, C.partial, C.rec64, C.g, sig_dev, sig_val, C.inv_mu, C.fscale,
+                           C.segF);
+    }
+    hipLaunchKernelGGL(k_node_gather, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, st, C.csr_ptr,
+                       C.csr_list, nn, ns, C.segF, F);
+}
+
+int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, double near_cut)
+{
+    if (n_nodes < 0 || n_segs < 0) return set_error(DD_EINVAL, "negative node or segment count");
+    if (n_nodes >= INT32_MAX || 2 * n_segs >= INT32_MAX)
+        return set_error(DD_EINVAL, "more than 2^31 nodes or 2^30 segments");
+    if (n_segs > 0 && n_nodes == 0) return set_error(DD_EINVAL, "segments without nodes");
+    if (n_gauss < 1 || n_gauss > DD_MAX_GAUSS) return set_error(DD_EINVAL, "n_gauss must be in 1..16");
+    if (precision != DD_FP64 && precision != DD_MIXED) return set_error(DD_EINVAL, "unknown precision");
+    if (precision == DD_MIXED && !(near_cut > 0.0)) return set_error(DD_EINVAL, "near_cutoff_a must be > 0");
+    return DD_OK;
+}
+
+}  // namespace
+}  // namespace dd
+
+using namespace dd;
+
+extern "C" int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
+                               const int32_t *seg_nodes, const double *burgers,
+                               const double *normal, const double *sigma_app,
+                               const dd_material *m, int n_gauss, int precision,
+                               double near_cutoff_a, double *force_out, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a))) return rc;
+    if ((rc = check_material(m, false))) return rc;
+    if (!sigma_app) return set_error(DD_EINVAL, "sigma_app is null");
+    if (n_nodes > 0 && (!x || !force_out)) return set_error(DD_EINVAL, "null x or force_out");
+    if (n_segs > 0 && (!seg_nodes || !burgers || !normal)) return set_error(DD_EINVAL, "null segment array");
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(sigma_app[k])) return set_error(DD_EINVAL, "non-finite sigma_app");
+    if (n_nodes == 0) return DD_OK;
+    hipStream_t st = (hipStream_t)stream;
+    Workspace *ws;
+    if ((rc = workspace(&ws))) return rc;
+    ForceCtx C;
+    std::vector<int64_t> so = {0, n_segs};
+    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, 0, false, C)))
+        return rc;
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
+    launch_csr(C, seg_nodes, st);
+    Sig6 sv;
+    for (int k = 0; k < 6; ++k) sv.v[k] = sigma_app[k];
+    launch_forces(C, ws, x, seg_nodes, burgers, normal, nullptr, sv, force_out, st);
+    DD_HIP(hipGetLastError());
+    if (validation_on()) {
+        hipLaunchKernelGGL(k_check_finite, dim3(grid_for(3 * n_nodes)), dim3(256), 0, st, force_out,
+                           3 * n_nodes, ws->flags_dev);
+        return read_flags(ws, st);
+    }
+    return DD_OK;
+}
+
+extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, int64_t n_segs,
+                             const int32_t *seg_nodes, const double *normal, const uint8_t *pinned,
+                             const dd_material *m, double dt, double *vel_out, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = common_checks(n_nodes, n_segs, 1, DD_FP64, 1.0))) return rc;
+    if (!m || !(m->B > 0.0) || !std::isfinite(m->B)) return set_error(DD_EINVAL, "drag B must be > 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(DD_EINVAL, "dt must be > 0");
+    if (n_nodes > 0 && (!x || !force)) return set_error(DD_EINVAL, "null x or force");
+    if (n_segs > 0 && (!seg_nodes || !normal)) return set_error(DD_EINVAL, "null segment array");
+    if (n_nodes == 0) return DD_OK;
+    hipStream_t st = (hipStream_t)stream;
+    Workspace *ws;
+    if ((rc = workspace(&ws))) return rc;
+    Layout L{};
+    L.nn = n_nodes;
+    L.ns = n_segs;
+    void *p;
+    if ((rc = ensure(ws, WS_CSR_PTR, sizeof(int32_t) * (n_nodes + 1), &p))) return rc;
+    ForceCtx C;
+    C.L = L;
+    C.csr_ptr = (int32_t *)p;
+    if ((rc = ensure(ws, WS_CSR_LIST, sizeof(int32_t) * std::max<int64_t>(2 * n_segs, 1), &p))) return rc;
+    C.csr_list = (int32_t *)p;
+    if ((rc = ensure(ws, WS_CSR_CNT, sizeof(int32_t) * n_nodes, &p))) return rc;
+    C.csr_cnt = (int32_t *)p;
+    double *vel = vel_out;
+    if (!vel) {
+        if ((rc = ensure(ws, WS_VEL, sizeof(double) * 3 * n_nodes, &p))) return rc;
+        vel = (double *)p;
+    }
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
+    launch_csr(C, seg_nodes, st);
+    if (validation_on() && n_segs > 0) {
+        // index and normal checks (the prep kernel also computes lengths)
+        if ((rc = ensure(ws, WS_SEG64, sizeof(double) * REC64 * n_segs, &p))) return rc;
+        PrepArgs A{};
+        A.L = L;
+        A.x = x;
+        A.seg_nodes = seg_nodes;
+        A.burgers = normal;   // any [3][n_segs] array: only the checks matter here
+        A.normal = normal;
+        A.inv_a = 1.0;
+        A.rec64 = (double *)p;
+        A.flags = ws->flags_dev;
+        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(n_segs, 256, INT32_MAX)), dim3(256), 0, st, A);
+    }
+    hipLaunchKernelGGL(k_glide<false>, dim3(grid_for(n_nodes, 256, INT32_MAX)), dim3(256), 0, st, L,
+                       C.csr_ptr, C.csr_list, seg_nodes, normal, (const double *)nullptr, 1.0, x, force,
+                       pinned, 1.0 / m->B, dt, vel);
+    hipLaunchKernelGGL(k_euler, dim3(grid_for(3 * n_nodes, 256, INT32_MAX)), dim3(256), 0, st, n_nodes, x,
+                       vel, dt);
+    DD_HIP(hipGetLastError());
+    if (validation_on()) {
+        hipLaunchKernelGGL(k_check_finite, dim3(grid_for(3 * n_nodes)), dim3(256), 0, st, x, 3 * n_nodes,
+                           ws->flags_dev);
+        return read_flags(ws, st);
+    }
+    return DD_OK;
+}
+
+extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                              const int32_t *seg_nodes, const double *burgers, const double *normal,
+                              const uint8_t *pinned, const double *sigma_app, const double *volume,
+                              const dd_material *m, int n_gauss, int precision, double near_cutoff_a,
+                              int n_steps, double dt, double *rate_avg_out, double *features_out,
+                              void *stream)
+{
+    clear_error();
+    int rc;
+    if (n_inst < 0) return set_error(DD_EINVAL, "n_inst < 0");
+    if (n_inst == 0) return DD_OK;
+    if (!node_off || !seg_off) return set_error(DD_EINVAL, "null offsets");
+    if (node_off[0] != 0 || seg_off[0] != 0) return set_error(DD_EINVAL, "offsets must start at 0");
+    for (int i = 0; i < n_inst; ++i)
+        if (node_off[i + 1] < node_off[i] || seg_off[i + 1] < seg_off[i])
+            return set_error(DD_EINVAL, "offsets must be non-decreasing");
+    for (int i = 0; i < n_inst; ++i)
+        if (seg_off[i + 1] > seg_off[i] && node_off[i + 1] == node_off[i])
+            return set_error(DD_EINVAL, "instance %d has segments but no nodes", i);
+    const int64_t nn = node_off[n_inst], ns = seg_off[n_inst];
+    if ((rc = common_checks(nn, ns, n_gauss, precision, near_cutoff_a))) return rc;
+    if ((rc = check_material(m, true))) return rc;
+    if (n_steps < 0) return set_error(DD_EINVAL, "n_steps < 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(DD_EINVAL, "dt must be > 0");
+    if (!sigma_app || !volume || !rate_avg_out) return set_error(DD_EINVAL, "null sigma_app, volume or rate_avg_out");
+    if (nn > 0 && !x) return set_error(DD_EINVAL, "null x");
+    if (ns > 0 && (!seg_nodes || !burgers || !normal)) return set_error(DD_EINVAL, "null segment array");
+    hipStream_t st = (hipStream_t)stream;
+    Workspace *ws;
+    if ((rc = workspace(&ws))) return rc;
+
+    std::vector<int64_t> so(seg_off, seg_off + n_inst + 1), no(node_off, node_off + n_inst + 1);
+    ForceCtx C;
+    if ((rc = setup(ws, st, so, nn, seg_nodes, m, n_gauss, precision, near_cutoff_a, 0, true, C))) return rc;
+    // instance tables: seg -> instance, node and segment offsets
+    std::vector<int32_t> si((size_t)std::max<int64_t>(ns, 1), 0);
+    for (int i = 0; i < n_inst; ++i)
+        for (int64_t s = so[i]; s < so[i + 1]; ++s) si[s] = i;
+    int32_t *d_si;
+    if ((rc = upload(ws, WS_SEG_INST, si, &d_si, st))) return rc;
+    std::vector<int64_t> offs;
+    offs.insert(offs.end(), no.begin(), no.end());
+    offs.insert(offs.end(), so.begin(), so.end());
+    // instance node offsets then segment offsets (the tile offsets of the
+    // plan live in WS_OFFS)
+    int64_t *d_offs;
+    if ((rc = upload(ws, WS_INST_OFFS, offs, &d_offs, st))) return rc;
+    C.L.seg_inst = d_si;
+    C.L.node_off = d_offs;
+    C.L.seg_off = d_offs + (n_inst + 1);
+    C.L.tile_begin = (const int64_t *)ws->ptr[WS_OFFS];
+    void *p;
+    if ((rc = ensure(ws, WS_VEL, sizeof(double) * 3 * std::max<int64_t>(nn, 1), &p))) return rc;
+    double *vel = (double *)p;
+    if ((rc = ensure(ws, WS_FORCE, sizeof(double) * 3 * std::max<int64_t>(nn, 1), &p))) return rc;
+    double *F = (double *)p;
+
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
+    launch_csr(C, seg_nodes, st);
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(12 * (int64_t)n_inst)), dim3(256), 0, st, rate_avg_out,
+                       12 * (int64_t)n_inst, 0.0);
+    Sig6 sv{};
+    // features of the initial state
+    if (features_out && ns > 0) {
+        PrepArgs A;
+        A.L = C.L;
+        A.x = x;
+        A.seg_nodes = seg_nodes;
+        A.burgers = burgers;
+        A.normal = normal;
+        A.inv_a = C.inv_a;
+        A.rec64 = C.rec64;
+        A.rec32 = C.rec32;
+        A.sys = C.sys;
+        A.flags = ws->flags_dev;
+        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
+        hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, st, C.L, 1, seg_nodes, C.rec64, C.sys,
+                           (const double *)nullptr, pinned, volume, sigma_app, C.a, features_out);
+    } else if (features_out) {
+        hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(36 * (int64_t)n_inst)), dim3(256), 0, st, features_out,
+                           36 * (int64_t)n_inst, 0.0);
+    }
+    DD_HIP(hipGetLastError());
+
+    if (n_steps > 0 && ns > 0) {
+        // capture the whole step loop once, launch it as one graph
+        if (!ws->capture_stream) DD_HIP(hipStreamCreateWithFlags(&ws->capture_stream, hipStreamNonBlocking));
+        hipStream_t cs = ws->capture_stream;
+        DD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        for (int k = 0; k < n_steps; ++k) {
+            launch_forces(C, ws, x, seg_nodes, burgers, normal, sigma_app, sv, F, cs);
+            hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
+                               C.csr_ptr, C.csr_list, seg_nodes, normal, C.rec64, C.a, x, F, pinned,
+                               1.0 / m->B, dt, vel);
+            hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 0, seg_nodes, C.rec64,
+                               C.sys, vel, pinned, volume, sigma_app, C.a, rate_avg_out);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (e != hipSuccess) return set_error(DD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return set_error(DD_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        e = hipGraphLaunch(exec, st);
+        hipError_t e2 = hipStreamSynchronize(st);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return set_error(DD_EHIP, "graph launch failed: %s", hipGetErrorString(e));
+        if (e2 != hipSuccess) return set_error(DD_EHIP, "burst execution failed: %s", hipGetErrorString(e2));
+        hipLaunchKernelGGL(k_scale_rates, dim3(grid_for(12 * (int64_t)n_inst, 256, INT32_MAX)), dim3(256), 0,
+                           st, rate_avg_out, 12 * (int64_t)n_inst, 1.0 / n_steps);
+    }
+    DD_HIP(hipGetLastError());
+    if (validation_on()) {
+        hipLaunchKernelGGL(k_check_finite, dim3(grid_for(12 * (int64_t)n_inst)), dim3(256), 0, st,
+                           rate_avg_out, 12 * (int64_t)n_inst, ws->flags_dev);
+        if (nn > 0)
+            hipLaunchKernelGGL(k_check_finite, dim3(grid_for(3 * nn)), dim3(256), 0, st, x, 3 * nn,
+                               ws->flags_dev);
+        return read_flags(ws, st);
+    }
+    DD_HIP(hipStreamSynchronize(st));
+    return DD_OK;
+}

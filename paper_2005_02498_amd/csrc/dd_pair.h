@@ -1,0 +1,126 @@
+// Per-pair device functions: contribution sigma^i(x) b_j of one source
+// segment i to the stress at a target Gauss point x, already contracted with
+// the target's Burgers vector (the Peach-Koehler force is linear in sigma,
+// so partial sums of sigma b_j can be accumulated instead of 6 stresses).
+//
+// Closed form (lengths in units of the core width a, stress in units of mu):
+// with R0 = x - x1, y = R0.t, rho = R0 - y t, d2 = rho.rho + 1, the endpoint
+// coordinates u1 = -y and u2 = L - y, Ra_k = sqrt(d2 + u_k^2) and the line
+// integrals I_{n,k} = int u^k Ra^-n du over [u1, u2] of the non-singular
+// isotropic kernel, the field of the straight segment regroups as
+//   sigma = S(t, w) + S(rho, z) + kd 1,    S(p, r) = p (x) r + r (x) p,
+//   w  = -k1 g0 (rho x b) + (k2 I31 - k1 g1) c + q k2 (1.5 I52 t - 3 I51 rho)
+//   z  = -k2 I30 c + 1.5 q k2 I50 rho
+//   kd = q k2 (I30 + 3 I50)
+// with c = b x t, q = c.rho, g0 = 2 I30 + 3 I50, g1 = 2 I31 + 3 I51,
+// k1 = 1/(8 pi), k2 = 1/(4 pi (1 - nu)); then
+//   sigma b_j = t (w.b_j) + w (t.b_j) + rho (z.b_j) + z (rho.b_j) + kd b_j.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dd {
+
+// FP64: endpoint differences taken directly,
+//   I30 = (s2 - s1)/d2, I31 = r1 - r2, I50 = ((3 s2 - s2^3) - (3 s1 - s1^3))/(3 d2^2),
+//   I51 = (r1^3 - r2^3)/3, I52 = (s2^3 - s1^3)/(3 d2), with r = 1/Ra, s = u r.
+__device__ __forceinline__ void pair_sigma_b_f64(
+    double x0, double x1, double x2, double bj0, double bj1, double bj2,
+    double p0, double p1, double p2, double t0, double t1, double t2, double L,
+    double b0, double b1, double b2, double c0, double c1, double c2,
+    double k1, double k2, double &o0, double &o1, double &o2)
+{
+    const double R0 = x0 - p0, R1 = x1 - p1, R2 = x2 - p2;
+    const double y = R0 * t0 + R1 * t1 + R2 * t2;
+    const double h0 = R0 - y * t0, h1 = R1 - y * t1, h2 = R2 - y * t2;   // rho
+    const double d2 = h0 * h0 + h1 * h1 + h2 * h2 + 1.0;
+    const double u2 = L - y;
+    const double r1 = rsqrt(d2 + y * y);
+    const double r2 = rsqrt(d2 + u2 * u2);
+    const double id2 = 1.0 / d2;
+    const double s1 = -y * r1, s2 = u2 * r2;
+    const double s1c = s1 * s1 * s1, s2c = s2 * s2 * s2;
+    const double I30 = (s2 - s1) * id2;
+    const double I31 = r1 - r2;
+    const double I50 = ((3.0 * s2 - s2c) - (3.0 * s1 - s1c)) * (id2 * id2) * (1.0 / 3.0);
+    const double I51 = (r1 * r1 * r1 - r2 * r2 * r2) * (1.0 / 3.0);
+    const double I52 = (s2c - s1c) * id2 * (1.0 / 3.0);
+    const double g0 = 2.0 * I30 + 3.0 * I50;
+    const double g1 = 2.0 * I31 + 3.0 * I51;
+    const double q = c0 * h0 + c1 * h1 + c2 * h2;
+    const double rb0 = h1 * b2 - h2 * b1, rb1 = h2 * b0 - h0 * b2, rb2 = h0 * b1 - h1 * b0;
+    const double A = -k1 * g0, Cc = k2 * I31 - k1 * g1, qk = q * k2;
+    const double Tt = 1.5 * qk * I52, Tr = -3.0 * qk * I51;
+    const double w0 = A * rb0 + Cc * c0 + Tt * t0 + Tr * h0;
+    const double w1 = A * rb1 + Cc * c1 + Tt * t1 + Tr * h1;
+    const double w2 = A * rb2 + Cc * c2 + Tt * t2 + Tr * h2;
+    const double Zc = -k2 * I30, Zr = 1.5 * qk * I50;
+    const double z0 = Zc * c0 + Zr * h0, z1 = Zc * c1 + Zr * h1, z2 = Zc * c2 + Zr * h2;
+    const double kd = qk * (I30 + 3.0 * I50);
+    const double wb = w0 * bj0 + w1 * bj1 + w2 * bj2;
+    const double tb = t0 * bj0 + t1 * bj1 + t2 * bj2;
+    const double zb = z0 * bj0 + z1 * bj1 + z2 * bj2;
+    const double hb = h0 * bj0 + h1 * bj1 + h2 * bj2;
+    o0 = t0 * wb + w0 * tb + h0 * zb + z0 * hb + kd * bj0;
+    o1 = t1 * wb + w1 * tb + h1 * zb + z1 * hb + kd * bj1;
+    o2 = t2 * wb + w2 * tb + h2 * zb + z2 * hb + kd * bj2;
+}
+
+// FP32, far pairs.  y and rho are formed in FP64 by the caller and rounded
+// once.  The endpoint differences are rearranged so that no two nearly equal
+// numbers are subtracted when the target lies far away or on the extension
+// of the segment:
+//   I31 = L (u1 + u2) r1 r2 / (Ra1 + Ra2)
+//   I30 = L (u1 + u2) r1 r2 / (u2 Ra1 + u1 Ra2)          if u1 u2 > 0
+//       = (s2 - s1) / d2                                 otherwise
+//   1 - s1 s2 = r1 r2 P,  P = d2 (d2 + u1^2 + u2^2) / (Ra1 Ra2 + u1 u2)  if u1 u2 > 0
+//                         P = Ra1 Ra2 - u1 u2                            otherwise
+//   I50 = I30 (d2 (r1^2 + r2^2) + r1 r2 P) / (3 d2)
+//   I51 = I31 (r1^2 + r1 r2 + r2^2) / 3
+//   I52 = I30 (s1^2 + s1 s2 + s2^2) / 3
+// (from s2^3 - s1^3 = (s2 - s1)(s1^2 + s1 s2 + s2^2), 1 - s^2 = d2 r^2 and
+// u2^2 Ra1^2 - u1^2 Ra2^2 = d2 (u2^2 - u1^2)).
+__device__ __forceinline__ void pair_sigma_b_f32(
+    float y, float h0, float h1, float h2, float bj0, float bj1, float bj2,
+    float t0, float t1, float t2, float L, float b0, float b1, float b2,
+    float c0, float c1, float c2, float k1, float k2, float &o0, float &o1, float &o2)
+{
+    const float d2 = h0 * h0 + h1 * h1 + h2 * h2 + 1.0f;
+    const float u1 = -y, u2 = L - y;
+    const float Ra1s = d2 + u1 * u1, Ra2s = d2 + u2 * u2;
+    const float r1 = __builtin_amdgcn_rsqf(Ra1s), r2 = __builtin_amdgcn_rsqf(Ra2s);
+    const float Ra1 = Ra1s * r1, Ra2 = Ra2s * r2;
+    const float s1 = u1 * r1, s2 = u2 * r2;
+    const float rr = r1 * r2;
+    const float Lus = L * (L - 2.0f * y) * rr;
+    const bool same = u1 * u2 > 0.0f;
+    const float id2 = __builtin_amdgcn_rcpf(d2);
+    const float I30 = same ? Lus * __builtin_amdgcn_rcpf(u2 * Ra1 + u1 * Ra2) : (s2 - s1) * id2;
+    const float P = same ? d2 * (d2 + u1 * u1 + u2 * u2) * __builtin_amdgcn_rcpf(Ra1 * Ra2 + u1 * u2)
+                         : Ra1 * Ra2 - u1 * u2;
+    const float I31 = Lus * __builtin_amdgcn_rcpf(Ra1 + Ra2);
+    const float I50 = I30 * (d2 * (r1 * r1 + r2 * r2) + rr * P) * id2 * (1.0f / 3.0f);
+    const float I51 = I31 * (r1 * r1 + rr + r2 * r2) * (1.0f / 3.0f);
+    const float I52 = I30 * (s1 * s1 + s1 * s2 + s2 * s2) * (1.0f / 3.0f);
+    const float g0 = 2.0f * I30 + 3.0f * I50;
+    const float g1 = 2.0f * I31 + 3.0f * I51;
+    const float q = c0 * h0 + c1 * h1 + c2 * h2;
+    const float rb0 = h1 * b2 - h2 * b1, rb1 = h2 * b0 - h0 * b2, rb2 = h0 * b1 - h1 * b0;
+    const float A = -k1 * g0, Cc = k2 * I31 - k1 * g1, qk = q * k2;
+    const float Tt = 1.5f * qk * I52, Tr = -3.0f * qk * I51;
+    const float w0 = A * rb0 + Cc * c0 + Tt * t0 + Tr * h0;
+    const float w1 = A * rb1 + Cc * c1 + Tt * t1 + Tr * h1;
+    const float w2 = A * rb2 + Cc * c2 + Tt * t2 + Tr * h2;
+    const float Zc = -k2 * I30, Zr = 1.5f * qk * I50;
+    const float z0 = Zc * c0 + Zr * h0, z1 = Zc * c1 + Zr * h1, z2 = Zc * c2 + Zr * h2;
+    const float kd = qk * (I30 + 3.0f * I50);
+    const float wb = w0 * bj0 + w1 * bj1 + w2 * bj2;
+    const float tb = t0 * bj0 + t1 * bj1 + t2 * bj2;
+    const float zb = z0 * bj0 + z1 * bj1 + z2 * bj2;
+    const float hb = h0 * bj0 + h1 * bj1 + h2 * bj2;
+    o0 = t0 * wb + w0 * tb + h0 * zb + z0 * hb + kd * bj0;
+    o1 = t1 * wb + w1 * tb + h1 * zb + z1 * hb + kd * bj1;
+    o2 = t2 * wb + w2 * tb + h2 * zb + z2 * hb + kd * bj2;
+}
+
+}  // namespace dd

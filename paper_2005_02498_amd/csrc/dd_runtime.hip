@@ -1,0 +1,151 @@
+// Host runtime of libdd.so: error reporting, per-device workspace, the
+// Gauss-Legendre rule, version/validation switches.
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "dd_common.h"
+
+namespace dd {
+
+namespace {
+thread_local char g_msg[1024] = "";
+std::atomic<int> g_validate{1};
+std::mutex g_ws_mu;
+std::vector<Workspace *> g_ws;   // indexed by device ordinal
+}  // namespace
+
+int set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_msg, sizeof g_msg, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { g_msg[0] = 0; }
+
+bool validation_on() { return g_validate.load() != 0; }
+
+int workspace(Workspace **out)
+{
+    int dev = 0;
+    DD_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1, nullptr);
+    if (!g_ws[dev]) {
+        Workspace *w = new Workspace();
+        w->device = dev;
+        if (hipMalloc(&w->flags_dev, 256) != hipSuccess) {
+            delete w;
+            return set_error(DD_ENOMEM, "hipMalloc of the flag word failed");
+        }
+        if (hipHostMalloc(&w->flags_host, 256, hipHostMallocDefault) != hipSuccess) {
+            (void)hipFree(w->flags_dev);
+            delete w;
+            return set_error(DD_ENOMEM, "hipHostMalloc of the flag mirror failed");
+        }
+        g_ws[dev] = w;
+    }
+    *out = g_ws[dev];
+    return DD_OK;
+}
+
+int ensure(Workspace *ws, Slot s, size_t bytes, void **out)
+{
+    if (bytes == 0) bytes = 256;
+    if (ws->cap[s] < bytes) {
+        size_t want = bytes + bytes / 4;
+        want = (want + 255) & ~size_t(255);
+        if (ws->ptr[s]) {
+            // an earlier call may still be reading it
+            DD_HIP(hipDeviceSynchronize());
+            DD_HIP(hipFree(ws->ptr[s]));
+            ws->ptr[s] = nullptr;
+            ws->cap[s] = 0;
+        }
+        if (hipMalloc(&ws->ptr[s], want) != hipSuccess) {
+            (void)hipGetLastError();
+            ws->ptr[s] = nullptr;
+            return set_error(DD_ENOMEM, "hipMalloc(%zu bytes) for workspace slot %d failed", want, (int)s);
+        }
+        ws->cap[s] = want;
+    }
+    *out = ws->ptr[s];
+    return DD_OK;
+}
+
+// Gauss-Legendre rule on [0, 1]: the roots z of P_n are found by Newton's
+// method on the Legendre recurrence (k P_k = (2k-1) z P_{k-1} - (k-1) P_{k-2})
+// from the guess cos(pi (4i + 3) / (4n + 2)); P_n'(z) = n (z P_n - P_{n-1}) /
+// (z^2 - 1) and the weight on [-1, 1] is 2 / ((1 - z^2) P_n'(z)^2).
+GaussRule gauss_rule(int n)
+{
+    GaussRule g{};
+    g.n = n;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0));
+        double p = 0, q = 0, dp = 1;
+        for (int it = 0; it < 60; ++it) {
+            q = 1.0;   // P_{k-1}
+            p = z;     // P_k
+            for (int k = 2; k <= n; ++k) {
+                double r = ((2 * k - 1) * z * p - (k - 1) * q) / k;
+                q = p;
+                p = r;
+            }
+            dp = n * (z * p - q) / (z * z - 1.0);
+            double step = p / dp;
+            z -= step;
+            if (std::fabs(step) < 1e-17) break;
+        }
+        q = 1.0; p = z;
+        for (int k = 2; k <= n; ++k) {
+            double r = ((2 * k - 1) * z * p - (k - 1) * q) / k;
+            q = p;
+            p = r;
+        }
+        dp = n * (z * p - q) / (z * z - 1.0);
+        // i = 0 is the largest root
+        g.s[n - 1 - i] = 0.5 * (1.0 + z);
+        g.w[n - 1 - i] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+    return g;
+}
+
+}  // namespace dd
+
+extern "C" {
+
+const char *dd_last_error(void) { return dd::g_msg; }
+
+int dd_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+int dd_set_validation(int on) { return dd::g_validate.exchange(on ? 1 : 0); }
+
+int dd_shutdown(void)
+{
+    std::lock_guard<std::mutex> lk(dd::g_ws_mu);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) cur = 0;
+    for (auto *&w : dd::g_ws) {
+        if (!w) continue;
+        (void)hipSetDevice(w->device);
+        (void)hipDeviceSynchronize();
+        for (int s = 0; s < dd::WS_NSLOTS; ++s)
+            if (w->ptr[s]) (void)hipFree(w->ptr[s]);
+        if (w->flags_dev) (void)hipFree(w->flags_dev);
+        if (w->flags_host) (void)hipHostFree(w->flags_host);
+        if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
+        delete w;
+        w = nullptr;
+    }
+    (void)hipSetDevice(cur);
+    return DD_OK;
+}
+
+}  // extern "C"

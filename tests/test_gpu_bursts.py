@@ -1,0 +1,116 @@
+"""GPU parity of batched bursts (dd_burst_batch) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2005_02498_amd import workloads as W
+import paper_2005_02498_amd as dd
+
+from gpu_util import MAT, batch_dev, normwise
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_burst(bt, n_steps, prec=dd.DD_FP64, Q=2, features=True):
+    d = batch_dev(bt)
+    rate, feat = dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"],
+                                   d["normal"], d["pinned"], d["sigma_app"], d["volume"], MAT,
+                                   Q, prec, 20.0, n_steps, W.DT, want_features=features)
+    torch.cuda.synchronize()
+    return (d["x"].cpu().numpy(), rate.cpu().numpy(),
+            feat.cpu().numpy() if feat is not None else None)
+
+
+def _small_batch():
+    insts = []
+    for i, nl in enumerate((1, 3, 2, 4)):
+        insts.append(W.subset(W.burst_instance(1_000_000 + i), nl))
+    # make sure the batch has mobile and pinned loops
+    insts[1].pinned[:] = 0
+    insts[1].pinned[64:] = 1
+    insts[3].pinned[:] = 0
+    insts[3].pinned[96:] = 1
+    return W.pack(insts)
+
+
+def test_config0_burst_100_steps_fp64():
+    inst = W.config0()
+    bt = W.pack([inst])
+    xg, rg, fg = _gpu_burst(bt, 100)
+    xo, ro, fo = O.burst(inst, W.material(), 2, 100, W.DT)
+    e_disp = normwise(xg - inst.x, xo - inst.x)
+    e_rate = np.abs(rg[0] - ro).max() / np.abs(ro).max()
+    print(f"config0 100 steps: displacement err {e_disp:.2e}, rate err {e_rate:.2e}, "
+          f"max displacement {np.linalg.norm(xo - inst.x, axis=0).max():.3f} b")
+    assert e_disp < 1e-9
+    assert e_rate < 1e-9
+    np.testing.assert_allclose(fg[0], fo, rtol=1e-12, atol=0)
+
+
+def test_small_batch_fp64_vs_oracle():
+    bt = _small_batch()
+    xg, rg, fg = _gpu_burst(bt, 5)
+    xo, ro, fo = O.burst_batch(bt, W.material(), 2, 5, W.DT)
+    assert normwise(xg - bt.x, xo - bt.x) < 1e-10
+    assert np.abs(rg - ro).max() / np.abs(ro).max() < 1e-10
+    np.testing.assert_allclose(fg, fo, rtol=1e-12, atol=0)
+    assert np.count_nonzero(ro) > 0
+
+
+def test_small_batch_mixed_vs_oracle():
+    bt = _small_batch()
+    xg, rg, _ = _gpu_burst(bt, 5, dd.DD_MIXED)
+    xo, ro, _ = O.burst_batch(bt, W.material(), 2, 5, W.DT)
+    assert normwise(xg - bt.x, xo - bt.x) < 1e-4
+    assert np.abs(rg - ro).max() / np.abs(ro).max() < 1e-4
+
+
+def test_batched_equals_single_calls():
+    bt = _small_batch()
+    xb, rb, fb = _gpu_burst(bt, 4)
+    for i in range(bt.n_inst):
+        n0, n1 = bt.node_off[i], bt.node_off[i + 1]
+        s0, s1 = bt.seg_off[i], bt.seg_off[i + 1]
+        one = W.Batch(np.array([0, n1 - n0]), np.array([0, s1 - s0]), bt.x[:, n0:n1].copy(),
+                      bt.seg_nodes[:, s0:s1].copy(), bt.burgers[:, s0:s1].copy(),
+                      bt.normal[:, s0:s1].copy(), bt.pinned[n0:n1].copy(),
+                      bt.sigma_app[i:i + 1].copy(), bt.volume[i:i + 1].copy())
+        x1, r1, f1 = _gpu_burst(one, 4)
+        np.testing.assert_allclose(r1[0], rb[i], rtol=1e-13, atol=1e-13 * np.abs(rb[i]).max())
+        np.testing.assert_allclose(x1, xb[:, n0:n1], rtol=0, atol=1e-11)
+        np.testing.assert_array_equal(f1[0], fb[i])
+
+
+def test_resume_equals_single_run():
+    bt = _small_batch()
+    x6, r6, _ = _gpu_burst(bt, 6, features=False)
+    d = batch_dev(bt)
+    r1, _ = dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"],
+                              d["normal"], d["pinned"], d["sigma_app"], d["volume"], MAT, 2,
+                              dd.DD_FP64, 20.0, 3, W.DT)
+    r1 = r1.cpu().numpy().copy()
+    r2, _ = dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"],
+                              d["normal"], d["pinned"], d["sigma_app"], d["volume"], MAT, 2,
+                              dd.DD_FP64, 20.0, 3, W.DT)
+    np.testing.assert_array_equal(d["x"].cpu().numpy(), x6)
+    np.testing.assert_allclose(0.5 * (r1 + r2.cpu().numpy()), r6, rtol=1e-14,
+                               atol=1e-14 * np.abs(r6).max())
+
+
+def test_zero_steps_and_empty_instances():
+    insts = [W.subset(W.burst_instance(1_000_010), 1), W.subset(W.burst_instance(1_000_011), 2)]
+    bt = W.pack(insts)
+    xg, rg, fg = _gpu_burst(bt, 0)
+    np.testing.assert_array_equal(xg, bt.x)
+    assert np.all(rg == 0)
+    _, _, fo = O.burst_batch(bt, W.material(), 2, 0, W.DT)
+    np.testing.assert_allclose(fg, fo, rtol=1e-12, atol=0)
+    # an instance with no nodes and no segments in the middle of the batch
+    e = W.Instance(np.zeros((3, 0)), np.zeros((2, 0), np.int32), np.zeros((3, 0)),
+                   np.zeros((3, 0)), np.zeros(0, np.uint8), np.zeros(6), 1.0)
+    bt = W.pack([insts[0], e, insts[1]])
+    xg, rg, _ = _gpu_burst(bt, 2)
+    xo, ro, _ = O.burst_batch(bt, W.material(), 2, 2, W.DT)
+    assert np.all(rg[1] == 0)
+    assert normwise(xg - bt.x, xo - bt.x) < 1e-10

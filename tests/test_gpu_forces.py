@@ -1,0 +1,203 @@
+"""GPU parity of the force path (dd_nodal_forces, dd_glide_step) against the
+FP64 oracle on the same seeded inputs.
+
+Tolerances (normwise, max node error over max node force): FP64 path 1e-10,
+mixed FP32/FP64 path 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2005_02498_amd import workloads as W
+import paper_2005_02498_amd as dd
+
+from gpu_util import MAT, dev, normwise
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOLMIX = 1e-10, 1e-4
+
+
+def _gpu_forces(inst, Q, prec=dd.DD_FP64, cut=20.0):
+    d = dev(inst)
+    F = dd.dd_nodal_forces(d["x"], d["seg_nodes"], d["burgers"], d["normal"], inst.sigma_app,
+                           MAT, Q, prec, cut)
+    torch.cuda.synchronize()
+    return F.cpu().numpy()
+
+
+def _oracle_forces(inst, Q):
+    return O.nodal_forces(inst.x, inst.seg_nodes, inst.burgers, inst.sigma_app,
+                          W.MU, W.NU, W.CORE_A, Q)
+
+
+def test_config0_fp64_q2():
+    inst = W.config0()
+    e = normwise(_gpu_forces(inst, 2), _oracle_forces(inst, 2))
+    print(f"config0 fp64 Q=2 err {e:.2e}")
+    assert e < TOL64
+
+
+@pytest.mark.parametrize("Q", [1, 3, 4, 16])
+def test_config0_fp64_other_Q(Q):
+    inst = W.subset(W.config0(), 3)
+    e = normwise(_gpu_forces(inst, Q), _oracle_forces(inst, Q))
+    assert e < TOL64, e
+
+
+@pytest.mark.parametrize("n_loops,Q", [(37, 2), (37, 3), (64, 4)])
+def test_multi_tile_ragged_fp64(n_loops, Q):
+    """Several 256-point tiles, several source chunks and a ragged last tile."""
+    inst = W.subset(W.config1(), n_loops)
+    e = normwise(_gpu_forces(inst, Q), _oracle_forces(inst, Q))
+    print(f"config1[:{n_loops}] fp64 Q={Q} err {e:.2e}")
+    assert e < TOL64
+
+
+@pytest.mark.parametrize("n_loops,Q", [(8, 2), (37, 2), (64, 4)])
+def test_mixed_vs_oracle(n_loops, Q):
+    base = W.config0() if n_loops == 8 else W.config1()
+    inst = W.subset(base, n_loops)
+    e = normwise(_gpu_forces(inst, Q, dd.DD_MIXED), _oracle_forces(inst, Q))
+    print(f"mixed {n_loops} loops Q={Q} err {e:.2e}")
+    assert e < TOLMIX
+
+
+@pytest.mark.parametrize("prec,tol", [(dd.DD_FP64, TOL64), (dd.DD_MIXED, TOLMIX)])
+@pytest.mark.parametrize("Q", [2, 4])
+def test_config1_full_sampled(prec, tol, Q):
+    """Full 16,384-segment volume in the launch configuration the benchmark
+    times; the oracle computes four whole loops (every node of a loop gets
+    both of its segments' contributions) against all sources."""
+    inst = W.config1()
+    F = _gpu_forces(inst, Q, prec)
+    errs, refmax = [], 0.0
+    num = 0.0
+    for lp in (0, 101, 300, 511):
+        t0, t1 = 32 * lp, 32 * lp + 32
+        ref = O.nodal_forces_sampled(inst.x, inst.seg_nodes, inst.burgers, inst.sigma_app,
+                                     W.MU, W.NU, W.CORE_A, Q, t0, t1)[:, t0:t1]
+        num = max(num, np.linalg.norm(F[:, t0:t1] - ref, axis=0).max())
+        refmax = max(refmax, np.linalg.norm(ref, axis=0).max())
+    e = num / refmax
+    print(f"config1 full sampled prec={prec} Q={Q} err {e:.2e}")
+    assert e < tol
+
+
+def test_mixed_cutoff_extremes_agree_with_fp64():
+    """A huge cutoff sends every pair to FP64: must equal the FP64 path to
+    rounding; a tiny cutoff sends (almost) everything to FP32."""
+    inst = W.subset(W.config1(), 16)
+    F64 = _gpu_forces(inst, 2)
+    Fbig = _gpu_forces(inst, 2, dd.DD_MIXED, 1e9)
+    assert normwise(Fbig, F64) < 1e-13
+    Fsmall = _gpu_forces(inst, 2, dd.DD_MIXED, 1e-3)
+    assert normwise(Fsmall, F64) < TOLMIX
+
+
+def test_deterministic():
+    inst = W.subset(W.config1(), 40)
+    a = _gpu_forces(inst, 2)
+    b = _gpu_forces(inst, 2)
+    np.testing.assert_array_equal(a, b)
+    a = _gpu_forces(inst, 2, dd.DD_MIXED)
+    b = _gpu_forces(inst, 2, dd.DD_MIXED)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_degenerate_inputs():
+    # one segment: no other source, applied stress only
+    x = np.array([[0.0, 10.0], [0.0, 0.0], [0.0, 0.0]])
+    sn = np.array([[0], [1]], np.int32)
+    b = np.array([[0.0], [0.0], [1.0]]) / 1.0
+    nrm = np.array([[0.0], [1.0], [0.0]])
+    inst = W.Instance(x, sn, b, nrm, np.zeros(2, np.uint8), np.array([0, 0, 0, 0, 3e7, 1e7]), 1.0)
+    np.testing.assert_allclose(_gpu_forces(inst, 2), _oracle_forces(inst, 2), rtol=1e-13, atol=0)
+    # two crossing segments (finite because a > 0), and touching ones
+    x = np.array([[-5.0, 5.0, 0.0, 0.0, 5.0], [0.0, 0.0, -5.0, 5.0, 0.0], [0.0, 0.0, 0.0, 0.0, 7.0]])
+    sn = np.array([[0, 2, 1], [1, 3, 4]], np.int32)
+    b = np.array([[1.0, 0.0, 0.5], [0.0, 1.0, 0.5], [0.0, 0.0, 0.0]])
+    nrm = np.array([[0.0, 0.0, 1.0], [0.0, 0.0, 0.0], [1.0, 1.0, 0.0]])
+    inst = W.Instance(x, sn, b, nrm, np.zeros(5, np.uint8), np.zeros(6), 1.0)
+    g = _gpu_forces(inst, 2)
+    assert np.all(np.isfinite(g))
+    assert normwise(g, _oracle_forces(inst, 2)) < TOL64
+    # nodes without segments get zero force; zero segments is allowed
+    x = np.zeros((3, 4)); x[0] = [0, 1, 2, 3]
+    inst = W.Instance(x, np.zeros((2, 0), np.int32), np.zeros((3, 0)), np.zeros((3, 0)),
+                      np.zeros(4, np.uint8), np.zeros(6), 1.0)
+    assert np.all(_gpu_forces(inst, 2) == 0)
+
+
+def test_invalid_inputs_raise():
+    inst = W.subset(W.config0(), 1)
+    d = dev(inst)
+    bad = d["seg_nodes"].clone()
+    bad[1, 3] = 99
+    with pytest.raises(dd.DDError) as e:
+        dd.dd_nodal_forces(d["x"], bad, d["burgers"], d["normal"], inst.sigma_app, MAT, 2)
+    assert e.value.code == -1
+    bad = d["seg_nodes"].clone()
+    bad[0, 2] = -1
+    with pytest.raises(dd.DDError):
+        dd.dd_nodal_forces(d["x"], bad, d["burgers"], d["normal"], inst.sigma_app, MAT, 2)
+    z = d["seg_nodes"].clone()
+    z[1, 4] = z[0, 4]                                  # zero-length segment
+    with pytest.raises(dd.DDError):
+        dd.dd_nodal_forces(d["x"], z, d["burgers"], d["normal"], inst.sigma_app, MAT, 2)
+    with pytest.raises(dd.DDError):
+        dd.dd_nodal_forces(d["x"], d["seg_nodes"], d["burgers"], 2 * d["normal"],
+                           inst.sigma_app, MAT, 2)
+    for Q in (0, 17):
+        with pytest.raises(dd.DDError):
+            dd.dd_nodal_forces(d["x"], d["seg_nodes"], d["burgers"], d["normal"],
+                               inst.sigma_app, MAT, Q)
+    with pytest.raises(dd.DDError):
+        dd.dd_nodal_forces(d["x"], d["seg_nodes"], d["burgers"], d["normal"], inst.sigma_app,
+                           dict(MAT, a=0.0), 2)
+    xn = d["x"].clone()
+    xn[0, 5] = float("nan")
+    with pytest.raises(dd.DDError):
+        dd.dd_nodal_forces(xn, d["seg_nodes"], d["burgers"], d["normal"], inst.sigma_app, MAT, 2)
+    # the library still works afterwards
+    F = dd.dd_nodal_forces(d["x"], d["seg_nodes"], d["burgers"], d["normal"], inst.sigma_app, MAT, 2)
+    assert torch.isfinite(F).all()
+
+
+def test_validation_off_is_same_result():
+    inst = W.subset(W.config1(), 20)
+    a = _gpu_forces(inst, 2)
+    prev = dd.dd_set_validation(False)
+    try:
+        b = _gpu_forces(inst, 2)
+    finally:
+        dd.dd_set_validation(prev)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_glide_step_vs_oracle():
+    inst = W.burst_instance(1_000_005)
+    F = _oracle_forces(inst, 2)
+    d = dev(inst)
+    Ft = torch.tensor(F, device="cuda:0")
+    v = dd.dd_glide_step(d["x"], Ft, d["seg_nodes"], d["normal"], d["pinned"], MAT, W.DT)
+    torch.cuda.synchronize()
+    xo, vo = O.glide_step(inst.x, F, inst.seg_nodes, inst.normal, inst.pinned, W.DRAG_B, W.DT)
+    np.testing.assert_allclose(v.cpu().numpy(), vo, rtol=0, atol=1e-13 * np.abs(vo).max())
+    np.testing.assert_allclose(d["x"].cpu().numpy(), xo, rtol=0, atol=1e-12)
+
+
+def test_glide_step_multiple_normals():
+    x = np.array([[0.0, 10.0, 20.0, 10.0], [0, 0, 0, 10.0], [0, 0, 0, 0]])
+    sn = np.array([[0, 1, 1], [1, 2, 3]], np.int32)
+    F = np.zeros((3, 4)); F[:, 1] = [1.0, 2.0, 3.0]; F[:, 0] = [0.5, -1, 2]
+    for normals in ((0, 1, 1), (0, 1, 2)):
+        nor = np.stack([W.PLANE_NORMALS[k] for k in normals], 1)
+        xo, vo = O.glide_step(x, F, sn, nor, None, 2.0, 1.0)
+        xt = torch.tensor(x, device="cuda:0")
+        v = dd.dd_glide_step(xt, torch.tensor(F, device="cuda:0"),
+                             torch.tensor(sn, device="cuda:0"), torch.tensor(nor, device="cuda:0"),
+                             None, dict(MAT, B=2.0), 1.0)
+        np.testing.assert_allclose(v.cpu().numpy(), vo, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(xt.cpu().numpy(), xo, rtol=0, atol=1e-15)
