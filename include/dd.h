@@ -98,6 +98,20 @@ int dd_set_validation(int on);
 /* Release the workspace of every device this thread's process used. */
 int dd_shutdown(void);
 
+/* Measurement hooks (for benchmarks and profilers).  With timing on, every
+ * launch of the all-pairs kernel made outside graph capture is bracketed by a
+ * HIP event pair recorded on the caller's stream.  dd_timing_read waits for
+ * the recorded events and returns, since the last reset: the summed
+ * event-to-event time of those launches in milliseconds, the number of
+ * launches, and the number of (target Gauss point, source segment)
+ * evaluations the mixed kernel sent to the FP64 near-field branch (counted
+ * whether or not timing is on).  Any output pointer may be null.  reset != 0
+ * clears all three afterwards.  Not for use while another thread calls the
+ * library. */
+int dd_timing_enable(int on);
+int dd_timing_read(double *kernel_ms, int64_t *launches, int64_t *near_evals,
+                   int reset);
+
 /* Nodal forces (internal + applied) on every node.
  *  For every segment j and Gauss-Legendre point q of an n_gauss-point rule
  *  on [0, 1] (points s_q, weights w_q):

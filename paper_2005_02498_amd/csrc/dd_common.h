@@ -61,7 +61,14 @@ struct Workspace {
     unsigned *flags_dev = nullptr;   // one word
     unsigned *flags_host = nullptr;  // pinned mirror
     hipStream_t capture_stream = nullptr;
+    unsigned long long *near_count = nullptr;   // device counter (mixed kernel)
+    bool capturing = false;
 };
+
+// Event timing of the all-pairs kernel (dd_timing_enable / dd_timing_read).
+bool timing_on();
+void timing_begin(hipStream_t st, bool capturing);
+void timing_end(hipStream_t st, bool capturing);
 
 // Returns the workspace of the current device (creating it on first use).
 int workspace(Workspace **out);

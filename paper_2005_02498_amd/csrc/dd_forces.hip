@@ -317,9 +317,11 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                                                      const float *__restrict__ rec32,
                                                      int64_t ns, GaussRule g, double k1,
                                                      double k2, float cut2,
-                                                     double *__restrict__ partial)
+                                                     double *__restrict__ partial,
+                                                     unsigned long long *near_count)
 {
     __shared__ double shx[6][TILE];    // x1, t (FP64)
+    __shared__ unsigned n_near_block;
     __shared__ float shf[7][TILE];     // L, b, c (FP32)
     const Item it = items[blockIdx.x];
     const Tile tl = tiles[it.tile];
@@ -340,6 +342,8 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
     const float fb0 = (float)bj0, fb1 = (float)bj1, fb2 = (float)bj2;
     const float fk1 = (float)k1, fk2 = (float)k2;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    unsigned n_near = 0;
+    if (lane == 0) n_near_block = 0;
 
     for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
         const int n = (int)min<int64_t>(TILE, it.src_end - base);
@@ -365,6 +369,7 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
             const float dmin2 = h0 * h0 + h1 * h1 + h2 * h2 + ya * ya;
             if (dmin2 < cut2) {
                 if (i != j) {
+                    n_near += valid ? 1u : 0u;
                     double c0, c1, c2;
                     pair_sigma_b_f64(xq0, xq1, xq2, bj0, bj1, bj2, shx[0][m], shx[1][m], shx[2][m],
                                      T0, T1, T2, rec[6 * ns + i], rec[7 * ns + i], rec[8 * ns + i],
@@ -394,6 +399,9 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
         o[TILE + lane] = a1;
         o[2 * TILE + lane] = a2;
     }
+    if (n_near) atomicAdd(&n_near_block, n_near);
+    __syncthreads();
+    if (lane == 0 && n_near_block) atomicAdd(near_count, (unsigned long long)n_near_block);
 }
 
 // ------------------------------ a3 + a4: Peach-Koehler and the quadrature --
@@ -885,12 +893,15 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
         if (C.n_items > 0) {
+            timing_begin(st, ws->capturing);
             if (C.precision == DD_MIXED)
                 hipLaunchKernelGGL(k_pair_mixed, dim3((unsigned)C.n_items), dim3(TILE), 0, st, C.items,
-                                   C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut2, C.partial);
+                                   C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut2, C.partial,
+                                   ws->near_count);
             else
                 hipLaunchKernelGGL(k_pair64, dim3((unsigned)C.n_items), dim3(TILE), 0, st, C.items,
                                    C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial);
+            timing_end(st, ws->capturing);
         }
         hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
                            C.tiles, C.partial, C.rec64, C.g, sig_dev, sig_val, C.inv_mu, C.fscale,
@@ -1105,6 +1116,7 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
         if (!ws->capture_stream) DD_HIP(hipStreamCreateWithFlags(&ws->capture_stream, hipStreamNonBlocking));
         hipStream_t cs = ws->capture_stream;
         DD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        ws->capturing = true;
         for (int k = 0; k < n_steps; ++k) {
             launch_forces(C, ws, x, seg_nodes, burgers, normal, sigma_app, sv, F, cs);
             hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
@@ -1115,6 +1127,7 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
         }
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(cs, &graph);
+        ws->capturing = false;
         if (e != hipSuccess) return set_error(DD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
         hipGraphExec_t exec = nullptr;
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
