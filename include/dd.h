@@ -231,6 +231,14 @@ int dd_mlp_train_step(dd_mlp *model, int64_t n, const float *feat,
                       const float *target, float lr, float *loss_out,
                       void *stream);
 
+/* Forward and backward pass without the update: grad_out (device float32
+ * [n_members][DD_MLP_PARAMS], flat layout of the parameters) receives the
+ * gradient of each member's standardised mean squared error on the batch,
+ * loss_out (nullable) the losses.  1 <= n <= 65536. */
+int dd_mlp_gradients(dd_mlp *model, int64_t n, const float *feat,
+                     const float *target, float *grad_out, float *loss_out,
+                     void *stream);
+
 /* Ensemble inference: rates [n][12] = member mean (unstandardised), spread
  * [n] = ||population std over members||_2 / max(||mean||_2, 1e-30),
  * needs_dd [n] = spread > spread_tol (DD is the fallback for those points).

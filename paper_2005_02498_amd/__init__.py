@@ -27,7 +27,7 @@ EXPORTS = [
     "dd_timing_enable", "dd_timing_read",
     "dd_nodal_forces", "dd_glide_step", "dd_burst_batch",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
-    "dd_mlp_set_scaling", "dd_mlp_train_step", "dd_surrogate_rates",
+    "dd_mlp_set_scaling", "dd_mlp_train_step", "dd_mlp_gradients", "dd_surrogate_rates",
 ]
 
 
@@ -81,6 +81,7 @@ def _declare(L):
         "dd_mlp_get_params": (C.c_int, [vp, C.c_int, fp]),
         "dd_mlp_set_scaling": (C.c_int, [vp, fp, fp, fp, fp]),
         "dd_mlp_train_step": (C.c_int, [vp, i64, vp, vp, C.c_float, vp, vp]),
+        "dd_mlp_gradients": (C.c_int, [vp, i64, vp, vp, vp, vp, vp]),
         "dd_surrogate_rates": (C.c_int, [vp, i64, vp, vp, vp, vp, C.c_float, vp]),
     }
     for name, (res, args) in sig.items():
@@ -293,6 +294,22 @@ def dd_mlp_train_step(model: SurrogateModel, feat, target, lr=1e-3, loss_out=Non
     pl = _dev(loss_out, torch.float32, (model.n_members,), "loss_out")
     _check(lib().dd_mlp_train_step(model.handle, n, pf, pt, C.c_float(lr), pl, _stream(stream)))
     return loss_out
+
+
+def dd_mlp_gradients(model: SurrogateModel, feat, target, grad_out=None, loss_out=None,
+                     stream=None):
+    """Per-member gradients [n_members][144140] and losses, without a step."""
+    n = feat.shape[0]
+    pf = _dev(feat, torch.float32, (n, MLP_IN), "feat")
+    pt = _dev(target, torch.float32, (n, MLP_OUT), "target")
+    if grad_out is None:
+        grad_out = torch.empty((model.n_members, MLP_PARAMS), dtype=torch.float32, device=feat.device)
+    pg = _dev(grad_out, torch.float32, (model.n_members, MLP_PARAMS), "grad_out")
+    if loss_out is None:
+        loss_out = torch.empty(model.n_members, dtype=torch.float32, device=feat.device)
+    pl = _dev(loss_out, torch.float32, (model.n_members,), "loss_out")
+    _check(lib().dd_mlp_gradients(model.handle, n, pf, pt, pg, pl, _stream(stream)))
+    return grad_out, loss_out
 
 
 def dd_surrogate_rates(model: SurrogateModel, feat, spread_tol=0.05, rates=None, spread=None,
