@@ -159,7 +159,24 @@ __global__ void k_seg_prep(PrepArgs A)
     r[6 * ns + s] = L;
     r[7 * ns + s] = b[0];  r[8 * ns + s] = b[1];  r[9 * ns + s] = b[2];
     r[10 * ns + s] = c[0]; r[11 * ns + s] = c[1]; r[12 * ns + s] = c[2];
-    r[13 * ns + s] = 0.0;
+    // length of the run of segments starting here in which each next segment
+    // starts at the node where the one before it ends (loops stored in order),
+    // capped at TILE: the all-pairs kernel computes the inverse distance to a
+    // shared node once per run
+    int run = 1;
+    {
+        const int inst = seg_instance(A.L, s);
+        const int64_t send = A.L.seg_off ? A.L.seg_off[inst + 1] : ns;
+        int64_t prev2 = g2;
+        while (run < TILE && s + run < send) {
+            int64_t q1, q2;
+            seg_ends(A.L, A.seg_nodes, s + run, q1, q2);
+            if (q1 != prev2) break;
+            prev2 = q2;
+            ++run;
+        }
+    }
+    r[13 * ns + s] = (double)run;
     if (A.rec32) {
         float *q = A.rec32;
         q[0 * ns + s] = (float)t[0]; q[1 * ns + s] = (float)t[1]; q[2 * ns + s] = (float)t[2];
@@ -253,13 +270,46 @@ __global__ void k_csr_sort(const int32_t *ptr, int64_t nn, int32_t *list)
 // lane) against a contiguous source range, staged through LDS TILE sources at
 // a time.  Each lane accumulates sigma b_j (3 values) over the range; the
 // item's partial sums go to their own slot, reduced in a fixed order later.
+// Only LDS stages that overlap the tile's own segments test for the excluded
+// self pair.
+template <bool SELF>
+__device__ __forceinline__ void pair64_stage(double (*sh)[TILE], int n, int64_t base, int64_t j,
+                                             double xq0, double xq1, double xq2, double bj0,
+                                             double bj1, double bj2, double k1, double k2,
+                                             double &a0, double &a1, double &a2)
+{
+    // runs of sources sharing consecutive nodes: one fresh inverse distance
+    // per run, then each source reuses the previous source's far endpoint
+    for (int m = 0; m < n;) {
+        const int run = min(__builtin_amdgcn_readfirstlane((int)sh[13][m]), n - m);
+        const double R0 = xq0 - sh[0][m], R1 = xq1 - sh[1][m], R2 = xq2 - sh[2][m];
+        double rprev = rsqrt64(R0 * R0 + R1 * R1 + R2 * R2 + 1.0);
+        for (int e = m + run; m < e; ++m) {
+            double c0, c1, c2;
+            pair_sigma_b_f64c(xq0, xq1, xq2, bj0, bj1, bj2, sh[0][m], sh[1][m], sh[2][m], sh[3][m],
+                              sh[4][m], sh[5][m], sh[6][m], sh[7][m], sh[8][m], sh[9][m], sh[10][m],
+                              sh[11][m], sh[12][m], k1, k2, true, rprev, c0, c1, c2);
+            if (SELF) {
+                const bool self = (base + m) == j;
+                a0 += self ? 0.0 : c0;
+                a1 += self ? 0.0 : c1;
+                a2 += self ? 0.0 : c2;
+            } else {
+                a0 += c0;
+                a1 += c1;
+                a2 += c2;
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(TILE) void k_pair64(const Item *__restrict__ items,
                                                  const Tile *__restrict__ tiles,
                                                  const double *__restrict__ rec, int64_t ns,
                                                  GaussRule g, double k1, double k2,
                                                  double *__restrict__ partial)
 {
-    __shared__ double sh[13][TILE];
+    __shared__ double sh[14][TILE];
     const Item it = items[blockIdx.x];
     const Tile tl = tiles[it.tile];
     const int lane = threadIdx.x;
@@ -268,6 +318,7 @@ __global__ __launch_bounds__(TILE) void k_pair64(const Item *__restrict__ items,
     const int Q = g.n;
     const int64_t j = p / Q;
     const int q = (int)(p - j * Q);
+    const int64_t jlo = tl.point_begin / Q, jhi = (tl.point_begin + tl.n_points - 1) / Q;
     double sq = g.s[0];
     for (int k = 1; k < DD_MAX_GAUSS; ++k)
         if (k == q) sq = g.s[k];
@@ -283,20 +334,13 @@ __global__ __launch_bounds__(TILE) void k_pair64(const Item *__restrict__ items,
         __syncthreads();
         if (lane < n) {
 #pragma unroll
-            for (int k = 0; k < 13; ++k) sh[k][lane] = rec[k * ns + base + lane];
+            for (int k = 0; k < 14; ++k) sh[k][lane] = rec[k * ns + base + lane];
         }
         __syncthreads();
-        for (int m = 0; m < n; ++m) {
-            double c0, c1, c2;
-            pair_sigma_b_f64(xq0, xq1, xq2, bj0, bj1, bj2,
-                             sh[0][m], sh[1][m], sh[2][m], sh[3][m], sh[4][m], sh[5][m],
-                             sh[6][m], sh[7][m], sh[8][m], sh[9][m], sh[10][m], sh[11][m],
-                             sh[12][m], k1, k2, c0, c1, c2);
-            const bool self = (base + m) == j;
-            a0 += self ? 0.0 : c0;
-            a1 += self ? 0.0 : c1;
-            a2 += self ? 0.0 : c2;
-        }
+        if (base <= jhi && base + n > jlo)
+            pair64_stage<true>(sh, n, base, j, xq0, xq1, xq2, bj0, bj1, bj2, k1, k2, a0, a1, a2);
+        else
+            pair64_stage<false>(sh, n, base, j, xq0, xq1, xq2, bj0, bj1, bj2, k1, k2, a0, a1, a2);
     }
     if (valid) {
         double *o = partial + it.slot * 3 * TILE;

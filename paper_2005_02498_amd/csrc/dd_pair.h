@@ -21,23 +21,50 @@
 
 namespace dd {
 
+// 1/sqrt(x) and 1/x in FP64 for x >= 1 (every argument here is at least the
+// squared core width, 1 in scaled units): the hardware estimate refined by one
+// third-order step, Householder's iteration y <- y (1 + e/2 + 3 e^2/8) with
+// e = 1 - x y^2 for the inverse square root, and r <- r (1 + e + e^2) with
+// e = 1 - x r for the reciprocal.  Each step cubes the estimate's relative
+// error.
+__device__ __forceinline__ double rsqrt64(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
+__device__ __forceinline__ double rcp64(double x)
+{
+    const double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, fma(e, e, e), r);
+}
+
 // FP64: endpoint differences taken directly,
 //   I30 = (s2 - s1)/d2, I31 = r1 - r2, I50 = ((3 s2 - s2^3) - (3 s1 - s1^3))/(3 d2^2),
 //   I51 = (r1^3 - r2^3)/3, I52 = (s2^3 - s1^3)/(3 d2), with r = 1/Ra, s = u r.
-__device__ __forceinline__ void pair_sigma_b_f64(
+// r at an endpoint depends only on the distance to that node, so when the
+// source starts at the node where the previous source (same target point)
+// ended, its r1 is the previous r2: `chained` (uniform across the wave) skips
+// that inverse square root; `rprev` carries r2 to the next call.
+__device__ __forceinline__ void pair_sigma_b_f64c(
     double x0, double x1, double x2, double bj0, double bj1, double bj2,
     double p0, double p1, double p2, double t0, double t1, double t2, double L,
     double b0, double b1, double b2, double c0, double c1, double c2,
-    double k1, double k2, double &o0, double &o1, double &o2)
+    double k1, double k2, bool chained, double &rprev, double &o0, double &o1, double &o2)
 {
     const double R0 = x0 - p0, R1 = x1 - p1, R2 = x2 - p2;
     const double y = R0 * t0 + R1 * t1 + R2 * t2;
     const double h0 = R0 - y * t0, h1 = R1 - y * t1, h2 = R2 - y * t2;   // rho
     const double d2 = h0 * h0 + h1 * h1 + h2 * h2 + 1.0;
     const double u2 = L - y;
-    const double r1 = rsqrt(d2 + y * y);
-    const double r2 = rsqrt(d2 + u2 * u2);
-    const double id2 = 1.0 / d2;
+    double r1;
+    if (chained) r1 = rprev;
+    else r1 = rsqrt64(d2 + y * y);
+    const double r2 = rsqrt64(d2 + u2 * u2);
+    rprev = r2;
+    const double id2 = rcp64(d2);
     const double s1 = -y * r1, s2 = u2 * r2;
     const double s1c = s1 * s1 * s1, s2c = s2 * s2 * s2;
     const double I30 = (s2 - s1) * id2;
@@ -64,6 +91,18 @@ __device__ __forceinline__ void pair_sigma_b_f64(
     o0 = t0 * wb + w0 * tb + h0 * zb + z0 * hb + kd * bj0;
     o1 = t1 * wb + w1 * tb + h1 * zb + z1 * hb + kd * bj1;
     o2 = t2 * wb + w2 * tb + h2 * zb + z2 * hb + kd * bj2;
+}
+
+// Unchained form (isolated pairs, e.g. the near-field branch of the mixed path).
+__device__ __forceinline__ void pair_sigma_b_f64(
+    double x0, double x1, double x2, double bj0, double bj1, double bj2,
+    double p0, double p1, double p2, double t0, double t1, double t2, double L,
+    double b0, double b1, double b2, double c0, double c1, double c2,
+    double k1, double k2, double &o0, double &o1, double &o2)
+{
+    double r = 0.0;
+    pair_sigma_b_f64c(x0, x1, x2, bj0, bj1, bj2, p0, p1, p2, t0, t1, t2, L, b0, b1, b2, c0, c1,
+                      c2, k1, k2, false, r, o0, o1, o2);
 }
 
 // FP32, far pairs.  y and rho are formed in FP64 by the caller and rounded
