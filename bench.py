@@ -40,9 +40,11 @@ UNIT = "segment-pair evals/s"
 # counted on the closed form as written in csrc/dd_pair.h (add, sub, mul = 1,
 # fma = 2, sqrt / rsqrt / reciprocal = 1; selects and compares = 0).
 FLOP_F64_EVAL = 169          # FP64 path
-FLOP_MIX_PREP_F64 = 14       # mixed: FP64 offset, axial and perpendicular parts (every pair)
-FLOP_MIX_CLASS_F32 = 8       # mixed: minimum-distance classification (every pair)
-FLOP_MIX_FAR_F32 = 179       # mixed: FP32 cancellation-free closed form (far pairs)
+FLOP_MIX_LOC_F32 = 27        # mixed: FP32 location and band test (every pair)
+FLOP_MIX_QUAD_F32 = 145      # mixed: FP32 2-point source quadrature (well-separated pairs)
+FLOP_MIX_PREP_F64 = 14       # mixed: FP64 offset, axial, perpendicular parts (other pairs)
+FLOP_MIX_CLASS_F32 = 8       # mixed: minimum-distance test (other pairs)
+FLOP_MIX_FAR_F32 = 179       # mixed: FP32 cancellation-free closed form
 FLOP_MIX_NEAR_F64 = 169      # mixed: FP64 closed form (near pairs)
 PEAK_F64 = 78.6e12
 PEAK_F32 = 157.3e12
@@ -146,19 +148,22 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         dd.dd_timing_enable(False)
-        kms, launches, near = dd.dd_timing_read(reset=True)
+        kms, launches, near, quad = dd.dd_timing_read(reset=True)
         assert launches == steps, (launches, steps)
-        return (t1 - t0) / steps, kms / 1e3 / launches, near / launches
+        return (t1 - t0) / steps, kms / 1e3 / launches, (near / launches, quad / launches)
 
-    def roof(prec, Q, kernel_s, near):
+    def roof(prec, Q, kernel_s, bands):
         if prec == dd.DD_FP64:
             f64 = FLOP_F64_EVAL * pairs * Q
             f32 = 0.0
         else:
-            allp = N * N * Q
-            far = pairs * Q - near
-            f64 = FLOP_MIX_PREP_F64 * allp + FLOP_MIX_NEAR_F64 * near
-            f32 = FLOP_MIX_CLASS_F32 * allp + FLOP_MIX_FAR_F32 * far
+            near, quad = bands
+            allp = N * N * Q                 # including the (skipped) self pairs
+            other = allp - quad              # pairs that take the FP64 location
+            closed = pairs * Q - quad - near
+            f64 = FLOP_MIX_PREP_F64 * other + FLOP_MIX_NEAR_F64 * near
+            f32 = (FLOP_MIX_LOC_F32 * allp + FLOP_MIX_QUAD_F32 * quad
+                   + FLOP_MIX_CLASS_F32 * other + FLOP_MIX_FAR_F32 * closed)
         flops = f64 + f32
         t_roof = f64 / PEAK_F64 + f32 / PEAK_F32
         peak = flops / t_roof
@@ -169,14 +174,14 @@ def main():
 
     if args.only in ("fp64", "mixed"):
         prec = dd.DD_FP64 if args.only == "fp64" else dd.DD_MIXED
-        s, k, near = run(prec, 2, args.steps, args.warmup)
+        s, k, _ = run(prec, 2, args.steps, args.warmup)
         print(json.dumps({"part": args.only, "ms_per_step": s * 1e3, "kernel_ms": k * 1e3}))
         return
 
     out = {}
     if args.only != "burst":
         step_s, ker_s, _ = run(dd.DD_FP64, 2, args.steps, args.warmup)
-        r = roof(dd.DD_FP64, 2, ker_s, 0)
+        r = roof(dd.DD_FP64, 2, ker_s, None)
         tb = traffic_bytes()
         rl = {"bound": "alu", "achieved": r["achieved"], "peak": r["peak"], "unit": "TFLOP/s",
               "frac": r["frac"], "traffic": tb, "kernel": "k_pair64",
@@ -200,11 +205,12 @@ def main():
         extras = {}
         for name, prec, Q in (("mixed_q2", dd.DD_MIXED, 2), ("fp64_q4", dd.DD_FP64, 4),
                               ("mixed_q4", dd.DD_MIXED, 4)):
-            s, k, near = run(prec, Q, max(5, args.steps // 2), 2)
-            r = roof(prec, Q, k, near)
+            s, k, bands = run(prec, Q, max(5, args.steps // 2), 2)
+            r = roof(prec, Q, k, bands)
             extras[name] = {"pairs_per_s": pairs / s, "gauss_evals_per_s": Q * pairs / s,
                             "ms_per_step": s * 1e3, "kernel_ms": k * 1e3,
-                            "near_fp64_evals_per_launch": near,
+                            "near_fp64_evals_per_launch": bands[0],
+                            "quad_fp32_evals_per_launch": bands[1],
                             "roofline": {kk: r[kk] for kk in ("bound", "achieved", "peak", "unit", "frac")}}
         out["extras"] = extras
 

@@ -78,9 +78,11 @@ typedef struct { double mu, nu, a, B; } dd_material;
 /* DD_FP64: every pair in float64.
  * DD_MIXED: pairs whose minimum distance from the target Gauss point to the
  * source segment is below near_cutoff_a * a are evaluated in float64, all
- * others in float32 (a cancellation-free arrangement of the closed form) with
- * float32 accumulation over a source tile; tile sums, nodal sums and the
- * mobility step stay float64. */
+ * others in float32 with float32 accumulation over a source tile: the closed
+ * form in a cancellation-free arrangement, or, when the target is at least 30
+ * source lengths from the source midpoint, 2-point Gauss-Legendre quadrature
+ * of the integrand along the source (error below 2e-7 relative there).  Tile
+ * sums, nodal sums and the mobility step stay float64. */
 typedef enum { DD_FP64 = 0, DD_MIXED = 1 } dd_precision;
 
 /* Message of the last error on the calling thread ("" if none). */
@@ -103,14 +105,15 @@ int dd_shutdown(void);
  * HIP event pair recorded on the caller's stream.  dd_timing_read waits for
  * the recorded events and returns, since the last reset: the summed
  * event-to-event time of those launches in milliseconds, the number of
- * launches, and the number of (target Gauss point, source segment)
- * evaluations the mixed kernel sent to the FP64 near-field branch (counted
- * whether or not timing is on).  Any output pointer may be null.  reset != 0
- * clears all three afterwards.  Not for use while another thread calls the
- * library. */
+ * launches, and how many (target Gauss point, source segment) evaluations
+ * the mixed kernel sent to its FP64 near-field branch and to its FP32
+ * source-quadrature branch (both counted whether or not timing is on; the
+ * remaining mixed evaluations used the FP32 closed form).  Any output pointer
+ * may be null.  reset != 0 clears everything afterwards.  Not for use while
+ * another thread calls the library. */
 int dd_timing_enable(int on);
 int dd_timing_read(double *kernel_ms, int64_t *launches, int64_t *near_evals,
-                   int reset);
+                   int64_t *quad_evals, int reset);
 
 /* Nodal forces (internal + applied) on every node.
  *  For every segment j and Gauss-Legendre point q of an n_gauss-point rule

@@ -67,7 +67,7 @@ def _declare(L):
         "dd_shutdown": (C.c_int, []),
         "dd_timing_enable": (C.c_int, [C.c_int]),
         "dd_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
-                                     C.POINTER(C.c_int64), C.c_int]),
+                                     C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]),
         "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
                                       C.POINTER(Material), C.c_int, C.c_int, dbl, vp, vp]),
         "dd_glide_step": (C.c_int, [i64, vp, vp, i64, vp, vp, vp, C.POINTER(Material), dbl,
@@ -159,10 +159,12 @@ def dd_timing_enable(on: bool) -> bool:
 
 
 def dd_timing_read(reset=True):
-    """(summed pair-kernel milliseconds, launches, near-field FP64 evaluations)."""
-    ms, n, near = C.c_double(), C.c_int64(), C.c_int64()
-    _check(lib().dd_timing_read(C.byref(ms), C.byref(n), C.byref(near), 1 if reset else 0))
-    return ms.value, n.value, near.value
+    """(summed pair-kernel milliseconds, launches, mixed-kernel FP64 near-field
+    evaluations, mixed-kernel FP32 source-quadrature evaluations)."""
+    ms, n, near, quad = C.c_double(), C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().dd_timing_read(C.byref(ms), C.byref(n), C.byref(near), C.byref(quad),
+                                1 if reset else 0))
+    return ms.value, n.value, near.value, quad.value
 
 
 # -------------------------------------------------------------- force path --

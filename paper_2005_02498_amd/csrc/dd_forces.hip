@@ -350,23 +350,27 @@ __global__ __launch_bounds__(TILE) void k_pair64(const Item *__restrict__ items,
     }
 }
 
-// Mixed precision: far pairs in FP32 (cancellation-free arrangement, FP32
-// accumulation over one LDS stage), near pairs (minimum distance from the
-// Gauss point to the closed source segment below the cutoff) in FP64.  The
-// target-source offset, its axial part y and its perpendicular part rho are
-// formed in FP64 and rounded once, so nearly collinear far pairs keep rho.
+// Mixed precision.  Each pair is first located in FP32 from FP32 positions:
+// when the target point lies at least max(30 L, cutoff + L/2) from the
+// source midpoint, the source is evaluated by FP32 2-point quadrature (the
+// integrand is evaluated directly, so FP32 position rounding costs at most
+// ~1e-6 relative there).  Other pairs get their offset, axial and
+// perpendicular parts in FP64: those closer than the cutoff (minimum distance
+// from the Gauss point to the closed source segment) are evaluated in FP64,
+// the rest by the cancellation-free FP32 closed form.  FP32 contributions
+// are accumulated in FP32 over one LDS stage, then added to FP64 sums.
 __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ items,
                                                      const Tile *__restrict__ tiles,
                                                      const double *__restrict__ rec,
                                                      const float *__restrict__ rec32,
                                                      int64_t ns, GaussRule g, double k1,
-                                                     double k2, float cut2,
+                                                     double k2, float cut,
                                                      double *__restrict__ partial,
                                                      unsigned long long *near_count)
 {
     __shared__ double shx[6][TILE];    // x1, t (FP64)
-    __shared__ unsigned n_near_block;
-    __shared__ float shf[7][TILE];     // L, b, c (FP32)
+    __shared__ float shf[13][TILE];    // x1, t, L, b, c (FP32)
+    __shared__ unsigned n_near_block, n_quad_block;
     const Item it = items[blockIdx.x];
     const Tile tl = tiles[it.tile];
     const int lane = threadIdx.x;
@@ -382,52 +386,75 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
     const double xq0 = rec[0 * ns + j] + sq * L * rec[3 * ns + j];
     const double xq1 = rec[1 * ns + j] + sq * L * rec[4 * ns + j];
     const double xq2 = rec[2 * ns + j] + sq * L * rec[5 * ns + j];
+    const float xf0 = (float)xq0, xf1 = (float)xq1, xf2 = (float)xq2;
     const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
     const float fb0 = (float)bj0, fb1 = (float)bj1, fb2 = (float)bj2;
-    const float fk1 = (float)k1, fk2 = (float)k2;
+    const float fk1 = (float)k1, fk2 = (float)k2, cut2 = cut * cut;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    unsigned n_near = 0;
-    if (lane == 0) n_near_block = 0;
+    unsigned n_near = 0, n_quad = 0;
+    if (lane == 0) {
+        n_near_block = 0;
+        n_quad_block = 0;
+    }
 
     for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
         const int n = (int)min<int64_t>(TILE, it.src_end - base);
         __syncthreads();
         if (lane < n) {
+            const int64_t sidx = base + lane;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) shx[k][lane] = rec[k * ns + base + lane];
-            shf[0][lane] = rec32[3 * ns + base + lane];
+            for (int k = 0; k < 6; ++k) {
+                const double v = rec[k * ns + sidx];
+                shx[k][lane] = v;
+                shf[k][lane] = (float)v;
+            }
 #pragma unroll
-            for (int k = 0; k < 6; ++k) shf[1 + k][lane] = rec32[(4 + k) * ns + base + lane];
+            for (int k = 0; k < 7; ++k) shf[6 + k][lane] = rec32[(3 + k) * ns + sidx];
         }
         __syncthreads();
         float f0 = 0.f, f1 = 0.f, f2 = 0.f;
         for (int m = 0; m < n; ++m) {
             const int64_t i = base + m;
+            const float t0 = shf[3][m], t1 = shf[4][m], t2 = shf[5][m], Ls = shf[6][m];
+            // FP32 location of the target relative to the source
+            const float e0 = xf0 - shf[0][m], e1 = xf1 - shf[1][m], e2 = xf2 - shf[2][m];
+            const float ye = e0 * t0 + e1 * t1 + e2 * t2;
+            const float g0 = e0 - ye * t0, g1 = e1 - ye * t1, g2 = e2 - ye * t2;
+            const float ym = ye - 0.5f * Ls;
+            const float GB = fmaxf(GAUSS_BAND * Ls, cut + 0.5f * Ls);
+            float c0, c1, c2;
+            if (g0 * g0 + g1 * g1 + g2 * g2 + ym * ym >= GB * GB) {
+                n_quad += valid ? 1u : 0u;
+                pair_sigma_b_f32_gauss2(ye, g0, g1, g2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[7][m],
+                                        shf[8][m], shf[9][m], shf[10][m], shf[11][m], shf[12][m], fk1,
+                                        fk2, c0, c1, c2);
+                f0 += c0;
+                f1 += c1;
+                f2 += c2;
+                continue;
+            }
+            // offset, axial and perpendicular parts in FP64, rounded once
             const double T0 = shx[3][m], T1 = shx[4][m], T2 = shx[5][m];
             const double R0 = xq0 - shx[0][m], R1 = xq1 - shx[1][m], R2 = xq2 - shx[2][m];
             const double yd = R0 * T0 + R1 * T1 + R2 * T2;
             const float y = (float)yd;
             const float h0 = (float)(R0 - yd * T0), h1 = (float)(R1 - yd * T1), h2 = (float)(R2 - yd * T2);
-            const float Ls = shf[0][m];
             const float ya = y - fminf(fmaxf(y, 0.f), Ls);
-            const float dmin2 = h0 * h0 + h1 * h1 + h2 * h2 + ya * ya;
-            if (dmin2 < cut2) {
+            if (h0 * h0 + h1 * h1 + h2 * h2 + ya * ya < cut2) {
                 if (i != j) {
                     n_near += valid ? 1u : 0u;
-                    double c0, c1, c2;
+                    double d0, d1, d2;
                     pair_sigma_b_f64(xq0, xq1, xq2, bj0, bj1, bj2, shx[0][m], shx[1][m], shx[2][m],
                                      T0, T1, T2, rec[6 * ns + i], rec[7 * ns + i], rec[8 * ns + i],
                                      rec[9 * ns + i], rec[10 * ns + i], rec[11 * ns + i],
-                                     rec[12 * ns + i], k1, k2, c0, c1, c2);
-                    a0 += c0;
-                    a1 += c1;
-                    a2 += c2;
+                                     rec[12 * ns + i], k1, k2, d0, d1, d2);
+                    a0 += d0;
+                    a1 += d1;
+                    a2 += d2;
                 }
             } else {
-                float c0, c1, c2;
-                pair_sigma_b_f32(y, h0, h1, h2, fb0, fb1, fb2, (float)T0, (float)T1, (float)T2, Ls,
-                                 shf[1][m], shf[2][m], shf[3][m], shf[4][m], shf[5][m], shf[6][m],
-                                 fk1, fk2, c0, c1, c2);
+                pair_sigma_b_f32(y, h0, h1, h2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[7][m], shf[8][m],
+                                 shf[9][m], shf[10][m], shf[11][m], shf[12][m], fk1, fk2, c0, c1, c2);
                 f0 += c0;
                 f1 += c1;
                 f2 += c2;
@@ -444,8 +471,10 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
         o[2 * TILE + lane] = a2;
     }
     if (n_near) atomicAdd(&n_near_block, n_near);
+    if (n_quad) atomicAdd(&n_quad_block, n_quad);
     __syncthreads();
     if (lane == 0 && n_near_block) atomicAdd(near_count, (unsigned long long)n_near_block);
+    if (lane == 0 && n_quad_block) atomicAdd(near_count + 1, (unsigned long long)n_quad_block);
 }
 
 // ------------------------------ a3 + a4: Peach-Koehler and the quadrature --
@@ -814,7 +843,7 @@ struct ForceCtx {
     GaussRule g{};
     double k1 = 0, k2 = 0, inv_a = 0, inv_mu = 0, fscale = 0, a = 0;
     int precision = DD_FP64;
-    float cut2 = 0.f;
+    float cut = 0.f;
 };
 
 // Cache of the last uploaded plan (the tables depend only on sizes).
@@ -846,7 +875,7 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
     C.inv_mu = 1.0 / m->mu;
     C.fscale = m->mu * m->a * m->a;
     C.precision = precision;
-    C.cut2 = (float)(near_cut * near_cut);
+    C.cut = (float)near_cut;
     C.L.nn = nn;
     C.L.ns = ns;
     void *p;
@@ -940,7 +969,7 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
             timing_begin(st, ws->capturing);
             if (C.precision == DD_MIXED)
                 hipLaunchKernelGGL(k_pair_mixed, dim3((unsigned)C.n_items), dim3(TILE), 0, st, C.items,
-                                   C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut2, C.partial,
+                                   C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut, C.partial,
                                    ws->near_count);
             else
                 hipLaunchKernelGGL(k_pair64, dim3((unsigned)C.n_items), dim3(TILE), 0, st, C.items,

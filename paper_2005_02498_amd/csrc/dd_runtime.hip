@@ -169,7 +169,8 @@ int dd_set_validation(int on) { return dd::g_validate.exchange(on ? 1 : 0); }
 
 int dd_timing_enable(int on) { return dd::g_timing.exchange(on ? 1 : 0); }
 
-int dd_timing_read(double *kernel_ms, int64_t *launches, int64_t *near_evals, int reset)
+int dd_timing_read(double *kernel_ms, int64_t *launches, int64_t *near_evals, int64_t *quad_evals,
+                   int reset)
 {
     dd::clear_error();
     double total = 0.0;
@@ -186,11 +187,12 @@ int dd_timing_read(double *kernel_ms, int64_t *launches, int64_t *near_evals, in
     dd::Workspace *ws = nullptr;
     int rc = dd::workspace(&ws);
     if (rc) return rc;
-    unsigned long long cnt = 0;
+    unsigned long long cnt[2] = {0, 0};
     if (hipDeviceSynchronize() != hipSuccess) return dd::set_error(DD_EHIP, "hipDeviceSynchronize failed");
-    if (hipMemcpy(&cnt, ws->near_count, sizeof cnt, hipMemcpyDeviceToHost) != hipSuccess)
-        return dd::set_error(DD_EHIP, "reading the near-pair counter failed");
-    if (near_evals) *near_evals = (int64_t)cnt;
+    if (hipMemcpy(cnt, ws->near_count, sizeof cnt, hipMemcpyDeviceToHost) != hipSuccess)
+        return dd::set_error(DD_EHIP, "reading the band counters failed");
+    if (near_evals) *near_evals = (int64_t)cnt[0];
+    if (quad_evals) *quad_evals = (int64_t)cnt[1];
     if (reset) {
         dd::g_ev_used = 0;
         if (hipMemset(ws->near_count, 0, sizeof cnt) != hipSuccess)
