@@ -40,10 +40,10 @@ UNIT = "segment-pair evals/s"
 # counted on the closed form as written in csrc/dd_pair.h (add, sub, mul = 1,
 # fma = 2, sqrt / rsqrt / reciprocal = 1; selects and compares = 0).
 FLOP_F64_EVAL = 169          # FP64 path
-FLOP_MIX_LOC_F32 = 27        # mixed: FP32 location and band test (every pair)
+FLOP_MIX_PREP_F64 = 14       # mixed: FP64 offset, axial, perpendicular parts (every pair)
+FLOP_MIX_BAND_F32 = 13       # mixed: |rho|^2 and distance-to-midpoint band test (every pair)
 FLOP_MIX_QUAD_F32 = 145      # mixed: FP32 2-point source quadrature (well-separated pairs)
-FLOP_MIX_PREP_F64 = 14       # mixed: FP64 offset, axial, perpendicular parts (other pairs)
-FLOP_MIX_CLASS_F32 = 8       # mixed: minimum-distance test (other pairs)
+FLOP_MIX_CLASS_F32 = 3       # mixed: minimum-distance test (other pairs)
 FLOP_MIX_FAR_F32 = 179       # mixed: FP32 cancellation-free closed form
 FLOP_MIX_NEAR_F64 = 169      # mixed: FP64 closed form (near pairs)
 PEAK_F64 = 78.6e12
@@ -51,7 +51,7 @@ PEAK_F32 = 157.3e12
 HBM_PEAK = 8.0e12
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair64_volume16384_q2_traffic.json")
-KERNEL_SOURCES = ["paper_2005_02498_amd/csrc/dd_forces.hip", "paper_2005_02498_amd/csrc/dd_pair.h"]
+KERNEL_SOURCES = ["paper_2005_02498_amd/csrc/dd_pair64.hip", "paper_2005_02498_amd/csrc/dd_pair64.h"]
 
 
 def kernel_source_sha() -> str:
@@ -159,10 +159,10 @@ def main():
         else:
             near, quad = bands
             allp = N * N * Q                 # including the (skipped) self pairs
-            other = allp - quad              # pairs that take the FP64 location
+            other = allp - quad              # pairs that take the minimum-distance test
             closed = pairs * Q - quad - near
-            f64 = FLOP_MIX_PREP_F64 * other + FLOP_MIX_NEAR_F64 * near
-            f32 = (FLOP_MIX_LOC_F32 * allp + FLOP_MIX_QUAD_F32 * quad
+            f64 = FLOP_MIX_PREP_F64 * allp + FLOP_MIX_NEAR_F64 * near
+            f32 = (FLOP_MIX_BAND_F32 * allp + FLOP_MIX_QUAD_F32 * quad
                    + FLOP_MIX_CLASS_F32 * other + FLOP_MIX_FAR_F32 * closed)
         flops = f64 + f32
         t_roof = f64 / PEAK_F64 + f32 / PEAK_F32

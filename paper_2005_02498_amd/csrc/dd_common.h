@@ -110,4 +110,11 @@ constexpr int REC32 = 10;
 
 GaussRule gauss_rule(int n);
 
+// All-pairs launchers (one workgroup per work item, TILE threads).
+void launch_pair64(const Item *items, const Tile *tiles, const double *rec, int64_t ns, const GaussRule &g,
+                   double k1, double k2, double *partial, int64_t n_items, hipStream_t st);
+void launch_pair_mixed(const Item *items, const Tile *tiles, const double *rec, const float *rec32, int64_t ns,
+                       const GaussRule &g, double k1, double k2, float cut, double *partial,
+                       unsigned long long *counters, int64_t n_items, hipStream_t st);
+
 }  // namespace dd

@@ -13,7 +13,6 @@
 #include <vector>
 
 #include "dd_common.h"
-#include "dd_pair.h"
 
 namespace dd {
 
@@ -263,218 +262,6 @@ __global__ void k_csr_sort(const int32_t *ptr, int64_t nn, int32_t *list)
         }
         list[k + 1] = v;
     }
-}
-
-// ------------------------------------------ a2: the all-pairs FP64 kernel --
-// One workgroup = one work item: up to TILE target Gauss points (one per
-// lane) against a contiguous source range, staged through LDS TILE sources at
-// a time.  Each lane accumulates sigma b_j (3 values) over the range; the
-// item's partial sums go to their own slot, reduced in a fixed order later.
-// Only LDS stages that overlap the tile's own segments test for the excluded
-// self pair.
-template <bool SELF>
-__device__ __forceinline__ void pair64_stage(double (*sh)[TILE], int n, int64_t base, int64_t j,
-                                             double xq0, double xq1, double xq2, double bj0,
-                                             double bj1, double bj2, double k1, double k2,
-                                             double &a0, double &a1, double &a2)
-{
-    // runs of sources sharing consecutive nodes: one fresh inverse distance
-    // per run, then each source reuses the previous source's far endpoint
-    for (int m = 0; m < n;) {
-        const int run = min(__builtin_amdgcn_readfirstlane((int)sh[13][m]), n - m);
-        const double R0 = xq0 - sh[0][m], R1 = xq1 - sh[1][m], R2 = xq2 - sh[2][m];
-        double rprev = rsqrt64(R0 * R0 + R1 * R1 + R2 * R2 + 1.0);
-        for (int e = m + run; m < e; ++m) {
-            double c0, c1, c2;
-            pair_sigma_b_f64c(xq0, xq1, xq2, bj0, bj1, bj2, sh[0][m], sh[1][m], sh[2][m], sh[3][m],
-                              sh[4][m], sh[5][m], sh[6][m], sh[7][m], sh[8][m], sh[9][m], sh[10][m],
-                              sh[11][m], sh[12][m], k1, k2, true, rprev, c0, c1, c2);
-            if (SELF) {
-                const bool self = (base + m) == j;
-                a0 += self ? 0.0 : c0;
-                a1 += self ? 0.0 : c1;
-                a2 += self ? 0.0 : c2;
-            } else {
-                a0 += c0;
-                a1 += c1;
-                a2 += c2;
-            }
-        }
-    }
-}
-
-__global__ __launch_bounds__(TILE) void k_pair64(const Item *__restrict__ items,
-                                                 const Tile *__restrict__ tiles,
-                                                 const double *__restrict__ rec, int64_t ns,
-                                                 GaussRule g, double k1, double k2,
-                                                 double *__restrict__ partial)
-{
-    __shared__ double sh[14][TILE];
-    const Item it = items[blockIdx.x];
-    const Tile tl = tiles[it.tile];
-    const int lane = threadIdx.x;
-    const bool valid = lane < tl.n_points;
-    const int64_t p = tl.point_begin + (valid ? lane : 0);
-    const int Q = g.n;
-    const int64_t j = p / Q;
-    const int q = (int)(p - j * Q);
-    const int64_t jlo = tl.point_begin / Q, jhi = (tl.point_begin + tl.n_points - 1) / Q;
-    double sq = g.s[0];
-    for (int k = 1; k < DD_MAX_GAUSS; ++k)
-        if (k == q) sq = g.s[k];
-    const double L = rec[6 * ns + j];
-    const double xq0 = rec[0 * ns + j] + sq * L * rec[3 * ns + j];
-    const double xq1 = rec[1 * ns + j] + sq * L * rec[4 * ns + j];
-    const double xq2 = rec[2 * ns + j] + sq * L * rec[5 * ns + j];
-    const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-
-    for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
-        const int n = (int)min<int64_t>(TILE, it.src_end - base);
-        __syncthreads();
-        if (lane < n) {
-#pragma unroll
-            for (int k = 0; k < 14; ++k) sh[k][lane] = rec[k * ns + base + lane];
-        }
-        __syncthreads();
-        if (base <= jhi && base + n > jlo)
-            pair64_stage<true>(sh, n, base, j, xq0, xq1, xq2, bj0, bj1, bj2, k1, k2, a0, a1, a2);
-        else
-            pair64_stage<false>(sh, n, base, j, xq0, xq1, xq2, bj0, bj1, bj2, k1, k2, a0, a1, a2);
-    }
-    if (valid) {
-        double *o = partial + it.slot * 3 * TILE;
-        o[lane] = a0;
-        o[TILE + lane] = a1;
-        o[2 * TILE + lane] = a2;
-    }
-}
-
-// Mixed precision.  Each pair is first located in FP32 from FP32 positions:
-// when the target point lies at least max(30 L, cutoff + L/2) from the
-// source midpoint, the source is evaluated by FP32 2-point quadrature (the
-// integrand is evaluated directly, so FP32 position rounding costs at most
-// ~1e-6 relative there).  Other pairs get their offset, axial and
-// perpendicular parts in FP64: those closer than the cutoff (minimum distance
-// from the Gauss point to the closed source segment) are evaluated in FP64,
-// the rest by the cancellation-free FP32 closed form.  FP32 contributions
-// are accumulated in FP32 over one LDS stage, then added to FP64 sums.
-__global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ items,
-                                                     const Tile *__restrict__ tiles,
-                                                     const double *__restrict__ rec,
-                                                     const float *__restrict__ rec32,
-                                                     int64_t ns, GaussRule g, double k1,
-                                                     double k2, float cut,
-                                                     double *__restrict__ partial,
-                                                     unsigned long long *near_count)
-{
-    __shared__ double shx[6][TILE];    // x1, t (FP64)
-    __shared__ float shf[13][TILE];    // x1, t, L, b, c (FP32)
-    __shared__ unsigned n_near_block, n_quad_block;
-    const Item it = items[blockIdx.x];
-    const Tile tl = tiles[it.tile];
-    const int lane = threadIdx.x;
-    const bool valid = lane < tl.n_points;
-    const int64_t p = tl.point_begin + (valid ? lane : 0);
-    const int Q = g.n;
-    const int64_t j = p / Q;
-    const int q = (int)(p - j * Q);
-    double sq = g.s[0];
-    for (int k = 1; k < DD_MAX_GAUSS; ++k)
-        if (k == q) sq = g.s[k];
-    const double L = rec[6 * ns + j];
-    const double xq0 = rec[0 * ns + j] + sq * L * rec[3 * ns + j];
-    const double xq1 = rec[1 * ns + j] + sq * L * rec[4 * ns + j];
-    const double xq2 = rec[2 * ns + j] + sq * L * rec[5 * ns + j];
-    const float xf0 = (float)xq0, xf1 = (float)xq1, xf2 = (float)xq2;
-    const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
-    const float fb0 = (float)bj0, fb1 = (float)bj1, fb2 = (float)bj2;
-    const float fk1 = (float)k1, fk2 = (float)k2, cut2 = cut * cut;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    unsigned n_near = 0, n_quad = 0;
-    if (lane == 0) {
-        n_near_block = 0;
-        n_quad_block = 0;
-    }
-
-    for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
-        const int n = (int)min<int64_t>(TILE, it.src_end - base);
-        __syncthreads();
-        if (lane < n) {
-            const int64_t sidx = base + lane;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const double v = rec[k * ns + sidx];
-                shx[k][lane] = v;
-                shf[k][lane] = (float)v;
-            }
-#pragma unroll
-            for (int k = 0; k < 7; ++k) shf[6 + k][lane] = rec32[(3 + k) * ns + sidx];
-        }
-        __syncthreads();
-        float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-        for (int m = 0; m < n; ++m) {
-            const int64_t i = base + m;
-            const float t0 = shf[3][m], t1 = shf[4][m], t2 = shf[5][m], Ls = shf[6][m];
-            // FP32 location of the target relative to the source
-            const float e0 = xf0 - shf[0][m], e1 = xf1 - shf[1][m], e2 = xf2 - shf[2][m];
-            const float ye = e0 * t0 + e1 * t1 + e2 * t2;
-            const float g0 = e0 - ye * t0, g1 = e1 - ye * t1, g2 = e2 - ye * t2;
-            const float ym = ye - 0.5f * Ls;
-            const float GB = fmaxf(GAUSS_BAND * Ls, cut + 0.5f * Ls);
-            float c0, c1, c2;
-            if (g0 * g0 + g1 * g1 + g2 * g2 + ym * ym >= GB * GB) {
-                n_quad += valid ? 1u : 0u;
-                pair_sigma_b_f32_gauss2(ye, g0, g1, g2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[7][m],
-                                        shf[8][m], shf[9][m], shf[10][m], shf[11][m], shf[12][m], fk1,
-                                        fk2, c0, c1, c2);
-                f0 += c0;
-                f1 += c1;
-                f2 += c2;
-                continue;
-            }
-            // offset, axial and perpendicular parts in FP64, rounded once
-            const double T0 = shx[3][m], T1 = shx[4][m], T2 = shx[5][m];
-            const double R0 = xq0 - shx[0][m], R1 = xq1 - shx[1][m], R2 = xq2 - shx[2][m];
-            const double yd = R0 * T0 + R1 * T1 + R2 * T2;
-            const float y = (float)yd;
-            const float h0 = (float)(R0 - yd * T0), h1 = (float)(R1 - yd * T1), h2 = (float)(R2 - yd * T2);
-            const float ya = y - fminf(fmaxf(y, 0.f), Ls);
-            if (h0 * h0 + h1 * h1 + h2 * h2 + ya * ya < cut2) {
-                if (i != j) {
-                    n_near += valid ? 1u : 0u;
-                    double d0, d1, d2;
-                    pair_sigma_b_f64(xq0, xq1, xq2, bj0, bj1, bj2, shx[0][m], shx[1][m], shx[2][m],
-                                     T0, T1, T2, rec[6 * ns + i], rec[7 * ns + i], rec[8 * ns + i],
-                                     rec[9 * ns + i], rec[10 * ns + i], rec[11 * ns + i],
-                                     rec[12 * ns + i], k1, k2, d0, d1, d2);
-                    a0 += d0;
-                    a1 += d1;
-                    a2 += d2;
-                }
-            } else {
-                pair_sigma_b_f32(y, h0, h1, h2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[7][m], shf[8][m],
-                                 shf[9][m], shf[10][m], shf[11][m], shf[12][m], fk1, fk2, c0, c1, c2);
-                f0 += c0;
-                f1 += c1;
-                f2 += c2;
-            }
-        }
-        a0 += (double)f0;
-        a1 += (double)f1;
-        a2 += (double)f2;
-    }
-    if (valid) {
-        double *o = partial + it.slot * 3 * TILE;
-        o[lane] = a0;
-        o[TILE + lane] = a1;
-        o[2 * TILE + lane] = a2;
-    }
-    if (n_near) atomicAdd(&n_near_block, n_near);
-    if (n_quad) atomicAdd(&n_quad_block, n_quad);
-    __syncthreads();
-    if (lane == 0 && n_near_block) atomicAdd(near_count, (unsigned long long)n_near_block);
-    if (lane == 0 && n_quad_block) atomicAdd(near_count + 1, (unsigned long long)n_quad_block);
 }
 
 // ------------------------------ a3 + a4: Peach-Koehler and the quadrature --
@@ -968,12 +755,10 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         if (C.n_items > 0) {
             timing_begin(st, ws->capturing);
             if (C.precision == DD_MIXED)
-                hipLaunchKernelGGL(k_pair_mixed, dim3((unsigned)C.n_items), dim3(TILE), 0, st, C.items,
-                                   C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut, C.partial,
-                                   ws->near_count);
+                launch_pair_mixed(C.items, C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut, C.partial,
+                                  ws->near_count, C.n_items, st);
             else
-                hipLaunchKernelGGL(k_pair64, dim3((unsigned)C.n_items), dim3(TILE), 0, st, C.items,
-                                   C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial);
+                launch_pair64(C.items, C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial, C.n_items, st);
             timing_end(st, ws->capturing);
         }
         hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
