@@ -87,11 +87,193 @@ def parse():
     ap.add_argument("--burst-steps", type=int, default=200)
     ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy"], default=None,
                     help="profiling aid: run only one part (no JSON contract)")
+    ap.add_argument("--surrogate-study", action="store_true",
+                    help="run the surrogate speed-up-at-fixed-error study and write --study-out")
+    ap.add_argument("--study-train", type=int, default=65536)
+    ap.add_argument("--study-states", type=int, default=256)
+    ap.add_argument("--study-seeds", type=int, default=16)
+    ap.add_argument("--study-epochs", type=int, default=60)
+    ap.add_argument("--study-out", default=os.path.join(ROOT, "gpurun_out", "surrogate_study.json"))
     return ap.parse_args()
+
+
+SURROGATE_FILE = os.path.join(ROOT, "profiles", "surrogate_study.json")
+
+
+def surrogate_study(args):
+    """Surrogate speed-up at fixed error.
+
+    Data: one 200-step mixed-precision burst per training state (states drawn
+    like the batched-burst workload from seeds 2,000,000 + i: k ~ U{8..128}
+    loops, mobile fraction, applied stress), features = resolved shear stress
+    and mobile/sessile line densities per system of the initial state,
+    targets = the 12 burst-averaged slip rates.  Held out: S states (seeds
+    3,000,000 + s) x M microstructures each; reference = the M-burst mean
+    Rbar_s.  The network: 4 members, densities as log10 of m^-2 (floor 1e10),
+    standardised, Adam.  Errors are (sum_s |pred_s - Rbar_s|^2 / sum_s
+    |Rbar_s|^2)^(1/2).  DD at error e needs n(e) = E1^2 / e^2 bursts per state
+    (E1: the single-burst error, from the per-state sample covariance); its
+    cost is n(e) times the measured mean burst time.  The surrogate is judged
+    on one microstructure per state (the second half of each state's
+    microstructures) against the mean of the first half, with that reference's
+    own noise E1^2 / (M/2) removed in quadrature.  Its cost per state is its
+    measured inference time per point plus, for the fraction of points whose
+    ensemble spread exceeds 5 % (spread floor: 10 % of the training RMS rate),
+    the DD cost at the same error.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2005_02498_amd as dd
+    from paper_2005_02498_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    mat = {"mu": W.MU, "nu": W.NU, "a": W.CORE_A, "B": W.DRAG_B}
+    dd.dd_set_validation(False)
+    t_start = time.perf_counter()
+
+    def bursts(instances):
+        bt = W.pack(instances)
+        d = dict(x=torch.tensor(bt.x, device=dev), sn=torch.tensor(bt.seg_nodes, device=dev),
+                 b=torch.tensor(bt.burgers, device=dev), n=torch.tensor(bt.normal, device=dev),
+                 p=torch.tensor(bt.pinned, device=dev), s=torch.tensor(bt.sigma_app, device=dev),
+                 v=torch.tensor(bt.volume, device=dev))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, f = dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["sn"], d["b"], d["n"], d["p"],
+                                 d["s"], d["v"], mat, 2, dd.DD_MIXED, 20.0, 200, W.DT,
+                                 want_features=True)
+        torch.cuda.synchronize()
+        return r.cpu().numpy(), f.cpu().numpy(), time.perf_counter() - t0
+
+    def log(msg):
+        print(f"[{time.perf_counter() - t_start:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+    B = 512
+    Xtr, Ytr, sec, n_b = [], [], 0.0, 0
+    for b0 in range(0, args.study_train, B):
+        ins = [W.burst_instance(2_000_000 + i) for i in range(b0, min(b0 + B, args.study_train))]
+        r, f, t = bursts(ins)
+        Xtr.append(f); Ytr.append(r); sec += t; n_b += len(ins)
+        log(f"training bursts {n_b}/{args.study_train} ({t:.2f} s for {len(ins)})")
+    Xtr = np.concatenate(Xtr); Ytr = np.concatenate(Ytr)
+    S, M = args.study_states, args.study_seeds
+    pairs_ho = [(s, k) for s in range(S) for k in range(M)]
+    Xho, Yho = [], []
+    for b0 in range(0, len(pairs_ho), B):
+        ins = [W.burst_instance_state(3_000_000 + s, 4_000_000 + M * s + k) for s, k in pairs_ho[b0:b0 + B]]
+        r, f, t = bursts(ins)
+        Xho.append(f); Yho.append(r); sec += t; n_b += len(ins)
+        log(f"held-out bursts {min(b0 + B, len(pairs_ho))}/{len(pairs_ho)}")
+    Xho = np.concatenate(Xho).reshape(S, M, 36); Yho = np.concatenate(Yho).reshape(S, M, 12)
+    t_burst = sec / n_b
+
+    # ---- training (all device work in the library's kernels)
+    dens_scale, dens_floor = 1.0 / W.B_SI ** 2, 1e10
+    Xt = Xtr.copy()
+    Xt[:, 12:] = np.log10(np.maximum(Xt[:, 12:], 0) * dens_scale + dens_floor)
+    in_shift = Xt.mean(0); in_scale = 1.0 / np.maximum(Xt.std(0), 1e-6)
+    out_shift = Ytr.mean(0); out_scale = np.maximum(Ytr.std(0), 1e-30)
+    model = dd.SurrogateModel(4, 12345)
+    model.set_log_densities(dens_scale, dens_floor)
+    model.set_scaling(in_shift, in_scale, out_shift, out_scale)
+    Xd = torch.tensor(Xtr, dtype=torch.float32, device=dev)
+    Yd = torch.tensor(Ytr, dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(0)
+    nb = 1024
+    steps_per_epoch = max(1, len(Xtr) // nb)
+    t0 = time.perf_counter()
+    losses = []
+    for ep in range(args.study_epochs):
+        lr = 1e-3 if ep < 0.6 * args.study_epochs else (3e-4 if ep < 0.85 * args.study_epochs else 1e-4)
+        perm = torch.tensor(rng.permutation(len(Xtr)), device=dev)
+        for k in range(steps_per_epoch):
+            idx = perm[k * nb:(k + 1) * nb]
+            loss = dd.dd_mlp_train_step(model, Xd[idx].contiguous(), Yd[idx].contiguous(), lr)
+        losses.append(loss.cpu().numpy().tolist())
+        if ep % 10 == 0 or ep == args.study_epochs - 1:
+            log(f"epoch {ep}: loss per member {np.round(losses[-1], 4).tolist()}")
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    # ---- evaluation on the held-out states.  Each state's microstructures are
+    # split: the first half gives the reference mean, the second half is what
+    # the surrogate (and DD) is judged on, so reference noise is independent
+    # and is removed in quadrature.
+    floor_rate = 0.1 * float(np.sqrt(np.mean(Ytr ** 2)))     # spread floor, rate units
+    model.set_spread_floor(floor_rate)
+    Fho = torch.tensor(Xho.reshape(-1, 36), dtype=torch.float32, device=dev)
+    pr, sp, fl = dd.dd_surrogate_rates(model, Fho, 0.05)
+    pred = pr.cpu().numpy().astype(np.float64).reshape(S, M, 12)
+    spread = sp.cpu().numpy().reshape(S, M)
+    half = M // 2
+    RA = Yho[:, :half].mean(1)
+    Rbar = Yho.mean(1)
+    den = float(np.sum(Rbar ** 2))
+    cov_tr = np.sum(Yho.var(1, ddof=1), axis=1)              # trace of the per-state covariance
+    E1 = float(np.sqrt(np.sum(cov_tr) / den))                # one burst vs the state mean
+    ref2 = E1 ** 2 / half                                    # noise of the half-sample reference
+    raw = float(np.mean(np.sum((pred[:, half:] - RA[:, None, :]) ** 2, axis=(0, 2))) / den)
+    E_sur1 = float(np.sqrt(max(raw - ref2, 0.0)))
+    raw_mean = float(np.sum((pred[:, half:].mean(1) - RA) ** 2) / den)
+    E_sur_mean = float(np.sqrt(max(raw_mean - ref2, 0.0)))
+    E_const = float(np.sqrt(max(np.sum((out_shift[None, :] - RA) ** 2) / den - ref2, 0.0)))
+    flagged = spread[:, half:] > 0.05
+
+    # ---- inference cost: 1,048,576 points per call
+    n_inf = 1 << 20
+    Fin = Fho[torch.tensor(rng.integers(0, len(Fho), n_inf), device=dev)].contiguous()
+    for _ in range(2):
+        dd.dd_surrogate_rates(model, Fin, 0.05)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        dd.dd_surrogate_rates(model, Fin, 0.05)
+    torch.cuda.synchronize()
+    t_inf_call = (time.perf_counter() - t0) / reps
+    t_inf = t_inf_call / n_inf
+
+    def n_needed(e):
+        return max(1, int(np.ceil((E1 / e) ** 2)))
+
+    f_flag = float(flagged.mean())
+    res = {"study": "surrogate speed-up at fixed error",
+           "training_states": int(len(Xtr)), "heldout_states": S, "microstructures_per_state": M,
+           "burst": "200 glide steps, mixed precision, 2 Gauss points, one graph launch per 512",
+           "mean_burst_seconds": t_burst, "data_generation_seconds": sec, "training_seconds": t_train,
+           "epochs": args.study_epochs, "final_losses": losses[-1],
+           "inference_seconds_per_call": t_inf_call, "inference_points_per_call": n_inf,
+           "inference_tflops": 1.20e12 * n_inf / (1 << 20) / t_inf_call / 1e12,
+           "error_single_burst": E1, "error_reference_noise": float(np.sqrt(ref2)),
+           "error_surrogate_one_microstructure": E_sur1,
+           "error_surrogate_mean_of_microstructures": E_sur_mean,
+           "error_mean_rate_predictor": E_const, "spread_floor_rate": floor_rate,
+           "fallback_fraction": f_flag,
+           "fallback_fraction_at_tol": {str(t): float((spread[:, half:] > t).mean())
+                                        for t in (0.05, 0.1, 0.2, 0.5)}}
+    for name, e in (("at_surrogate_error", E_sur1), ("at_5_percent", 0.05)):
+        n = n_needed(e)
+        dd_cost = n * t_burst
+        sur_cost = t_inf + f_flag * dd_cost
+        res[name] = {"error": e, "dd_bursts_per_state": n, "dd_seconds_per_state": dd_cost,
+                     "surrogate_seconds_per_state": sur_cost, "speedup": dd_cost / sur_cost,
+                     "speedup_without_fallback": dd_cost / t_inf,
+                     "surrogate_reaches_it": bool(E_sur1 <= e + 1e-12)}
+    res["total_seconds"] = time.perf_counter() - t_start
+    os.makedirs(os.path.dirname(args.study_out), exist_ok=True)
+    with open(args.study_out, "w") as f:
+        json.dump(res, f, indent=1)
+    np.savez_compressed(os.path.splitext(args.study_out)[0] + "_data.npz", Xtr=Xtr.astype(np.float32),
+                        Ytr=Ytr.astype(np.float32), Xho=Xho.astype(np.float32), Yho=Yho.astype(np.float32))
+    print(json.dumps(res))
 
 
 def main():
     args = parse()
+    if args.surrogate_study:
+        surrogate_study(args)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the force path shards by loops across GPUs by design, but no multi-GPU code "
@@ -243,6 +425,14 @@ def main():
             print(json.dumps(bursts))
             return
         out["bursts"] = bursts
+
+    if os.path.exists(SURROGATE_FILE) and args.only is None:
+        with open(SURROGATE_FILE) as f:
+            sur = json.load(f)
+        out["surrogate"] = {"speedup_at_fixed_error": sur["at_surrogate_error"]["speedup"],
+                            "error": sur["at_surrogate_error"]["error"],
+                            "reaches_5_percent": sur["at_5_percent"]["surrogate_reaches_it"],
+                            "source": "profiles/surrogate_study.json (python bench.py --surrogate-study)"}
 
     if args.cpu_targets > 0:
         import oracle as O

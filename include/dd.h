@@ -225,6 +225,16 @@ int dd_mlp_get_params(const dd_mlp *model, int member, float *host_params);
 int dd_mlp_set_scaling(dd_mlp *model, const float *in_shift, const float *in_scale,
                        const float *out_shift, const float *out_scale);
 
+/* Density features 12..35 enter the network as log10(rho * dens_scale +
+ * dens_floor) (before standardisation) when dens_floor > 0; dens_floor = 0
+ * (the default) passes them through unchanged.  Resolved shear stresses
+ * (features 0..11) are never transformed. */
+int dd_mlp_set_log_densities(dd_mlp *model, float dens_scale, float dens_floor);
+
+/* Floor of the spread denominator in dd_surrogate_rates (default 1e-30):
+ * spread = |std|_2 / max(|mean|_2, floor), in rate units.  floor >= 0. */
+int dd_mlp_set_spread_floor(dd_mlp *model, float floor);
+
 /* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) of
  * every member on the same mini-batch: feat [n][36], target rates [n][12]
  * (device float32, unstandardised); loss_out (device float32

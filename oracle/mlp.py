@@ -107,10 +107,19 @@ class Adam:
             p -= self.lr * (m / c1) / (np.sqrt(v / c2) + self.eps)
 
 
+def transform_features(feat, log_dens=None):
+    """Density features 12..35 -> log10(rho * scale + floor) when log_dens =
+    (scale, floor) is given; resolved shear stresses unchanged."""
+    f = np.array(feat, np.float64)
+    if log_dens is not None and log_dens[1] > 0:
+        f[:, 12:] = np.log10(np.maximum(f[:, 12:], 0.0) * log_dens[0] + log_dens[1])
+    return f
+
+
 def ensemble_predict(members, feat, in_shift, in_scale, out_shift, out_scale,
-                     tol=0.05, floor=1e-30, bf16=False):
+                     tol=0.05, floor=1e-30, bf16=False, log_dens=None):
     """members: list of (Ws, bs).  Returns (rates [n][12], spread [n], needs_dd [n])."""
-    x = (np.asarray(feat, np.float64) - in_shift) * in_scale
+    x = (transform_features(feat, log_dens) - in_shift) * in_scale
     ys = []
     for Ws, bs in members:
         y, _ = forward(Ws, bs, x, bf16)

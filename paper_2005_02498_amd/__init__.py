@@ -27,7 +27,8 @@ EXPORTS = [
     "dd_timing_enable", "dd_timing_read",
     "dd_nodal_forces", "dd_glide_step", "dd_burst_batch",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
-    "dd_mlp_set_scaling", "dd_mlp_train_step", "dd_mlp_gradients", "dd_surrogate_rates",
+    "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
+    "dd_surrogate_rates",
 ]
 
 
@@ -80,6 +81,8 @@ def _declare(L):
         "dd_mlp_set_params": (C.c_int, [vp, C.c_int, fp]),
         "dd_mlp_get_params": (C.c_int, [vp, C.c_int, fp]),
         "dd_mlp_set_scaling": (C.c_int, [vp, fp, fp, fp, fp]),
+        "dd_mlp_set_log_densities": (C.c_int, [vp, C.c_float, C.c_float]),
+        "dd_mlp_set_spread_floor": (C.c_int, [vp, C.c_float]),
         "dd_mlp_train_step": (C.c_int, [vp, i64, vp, vp, C.c_float, vp, vp]),
         "dd_mlp_gradients": (C.c_int, [vp, i64, vp, vp, vp, vp, vp]),
         "dd_surrogate_rates": (C.c_int, [vp, i64, vp, vp, vp, vp, C.c_float, vp]),
@@ -285,6 +288,12 @@ class SurrogateModel:
         c, p3 = _host_f32(out_shift, MLP_OUT, "out_shift")
         d, p4 = _host_f32(out_scale, MLP_OUT, "out_scale")
         _check(lib().dd_mlp_set_scaling(self.handle, p1, p2, p3, p4))
+
+    def set_spread_floor(self, floor):
+        _check(lib().dd_mlp_set_spread_floor(self.handle, C.c_float(floor)))
+
+    def set_log_densities(self, dens_scale, dens_floor):
+        _check(lib().dd_mlp_set_log_densities(self.handle, C.c_float(dens_scale), C.c_float(dens_floor)))
 
 
 def dd_mlp_train_step(model: SurrogateModel, feat, target, lr=1e-3, loss_out=None, stream=None):

@@ -161,7 +161,11 @@ static void gemm(const GemmArgs &g, int members, hipStream_t st)
 }
 
 // ------------------------------------------------------- small kernels --
-// X0[r][k] = bf16((feat[r][k] - shift[k]) * scale[k]) for k < 36, 0 up to 64
+// X0[r][k] = bf16((f - shift[k]) * scale[k]) for k < 36 (0 up to 64), with
+// f = log10(max(feat, 0) * dens_scale + dens_floor) for the density features
+// 12..35 when dens_floor > 0, f = feat otherwise.
+constexpr int SCAL = 2 * IN + 2 * OUT + 3;   // shifts/scales, dens_scale, dens_floor, spread floor
+
 __global__ void k_standardize(const float *__restrict__ feat, int64_t n, const float *__restrict__ scal,
                               __bf16 *__restrict__ X0)
 {
@@ -170,7 +174,12 @@ __global__ void k_standardize(const float *__restrict__ feat, int64_t n, const f
     const int64_t r = i / INP;
     const int k = (int)(i % INP);
     float v = 0.f;
-    if (k < IN) v = (feat[r * IN + k] - scal[k]) * scal[IN + k];
+    if (k < IN) {
+        float f = feat[r * IN + k];
+        const float dfloor = scal[2 * IN + 2 * OUT + 1];
+        if (k >= 12 && dfloor > 0.f) f = log10f(fmaxf(f, 0.f) * scal[2 * IN + 2 * OUT] + dfloor);
+        v = (f - scal[k]) * scal[IN + k];
+    }
     X0[i] = to_bf16(v);
 }
 
@@ -320,7 +329,7 @@ __global__ void k_ensemble(const float *__restrict__ Y, int64_t sY, int members,
         m2 += mean[o] * mean[o];
         rates[r * OUT + o] = mean[o];
     }
-    const float sp = sqrtf(s2) / fmaxf(sqrtf(m2), 1e-30f);
+    const float sp = sqrtf(s2) / fmaxf(sqrtf(m2), scal[2 * IN + 2 * OUT + 2]);
     spread[r] = sp;
     needs_dd[r] = sp > tol ? 1 : 0;
 }
@@ -339,7 +348,7 @@ struct dd_mlp {
     int64_t t = 0;                                        // Adam steps taken
     __bf16 *W1p = nullptr, *W2 = nullptr, *W3 = nullptr, *W4p = nullptr;
     float *scal = nullptr;                                // device [2*36 + 2*12]
-    float h_scal[2 * IN + 2 * OUT];                       // host copy
+    float h_scal[SCAL];                                   // host copy
     float *dW1 = nullptr, *dW2 = nullptr, *dW3 = nullptr, *dW4 = nullptr, *db = nullptr;
     // row workspace, sized for `cap` rows
     int64_t cap = 0;
@@ -573,7 +582,7 @@ extern "C" int dd_mlp_create(int n_members, uint64_t seed, dd_mlp **out)
     if (!rc) rc = dev_alloc((void **)&h->W2, sizeof(__bf16) * M * HID * HID);
     if (!rc) rc = dev_alloc((void **)&h->W3, sizeof(__bf16) * M * HID * HID);
     if (!rc) rc = dev_alloc((void **)&h->W4p, sizeof(__bf16) * M * OUTP * HID);
-    if (!rc) rc = dev_alloc((void **)&h->scal, sizeof(float) * (2 * IN + 2 * OUT));
+    if (!rc) rc = dev_alloc((void **)&h->scal, sizeof(float) * SCAL);
     if (!rc) rc = dev_alloc((void **)&h->dW1, sizeof(float) * M * HID * INP);
     if (!rc) rc = dev_alloc((void **)&h->dW2, sizeof(float) * M * HID * HID);
     if (!rc) rc = dev_alloc((void **)&h->dW3, sizeof(float) * M * HID * HID);
@@ -602,6 +611,9 @@ extern "C" int dd_mlp_create(int n_members, uint64_t seed, dd_mlp **out)
     }
     for (int k = 0; k < IN; ++k) { h->h_scal[k] = 0.f; h->h_scal[IN + k] = 1.f; }
     for (int k = 0; k < OUT; ++k) { h->h_scal[2 * IN + k] = 0.f; h->h_scal[2 * IN + OUT + k] = 1.f; }
+    h->h_scal[2 * IN + 2 * OUT] = 1.f;
+    h->h_scal[2 * IN + 2 * OUT + 1] = 0.f;
+    h->h_scal[2 * IN + 2 * OUT + 2] = 1e-30f;
     if (hipMemcpy(h->w, p.data(), sizeof(float) * M * P, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(h->m1, 0, sizeof(float) * M * P) != hipSuccess ||
         hipMemset(h->m2, 0, sizeof(float) * M * P) != hipSuccess ||
@@ -667,7 +679,8 @@ extern "C" int dd_mlp_set_scaling(dd_mlp *h, const float *in_shift, const float 
     int rc;
     if ((rc = check_model(h))) return rc;
     if (!in_shift || !in_scale || !out_shift || !out_scale) return set_error(DD_EINVAL, "null scaling array");
-    float s[2 * IN + 2 * OUT];
+    float s[SCAL];
+    std::memcpy(s, h->h_scal, sizeof s);
     std::memcpy(s, in_shift, sizeof(float) * IN);
     std::memcpy(s + IN, in_scale, sizeof(float) * IN);
     std::memcpy(s + 2 * IN, out_shift, sizeof(float) * OUT);
@@ -679,6 +692,32 @@ extern "C" int dd_mlp_set_scaling(dd_mlp *h, const float *in_shift, const float 
     DD_HIP(hipDeviceSynchronize());
     std::memcpy(h->h_scal, s, sizeof s);
     DD_HIP(hipMemcpy(h->scal, s, sizeof s, hipMemcpyHostToDevice));
+    return DD_OK;
+}
+
+extern "C" int dd_mlp_set_log_densities(dd_mlp *h, float dens_scale, float dens_floor)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_model(h))) return rc;
+    if (!(dens_floor >= 0.f) || !std::isfinite(dens_floor) || !(dens_scale > 0.f) || !std::isfinite(dens_scale))
+        return set_error(DD_EINVAL, "need dens_scale > 0 and dens_floor >= 0");
+    DD_HIP(hipDeviceSynchronize());
+    h->h_scal[2 * IN + 2 * OUT] = dens_scale;
+    h->h_scal[2 * IN + 2 * OUT + 1] = dens_floor;
+    DD_HIP(hipMemcpy(h->scal, h->h_scal, sizeof h->h_scal, hipMemcpyHostToDevice));
+    return DD_OK;
+}
+
+extern "C" int dd_mlp_set_spread_floor(dd_mlp *h, float floor)
+{
+    clear_error();
+    int rc;
+    if ((rc = check_model(h))) return rc;
+    if (!(floor >= 0.f) || !std::isfinite(floor)) return set_error(DD_EINVAL, "spread floor must be >= 0");
+    DD_HIP(hipDeviceSynchronize());
+    h->h_scal[2 * IN + 2 * OUT + 2] = std::max(floor, 1e-30f);
+    DD_HIP(hipMemcpy(h->scal, h->h_scal, sizeof h->h_scal, hipMemcpyHostToDevice));
     return DD_OK;
 }
 

@@ -95,25 +95,20 @@ def _loops(rng, n_loops, box, rmin, rmax, log_radius=False, nseg=SEGS_PER_LOOP):
     phi0 = rng.uniform(0.0, 2.0 * math.pi, n_loops)
 
     n_nodes = n_loops * nseg
-    x = np.empty((3, n_nodes))
-    seg = np.empty((2, n_nodes), np.int32)
-    bur = np.empty((3, n_nodes))
-    nor = np.empty((3, n_nodes))
     k = np.arange(nseg)
-    for i in range(n_loops):
-        n = PLANE_NORMALS[planes[i]]
-        # in-plane orthonormal pair (e1, e2) with e1 x e2 = n
-        e1 = SLIP_DIRS[planes[i], 0].copy()
-        e2 = np.cross(n, e1)
-        ang = phi0[i] + 2.0 * math.pi * k / nseg
-        pts = centres[i][:, None] + radii[i] * (np.cos(ang)[None, :] * e1[:, None]
-                                                + np.sin(ang)[None, :] * e2[:, None])
-        base = i * nseg
-        x[:, base:base + nseg] = pts
-        seg[0, base:base + nseg] = base + k
-        seg[1, base:base + nseg] = base + (k + 1) % nseg
-        bur[:, base:base + nseg] = (signs[i] * SLIP_DIRS[planes[i], dirs[i]])[:, None]
-        nor[:, base:base + nseg] = n[:, None]
+    nrm = PLANE_NORMALS[planes]                      # [n_loops][3]
+    e1 = SLIP_DIRS[planes, 0]                        # in-plane pair (e1, e2), e1 x e2 = n
+    e2 = np.cross(nrm, e1)
+    ang = phi0[:, None] + 2.0 * math.pi * k[None, :] / nseg          # [n_loops][nseg]
+    pts = centres[:, :, None] + radii[:, None, None] * (np.cos(ang)[:, None, :] * e1[:, :, None]
+                                                        + np.sin(ang)[:, None, :] * e2[:, :, None])
+    x = np.ascontiguousarray(pts.transpose(1, 0, 2).reshape(3, n_nodes))
+    base = (np.arange(n_loops) * nseg)[:, None]
+    seg = np.ascontiguousarray(np.stack([(base + k[None, :]).ravel(),
+                                         (base + (k[None, :] + 1) % nseg).ravel()]).astype(np.int32))
+    bvec = signs[:, None] * SLIP_DIRS[planes, dirs]  # [n_loops][3]
+    bur = np.ascontiguousarray(np.repeat(bvec.T, nseg, axis=1))
+    nor = np.ascontiguousarray(np.repeat(nrm.T, nseg, axis=1))
     meta = {"planes": planes, "dirs": dirs, "signs": signs, "radii": radii,
             "centres": centres, "phi0": phi0}
     return x, seg, bur, nor, meta
@@ -216,3 +211,19 @@ def surrogate_state(seed) -> Instance:
     """One training/inference state for the slip-rate surrogate: a burst volume
     drawn like ``burst_instance`` from its own seed stream."""
     return burst_instance(seed)
+
+
+def burst_instance_state(state_seed, micro_seed, box=2000.0, kmin=8, kmax=128) -> Instance:
+    """Like ``burst_instance``, but the state (k loops, mobile fraction f,
+    applied stress) is drawn from ``state_seed`` and the microstructure (the
+    loops) from ``micro_seed``: several microstructures of one state."""
+    rng = np.random.default_rng(state_seed)
+    k = int(rng.integers(kmin, kmax + 1))
+    f = float(rng.uniform(0.1, 0.9))
+    sig = rng.uniform(-100e6, 100e6, 6)
+    x, seg, bur, nor, meta = _loops(np.random.default_rng(micro_seed), k, box, 100.0, 500.0)
+    n_mob = int(round(f * k))
+    pinned = np.zeros(x.shape[1], np.uint8)
+    pinned[n_mob * SEGS_PER_LOOP:] = 1
+    return Instance(x, seg, bur, nor, pinned, sig, float(box) ** 3,
+                    dict(meta, seed=(state_seed, micro_seed), box=box, k=k, f=f, n_mobile_loops=n_mob))

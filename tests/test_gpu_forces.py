@@ -201,3 +201,45 @@ def test_glide_step_multiple_normals():
                              None, dict(MAT, B=2.0), 1.0)
         np.testing.assert_allclose(v.cpu().numpy(), vo, rtol=0, atol=1e-15)
         np.testing.assert_allclose(xt.cpu().numpy(), xo, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("prec,tol", [(dd.DD_FP64, TOL64), (dd.DD_MIXED, TOLMIX)])
+def test_large_volume_sampled(prec, tol):
+    """262,144 segments (8192 loops, radii 50-2000 b, 50,000 b cube) at full
+    size: two whole loops against every source, by the oracle."""
+    inst = W.config3()
+    F = _gpu_forces(inst, 2, prec)
+    assert np.all(np.isfinite(F))
+    num, den = 0.0, 0.0
+    for lp in (17, 6000):
+        t0, t1 = 32 * lp, 32 * lp + 32
+        ref = O.nodal_forces_sampled(inst.x, inst.seg_nodes, inst.burgers, inst.sigma_app,
+                                     W.MU, W.NU, W.CORE_A, 2, t0, t1)[:, t0:t1]
+        num = max(num, np.linalg.norm(F[:, t0:t1] - ref, axis=0).max())
+        den = max(den, np.linalg.norm(ref, axis=0).max())
+    print(f"large volume sampled prec={prec} err {num / den:.2e}")
+    assert num / den < tol
+
+
+def test_large_volume_mixed_vs_fp64_ten_steps():
+    """Mixed against the FP64 GPU path on every node of the large volume, at
+    step 0 and after 10 glide steps of each."""
+    inst = W.config3()
+    d = dev(inst)
+    x64 = d["x"].clone()
+    xmx = d["x"].clone()
+    errs = []
+    for step in range(11):
+        F64 = dd.dd_nodal_forces(x64, d["seg_nodes"], d["burgers"], d["normal"], inst.sigma_app, MAT, 2,
+                                 dd.DD_FP64)
+        Fmx = dd.dd_nodal_forces(xmx, d["seg_nodes"], d["burgers"], d["normal"], inst.sigma_app, MAT, 2,
+                                 dd.DD_MIXED)
+        if step in (0, 10):
+            errs.append(normwise(Fmx.cpu().numpy(), F64.cpu().numpy()))
+        if step < 10:
+            dd.dd_glide_step(x64, F64, d["seg_nodes"], d["normal"], d["pinned"], MAT, W.DT)
+            dd.dd_glide_step(xmx, Fmx, d["seg_nodes"], d["normal"], d["pinned"], MAT, W.DT)
+    disp = normwise((xmx - d["x"]).cpu().numpy(), (x64 - d["x"]).cpu().numpy())
+    print(f"large volume mixed vs fp64: force err step0 {errs[0]:.2e} step10 {errs[1]:.2e}, "
+          f"displacement err {disp:.2e}")
+    assert max(errs) < TOLMIX and disp < TOLMIX

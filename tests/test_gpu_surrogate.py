@@ -180,3 +180,22 @@ def test_invalid_arguments():
         mdl.set_params(2, np.zeros(dd.MLP_PARAMS, np.float32))
     with pytest.raises(dd.DDError):
         dd.SurrogateModel(0, 0)
+
+
+def test_forward_parity_log_densities():
+    mdl, params, sc = _model()
+    rng = np.random.default_rng(5)
+    feat = np.concatenate([rng.normal(size=(300, 12)) * 5e7,
+                           np.where(rng.uniform(size=(300, 24)) < 0.3, 0.0,
+                                    10 ** rng.uniform(-9, -6, (300, 24)))], 1).astype(np.float32)
+    dens = (1.0 / (0.2556e-9) ** 2, 1e10)
+    mdl.set_log_densities(*dens)
+    shift = np.concatenate([np.zeros(12), np.full(24, 12.0)]).astype(np.float32)
+    scale = np.concatenate([np.full(12, 1e-8), np.full(24, 1.0)]).astype(np.float32)
+    mdl.set_scaling(shift, scale, sc[2], sc[3])
+    r, s, f = dd.dd_surrogate_rates(mdl, torch.tensor(feat, device=DEV), 0.05)
+    ro, so, fo = M.ensemble_predict(params, feat.astype(np.float64), shift, scale, sc[2], sc[3],
+                                    tol=0.05, bf16=True, log_dens=dens)
+    e = nrel(r.cpu().numpy(), ro)
+    print(f"surrogate forward with log densities err {e:.2e}")
+    assert e < TOL
