@@ -100,6 +100,18 @@ int dd_set_validation(int on);
 /* Release the workspace of every device this thread's process used. */
 int dd_shutdown(void);
 
+/* Work-item autotuner on (1, default) or off (0: a fixed heuristic).  When
+ * on, the first dd_nodal_forces / dd_burst_batch call for a new problem
+ * class (GPU architecture, Gauss points, precision, and the instance count,
+ * total and largest instance size rounded up to powers of two) times the
+ * candidate source-range lengths of a work item on one all-pairs pass over
+ * its own inputs (synchronising the stream) and keeps the fastest for the
+ * process; with the environment variable DD_AUTOTUNE_CACHE naming a file,
+ * choices are also read from and appended to it.  Results do not depend on
+ * the choice beyond the order of floating-point sums.  Returns the previous
+ * setting. */
+int dd_set_autotune(int on);
+
 /* Measurement hooks (for benchmarks and profilers).  With timing on, every
  * launch of the all-pairs kernel made outside graph capture is bracketed by a
  * HIP event pair recorded on the caller's stream.  dd_timing_read waits for

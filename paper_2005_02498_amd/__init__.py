@@ -24,7 +24,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
-    "dd_timing_enable", "dd_timing_read",
+    "dd_timing_enable", "dd_timing_read", "dd_set_autotune",
     "dd_nodal_forces", "dd_glide_step", "dd_burst_batch",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -67,6 +67,7 @@ def _declare(L):
         "dd_set_validation": (C.c_int, [C.c_int]),
         "dd_shutdown": (C.c_int, []),
         "dd_timing_enable": (C.c_int, [C.c_int]),
+        "dd_set_autotune": (C.c_int, [C.c_int]),
         "dd_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]),
         "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
@@ -155,6 +156,10 @@ def dd_shutdown():
 
 def dd_last_error() -> str:
     return lib().dd_last_error().decode()
+
+
+def dd_set_autotune(on: bool) -> bool:
+    return bool(lib().dd_set_autotune(1 if on else 0))
 
 
 def dd_timing_enable(on: bool) -> bool:

@@ -9,7 +9,12 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "dd_common.h"
@@ -769,6 +774,146 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
                        C.csr_list, nn, ns, C.segF, F);
 }
 
+// ------------------------------------------------------------- autotuner --
+// The source-range length of a work item (how many sources one workgroup
+// streams through LDS for its 256 target points) sets the number of items,
+// the partial-sum traffic and the load balance between uneven instances.  On
+// the first call for a given (GPU architecture, Gauss points, precision,
+// instance count, total and largest instance size, in powers of two) the
+// candidates below are timed with HIP events on one all-pairs pass over the
+// caller's own data, and the fastest is kept for the process (and appended
+// to the file named by DD_AUTOTUNE_CACHE, read back at start-up).
+std::atomic<int> g_autotune{1};
+
+struct TuneKey {
+    std::string arch;
+    int Q, prec, li, ls, lm;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(arch, Q, prec, li, ls, lm) < std::tie(o.arch, o.Q, o.prec, o.li, o.ls, o.lm);
+    }
+};
+std::map<TuneKey, int64_t> g_tuned;
+std::mutex g_tune_mu;
+bool g_tune_loaded = false;
+
+int ceil_log2(int64_t v)
+{
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+void load_tune_cache()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("DD_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *fp = std::fopen(path, "r");
+    if (!fp) return;
+    char arch[128];
+    int Q, prec, li, ls, lm;
+    long long c;
+    while (std::fscanf(fp, "%127s %d %d %d %d %d %lld", arch, &Q, &prec, &li, &ls, &lm, &c) == 7)
+        g_tuned[TuneKey{arch, Q, prec, li, ls, lm}] = c;
+    std::fclose(fp);
+}
+
+void save_tune(const TuneKey &k, int64_t c)
+{
+    const char *path = std::getenv("DD_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *fp = std::fopen(path, "a");
+    if (!fp) return;
+    std::fprintf(fp, "%s %d %d %d %d %d %lld\n", k.arch.c_str(), k.Q, k.prec, k.li, k.ls, k.lm, (long long)c);
+    std::fclose(fp);
+}
+
+// Returns the chunk length to use (0 = the built-in heuristic).
+int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, int64_t nn,
+                const Layout &inst, const int32_t *seg_nodes, const double *x, const double *burgers,
+                const double *normal, const dd_material *m, int Q, int prec, double cut, bool need_sys,
+                int64_t *out)
+{
+    *out = 0;
+    if (!g_autotune.load()) return DD_OK;
+    const int n_inst = (int)so.size() - 1;
+    int64_t ns = so.back(), nmax = 0;
+    for (int i = 0; i < n_inst; ++i) nmax = std::max(nmax, so[i + 1] - so[i]);
+    if (ns < 2 * TILE) return DD_OK;   // nothing to choose
+    double evals = 0.0;
+    for (int i = 0; i < n_inst; ++i) evals += (double)(so[i + 1] - so[i]) * (double)(so[i + 1] - so[i]) * Q;
+    if (evals > 2e10) return DD_OK;   // one timed pass would cost more than the choice can save
+    const int reps = evals > 1e9 ? 1 : 2;
+    hipDeviceProp_t prop;
+    DD_HIP(hipGetDeviceProperties(&prop, ws->device));
+    TuneKey key{prop.gcnArchName, Q, prec, ceil_log2(n_inst), ceil_log2(ns), ceil_log2(nmax)};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_cache();
+    auto itk = g_tuned.find(key);
+    if (itk != g_tuned.end()) {
+        *out = itk->second;
+        return DD_OK;
+    }
+    std::vector<int64_t> cands = {0};
+    for (int64_t c = TILE; c < nmax; c *= 2) cands.push_back(c);
+    cands.push_back(((nmax + TILE - 1) / TILE) * TILE);   // one range per tile
+    hipEvent_t e0, e1;
+    DD_HIP(hipEventCreate(&e0));
+    DD_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int64_t best_c = 0;
+    int rc = DD_OK;
+    for (int64_t c : cands) {
+        ForceCtx C;
+        if ((rc = setup(ws, st, so, nn, seg_nodes, m, Q, prec, cut, c, need_sys, C))) break;
+        PrepArgs A{};
+        A.L = C.L;
+        A.L.seg_inst = inst.seg_inst;
+        A.L.node_off = inst.node_off;
+        A.L.seg_off = inst.seg_off;
+        A.x = x;
+        A.seg_nodes = seg_nodes;
+        A.burgers = burgers;
+        A.normal = normal;
+        A.inv_a = C.inv_a;
+        A.rec64 = C.rec64;
+        A.rec32 = C.rec32;
+        A.flags = ws->flags_dev;
+        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
+        double t_min = 1e300;
+        for (int rep = 0; rep < reps; ++rep) {
+            (void)hipEventRecord(e0, st);
+            if (prec == DD_MIXED)
+                launch_pair_mixed(C.items, C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut, C.partial,
+                                  ws->near_count, C.n_items, st);
+            else
+                launch_pair64(C.items, C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial, C.n_items, st);
+            (void)hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = set_error(DD_EHIP, "autotuner timing failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t_min = std::min(t_min, (double)ms);
+        }
+        if (rc) break;
+        if (t_min < best) {
+            best = t_min;
+            best_c = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    g_tuned[key] = best_c;
+    save_tune(key, best_c);
+    *out = best_c;
+    return DD_OK;
+}
+
 int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, double near_cut)
 {
     if (n_nodes < 0 || n_segs < 0) return set_error(DD_EINVAL, "negative node or segment count");
@@ -785,6 +930,8 @@ int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, d
 }  // namespace dd
 
 using namespace dd;
+
+extern "C" int dd_set_autotune(int on) { return dd::g_autotune.exchange(on ? 1 : 0); }
 
 extern "C" int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
                                const int32_t *seg_nodes, const double *burgers,
@@ -807,7 +954,12 @@ extern "C" int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
     if ((rc = workspace(&ws))) return rc;
     ForceCtx C;
     std::vector<int64_t> so = {0, n_segs};
-    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, 0, false, C)))
+    int64_t chunk = 0;
+    Layout flat{};
+    if ((rc = tuned_chunk(ws, st, so, n_nodes, flat, seg_nodes, x, burgers, normal, m, n_gauss, precision,
+                          near_cutoff_a, false, &chunk)))
+        return rc;
+    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, chunk, false, C)))
         return rc;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
     launch_csr(C, seg_nodes, st);
@@ -917,9 +1069,7 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
     if ((rc = workspace(&ws))) return rc;
 
     std::vector<int64_t> so(seg_off, seg_off + n_inst + 1), no(node_off, node_off + n_inst + 1);
-    ForceCtx C;
-    if ((rc = setup(ws, st, so, nn, seg_nodes, m, n_gauss, precision, near_cutoff_a, 0, true, C))) return rc;
-    // instance tables: seg -> instance, node and segment offsets
+    // instance tables: segment -> instance, node offsets then segment offsets
     std::vector<int32_t> si((size_t)std::max<int64_t>(ns, 1), 0);
     for (int i = 0; i < n_inst; ++i)
         for (int64_t s = so[i]; s < so[i + 1]; ++s) si[s] = i;
@@ -928,13 +1078,21 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
     std::vector<int64_t> offs;
     offs.insert(offs.end(), no.begin(), no.end());
     offs.insert(offs.end(), so.begin(), so.end());
-    // instance node offsets then segment offsets (the tile offsets of the
-    // plan live in WS_OFFS)
     int64_t *d_offs;
     if ((rc = upload(ws, WS_INST_OFFS, offs, &d_offs, st))) return rc;
-    C.L.seg_inst = d_si;
-    C.L.node_off = d_offs;
-    C.L.seg_off = d_offs + (n_inst + 1);
+    Layout inst{};
+    inst.seg_inst = d_si;
+    inst.node_off = d_offs;
+    inst.seg_off = d_offs + (n_inst + 1);
+    ForceCtx C;
+    int64_t chunk = 0;
+    if ((rc = tuned_chunk(ws, st, so, nn, inst, seg_nodes, x, burgers, normal, m, n_gauss, precision,
+                          near_cutoff_a, true, &chunk)))
+        return rc;
+    if ((rc = setup(ws, st, so, nn, seg_nodes, m, n_gauss, precision, near_cutoff_a, chunk, true, C))) return rc;
+    C.L.seg_inst = inst.seg_inst;
+    C.L.node_off = inst.node_off;
+    C.L.seg_off = inst.seg_off;
     C.L.tile_begin = (const int64_t *)ws->ptr[WS_OFFS];
     void *p;
     if ((rc = ensure(ws, WS_VEL, sizeof(double) * 3 * std::max<int64_t>(nn, 1), &p))) return rc;

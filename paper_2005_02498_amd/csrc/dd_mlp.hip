@@ -334,6 +334,112 @@ __global__ void k_ensemble(const float *__restrict__ Y, int64_t sY, int members,
     needs_dd[r] = sp > tol ? 1 : 0;
 }
 
+
+// ------------------------------------------------- fused inference kernel --
+// One workgroup (4 waves) carries FROWS rows of one member (blockIdx.y)
+// through all four layers: the standardised inputs and every hidden
+// activation stay in LDS (rows padded by 8 bf16 so that the 16-byte fragment
+// reads of 16 consecutive rows fall in distinct banks), weight fragments are
+// read from global memory (L2-resident), bias + ReLU are applied when a layer's
+// accumulators are written back to LDS.  Hidden layers: each wave owns 64
+// output columns = 4 x 4 tiles of v_mfma_f32_16x16x32_bf16 over the 64 rows.
+// Output layer: each wave owns 16 rows x 16 (padded) columns.
+constexpr int FROWS = 64;
+constexpr int HSTR = HID + 8;   // LDS row stride of hidden activations (bf16)
+constexpr int XSTR = INP + 8;   // LDS row stride of the input tile
+
+__device__ __forceinline__ bf16x8 lds_frag(const __bf16 *p)
+{
+    return *reinterpret_cast<const bf16x8 *>(p);
+}
+
+__device__ __forceinline__ bf16x8 glb_frag(const __bf16 *p)
+{
+    return *reinterpret_cast<const bf16x8 *>(p);
+}
+
+template <int K, int ASTR>
+__device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ Ain, __bf16 *__restrict__ Hout,
+                                             const __bf16 *__restrict__ W, const float *__restrict__ bias,
+                                             int wave, int lane)
+{
+    // W: [HID][K] (out, in), K contiguous
+    f32x4 acc[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int lr = lane & 15, lk = (lane >> 4) * 8;
+    const int n0 = wave * 64;
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 b[4], a[4];
+        for (int j = 0; j < 4; ++j) b[j] = glb_frag(W + (int64_t)(n0 + 16 * j + lr) * K + k0 + lk);
+        for (int i = 0; i < 4; ++i) a[i] = lds_frag(Ain + (16 * i + lr) * ASTR + k0 + lk);
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    for (int j = 0; j < 4; ++j) {
+        const int n = n0 + 16 * j + lr;
+        const float bn = bias[n];
+        for (int i = 0; i < 4; ++i)
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * i + (lane >> 4) * 4 + e;
+                Hout[r * HSTR + n] = to_bf16(fmaxf(acc[i][j][e] + bn, 0.f));
+            }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ feat, int64_t n,
+                                                   const float *__restrict__ scal, const __bf16 *__restrict__ W1p,
+                                                   const __bf16 *__restrict__ W2, const __bf16 *__restrict__ W3,
+                                                   const __bf16 *__restrict__ W4p, const float *__restrict__ w,
+                                                   float *__restrict__ Y, int64_t sY)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 X[FROWS * XSTR];
+    __shared__ __attribute__((aligned(16))) __bf16 HA[FROWS * HSTR];
+    __shared__ __attribute__((aligned(16))) __bf16 HB[FROWS * HSTR];
+    const int member = blockIdx.y;
+    const int64_t r0 = (int64_t)blockIdx.x * FROWS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const float dfloor = scal[2 * IN + 2 * OUT + 1], dscale = scal[2 * IN + 2 * OUT];
+    // standardised input tile (rows beyond n are zero)
+    for (int i = tid; i < FROWS * INP; i += 256) {
+        const int r = i / INP, k = i % INP;
+        float v = 0.f;
+        if (k < IN && r0 + r < n) {
+            float f = feat[(r0 + r) * IN + k];
+            if (k >= 12 && dfloor > 0.f) f = log10f(fmaxf(f, 0.f) * dscale + dfloor);
+            v = (f - scal[k]) * scal[IN + k];
+        }
+        X[r * XSTR + k] = to_bf16(v);
+    }
+    __syncthreads();
+    const float *wm = w + member * P;
+    hidden_layer<INP, XSTR>(X, HA, W1p + (int64_t)member * HID * INP, wm + OB1, wave, lane);
+    __syncthreads();
+    hidden_layer<HID, HSTR>(HA, HB, W2 + (int64_t)member * HID * HID, wm + OB2, wave, lane);
+    __syncthreads();
+    hidden_layer<HID, HSTR>(HB, HA, W3 + (int64_t)member * HID * HID, wm + OB3, wave, lane);
+    __syncthreads();
+    // output layer: wave owns rows 16 wave .. +15, 16 padded columns
+    {
+        const int lr = lane & 15, lk = (lane >> 4) * 8;
+        const __bf16 *W4m = W4p + (int64_t)member * OUTP * HID;
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < HID; k0 += 32) {
+            const bf16x8 a = lds_frag(HA + (16 * wave + lr) * HSTR + k0 + lk);
+            const bf16x8 b = glb_frag(W4m + lr * HID + k0 + lk);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        }
+        const int o = lr;
+        const float bo = o < OUT ? wm[OB4 + o] : 0.f;
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r = r0 + 16 * wave + (lane >> 4) * 4 + e;
+            if (r < n) Y[member * sY + r * OUTP + o] = acc[e] + bo;
+        }
+    }
+}
+
 }  // namespace mlp
 }  // namespace dd
 
@@ -772,9 +878,9 @@ extern "C" int dd_surrogate_rates(const dd_mlp *hc, int64_t n, const float *feat
     if ((rc = ensure_rows(h, chunk, false))) return rc;
     for (int64_t r0 = 0; r0 < n; r0 += chunk) {
         const int64_t m = std::min(chunk, n - r0);
-        hipLaunchKernelGGL(k_standardize, dim3((unsigned)((m * INP + 255) / 256)), dim3(256), 0, st,
-                           feat + r0 * IN, m, h->scal, h->X0);
-        forward(h, m, st);
+        dim3 grid((unsigned)((m + FROWS - 1) / FROWS), h->members);
+        hipLaunchKernelGGL(k_mlp_infer, grid, dim3(256), 0, st, feat + r0 * IN, m, h->scal, h->W1p, h->W2, h->W3,
+                           h->W4p, h->w, h->Y, m * OUTP);
         hipLaunchKernelGGL(k_ensemble, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, h->Y, m * OUTP,
                            h->members, m, h->scal, spread_tol, rates + r0 * OUT, spread + r0, needs_dd + r0);
     }

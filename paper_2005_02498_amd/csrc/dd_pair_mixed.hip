@@ -25,7 +25,7 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                                                      unsigned long long *near_count)
 {
     __shared__ double shx[6][TILE];    // x1, t (FP64)
-    __shared__ float shf[13][TILE];    // x1, t, L, b, c (FP32)
+    __shared__ float shf[10][TILE];    // t, L, b, c (FP32)
     __shared__ unsigned n_near_block, n_quad_block;
     const Item it = items[blockIdx.x];
     const Tile tl = tiles[it.tile];
@@ -42,7 +42,6 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
     const double xq0 = rec[0 * ns + j] + sq * L * rec[3 * ns + j];
     const double xq1 = rec[1 * ns + j] + sq * L * rec[4 * ns + j];
     const double xq2 = rec[2 * ns + j] + sq * L * rec[5 * ns + j];
-    const float xf0 = (float)xq0, xf1 = (float)xq1, xf2 = (float)xq2;
     const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
     const float fb0 = (float)bj0, fb1 = (float)bj1, fb2 = (float)bj2;
     const float fk1 = (float)k1, fk2 = (float)k2, cut2 = cut * cut;
@@ -59,19 +58,15 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
         if (lane < n) {
             const int64_t sidx = base + lane;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const double v = rec[k * ns + sidx];
-                shx[k][lane] = v;
-                shf[k][lane] = (float)v;
-            }
+            for (int k = 0; k < 6; ++k) shx[k][lane] = rec[k * ns + sidx];
 #pragma unroll
-            for (int k = 0; k < 7; ++k) shf[6 + k][lane] = rec32[(3 + k) * ns + sidx];
+            for (int k = 0; k < 10; ++k) shf[k][lane] = rec32[k * ns + sidx];
         }
         __syncthreads();
         float f0 = 0.f, f1 = 0.f, f2 = 0.f;
         for (int m = 0; m < n; ++m) {
             const int64_t i = base + m;
-            const float t0 = shf[3][m], t1 = shf[4][m], t2 = shf[5][m], Ls = shf[6][m];
+            const float t0 = shf[0][m], t1 = shf[1][m], t2 = shf[2][m], Ls = shf[3][m];
             // offset, axial and perpendicular parts in FP64, rounded once
             const double T0 = shx[3][m], T1 = shx[4][m], T2 = shx[5][m];
             const double R0 = xq0 - shx[0][m], R1 = xq1 - shx[1][m], R2 = xq2 - shx[2][m];
@@ -86,8 +81,8 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
             // wavefront qualifies, so no wavefront runs both branches
             if (__all(hh + ym * ym >= GB * GB)) {
                 n_quad += valid ? 1u : 0u;
-                pair_sigma_b_f32_gauss2(y, h0, h1, h2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[7][m], shf[8][m],
-                                        shf[9][m], shf[10][m], shf[11][m], shf[12][m], fk1, fk2, c0, c1, c2);
+                pair_sigma_b_f32_gauss2(y, h0, h1, h2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[4][m], shf[5][m],
+                                        shf[6][m], shf[7][m], shf[8][m], shf[9][m], fk1, fk2, c0, c1, c2);
                 f0 += c0;
                 f1 += c1;
                 f2 += c2;
@@ -107,8 +102,8 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                     a2 += d2;
                 }
             } else {
-                pair_sigma_b_f32(y, h0, h1, h2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[7][m], shf[8][m],
-                                 shf[9][m], shf[10][m], shf[11][m], shf[12][m], fk1, fk2, c0, c1, c2);
+                pair_sigma_b_f32(y, h0, h1, h2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[4][m], shf[5][m],
+                                 shf[6][m], shf[7][m], shf[8][m], shf[9][m], fk1, fk2, c0, c1, c2);
                 f0 += c0;
                 f1 += c1;
                 f2 += c2;

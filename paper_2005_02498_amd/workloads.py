@@ -93,7 +93,12 @@ def _loops(rng, n_loops, box, rmin, rmax, log_radius=False, nseg=SEGS_PER_LOOP):
         radii = rng.uniform(rmin, rmax, n_loops)
     centres = rng.uniform(0.0, box, (n_loops, 3))
     phi0 = rng.uniform(0.0, 2.0 * math.pi, n_loops)
+    return _loop_geometry(planes, dirs, signs, radii, centres, phi0, nseg)
 
+
+def _loop_geometry(planes, dirs, signs, radii, centres, phi0, nseg=SEGS_PER_LOOP):
+    """Nodes, connectivity, Burgers vectors and normals of the given loops."""
+    n_loops = len(planes)
     n_nodes = n_loops * nseg
     k = np.arange(nseg)
     nrm = PLANE_NORMALS[planes]                      # [n_loops][3]
@@ -214,14 +219,24 @@ def surrogate_state(seed) -> Instance:
 
 
 def burst_instance_state(state_seed, micro_seed, box=2000.0, kmin=8, kmax=128) -> Instance:
-    """Like ``burst_instance``, but the state (k loops, mobile fraction f,
-    applied stress) is drawn from ``state_seed`` and the microstructure (the
-    loops) from ``micro_seed``: several microstructures of one state."""
+    """A burst volume whose coarse state and fine microstructure come from two
+    seeds.  ``state_seed`` fixes the applied stress, the loop count k, the
+    mobile fraction and, per loop, its slip plane, Burgers direction and
+    radius: hence the per-system resolved shear stresses and mobile/sessile
+    line densities.  ``micro_seed`` draws what those leave free: loop centres,
+    first-vertex angles and Burgers-vector signs."""
     rng = np.random.default_rng(state_seed)
     k = int(rng.integers(kmin, kmax + 1))
     f = float(rng.uniform(0.1, 0.9))
     sig = rng.uniform(-100e6, 100e6, 6)
-    x, seg, bur, nor, meta = _loops(np.random.default_rng(micro_seed), k, box, 100.0, 500.0)
+    planes = rng.integers(0, 4, k)
+    dirs = rng.integers(0, 3, k)
+    radii = rng.uniform(100.0, 500.0, k)
+    mrng = np.random.default_rng(micro_seed)
+    signs = mrng.integers(0, 2, k) * 2 - 1
+    centres = mrng.uniform(0.0, box, (k, 3))
+    phi0 = mrng.uniform(0.0, 2.0 * math.pi, k)
+    x, seg, bur, nor, meta = _loop_geometry(planes, dirs, signs, radii, centres, phi0)
     n_mob = int(round(f * k))
     pinned = np.zeros(x.shape[1], np.uint8)
     pinned[n_mob * SEGS_PER_LOOP:] = 1

@@ -243,3 +243,19 @@ def test_large_volume_mixed_vs_fp64_ten_steps():
     print(f"large volume mixed vs fp64: force err step0 {errs[0]:.2e} step10 {errs[1]:.2e}, "
           f"displacement err {disp:.2e}")
     assert max(errs) < TOLMIX and disp < TOLMIX
+
+
+def test_autotuner_on_off_same_forces():
+    """The autotuned work split changes only the order of partial sums."""
+    inst = W.subset(W.config1(), 100)
+    prev = dd.dd_set_autotune(False)
+    try:
+        a = _gpu_forces(inst, 2)
+        am = _gpu_forces(inst, 2, dd.DD_MIXED)
+    finally:
+        dd.dd_set_autotune(prev)
+    dd.dd_set_autotune(True)
+    b = _gpu_forces(inst, 2)
+    bm = _gpu_forces(inst, 2, dd.DD_MIXED)
+    assert normwise(a, b) < 1e-13
+    assert normwise(am, bm) < 1e-6
