@@ -39,13 +39,13 @@ UNIT = "segment-pair evals/s"
 # Algorithmic FLOPs per (target Gauss point, source segment) evaluation,
 # counted on the closed form as written in csrc/dd_pair.h (add, sub, mul = 1,
 # fma = 2, sqrt / rsqrt / reciprocal = 1; selects and compares = 0).
-FLOP_F64_EVAL = 169          # FP64 path
+FLOP_F64_EVAL = 159          # FP64 path
 FLOP_MIX_PREP_F64 = 14       # mixed: FP64 offset, axial, perpendicular parts (every pair)
 FLOP_MIX_BAND_F32 = 13       # mixed: |rho|^2 and distance-to-midpoint band test (every pair)
 FLOP_MIX_QUAD_F32 = 145      # mixed: FP32 2-point source quadrature (well-separated pairs)
 FLOP_MIX_CLASS_F32 = 3       # mixed: minimum-distance test (other pairs)
-FLOP_MIX_FAR_F32 = 179       # mixed: FP32 cancellation-free closed form
-FLOP_MIX_NEAR_F64 = 169      # mixed: FP64 closed form (near pairs)
+FLOP_MIX_FAR_F32 = 169       # mixed: FP32 cancellation-free closed form
+FLOP_MIX_NEAR_F64 = 159      # mixed: FP64 closed form (near pairs)
 PEAK_F64 = 78.6e12
 PEAK_F32 = 157.3e12
 HBM_PEAK = 8.0e12
@@ -185,22 +185,35 @@ def surrogate_study(args):
     model = dd.SurrogateModel(4, 12345)
     model.set_log_densities(dens_scale, dens_floor)
     model.set_scaling(in_shift, in_scale, out_shift, out_scale)
-    Xd = torch.tensor(Xtr, dtype=torch.float32, device=dev)
-    Yd = torch.tensor(Ytr, dtype=torch.float32, device=dev)
+    # 10 % of the training bursts are a validation split for early stopping
     rng = np.random.default_rng(0)
+    order = rng.permutation(len(Xtr))
+    n_val = len(Xtr) // 10
+    val, trn = order[:n_val], order[n_val:]
+    Xd = torch.tensor(Xtr[trn], dtype=torch.float32, device=dev)
+    Yd = torch.tensor(Ytr[trn], dtype=torch.float32, device=dev)
+    Xv = torch.tensor(Xtr[val], dtype=torch.float32, device=dev)
+    Yv = Ytr[val]
     nb = 1024
-    steps_per_epoch = max(1, len(Xtr) // nb)
+    steps_per_epoch = max(1, len(trn) // nb)
     t0 = time.perf_counter()
-    losses = []
+    losses, best, best_ep, best_params = [], float("inf"), -1, None
     for ep in range(args.study_epochs):
         lr = 1e-3 if ep < 0.6 * args.study_epochs else (3e-4 if ep < 0.85 * args.study_epochs else 1e-4)
-        perm = torch.tensor(rng.permutation(len(Xtr)), device=dev)
+        perm = torch.tensor(rng.permutation(len(trn)), device=dev)
         for k in range(steps_per_epoch):
             idx = perm[k * nb:(k + 1) * nb]
             loss = dd.dd_mlp_train_step(model, Xd[idx].contiguous(), Yd[idx].contiguous(), lr)
-        losses.append(loss.cpu().numpy().tolist())
-        if ep % 10 == 0 or ep == args.study_epochs - 1:
-            log(f"epoch {ep}: loss per member {np.round(losses[-1], 4).tolist()}")
+        if ep % 5 == 4 or ep == args.study_epochs - 1:
+            losses.append(loss.cpu().numpy().tolist())
+            pv, _, _ = dd.dd_surrogate_rates(model, Xv, 0.05)
+            vloss = float(np.mean(((pv.cpu().numpy() - Yv) / out_scale) ** 2))
+            if vloss < best:
+                best, best_ep = vloss, ep
+                best_params = [model.get_params(m) for m in range(4)]
+            log(f"epoch {ep}: train loss {np.round(losses[-1], 4).tolist()}, validation {vloss:.4f}")
+    for m in range(4):
+        model.set_params(m, best_params[m])
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
 
@@ -249,7 +262,8 @@ def surrogate_study(args):
            "training_states": int(len(Xtr)), "heldout_states": S, "microstructures_per_state": M,
            "burst": "200 glide steps, mixed precision, 2 Gauss points, one graph launch per 512",
            "mean_burst_seconds": t_burst, "data_generation_seconds": sec, "training_seconds": t_train,
-           "epochs": args.study_epochs, "final_losses": losses[-1],
+           "epochs": args.study_epochs, "best_epoch": best_ep, "validation_loss": best,
+           "final_losses": losses[-1],
            "inference_seconds_per_call": t_inf_call, "inference_points_per_call": n_inf,
            "inference_tflops": 1.20e12 * n_inf / (1 << 20) / t_inf_call / 1e12,
            "error_single_burst": E1, "error_reference_noise": float(np.sqrt(ref2)),

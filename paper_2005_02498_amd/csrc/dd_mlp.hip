@@ -265,14 +265,18 @@ __global__ void k_gather_grads(GradPtrs G, int members, float *__restrict__ out)
     out[i] = grad_at(G, (int)(i / P), i % P);
 }
 
+// Adam with (1 - beta1), (1 - beta2) and the bias corrections 1 - beta^t all
+// formed in double on the host and rounded once, so that the first step is
+// exactly the normalised gradient.
 __global__ void k_adam(GradPtrs G, int members, float *__restrict__ w, float *__restrict__ m1,
-                       float *__restrict__ m2, float lr, float b1, float b2, float eps, float c1, float c2)
+                       float *__restrict__ m2, float lr, float b1, float b2, float omb1, float omb2, float eps,
+                       float c1, float c2)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= members * P) return;
     const float g = grad_at(G, (int)(i / P), i % P);
-    const float a = b1 * m1[i] + (1.f - b1) * g;
-    const float v = b2 * m2[i] + (1.f - b2) * g * g;
+    const float a = b1 * m1[i] + omb1 * g;
+    const float v = b2 * m2[i] + omb2 * g * g;
     m1[i] = a;
     m2[i] = v;
     w[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
@@ -853,12 +857,13 @@ extern "C" int dd_mlp_train_step(dd_mlp *h, int64_t n, const float *feat, const 
     hipStream_t st = (hipStream_t)stream;
     if ((rc = gradients(h, n, feat, target, loss_out, st))) return rc;
     h->t += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = (float)(1.0 - std::pow(0.9, (double)h->t));
-    const float c2 = (float)(1.0 - std::pow(0.999, (double)h->t));
+    const double B1 = 0.9, B2 = 0.999;
+    const float c1 = (float)(1.0 - std::pow(B1, (double)h->t));
+    const float c2 = (float)(1.0 - std::pow(B2, (double)h->t));
     const int64_t tot = h->members * P;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, grad_ptrs(h), h->members,
-                       h->w, h->m1, h->m2, lr, b1, b2, 1e-8f, c1, c2);
+                       h->w, h->m1, h->m2, lr, (float)B1, (float)B2, (float)(1.0 - B1), (float)(1.0 - B2), 1e-8f,
+                       c1, c2);
     return refresh(h, st);
 }
 

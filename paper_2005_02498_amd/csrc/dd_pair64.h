@@ -78,19 +78,20 @@ __device__ __forceinline__ void pair_sigma_b_f64c(
     const double rb0 = h1 * b2 - h2 * b1, rb1 = h2 * b0 - h0 * b2, rb2 = h0 * b1 - h1 * b0;
     const double A = -k1 * g0, Cc = k2 * I31 - k1 * g1, qk = q * k2;
     const double Tt = 1.5 * qk * I52, Tr = -3.0 * qk * I51;
-    const double w0 = A * rb0 + Cc * c0 + Tt * t0 + Tr * h0;
-    const double w1 = A * rb1 + Cc * c1 + Tt * t1 + Tr * h1;
-    const double w2 = A * rb2 + Cc * c2 + Tt * t2 + Tr * h2;
     const double Zc = -k2 * I30, Zr = 1.5 * qk * I50;
-    const double z0 = Zc * c0 + Zr * h0, z1 = Zc * c1 + Zr * h1, z2 = Zc * c2 + Zr * h2;
     const double kd = qk * (I30 + 3.0 * I50);
-    const double wb = w0 * bj0 + w1 * bj1 + w2 * bj2;
+    // sigma b_j = t (w.b_j) + w (t.b_j) + rho (z.b_j) + z (rho.b_j) + kd b_j, with w and z
+    // expanded: coefficients of the five vectors rho x b, c, t, rho and b_j
     const double tb = t0 * bj0 + t1 * bj1 + t2 * bj2;
-    const double zb = z0 * bj0 + z1 * bj1 + z2 * bj2;
     const double hb = h0 * bj0 + h1 * bj1 + h2 * bj2;
-    o0 = t0 * wb + w0 * tb + h0 * zb + z0 * hb + kd * bj0;
-    o1 = t1 * wb + w1 * tb + h1 * zb + z1 * hb + kd * bj1;
-    o2 = t2 * wb + w2 * tb + h2 * zb + z2 * hb + kd * bj2;
+    const double cb = c0 * bj0 + c1 * bj1 + c2 * bj2;
+    const double rbb = rb0 * bj0 + rb1 * bj1 + rb2 * bj2;
+    const double wb = A * rbb + Cc * cb + Tt * tb + Tr * hb;
+    const double zb = Zc * cb + Zr * hb;
+    const double Pr = A * tb, Pc = Cc * tb + Zc * hb, Pt = wb + Tt * tb, Ph = Tr * tb + zb + Zr * hb;
+    o0 = Pr * rb0 + Pc * c0 + Pt * t0 + Ph * h0 + kd * bj0;
+    o1 = Pr * rb1 + Pc * c1 + Pt * t1 + Ph * h1 + kd * bj1;
+    o2 = Pr * rb2 + Pc * c2 + Pt * t2 + Ph * h2 + kd * bj2;
 }
 
 // Unchained form (isolated pairs, e.g. the near-field branch of the mixed path).
