@@ -40,7 +40,9 @@ UNIT = "segment-pair evals/s"
 # counted on the closed form as written in csrc/dd_pair.h (add, sub, mul = 1,
 # fma = 2, sqrt / rsqrt / reciprocal = 1; selects and compares = 0).
 FLOP_F64_EVAL = 159          # FP64 path
-FLOP_MIX_PREP_F64 = 14       # mixed: FP64 offset, axial, perpendicular parts (every pair)
+FLOP_MIX_PREP_F64 = 14       # mixed: FP64 offset, axial, perpendicular parts (every pair; with
+                             # the FP32-first variant, quadrature pairs take an FP32 location of
+                             # the same count instead)
 FLOP_MIX_BAND_F32 = 13       # mixed: |rho|^2 and distance-to-midpoint band test (every pair)
 FLOP_MIX_QUAD_F32 = 145      # mixed: FP32 2-point source quadrature (well-separated pairs)
 FLOP_MIX_CLASS_F32 = 3       # mixed: minimum-distance test (other pairs)
@@ -355,19 +357,21 @@ def main():
         dd.dd_timing_enable(False)
         kms, launches, near, quad = dd.dd_timing_read(reset=True)
         assert launches == steps, (launches, steps)
-        return (t1 - t0) / steps, kms / 1e3 / launches, (near / launches, quad / launches)
+        chunk, items, variant = dd.dd_last_plan()
+        return (t1 - t0) / steps, kms / 1e3 / launches, (near / launches, quad / launches, variant, chunk, items)
 
     def roof(prec, Q, kernel_s, bands):
         if prec == dd.DD_FP64:
             f64 = FLOP_F64_EVAL * pairs * Q
             f32 = 0.0
         else:
-            near, quad = bands
+            near, quad, variant = bands[:3]
             allp = N * N * Q                 # including the (skipped) self pairs
             other = allp - quad              # pairs that take the minimum-distance test
             closed = pairs * Q - quad - near
-            f64 = FLOP_MIX_PREP_F64 * allp + FLOP_MIX_NEAR_F64 * near
-            f32 = (FLOP_MIX_BAND_F32 * allp + FLOP_MIX_QUAD_F32 * quad
+            loc64 = other if variant else allp   # FP32-first: quadrature pairs located in FP32
+            f64 = FLOP_MIX_PREP_F64 * loc64 + FLOP_MIX_NEAR_F64 * near
+            f32 = (FLOP_MIX_PREP_F64 * (allp - loc64) + FLOP_MIX_BAND_F32 * allp + FLOP_MIX_QUAD_F32 * quad
                    + FLOP_MIX_CLASS_F32 * other + FLOP_MIX_FAR_F32 * closed)
         flops = f64 + f32
         t_roof = f64 / PEAK_F64 + f32 / PEAK_F32
@@ -416,6 +420,8 @@ def main():
                             "ms_per_step": s * 1e3, "kernel_ms": k * 1e3,
                             "near_fp64_evals_per_launch": bands[0],
                             "quad_fp32_evals_per_launch": bands[1],
+                            "plan": {"chunk_len": bands[3], "work_items": bands[4],
+                                     "mixed_fp32_first": bool(bands[2])},
                             "roofline": {kk: r[kk] for kk in ("bound", "achieved", "peak", "unit", "frac")}}
         out["extras"] = extras
 

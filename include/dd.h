@@ -112,6 +112,12 @@ int dd_shutdown(void);
  * setting. */
 int dd_set_autotune(int on);
 
+/* The work split of the most recent force evaluation on this device: the
+ * source-range length of a work item, the number of work items, and the
+ * mixed kernel's variant (1: pairs located in FP32 first, 0: in FP64).  Any
+ * pointer may be null. */
+int dd_last_plan(int64_t *chunk_len, int64_t *n_items, int *variant);
+
 /* Measurement hooks (for benchmarks and profilers).  With timing on, every
  * launch of the all-pairs kernel made outside graph capture is bracketed by a
  * HIP event pair recorded on the caller's stream.  dd_timing_read waits for

@@ -24,7 +24,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
-    "dd_timing_enable", "dd_timing_read", "dd_set_autotune",
+    "dd_timing_enable", "dd_timing_read", "dd_set_autotune", "dd_last_plan",
     "dd_nodal_forces", "dd_glide_step", "dd_burst_batch",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -68,6 +68,7 @@ def _declare(L):
         "dd_shutdown": (C.c_int, []),
         "dd_timing_enable": (C.c_int, [C.c_int]),
         "dd_set_autotune": (C.c_int, [C.c_int]),
+        "dd_last_plan": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
         "dd_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]),
         "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
@@ -160,6 +161,13 @@ def dd_last_error() -> str:
 
 def dd_set_autotune(on: bool) -> bool:
     return bool(lib().dd_set_autotune(1 if on else 0))
+
+
+def dd_last_plan():
+    """(source-range length, work items, mixed-kernel variant) of the last force evaluation."""
+    c, n, v = C.c_int64(), C.c_int64(), C.c_int()
+    _check(lib().dd_last_plan(C.byref(c), C.byref(n), C.byref(v)))
+    return c.value, n.value, v.value
 
 
 def dd_timing_enable(on: bool) -> bool:

@@ -115,6 +115,6 @@ void launch_pair64(const Item *items, const Tile *tiles, const double *rec, int6
                    double k1, double k2, double *partial, int64_t n_items, hipStream_t st);
 void launch_pair_mixed(const Item *items, const Tile *tiles, const double *rec, const float *rec32, int64_t ns,
                        const GaussRule &g, double k1, double k2, float cut, double *partial,
-                       unsigned long long *counters, int64_t n_items, hipStream_t st);
+                       unsigned long long *counters, int64_t n_items, int variant, hipStream_t st);
 
 }  // namespace dd

@@ -635,6 +635,7 @@ struct ForceCtx {
     GaussRule g{};
     double k1 = 0, k2 = 0, inv_a = 0, inv_mu = 0, fscale = 0, a = 0;
     int precision = DD_FP64;
+    int variant = 0;   // mixed kernel: 1 = FP32 location first
     float cut = 0.f;
 };
 
@@ -652,6 +653,7 @@ PlanKey g_plan_key;   // guarded by the single-caller-per-device rule
 int g_plan_dev = -1;
 int64_t g_plan_items = 0;
 int64_t g_plan_chunk = 0;
+int g_last_variant = 0;
 
 int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, int64_t nn,
           const int32_t *seg_nodes, const dd_material *m, int n_gauss, int precision,
@@ -761,7 +763,7 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
             timing_begin(st, ws->capturing);
             if (C.precision == DD_MIXED)
                 launch_pair_mixed(C.items, C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut, C.partial,
-                                  ws->near_count, C.n_items, st);
+                                  ws->near_count, C.n_items, C.variant, st);
             else
                 launch_pair64(C.items, C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial, C.n_items, st);
             timing_end(st, ws->capturing);
@@ -777,7 +779,9 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
 // ------------------------------------------------------------- autotuner --
 // The source-range length of a work item (how many sources one workgroup
 // streams through LDS for its 256 target points) sets the number of items,
-// the partial-sum traffic and the load balance between uneven instances.  On
+// the partial-sum traffic and the load balance between uneven instances; the
+// mixed kernel also has two orders of locating a pair (FP32 first or FP64
+// first) whose relative cost depends on how sparse the volume is.  On
 // the first call for a given (GPU architecture, Gauss points, precision,
 // instance count, total and largest instance size, in powers of two) the
 // candidates below are timed with HIP events on one all-pairs pass over the
@@ -830,7 +834,8 @@ void save_tune(const TuneKey &k, int64_t c)
     std::fclose(fp);
 }
 
-// Returns the chunk length to use (0 = the built-in heuristic).
+// Returns 2 * (chunk length to use, 0 = the built-in heuristic) + the mixed
+// kernel's variant.
 int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, int64_t nn,
                 const Layout &inst, const int32_t *seg_nodes, const double *x, const double *burgers,
                 const double *normal, const dd_material *m, int Q, int prec, double cut, bool need_sys,
@@ -856,18 +861,24 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
         *out = itk->second;
         return DD_OK;
     }
-    std::vector<int64_t> cands = {0};
-    for (int64_t c = TILE; c < nmax; c *= 2) cands.push_back(c);
-    cands.push_back(((nmax + TILE - 1) / TILE) * TILE);   // one range per tile
+    // a choice is encoded as 2 * chunk_length + mixed-kernel variant
+    std::vector<int64_t> chunks = {0};
+    for (int64_t c = TILE; c < nmax; c *= 2) chunks.push_back(c);
+    chunks.push_back(((nmax + TILE - 1) / TILE) * TILE);   // one range per tile
+    std::vector<int64_t> cands;
+    for (int64_t c : chunks)
+        for (int v = 0; v < (prec == DD_MIXED ? 2 : 1); ++v) cands.push_back(2 * c + v);
     hipEvent_t e0, e1;
     DD_HIP(hipEventCreate(&e0));
     DD_HIP(hipEventCreate(&e1));
     double best = 1e300;
     int64_t best_c = 0;
     int rc = DD_OK;
-    for (int64_t c : cands) {
+    for (int64_t cv : cands) {
+        const int64_t c = cv / 2;
         ForceCtx C;
         if ((rc = setup(ws, st, so, nn, seg_nodes, m, Q, prec, cut, c, need_sys, C))) break;
+        C.variant = (int)(cv % 2);
         PrepArgs A{};
         A.L = C.L;
         A.L.seg_inst = inst.seg_inst;
@@ -887,7 +898,7 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
             (void)hipEventRecord(e0, st);
             if (prec == DD_MIXED)
                 launch_pair_mixed(C.items, C.tiles, C.rec64, C.rec32, ns, C.g, C.k1, C.k2, C.cut, C.partial,
-                                  ws->near_count, C.n_items, st);
+                                  ws->near_count, C.n_items, C.variant, st);
             else
                 launch_pair64(C.items, C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial, C.n_items, st);
             (void)hipEventRecord(e1, st);
@@ -902,7 +913,7 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
         if (rc) break;
         if (t_min < best) {
             best = t_min;
-            best_c = c;
+            best_c = cv;
         }
     }
     (void)hipEventDestroy(e0);
@@ -933,6 +944,14 @@ using namespace dd;
 
 extern "C" int dd_set_autotune(int on) { return dd::g_autotune.exchange(on ? 1 : 0); }
 
+extern "C" int dd_last_plan(int64_t *chunk_len, int64_t *n_items, int *variant)
+{
+    if (chunk_len) *chunk_len = g_plan_chunk;
+    if (n_items) *n_items = g_plan_items;
+    if (variant) *variant = g_last_variant;
+    return DD_OK;
+}
+
 extern "C" int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
                                const int32_t *seg_nodes, const double *burgers,
                                const double *normal, const double *sigma_app,
@@ -954,13 +973,15 @@ extern "C" int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
     if ((rc = workspace(&ws))) return rc;
     ForceCtx C;
     std::vector<int64_t> so = {0, n_segs};
-    int64_t chunk = 0;
+    int64_t choice = 0;
     Layout flat{};
     if ((rc = tuned_chunk(ws, st, so, n_nodes, flat, seg_nodes, x, burgers, normal, m, n_gauss, precision,
-                          near_cutoff_a, false, &chunk)))
+                          near_cutoff_a, false, &choice)))
         return rc;
-    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, chunk, false, C)))
+    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / 2, false, C)))
         return rc;
+    C.variant = (int)(choice % 2);
+    g_last_variant = C.variant;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
     launch_csr(C, seg_nodes, st);
     Sig6 sv;
@@ -1085,11 +1106,14 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
     inst.node_off = d_offs;
     inst.seg_off = d_offs + (n_inst + 1);
     ForceCtx C;
-    int64_t chunk = 0;
+    int64_t choice = 0;
     if ((rc = tuned_chunk(ws, st, so, nn, inst, seg_nodes, x, burgers, normal, m, n_gauss, precision,
-                          near_cutoff_a, true, &chunk)))
+                          near_cutoff_a, true, &choice)))
         return rc;
-    if ((rc = setup(ws, st, so, nn, seg_nodes, m, n_gauss, precision, near_cutoff_a, chunk, true, C))) return rc;
+    if ((rc = setup(ws, st, so, nn, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / 2, true, C)))
+        return rc;
+    C.variant = (int)(choice % 2);
+    g_last_variant = C.variant;
     C.L.seg_inst = inst.seg_inst;
     C.L.node_off = inst.node_off;
     C.L.seg_off = inst.seg_off;

@@ -15,6 +15,7 @@ namespace dd {
 // from the Gauss point to the closed source segment) are evaluated in FP64,
 // the rest by the cancellation-free FP32 closed form.  FP32 contributions
 // are accumulated in FP32 over one LDS stage, then added to FP64 sums.
+template <bool FP32_FIRST>
 __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ items,
                                                      const Tile *__restrict__ tiles,
                                                      const double *__restrict__ rec,
@@ -42,6 +43,7 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
     const double xq0 = rec[0 * ns + j] + sq * L * rec[3 * ns + j];
     const double xq1 = rec[1 * ns + j] + sq * L * rec[4 * ns + j];
     const double xq2 = rec[2 * ns + j] + sq * L * rec[5 * ns + j];
+    const float xf0 = (float)xq0, xf1 = (float)xq1, xf2 = (float)xq2;
     const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
     const float fb0 = (float)bj0, fb1 = (float)bj1, fb2 = (float)bj2;
     const float fk1 = (float)k1, fk2 = (float)k2, cut2 = cut * cut;
@@ -67,19 +69,33 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
         for (int m = 0; m < n; ++m) {
             const int64_t i = base + m;
             const float t0 = shf[0][m], t1 = shf[1][m], t2 = shf[2][m], Ls = shf[3][m];
-            // offset, axial and perpendicular parts in FP64, rounded once
-            const double T0 = shx[3][m], T1 = shx[4][m], T2 = shx[5][m];
-            const double R0 = xq0 - shx[0][m], R1 = xq1 - shx[1][m], R2 = xq2 - shx[2][m];
-            const double yd = R0 * T0 + R1 * T1 + R2 * T2;
-            const float y = (float)yd;
-            const float h0 = (float)(R0 - yd * T0), h1 = (float)(R1 - yd * T1), h2 = (float)(R2 - yd * T2);
-            const float hh = h0 * h0 + h1 * h1 + h2 * h2;
-            const float ym = y - 0.5f * Ls;
             const float GB = fmaxf(GAUSS_BAND * Ls, cut + 0.5f * Ls);
-            float c0, c1, c2;
-            // the quadrature branch is taken only when every lane of the
-            // wavefront qualifies, so no wavefront runs both branches
-            if (__all(hh + ym * ym >= GB * GB)) {
+            const double T0 = shx[3][m], T1 = shx[4][m], T2 = shx[5][m];
+            float y, h0, h1, h2, hh, c0, c1, c2;
+            bool quad;
+            if (FP32_FIRST) {
+                // FP32 location from FP32 positions: enough for the quadrature
+                // branch (no cancellation there, ~1e-6 relative at worst)
+                const float e0 = xf0 - (float)shx[0][m], e1 = xf1 - (float)shx[1][m], e2 = xf2 - (float)shx[2][m];
+                y = e0 * t0 + e1 * t1 + e2 * t2;
+                h0 = e0 - y * t0; h1 = e1 - y * t1; h2 = e2 - y * t2;
+                hh = h0 * h0 + h1 * h1 + h2 * h2;
+                const float ym = y - 0.5f * Ls;
+                quad = __all(hh + ym * ym >= GB * GB);
+            }
+            if (!FP32_FIRST || !quad) {
+                // offset, axial and perpendicular parts in FP64, rounded once
+                const double R0 = xq0 - shx[0][m], R1 = xq1 - shx[1][m], R2 = xq2 - shx[2][m];
+                const double yd = R0 * T0 + R1 * T1 + R2 * T2;
+                y = (float)yd;
+                h0 = (float)(R0 - yd * T0); h1 = (float)(R1 - yd * T1); h2 = (float)(R2 - yd * T2);
+                hh = h0 * h0 + h1 * h1 + h2 * h2;
+                if (!FP32_FIRST) {
+                    const float ym = y - 0.5f * Ls;
+                    quad = __all(hh + ym * ym >= GB * GB);
+                }
+            }
+            if (quad) {
                 n_quad += valid ? 1u : 0u;
                 pair_sigma_b_f32_gauss2(y, h0, h1, h2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[4][m], shf[5][m],
                                         shf[6][m], shf[7][m], shf[8][m], shf[9][m], fk1, fk2, c0, c1, c2);
@@ -128,10 +144,14 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
 
 void launch_pair_mixed(const Item *items, const Tile *tiles, const double *rec, const float *rec32, int64_t ns,
                        const GaussRule &g, double k1, double k2, float cut, double *partial,
-                       unsigned long long *counters, int64_t n_items, hipStream_t st)
+                       unsigned long long *counters, int64_t n_items, int variant, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pair_mixed, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, rec32, ns, g,
-                       k1, k2, cut, partial, counters);
+    if (variant)
+        hipLaunchKernelGGL(k_pair_mixed<true>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, rec32,
+                           ns, g, k1, k2, cut, partial, counters);
+    else
+        hipLaunchKernelGGL(k_pair_mixed<false>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, rec32,
+                           ns, g, k1, k2, cut, partial, counters);
 }
 
 }  // namespace dd
