@@ -18,8 +18,10 @@ Printed as one JSON line, with
   was taken on the current kernel source;
 * cpu_baseline: the FP64 C oracle, single-threaded, on a bounded sample of the
   same workload (the first --cpu-targets target segments against all sources);
-* extras: the mixed FP32/FP64 path and 4 Gauss points on the same volume, and
-  512 batched bursts (200 glide steps each) in one graph launch.
+* extras: the mixed FP32/FP64 path and 4 Gauss points on the same volume, one
+  step of the 262,144-segment volume in both precisions, 100 graph-captured
+  steps of the 256-segment volume, 512 batched bursts (200 glide steps each)
+  in one graph launch, surrogate inference and training.
 """
 from __future__ import annotations
 
@@ -37,17 +39,18 @@ METRIC = "segment-pair force evals/s (FP64 vs mixed) + surrogate speedup at fixe
 UNIT = "segment-pair evals/s"
 
 # Algorithmic FLOPs per (target Gauss point, source segment) evaluation,
-# counted on the closed form as written in csrc/dd_pair.h (add, sub, mul = 1,
-# fma = 2, sqrt / rsqrt / reciprocal = 1; selects and compares = 0).
-FLOP_F64_EVAL = 159          # FP64 path
-FLOP_MIX_PREP_F64 = 14       # mixed: FP64 offset, axial, perpendicular parts (every pair; with
-                             # the FP32-first variant, quadrature pairs take an FP32 location of
-                             # the same count instead)
-FLOP_MIX_BAND_F32 = 13       # mixed: |rho|^2 and distance-to-midpoint band test (every pair)
-FLOP_MIX_QUAD_F32 = 145      # mixed: FP32 2-point source quadrature (well-separated pairs)
-FLOP_MIX_CLASS_F32 = 3       # mixed: minimum-distance test (other pairs)
-FLOP_MIX_FAR_F32 = 169       # mixed: FP32 cancellation-free closed form
-FLOP_MIX_NEAR_F64 = 159      # mixed: FP64 closed form (near pairs)
+# counted on the formulas as written in csrc/dd_pair64.h and csrc/dd_pair32.h
+# (add, sub, mul = 1, fma = 2, sqrt / rsqrt / reciprocal = 1 including their
+# refinement steps; selects, compares and sign changes = 0).
+FLOP_F64_EVAL = 133          # FP64 path (pair_acc_f64)
+FLOP_MIX_BAND_F32 = 14       # mixed: offset to the source midpoint and its square (every
+                             # pair, variant 0)
+FLOP_MIX_QUAD_F32 = 132      # mixed: FP32 2-point source quadrature (quad2_acc_f32)
+FLOP_MIX_LOC_F64 = 14        # mixed: FP64 offset, axial and perpendicular parts (pairs
+                             # that are not evaluated by quadrature)
+FLOP_MIX_CLASS_F32 = 8       # mixed: minimum-distance test (the same pairs)
+FLOP_MIX_FAR_F32 = 164       # mixed: FP32 cancellation-free closed form (pair_sigma_b_f32)
+FLOP_MIX_NEAR_F64 = 145      # mixed: FP64 closed form of an isolated pair (near field)
 PEAK_F64 = 78.6e12
 PEAK_F32 = 157.3e12
 HBM_PEAK = 8.0e12
@@ -329,19 +332,22 @@ def main():
     inst = W.config1()
     N = inst.n_segs
     pairs = N * (N - 1)
-    x0 = torch.tensor(inst.x, device=dev)
-    sn = torch.tensor(inst.seg_nodes, device=dev)
-    bg = torch.tensor(inst.burgers, device=dev)
-    nr = torch.tensor(inst.normal, device=dev)
-    F = torch.empty((3, inst.n_nodes), dtype=torch.float64, device=dev)
-    V = torch.empty_like(F)
     dd.dd_set_validation(False)
 
-    def run(prec, Q, steps, warmup):
-        x = x0.clone()
+    def resident(v):
+        return {"x": torch.tensor(v.x, device=dev), "sn": torch.tensor(v.seg_nodes, device=dev),
+                "b": torch.tensor(v.burgers, device=dev), "n": torch.tensor(v.normal, device=dev),
+                "F": torch.empty((3, v.n_nodes), dtype=torch.float64, device=dev),
+                "V": torch.empty((3, v.n_nodes), dtype=torch.float64, device=dev), "sig": v.sigma_app}
+
+    vol = resident(inst)
+
+    def run(prec, Q, steps, warmup, v=None):
+        v = vol if v is None else v
+        x, sn, bg, nr, F, V = v["x"].clone(), v["sn"], v["b"], v["n"], v["F"], v["V"]
 
         def step():
-            dd.dd_nodal_forces(x, sn, bg, nr, inst.sigma_app, mat, Q, prec, 20.0, force_out=F)
+            dd.dd_nodal_forces(x, sn, bg, nr, v["sig"], mat, Q, prec, 20.0, force_out=F)
             dd.dd_glide_step(x, F, sn, nr, None, mat, W.DT, vel_out=V)
 
         for _ in range(warmup):
@@ -360,6 +366,10 @@ def main():
         chunk, items, variant = dd.dd_last_plan()
         return (t1 - t0) / steps, kms / 1e3 / launches, (near / launches, quad / launches, variant, chunk, items)
 
+    # measured FMA rates: FP64 with a scalar-register operand (the FP64 kernel's
+    # form), FP32 with vector-register operands (the FP32 quadrature's form)
+    peaks_measured = {k: dd.dd_vector_peak(k, 20) * 1e12 for k in ("fp64", "fp32", "fp64_vec", "fp32_vec")}
+
     def roof(prec, Q, kernel_s, bands):
         if prec == dd.DD_FP64:
             f64 = FLOP_F64_EVAL * pairs * Q
@@ -367,19 +377,21 @@ def main():
         else:
             near, quad, variant = bands[:3]
             allp = N * N * Q                 # including the (skipped) self pairs
-            other = allp - quad              # pairs that take the minimum-distance test
+            other = allp - quad              # pairs located in FP64
             closed = pairs * Q - quad - near
-            loc64 = other if variant else allp   # FP32-first: quadrature pairs located in FP32
-            f64 = FLOP_MIX_PREP_F64 * loc64 + FLOP_MIX_NEAR_F64 * near
-            f32 = (FLOP_MIX_PREP_F64 * (allp - loc64) + FLOP_MIX_BAND_F32 * allp + FLOP_MIX_QUAD_F32 * quad
-                   + FLOP_MIX_CLASS_F32 * other + FLOP_MIX_FAR_F32 * closed)
+            band = allp if variant == 0 else 0
+            f64 = FLOP_MIX_LOC_F64 * other + FLOP_MIX_NEAR_F64 * near
+            f32 = (FLOP_MIX_BAND_F32 * band + FLOP_MIX_QUAD_F32 * quad + FLOP_MIX_CLASS_F32 * other
+                   + FLOP_MIX_FAR_F32 * closed)
         flops = f64 + f32
         t_roof = f64 / PEAK_F64 + f32 / PEAK_F32
+        t_meas = f64 / peaks_measured["fp64"] + f32 / peaks_measured["fp32_vec"]
         peak = flops / t_roof
         ach = flops / kernel_s
         return {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                 "frac": ach / peak, "flop_per_launch": flops, "fp64_flop": f64, "fp32_flop": f32,
-                "kernel_ms": kernel_s * 1e3}
+                "kernel_ms": kernel_s * 1e3, "peak_measured": flops / t_meas / 1e12,
+                "frac_of_measured": ach / (flops / t_meas)}
 
     if args.only in ("fp64", "mixed"):
         prec = dd.DD_FP64 if args.only == "fp64" else dd.DD_MIXED
@@ -389,13 +401,18 @@ def main():
 
     out = {}
     if args.only != "burst":
-        step_s, ker_s, _ = run(dd.DD_FP64, 2, args.steps, args.warmup)
+        step_s, ker_s, bands64 = run(dd.DD_FP64, 2, args.steps, args.warmup)
+        plan64 = bands64[3:5]
         r = roof(dd.DD_FP64, 2, ker_s, None)
         tb = traffic_bytes()
         rl = {"bound": "alu", "achieved": r["achieved"], "peak": r["peak"], "unit": "TFLOP/s",
               "frac": r["frac"], "traffic": tb, "kernel": "k_pair64",
               "kernel_ms": r["kernel_ms"], "flop_per_launch": r["flop_per_launch"],
-              "flop_per_eval": FLOP_F64_EVAL}
+              "flop_per_eval": FLOP_F64_EVAL, "peak_measured": r["peak_measured"],
+              "frac_of_measured": r["frac_of_measured"],
+              "peak_measured_note": "dd_vector_peak: FP64 multiply-add chains with a scalar-register "
+                                    "operand on every CU",
+              "plan": {"chunk_len": plan64[0], "work_items": plan64[1]}}
         out = {
             "metric": METRIC, "value": pairs / step_s, "unit": UNIT, "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3,
@@ -408,6 +425,7 @@ def main():
             "gauss_evals_per_s": 2 * pairs / step_s,
             "kernel_pairs_per_s": pairs / ker_s,
             "roofline": rl,
+            "vector_peaks_measured_tflops": {k: v / 1e12 for k, v in peaks_measured.items()},
         }
 
     if not args.no_extras and args.only is None:
@@ -421,8 +439,41 @@ def main():
                             "near_fp64_evals_per_launch": bands[0],
                             "quad_fp32_evals_per_launch": bands[1],
                             "plan": {"chunk_len": bands[3], "work_items": bands[4],
-                                     "mixed_fp32_first": bool(bands[2])},
-                            "roofline": {kk: r[kk] for kk in ("bound", "achieved", "peak", "unit", "frac")}}
+                                     "mixed_quadrature_test": bands[2] == 0},
+                            "roofline": {kk: r[kk] for kk in ("bound", "achieved", "peak", "unit", "frac",
+                                                              "peak_measured", "frac_of_measured")}}
+        # the 262,144-segment volume (radii 50-2000 b, 50,000 b cube): one step per precision
+        big = W.config3()
+        vb = resident(big)
+        bp = big.n_segs * (big.n_segs - 1)
+        for name, prec in (("large_volume_fp64_q2", dd.DD_FP64), ("large_volume_mixed_q2", dd.DD_MIXED)):
+            s, k, bands = run(prec, 2, 2, 1, vb)
+            extras[name] = {"segments": big.n_segs, "pairs_per_s": bp / s, "ms_per_step": s * 1e3,
+                            "kernel_ms": k * 1e3, "near_fp64_evals_per_launch": bands[0],
+                            "quad_fp32_evals_per_launch": bands[1],
+                            "plan": {"chunk_len": bands[3], "work_items": bands[4],
+                                     "mixed_quadrature_test": bands[2] == 0}}
+        del vb
+        # the 256-segment volume: 100 FP64 glide steps captured in one graph launch
+        sb = W.pack([W.config0()])
+        ds = dict(x=torch.tensor(sb.x, device=dev), sn=torch.tensor(sb.seg_nodes, device=dev),
+                  b=torch.tensor(sb.burgers, device=dev), n=torch.tensor(sb.normal, device=dev),
+                  p=torch.tensor(sb.pinned, device=dev), s=torch.tensor(sb.sigma_app, device=dev),
+                  v=torch.tensor(sb.volume, device=dev))
+        dd.dd_burst_batch(sb.node_off, sb.seg_off, ds["x"].clone(), ds["sn"], ds["b"], ds["n"], ds["p"],
+                          ds["s"], ds["v"], mat, 2, dd.DD_FP64, 20.0, 100, W.DT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            dd.dd_burst_batch(sb.node_off, sb.seg_off, ds["x"].clone(), ds["sn"], ds["b"], ds["n"],
+                              ds["p"], ds["s"], ds["v"], mat, 2, dd.DD_FP64, 20.0, 100, W.DT)
+        torch.cuda.synchronize()
+        t_small = (time.perf_counter() - t0) / reps
+        extras["small_volume_100_steps_fp64"] = {
+            "segments": 256, "steps": 100, "seconds_per_call": t_small,
+            "us_per_step": t_small / 100 * 1e6,
+            "note": "one call = upload, graph capture of the 100 steps, one launch, synchronise"}
         out["extras"] = extras
 
     if (not args.no_extras and args.only is None) or args.only == "burst":

@@ -104,8 +104,10 @@ int dd_shutdown(void);
  * on, the first dd_nodal_forces / dd_burst_batch call for a new problem
  * class (GPU architecture, Gauss points, precision, and the instance count,
  * total and largest instance size rounded up to powers of two) times the
- * candidate source-range lengths of a work item on one all-pairs pass over
- * its own inputs (synchronising the stream) and keeps the fastest for the
+ * candidate source-range lengths of a work item (and, for the mixed path,
+ * both variants of its kernel) on one all-pairs pass over its own inputs plus
+ * the reduction of that pass's partial sums (synchronising the stream), and
+ * keeps the fastest for the
  * process; with the environment variable DD_AUTOTUNE_CACHE naming a file,
  * choices are also read from and appended to it.  Results do not depend on
  * the choice beyond the order of floating-point sums.  Returns the previous
@@ -114,8 +116,9 @@ int dd_set_autotune(int on);
 
 /* The work split of the most recent force evaluation on this device: the
  * source-range length of a work item, the number of work items, and the
- * mixed kernel's variant (1: pairs located in FP32 first, 0: in FP64).  Any
- * pointer may be null. */
+ * mixed kernel's variant (0: each source first tested in FP32 for the
+ * well-separated band evaluated by 2-point quadrature, 1: no such test, every
+ * pair located in FP64).  Any pointer may be null. */
 int dd_last_plan(int64_t *chunk_len, int64_t *n_items, int *variant);
 
 /* Measurement hooks (for benchmarks and profilers).  With timing on, every
@@ -132,6 +135,20 @@ int dd_last_plan(int64_t *chunk_len, int64_t *n_items, int *variant);
 int dd_timing_enable(int on);
 int dd_timing_read(double *kernel_ms, int64_t *launches, int64_t *near_evals,
                    int64_t *quad_evals, int reset);
+
+/* Measured vector-ALU peak of the current device, a reference point for the
+ * all-pairs kernels' roofline beside the published peaks.  kind selects the
+ * fused multiply-add form: 0 = FP64 and 1 = FP32 with one operand the same
+ * for every lane (read from a scalar register), 2 = FP64 and 3 = FP32 with
+ * every operand per lane (vector registers); FP32 is the unpacked form the
+ * library is built with (packed FP32 instructions are disabled).  Runs three
+ * warm-up and then `reps` (1..1000) launches of a kernel that keeps 8
+ * independent multiply-add chains per lane on 4096 workgroups of 256 lanes,
+ * times them with HIP events on `stream` (hipStream_t, may be null), waits,
+ * and writes the rate in TFLOP/s (a multiply-add counts 2) to *tflops.
+ * Uses a 4 MiB workspace buffer.  DD_EINVAL for a null pointer or a bad
+ * kind or reps. */
+int dd_vector_peak(int kind, int reps, double *tflops, void *stream);
 
 /* Nodal forces (internal + applied) on every node.
  *  For every segment j and Gauss-Legendre point q of an n_gauss-point rule

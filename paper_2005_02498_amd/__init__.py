@@ -24,7 +24,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
-    "dd_timing_enable", "dd_timing_read", "dd_set_autotune", "dd_last_plan",
+    "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_last_plan",
     "dd_nodal_forces", "dd_glide_step", "dd_burst_batch",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -71,6 +71,7 @@ def _declare(L):
         "dd_last_plan": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
         "dd_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]),
+        "dd_vector_peak": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), vp]),
         "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
                                       C.POINTER(Material), C.c_int, C.c_int, dbl, vp, vp]),
         "dd_glide_step": (C.c_int, [i64, vp, vp, i64, vp, vp, vp, C.POINTER(Material), dbl,
@@ -181,6 +182,16 @@ def dd_timing_read(reset=True):
     _check(lib().dd_timing_read(C.byref(ms), C.byref(n), C.byref(near), C.byref(quad),
                                 1 if reset else 0))
     return ms.value, n.value, near.value, quad.value
+
+
+def dd_vector_peak(kind: str = "fp64", reps: int = 20, stream=None) -> float:
+    """Measured FMA throughput in TFLOP/s.  kind: "fp64" / "fp32" (one operand
+    from a scalar register), "fp64_vec" / "fp32_vec" (all operands per lane);
+    FP32 is unpacked."""
+    k = {"fp64": 0, "fp32": 1, "fp64_vec": 2, "fp32_vec": 3}[kind]
+    t = C.c_double()
+    _check(lib().dd_vector_peak(k, int(reps), C.byref(t), _stream(stream)))
+    return t.value
 
 
 # -------------------------------------------------------------- force path --

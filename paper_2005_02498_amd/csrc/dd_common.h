@@ -51,6 +51,7 @@ enum Slot {
     WS_RATE,           // running slip-rate sums
     WS_INST_OFFS,      // instance node and segment offsets
     WS_MISC,
+    WS_PROBE,          // output of the vector-peak probe
     WS_NSLOTS
 };
 
@@ -102,11 +103,27 @@ struct GaussRule {
     int n;
 };
 
-// FP64 segment record, structure of arrays with stride n_segs:
-//  0..2 x1/a, 3..5 t, 6 L/a, 7..9 b/a, 10..12 c = (b/a) x t, 13 unused.
+// FP64 segment records, structure of arrays with stride n_segs:
+//  0..2 x1/a, 3..5 t, 6 L/a, 7..9 b/a, 10..12 c = (b/a) x t, 13 length of the
+//  run of segments that each start where the one before ends (as a double);
+// followed in the same buffer by one RECA-double record per segment (array of
+// structures, read with wavefront-uniform scalar loads by the FP64 kernel):
+//  0..12 as above, 13 the run length as int64 bits, 14..15 zero.
 constexpr int REC64 = 14;
-// FP32 segment record: 0..2 t, 3 L/a, 4..6 b/a, 7..9 c.
-constexpr int REC32 = 10;
+constexpr int RECA = 16;
+constexpr int REC64_TOTAL = REC64 + RECA;   // doubles per segment in the buffer
+// Bytes of the FP64 record buffer for ns segments.
+inline size_t rec64_bytes(int64_t ns)
+{
+    return sizeof(double) * (size_t)REC64_TOTAL * (size_t)(ns > 1 ? ns : 1);
+}
+// FP32 segment record of the mixed path, REC32A floats per segment (array of
+// structures, read with wavefront-uniform scalar loads):
+//  0..2 midpoint xm/a rounded to FP32, 3..5 the rounding remainder xm/a - [0..2],
+//  6..8 t, 9 L/a, 10 hoff = L/(2 sqrt 3), 11..13 b/a, 14..16 c, 17 the squared
+//  quadrature band max(30 L, cutoff + L/2)^2, 18 L/2, 19 1 + hoff^2,
+//  20 2 hoff, 21..23 zero.
+constexpr int REC32A = 24;
 
 GaussRule gauss_rule(int n);
 

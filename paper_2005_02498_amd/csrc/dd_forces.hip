@@ -127,8 +127,9 @@ struct PrepArgs {
     const double *burgers;
     const double *normal;
     double inv_a;
-    double *rec64;        // [REC64][ns]
-    float *rec32;         // [REC32][ns] or null
+    double *rec64;        // [REC64][ns], then [ns][RECA]
+    float *rec32;         // [ns][REC32A] or null
+    float cut;            // near-field cutoff in units of a (FP32 record)
     int32_t *sys;         // [ns] slip system or -1, or null
     unsigned *flags;
 };
@@ -181,12 +182,35 @@ __global__ void k_seg_prep(PrepArgs A)
         }
     }
     r[13 * ns + s] = (double)run;
+    {
+        double *ra = r + (int64_t)REC64 * ns + s * RECA;
+        ra[0] = x1[0]; ra[1] = x1[1]; ra[2] = x1[2];
+        ra[3] = t[0];  ra[4] = t[1];  ra[5] = t[2];
+        ra[6] = L;
+        ra[7] = b[0];  ra[8] = b[1];  ra[9] = b[2];
+        ra[10] = c[0]; ra[11] = c[1]; ra[12] = c[2];
+        ra[13] = __longlong_as_double((long long)run);
+        ra[14] = 0.0;  ra[15] = 0.0;
+    }
     if (A.rec32) {
-        float *q = A.rec32;
-        q[0 * ns + s] = (float)t[0]; q[1 * ns + s] = (float)t[1]; q[2 * ns + s] = (float)t[2];
-        q[3 * ns + s] = (float)L;
-        q[4 * ns + s] = (float)b[0]; q[5 * ns + s] = (float)b[1]; q[6 * ns + s] = (float)b[2];
-        q[7 * ns + s] = (float)c[0]; q[8 * ns + s] = (float)c[1]; q[9 * ns + s] = (float)c[2];
+        float *q = A.rec32 + s * REC32A;
+        for (int k = 0; k < 3; ++k) {
+            const double xm = x1[k] + 0.5 * L * t[k];
+            q[k] = (float)xm;
+            q[3 + k] = (float)(xm - (double)q[k]);
+            q[6 + k] = (float)t[k];
+            q[11 + k] = (float)b[k];
+            q[14 + k] = (float)c[k];
+        }
+        const double hoff = L * 0.28867513459481288225;   // L / (2 sqrt 3)
+        const double band = fmax(30.0 * L, (double)A.cut + 0.5 * L);
+        q[9] = (float)L;
+        q[10] = (float)hoff;
+        q[17] = (float)(band * band);
+        q[18] = (float)(0.5 * L);
+        q[19] = (float)(1.0 + hoff * hoff);
+        q[20] = (float)(2.0 * hoff);
+        q[21] = 0.f; q[22] = 0.f; q[23] = 0.f;
     }
     if (A.sys) {
         int found = -1;
@@ -214,29 +238,45 @@ __global__ void k_csr_count(Layout L, const int32_t *seg_nodes, int32_t *cnt)
     atomicAdd(&cnt[g2], 1);
 }
 
-// Exclusive scan of cnt[0..n) into ptr[0..n] by one workgroup of 1024 threads.
+// Exclusive scan of cnt[0..n) into ptr[0..n] by one workgroup of 1024
+// threads, 4096 counts per round: each thread takes 4 consecutive counts,
+// wavefront prefix sums by shuffles, the 16 wavefront totals through LDS, and
+// a running carry from round to round.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *cnt, int64_t n, int32_t *ptr)
 {
-    __shared__ int32_t part[1024];
-    const int T = 1024, tid = threadIdx.x;
-    int64_t per = (n + T - 1) / T;
-    int64_t b = tid * per, e = min(n, b + per);
-    int32_t sum = 0;
-    for (int64_t i = b; i < e; ++i) sum += cnt[i];
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < T; off <<= 1) {
-        int32_t v = tid >= off ? part[tid - off] : 0;
+    __shared__ int32_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int32_t carry = 0;
+    for (int64_t base = 0; base < n; base += 4096) {
+        const int64_t i0 = base + 4 * (int64_t)tid;
+        int32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = (i0 + k < n) ? cnt[i0 + k] : 0;
+        const int32_t t = v[0] + v[1] + v[2] + v[3];
+        int32_t s = t;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t u = __shfl_up(s, off, 64);
+            if (lane >= off) s += u;
+        }
+        if (lane == 63) wsum[w] = s;
         __syncthreads();
-        part[tid] += v;
+        int32_t before = carry, total = carry;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            before += k < w ? wsum[k] : 0;
+            total += wsum[k];
+        }
+        int32_t run = before + s - t;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < n) ptr[i0 + k] = run;
+            run += v[k];
+        }
+        carry = total;
         __syncthreads();
     }
-    int32_t run = tid ? part[tid - 1] : 0;
-    for (int64_t i = b; i < e; ++i) {
-        ptr[i] = run;
-        run += cnt[i];
-    }
-    if (tid == T - 1) ptr[n] = part[T - 1];
+    if (tid == 0) ptr[n] = carry;
 }
 
 __global__ void k_csr_fill(Layout L, const int32_t *seg_nodes, const int32_t *ptr,
@@ -247,7 +287,8 @@ __global__ void k_csr_fill(Layout L, const int32_t *seg_nodes, const int32_t *pt
     int64_t g[2];
     if (!seg_ends(L, seg_nodes, s, g[0], g[1])) return;
     for (int e = 0; e < 2; ++e) {
-        int32_t k = atomicAdd(&cursor[g[e]], 1);
+        // counts down from the node's count: slots ptr .. ptr + count - 1
+        const int32_t k = atomicSub(&cursor[g[e]], 1) - 1;
         list[ptr[g[e]] + k] = (int32_t)(2 * s + e);
     }
 }
@@ -635,7 +676,7 @@ struct ForceCtx {
     GaussRule g{};
     double k1 = 0, k2 = 0, inv_a = 0, inv_mu = 0, fscale = 0, a = 0;
     int precision = DD_FP64;
-    int variant = 0;   // mixed kernel: 1 = FP32 location first
+    int variant = 0;   // mixed kernel: 0 = FP32 quadrature band test first, 1 = no quadrature
     float cut = 0.f;
 };
 
@@ -674,10 +715,10 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
     C.L.ns = ns;
     void *p;
     int rc;
-    if ((rc = ensure(ws, WS_SEG64, sizeof(double) * REC64 * std::max<int64_t>(ns, 1), &p))) return rc;
+    if ((rc = ensure(ws, WS_SEG64, rec64_bytes(ns), &p))) return rc;
     C.rec64 = (double *)p;
     if (precision == DD_MIXED) {
-        if ((rc = ensure(ws, WS_SEG32, sizeof(float) * REC32 * std::max<int64_t>(ns, 1), &p))) return rc;
+        if ((rc = ensure(ws, WS_SEG32, sizeof(float) * REC32A * std::max<int64_t>(ns, 1), &p))) return rc;
         C.rec32 = (float *)p;
     }
     if (need_sys) {
@@ -733,7 +774,6 @@ void launch_csr(const ForceCtx &C, const int32_t *seg_nodes, hipStream_t st)
     hipLaunchKernelGGL(k_csr_count, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L, seg_nodes,
                        C.csr_cnt);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, C.csr_cnt, nn, C.csr_ptr);
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nn)), dim3(256), 0, st, (unsigned *)C.csr_cnt, nn, 0u);
     hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L, seg_nodes,
                        C.csr_ptr, C.csr_cnt, C.csr_list);
     hipLaunchKernelGGL(k_csr_sort, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, st, C.csr_ptr, nn,
@@ -756,6 +796,7 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         A.inv_a = C.inv_a;
         A.rec64 = C.rec64;
         A.rec32 = C.rec32;
+        A.cut = C.cut;
         A.sys = C.sys;
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
@@ -891,6 +932,7 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
         A.inv_a = C.inv_a;
         A.rec64 = C.rec64;
         A.rec32 = C.rec32;
+        A.cut = C.cut;
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
         double t_min = 1e300;
@@ -901,6 +943,11 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
                                   ws->near_count, C.n_items, C.variant, st);
             else
                 launch_pair64(C.items, C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial, C.n_items, st);
+            // the reduction of the partial sums grows with the number of work
+            // items, so it is part of the cost being compared
+            hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A.L,
+                               C.tiles, C.partial, C.rec64, C.g, (const double *)nullptr, Sig6{}, C.inv_mu,
+                               C.fscale, C.segF);
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) {
                 rc = set_error(DD_EHIP, "autotuner timing failed");
@@ -1032,7 +1079,7 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
     launch_csr(C, seg_nodes, st);
     if (validation_on() && n_segs > 0) {
         // index and normal checks (the prep kernel also computes lengths)
-        if ((rc = ensure(ws, WS_SEG64, sizeof(double) * REC64 * n_segs, &p))) return rc;
+        if ((rc = ensure(ws, WS_SEG64, rec64_bytes(n_segs), &p))) return rc;
         PrepArgs A{};
         A.L = L;
         A.x = x;
@@ -1140,6 +1187,7 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
         A.inv_a = C.inv_a;
         A.rec64 = C.rec64;
         A.rec32 = C.rec32;
+        A.cut = C.cut;
         A.sys = C.sys;
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);

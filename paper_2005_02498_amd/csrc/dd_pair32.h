@@ -68,55 +68,65 @@ __device__ __forceinline__ void pair_sigma_b_f32(
 
 // FP32, well-separated pairs (target at least GAUSS_BAND source lengths from
 // the source midpoint): 2-point Gauss-Legendre quadrature of the integrand
-// along the source instead of the closed form.  With R = rho + v t at the
-// source points (v = y - s_g, s_g = L (1/2 -+ 1/(2 sqrt 3)), weight L/2),
-// R x b = rho x b - v c and q = c.R = c.rho, the integrand contracted with b_j,
+// along the source instead of the closed form.  Source points xm -+ hoff t
+// (hoff = L / (2 sqrt 3), weight W = L/2 each); with e = x - xm, ym = e.t,
+// rho = e - ym t, the axial coordinates of the target relative to the two
+// points are v = ym +- hoff and Ra^2 = |e|^2 + 1 + hoff^2 +- 2 hoff ym.  With
+// R = rho + v t, R x b = rho x b - v c and q = c.rho, the integrand
+// contracted with b_j (divided by k2, kr = k1/k2 = (1 - nu)/2) is
 //   K b_j = al [ (R x b)(t.b_j) + t ((R x b).b_j) ] + be b_j
 //         + ga [ R (c.b_j) + c (R.b_j) ] + de R (R.b_j),
-//   al = -k1 (2/Ra^3 + 3/Ra^5), be = k2 q (1/Ra^3 + 3/Ra^5),
-//   ga = -k2/Ra^3, de = 3 k2 q / Ra^5,   Ra^2 = d2 + v^2,
-// is summed over the two points as coefficients of the five vectors
-// rho x b, c, t, b_j, rho.  Quadrature error below 2e-7 relative at that
-// separation.
+//   al = -kr (2/Ra^3 + 3/Ra^5), be = q (1/Ra^3 + 3/Ra^5),
+//   ga = -1/Ra^3, de = 3 q / Ra^5.
+// Summed over the two points it depends on them only through
+//   S3 = sum W/Ra^3, S5 = sum W/Ra^5, S3v = sum W v/Ra^3, S5v = sum W v/Ra^5,
+//   S5vv = sum W v^2/Ra^5,
+// and collects as coefficients of rho x b, c, t, b_j and rho:
+//   rho x b : (t.b_j) Sal                       Sal = -kr (2 S3 + 3 S5)
+//   c       : (rho.b_j) Sga + (t.b_j) Sgv       Sga = -S3, Sgv = -nu S3v + 3 kr S5v
+//   t       : ((rho x b).b_j) Sal + (c.b_j) Sgv + 3 q ((rho.b_j) S5v + (t.b_j) S5vv)
+//   b_j     : q (S3 + 3 S5)
+//   rho     : (c.b_j) Sga + 3 q ((rho.b_j) S5 + (t.b_j) S5v)
+// The quadrature error is below 2e-7 relative at that separation.
 constexpr float GAUSS_BAND = 30.0f;
 
-__device__ __forceinline__ void pair_sigma_b_f32_gauss2(
-    float y, float h0, float h1, float h2, float bj0, float bj1, float bj2,
-    float t0, float t1, float t2, float L, float b0, float b1, float b2,
-    float c0, float c1, float c2, float k1, float k2, float &o0, float &o1, float &o2)
+// e = target - source midpoint; s = the source's FP32 record (see REC32A);
+// adds K b_j / k2 to (f0, f1, f2).
+__device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, float ee, const float *s,
+                                              float bj0, float bj1, float bj2, float kr, float nu,
+                                              float &f0, float &f1, float &f2)
 {
-    const float d2 = h0 * h0 + h1 * h1 + h2 * h2 + 1.0f;
-    const float rb0 = h1 * b2 - h2 * b1, rb1 = h2 * b0 - h0 * b2, rb2 = h0 * b1 - h1 * b0;
-    const float tb = t0 * bj0 + t1 * bj1 + t2 * bj2;
-    const float cb = c0 * bj0 + c1 * bj1 + c2 * bj2;
-    const float hb = h0 * bj0 + h1 * bj1 + h2 * bj2;
-    const float rbb = rb0 * bj0 + rb1 * bj1 + rb2 * bj2;
-    const float q = c0 * h0 + c1 * h1 + c2 * h2;
-    const float W = 0.5f * L;
-    const float cA = -W * k1, cB = W * k2 * q, cG = -W * k2, cD = 3.0f * cB;
-    const float hoff = 0.28867513459481288225f * L;   // L / (2 sqrt 3)
-    const float vm = y - 0.5f * L;
-    float P1 = 0.f, Pc = 0.f, Pt = 0.f, Pb = 0.f, Ph = 0.f;
-#pragma unroll
-    for (int g = 0; g < 2; ++g) {
-        const float v = g ? vm - hoff : vm + hoff;
-        const float ir = __builtin_amdgcn_rsqf(d2 + v * v);
-        const float ir2 = ir * ir, ir3 = ir * ir2, ir5 = ir3 * ir2;
-        const float s1 = ir3 + 3.0f * ir5;
-        const float al = cA * (s1 + ir3), be = cB * s1, ga = cG * ir3, de = cD * ir5;
-        const float Rbj = hb + v * tb;
-        const float Rbb = rbb - v * cb;
-        const float p1 = al * tb;
-        const float Dg = ga * cb + de * Rbj;
-        P1 += p1;
-        Pc += ga * Rbj - p1 * v;
-        Pt += al * Rbb + Dg * v;
-        Pb += be;
-        Ph += Dg;
-    }
-    o0 = P1 * rb0 + Pc * c0 + Pt * t0 + Pb * bj0 + Ph * h0;
-    o1 = P1 * rb1 + Pc * c1 + Pt * t1 + Pb * bj1 + Ph * h1;
-    o2 = P1 * rb2 + Pc * c2 + Pt * t2 + Pb * bj2 + Ph * h2;
+    const float t0 = s[6], t1 = s[7], t2 = s[8], hoff = s[10], W = s[18];
+    const float b0 = s[11], b1 = s[12], b2 = s[13], c0 = s[14], c1 = s[15], c2 = s[16];
+    const float ym = fmaf(e2, t2, fmaf(e1, t1, e0 * t0));
+    const float h0 = fmaf(-ym, t0, e0), h1 = fmaf(-ym, t1, e1), h2 = fmaf(-ym, t2, e2);
+    const float base = ee + s[19], tw = s[20] * ym;
+    const float vA = ym + hoff, vB = ym - hoff;
+    const float iA = __builtin_amdgcn_rsqf(base + tw), iB = __builtin_amdgcn_rsqf(base - tw);
+    const float iA2 = iA * iA, iB2 = iB * iB;
+    const float iA3 = iA2 * iA, iB3 = iB2 * iB;
+    const float iA5 = iA3 * iA2, iB5 = iB3 * iB2;
+    const float pA = iA5 * vA, pB = iB5 * vB;
+    const float S3 = W * (iA3 + iB3), S5 = W * (iA5 + iB5);
+    const float S3v = W * fmaf(iA3, vA, iB3 * vB), S5v = W * (pA + pB);
+    const float S5vv = W * fmaf(pA, vA, pB * vB);
+    const float rb0 = fmaf(h1, b2, -h2 * b1), rb1 = fmaf(h2, b0, -h0 * b2), rb2 = fmaf(h0, b1, -h1 * b0);
+    const float tb = fmaf(t2, bj2, fmaf(t1, bj1, t0 * bj0));
+    const float hb = fmaf(h2, bj2, fmaf(h1, bj1, h0 * bj0));
+    const float cb = fmaf(c2, bj2, fmaf(c1, bj1, c0 * bj0));
+    const float rbb = fmaf(rb2, bj2, fmaf(rb1, bj1, rb0 * bj0));
+    const float q = fmaf(c2, h2, fmaf(c1, h1, c0 * h0));
+    const float q3 = 3.0f * q;
+    const float Sal = -kr * fmaf(2.0f, S3, 3.0f * S5);
+    const float Sgv = fmaf(-nu, S3v, 3.0f * kr * S5v);
+    const float Cr = tb * Sal;
+    const float Cc = fmaf(tb, Sgv, -hb * S3);
+    const float Ct = fmaf(rbb, Sal, fmaf(cb, Sgv, q3 * fmaf(hb, S5v, tb * S5vv)));
+    const float Cb = q * fmaf(3.0f, S5, S3);
+    const float Ch = fmaf(-cb, S3, q3 * fmaf(hb, S5, tb * S5v));
+    f0 = fmaf(Cb, bj0, fmaf(Ch, h0, fmaf(Ct, t0, fmaf(Cc, c0, fmaf(Cr, rb0, f0)))));
+    f1 = fmaf(Cb, bj1, fmaf(Ch, h1, fmaf(Ct, t1, fmaf(Cc, c1, fmaf(Cr, rb1, f1)))));
+    f2 = fmaf(Cb, bj2, fmaf(Ch, h2, fmaf(Ct, t2, fmaf(Cc, c2, fmaf(Cr, rb2, f2)))));
 }
 
 }  // namespace dd

@@ -15,6 +15,15 @@
 // with c = b x t, q = c.rho, g0 = 2 I30 + 3 I50, g1 = 2 I31 + 3 I51,
 // k1 = 1/(8 pi), k2 = 1/(4 pi (1 - nu)); then
 //   sigma b_j = t (w.b_j) + w (t.b_j) + rho (z.b_j) + z (rho.b_j) + kd b_j.
+//
+// The device form divides by k2 (the caller scales the sum once): with
+// kr = k1/k2 = (1 - nu)/2 and k2 - 2 k1 = nu k2 the coefficients become
+//   w/k2  = -kr g0 (rho x b) + (nu I31 - kr D51) c + q (P/2 t - D51 rho)
+//   z/k2  = -I30 c + q E50/2 rho,       kd/k2 = q (I30 + E50)
+// in terms of D51 = 3 I51 = r1^3 - r2^3, P = 3 I52 and E50 = 3 I50, with
+// r = 1/Ra and s = u r at the two endpoints:
+//   I30 = (s2 - s1)/d2,  P = (s2^3 - s1^3)/d2,  E50 = (3 I30 - P)/d2,
+//   I31 = r1 - r2,       g0 = 2 I30 + E50.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,69 +50,70 @@ __device__ __forceinline__ double rcp64(double x)
     return fma(r, fma(e, e, e), r);
 }
 
-// FP64: endpoint differences taken directly,
-//   I30 = (s2 - s1)/d2, I31 = r1 - r2, I50 = ((3 s2 - s2^3) - (3 s1 - s1^3))/(3 d2^2),
-//   I51 = (r1^3 - r2^3)/3, I52 = (s2^3 - s1^3)/(3 d2), with r = 1/Ra, s = u r.
-// r at an endpoint depends only on the distance to that node, so when the
-// source starts at the node where the previous source (same target point)
-// ended, its r1 is the previous r2: `chained` (uniform across the wave) skips
-// that inverse square root; `rprev` carries r2 to the next call.
-__device__ __forceinline__ void pair_sigma_b_f64c(
+// Adds sigma^i b_j / k2 of source (p, t, L, b, c) at target point x to
+// (a0, a1, a2).  r1 and r1c = r1^3 belong to the source's first node and are
+// supplied by the caller; r2 and r2c are returned, so that a source starting
+// where this one ends (same target point) reuses them as its r1, r1c.
+// kr = (1 - nu)/2.
+__device__ __forceinline__ void pair_acc_f64(
     double x0, double x1, double x2, double bj0, double bj1, double bj2,
     double p0, double p1, double p2, double t0, double t1, double t2, double L,
     double b0, double b1, double b2, double c0, double c1, double c2,
-    double k1, double k2, bool chained, double &rprev, double &o0, double &o1, double &o2)
+    double kr, double nu, double r1, double r1c, double &r2, double &r2c,
+    double &a0, double &a1, double &a2)
 {
     const double R0 = x0 - p0, R1 = x1 - p1, R2 = x2 - p2;
-    const double y = R0 * t0 + R1 * t1 + R2 * t2;
-    const double h0 = R0 - y * t0, h1 = R1 - y * t1, h2 = R2 - y * t2;   // rho
-    const double d2 = h0 * h0 + h1 * h1 + h2 * h2 + 1.0;
+    const double y = fma(R2, t2, fma(R1, t1, R0 * t0));
+    const double h0 = fma(-y, t0, R0), h1 = fma(-y, t1, R1), h2 = fma(-y, t2, R2);   // rho
+    const double d2 = fma(h2, h2, fma(h1, h1, fma(h0, h0, 1.0)));
     const double u2 = L - y;
-    double r1;
-    if (chained) r1 = rprev;
-    else r1 = rsqrt64(d2 + y * y);
-    const double r2 = rsqrt64(d2 + u2 * u2);
-    rprev = r2;
+    r2 = rsqrt64(fma(u2, u2, d2));
+    r2c = r2 * r2 * r2;
     const double id2 = rcp64(d2);
     const double s1 = -y * r1, s2 = u2 * r2;
-    const double s1c = s1 * s1 * s1, s2c = s2 * s2 * s2;
-    const double I30 = (s2 - s1) * id2;
+    const double D1 = s2 - s1;
+    const double D3 = fma(s2 * s2, s2, -(s1 * s1) * s1);
+    const double I30 = D1 * id2;
+    const double P = D3 * id2;
+    const double E50 = fma(3.0, I30, -P) * id2;
     const double I31 = r1 - r2;
-    const double I50 = ((3.0 * s2 - s2c) - (3.0 * s1 - s1c)) * (id2 * id2) * (1.0 / 3.0);
-    const double I51 = (r1 * r1 * r1 - r2 * r2 * r2) * (1.0 / 3.0);
-    const double I52 = (s2c - s1c) * id2 * (1.0 / 3.0);
-    const double g0 = 2.0 * I30 + 3.0 * I50;
-    const double g1 = 2.0 * I31 + 3.0 * I51;
-    const double q = c0 * h0 + c1 * h1 + c2 * h2;
-    const double rb0 = h1 * b2 - h2 * b1, rb1 = h2 * b0 - h0 * b2, rb2 = h0 * b1 - h1 * b0;
-    const double A = -k1 * g0, Cc = k2 * I31 - k1 * g1, qk = q * k2;
-    const double Tt = 1.5 * qk * I52, Tr = -3.0 * qk * I51;
-    const double Zc = -k2 * I30, Zr = 1.5 * qk * I50;
-    const double kd = qk * (I30 + 3.0 * I50);
+    const double D51 = r1c - r2c;
+    const double g0 = fma(2.0, I30, E50);
+    const double q = fma(c2, h2, fma(c1, h1, c0 * h0));
+    const double A = -kr * g0;
+    const double Cc = fma(nu, I31, -kr * D51);
+    // twice the t coefficient of w/k2, its rho coefficient, twice the rho coefficient of z/k2
+    const double Tt2 = q * P, Tr = -q * D51, Zr2 = q * E50;
+    const double kd = q * (I30 + E50);
+    const double rb0 = fma(h1, b2, -h2 * b1), rb1 = fma(h2, b0, -h0 * b2), rb2 = fma(h0, b1, -h1 * b0);
     // sigma b_j = t (w.b_j) + w (t.b_j) + rho (z.b_j) + z (rho.b_j) + kd b_j, with w and z
     // expanded: coefficients of the five vectors rho x b, c, t, rho and b_j
-    const double tb = t0 * bj0 + t1 * bj1 + t2 * bj2;
-    const double hb = h0 * bj0 + h1 * bj1 + h2 * bj2;
-    const double cb = c0 * bj0 + c1 * bj1 + c2 * bj2;
-    const double rbb = rb0 * bj0 + rb1 * bj1 + rb2 * bj2;
-    const double wb = A * rbb + Cc * cb + Tt * tb + Tr * hb;
-    const double zb = Zc * cb + Zr * hb;
-    const double Pr = A * tb, Pc = Cc * tb + Zc * hb, Pt = wb + Tt * tb, Ph = Tr * tb + zb + Zr * hb;
-    o0 = Pr * rb0 + Pc * c0 + Pt * t0 + Ph * h0 + kd * bj0;
-    o1 = Pr * rb1 + Pc * c1 + Pt * t1 + Ph * h1 + kd * bj1;
-    o2 = Pr * rb2 + Pc * c2 + Pt * t2 + Ph * h2 + kd * bj2;
+    const double tb = fma(t2, bj2, fma(t1, bj1, t0 * bj0));
+    const double hb = fma(h2, bj2, fma(h1, bj1, h0 * bj0));
+    const double cb = fma(c2, bj2, fma(c1, bj1, c0 * bj0));
+    const double rbb = fma(rb2, bj2, fma(rb1, bj1, rb0 * bj0));
+    const double Pt = fma(Tt2, tb, fma(Tr, hb, fma(Cc, cb, A * rbb)));
+    const double Ph = fma(Tr, tb, fma(Zr2, hb, -I30 * cb));
+    const double Pc = fma(Cc, tb, -I30 * hb);
+    const double Pr = A * tb;
+    a0 = fma(kd, bj0, fma(Ph, h0, fma(Pt, t0, fma(Pc, c0, fma(Pr, rb0, a0)))));
+    a1 = fma(kd, bj1, fma(Ph, h1, fma(Pt, t1, fma(Pc, c1, fma(Pr, rb1, a1)))));
+    a2 = fma(kd, bj2, fma(Ph, h2, fma(Pt, t2, fma(Pc, c2, fma(Pr, rb2, a2)))));
 }
 
-// Unchained form (isolated pairs, e.g. the near-field branch of the mixed path).
-__device__ __forceinline__ void pair_sigma_b_f64(
-    double x0, double x1, double x2, double bj0, double bj1, double bj2,
-    double p0, double p1, double p2, double t0, double t1, double t2, double L,
-    double b0, double b1, double b2, double c0, double c1, double c2,
-    double k1, double k2, double &o0, double &o1, double &o2)
+// One isolated pair (the near-field branch of the mixed path): adds
+// sigma^i b_j / k2 of the source whose FP64 record is d (x1, t, L, b, c in
+// entries 0..12) to (a0, a1, a2).
+__device__ __forceinline__ void pair_acc_isolated_f64(double x0, double x1, double x2, double bj0,
+                                                      double bj1, double bj2, const double *d,
+                                                      double kr, double nu, double &a0, double &a1,
+                                                      double &a2)
 {
-    double r = 0.0;
-    pair_sigma_b_f64c(x0, x1, x2, bj0, bj1, bj2, p0, p1, p2, t0, t1, t2, L, b0, b1, b2, c0, c1,
-                      c2, k1, k2, false, r, o0, o1, o2);
+    const double R0 = x0 - d[0], R1 = x1 - d[1], R2 = x2 - d[2];
+    const double r1 = rsqrt64(fma(R2, R2, fma(R1, R1, fma(R0, R0, 1.0))));
+    double r2, r2c;
+    pair_acc_f64(x0, x1, x2, bj0, bj1, bj2, d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], d[8],
+                 d[9], d[10], d[11], d[12], kr, nu, r1, r1 * r1 * r1, r2, r2c, a0, a1, a2);
 }
 
 }  // namespace dd

@@ -5,28 +5,36 @@
 
 namespace dd {
 
-// Mixed precision.  Each pair is first located in FP32 from FP32 positions:
-// when, for every target point of the wavefront, the source midpoint lies at
-// least max(30 L, cutoff + L/2) away, the source is evaluated by FP32 2-point
-// quadrature (the
-// integrand is evaluated directly, so FP32 position rounding costs at most
-// ~1e-6 relative there).  Other pairs get their offset, axial and
-// perpendicular parts in FP64: those closer than the cutoff (minimum distance
-// from the Gauss point to the closed source segment) are evaluated in FP64,
-// the rest by the cancellation-free FP32 closed form.  FP32 contributions
-// are accumulated in FP32 over one LDS stage, then added to FP64 sums.
-template <bool FP32_FIRST>
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Mixed precision.  As in the FP64 kernel, every lane of a wavefront works on
+// the same source at the same time.  FP64 records are read with scalar loads;
+// the FP32 records are staged through LDS TILE sources at a time with QUAD
+// (the quadrature's FP32 instructions issue faster with every operand in a
+// vector register) and read with scalar loads without it.
+// With QUAD, each source is first located in FP32 relative to its midpoint
+// (positions split into FP32 high and low parts, so the offset carries no
+// rounding of the absolute coordinates): when, for every target point of the
+// wavefront, the midpoint lies at least max(30 L, cutoff + L/2) away, the
+// source is evaluated by FP32 2-point quadrature.  Other pairs get their
+// offset, axial and perpendicular parts in FP64: those closer than the cutoff
+// (minimum distance from the Gauss point to the closed source segment) are
+// evaluated in FP64, the rest by the cancellation-free FP32 closed form.  FP32
+// contributions are summed in FP32 over TILE sources at a time, then added to
+// FP64 sums; all sums are in units of k2 and scaled once at the end.
+template <bool QUAD>
 __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ items,
                                                      const Tile *__restrict__ tiles,
                                                      const double *__restrict__ rec,
-                                                     const float *__restrict__ rec32,
-                                                     int64_t ns, GaussRule g, double k1,
-                                                     double k2, float cut,
-                                                     double *__restrict__ partial,
+                                                     const double *__restrict__ ra,
+                                                     const float *__restrict__ rf, int64_t ns,
+                                                     GaussRule g, double kr, double nu, double k2,
+                                                     float cut, double *__restrict__ partial,
                                                      unsigned long long *near_count)
 {
-    __shared__ double shx[6][TILE];    // x1, t (FP64)
-    __shared__ float shf[10][TILE];    // t, L, b, c (FP32)
+    __shared__ f32x4 shr[QUAD ? TILE : 1][REC32A / 4];   // FP32 records of one stage of sources
     __shared__ unsigned n_near_block, n_quad_block;
     const Item it = items[blockIdx.x];
     const Tile tl = tiles[it.tile];
@@ -43,83 +51,87 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
     const double xq0 = rec[0 * ns + j] + sq * L * rec[3 * ns + j];
     const double xq1 = rec[1 * ns + j] + sq * L * rec[4 * ns + j];
     const double xq2 = rec[2 * ns + j] + sq * L * rec[5 * ns + j];
-    const float xf0 = (float)xq0, xf1 = (float)xq1, xf2 = (float)xq2;
+    const float xh0 = (float)xq0, xh1 = (float)xq1, xh2 = (float)xq2;
+    const float xl0 = (float)(xq0 - (double)xh0), xl1 = (float)(xq1 - (double)xh1),
+                xl2 = (float)(xq2 - (double)xh2);
     const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
     const float fb0 = (float)bj0, fb1 = (float)bj1, fb2 = (float)bj2;
-    const float fk1 = (float)k1, fk2 = (float)k2, cut2 = cut * cut;
+    const float fkr = (float)kr, fnu = (float)nu, cut2 = cut * cut;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    unsigned n_near = 0, n_quad = 0;
+    unsigned n_near = 0, n_quad_src = 0;
     if (lane == 0) {
         n_near_block = 0;
         n_quad_block = 0;
     }
+    __syncthreads();   // the counters are cleared before any wavefront adds to them
 
     for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
-        const int n = (int)min<int64_t>(TILE, it.src_end - base);
-        __syncthreads();
-        if (lane < n) {
-            const int64_t sidx = base + lane;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) shx[k][lane] = rec[k * ns + sidx];
-#pragma unroll
-            for (int k = 0; k < 10; ++k) shf[k][lane] = rec32[k * ns + sidx];
-        }
-        __syncthreads();
+        const int n = (int)min(it.src_end - base, (int64_t)TILE);
         float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-        for (int m = 0; m < n; ++m) {
-            const int64_t i = base + m;
-            const float t0 = shf[0][m], t1 = shf[1][m], t2 = shf[2][m], Ls = shf[3][m];
-            const float GB = fmaxf(GAUSS_BAND * Ls, cut + 0.5f * Ls);
-            const double T0 = shx[3][m], T1 = shx[4][m], T2 = shx[5][m];
-            float y, h0, h1, h2, hh, c0, c1, c2;
-            bool quad;
-            if (FP32_FIRST) {
-                // FP32 location from FP32 positions: enough for the quadrature
-                // branch (no cancellation there, ~1e-6 relative at worst)
-                const float e0 = xf0 - (float)shx[0][m], e1 = xf1 - (float)shx[1][m], e2 = xf2 - (float)shx[2][m];
-                y = e0 * t0 + e1 * t1 + e2 * t2;
-                h0 = e0 - y * t0; h1 = e1 - y * t1; h2 = e2 - y * t2;
-                hh = h0 * h0 + h1 * h1 + h2 * h2;
-                const float ym = y - 0.5f * Ls;
-                quad = __all(hh + ym * ym >= GB * GB);
+        if (QUAD) {
+            __syncthreads();
+            if (lane < n) {
+                const f32x4 *g4 = reinterpret_cast<const f32x4 *>(rf + (base + lane) * REC32A);
+#pragma unroll
+                for (int f = 0; f < REC32A / 4; ++f) shr[lane][f] = g4[f];
             }
-            if (!FP32_FIRST || !quad) {
-                // offset, axial and perpendicular parts in FP64, rounded once
-                const double R0 = xq0 - shx[0][m], R1 = xq1 - shx[1][m], R2 = xq2 - shx[2][m];
-                const double yd = R0 * T0 + R1 * T1 + R2 * T2;
-                y = (float)yd;
-                h0 = (float)(R0 - yd * T0); h1 = (float)(R1 - yd * T1); h2 = (float)(R2 - yd * T2);
-                hh = h0 * h0 + h1 * h1 + h2 * h2;
-                if (!FP32_FIRST) {
-                    const float ym = y - 0.5f * Ls;
-                    quad = __all(hh + ym * ym >= GB * GB);
-                }
-            }
-            if (quad) {
-                n_quad += valid ? 1u : 0u;
-                pair_sigma_b_f32_gauss2(y, h0, h1, h2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[4][m], shf[5][m],
-                                        shf[6][m], shf[7][m], shf[8][m], shf[9][m], fk1, fk2, c0, c1, c2);
-                f0 += c0;
-                f1 += c1;
-                f2 += c2;
-                continue;
-            }
-            const float ya = y - fminf(fmaxf(y, 0.f), Ls);
-            if (hh + ya * ya < cut2) {
-                if (i != j) {
-                    n_near += valid ? 1u : 0u;
-                    double d0, d1, d2;
-                    pair_sigma_b_f64(xq0, xq1, xq2, bj0, bj1, bj2, shx[0][m], shx[1][m], shx[2][m],
-                                     T0, T1, T2, rec[6 * ns + i], rec[7 * ns + i], rec[8 * ns + i],
-                                     rec[9 * ns + i], rec[10 * ns + i], rec[11 * ns + i],
-                                     rec[12 * ns + i], k1, k2, d0, d1, d2);
-                    a0 += d0;
-                    a1 += d1;
-                    a2 += d2;
+            __syncthreads();
+        }
+        const float *s = rf + base * REC32A;
+        for (int k = 0; k < n; ++k, s += REC32A) {
+            const int64_t m = base + k;
+            float r[REC32A];
+            if (QUAD) {
+                // from LDS (broadcast reads): the FP32 quadrature then runs on
+                // vector-register operands, which issue faster than FP32
+                // instructions with a scalar operand
+#pragma unroll
+                for (int f = 0; f < REC32A / 4; ++f) {
+                    const f32x4 v = shr[k][f];
+                    r[4 * f] = v[0];
+                    r[4 * f + 1] = v[1];
+                    r[4 * f + 2] = v[2];
+                    r[4 * f + 3] = v[3];
                 }
             } else {
-                pair_sigma_b_f32(y, h0, h1, h2, fb0, fb1, fb2, t0, t1, t2, Ls, shf[4][m], shf[5][m],
-                                 shf[6][m], shf[7][m], shf[8][m], shf[9][m], fk1, fk2, c0, c1, c2);
+                // straight from memory into scalar registers (two loads, one wait)
+                const f32x16 va = *reinterpret_cast<const f32x16 *>(s);
+                const f32x8 vb = *reinterpret_cast<const f32x8 *>(s + 16);
+#pragma unroll
+                for (int f = 0; f < 16; ++f) r[f] = va[f];
+#pragma unroll
+                for (int f = 0; f < 8; ++f) r[16 + f] = vb[f];
+            }
+            if (QUAD) {
+                const float e0 = (xh0 - r[0]) + (xl0 - r[3]);
+                const float e1 = (xh1 - r[1]) + (xl1 - r[4]);
+                const float e2 = (xh2 - r[2]) + (xl2 - r[5]);
+                const float ee = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
+                if (__all(ee >= r[17])) {
+                    ++n_quad_src;
+                    quad2_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2);
+                    continue;
+                }
+            }
+            // offset, axial and perpendicular parts in FP64, rounded once
+            const double *d = ra + m * RECA;
+            const double R0 = xq0 - d[0], R1 = xq1 - d[1], R2 = xq2 - d[2];
+            const double yd = fma(R2, d[5], fma(R1, d[4], R0 * d[3]));
+            const float y = (float)yd;
+            const float h0 = (float)fma(-yd, d[3], R0), h1 = (float)fma(-yd, d[4], R1),
+                        h2 = (float)fma(-yd, d[5], R2);
+            const float hh = fmaf(h2, h2, fmaf(h1, h1, h0 * h0));
+            const float Ls = r[9];
+            const float ya = y - fminf(fmaxf(y, 0.f), Ls);
+            if (hh + ya * ya < cut2) {
+                if (m != j) {
+                    n_near += valid ? 1u : 0u;
+                    pair_acc_isolated_f64(xq0, xq1, xq2, bj0, bj1, bj2, d, kr, nu, a0, a1, a2);
+                }
+            } else {
+                float c0, c1, c2;
+                pair_sigma_b_f32(y, h0, h1, h2, fb0, fb1, fb2, r[6], r[7], r[8], Ls, r[11], r[12], r[13],
+                                 r[14], r[15], r[16], fkr, 1.0f, c0, c1, c2);
                 f0 += c0;
                 f1 += c1;
                 f2 += c2;
@@ -131,10 +143,11 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
     }
     if (valid) {
         double *o = partial + it.slot * 3 * TILE;
-        o[lane] = a0;
-        o[TILE + lane] = a1;
-        o[2 * TILE + lane] = a2;
+        o[lane] = k2 * a0;
+        o[TILE + lane] = k2 * a1;
+        o[2 * TILE + lane] = k2 * a2;
     }
+    const unsigned n_quad = valid ? n_quad_src : 0u;
     if (n_near) atomicAdd(&n_near_block, n_near);
     if (n_quad) atomicAdd(&n_quad_block, n_quad);
     __syncthreads();
@@ -146,12 +159,14 @@ void launch_pair_mixed(const Item *items, const Tile *tiles, const double *rec, 
                        const GaussRule &g, double k1, double k2, float cut, double *partial,
                        unsigned long long *counters, int64_t n_items, int variant, hipStream_t st)
 {
-    if (variant)
-        hipLaunchKernelGGL(k_pair_mixed<true>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, rec32,
-                           ns, g, k1, k2, cut, partial, counters);
+    const double kr = k1 / k2, nu = 1.0 - 2.0 * kr;
+    const double *ra = rec + (int64_t)REC64 * ns;
+    if (variant == 0)
+        hipLaunchKernelGGL(k_pair_mixed<true>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, ra,
+                           rec32, ns, g, kr, nu, k2, cut, partial, counters);
     else
-        hipLaunchKernelGGL(k_pair_mixed<false>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, rec32,
-                           ns, g, k1, k2, cut, partial, counters);
+        hipLaunchKernelGGL(k_pair_mixed<false>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, ra,
+                           rec32, ns, g, kr, nu, k2, cut, partial, counters);
 }
 
 }  // namespace dd
