@@ -49,7 +49,7 @@ FLOP_MIX_QUAD_F32 = 132      # mixed: FP32 2-point source quadrature (quad2_acc_
 FLOP_MIX_LOC_F64 = 14        # mixed: FP64 offset, axial and perpendicular parts (pairs
                              # that are not evaluated by quadrature)
 FLOP_MIX_CLASS_F32 = 8       # mixed: minimum-distance test (the same pairs)
-FLOP_MIX_FAR_F32 = 164       # mixed: FP32 cancellation-free closed form (pair_sigma_b_f32)
+FLOP_MIX_FAR_F32 = 150       # mixed: FP32 cancellation-free closed form (pair_acc_f32)
 FLOP_MIX_NEAR_F64 = 145      # mixed: FP64 closed form of an isolated pair (near field)
 PEAK_F64 = 78.6e12
 PEAK_F32 = 157.3e12
@@ -544,7 +544,10 @@ def main():
         with open(SURROGATE_FILE) as f:
             sur = json.load(f)
         out["surrogate"] = {"speedup_at_fixed_error": sur["at_surrogate_error"]["speedup"],
+                            "speedup_without_fallback": sur["at_surrogate_error"]["speedup_without_fallback"],
                             "error": sur["at_surrogate_error"]["error"],
+                            "dd_bursts_for_same_error": sur["at_surrogate_error"]["dd_bursts_per_state"],
+                            "fallback_fraction_at_5_percent_spread": sur["fallback_fraction"],
                             "reaches_5_percent": sur["at_5_percent"]["surrogate_reaches_it"],
                             "source": "profiles/surrogate_study.json (python bench.py --surrogate-study)"}
 

@@ -829,6 +829,7 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
 // caller's own data, and the fastest is kept for the process (and appended
 // to the file named by DD_AUTOTUNE_CACHE, read back at start-up).
 std::atomic<int> g_autotune{1};
+std::atomic<int64_t> g_forced_choice{-1};   // dd_set_plan: 2 * chunk + variant, or -1
 
 struct TuneKey {
     std::string arch;
@@ -883,6 +884,11 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
                 int64_t *out)
 {
     *out = 0;
+    const int64_t forced = g_forced_choice.load();
+    if (forced >= 0) {
+        *out = forced;
+        return DD_OK;
+    }
     if (!g_autotune.load()) return DD_OK;
     const int n_inst = (int)so.size() - 1;
     int64_t ns = so.back(), nmax = 0;
@@ -990,6 +996,20 @@ int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, d
 using namespace dd;
 
 extern "C" int dd_set_autotune(int on) { return dd::g_autotune.exchange(on ? 1 : 0); }
+
+extern "C" int dd_set_plan(int64_t chunk_len, int variant)
+{
+    dd::clear_error();
+    if (chunk_len < 0) {
+        dd::g_forced_choice.store(-1);
+        return DD_OK;
+    }
+    if (chunk_len != 0 && chunk_len < TILE)
+        return dd::set_error(DD_EINVAL, "chunk_len must be 0 (heuristic) or at least %d", TILE);
+    if (variant != 0 && variant != 1) return dd::set_error(DD_EINVAL, "variant must be 0 or 1");
+    dd::g_forced_choice.store(2 * chunk_len + variant);
+    return DD_OK;
+}
 
 extern "C" int dd_last_plan(int64_t *chunk_len, int64_t *n_items, int *variant)
 {

@@ -341,16 +341,18 @@ __global__ void k_ensemble(const float *__restrict__ Y, int64_t sY, int members,
 
 // ------------------------------------------------- fused inference kernel --
 // One workgroup (4 waves) carries FROWS rows of one member (blockIdx.y)
-// through all four layers: the standardised inputs and every hidden
-// activation stay in LDS (rows padded by 8 bf16 so that the 16-byte fragment
-// reads of 16 consecutive rows fall in distinct banks), weight fragments are
-// read from global memory (L2-resident), bias + ReLU are applied when a layer's
-// accumulators are written back to LDS.  Hidden layers: each wave owns 64
-// output columns = 4 x 4 tiles of v_mfma_f32_16x16x32_bf16 over the 64 rows.
-// Output layer: each wave owns 16 rows x 16 (padded) columns.
+// through all four layers in one LDS buffer: the standardised inputs, then
+// each hidden layer's activations overwrite the previous ones (every wave
+// holds its whole output tile in registers until all waves have finished
+// reading the layer's input), so that 4 workgroups fit on a CU.  Rows are
+// padded by 8 bf16 so that the 16-byte fragment reads of 16 consecutive rows
+// fall in distinct banks.  Weight fragments come from global memory
+// (L2-resident), loaded one K step ahead of their use; bias + ReLU are applied
+// when a layer's accumulators are written back.  Hidden layers: each wave owns
+// 64 output columns = 4 x 4 tiles of v_mfma_f32_16x16x32_bf16 over the 64
+// rows.  Output layer: each wave owns 16 rows x 16 (padded) columns.
 constexpr int FROWS = 64;
-constexpr int HSTR = HID + 8;   // LDS row stride of hidden activations (bf16)
-constexpr int XSTR = INP + 8;   // LDS row stride of the input tile
+constexpr int HSTR = HID + 8;   // LDS row stride of the activations (bf16)
 
 __device__ __forceinline__ bf16x8 lds_frag(const __bf16 *p)
 {
@@ -362,10 +364,11 @@ __device__ __forceinline__ bf16x8 glb_frag(const __bf16 *p)
     return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-template <int K, int ASTR>
-__device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ Ain, __bf16 *__restrict__ Hout,
-                                             const __bf16 *__restrict__ W, const float *__restrict__ bias,
-                                             int wave, int lane)
+// H[FROWS][HSTR] holds the layer input in columns 0..K-1 on entry and the
+// layer output in columns 0..HID-1 on return.
+template <int K>
+__device__ __forceinline__ void hidden_layer(__bf16 *__restrict__ H, const __bf16 *__restrict__ W,
+                                             const float *__restrict__ bias, int wave, int lane)
 {
     // W: [HID][K] (out, in), K contiguous
     f32x4 acc[4][4];
@@ -373,22 +376,35 @@ __device__ __forceinline__ void hidden_layer(const __bf16 *__restrict__ Ain, __b
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int lr = lane & 15, lk = (lane >> 4) * 8;
     const int n0 = wave * 64;
-#pragma unroll 2
+    const __bf16 *Wl = W + (int64_t)(n0 + lr) * K + lk;
+    bf16x8 bn[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) bn[j] = glb_frag(Wl + (int64_t)16 * j * K);
+#pragma unroll
     for (int k0 = 0; k0 < K; k0 += 32) {
         bf16x8 b[4], a[4];
-        for (int j = 0; j < 4; ++j) b[j] = glb_frag(W + (int64_t)(n0 + 16 * j + lr) * K + k0 + lk);
-        for (int i = 0; i < 4; ++i) a[i] = lds_frag(Ain + (16 * i + lr) * ASTR + k0 + lk);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = bn[j];
+        if (k0 + 32 < K) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bn[j] = glb_frag(Wl + (int64_t)16 * j * K + k0 + 32);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = lds_frag(H + (16 * i + lr) * HSTR + k0 + lk);
+#pragma unroll
         for (int i = 0; i < 4; ++i)
+#pragma unroll
             for (int j = 0; j < 4; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    __syncthreads();   // every wave has read the layer input
     for (int j = 0; j < 4; ++j) {
         const int n = n0 + 16 * j + lr;
-        const float bn = bias[n];
+        const float bn_ = bias[n];
         for (int i = 0; i < 4; ++i)
             for (int e = 0; e < 4; ++e) {
                 const int r = 16 * i + (lane >> 4) * 4 + e;
-                Hout[r * HSTR + n] = to_bf16(fmaxf(acc[i][j][e] + bn, 0.f));
+                H[r * HSTR + n] = to_bf16(fmaxf(acc[i][j][e] + bn_, 0.f));
             }
     }
 }
@@ -399,14 +415,12 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ fea
                                                    const __bf16 *__restrict__ W4p, const float *__restrict__ w,
                                                    float *__restrict__ Y, int64_t sY)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 X[FROWS * XSTR];
-    __shared__ __attribute__((aligned(16))) __bf16 HA[FROWS * HSTR];
-    __shared__ __attribute__((aligned(16))) __bf16 HB[FROWS * HSTR];
+    __shared__ __attribute__((aligned(16))) __bf16 H[FROWS * HSTR];
     const int member = blockIdx.y;
     const int64_t r0 = (int64_t)blockIdx.x * FROWS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float dfloor = scal[2 * IN + 2 * OUT + 1], dscale = scal[2 * IN + 2 * OUT];
-    // standardised input tile (rows beyond n are zero)
+    // standardised input tile (rows beyond n and columns beyond IN are zero)
     for (int i = tid; i < FROWS * INP; i += 256) {
         const int r = i / INP, k = i % INP;
         float v = 0.f;
@@ -415,23 +429,24 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ fea
             if (k >= 12 && dfloor > 0.f) f = log10f(fmaxf(f, 0.f) * dscale + dfloor);
             v = (f - scal[k]) * scal[IN + k];
         }
-        X[r * XSTR + k] = to_bf16(v);
+        H[r * HSTR + k] = to_bf16(v);
     }
     __syncthreads();
     const float *wm = w + member * P;
-    hidden_layer<INP, XSTR>(X, HA, W1p + (int64_t)member * HID * INP, wm + OB1, wave, lane);
+    hidden_layer<INP>(H, W1p + (int64_t)member * HID * INP, wm + OB1, wave, lane);
     __syncthreads();
-    hidden_layer<HID, HSTR>(HA, HB, W2 + (int64_t)member * HID * HID, wm + OB2, wave, lane);
+    hidden_layer<HID>(H, W2 + (int64_t)member * HID * HID, wm + OB2, wave, lane);
     __syncthreads();
-    hidden_layer<HID, HSTR>(HB, HA, W3 + (int64_t)member * HID * HID, wm + OB3, wave, lane);
+    hidden_layer<HID>(H, W3 + (int64_t)member * HID * HID, wm + OB3, wave, lane);
     __syncthreads();
     // output layer: wave owns rows 16 wave .. +15, 16 padded columns
     {
         const int lr = lane & 15, lk = (lane >> 4) * 8;
         const __bf16 *W4m = W4p + (int64_t)member * OUTP * HID;
         f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
         for (int k0 = 0; k0 < HID; k0 += 32) {
-            const bf16x8 a = lds_frag(HA + (16 * wave + lr) * HSTR + k0 + lk);
+            const bf16x8 a = lds_frag(H + (16 * wave + lr) * HSTR + k0 + lk);
             const bf16x8 b = glb_frag(W4m + lr * HID + k0 + lk);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }

@@ -1,68 +1,74 @@
-// FP32 per-pair device functions of the mixed-precision path (same
-// regrouped closed form as dd_pair64.h, in FP32 with the endpoint
-// differences rearranged, and a 2-point source quadrature).
+// FP32 per-pair device functions of the mixed-precision path (the regrouped
+// closed form of dd_pair64.h in FP32 with the endpoint differences
+// rearranged, and a 2-point source quadrature).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace dd {
 
-// FP32, far pairs.  y and rho are formed in FP64 by the caller and rounded
-// once.  The endpoint differences are rearranged so that no two nearly equal
-// numbers are subtracted when the target lies far away or on the extension
-// of the segment:
+// FP32, far pairs: adds sigma^i b_j / k2 (the regrouped closed form of
+// dd_pair64.h, kr = (1 - nu)/2) to (f0, f1, f2).  y, rho and hh = |rho|^2 are
+// formed by the caller (y and rho in FP64, rounded once).  The endpoint
+// differences are rearranged so that no two nearly equal numbers are
+// subtracted when the target lies far away or on the extension of the segment
+// (u1 = -y, u2 = L - y, r = 1/Ra, s = u r):
 //   I31 = L (u1 + u2) r1 r2 / (Ra1 + Ra2)
 //   I30 = L (u1 + u2) r1 r2 / (u2 Ra1 + u1 Ra2)          if u1 u2 > 0
 //       = (s2 - s1) / d2                                 otherwise
 //   1 - s1 s2 = r1 r2 P,  P = d2 (d2 + u1^2 + u2^2) / (Ra1 Ra2 + u1 u2)  if u1 u2 > 0
 //                         P = Ra1 Ra2 - u1 u2                            otherwise
-//   I50 = I30 (d2 (r1^2 + r2^2) + r1 r2 P) / (3 d2)
-//   I51 = I31 (r1^2 + r1 r2 + r2^2) / 3
-//   I52 = I30 (s1^2 + s1 s2 + s2^2) / 3
+//   E50 = 3 I50 = I30 (d2 (r1^2 + r2^2) + r1 r2 P) / d2
+//   D51 = 3 I51 = I31 (r1^2 + r1 r2 + r2^2)
+//   P3  = 3 I52 = I30 (s1^2 + s1 s2 + s2^2)
 // (from s2^3 - s1^3 = (s2 - s1)(s1^2 + s1 s2 + s2^2), 1 - s^2 = d2 r^2 and
-// u2^2 Ra1^2 - u1^2 Ra2^2 = d2 (u2^2 - u1^2)).
-__device__ __forceinline__ void pair_sigma_b_f32(
-    float y, float h0, float h1, float h2, float bj0, float bj1, float bj2,
+// u2^2 Ra1^2 - u1^2 Ra2^2 = d2 (u2^2 - u1^2)).  The four reciprocals come in
+// pairs from two: 1/X and 1/Y as Y/(X Y) and X/(X Y).
+__device__ __forceinline__ void pair_acc_f32(
+    float y, float h0, float h1, float h2, float hh, float bj0, float bj1, float bj2,
     float t0, float t1, float t2, float L, float b0, float b1, float b2,
-    float c0, float c1, float c2, float k1, float k2, float &o0, float &o1, float &o2)
+    float c0, float c1, float c2, float kr, float nu, float &f0, float &f1, float &f2)
 {
-    const float d2 = h0 * h0 + h1 * h1 + h2 * h2 + 1.0f;
-    const float u1 = -y, u2 = L - y;
-    const float Ra1s = d2 + u1 * u1, Ra2s = d2 + u2 * u2;
+    const float d2 = hh + 1.0f;
+    const float u2 = L - y;
+    const float Ra1s = fmaf(y, y, d2), Ra2s = fmaf(u2, u2, d2);
     const float r1 = __builtin_amdgcn_rsqf(Ra1s), r2 = __builtin_amdgcn_rsqf(Ra2s);
     const float Ra1 = Ra1s * r1, Ra2 = Ra2s * r2;
-    const float s1 = u1 * r1, s2 = u2 * r2;
+    const float s1 = -y * r1, s2 = u2 * r2;
     const float rr = r1 * r2;
-    const float Lus = L * (L - 2.0f * y) * rr;
-    const bool same = u1 * u2 > 0.0f;
-    const float id2 = __builtin_amdgcn_rcpf(d2);
-    const float I30 = same ? Lus * __builtin_amdgcn_rcpf(u2 * Ra1 + u1 * Ra2) : (s2 - s1) * id2;
-    const float P = same ? d2 * (d2 + u1 * u1 + u2 * u2) * __builtin_amdgcn_rcpf(Ra1 * Ra2 + u1 * u2)
-                         : Ra1 * Ra2 - u1 * u2;
-    const float I31 = Lus * __builtin_amdgcn_rcpf(Ra1 + Ra2);
-    const float I50 = I30 * (d2 * (r1 * r1 + r2 * r2) + rr * P) * id2 * (1.0f / 3.0f);
-    const float I51 = I31 * (r1 * r1 + rr + r2 * r2) * (1.0f / 3.0f);
-    const float I52 = I30 * (s1 * s1 + s1 * s2 + s2 * s2) * (1.0f / 3.0f);
-    const float g0 = 2.0f * I30 + 3.0f * I50;
-    const float g1 = 2.0f * I31 + 3.0f * I51;
-    const float q = c0 * h0 + c1 * h1 + c2 * h2;
-    const float rb0 = h1 * b2 - h2 * b1, rb1 = h2 * b0 - h0 * b2, rb2 = h0 * b1 - h1 * b0;
-    const float A = -k1 * g0, Cc = k2 * I31 - k1 * g1, qk = q * k2;
-    const float Tt = 1.5f * qk * I52, Tr = -3.0f * qk * I51;
-    const float Zc = -k2 * I30, Zr = 1.5f * qk * I50;
-    const float kd = qk * (I30 + 3.0f * I50);
-    // sigma b_j = t (w.b_j) + w (t.b_j) + rho (z.b_j) + z (rho.b_j) + kd b_j, with w and z
-    // expanded: coefficients of the five vectors rho x b, c, t, rho and b_j
-    const float tb = t0 * bj0 + t1 * bj1 + t2 * bj2;
-    const float hb = h0 * bj0 + h1 * bj1 + h2 * bj2;
-    const float cb = c0 * bj0 + c1 * bj1 + c2 * bj2;
-    const float rbb = rb0 * bj0 + rb1 * bj1 + rb2 * bj2;
-    const float wb = A * rbb + Cc * cb + Tt * tb + Tr * hb;
-    const float zb = Zc * cb + Zr * hb;
-    const float Pr = A * tb, Pc = Cc * tb + Zc * hb, Pt = wb + Tt * tb, Ph = Tr * tb + zb + Zr * hb;
-    o0 = Pr * rb0 + Pc * c0 + Pt * t0 + Ph * h0 + kd * bj0;
-    o1 = Pr * rb1 + Pc * c1 + Pt * t1 + Ph * h1 + kd * bj1;
-    o2 = Pr * rb2 + Pc * c2 + Pt * t2 + Ph * h2 + kd * bj2;
+    const float Lus = L * fmaf(-2.0f, y, L) * rr;
+    const bool same = y * u2 < 0.0f;                    // u1 u2 > 0
+    const float Aq = fmaf(u2, Ra1, -y * Ra2);           // u2 Ra1 + u1 Ra2 (> 0 when same)
+    const float Bq = fmaf(Ra1, Ra2, -y * u2);           // Ra1 Ra2 + u1 u2 (>= d2 when same)
+    const float Cs = Ra1 + Ra2;
+    const float iAB = __builtin_amdgcn_rcpf(Aq * Bq), iCD = __builtin_amdgcn_rcpf(Cs * d2);
+    const float id2 = Cs * iCD;
+    const float I30 = same ? Lus * (Bq * iAB) : (s2 - s1) * id2;
+    const float Pm = same ? d2 * (Ra1s + u2 * u2) * (Aq * iAB) : fmaf(y, u2, Ra1 * Ra2);
+    const float I31 = Lus * (d2 * iCD);
+    const float r12 = fmaf(r1, r1, r2 * r2);
+    const float E50 = I30 * fmaf(d2, r12, rr * Pm) * id2;
+    const float D51 = I31 * (r12 + rr);
+    const float P3 = I30 * fmaf(s1, s1 + s2, s2 * s2);
+    const float g0 = fmaf(2.0f, I30, E50);
+    const float q = fmaf(c2, h2, fmaf(c1, h1, c0 * h0));
+    const float A = -kr * g0;
+    const float Cc = fmaf(nu, I31, -kr * D51);
+    const float Tt2 = q * P3, Tr = -q * D51, Zr2 = q * E50;
+    const float kd = q * (I30 + E50);
+    const float rb0 = fmaf(h1, b2, -h2 * b1), rb1 = fmaf(h2, b0, -h0 * b2), rb2 = fmaf(h0, b1, -h1 * b0);
+    // sigma b_j / k2 as coefficients of the five vectors rho x b, c, t, rho and b_j
+    const float tb = fmaf(t2, bj2, fmaf(t1, bj1, t0 * bj0));
+    const float hb = fmaf(h2, bj2, fmaf(h1, bj1, h0 * bj0));
+    const float cb = fmaf(c2, bj2, fmaf(c1, bj1, c0 * bj0));
+    const float rbb = fmaf(rb2, bj2, fmaf(rb1, bj1, rb0 * bj0));
+    const float Pt = fmaf(Tt2, tb, fmaf(Tr, hb, fmaf(Cc, cb, A * rbb)));
+    const float Ph = fmaf(Tr, tb, fmaf(Zr2, hb, -I30 * cb));
+    const float Pc = fmaf(Cc, tb, -I30 * hb);
+    const float Pr = A * tb;
+    f0 = fmaf(kd, bj0, fmaf(Ph, h0, fmaf(Pt, t0, fmaf(Pc, c0, fmaf(Pr, rb0, f0)))));
+    f1 = fmaf(kd, bj1, fmaf(Ph, h1, fmaf(Pt, t1, fmaf(Pc, c1, fmaf(Pr, rb1, f1)))));
+    f2 = fmaf(kd, bj2, fmaf(Ph, h2, fmaf(Pt, t2, fmaf(Pc, c2, fmaf(Pr, rb2, f2)))));
 }
 
 

@@ -129,12 +129,8 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                     pair_acc_isolated_f64(xq0, xq1, xq2, bj0, bj1, bj2, d, kr, nu, a0, a1, a2);
                 }
             } else {
-                float c0, c1, c2;
-                pair_sigma_b_f32(y, h0, h1, h2, fb0, fb1, fb2, r[6], r[7], r[8], Ls, r[11], r[12], r[13],
-                                 r[14], r[15], r[16], fkr, 1.0f, c0, c1, c2);
-                f0 += c0;
-                f1 += c1;
-                f2 += c2;
+                pair_acc_f32(y, h0, h1, h2, hh, fb0, fb1, fb2, r[6], r[7], r[8], Ls, r[11], r[12], r[13],
+                             r[14], r[15], r[16], fkr, fnu, f0, f1, f2);
             }
         }
         a0 += (double)f0;

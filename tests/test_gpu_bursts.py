@@ -66,6 +66,20 @@ def test_small_batch_mixed_vs_oracle():
     assert np.abs(rg - ro).max() / np.abs(ro).max() < 1e-4
 
 
+@pytest.mark.parametrize("variant", [0, 1])
+def test_small_batch_mixed_each_variant(variant):
+    bt = _small_batch()
+    dd.dd_set_plan(0, variant)
+    try:
+        xg, rg, _ = _gpu_burst(bt, 5, dd.DD_MIXED)
+        assert dd.dd_last_plan()[2] == variant
+    finally:
+        dd.dd_set_plan(-1)
+    xo, ro, _ = O.burst_batch(bt, W.material(), 2, 5, W.DT)
+    assert normwise(xg - bt.x, xo - bt.x) < 1e-4
+    assert np.abs(rg - ro).max() / np.abs(ro).max() < 1e-4
+
+
 def test_batched_equals_single_calls():
     bt = _small_batch()
     xb, rb, fb = _gpu_burst(bt, 4)

@@ -4,6 +4,8 @@ FP64 oracle on the same seeded inputs.
 Tolerances (normwise, max node error over max node force): FP64 path 1e-10,
 mixed FP32/FP64 path 1e-4.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -62,6 +64,46 @@ def test_mixed_vs_oracle(n_loops, Q):
     e = normwise(_gpu_forces(inst, Q, dd.DD_MIXED), _oracle_forces(inst, Q))
     print(f"mixed {n_loops} loops Q={Q} err {e:.2e}")
     assert e < TOLMIX
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_100_loops():
+    return _oracle_forces(W.subset(W.config1(), 100), 2)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("chunk", [0, 256])
+def test_mixed_each_variant_and_split(variant, chunk):
+    """Both mixed-kernel variants (0: FP32 quadrature band, 1: none) and a
+    forced short source range, on several tiles with a ragged tail; variant 0
+    must actually take the quadrature branch here."""
+    inst = W.subset(W.config1(), 100)
+    ref = _oracle_100_loops()
+    dd.dd_set_plan(chunk, variant)
+    try:
+        dd.dd_timing_read(reset=True)
+        F = _gpu_forces(inst, 2, dd.DD_MIXED)
+        _, _, near, quad = dd.dd_timing_read(reset=True)
+        c, items, v = dd.dd_last_plan()
+    finally:
+        dd.dd_set_plan(-1)
+    e = normwise(F, ref)
+    print(f"mixed variant {variant} chunk {chunk}: err {e:.2e}, items {items}, quad {quad}, near {near}")
+    assert v == variant
+    assert e < TOLMIX
+    assert (quad > 0) if variant == 0 else (quad == 0)
+    if chunk:
+        assert c == chunk
+
+
+def test_fp64_forced_short_split():
+    inst = W.subset(W.config1(), 37)
+    dd.dd_set_plan(256, 0)
+    try:
+        F = _gpu_forces(inst, 3)
+    finally:
+        dd.dd_set_plan(-1)
+    assert normwise(F, _oracle_forces(inst, 3)) < TOL64
 
 
 @pytest.mark.parametrize("prec,tol", [(dd.DD_FP64, TOL64), (dd.DD_MIXED, TOLMIX)])
