@@ -44,8 +44,9 @@ UNIT = "segment-pair evals/s"
 # refinement steps; selects, compares and sign changes = 0).
 FLOP_F64_EVAL = 133          # FP64 path (pair_acc_f64)
 FLOP_MIX_BAND_F32 = 14       # mixed: offset to the source midpoint and its square (every
-                             # pair, variant 0)
-FLOP_MIX_QUAD_F32 = 132      # mixed: FP32 2-point source quadrature (quad2_acc_f32)
+                             # pair, variants 0 and 2)
+FLOP_MIX_QUAD_F32 = {0: 134, 2: 152}   # mixed: FP32 2-point (variant 0) and 3-point (variant 2)
+                                       # source quadrature (quad2/quad3_acc_f32)
 FLOP_MIX_LOC_F64 = 14        # mixed: FP64 offset, axial and perpendicular parts (pairs
                              # that are not evaluated by quadrature)
 FLOP_MIX_CLASS_F32 = 8       # mixed: minimum-distance test (the same pairs)
@@ -379,10 +380,10 @@ def main():
             allp = N * N * Q                 # including the (skipped) self pairs
             other = allp - quad              # pairs located in FP64
             closed = pairs * Q - quad - near
-            band = allp if variant == 0 else 0
+            band = allp if variant in (0, 2) else 0
             f64 = FLOP_MIX_LOC_F64 * other + FLOP_MIX_NEAR_F64 * near
-            f32 = (FLOP_MIX_BAND_F32 * band + FLOP_MIX_QUAD_F32 * quad + FLOP_MIX_CLASS_F32 * other
-                   + FLOP_MIX_FAR_F32 * closed)
+            f32 = (FLOP_MIX_BAND_F32 * band + FLOP_MIX_QUAD_F32.get(variant, 0) * quad
+                   + FLOP_MIX_CLASS_F32 * other + FLOP_MIX_FAR_F32 * closed)
         flops = f64 + f32
         t_roof = f64 / PEAK_F64 + f32 / PEAK_F32
         t_meas = f64 / peaks_measured["fp64"] + f32 / peaks_measured["fp32_vec"]
@@ -439,7 +440,7 @@ def main():
                             "near_fp64_evals_per_launch": bands[0],
                             "quad_fp32_evals_per_launch": bands[1],
                             "plan": {"chunk_len": bands[3], "work_items": bands[4],
-                                     "mixed_quadrature_test": bands[2] == 0},
+                                     "mixed_variant": bands[2]},
                             "roofline": {kk: r[kk] for kk in ("bound", "achieved", "peak", "unit", "frac",
                                                               "peak_measured", "frac_of_measured")}}
         # the 262,144-segment volume (radii 50-2000 b, 50,000 b cube): one step per precision
@@ -452,7 +453,7 @@ def main():
                             "kernel_ms": k * 1e3, "near_fp64_evals_per_launch": bands[0],
                             "quad_fp32_evals_per_launch": bands[1],
                             "plan": {"chunk_len": bands[3], "work_items": bands[4],
-                                     "mixed_quadrature_test": bands[2] == 0}}
+                                     "mixed_variant": bands[2]}}
         del vb
         # the 256-segment volume: 100 FP64 glide steps captured in one graph launch
         sb = W.pack([W.config0()])

@@ -120,14 +120,19 @@ int dd_set_autotune(int on);
  * heuristic, else at least 256), variant = the mixed kernel's variant (see
  * dd_last_plan).  chunk_len < 0 returns to the automatic choice.  Applies to
  * every later force evaluation in the process.  DD_EINVAL for a chunk_len in
- * 1..255 or a variant other than 0 and 1. */
+ * 1..255 or a variant other than 0, 1 and 2. */
 int dd_set_plan(int64_t chunk_len, int variant);
 
 /* The work split of the most recent force evaluation on this device: the
  * source-range length of a work item, the number of work items, and the
- * mixed kernel's variant (0: each source first tested in FP32 for the
- * well-separated band evaluated by 2-point quadrature, 1: no such test, every
- * pair located in FP64).  Any pointer may be null. */
+ * mixed kernel's variant.  Variants: 0 = each source is first tested in FP32
+ * against a band of max(30 L, cutoff + L/2) around its midpoint, and sources
+ * outside it for every target point of a wavefront are evaluated by 2-point
+ * Gauss-Legendre quadrature along the source; 1 = no such test, every pair
+ * located in FP64 and evaluated by the FP32 closed form or the FP64 near
+ * field; 2 = as 0 with 3-point quadrature beyond max(6 L, cutoff + L/2).
+ * All three stay within 5e-7 relative of the exact segment field per pair.
+ * Any pointer may be null. */
 int dd_last_plan(int64_t *chunk_len, int64_t *n_items, int *variant);
 
 /* Measurement hooks (for benchmarks and profilers).  With timing on, every

@@ -118,12 +118,19 @@ inline size_t rec64_bytes(int64_t ns)
     return sizeof(double) * (size_t)REC64_TOTAL * (size_t)(ns > 1 ? ns : 1);
 }
 // FP32 segment record of the mixed path, REC32A floats per segment (array of
-// structures, read with wavefront-uniform scalar loads):
+// structures, read with wavefront-uniform scalar loads or staged in LDS):
 //  0..2 midpoint xm/a rounded to FP32, 3..5 the rounding remainder xm/a - [0..2],
-//  6..8 t, 9 L/a, 10 hoff = L/(2 sqrt 3), 11..13 b/a, 14..16 c, 17 the squared
-//  quadrature band max(30 L, cutoff + L/2)^2, 18 L/2, 19 1 + hoff^2,
-//  20 2 hoff, 21..23 zero.
+//  6..8 t, 9 L/a, 11..13 b/a, 14..16 c, and for the source quadrature of the
+//  kernel variant in use (points xm +- hq t with weight Wo each, plus xm with
+//  weight Wc for 3 points): 10 hq, 17 the squared band outside which it is
+//  used, 18 Wo, 19 1 + hq^2, 20 2 hq, 21 Wc, 22..23 zero.
 constexpr int REC32A = 24;
+// Mixed kernel variants: 0 = 2-point source quadrature beyond max(30 L,
+// cutoff + L/2), 1 = no quadrature, 2 = 3-point source quadrature beyond
+// max(6 L, cutoff + L/2).  A work split is encoded as MIXED_VARIANTS *
+// (source-range length) + variant.
+constexpr int MIXED_VARIANTS = 3;
+inline __host__ __device__ int quad_points(int variant) { return variant == 0 ? 2 : (variant == 2 ? 3 : 0); }
 
 GaussRule gauss_rule(int n);
 

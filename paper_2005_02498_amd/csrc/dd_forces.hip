@@ -130,6 +130,7 @@ struct PrepArgs {
     double *rec64;        // [REC64][ns], then [ns][RECA]
     float *rec32;         // [ns][REC32A] or null
     float cut;            // near-field cutoff in units of a (FP32 record)
+    int quadn;            // source-quadrature points of the mixed kernel variant (0, 2, 3)
     int32_t *sys;         // [ns] slip system or -1, or null
     unsigned *flags;
 };
@@ -202,15 +203,26 @@ __global__ void k_seg_prep(PrepArgs A)
             q[11 + k] = (float)b[k];
             q[14 + k] = (float)c[k];
         }
-        const double hoff = L * 0.28867513459481288225;   // L / (2 sqrt 3)
-        const double band = fmax(30.0 * L, (double)A.cut + 0.5 * L);
+        // source quadrature of the variant: Gauss-Legendre points on the source
+        double hq = 0.0, wo = 0.0, wc = 0.0, band = 0.0;
+        if (A.quadn == 2) {
+            hq = L * 0.28867513459481288225;            // L / (2 sqrt 3)
+            wo = 0.5 * L;
+            band = fmax(30.0 * L, (double)A.cut + 0.5 * L);
+        } else if (A.quadn == 3) {
+            hq = L * 0.38729833462074168852;            // (L / 2) sqrt(3/5)
+            wo = L * (5.0 / 18.0);
+            wc = L * (8.0 / 18.0);
+            band = fmax(6.0 * L, (double)A.cut + 0.5 * L);
+        }
         q[9] = (float)L;
-        q[10] = (float)hoff;
+        q[10] = (float)hq;
         q[17] = (float)(band * band);
-        q[18] = (float)(0.5 * L);
-        q[19] = (float)(1.0 + hoff * hoff);
-        q[20] = (float)(2.0 * hoff);
-        q[21] = 0.f; q[22] = 0.f; q[23] = 0.f;
+        q[18] = (float)wo;
+        q[19] = (float)(1.0 + hq * hq);
+        q[20] = (float)(2.0 * hq);
+        q[21] = (float)wc;
+        q[22] = 0.f; q[23] = 0.f;
     }
     if (A.sys) {
         int found = -1;
@@ -797,6 +809,7 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         A.rec64 = C.rec64;
         A.rec32 = C.rec32;
         A.cut = C.cut;
+        A.quadn = C.precision == DD_MIXED ? quad_points(C.variant) : 0;
         A.sys = C.sys;
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
@@ -829,7 +842,7 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
 // caller's own data, and the fastest is kept for the process (and appended
 // to the file named by DD_AUTOTUNE_CACHE, read back at start-up).
 std::atomic<int> g_autotune{1};
-std::atomic<int64_t> g_forced_choice{-1};   // dd_set_plan: 2 * chunk + variant, or -1
+std::atomic<int64_t> g_forced_choice{-1};   // dd_set_plan: encoded split, or -1
 
 struct TuneKey {
     std::string arch;
@@ -876,8 +889,8 @@ void save_tune(const TuneKey &k, int64_t c)
     std::fclose(fp);
 }
 
-// Returns 2 * (chunk length to use, 0 = the built-in heuristic) + the mixed
-// kernel's variant.
+// Returns MIXED_VARIANTS * (chunk length to use, 0 = the built-in heuristic)
+// + the mixed kernel's variant.
 int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, int64_t nn,
                 const Layout &inst, const int32_t *seg_nodes, const double *x, const double *burgers,
                 const double *normal, const dd_material *m, int Q, int prec, double cut, bool need_sys,
@@ -908,13 +921,14 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
         *out = itk->second;
         return DD_OK;
     }
-    // a choice is encoded as 2 * chunk_length + mixed-kernel variant
+    // a choice is encoded as MIXED_VARIANTS * chunk_length + mixed-kernel variant
     std::vector<int64_t> chunks = {0};
     for (int64_t c = TILE; c < nmax; c *= 2) chunks.push_back(c);
     chunks.push_back(((nmax + TILE - 1) / TILE) * TILE);   // one range per tile
     std::vector<int64_t> cands;
     for (int64_t c : chunks)
-        for (int v = 0; v < (prec == DD_MIXED ? 2 : 1); ++v) cands.push_back(2 * c + v);
+        for (int v = 0; v < (prec == DD_MIXED ? MIXED_VARIANTS : 1); ++v)
+            cands.push_back(MIXED_VARIANTS * c + v);
     hipEvent_t e0, e1;
     DD_HIP(hipEventCreate(&e0));
     DD_HIP(hipEventCreate(&e1));
@@ -922,10 +936,10 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
     int64_t best_c = 0;
     int rc = DD_OK;
     for (int64_t cv : cands) {
-        const int64_t c = cv / 2;
+        const int64_t c = cv / MIXED_VARIANTS;
         ForceCtx C;
         if ((rc = setup(ws, st, so, nn, seg_nodes, m, Q, prec, cut, c, need_sys, C))) break;
-        C.variant = (int)(cv % 2);
+        C.variant = (int)(cv % MIXED_VARIANTS);
         PrepArgs A{};
         A.L = C.L;
         A.L.seg_inst = inst.seg_inst;
@@ -939,6 +953,7 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
         A.rec64 = C.rec64;
         A.rec32 = C.rec32;
         A.cut = C.cut;
+        A.quadn = C.precision == DD_MIXED ? quad_points(C.variant) : 0;
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
         double t_min = 1e300;
@@ -1006,8 +1021,8 @@ extern "C" int dd_set_plan(int64_t chunk_len, int variant)
     }
     if (chunk_len != 0 && chunk_len < TILE)
         return dd::set_error(DD_EINVAL, "chunk_len must be 0 (heuristic) or at least %d", TILE);
-    if (variant != 0 && variant != 1) return dd::set_error(DD_EINVAL, "variant must be 0 or 1");
-    dd::g_forced_choice.store(2 * chunk_len + variant);
+    if (variant < 0 || variant >= MIXED_VARIANTS) return dd::set_error(DD_EINVAL, "variant must be 0, 1 or 2");
+    dd::g_forced_choice.store(MIXED_VARIANTS * chunk_len + variant);
     return DD_OK;
 }
 
@@ -1045,9 +1060,9 @@ extern "C" int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
     if ((rc = tuned_chunk(ws, st, so, n_nodes, flat, seg_nodes, x, burgers, normal, m, n_gauss, precision,
                           near_cutoff_a, false, &choice)))
         return rc;
-    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / 2, false, C)))
+    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / MIXED_VARIANTS, false, C)))
         return rc;
-    C.variant = (int)(choice % 2);
+    C.variant = (int)(choice % MIXED_VARIANTS);
     g_last_variant = C.variant;
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
     launch_csr(C, seg_nodes, st);
@@ -1177,9 +1192,9 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
     if ((rc = tuned_chunk(ws, st, so, nn, inst, seg_nodes, x, burgers, normal, m, n_gauss, precision,
                           near_cutoff_a, true, &choice)))
         return rc;
-    if ((rc = setup(ws, st, so, nn, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / 2, true, C)))
+    if ((rc = setup(ws, st, so, nn, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / MIXED_VARIANTS, true, C)))
         return rc;
-    C.variant = (int)(choice % 2);
+    C.variant = (int)(choice % MIXED_VARIANTS);
     g_last_variant = C.variant;
     C.L.seg_inst = inst.seg_inst;
     C.L.node_off = inst.node_off;
@@ -1208,6 +1223,7 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
         A.rec64 = C.rec64;
         A.rec32 = C.rec32;
         A.cut = C.cut;
+        A.quadn = C.precision == DD_MIXED ? quad_points(C.variant) : 0;
         A.sys = C.sys;
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);

@@ -72,50 +72,39 @@ __device__ __forceinline__ void pair_acc_f32(
 }
 
 
-// FP32, well-separated pairs (target at least GAUSS_BAND source lengths from
-// the source midpoint): 2-point Gauss-Legendre quadrature of the integrand
-// along the source instead of the closed form.  Source points xm -+ hoff t
-// (hoff = L / (2 sqrt 3), weight W = L/2 each); with e = x - xm, ym = e.t,
-// rho = e - ym t, the axial coordinates of the target relative to the two
-// points are v = ym +- hoff and Ra^2 = |e|^2 + 1 + hoff^2 +- 2 hoff ym.  With
-// R = rho + v t, R x b = rho x b - v c and q = c.rho, the integrand
-// contracted with b_j (divided by k2, kr = k1/k2 = (1 - nu)/2) is
+// FP32, well-separated pairs: Gauss-Legendre quadrature of the integrand
+// along the source instead of the closed form, used when the target lies far
+// enough from the source midpoint (30 source lengths for 2 points, 6 for 3:
+// the rule's error is then below 2e-7 relative).  Source points xm + sg t with
+// weights wg; with e = x - xm, ym = e.t, rho = e - ym t, the axial coordinate
+// of the target relative to a point is v = ym - sg and Ra^2 = |e|^2 + 1 +
+// sg^2 - 2 sg ym.  With R = rho + v t, R x b = rho x b - v c and q = c.rho,
+// the integrand contracted with b_j (divided by k2, kr = k1/k2 = (1 - nu)/2)
+// is
 //   K b_j = al [ (R x b)(t.b_j) + t ((R x b).b_j) ] + be b_j
 //         + ga [ R (c.b_j) + c (R.b_j) ] + de R (R.b_j),
 //   al = -kr (2/Ra^3 + 3/Ra^5), be = q (1/Ra^3 + 3/Ra^5),
 //   ga = -1/Ra^3, de = 3 q / Ra^5.
-// Summed over the two points it depends on them only through
-//   S3 = sum W/Ra^3, S5 = sum W/Ra^5, S3v = sum W v/Ra^3, S5v = sum W v/Ra^5,
-//   S5vv = sum W v^2/Ra^5,
+// Summed over the points it depends on them only through
+//   S3 = sum w/Ra^3, S5 = sum w/Ra^5, S3v = sum w v/Ra^3, S5v = sum w v/Ra^5,
+//   S5vv = sum w v^2/Ra^5,
 // and collects as coefficients of rho x b, c, t, b_j and rho:
 //   rho x b : (t.b_j) Sal                       Sal = -kr (2 S3 + 3 S5)
 //   c       : (rho.b_j) Sga + (t.b_j) Sgv       Sga = -S3, Sgv = -nu S3v + 3 kr S5v
 //   t       : ((rho x b).b_j) Sal + (c.b_j) Sgv + 3 q ((rho.b_j) S5v + (t.b_j) S5vv)
 //   b_j     : q (S3 + 3 S5)
 //   rho     : (c.b_j) Sga + 3 q ((rho.b_j) S5 + (t.b_j) S5v)
-// The quadrature error is below 2e-7 relative at that separation.
-constexpr float GAUSS_BAND = 30.0f;
 
-// e = target - source midpoint; s = the source's FP32 record (see REC32A);
-// adds K b_j / k2 to (f0, f1, f2).
-__device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, float ee, const float *s,
-                                              float bj0, float bj1, float bj2, float kr, float nu,
-                                              float &f0, float &f1, float &f2)
+// The moments are collected as the coefficients of the five vectors; shared
+// by the 2- and 3-point rules.
+__device__ __forceinline__ void quad_moments_acc_f32(float e0, float e1, float e2, float ym, const float *s,
+                                                     float S3, float S5, float S3v, float S5v, float S5vv,
+                                                     float bj0, float bj1, float bj2, float kr, float nu,
+                                                     float &f0, float &f1, float &f2)
 {
-    const float t0 = s[6], t1 = s[7], t2 = s[8], hoff = s[10], W = s[18];
+    const float t0 = s[6], t1 = s[7], t2 = s[8];
     const float b0 = s[11], b1 = s[12], b2 = s[13], c0 = s[14], c1 = s[15], c2 = s[16];
-    const float ym = fmaf(e2, t2, fmaf(e1, t1, e0 * t0));
     const float h0 = fmaf(-ym, t0, e0), h1 = fmaf(-ym, t1, e1), h2 = fmaf(-ym, t2, e2);
-    const float base = ee + s[19], tw = s[20] * ym;
-    const float vA = ym + hoff, vB = ym - hoff;
-    const float iA = __builtin_amdgcn_rsqf(base + tw), iB = __builtin_amdgcn_rsqf(base - tw);
-    const float iA2 = iA * iA, iB2 = iB * iB;
-    const float iA3 = iA2 * iA, iB3 = iB2 * iB;
-    const float iA5 = iA3 * iA2, iB5 = iB3 * iB2;
-    const float pA = iA5 * vA, pB = iB5 * vB;
-    const float S3 = W * (iA3 + iB3), S5 = W * (iA5 + iB5);
-    const float S3v = W * fmaf(iA3, vA, iB3 * vB), S5v = W * (pA + pB);
-    const float S5vv = W * fmaf(pA, vA, pB * vB);
     const float rb0 = fmaf(h1, b2, -h2 * b1), rb1 = fmaf(h2, b0, -h0 * b2), rb2 = fmaf(h0, b1, -h1 * b0);
     const float tb = fmaf(t2, bj2, fmaf(t1, bj1, t0 * bj0));
     const float hb = fmaf(h2, bj2, fmaf(h1, bj1, h0 * bj0));
@@ -133,6 +122,52 @@ __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, floa
     f0 = fmaf(Cb, bj0, fmaf(Ch, h0, fmaf(Ct, t0, fmaf(Cc, c0, fmaf(Cr, rb0, f0)))));
     f1 = fmaf(Cb, bj1, fmaf(Ch, h1, fmaf(Ct, t1, fmaf(Cc, c1, fmaf(Cr, rb1, f1)))));
     f2 = fmaf(Cb, bj2, fmaf(Ch, h2, fmaf(Ct, t2, fmaf(Cc, c2, fmaf(Cr, rb2, f2)))));
+}
+
+// e = target - source midpoint, ee = |e|^2; s = the source's FP32 record (see
+// REC32A); adds K b_j / k2 to (f0, f1, f2).  2-point rule: points at
+// v = ym -+ hq, weight Wo each.
+__device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, float ee, const float *s,
+                                              float bj0, float bj1, float bj2, float kr, float nu,
+                                              float &f0, float &f1, float &f2)
+{
+    const float hq = s[10], W = s[18];
+    const float ym = fmaf(e2, s[8], fmaf(e1, s[7], e0 * s[6]));
+    const float base = ee + s[19], tw = s[20] * ym;
+    const float vA = ym + hq, vB = ym - hq;
+    const float iA = __builtin_amdgcn_rsqf(base + tw), iB = __builtin_amdgcn_rsqf(base - tw);
+    const float iA2 = iA * iA, iB2 = iB * iB;
+    const float iA3 = iA2 * iA, iB3 = iB2 * iB;
+    const float iA5 = iA3 * iA2, iB5 = iB3 * iB2;
+    const float pA = iA5 * vA, pB = iB5 * vB;
+    const float S3 = W * (iA3 + iB3), S5 = W * (iA5 + iB5);
+    const float S3v = W * fmaf(iA3, vA, iB3 * vB), S5v = W * (pA + pB);
+    const float S5vv = W * fmaf(pA, vA, pB * vB);
+    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2);
+}
+
+// 3-point rule: points at v = ym -+ hq with weight Wo and at v = ym with
+// weight Wc (Gauss-Legendre, hq = (L/2) sqrt(3/5), Wo = 5L/18, Wc = 8L/18).
+// Its error is below 2e-7 relative beyond 6 source lengths from the midpoint.
+__device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, float ee, const float *s,
+                                              float bj0, float bj1, float bj2, float kr, float nu,
+                                              float &f0, float &f1, float &f2)
+{
+    const float hq = s[10], Wo = s[18], Wc = s[21];
+    const float ym = fmaf(e2, s[8], fmaf(e1, s[7], e0 * s[6]));
+    const float base = ee + s[19], tw = s[20] * ym;
+    const float vA = ym + hq, vB = ym - hq;
+    const float iA = __builtin_amdgcn_rsqf(base + tw), iB = __builtin_amdgcn_rsqf(base - tw);
+    const float iC = __builtin_amdgcn_rsqf(ee + 1.0f);
+    const float iA2 = iA * iA, iB2 = iB * iB, iC2 = iC * iC;
+    const float iA3 = iA2 * iA, iB3 = iB2 * iB, iC3 = iC2 * iC;
+    const float iA5 = iA3 * iA2, iB5 = iB3 * iB2, iC5 = iC3 * iC2;
+    const float pA = iA5 * vA, pB = iB5 * vB, pC = iC5 * ym;
+    const float S3 = fmaf(Wc, iC3, Wo * (iA3 + iB3)), S5 = fmaf(Wc, iC5, Wo * (iA5 + iB5));
+    const float S3v = fmaf(Wc, iC3 * ym, Wo * fmaf(iA3, vA, iB3 * vB));
+    const float S5v = fmaf(Wc, pC, Wo * (pA + pB));
+    const float S5vv = fmaf(Wc, pC * ym, Wo * fmaf(pA, vA, pB * vB));
+    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2);
 }
 
 }  // namespace dd

@@ -10,21 +10,23 @@ typedef float f32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 // Mixed precision.  As in the FP64 kernel, every lane of a wavefront works on
-// the same source at the same time.  FP64 records are read with scalar loads;
-// the FP32 records are staged through LDS TILE sources at a time with QUAD
-// (the quadrature's FP32 instructions issue faster with every operand in a
-// vector register) and read with scalar loads without it.
-// With QUAD, each source is first located in FP32 relative to its midpoint
+// the same source at the same time.  FP64 records are read with scalar loads.
+// QN = the source-quadrature points of the variant (0: none, 2 or 3).  With
+// QN > 0 the FP32 records are staged through LDS TILE sources at a time (the
+// quadrature's FP32 instructions issue faster with every operand in a vector
+// register) and each source is first located in FP32 relative to its midpoint
 // (positions split into FP32 high and low parts, so the offset carries no
 // rounding of the absolute coordinates): when, for every target point of the
-// wavefront, the midpoint lies at least max(30 L, cutoff + L/2) away, the
-// source is evaluated by FP32 2-point quadrature.  Other pairs get their
-// offset, axial and perpendicular parts in FP64: those closer than the cutoff
-// (minimum distance from the Gauss point to the closed source segment) are
-// evaluated in FP64, the rest by the cancellation-free FP32 closed form.  FP32
-// contributions are summed in FP32 over TILE sources at a time, then added to
-// FP64 sums; all sums are in units of k2 and scaled once at the end.
-template <bool QUAD>
+// wavefront, the midpoint lies outside the source's band (max(30 L, cutoff +
+// L/2) for 2 points, max(6 L, cutoff + L/2) for 3), the source is evaluated by
+// FP32 quadrature.  With QN = 0 the FP32 records are read with scalar loads.
+// Other pairs get their offset, axial and perpendicular parts in FP64: those
+// closer than the cutoff (minimum distance from the Gauss point to the closed
+// source segment) are evaluated in FP64, the rest by the cancellation-free
+// FP32 closed form.  FP32 contributions are summed in FP32 over TILE sources
+// at a time, then added to FP64 sums; all sums are in units of k2 and scaled
+// once at the end.
+template <int QN>
 __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ items,
                                                      const Tile *__restrict__ tiles,
                                                      const double *__restrict__ rec,
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                                                      float cut, double *__restrict__ partial,
                                                      unsigned long long *near_count)
 {
-    __shared__ f32x4 shr[QUAD ? TILE : 1][REC32A / 4];   // FP32 records of one stage of sources
+    __shared__ f32x4 shr[QN ? TILE : 1][REC32A / 4];   // FP32 records of one stage of sources
     __shared__ unsigned n_near_block, n_quad_block;
     const Item it = items[blockIdx.x];
     const Tile tl = tiles[it.tile];
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
     for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
         const int n = (int)min(it.src_end - base, (int64_t)TILE);
         float f0 = 0.f, f1 = 0.f, f2 = 0.f;
-        if (QUAD) {
+        if (QN) {
             __syncthreads();
             if (lane < n) {
                 const f32x4 *g4 = reinterpret_cast<const f32x4 *>(rf + (base + lane) * REC32A);
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
         for (int k = 0; k < n; ++k, s += REC32A) {
             const int64_t m = base + k;
             float r[REC32A];
-            if (QUAD) {
+            if (QN) {
                 // from LDS (broadcast reads): the FP32 quadrature then runs on
                 // vector-register operands, which issue faster than FP32
                 // instructions with a scalar operand
@@ -102,14 +104,17 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
 #pragma unroll
                 for (int f = 0; f < 8; ++f) r[16 + f] = vb[f];
             }
-            if (QUAD) {
+            if (QN) {
                 const float e0 = (xh0 - r[0]) + (xl0 - r[3]);
                 const float e1 = (xh1 - r[1]) + (xl1 - r[4]);
                 const float e2 = (xh2 - r[2]) + (xl2 - r[5]);
                 const float ee = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
                 if (__all(ee >= r[17])) {
                     ++n_quad_src;
-                    quad2_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2);
+                    if (QN == 2)
+                        quad2_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2);
+                    else
+                        quad3_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2);
                     continue;
                 }
             }
@@ -157,11 +162,15 @@ void launch_pair_mixed(const Item *items, const Tile *tiles, const double *rec, 
 {
     const double kr = k1 / k2, nu = 1.0 - 2.0 * kr;
     const double *ra = rec + (int64_t)REC64 * ns;
-    if (variant == 0)
-        hipLaunchKernelGGL(k_pair_mixed<true>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, ra,
+    const int qn = quad_points(variant);
+    if (qn == 2)
+        hipLaunchKernelGGL(k_pair_mixed<2>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, ra,
+                           rec32, ns, g, kr, nu, k2, cut, partial, counters);
+    else if (qn == 3)
+        hipLaunchKernelGGL(k_pair_mixed<3>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, ra,
                            rec32, ns, g, kr, nu, k2, cut, partial, counters);
     else
-        hipLaunchKernelGGL(k_pair_mixed<false>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, ra,
+        hipLaunchKernelGGL(k_pair_mixed<0>, dim3((unsigned)n_items), dim3(TILE), 0, st, items, tiles, rec, ra,
                            rec32, ns, g, kr, nu, k2, cut, partial, counters);
 }
 

@@ -66,7 +66,7 @@ def test_small_batch_mixed_vs_oracle():
     assert np.abs(rg - ro).max() / np.abs(ro).max() < 1e-4
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_small_batch_mixed_each_variant(variant):
     bt = _small_batch()
     dd.dd_set_plan(0, variant)

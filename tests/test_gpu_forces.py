@@ -71,12 +71,12 @@ def _oracle_100_loops():
     return _oracle_forces(W.subset(W.config1(), 100), 2)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 @pytest.mark.parametrize("chunk", [0, 256])
 def test_mixed_each_variant_and_split(variant, chunk):
-    """Both mixed-kernel variants (0: FP32 quadrature band, 1: none) and a
-    forced short source range, on several tiles with a ragged tail; variant 0
-    must actually take the quadrature branch here."""
+    """Every mixed-kernel variant (0: 2-point FP32 quadrature band, 1: none,
+    2: 3-point band) and a forced short source range, on several tiles with a
+    ragged tail; variants 0 and 2 must actually take the quadrature branch."""
     inst = W.subset(W.config1(), 100)
     ref = _oracle_100_loops()
     dd.dd_set_plan(chunk, variant)
@@ -91,7 +91,7 @@ def test_mixed_each_variant_and_split(variant, chunk):
     print(f"mixed variant {variant} chunk {chunk}: err {e:.2e}, items {items}, quad {quad}, near {near}")
     assert v == variant
     assert e < TOLMIX
-    assert (quad > 0) if variant == 0 else (quad == 0)
+    assert (quad > 0) if variant in (0, 2) else (quad == 0)
     if chunk:
         assert c == chunk
 
