@@ -135,14 +135,32 @@ struct PrepArgs {
     unsigned *flags;
 };
 
-__global__ void k_seg_prep(PrepArgs A)
+constexpr int PREP_BLOCK = 256;   // threads per workgroup of k_seg_prep
+
+__global__ __launch_bounds__(PREP_BLOCK) void k_seg_prep(PrepArgs A)
 {
-    int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    __shared__ int64_t sh_g1[PREP_BLOCK], sh_g2[PREP_BLOCK];
+    __shared__ int sh_inst[PREP_BLOCK];
+    __shared__ unsigned char sh_chain[PREP_BLOCK];
+    const int tid = threadIdx.x;
+    const int64_t s = blockIdx.x * (int64_t)PREP_BLOCK + tid;
     const int64_t ns = A.L.ns, nn = A.L.nn;
-    if (s >= ns) return;
+    const bool live = s < ns;
     unsigned fl = 0;
-    int64_t g1, g2;
-    if (!seg_ends(A.L, A.seg_nodes, s, g1, g2)) fl |= FLAG_BAD_INDEX;
+    int64_t g1 = -1, g2 = -1;
+    int inst = -1;
+    if (live) {
+        if (!seg_ends(A.L, A.seg_nodes, s, g1, g2)) fl |= FLAG_BAD_INDEX;
+        inst = seg_instance(A.L, s);
+    }
+    sh_g1[tid] = g1;
+    sh_g2[tid] = g2;
+    sh_inst[tid] = inst;
+    __syncthreads();
+    // does the next segment of this workgroup start at the node where this one ends?
+    sh_chain[tid] = live && tid + 1 < PREP_BLOCK && sh_inst[tid + 1] == inst && sh_g1[tid + 1] == g2;
+    __syncthreads();
+    if (!live) return;
     double x1[3], d[3], b[3], t[3], c[3];
     for (int k = 0; k < 3; ++k) {
         x1[k] = A.x[k * nn + g1] * A.inv_a;
@@ -167,21 +185,10 @@ __global__ void k_seg_prep(PrepArgs A)
     r[10 * ns + s] = c[0]; r[11 * ns + s] = c[1]; r[12 * ns + s] = c[2];
     // length of the run of segments starting here in which each next segment
     // starts at the node where the one before it ends (loops stored in order),
-    // capped at TILE: the all-pairs kernel computes the inverse distance to a
-    // shared node once per run
+    // within this workgroup's segments: the all-pairs kernel computes the
+    // inverse distance to a shared node once per run
     int run = 1;
-    {
-        const int inst = seg_instance(A.L, s);
-        const int64_t send = A.L.seg_off ? A.L.seg_off[inst + 1] : ns;
-        int64_t prev2 = g2;
-        while (run < TILE && s + run < send) {
-            int64_t q1, q2;
-            seg_ends(A.L, A.seg_nodes, s + run, q1, q2);
-            if (q1 != prev2) break;
-            prev2 = q2;
-            ++run;
-        }
-    }
+    while (tid + run < PREP_BLOCK && sh_chain[tid + run - 1]) ++run;
     r[13 * ns + s] = (double)run;
     {
         double *ra = r + (int64_t)REC64 * ns + s * RECA;
@@ -617,11 +624,14 @@ void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Pl
             total_tiles += (N * Q + TILE - 1) / TILE;
             max_src = std::max(max_src, N);
         }
-        const int64_t want_items = 2048;
+        // about 2048 work items; source ranges of at least MIN_CHUNK sources
+        // (small problems spread over many CUs), in whole TILEs above that
+        const int64_t want_items = 2048, MIN_CHUNK = 16;
         int64_t chunks = total_tiles > 0 ? (want_items + total_tiles - 1) / total_tiles : 1;
-        chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, (max_src + TILE - 1) / TILE));
+        chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, (max_src + MIN_CHUNK - 1) / MIN_CHUNK));
         chunk_len = (max_src + chunks - 1) / chunks;
-        chunk_len = std::max<int64_t>(TILE, (chunk_len + TILE - 1) / TILE * TILE);
+        const int64_t gran = chunk_len > TILE ? TILE : MIN_CHUNK;
+        chunk_len = std::max<int64_t>(MIN_CHUNK, (chunk_len + gran - 1) / gran * gran);
     }
     P.chunk_len = chunk_len;
     int64_t slot = 0;
@@ -812,7 +822,7 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         A.quadn = C.precision == DD_MIXED ? quad_points(C.variant) : 0;
         A.sys = C.sys;
         A.flags = ws->flags_dev;
-        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
+        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, PREP_BLOCK, INT32_MAX)), dim3(PREP_BLOCK), 0, st, A);
         if (C.n_items > 0) {
             timing_begin(st, ws->capturing);
             if (C.precision == DD_MIXED)
@@ -955,7 +965,7 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
         A.cut = C.cut;
         A.quadn = C.precision == DD_MIXED ? quad_points(C.variant) : 0;
         A.flags = ws->flags_dev;
-        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
+        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, PREP_BLOCK, INT32_MAX)), dim3(PREP_BLOCK), 0, st, A);
         double t_min = 1e300;
         for (int rep = 0; rep < reps; ++rep) {
             (void)hipEventRecord(e0, st);
@@ -1124,7 +1134,7 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
         A.inv_a = 1.0;
         A.rec64 = (double *)p;
         A.flags = ws->flags_dev;
-        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(n_segs, 256, INT32_MAX)), dim3(256), 0, st, A);
+        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(n_segs, PREP_BLOCK, INT32_MAX)), dim3(PREP_BLOCK), 0, st, A);
     }
     hipLaunchKernelGGL(k_glide<false>, dim3(grid_for(n_nodes, 256, INT32_MAX)), dim3(256), 0, st, L,
                        C.csr_ptr, C.csr_list, seg_nodes, normal, (const double *)nullptr, 1.0, x, force,
@@ -1226,7 +1236,7 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
         A.quadn = C.precision == DD_MIXED ? quad_points(C.variant) : 0;
         A.sys = C.sys;
         A.flags = ws->flags_dev;
-        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A);
+        hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, PREP_BLOCK, INT32_MAX)), dim3(PREP_BLOCK), 0, st, A);
         hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, st, C.L, 1, seg_nodes, C.rec64, C.sys,
                            (const double *)nullptr, pinned, volume, sigma_app, C.a, features_out);
     } else if (features_out) {
