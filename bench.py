@@ -94,7 +94,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true", help="skip mixed / Q=4 / burst extras")
     ap.add_argument("--burst-instances", type=int, default=512)
     ap.add_argument("--burst-steps", type=int, default=200)
-    ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy"], default=None,
+    ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy", "surrogate"], default=None,
                     help="profiling aid: run only one part (no JSON contract)")
     ap.add_argument("--surrogate-study", action="store_true",
                     help="run the surrogate speed-up-at-fixed-error study and write --study-out")
@@ -318,6 +318,24 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     mat = {"mu": W.MU, "nu": W.NU, "a": W.CORE_A, "B": W.DRAG_B}
+
+    if args.only == "surrogate":
+        # surrogate inference only: 1,048,576 points, 4-member ensemble
+        n_inf = 1 << 20
+        model = dd.SurrogateModel(4, 7)
+        feat = torch.tensor(np.random.default_rng(1).normal(size=(n_inf, 36)).astype(np.float32), device=dev)
+        for _ in range(args.warmup):
+            dd.dd_surrogate_rates(model, feat, 0.05)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dd.dd_surrogate_rates(model, feat, 0.05)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"part": "surrogate", "ms_per_call": t * 1e3,
+                          "tflops": 2.0 * MLP_MACS * 4 * n_inf / t / 1e12}))
+        model.close()
+        return
 
     if args.only == "copy":
         # plain copy of a known size, for scaling HBM counters
