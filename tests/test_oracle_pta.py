@@ -1,0 +1,94 @@
+"""Pins of the PTA-step oracle (oracle/pta.py) on the CPU: its running
+averages, state functions and control rules against independent
+computations and hand-worked cases."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import pta
+from paper_2005_02498_amd import workloads as W
+
+Q = 2
+
+
+def _tiny(seed=1_000_002, loops=2):
+    inst = W.subset(W.burst_instance(seed), loops)
+    inst.pinned[:] = 0
+    return inst
+
+
+def test_lp_from_rates_equals_direct_segment_sum():
+    """L^p = (1/V) sum_s b_s (x) (t_s x vbar_s) L_s, computed directly from the
+    oracle's velocities, equals sum_alpha gdot_alpha m_alpha (x) n_alpha built
+    from the burst routine's resolved rates: glide keeps t x v along n."""
+    inst = _tiny()
+    mat = W.material()
+    F = O.nodal_forces(inst.x, inst.seg_nodes, inst.burgers, inst.sigma_app, mat["mu"], mat["nu"],
+                       mat["a"], Q)
+    _, v = O.glide_step(inst.x, F, inst.seg_nodes, inst.normal, inst.pinned, mat["B"], W.DT)
+    Lp = np.zeros((3, 3))
+    for s in range(inst.n_segs):
+        n1, n2 = inst.seg_nodes[:, s]
+        d = inst.x[:, n2] - inst.x[:, n1]
+        L = np.linalg.norm(d)
+        vb = 0.5 * (v[:, n1] + v[:, n2])
+        Lp += np.outer(inst.burgers[:, s], np.cross(d / L, vb)) * L / inst.volume
+    _, rate, _ = O.burst(inst, mat, Q, 1, W.DT)
+    np.testing.assert_allclose(pta.lp_from_rates(rate), Lp, rtol=0, atol=1e-12 * np.abs(Lp).max())
+    assert np.abs(Lp).max() > 0
+
+
+def test_density_is_total_line_length_over_volume():
+    inst = _tiny()
+    _, _, feat = O.burst(inst, W.material(), Q, 1, W.DT)
+    d = inst.x[:, inst.seg_nodes[1]] - inst.x[:, inst.seg_nodes[0]]
+    rho = np.linalg.norm(d, axis=0).sum() / inst.volume
+    assert abs(feat[12:].sum() - rho) <= 1e-13 * rho
+
+
+def test_running_average_equals_one_long_burst():
+    """Chunked one-step accumulation (never converging) = the burst routine's
+    own average over the same steps, and the same final state."""
+    inst = _tiny()
+    mat = W.material()
+    P = pta.PTAParams(dt=W.DT, chunk=4, max_chunks=3, tol_rho=0.0, tol_lp=0.0)
+    run, checks = pta.fast_run(inst, inst.x, inst.sigma_app, mat, Q, P)
+    assert checks == 3 and run.steps == 12 and not run.converged
+    x, rate, _ = O.burst(inst, mat, Q, 12, W.DT)
+    np.testing.assert_allclose(run.sums[:12] / run.steps, rate, rtol=1e-12, atol=1e-12 * np.abs(rate).max())
+    np.testing.assert_allclose(run.x, x, rtol=0, atol=1e-9)
+
+
+def test_converged_rule_hand_cases():
+    assert pta.converged(1.0, 1.005, 1e-2, abs)
+    assert not pta.converged(1.0, 1.02, 1e-2, abs)
+    assert pta.converged(0.0, 0.0, 1e-2, abs)
+    a = np.eye(3)
+    assert pta.converged(a, 1.02 * a, 3e-2, np.linalg.norm)
+    assert not pta.converged(a, 1.05 * a, 3e-2, np.linalg.norm)
+
+
+def test_first_check_never_converges_and_loose_tolerance_stops_at_second():
+    inst = _tiny()
+    P = pta.PTAParams(dt=W.DT, chunk=3, max_chunks=5, tol_rho=10.0, tol_lp=10.0)
+    run, checks = pta.fast_run(inst, inst.x, inst.sigma_app, W.material(), Q, P)
+    assert run.converged and checks == 2 and run.steps == 6
+
+
+def test_pta_step_rules():
+    inst = _tiny()
+    mat = W.material()
+    rate6 = np.array([0, 0, 1e15, 0, 0, 0.0])          # Pa/s: 50 MPa reached at t = 5e-8 s
+    base = dict(dt=W.DT, chunk=3, max_chunks=3, delta=1e-8, tol_rho=1e-2, tol_lp=3e-2)
+    # no jump allowed to trigger
+    r = pta.pta_step(inst, 5e-8, rate6, mat, Q, pta.PTAParams(lpdot_max=np.inf, **base))
+    assert r["jumps"] == 0
+    nlp = np.linalg.norm(r["lp_b"])
+    assert r["h"] == pytest.approx(min(1.0, 0.002 / nlp), rel=1e-15)
+    np.testing.assert_allclose(r["lpdot"], (r["lp_b"] - r["lp_a"]) / 1e-8, rtol=1e-15)
+    assert np.linalg.norm(r["lp_a"]) <= nlp or r["rerun_chunks"] == 3
+    # every check a jump: exactly max_jumps restarts, the state moved on
+    r2 = pta.pta_step(inst, 5e-8, rate6, mat, Q, pta.PTAParams(lpdot_max=0.0, max_jumps=2, **base))
+    assert r2["jumps"] == 2
+    assert r2["steps_a"] >= 6 and r2["steps_b"] >= 6
+    assert np.abs(r2["x"] - r["x"]).max() > 0
