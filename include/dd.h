@@ -240,6 +240,76 @@ int dd_burst_batch(int32_t n_inst, const int64_t *node_off,
                    double near_cutoff_a, int n_steps, double dt,
                    double *rate_avg_out, double *features_out, void *stream);
 
+/* One slow-time step of Practical Time Averaging for a batch of independent
+ * DD volumes (Sec. "Application of PTA for coarse-graining DD simulation",
+ * subsection "Algorithm", steps 1-7).  Volume i is at slow time t[i] under
+ * the load l(t) = t * stress_rate[i] (a constant stress-rate tensor).  State
+ * functions: the line density rho (segments that belong to a slip system,
+ * length over volume) and the plastic distortion rate
+ * L^p = sum_alpha gdot_alpha m_alpha (x) n_alpha (gdot as dd_burst_batch;
+ * for glide motion this equals (1/V) sum_s b_s (x) (t_s x v_s) L_s).  Their
+ * running time averages R (Eq. R_lambda_t, equal fast steps) are advanced in
+ * chunks of chunk_steps fast steps and have converged when, from the second
+ * check on, |R - R at the previous check| <= tol |R| for rho (tol_rho) and
+ * for L^p (tol_lp, Frobenius norm); a fast run stops unconverged after
+ * max_chunks checks.
+ *  1. from the current microstructure, fast run at l(t - delta) -> R_a;
+ *  2. from the end state of 1, fast run at l(t) -> R_b;
+ *  3. Lpdot = (R_b^Lp - R_a^Lp) / delta;
+ *  4. if |Lpdot| > lpdot_max (a jump), 1-3 again from the end state of 2, at
+ *     most max_jumps times;
+ *  5. while |R_a^Lp| > |R_b^Lp|, the run of 1 continues from its own end
+ *     state one chunk at a time (at most max_chunks more);
+ *  6. Lpdot and rhodot = (R_b^rho - R_a^rho) / delta from the final values;
+ *     next slow step h = min(h_max, strain_step / |R_b^Lp|).
+ * x ends as the end state of step 2 (the microstructure for the next step).
+ * All instances advance together on the GPU; only those still running take
+ * fast steps.
+ * Arguments: node_off, seg_off HOST; x, seg_nodes, burgers, normal, pinned
+ *  (nullable) and volume device, as dd_burst_batch; stress_rate HOST
+ *  [n_inst][6] Voigt Pa/s; t HOST [n_inst] s; prm, m host; n_gauss,
+ *  precision, near_cutoff_a as dd_nodal_forces; out HOST
+ *  [n_inst][DD_PTA_OUT] doubles laid out by the DD_PTA_* indices below
+ *  (L^p row-major).  Synchronises the stream.
+ * Errors: DD_EINVAL for inconsistent offsets or parameters (dt, delta,
+ *  strain_step, h_max > 0; chunk_steps >= 1; max_chunks >= 2; tolerances
+ *  >= 0; max_jumps >= 0), otherwise as dd_burst_batch. */
+typedef struct {
+    double dt;            /* fast (DD) time step, s */
+    int32_t chunk_steps;  /* fast steps between convergence checks */
+    int32_t max_chunks;   /* checks before a fast run stops unconverged */
+    double tol_rho;       /* relative tolerance of R^rho (paper: 1e-2) */
+    double tol_lp;        /* relative tolerance of R^Lp (paper: 3e-2) */
+    double lpdot_max;     /* jump threshold on |Lpdot|, 1/s^2 (paper: 0.05) */
+    double delta;         /* slow-time interval, s (paper: 0.1) */
+    double strain_step;   /* step control: h |R_b^Lp| <= strain_step (paper: 0.002) */
+    double h_max;         /* largest slow step, s */
+    int32_t max_jumps;    /* restarts after jumps in one step */
+} dd_pta_params;
+
+#define DD_PTA_OUT 64
+#define DD_PTA_RHO_A 0    /* R^rho at t - delta */
+#define DD_PTA_RHO_B 1    /* R^rho at t */
+#define DD_PTA_G_A 2      /* [12] running averages of gdot_alpha at t - delta */
+#define DD_PTA_G_B 14     /* [12] ... at t */
+#define DD_PTA_LP_A 26    /* [9] R^Lp at t - delta */
+#define DD_PTA_LP_B 35    /* [9] R^Lp at t */
+#define DD_PTA_LPDOT 44   /* [9] Lpdot */
+#define DD_PTA_RHODOT 53  /* rhodot */
+#define DD_PTA_H 54       /* next slow step h */
+#define DD_PTA_STEPS_A 55 /* fast steps of the t - delta run (step 5 included) */
+#define DD_PTA_STEPS_B 56 /* fast steps of the t run */
+#define DD_PTA_CONV_A 57  /* 1 if the t - delta run converged */
+#define DD_PTA_CONV_B 58  /* 1 if the t run converged */
+#define DD_PTA_JUMPS 59   /* restarts taken in step 4 */
+#define DD_PTA_RERUN 60   /* chunks added in step 5 */
+
+int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                const int32_t *seg_nodes, const double *burgers, const double *normal,
+                const uint8_t *pinned, const double *volume, const double *stress_rate,
+                const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
+                int precision, double near_cutoff_a, double *out, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Slip-rate surrogate (not in the paper): a 4-member ensemble of MLPs     */
 /* 36 -> 256 -> 256 -> 256 -> 12, ReLU hidden layers, that maps the 36     */

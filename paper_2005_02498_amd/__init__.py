@@ -25,7 +25,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
     "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_plan", "dd_last_plan",
-    "dd_nodal_forces", "dd_glide_step", "dd_burst_batch",
+    "dd_nodal_forces", "dd_glide_step", "dd_burst_batch", "dd_pta_step",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
     "dd_surrogate_rates",
@@ -40,6 +40,22 @@ class DDError(RuntimeError):
 
 class Material(C.Structure):
     _fields_ = [("mu", C.c_double), ("nu", C.c_double), ("a", C.c_double), ("B", C.c_double)]
+
+
+class PTAParams(C.Structure):
+    """dd_pta_params (see dd.h); the paper's values are the defaults where it gives them."""
+    _fields_ = [("dt", C.c_double), ("chunk_steps", C.c_int32), ("max_chunks", C.c_int32),
+                ("tol_rho", C.c_double), ("tol_lp", C.c_double), ("lpdot_max", C.c_double),
+                ("delta", C.c_double), ("strain_step", C.c_double), ("h_max", C.c_double),
+                ("max_jumps", C.c_int32)]
+
+    def __init__(self, dt, chunk_steps=10, max_chunks=20, tol_rho=1e-2, tol_lp=3e-2, lpdot_max=0.05,
+                 delta=0.1, strain_step=0.002, h_max=1.0, max_jumps=2):
+        super().__init__(dt, chunk_steps, max_chunks, tol_rho, tol_lp, lpdot_max, delta, strain_step,
+                         h_max, max_jumps)
+
+
+DD_PTA_OUT = 64
 
 
 _lib = None
@@ -72,6 +88,10 @@ def _declare(L):
         "dd_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]),
         "dd_vector_peak": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), vp]),
+        "dd_pta_step": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp, vp, vp,
+                                  vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(PTAParams), C.POINTER(Material), C.c_int, C.c_int, dbl,
+                                  C.POINTER(C.c_double), vp]),
         "dd_set_plan": (C.c_int, [i64, C.c_int]),
         "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
                                       C.POINTER(Material), C.c_int, C.c_int, dbl, vp, vp]),
@@ -270,6 +290,41 @@ def dd_burst_batch(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sig
                                 int(n_gauss), _prec(precision), float(near_cutoff_a),
                                 int(n_steps), float(dt), pr, pfe, _stream(stream)))
     return rate_avg_out, features_out
+
+
+def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t,
+                params, mat, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0, stream=None):
+    """One PTA slow-time step for every instance (see dd.h); x advances to the
+    microstructure for the next step.  stress_rate [n_inst][6] (Pa/s) and t
+    [n_inst] (s) are host sequences.  Returns a dict of NumPy arrays."""
+    import numpy as np
+    no = (C.c_int64 * len(node_off))(*[int(v) for v in node_off])
+    so = (C.c_int64 * len(seg_off))(*[int(v) for v in seg_off])
+    n_inst = len(node_off) - 1
+    if len(seg_off) != n_inst + 1:
+        raise ValueError("node_off and seg_off must have the same length")
+    nn, ns = int(node_off[-1]), int(seg_off[-1])
+    px = _dev(x, torch.float64, (3, nn), "x")
+    psn = _dev(seg_nodes, torch.int32, (2, ns), "seg_nodes")
+    pb = _dev(burgers, torch.float64, (3, ns), "burgers")
+    pn = _dev(normal, torch.float64, (3, ns), "normal")
+    pp = _dev(pinned, torch.uint8, (nn,), "pinned", nullable=True)
+    pv = _dev(volume, torch.float64, (n_inst,), "volume")
+    sr = np.ascontiguousarray(stress_rate, dtype=np.float64).reshape(n_inst, 6)
+    tt = np.ascontiguousarray(t, dtype=np.float64).reshape(n_inst)
+    out = np.zeros((n_inst, DD_PTA_OUT))
+    m = _mat(mat)
+    dp = C.POINTER(C.c_double)
+    _check(lib().dd_pta_step(n_inst, no, so, px, psn, pb, pn, pp, pv, sr.ctypes.data_as(dp),
+                             tt.ctypes.data_as(dp), C.byref(params), C.byref(m), int(n_gauss),
+                             _prec(precision), float(near_cutoff_a), out.ctypes.data_as(dp),
+                             _stream(stream)))
+    return {"rho_a": out[:, 0], "rho_b": out[:, 1], "g_a": out[:, 2:14], "g_b": out[:, 14:26],
+            "lp_a": out[:, 26:35].reshape(n_inst, 3, 3), "lp_b": out[:, 35:44].reshape(n_inst, 3, 3),
+            "lpdot": out[:, 44:53].reshape(n_inst, 3, 3), "rhodot": out[:, 53], "h": out[:, 54],
+            "steps_a": out[:, 55].astype(int), "steps_b": out[:, 56].astype(int),
+            "conv_a": out[:, 57] > 0, "conv_b": out[:, 58] > 0, "jumps": out[:, 59].astype(int),
+            "rerun_chunks": out[:, 60].astype(int)}
 
 
 # --------------------------------------------------------------- surrogate --

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "dd.h"
 
@@ -52,6 +53,12 @@ enum Slot {
     WS_INST_OFFS,      // instance node and segment offsets
     WS_MISC,
     WS_PROBE,          // output of the vector-peak probe
+    WS_ACTIVE,         // per-instance active flags of a partial burst
+    WS_PTA_SIGMA,      // PTA driver: applied stress per instance
+    WS_PTA_SUMS,       //   per-chunk sums per instance
+    WS_PTA_XA,         //   saved positions (end of the t - Delta run)
+    WS_PTA_XB,         //   saved positions (end of the t run)
+    WS_PTA_MASK,       //   per-instance copy mask
     WS_NSLOTS
 };
 
@@ -133,6 +140,30 @@ constexpr int MIXED_VARIANTS = 3;
 inline __host__ __device__ int quad_points(int variant) { return variant == 0 ? 2 : (variant == 2 ? 3 : 0); }
 
 GaussRule gauss_rule(int n);
+
+// Glide steps of a batch of independent volumes in which only some instances
+// advance (the PTA driver's fast runs): burst_batch_init uploads the instance
+// tables and picks the work split (autotuner) once; each burst_batch_run
+// takes n_steps for the instances with active[i] != 0, each under its own
+// applied stress sigma_dev[6 i ..] (device, Voigt, Pa), and adds, per
+// instance, the sum over the steps of the 12 resolved slip rates and of the
+// line density to sums_dev[13 i ..] (device).  Idle instances keep their
+// positions.  The arrays stay owned by the caller.
+struct BurstBatch {
+    int n_inst = 0;
+    std::vector<int64_t> node_off, seg_off;   // host [n_inst + 1]
+    double *x = nullptr;
+    const int32_t *seg_nodes = nullptr;
+    const double *burgers = nullptr, *normal = nullptr, *volume = nullptr;
+    const uint8_t *pinned = nullptr;
+    dd_material mat{};
+    int n_gauss = 2, precision = DD_FP64;
+    double near_cut = 20.0, dt = 0.0;
+    int64_t choice = 0;                       // encoded work split, set by burst_batch_init
+};
+int burst_batch_init(BurstBatch &B, hipStream_t st);
+int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, const double *sigma_dev,
+                    int n_steps, double *sums_dev, hipStream_t st);
 
 // All-pairs launchers (one workgroup per work item, TILE threads).
 void launch_pair64(const Item *items, const Tile *tiles, const double *rec, int64_t ns, const GaussRule &g,

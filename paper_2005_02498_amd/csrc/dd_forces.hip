@@ -355,9 +355,11 @@ __global__ void k_segment_ends(Layout L, const Tile *__restrict__ tiles,
     const double ab1 = S[5] * b0 + S[1] * b1 + S[3] * b2;
     const double ab2 = S[4] * b0 + S[3] * b1 + S[2] * b2;
     double F1[3] = {0, 0, 0}, F2[3] = {0, 0, 0};
+    // an instance left out of the work plan (idle in this pass) has no tiles
+    const bool has_tiles = !L.tile_begin || L.tile_begin[inst + 1] > tb;
     for (int q = 0; q < Q; ++q) {
         const int64_t lp = lp0 + q;
-        const Tile T = tiles[tb + lp / TILE];
+        const Tile T = has_tiles ? tiles[tb + lp / TILE] : Tile{0, 0, 0, 0};
         const int lane = (int)(lp % TILE);
         double s0 = 0, s1 = 0, s2 = 0;
         for (int c = 0; c < T.n_chunks; ++c) {
@@ -415,11 +417,14 @@ __global__ void k_glide(Layout L, const int32_t *__restrict__ ptr, const int32_t
                         const int32_t *__restrict__ seg_nodes, const double *__restrict__ normal,
                         const double *__restrict__ rec, double a, double *x,
                         const double *__restrict__ F, const uint8_t *__restrict__ pinned,
-                        double invB, double dt, double *__restrict__ vel)
+                        const uint8_t *__restrict__ active, double invB, double dt,
+                        double *__restrict__ vel)
 {
     int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nn = L.nn, ns = L.ns;
     if (n >= nn) return;
+    // nodes of an idle instance (active[instance] == 0) do not move
+    const bool idle = active && ptr[n + 1] > ptr[n] && !active[seg_instance(L, list[ptr[n]] >> 1)];
     double ell = 0.0;
     double nrm[3][3];
     int cnt = 0;
@@ -448,7 +453,7 @@ __global__ void k_glide(Layout L, const int32_t *__restrict__ ptr, const int32_t
         }
     }
     double v0 = 0, v1 = 0, v2 = 0;
-    const bool fixed = (pinned && pinned[n]) || !(ell > 0.0) || cnt == 0 || cnt >= 3;
+    const bool fixed = idle || (pinned && pinned[n]) || !(ell > 0.0) || cnt == 0 || cnt >= 3;
     if (!fixed) {
         const double sc = invB / ell;
         v0 = F[n] * sc;
@@ -489,9 +494,11 @@ __global__ void k_euler(int64_t nn, double *x, const double *__restrict__ vel, d
 }
 
 // ---------------------------------------------- a7: slip-rate accumulation --
-// One workgroup per instance; 12 sums per lane, reduced in a fixed tree order
-// and added to acc[inst][12].  mode 0: gdot_alpha(k) from velocities;
-// mode 1: features (resolved shear, mobile and sessile densities).
+// One workgroup per instance; per-lane sums reduced in a fixed tree order.
+// mode 0: gdot_alpha(k) from velocities, added to out[inst][12]; mode 1:
+// features (resolved shear, mobile and sessile densities) written to
+// out[inst][36]; mode 2: gdot_alpha(k) and the line density of the segments
+// that belong to a slip system, added to out[inst][13].
 __global__ __launch_bounds__(256) void k_instance_sums(Layout L, int mode,
                                                        const int32_t *__restrict__ seg_nodes,
                                                        const double *__restrict__ rec,
@@ -516,7 +523,8 @@ __global__ __launch_bounds__(256) void k_instance_sums(Layout L, int mode,
         double n[3], m[3];
         fcc(al, n, m);
         const double Ls = rec[6 * ns + s] * a;
-        if (mode == 0) {
+        if (mode == 2) acc[12] += Ls * invV;
+        if (mode == 0 || mode == 2) {
             int64_t g1, g2;
             seg_ends(L, seg_nodes, s, g1, g2);
             const double t0 = rec[3 * ns + s], t1 = rec[4 * ns + s], t2 = rec[5 * ns + s];
@@ -539,7 +547,7 @@ __global__ __launch_bounds__(256) void k_instance_sums(Layout L, int mode,
                 }
         }
     }
-    const int nv = mode == 0 ? 12 : 24;
+    const int nv = mode == 0 ? 12 : (mode == 2 ? 13 : 24);
     for (int k = 0; k < nv; ++k) red[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -550,6 +558,8 @@ __global__ __launch_bounds__(256) void k_instance_sums(Layout L, int mode,
     if (threadIdx.x == 0) {
         if (mode == 0) {
             for (int k = 0; k < 12; ++k) out[12 * inst + k] += red[k][0];
+        } else if (mode == 2) {
+            for (int k = 0; k < 13; ++k) out[13 * inst + k] += red[k][0];
         } else {
             double S[3][3];
             const double *sv = sig_dev + 6 * inst;
@@ -611,7 +621,8 @@ struct Plan {
 };
 
 // chunk_len <= 0: choose so that a single large volume fills the chip.
-void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Plan &P)
+void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Plan &P,
+               const std::vector<uint8_t> *active = nullptr)
 {
     const int n_inst = (int)seg_off.size() - 1;
     P.tiles.clear();
@@ -620,6 +631,7 @@ void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Pl
     if (chunk_len <= 0) {
         int64_t total_tiles = 0, max_src = 0;
         for (int i = 0; i < n_inst; ++i) {
+            if (active && !(*active)[i]) continue;
             int64_t N = seg_off[i + 1] - seg_off[i];
             total_tiles += (N * Q + TILE - 1) / TILE;
             max_src = std::max(max_src, N);
@@ -638,6 +650,7 @@ void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Pl
     for (int i = 0; i < n_inst; ++i) {
         const int64_t s0 = seg_off[i], N = seg_off[i + 1] - s0;
         P.tile_begin[i] = (int64_t)P.tiles.size();
+        if (active && !(*active)[i]) continue;   // an idle instance gets no tiles
         const int64_t npts = N * Q;
         const int nchunks = N > 0 ? (int)((N + chunk_len - 1) / chunk_len) : 0;
         for (int64_t pb = 0; pb < npts; pb += TILE) {
@@ -705,11 +718,12 @@ struct ForceCtx {
 // Cache of the last uploaded plan (the tables depend only on sizes).
 struct PlanKey {
     std::vector<int64_t> seg_off;
+    std::vector<uint8_t> active;   // empty: every instance
     int Q = 0;
     int64_t chunk_len = -1;
     bool operator==(const PlanKey &o) const
     {
-        return Q == o.Q && chunk_len == o.chunk_len && seg_off == o.seg_off;
+        return Q == o.Q && chunk_len == o.chunk_len && seg_off == o.seg_off && active == o.active;
     }
 };
 PlanKey g_plan_key;   // guarded by the single-caller-per-device rule
@@ -720,7 +734,8 @@ int g_last_variant = 0;
 
 int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, int64_t nn,
           const int32_t *seg_nodes, const dd_material *m, int n_gauss, int precision,
-          double near_cut, int64_t chunk_len, bool need_sys, ForceCtx &C)
+          double near_cut, int64_t chunk_len, bool need_sys, ForceCtx &C,
+          const std::vector<uint8_t> *active = nullptr)
 {
     const int64_t ns = seg_off_h.back();
     const int n_inst = (int)seg_off_h.size() - 1;
@@ -761,9 +776,10 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
     key.seg_off = seg_off_h;
     key.Q = n_gauss;
     key.chunk_len = chunk_len;
+    if (active) key.active = *active;
     if (!(key == g_plan_key) || g_plan_dev != ws->device || !ws->ptr[WS_TILES]) {
         Plan P;
-        make_plan(seg_off_h, n_gauss, chunk_len, P);
+        make_plan(seg_off_h, n_gauss, chunk_len, P, active);
         Tile *dt;
         Item *di;
         int64_t *dtb;
@@ -779,7 +795,7 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
     }
     C.tiles = (Tile *)ws->ptr[WS_TILES];
     C.items = (Item *)ws->ptr[WS_ITEMS];
-    C.L.tile_begin = n_inst > 1 ? (const int64_t *)ws->ptr[WS_OFFS] : nullptr;
+    C.L.tile_begin = n_inst > 1 || active ? (const int64_t *)ws->ptr[WS_OFFS] : nullptr;
     C.n_items = g_plan_items;
     if ((rc = ensure(ws, WS_PARTIAL, sizeof(double) * 3 * TILE * std::max<int64_t>(C.n_items, 1), &p)))
         return rc;
@@ -1016,6 +1032,94 @@ int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, d
 }
 
 }  // namespace
+
+// ------------------------------------------------ bursts of an active subset --
+int burst_batch_init(BurstBatch &B, hipStream_t st)
+{
+    int rc;
+    const int n_inst = B.n_inst;
+    const int64_t nn = B.node_off[n_inst], ns = B.seg_off[n_inst];
+    Workspace *ws;
+    if ((rc = workspace(&ws))) return rc;
+    std::vector<int32_t> si((size_t)std::max<int64_t>(ns, 1), 0);
+    for (int i = 0; i < n_inst; ++i)
+        for (int64_t s = B.seg_off[i]; s < B.seg_off[i + 1]; ++s) si[s] = i;
+    int32_t *d_si;
+    if ((rc = upload(ws, WS_SEG_INST, si, &d_si, st))) return rc;
+    std::vector<int64_t> offs(B.node_off);
+    offs.insert(offs.end(), B.seg_off.begin(), B.seg_off.end());
+    int64_t *d_offs;
+    if ((rc = upload(ws, WS_INST_OFFS, offs, &d_offs, st))) return rc;
+    Layout inst{};
+    inst.seg_inst = d_si;
+    inst.node_off = d_offs;
+    inst.seg_off = d_offs + (n_inst + 1);
+    return tuned_chunk(ws, st, B.seg_off, nn, inst, B.seg_nodes, B.x, B.burgers, B.normal, &B.mat, B.n_gauss,
+                       B.precision, B.near_cut, true, &B.choice);
+}
+
+int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, const double *sigma_dev,
+                    int n_steps, double *sums_dev, hipStream_t st)
+{
+    int rc;
+    const int n_inst = B.n_inst;
+    const int64_t nn = B.node_off[n_inst], ns = B.seg_off[n_inst];
+    if (n_steps <= 0 || ns == 0) return DD_OK;
+    bool any = false;
+    for (int i = 0; i < n_inst; ++i) any = any || (active[i] && B.seg_off[i + 1] > B.seg_off[i]);
+    if (!any) return DD_OK;
+    Workspace *ws;
+    if ((rc = workspace(&ws))) return rc;
+    ForceCtx C;
+    if ((rc = setup(ws, st, B.seg_off, nn, B.seg_nodes, &B.mat, B.n_gauss, B.precision, B.near_cut,
+                    B.choice / MIXED_VARIANTS, true, C, &active)))
+        return rc;
+    C.variant = (int)(B.choice % MIXED_VARIANTS);
+    g_last_variant = C.variant;
+    C.L.seg_inst = (const int32_t *)ws->ptr[WS_SEG_INST];
+    C.L.node_off = (const int64_t *)ws->ptr[WS_INST_OFFS];
+    C.L.seg_off = C.L.node_off + (n_inst + 1);
+    uint8_t *d_act;
+    if ((rc = upload(ws, WS_ACTIVE, active, &d_act, st))) return rc;
+    void *p;
+    if ((rc = ensure(ws, WS_VEL, sizeof(double) * 3 * std::max<int64_t>(nn, 1), &p))) return rc;
+    double *vel = (double *)p;
+    if ((rc = ensure(ws, WS_FORCE, sizeof(double) * 3 * std::max<int64_t>(nn, 1), &p))) return rc;
+    double *F = (double *)p;
+    launch_csr(C, B.seg_nodes, st);
+    DD_HIP(hipGetLastError());
+    if (!ws->capture_stream) DD_HIP(hipStreamCreateWithFlags(&ws->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = ws->capture_stream;   // records the steps; the graph then runs on st
+    DD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    ws->capturing = true;
+    const Sig6 sv{};
+    for (int k = 0; k < n_steps; ++k) {
+        launch_forces(C, ws, B.x, B.seg_nodes, B.burgers, B.normal, sigma_dev, sv, F, cs);
+        hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L, C.csr_ptr,
+                           C.csr_list, B.seg_nodes, B.normal, C.rec64, C.a, B.x, F, B.pinned,
+                           (const uint8_t *)d_act, 1.0 / B.mat.B, B.dt, vel);
+        hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 2, B.seg_nodes, C.rec64, C.sys,
+                           vel, B.pinned, B.volume, sigma_dev, C.a, sums_dev);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    ws->capturing = false;
+    if (e != hipSuccess) return set_error(DD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return set_error(DD_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    e = hipGraphLaunch(exec, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return set_error(DD_EHIP, "graph launch failed: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return set_error(DD_EHIP, "burst execution failed: %s", hipGetErrorString(e2));
+    return DD_OK;
+}
+
 }  // namespace dd
 
 using namespace dd;
@@ -1138,7 +1242,7 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
     }
     hipLaunchKernelGGL(k_glide<false>, dim3(grid_for(n_nodes, 256, INT32_MAX)), dim3(256), 0, st, L,
                        C.csr_ptr, C.csr_list, seg_nodes, normal, (const double *)nullptr, 1.0, x, force,
-                       pinned, 1.0 / m->B, dt, vel);
+                       pinned, (const uint8_t *)nullptr, 1.0 / m->B, dt, vel);
     hipLaunchKernelGGL(k_euler, dim3(grid_for(3 * n_nodes, 256, INT32_MAX)), dim3(256), 0, st, n_nodes, x,
                        vel, dt);
     DD_HIP(hipGetLastError());
@@ -1255,7 +1359,7 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
             launch_forces(C, ws, x, seg_nodes, burgers, normal, sigma_app, sv, F, cs);
             hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
                                C.csr_ptr, C.csr_list, seg_nodes, normal, C.rec64, C.a, x, F, pinned,
-                               1.0 / m->B, dt, vel);
+                               (const uint8_t *)nullptr, 1.0 / m->B, dt, vel);
             hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 0, seg_nodes, C.rec64,
                                C.sys, vel, pinned, volume, sigma_app, C.a, rate_avg_out);
         }
