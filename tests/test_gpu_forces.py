@@ -207,6 +207,43 @@ def test_invalid_inputs_raise():
     assert torch.isfinite(F).all()
 
 
+def test_size_limits_rejected():
+    """Sizes beyond the index ranges (2^31 nodes, 2^30 segments) fail before
+    any device work."""
+    import ctypes as C
+    inst = W.subset(W.config0(), 1)
+    d = dev(inst)
+    sig = (C.c_double * 6)(*inst.sigma_app)
+    m = dd._mat(MAT)
+    F = torch.empty_like(d["x"])
+    p = [C.c_void_p(t.data_ptr()) for t in (d["x"], d["seg_nodes"], d["burgers"], d["normal"], F)]
+    for nn, ns in ((2 ** 31, inst.n_segs), (inst.n_nodes, 2 ** 30)):
+        rc = dd.lib().dd_nodal_forces(nn, p[0], ns, p[1], p[2], p[3], sig, C.byref(m), 2, 0, 20.0, p[4], None)
+        assert rc == -1, rc
+        assert "2^31" in dd.dd_last_error() or "2^30" in dd.dd_last_error()
+
+
+@pytest.mark.parametrize("shift", [1e5, 1e6])
+def test_mixed_far_from_origin(shift):
+    """Forces do not depend on where the volume sits; the mixed path locates
+    quadrature pairs from FP32 high/low parts of the positions, so a shift of
+    10^5-10^6 b (FP32 spacing 0.008-0.06 b) costs it nothing."""
+    inst = W.subset(W.config1(), 64)
+    ref = _gpu_forces(inst, 2)
+    moved = W.Instance(inst.x + shift, inst.seg_nodes, inst.burgers, inst.normal, inst.pinned,
+                       inst.sigma_app, inst.volume)
+    dd.dd_set_plan(0, 0)
+    try:
+        dd.dd_timing_read(reset=True)
+        g = _gpu_forces(moved, 2, dd.DD_MIXED)
+        quad = dd.dd_timing_read(reset=True)[3]
+    finally:
+        dd.dd_set_plan(-1)
+    e = normwise(g, ref)
+    print(f"shift {shift:g}: mixed vs unshifted fp64 err {e:.2e}, quadrature evaluations {quad}")
+    assert e < 1e-5
+
+
 def test_validation_off_is_same_result():
     inst = W.subset(W.config1(), 20)
     a = _gpu_forces(inst, 2)
