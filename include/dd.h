@@ -117,10 +117,10 @@ int dd_set_autotune(int on);
 /* Fix the work split instead of letting the autotuner (or its heuristic)
  * choose it, for reproducible benchmarks and for tests of each kernel
  * variant: chunk_len = source-range length of a work item (0: the built-in
- * heuristic, else at least 256), variant = the mixed kernel's variant (see
+ * heuristic, else at least 16), variant = the mixed kernel's variant (see
  * dd_last_plan).  chunk_len < 0 returns to the automatic choice.  Applies to
  * every later force evaluation in the process.  DD_EINVAL for a chunk_len in
- * 1..255 or a variant other than 0, 1 and 2. */
+ * 1..15 or a variant other than 0, 1 and 2. */
 int dd_set_plan(int64_t chunk_len, int variant);
 
 /* The work split of the most recent force evaluation on this device: the

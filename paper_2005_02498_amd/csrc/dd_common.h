@@ -137,6 +137,8 @@ constexpr int REC32A = 24;
 // max(6 L, cutoff + L/2).  A work split is encoded as MIXED_VARIANTS *
 // (source-range length) + variant.
 constexpr int MIXED_VARIANTS = 3;
+// shortest source range of a work item
+constexpr int MIN_CHUNK_LEN = 16;
 inline __host__ __device__ int quad_points(int variant) { return variant == 0 ? 2 : (variant == 2 ? 3 : 0); }
 
 GaussRule gauss_rule(int n);

@@ -636,12 +636,17 @@ void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Pl
             total_tiles += (N * Q + TILE - 1) / TILE;
             max_src = std::max(max_src, N);
         }
-        // about 2048 work items; source ranges of at least MIN_CHUNK sources
-        // (small problems spread over many CUs), in whole TILEs above that
-        const int64_t want_items = 2048, MIN_CHUNK = 16;
+        // at least about 2048 work items; source ranges of at least MIN_CHUNK
+        // sources (small problems spread over many CUs), in whole TILEs above
+        // that, and no longer than max(512, N_max / 16): the largest items set
+        // the tail of the schedule, and splitting them further costs only
+        // partial sums (on many bursts or one very large volume this is 7-12 %
+        // faster than one range per tile)
+        const int64_t want_items = 2048, MIN_CHUNK = MIN_CHUNK_LEN;
         int64_t chunks = total_tiles > 0 ? (want_items + total_tiles - 1) / total_tiles : 1;
         chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, (max_src + MIN_CHUNK - 1) / MIN_CHUNK));
         chunk_len = (max_src + chunks - 1) / chunks;
+        chunk_len = std::min<int64_t>(chunk_len, std::max<int64_t>(512, (max_src + 15) / 16));
         const int64_t gran = chunk_len > TILE ? TILE : MIN_CHUNK;
         chunk_len = std::max<int64_t>(MIN_CHUNK, (chunk_len + gran - 1) / gran * gran);
     }
@@ -949,7 +954,8 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
     }
     // a choice is encoded as MIXED_VARIANTS * chunk_length + mixed-kernel variant
     std::vector<int64_t> chunks = {0};
-    for (int64_t c = TILE; c < nmax; c *= 2) chunks.push_back(c);
+    // short ranges spread small batches over more CUs; long ones need fewer partial sums
+    for (int64_t c = 64; c < nmax; c *= 2) chunks.push_back(c);
     chunks.push_back(((nmax + TILE - 1) / TILE) * TILE);   // one range per tile
     std::vector<int64_t> cands;
     for (int64_t c : chunks)
@@ -1133,8 +1139,8 @@ extern "C" int dd_set_plan(int64_t chunk_len, int variant)
         dd::g_forced_choice.store(-1);
         return DD_OK;
     }
-    if (chunk_len != 0 && chunk_len < TILE)
-        return dd::set_error(DD_EINVAL, "chunk_len must be 0 (heuristic) or at least %d", TILE);
+    if (chunk_len != 0 && chunk_len < MIN_CHUNK_LEN)
+        return dd::set_error(DD_EINVAL, "chunk_len must be 0 (heuristic) or at least %d", MIN_CHUNK_LEN);
     if (variant < 0 || variant >= MIXED_VARIANTS) return dd::set_error(DD_EINVAL, "variant must be 0, 1 or 2");
     dd::g_forced_choice.store(MIXED_VARIANTS * chunk_len + variant);
     return DD_OK;

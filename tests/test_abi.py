@@ -48,7 +48,7 @@ def test_host_only_calls_without_gpu():
     prev = dd.dd_set_validation(False)
     assert dd.dd_set_validation(prev) is False
     assert isinstance(dd.dd_last_error(), str)
-    for bad in ((100, 0), (0, 3), (256, -1)):
+    for bad in ((8, 0), (0, 3), (256, -1)):
         with pytest.raises(dd.DDError):
             dd.dd_set_plan(*bad)
     dd.dd_set_plan(-1)
