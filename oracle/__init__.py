@@ -73,6 +73,9 @@ def _setup(L):
     L.ddo_segment_end_forces.argtypes = [C.c_int64, _dp, C.c_int64, _ip, _dp, _dp,
                                          C.POINTER(Material), C.c_int, C.c_int64,
                                          C.c_int64, _dp]
+    L.ddo_pair_exact.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
+                                 C.c_double, _dp, _dp]
+    L.ddo_set_exact_band.argtypes = [C.c_double]
     L.ddo_glide_step.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _ip, _dp, _up,
                                  C.POINTER(Material), C.c_double, _dp]
     L.ddo_fcc_system.argtypes = [C.c_int, _dp, _dp]
@@ -144,6 +147,35 @@ def segment_stress_quad(x, x1, x2, b, mu, nu, a, n=64, panels=64):
     x, px = _d(x); x1, p1 = _d(x1); x2, p2 = _d(x2); b, pb = _d(b)
     lib().ddo_segment_stress_quad(px, p1, p2, pb, mu, nu, a, n, panels, out.ctypes.data_as(_dp))
     return out.reshape(3, 3)
+
+
+def pair_exact(xa, xb, bj, y1, y2, bi, mu, nu, a):
+    """(F1, F2): what source y1 -> y2 sends to the two nodes of target xa -> xb,
+    with the target integral taken exactly (adaptive quadrature)."""
+    F1 = np.zeros(3); F2 = np.zeros(3)
+    xa, p0 = _d(xa); xb, p1 = _d(xb); bj, p2 = _d(bj); y1, p3 = _d(y1); y2, p4 = _d(y2); bi, p5 = _d(bi)
+    _check(lib().ddo_pair_exact(p0, p1, p2, p3, p4, p5, mu, nu, a, F1.ctypes.data_as(_dp),
+                                F2.ctypes.data_as(_dp)), "pair_exact")
+    return F1, F2
+
+
+def set_exact_band(eta: float):
+    """Process-wide exact band of every later force call (0 = Q-point rule only)."""
+    _check(lib().ddo_set_exact_band(float(eta)), "set_exact_band")
+
+
+class exact_band:
+    """Context manager: the exact band eta inside, 0 again on exit."""
+
+    def __init__(self, eta):
+        self.eta = eta
+
+    def __enter__(self):
+        set_exact_band(self.eta)
+        return self
+
+    def __exit__(self, *exc):
+        set_exact_band(0.0)
 
 
 def fcc_system(alpha: int):

@@ -14,7 +14,10 @@
  *    integrated in closed form along the straight segment;
  *  - the Peach-Koehler force df_k = eps_kjm sigma_ji b_i dl_m (Sec. 2.1);
  *  - Q-point Gauss-Legendre quadrature of that force against the linear shape
- *    functions of each segment, scattered to its two nodes;
+ *    functions of each segment, scattered to its two nodes; optionally, for
+ *    pairs inside a band around the target (the exact band, set by
+ *    ddo_set_exact_band), the same integral along the target taken exactly
+ *    (adaptive quadrature to rounding level) instead;
  *  - the glide-constrained linear mobility (velocity weak form, Eq. DD_evol:
  *    scalar drag, lumped, no-climb by projection onto the glide plane) and the
  *    forward-Euler node update (Sec. 2.1);
@@ -230,6 +233,166 @@ void ddo_segment_stress_quad(const double x[3], const double x1[3], const double
 }
 
 /* ------------------------------------------------------------------------- */
+/* Exact target integral of one pair.  Target segment xa -> xb (length Lt,   */
+/* unit tangent t, Burgers vector bj), source segment y1 -> y2 (Burgers bi). */
+/* What the source sends to the target's two nodes is                       */
+/*   F1 = Lt int_0^1 (1 - u) f(u) du,   F2 = Lt int_0^1 u f(u) du,           */
+/*   f(u) = (sigma^i(xa + u (xb - xa)) bj) x t                               */
+/* (the Peach-Koehler force of Sec. 2.1 against the linear shape functions), */
+/* i.e. the Q-point rule of the nodal-force routine with Q -> infinity.      */
+/* Computed by globally adaptive bisection: each panel carries its 10-point  */
+/* Gauss-Legendre value and the sum over its two halves; the difference of  */
+/* the two is its error estimate and the sum its value.  The panel with the  */
+/* largest estimate is split until the estimates add up to at most 1e-14     */
+/* times the largest integrand component seen on a 65-point sample of        */
+/* [0, 1], or 2048 panels are reached (only the integrand's own rounding     */
+/* noise, a few 1e-15 of its scale or 1e-13 for a target on the source's own  */
+/* line, keeps the estimates from shrinking further).                        */
+/* ------------------------------------------------------------------------- */
+#define DDO_EXACT_N 10
+
+typedef struct {
+    double xa[3], d[3], t[3], bj[3], Lt;
+    double y1[3], y2[3], bi[3];
+    double mu, nu, a;
+    double s[DDO_EXACT_N], w[DDO_EXACT_N];
+} ddo_pair_ctx;
+
+/* out[0..2] = (1 - u) f(u), out[3..5] = u f(u) */
+static void pair_integrand(const ddo_pair_ctx *P, double u, double out[6])
+{
+    double xq[3] = { P->xa[0] + u*P->d[0], P->xa[1] + u*P->d[1], P->xa[2] + u*P->d[2] };
+    double sg[9], sb[3], f[3];
+    ddo_segment_stress(xq, P->y1, P->y2, P->bi, P->mu, P->nu, P->a, sg);
+    for (int r = 0; r < 3; ++r) sb[r] = sg[3*r]*P->bj[0] + sg[3*r + 1]*P->bj[1] + sg[3*r + 2]*P->bj[2];
+    cross3(sb, P->t, f);
+    for (int r = 0; r < 3; ++r) {
+        out[r] = (1.0 - u) * f[r];
+        out[3 + r] = u * f[r];
+    }
+}
+
+static void pair_panel(const ddo_pair_ctx *P, double lo, double hi, double out[6])
+{
+    for (int k = 0; k < 6; ++k) out[k] = 0.0;
+    for (int g = 0; g < DDO_EXACT_N; ++g) {
+        double v[6];
+        pair_integrand(P, lo + P->s[g] * (hi - lo), v);
+        for (int k = 0; k < 6; ++k) out[k] += P->w[g] * (hi - lo) * v[k];
+    }
+}
+
+#define DDO_EXACT_MAXP 2048
+
+typedef struct { double lo, hi, whole[6], value[6], err; } ddo_panel;
+
+/* fills value and err of a panel whose lo, hi and whole are set */
+static void pair_refine(const ddo_pair_ctx *P, ddo_panel *q)
+{
+    double mid = 0.5 * (q->lo + q->hi), left[6], right[6];
+    pair_panel(P, q->lo, mid, left);
+    pair_panel(P, mid, q->hi, right);
+    q->err = 0.0;
+    for (int k = 0; k < 6; ++k) {
+        q->value[k] = left[k] + right[k];
+        q->err = fmax(q->err, fabs(q->value[k] - q->whole[k]));
+    }
+}
+
+int ddo_pair_exact(const double xa[3], const double xb[3], const double bj[3],
+                   const double y1[3], const double y2[3], const double bi[3],
+                   double mu, double nu, double a, double F1[3], double F2[3])
+{
+    ddo_pair_ctx P;
+    for (int r = 0; r < 3; ++r) {
+        P.xa[r] = xa[r];
+        P.d[r] = xb[r] - xa[r];
+        P.bj[r] = bj[r];
+        P.y1[r] = y1[r];
+        P.y2[r] = y2[r];
+        P.bi[r] = bi[r];
+    }
+    P.Lt = sqrt(dot3(P.d, P.d));
+    if (!(P.Lt > 0.0)) return -1;
+    for (int r = 0; r < 3; ++r) P.t[r] = P.d[r] / P.Lt;
+    P.mu = mu; P.nu = nu; P.a = a;
+    ddo_gauss_legendre(DDO_EXACT_N, P.s, P.w);
+    double scale = 0.0;
+    for (int k = 0; k <= 64; ++k) {
+        double v[6];
+        pair_integrand(&P, k / 64.0, v);
+        for (int c = 0; c < 6; ++c) scale = fmax(scale, fabs(v[c]));
+    }
+    double acc[6] = {0};
+    if (scale > 0.0) {
+        ddo_panel *pan = (ddo_panel *)malloc(sizeof(ddo_panel) * DDO_EXACT_MAXP);
+        if (!pan) return -1;
+        int np = 1;
+        pan[0].lo = 0.0;
+        pan[0].hi = 1.0;
+        pair_panel(&P, 0.0, 1.0, pan[0].whole);
+        pair_refine(&P, &pan[0]);
+        for (;;) {
+            double total = 0.0;
+            int worst = 0;
+            for (int k = 0; k < np; ++k) {
+                total += pan[k].err;
+                if (pan[k].err > pan[worst].err) worst = k;
+            }
+            if (total <= 1e-14 * scale || np + 1 > DDO_EXACT_MAXP) break;
+            /* split the worst panel: its halves become panels of their own */
+            ddo_panel *q = &pan[worst], *r = &pan[np++];
+            double mid = 0.5 * (q->lo + q->hi);
+            r->lo = mid;
+            r->hi = q->hi;
+            pair_panel(&P, mid, q->hi, r->whole);
+            q->hi = mid;
+            pair_panel(&P, q->lo, mid, q->whole);
+            pair_refine(&P, q);
+            pair_refine(&P, r);
+        }
+        for (int k = 0; k < np; ++k)
+            for (int c = 0; c < 6; ++c) acc[c] += pan[k].value[c];
+        free(pan);
+    }
+    for (int r = 0; r < 3; ++r) {
+        F1[r] = P.Lt * acc[r];
+        F2[r] = P.Lt * acc[3 + r];
+    }
+    return 0;
+}
+
+/* The exact band: a pair (target j, source i) is near when                  */
+/*   |S_i - S_j|^2 < 2 eta^2 (|D_i|^2 + |D_j|^2),                            */
+/* S = x1 + x2 (twice the midpoint), D = x2 - x1, i.e. when the midpoints are */
+/* closer than eta sqrt((L_i^2 + L_j^2)/2).  Near pairs take the exact       */
+/* target integral above, all others the Q-point rule.  eta = 0 (the         */
+/* default) takes the Q-point rule everywhere.  The products and sums are    */
+/* written out in this order so that the decision is reproducible exactly.  */
+static double g_exact_c2 = 0.0;   /* 2 eta^2 */
+
+int ddo_set_exact_band(double eta)
+{
+    if (!(eta >= 0.0) || isinf(eta)) return -1;
+    g_exact_c2 = 2.0 * eta * eta;
+    return 0;
+}
+
+static int near_pair(const double *xa, const double *xb, const double *y1, const double *y2)
+{
+    if (!(g_exact_c2 > 0.0)) return 0;
+    double e0 = (y1[0] + y2[0]) - (xa[0] + xb[0]);
+    double e1 = (y1[1] + y2[1]) - (xa[1] + xb[1]);
+    double e2 = (y1[2] + y2[2]) - (xa[2] + xb[2]);
+    double di0 = y2[0] - y1[0], di1 = y2[1] - y1[1], di2 = y2[2] - y1[2];
+    double dj0 = xb[0] - xa[0], dj1 = xb[1] - xa[1], dj2 = xb[2] - xa[2];
+    double dd = e0*e0 + e1*e1 + e2*e2;
+    double Di = di0*di0 + di1*di1 + di2*di2;
+    double Dj = dj0*dj0 + dj1*dj1 + dj2*dj2;
+    return dd < g_exact_c2 * (Di + Dj);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Nodal forces: for every target segment j and Gauss point q,               */
 /*   sigma(x_jq) = sigma_app + sum_{i != j} sigma^i(x_jq)  (sources in order) */
 /*   f_jq = (sigma b_j) x t_j                      (Peach-Koehler, Sec. 2.1) */
@@ -266,6 +429,7 @@ static int ddo_forces_impl(int64_t n_nodes, const double *x, int64_t n_segs,
                 if (i == j && !include_self) continue;
                 int32_t c1 = N1[i], c2 = N2[i];
                 double y1[3] = { X[c1], Y[c1], Z[c1] }, y2[3] = { X[c2], Y[c2], Z[c2] };
+                if (near_pair(xa, xb, y1, y2)) continue;
                 double bi[3] = { burgers[i], burgers[n_segs + i], burgers[2*n_segs + i] };
                 double sg[9];
                 ddo_segment_stress(xq, y1, y2, bi, m->mu, m->nu, m->a, sg);
@@ -279,6 +443,20 @@ static int ddo_forces_impl(int64_t n_nodes, const double *x, int64_t n_segs,
             for (int r = 0; r < 3; ++r) {
                 force_out[r*n_nodes + a1] += w1 * f[r];
                 force_out[r*n_nodes + a2] += w2 * f[r];
+            }
+        }
+        /* near pairs: the exact target integral */
+        for (int64_t i = 0; i < n_segs && g_exact_c2 > 0.0; ++i) {
+            if (i == j && !include_self) continue;
+            int32_t c1 = N1[i], c2 = N2[i];
+            double y1[3] = { X[c1], Y[c1], Z[c1] }, y2[3] = { X[c2], Y[c2], Z[c2] };
+            if (!near_pair(xa, xb, y1, y2)) continue;
+            double bi[3] = { burgers[i], burgers[n_segs + i], burgers[2*n_segs + i] };
+            double F1[3], F2[3];
+            if (ddo_pair_exact(xa, xb, bj, y1, y2, bi, m->mu, m->nu, m->a, F1, F2)) return -1;
+            for (int r = 0; r < 3; ++r) {
+                force_out[r*n_nodes + a1] += F1[r];
+                force_out[r*n_nodes + a2] += F2[r];
             }
         }
     }
@@ -353,6 +531,7 @@ int ddo_segment_end_forces(int64_t n_nodes, const double *x, int64_t n_segs,
                 if (i == j) continue;
                 int32_t c1 = N1[i], c2 = N2[i];
                 double y1[3] = { X[c1], Y[c1], Z[c1] }, y2[3] = { X[c2], Y[c2], Z[c2] };
+                if (near_pair(xa, xb, y1, y2)) continue;
                 double bi[3] = { burgers[i], burgers[n_segs + i], burgers[2*n_segs + i] };
                 double sg[9];
                 ddo_segment_stress(xq, y1, y2, bi, m->mu, m->nu, m->a, sg);
@@ -365,6 +544,19 @@ int ddo_segment_end_forces(int64_t n_nodes, const double *x, int64_t n_segs,
             for (int r = 0; r < 3; ++r) {
                 o[r]     += L * w[g] * (1.0 - s[g]) * f[r];
                 o[3 + r] += L * w[g] * s[g] * f[r];
+            }
+        }
+        for (int64_t i = 0; i < n_segs && g_exact_c2 > 0.0; ++i) {
+            if (i == j) continue;
+            int32_t c1 = N1[i], c2 = N2[i];
+            double y1[3] = { X[c1], Y[c1], Z[c1] }, y2[3] = { X[c2], Y[c2], Z[c2] };
+            if (!near_pair(xa, xb, y1, y2)) continue;
+            double bi[3] = { burgers[i], burgers[n_segs + i], burgers[2*n_segs + i] };
+            double F1[3], F2[3];
+            if (ddo_pair_exact(xa, xb, bj, y1, y2, bi, m->mu, m->nu, m->a, F1, F2)) return -1;
+            for (int r = 0; r < 3; ++r) {
+                o[r] += F1[r];
+                o[3 + r] += F2[r];
             }
         }
     }
