@@ -65,6 +65,7 @@ extern "C" {
 #define DD_EHIP       (-2)   /* a HIP runtime call failed                 */
 #define DD_ENOMEM     (-3)   /* device workspace allocation failed        */
 #define DD_ENONFINITE (-4)   /* a NaN or Inf reached an output            */
+#define DD_ECAPACITY  (-5)   /* a fixed-size device list ran out of room  */
 
 #define DD_MAX_GAUSS  16
 #define DD_N_SYSTEMS  12
@@ -113,6 +114,29 @@ int dd_shutdown(void);
  * the choice beyond the order of floating-point sums.  Returns the previous
  * setting. */
 int dd_set_autotune(int on);
+
+/* Exact band.  The nodal force a source segment i sends to target segment j
+ * is L_j int_0^1 N(u) (sigma^i(x_j(u)) b_j) x t_j du for the two linear shape
+ * functions N (the Peach-Koehler force of Sec. "Discrete Dislocation
+ * Dynamics" integrated along the target).  By default every pair takes the
+ * n_gauss-point Gauss-Legendre rule for this integral.  With eta > 0, pairs
+ * whose midpoints are closer than eta sqrt((L_i^2 + L_j^2)/2), i.e. with
+ * S = x1 + x2 and D = x2 - x1,
+ *     |S_i - S_j|^2 < 2 eta^2 (|D_i|^2 + |D_j|^2)
+ * (evaluated in float64 without fused multiply-adds, in this order, on the
+ * caller's positions), take the integral exactly instead (to ~1e-14 of the
+ * pair's contribution: 12-point Gauss-Legendre on panels graded towards the
+ * integrand's complex singularities).  This removes the quadrature error of
+ * a small n_gauss on adjacent and close segments (several per cent of the
+ * net self-force of an irregular loop at n_gauss = 2); eta = 2 to 4 selects
+ * about 4 to 16 near sources per segment in dislocation loops.  The self pair
+ * is never included.  Process-wide: applies to every later call of
+ * dd_nodal_forces, dd_burst_batch and dd_pta_step, with either precision
+ * (the correction is always float64).  eta = 0 (the default) turns it off.
+ * Limits: at most 64 near sources per segment and 32 per segment on average,
+ * else the force call returns DD_ECAPACITY; at most 33,554,431 segments.
+ * DD_EINVAL for a negative or non-finite eta. */
+int dd_set_exact_band(double eta);
 
 /* Fix the work split instead of letting the autotuner (or its heuristic)
  * choose it, for reproducible benchmarks and for tests of each kernel

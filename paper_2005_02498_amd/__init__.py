@@ -24,7 +24,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
-    "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_plan", "dd_last_plan",
+    "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_exact_band", "dd_set_plan", "dd_last_plan",
     "dd_nodal_forces", "dd_glide_step", "dd_burst_batch", "dd_pta_step",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -93,6 +93,7 @@ def _declare(L):
                                   C.POINTER(PTAParams), C.POINTER(Material), C.c_int, C.c_int, dbl,
                                   C.POINTER(C.c_double), vp]),
         "dd_set_plan": (C.c_int, [i64, C.c_int]),
+        "dd_set_exact_band": (C.c_int, [C.c_double]),
         "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
                                       C.POINTER(Material), C.c_int, C.c_int, dbl, vp, vp]),
         "dd_glide_step": (C.c_int, [i64, vp, vp, i64, vp, vp, vp, C.POINTER(Material), dbl,
@@ -183,6 +184,12 @@ def dd_last_error() -> str:
 
 def dd_set_autotune(on: bool) -> bool:
     return bool(lib().dd_set_autotune(1 if on else 0))
+
+
+def dd_set_exact_band(eta: float = 0.0):
+    """Exact target integral for pairs with midpoints closer than
+    eta*sqrt((Li^2+Lj^2)/2); 0 turns it off.  Process-wide; see dd.h."""
+    _check(lib().dd_set_exact_band(float(eta)))
 
 
 def dd_set_plan(chunk_len: int = -1, variant: int = 0):

@@ -31,6 +31,8 @@ enum : unsigned {
     FLAG_ZERO_LENGTH = 2u,
     FLAG_BAD_NORMAL = 4u,
     FLAG_NONFINITE = 8u,
+    FLAG_NEAR_FULL = 16u,     // a near-pair list or the pair store ran out of room
+    FLAG_NEAR_PANELS = 32u,   // an exact-band integral needed more panels than allowed
 };
 
 // -------------------------------------------------------------- workspace --
@@ -59,6 +61,13 @@ enum Slot {
     WS_PTA_XA,         //   saved positions (end of the t - Delta run)
     WS_PTA_XB,         //   saved positions (end of the t run)
     WS_PTA_MASK,       //   per-instance copy mask
+    WS_NEAR_KEY,       // exact band: per-segment keys
+    WS_NEAR_GRP,       //   per-group spheres
+    WS_NEAR_LIST,      //   per-target near sources
+    WS_NEAR_IDX,       //   per-target counts, in-wavefront offsets, first pair
+    WS_NEAR_WAVE,      //   per-wavefront totals and their prefix
+    WS_NEAR_PAIR,      //   flat (target, source) pairs
+    WS_NEAR_CORR,      //   per-pair end-force corrections
     WS_NSLOTS
 };
 
@@ -142,6 +151,34 @@ constexpr int MIN_CHUNK_LEN = 16;
 inline __host__ __device__ int quad_points(int variant) { return variant == 0 ? 2 : (variant == 2 ? 3 : 0); }
 
 GaussRule gauss_rule(int n);
+
+// Exact band (dd_set_exact_band): near-pair lists and the exact target
+// integrals of those pairs, as corrections to the Q-point end forces.
+constexpr int NEAR_CAP = 64;   // near sources kept per target segment
+constexpr int NEAR_AVG = 32;   // pair storage per segment (the mean near count may not exceed it)
+struct NearArgs {
+    int64_t ns = 0, nn = 0, n_waves = 0, pair_cap = 0;
+    const int32_t *seg_inst = nullptr;   // device [ns] or null (one volume)
+    const int64_t *seg_off = nullptr;    // device [n_inst + 1] or null
+    const int64_t *node_off = nullptr;   // device [n_inst + 1] or null
+    const int32_t *seg_nodes = nullptr;
+    const double *x = nullptr;           // positions, caller's units
+    const double *rec = nullptr;         // FP64 segment records (lengths in units of a)
+    double c2 = 0.0;                     // 2 eta^2
+    double kr = 0.0, nu = 0.0, k2 = 0.0;
+    GaussRule g{}, gp{};                 // the Q-point rule and the 12-point panel rule
+    double *key = nullptr;               // [ns][4]
+    double *grp = nullptr;               // [n_waves][4]
+    int32_t *list = nullptr;             // [ns][NEAR_CAP]
+    int32_t *cnt = nullptr, *loc = nullptr, *ptr = nullptr;   // [ns] each
+    int32_t *wtot = nullptr, *woff = nullptr;                 // [n_waves], [n_waves + 1]
+    int32_t *pair_t = nullptr, *pair_s = nullptr;             // [pair_cap] each
+    double *corr = nullptr;                                   // [pair_cap][6]
+    unsigned *flags = nullptr;
+};
+void launch_near(const NearArgs &A, hipStream_t st);
+// 2 eta^2 of the current exact band (0: off)
+double exact_band_c2();
 
 // Glide steps of a batch of independent volumes in which only some instances
 // advance (the PTA driver's fast runs): burst_batch_init uploads the instance

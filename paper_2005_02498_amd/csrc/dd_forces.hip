@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "dd_common.h"
+#include "dd_scan.h"
 
 namespace dd {
 
@@ -257,46 +258,6 @@ __global__ void k_csr_count(Layout L, const int32_t *seg_nodes, int32_t *cnt)
     atomicAdd(&cnt[g2], 1);
 }
 
-// Exclusive scan of cnt[0..n) into ptr[0..n] by one workgroup of 1024
-// threads, 4096 counts per round: each thread takes 4 consecutive counts,
-// wavefront prefix sums by shuffles, the 16 wavefront totals through LDS, and
-// a running carry from round to round.
-__global__ __launch_bounds__(1024) void k_scan(const int32_t *cnt, int64_t n, int32_t *ptr)
-{
-    __shared__ int32_t wsum[16];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    int32_t carry = 0;
-    for (int64_t base = 0; base < n; base += 4096) {
-        const int64_t i0 = base + 4 * (int64_t)tid;
-        int32_t v[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = (i0 + k < n) ? cnt[i0 + k] : 0;
-        const int32_t t = v[0] + v[1] + v[2] + v[3];
-        int32_t s = t;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int32_t u = __shfl_up(s, off, 64);
-            if (lane >= off) s += u;
-        }
-        if (lane == 63) wsum[w] = s;
-        __syncthreads();
-        int32_t before = carry, total = carry;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            before += k < w ? wsum[k] : 0;
-            total += wsum[k];
-        }
-        int32_t run = before + s - t;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (i0 + k < n) ptr[i0 + k] = run;
-            run += v[k];
-        }
-        carry = total;
-        __syncthreads();
-    }
-    if (tid == 0) ptr[n] = carry;
-}
 
 __global__ void k_csr_fill(Layout L, const int32_t *seg_nodes, const int32_t *ptr,
                            int32_t *cursor, int32_t *list)
@@ -336,7 +297,9 @@ __global__ void k_segment_ends(Layout L, const Tile *__restrict__ tiles,
                                const double *__restrict__ partial,
                                const double *__restrict__ rec, GaussRule g,
                                const double *__restrict__ sig_dev, Sig6 sig_val,
-                               double inv_mu, double fscale, double *__restrict__ segF)
+                               double inv_mu, double fscale, double *__restrict__ segF,
+                               const int32_t *__restrict__ near_ptr, const int32_t *__restrict__ near_cnt,
+                               const double *__restrict__ near_corr, int64_t pair_cap)
 {
     int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t ns = L.ns;
@@ -378,6 +341,16 @@ __global__ void k_segment_ends(Layout L, const Tile *__restrict__ tiles,
         const double w1 = Ls * g.w[q] * (1.0 - g.s[q]), w2 = Ls * g.w[q] * g.s[q];
         F1[0] += w1 * f0; F1[1] += w1 * f1; F1[2] += w1 * f2;
         F2[0] += w2 * f0; F2[1] += w2 * f1; F2[2] += w2 * f2;
+    }
+    // exact band: (exact - Q-point) for this target's near sources, in source order
+    if (near_ptr) {
+        const int64_t p0 = near_ptr[j];
+        const int nc = near_cnt[j];
+        for (int k = 0; k < nc && p0 + k < pair_cap; ++k) {
+            const double *o = near_corr + 6 * (p0 + k);
+            F1[0] += o[0]; F1[1] += o[1]; F1[2] += o[2];
+            F2[0] += o[3]; F2[1] += o[4]; F2[2] += o[5];
+        }
     }
     for (int k = 0; k < 3; ++k) {
         segF[k * ns + j] = F1[k] * fscale;
@@ -609,6 +582,10 @@ int read_flags(Workspace *ws, hipStream_t st)
     if (f & FLAG_ZERO_LENGTH) return set_error(DD_EINVAL, "zero-length (or non-finite) segment");
     if (f & FLAG_BAD_NORMAL) return set_error(DD_EINVAL, "slip-plane normal is not of unit length");
     if (f & FLAG_NONFINITE) return set_error(DD_ENONFINITE, "non-finite value in an output");
+    if (f & FLAG_NEAR_FULL)
+        return set_error(DD_ECAPACITY, "exact band: more than %d near sources for one segment, or more than %d "
+                         "per segment on average; use a narrower band", NEAR_CAP, NEAR_AVG);
+    if (f & FLAG_NEAR_PANELS) return set_error(DD_EINVAL, "exact band: a pair integral did not converge");
     return DD_OK;
 }
 
@@ -718,6 +695,8 @@ struct ForceCtx {
     int precision = DD_FP64;
     int variant = 0;   // mixed kernel: 0 = FP32 quadrature band test first, 1 = no quadrature
     float cut = 0.f;
+    bool near_on = false;   // exact band in use (positions, topology and layout are set per launch)
+    NearArgs near{};
 };
 
 // Cache of the last uploaded plan (the tables depend only on sizes).
@@ -806,6 +785,44 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
         return rc;
     C.partial = (double *)p;
     (void)seg_nodes;
+    const double c2 = exact_band_c2();
+    C.near_on = c2 > 0.0 && ns > 0;
+    if (C.near_on) {
+        if (ns > (int64_t)INT32_MAX / NEAR_CAP)
+            return set_error(DD_EINVAL, "the exact band supports at most %d segments", INT32_MAX / NEAR_CAP);
+        NearArgs &N = C.near;
+        N = NearArgs{};
+        N.ns = ns;
+        N.nn = nn;
+        N.n_waves = (ns + 63) / 64;
+        N.pair_cap = ns * NEAR_AVG;
+        N.c2 = c2;
+        N.kr = C.k1 / C.k2;
+        N.nu = m->nu;
+        N.k2 = C.k2;
+        N.g = C.g;
+        N.gp = gauss_rule(12);
+        N.rec = C.rec64;
+        N.flags = ws->flags_dev;
+        if ((rc = ensure(ws, WS_NEAR_KEY, sizeof(double) * 4 * ns, &p))) return rc;
+        N.key = (double *)p;
+        if ((rc = ensure(ws, WS_NEAR_GRP, sizeof(double) * 4 * N.n_waves, &p))) return rc;
+        N.grp = (double *)p;
+        if ((rc = ensure(ws, WS_NEAR_LIST, sizeof(int32_t) * NEAR_CAP * ns, &p))) return rc;
+        N.list = (int32_t *)p;
+        if ((rc = ensure(ws, WS_NEAR_IDX, sizeof(int32_t) * 3 * ns, &p))) return rc;
+        N.cnt = (int32_t *)p;
+        N.loc = N.cnt + ns;
+        N.ptr = N.loc + ns;
+        if ((rc = ensure(ws, WS_NEAR_WAVE, sizeof(int32_t) * (2 * N.n_waves + 1), &p))) return rc;
+        N.wtot = (int32_t *)p;
+        N.woff = N.wtot + N.n_waves;
+        if ((rc = ensure(ws, WS_NEAR_PAIR, sizeof(int32_t) * 2 * N.pair_cap, &p))) return rc;
+        N.pair_t = (int32_t *)p;
+        N.pair_s = N.pair_t + N.pair_cap;
+        if ((rc = ensure(ws, WS_NEAR_CORR, sizeof(double) * 6 * N.pair_cap, &p))) return rc;
+        N.corr = (double *)p;
+    }
     return DD_OK;
 }
 
@@ -816,7 +833,8 @@ void launch_csr(const ForceCtx &C, const int32_t *seg_nodes, hipStream_t st)
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nn)), dim3(256), 0, st, (unsigned *)C.csr_cnt, nn, 0u);
     hipLaunchKernelGGL(k_csr_count, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L, seg_nodes,
                        C.csr_cnt);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, C.csr_cnt, nn, C.csr_ptr);
+    hipLaunchKernelGGL((k_scan<int32_t>), dim3(1), dim3(1024), 0, st, (const int32_t *)C.csr_cnt, nn,
+                       C.csr_ptr);
     hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L, seg_nodes,
                        C.csr_ptr, C.csr_cnt, C.csr_list);
     hipLaunchKernelGGL(k_csr_sort, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, st, C.csr_ptr, nn,
@@ -844,6 +862,15 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         A.sys = C.sys;
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, PREP_BLOCK, INT32_MAX)), dim3(PREP_BLOCK), 0, st, A);
+        if (C.near_on) {
+            NearArgs N = C.near;
+            N.x = x;
+            N.seg_nodes = seg_nodes;
+            N.seg_inst = C.L.seg_inst;
+            N.seg_off = C.L.seg_off;
+            N.node_off = C.L.node_off;
+            launch_near(N, st);
+        }
         if (C.n_items > 0) {
             timing_begin(st, ws->capturing);
             if (C.precision == DD_MIXED)
@@ -855,7 +882,8 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         }
         hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
                            C.tiles, C.partial, C.rec64, C.g, sig_dev, sig_val, C.inv_mu, C.fscale,
-                           C.segF);
+                           C.segF, C.near_on ? (const int32_t *)C.near.ptr : nullptr,
+                           (const int32_t *)C.near.cnt, (const double *)C.near.corr, C.near.pair_cap);
     }
     hipLaunchKernelGGL(k_node_gather, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, st, C.csr_ptr,
                        C.csr_list, nn, ns, C.segF, F);
@@ -873,6 +901,7 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
 // caller's own data, and the fastest is kept for the process (and appended
 // to the file named by DD_AUTOTUNE_CACHE, read back at start-up).
 std::atomic<int> g_autotune{1};
+std::atomic<double> g_exact_c2{0.0};   // dd_set_exact_band: 2 eta^2
 std::atomic<int64_t> g_forced_choice{-1};   // dd_set_plan: encoded split, or -1
 
 struct TuneKey {
@@ -1000,7 +1029,8 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
             // items, so it is part of the cost being compared
             hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A.L,
                                C.tiles, C.partial, C.rec64, C.g, (const double *)nullptr, Sig6{}, C.inv_mu,
-                               C.fscale, C.segF);
+                               C.fscale, C.segF, (const int32_t *)nullptr, (const int32_t *)nullptr,
+                               (const double *)nullptr, (int64_t)0);
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) {
                 rc = set_error(DD_EHIP, "autotuner timing failed");
@@ -1038,6 +1068,8 @@ int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, d
 }
 
 }  // namespace
+
+double exact_band_c2() { return g_exact_c2.load(); }
 
 // ------------------------------------------------ bursts of an active subset --
 int burst_batch_init(BurstBatch &B, hipStream_t st)
@@ -1131,6 +1163,14 @@ int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, con
 using namespace dd;
 
 extern "C" int dd_set_autotune(int on) { return dd::g_autotune.exchange(on ? 1 : 0); }
+
+extern "C" int dd_set_exact_band(double eta)
+{
+    dd::clear_error();
+    if (!(eta >= 0.0) || std::isinf(eta)) return dd::set_error(DD_EINVAL, "eta must be finite and >= 0");
+    dd::g_exact_c2.store(2.0 * eta * eta);
+    return DD_OK;
+}
 
 extern "C" int dd_set_plan(int64_t chunk_len, int variant)
 {

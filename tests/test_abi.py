@@ -52,3 +52,7 @@ def test_host_only_calls_without_gpu():
         with pytest.raises(dd.DDError):
             dd.dd_set_plan(*bad)
     dd.dd_set_plan(-1)
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(dd.DDError):
+            dd.dd_set_exact_band(bad)
+    dd.dd_set_exact_band(0.0)

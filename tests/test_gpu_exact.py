@@ -1,0 +1,158 @@
+"""GPU parity of the exact band (dd_set_exact_band) against the oracle with the
+same band: near pairs take the exact target integral, all others the Q-point
+rule.  Tolerances as for the plain force path: FP64 1e-10, mixed 1e-4
+(normwise over nodes).  The near decision is the same arithmetic on both
+sides, so the same pairs are corrected."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2005_02498_amd import workloads as W
+import paper_2005_02498_amd as dd
+
+from gpu_util import MAT, batch_dev, dev, normwise
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOLMIX = 1e-10, 1e-4
+
+
+class band:
+    """The same exact band on the GPU library and in the oracle, 0 on exit."""
+
+    def __init__(self, eta):
+        self.eta = eta
+
+    def __enter__(self):
+        dd.dd_set_exact_band(self.eta)
+        O.set_exact_band(self.eta)
+
+    def __exit__(self, *exc):
+        dd.dd_set_exact_band(0.0)
+        O.set_exact_band(0.0)
+
+
+def _gpu(inst, Q=2, prec=dd.DD_FP64):
+    d = dev(inst)
+    F = dd.dd_nodal_forces(d["x"], d["seg_nodes"], d["burgers"], d["normal"], inst.sigma_app, MAT, Q, prec)
+    torch.cuda.synchronize()
+    return F.cpu().numpy()
+
+
+def _oracle(inst, Q=2):
+    return O.nodal_forces(inst.x, inst.seg_nodes, inst.burgers, inst.sigma_app, W.MU, W.NU, W.CORE_A, Q)
+
+
+@pytest.mark.parametrize("eta", [2.0, 4.0])
+@pytest.mark.parametrize("Q", [1, 2, 3])
+def test_config0_fp64(eta, Q):
+    inst = W.config0()
+    F_plain = _gpu(inst, Q)
+    with band(eta):
+        F = _gpu(inst, Q)
+        ref = _oracle(inst, Q)
+    e = normwise(F, ref)
+    moved = normwise(F_plain, ref)
+    print(f"config0 eta={eta} Q={Q}: err {e:.2e} (Q-point rule alone differs by {moved:.2e})")
+    assert e < TOL64
+    assert moved > 100 * TOL64   # the band changed the result
+
+
+@pytest.mark.parametrize("eta", [2.0, 4.0])
+def test_config0_mixed(eta):
+    inst = W.config0()
+    with band(eta):
+        e = normwise(_gpu(inst, 2, dd.DD_MIXED), _oracle(inst, 2))
+    print(f"config0 mixed eta={eta}: err {e:.2e}")
+    assert e < TOLMIX
+
+
+def test_multi_tile_ragged_fp64():
+    inst = W.subset(W.config1(), 37)
+    with band(3.0):
+        e = normwise(_gpu(inst, 2), _oracle(inst, 2))
+    print(f"37 loops eta=3: err {e:.2e}")
+    assert e < TOL64
+
+
+def test_full_volume_sampled_fp64():
+    """The 16,384-segment volume at full size; four whole loops by the oracle."""
+    inst = W.config1()
+    with band(2.0):
+        F = _gpu(inst, 2)
+        num = den = 0.0
+        for lp in (0, 101, 300, 511):
+            t0, t1 = 32 * lp, 32 * lp + 32
+            ref = O.nodal_forces_sampled(inst.x, inst.seg_nodes, inst.burgers, inst.sigma_app,
+                                         W.MU, W.NU, W.CORE_A, 2, t0, t1)[:, t0:t1]
+            num = max(num, np.linalg.norm(F[:, t0:t1] - ref, axis=0).max())
+            den = max(den, np.linalg.norm(ref, axis=0).max())
+    print(f"config1 full sampled eta=2: err {num / den:.2e}")
+    assert num / den < TOL64
+
+
+def test_closed_loop_net_force_vanishes_with_wide_band():
+    """Every pair of one irregular loop exact: no net self-force (the oracle's
+    pin, now on the GPU path)."""
+    rng = np.random.default_rng(3)
+    n = 32
+    ang = np.sort(rng.uniform(0, 2 * np.pi, n))
+    R = 300 * (1 + 0.3 * rng.uniform(-1, 1, n))
+    x = np.stack([R * np.cos(ang), R * np.sin(ang), 0.2 * R * np.cos(ang) + rng.uniform(-5, 5, n)])
+    sn = np.stack([np.arange(n), (np.arange(n) + 1) % n]).astype(np.int32)
+    b = np.tile((np.array([1.0, 1.0, 0.0]) / np.sqrt(2.0))[:, None], (1, n))
+    nrm = np.tile((np.array([1.0, -1.0, 1.0]) / np.sqrt(3.0))[:, None], (1, n))
+    d = torch.device("cuda:0")
+    args = (torch.tensor(x, device=d), torch.tensor(sn, device=d), torch.tensor(b, device=d),
+            torch.tensor(nrm, device=d), np.zeros(6), MAT, 2)
+    Fq = dd.dd_nodal_forces(*args).cpu().numpy()
+    with band(100.0):   # every pair of the loop (31 near sources per segment)
+        Fe = dd.dd_nodal_forces(*args).cpu().numpy()
+        ref = O.nodal_forces(x, sn, b, np.zeros(6), W.MU, W.NU, W.CORE_A, 2)
+    ratio_q = np.abs(Fq.sum(1)).max() / np.abs(Fq).sum(1).max()
+    ratio_e = np.abs(Fe.sum(1)).max() / np.abs(Fe).sum(1).max()
+    e = normwise(Fe, ref)
+    print(f"net force / total: Q-point {ratio_q:.2e}, all pairs exact {ratio_e:.2e}; err vs oracle {e:.2e}")
+    assert ratio_q > 1e-2
+    # zero up to the rounding of 32 x 31 pair integrals
+    assert ratio_e < 1e-10
+    assert e < TOL64
+
+
+def test_small_batch_bursts_fp64():
+    insts = [W.subset(W.burst_instance(1_000_010 + i), nl) for i, nl in enumerate((2, 3, 1))]
+    bt = W.pack(insts)
+    d = batch_dev(bt)
+    with band(2.0):
+        rate, _ = dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"], d["normal"],
+                                    d["pinned"], d["sigma_app"], d["volume"], MAT, 2, dd.DD_FP64, 20.0, 4, W.DT)
+        torch.cuda.synchronize()
+        xo, ro, _ = O.burst_batch(bt, W.material(), 2, 4, W.DT)
+    xg = d["x"].cpu().numpy()
+    e_x = normwise(xg - bt.x, xo - bt.x)
+    e_r = np.abs(rate.cpu().numpy() - ro).max() / np.abs(ro).max()
+    print(f"bursts eta=2: displacement err {e_x:.2e}, rate err {e_r:.2e}")
+    assert e_x < 1e-10 and e_r < 1e-10
+
+
+def test_deterministic_and_off_again():
+    inst = W.subset(W.config1(), 20)
+    F0 = _gpu(inst)
+    with band(3.0):
+        F1 = _gpu(inst)
+        F2 = _gpu(inst)
+    F3 = _gpu(inst)
+    assert np.array_equal(F1, F2)
+    assert np.array_equal(F0, F3)
+    assert not np.array_equal(F0, F1)
+
+
+def test_capacity_exceeded_is_an_error():
+    inst = W.config0()
+    with band(60.0):   # every one of the 255 other segments is near
+        with pytest.raises(dd.DDError) as ei:
+            _gpu(inst)
+        assert ei.value.code == -5
+    # a later call without the band is unaffected
+    assert normwise(_gpu(inst), _oracle(inst)) < TOL64
