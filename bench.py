@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--cpu-targets", type=int, default=4096,
                     help="target segments in the CPU oracle sample (0: skip)")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed / Q=4 / burst extras")
+    ap.add_argument("--exact-band", type=float, default=0.0,
+                    help="with --only fp64|mixed: exact target integral for pairs closer than this band")
     ap.add_argument("--burst-instances", type=int, default=512)
     ap.add_argument("--burst-steps", type=int, default=200)
     ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy", "surrogate"], default=None,
@@ -414,8 +416,11 @@ def main():
 
     if args.only in ("fp64", "mixed"):
         prec = dd.DD_FP64 if args.only == "fp64" else dd.DD_MIXED
+        dd.dd_set_exact_band(args.exact_band)
         s, k, _ = run(prec, 2, args.steps, args.warmup)
-        print(json.dumps({"part": args.only, "ms_per_step": s * 1e3, "kernel_ms": k * 1e3}))
+        dd.dd_set_exact_band(0.0)
+        print(json.dumps({"part": args.only, "exact_band": args.exact_band, "ms_per_step": s * 1e3,
+                          "kernel_ms": k * 1e3}))
         return
 
     out = {}
@@ -461,6 +466,28 @@ def main():
                                      "mixed_variant": bands[2]},
                             "roofline": {kk: r[kk] for kk in ("bound", "achieved", "peak", "unit", "frac",
                                                               "peak_measured", "frac_of_measured")}}
+        # exact band (exact target integral for pairs with midpoints closer than
+        # eta sqrt((Li^2 + Lj^2)/2)): cost over the plain Q = 2 step
+        K = np.concatenate([(inst.x[:, inst.seg_nodes[0]] + inst.x[:, inst.seg_nodes[1]]).T,
+                            (((inst.x[:, inst.seg_nodes[1]] - inst.x[:, inst.seg_nodes[0]]) ** 2).sum(0))[:, None]],
+                           axis=1)
+        for eta, prec, name in ((2.0, dd.DD_FP64, "exact_band_2_fp64_q2"), (4.0, dd.DD_FP64, "exact_band_4_fp64_q2"),
+                                (2.0, dd.DD_MIXED, "exact_band_2_mixed_q2")):
+            c2 = 2.0 * eta * eta
+            n_near = 0
+            for j0 in range(0, N, 256):
+                e = K[None, :, :3] - K[j0:j0 + 256, None, :3]
+                dd2 = e[..., 0] * e[..., 0] + e[..., 1] * e[..., 1] + e[..., 2] * e[..., 2]
+                n_near += int((dd2 < c2 * (K[None, :, 3] + K[j0:j0 + 256, None, 3])).sum()) - min(256, N - j0)
+            dd.dd_set_exact_band(eta)
+            try:
+                s_b, _, _ = run(prec, 2, max(5, args.steps // 2), 2)
+            finally:
+                dd.dd_set_exact_band(0.0)
+            base = step_s if prec == dd.DD_FP64 else extras["mixed_q2"]["ms_per_step"] / 1e3
+            extras[name] = {"eta": eta, "near_pairs_per_step": n_near, "ms_per_step": s_b * 1e3,
+                            "plain_ms_per_step": base * 1e3, "overhead_ms": (s_b - base) * 1e3,
+                            "ns_per_near_pair": (s_b - base) * 1e9 / max(n_near, 1)}
         # the 262,144-segment volume (radii 50-2000 b, 50,000 b cube): one step per precision
         big = W.config3()
         vb = resident(big)

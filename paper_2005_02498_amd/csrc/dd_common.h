@@ -62,7 +62,7 @@ enum Slot {
     WS_PTA_XB,         //   saved positions (end of the t run)
     WS_PTA_MASK,       //   per-instance copy mask
     WS_NEAR_KEY,       // exact band: per-segment keys
-    WS_NEAR_GRP,       //   per-group spheres
+    WS_NEAR_SPH,       //   per-group bounding spheres
     WS_NEAR_LIST,      //   per-target near sources
     WS_NEAR_IDX,       //   per-target counts, in-wavefront offsets, first pair
     WS_NEAR_WAVE,      //   per-wavefront totals and their prefix
@@ -78,6 +78,8 @@ struct Workspace {
     unsigned *flags_dev = nullptr;   // one word
     unsigned *flags_host = nullptr;  // pinned mirror
     hipStream_t capture_stream = nullptr;
+    hipStream_t side_stream = nullptr;           // exact band, overlapping the pair kernel
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     unsigned long long *near_count = nullptr;   // device counter (mixed kernel)
     bool capturing = false;
 };
@@ -156,8 +158,10 @@ GaussRule gauss_rule(int n);
 // integrals of those pairs, as corrections to the Q-point end forces.
 constexpr int NEAR_CAP = 64;   // near sources kept per target segment
 constexpr int NEAR_AVG = 32;   // pair storage per segment (the mean near count may not exceed it)
+constexpr int NEAR_GROUP = 8;  // consecutive segments per bounding sphere of the near search
 struct NearArgs {
     int64_t ns = 0, nn = 0, n_waves = 0, pair_cap = 0;
+    int splits = 1;                      // source ranges per target (workgroups along y)
     const int32_t *seg_inst = nullptr;   // device [ns] or null (one volume)
     const int64_t *seg_off = nullptr;    // device [n_inst + 1] or null
     const int64_t *node_off = nullptr;   // device [n_inst + 1] or null
@@ -168,8 +172,9 @@ struct NearArgs {
     double kr = 0.0, nu = 0.0, k2 = 0.0;
     GaussRule g{}, gp{};                 // the Q-point rule and the 12-point panel rule
     double *key = nullptr;               // [ns][4]
-    double *grp = nullptr;               // [n_waves][4]
-    int32_t *list = nullptr;             // [ns][NEAR_CAP]
+    float4 *sph = nullptr;               // [ceil(ns / NEAR_GROUP)] sphere centre, radius
+    int32_t *list = nullptr;             // [ns][splits][NEAR_CAP]
+    int32_t *scnt = nullptr;             // [ns][splits] kept per split
     int32_t *cnt = nullptr, *loc = nullptr, *ptr = nullptr;   // [ns] each
     int32_t *wtot = nullptr, *woff = nullptr;                 // [n_waves], [n_waves + 1]
     int32_t *pair_t = nullptr, *pair_s = nullptr;             // [pair_cap] each

@@ -806,14 +806,23 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
         N.flags = ws->flags_dev;
         if ((rc = ensure(ws, WS_NEAR_KEY, sizeof(double) * 4 * ns, &p))) return rc;
         N.key = (double *)p;
-        if ((rc = ensure(ws, WS_NEAR_GRP, sizeof(double) * 4 * N.n_waves, &p))) return rc;
-        N.grp = (double *)p;
-        if ((rc = ensure(ws, WS_NEAR_LIST, sizeof(int32_t) * NEAR_CAP * ns, &p))) return rc;
+        if ((rc = ensure(ws, WS_NEAR_SPH, sizeof(float4) * ((ns + NEAR_GROUP - 1) / NEAR_GROUP), &p))) return rc;
+        N.sph = (float4 *)p;
+        // split the source range of an instance over several workgroups when
+        // the targets alone give fewer than ~4096 wavefronts: at least 64
+        // source groups per split, at most 32 splits
+        int64_t max_inst = 0;
+        for (size_t i = 0; i + 1 < seg_off_h.size(); ++i) max_inst = std::max(max_inst, seg_off_h[i + 1] - seg_off_h[i]);
+        const int64_t groups = (max_inst + NEAR_GROUP - 1) / NEAR_GROUP;
+        const int64_t want = std::min<int64_t>((groups + 63) / 64, (262144 + ns - 1) / ns);
+        N.splits = (int)std::min<int64_t>(32, std::max<int64_t>(1, want));
+        if ((rc = ensure(ws, WS_NEAR_LIST, sizeof(int32_t) * NEAR_CAP * N.splits * ns, &p))) return rc;
         N.list = (int32_t *)p;
-        if ((rc = ensure(ws, WS_NEAR_IDX, sizeof(int32_t) * 3 * ns, &p))) return rc;
+        if ((rc = ensure(ws, WS_NEAR_IDX, sizeof(int32_t) * (3 + N.splits) * ns, &p))) return rc;
         N.cnt = (int32_t *)p;
         N.loc = N.cnt + ns;
         N.ptr = N.loc + ns;
+        N.scnt = N.ptr + ns;
         if ((rc = ensure(ws, WS_NEAR_WAVE, sizeof(int32_t) * (2 * N.n_waves + 1), &p))) return rc;
         N.wtot = (int32_t *)p;
         N.woff = N.wtot + N.n_waves;
@@ -822,6 +831,9 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
         N.pair_s = N.pair_t + N.pair_cap;
         if ((rc = ensure(ws, WS_NEAR_CORR, sizeof(double) * 6 * N.pair_cap, &p))) return rc;
         N.corr = (double *)p;
+        if (!ws->side_stream) DD_HIP(hipStreamCreateWithFlags(&ws->side_stream, hipStreamNonBlocking));
+        if (!ws->ev_fork) DD_HIP(hipEventCreateWithFlags(&ws->ev_fork, hipEventDisableTiming));
+        if (!ws->ev_join) DD_HIP(hipEventCreateWithFlags(&ws->ev_join, hipEventDisableTiming));
     }
     return DD_OK;
 }
@@ -863,13 +875,18 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, PREP_BLOCK, INT32_MAX)), dim3(PREP_BLOCK), 0, st, A);
         if (C.near_on) {
+            // the near-pair work needs only the records: it runs on a side
+            // stream, alongside the pair kernel, and joins before the epilogue
             NearArgs N = C.near;
             N.x = x;
             N.seg_nodes = seg_nodes;
             N.seg_inst = C.L.seg_inst;
             N.seg_off = C.L.seg_off;
             N.node_off = C.L.node_off;
-            launch_near(N, st);
+            (void)hipEventRecord(ws->ev_fork, st);
+            (void)hipStreamWaitEvent(ws->side_stream, ws->ev_fork, 0);
+            launch_near(N, ws->side_stream);
+            (void)hipEventRecord(ws->ev_join, ws->side_stream);
         }
         if (C.n_items > 0) {
             timing_begin(st, ws->capturing);
@@ -880,6 +897,7 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
                 launch_pair64(C.items, C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial, C.n_items, st);
             timing_end(st, ws->capturing);
         }
+        if (C.near_on) (void)hipStreamWaitEvent(st, ws->ev_join, 0);
         hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
                            C.tiles, C.partial, C.rec64, C.g, sig_dev, sig_val, C.inv_mu, C.fscale,
                            C.segF, C.near_on ? (const int32_t *)C.near.ptr : nullptr,

@@ -6,15 +6,17 @@
 // computes the difference (exact integral - Q-point rule) and the epilogue
 // adds it to the target's end forces.  Steps, all on the device so that the
 // force evaluation stays capturable in a graph:
-//   k_near_groups   per 64 consecutive segments: the keys (x1 + x2, |x2 - x1|^2,
-//                   physical units) and a bounding sphere of the group;
-//   k_near_list     one wavefront per 64 targets: source groups whose sphere
-//                   can hold a near pair are scanned and every target keeps
-//                   its near sources in increasing index order (at most
-//                   NEAR_CAP), with per-wavefront totals;
+//   k_near_keys     per segment its key (x1 + x2, |x2 - x1|^2, physical
+//                   units), per NEAR_GROUP consecutive segments a bounding
+//                   sphere;
+//   k_near_list     one thread per target and source split: source groups
+//                   whose sphere can hold a near pair are scanned and every
+//                   target keeps its near sources in increasing index order;
+//   k_near_count    per-target totals over the splits (at most NEAR_CAP) and
+//                   per-wavefront totals;
 //   k_scan          prefix of the per-wavefront totals;
 //   k_near_compact  one flat array of (target, source) pairs;
-//   k_near_exact    one thread per pair: the exact integral on panels graded
+//   k_near_exact    four lanes per pair: the exact integral on panels graded
 //                   towards the integrand's complex singularities, minus the
 //                   Q-point rule, as two end-force vectors.
 //
@@ -49,6 +51,7 @@ constexpr double ELLIPSE_IA2 = 1.0 / (2.6 * 2.6);   // 1/A^2, A = (5 + 1/5)/2
 constexpr double ELLIPSE_IB2 = 1.0 / (2.4 * 2.4);   // 1/B^2, B = (5 - 1/5)/2
 constexpr int PANEL_POINTS = 12;
 constexpr int MAX_PANELS = 256;
+constexpr int NEAR_CHUNK = 128;   // source groups (spheres and keys) staged in LDS at a time
 
 __device__ __forceinline__ int64_t inst_of(const NearArgs &A, int64_t s)
 {
@@ -95,16 +98,18 @@ __device__ __forceinline__ T wave_min(T v)
     return v;
 }
 
-// One wavefront per group of 64 consecutive segments (the last one may be
-// partial): keys, and a sphere (centre C = key of the group's first segment,
-// radius R = max |S_i - C| + sqrt(c2 |D_i|^2)) holding, for every segment of
-// the group, every point closer than the band allows.
-__global__ __launch_bounds__(256) void k_near_groups(NearArgs A)
+// One thread per segment: its key; the NEAR_GROUP lanes of a group (the last
+// one may be partial) then form the group's sphere (centre C = key of its
+// first segment, radius R = max |S_i - C| + sqrt(c2 |D_i|^2)), which holds
+// S_j of every segment j that can be near one of them, since near(i, j)
+// implies |S_i - S_j| < sqrt(c2 |D_i|^2) + sqrt(c2 |D_j|^2).  The sphere is
+// stored in FP32 with R widened by 4e-6 (|C|_1 + R), more than the rounding
+// of the FP32 test below can take away.
+__global__ __launch_bounds__(256) void k_near_keys(NearArgs A)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t g = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t s = g * 64 + lane;
-    if (g * 64 >= A.ns) return;   // whole wavefront
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63, first = lane & ~(NEAR_GROUP - 1);
+    if (s - (lane - first) >= A.ns) return;   // whole group past the end
     const bool live = s < A.ns;
     double k[4] = {0, 0, 0, 0};
     if (live) {
@@ -120,82 +125,142 @@ __global__ __launch_bounds__(256) void k_near_groups(NearArgs A)
         double *o = A.key + 4 * s;
         o[0] = k[0]; o[1] = k[1]; o[2] = k[2]; o[3] = k[3];
     }
-    const double c0 = __shfl(k[0], 0, 64), c1 = __shfl(k[1], 0, 64), c2 = __shfl(k[2], 0, 64);
+    const double c0 = __shfl(k[0], first, 64), c1 = __shfl(k[1], first, 64), c2 = __shfl(k[2], first, 64);
     double r = 0.0;
     if (live) {
         const double e0 = k[0] - c0, e1 = k[1] - c1, e2 = k[2] - c2;
         r = sqrt(e0 * e0 + e1 * e1 + e2 * e2) + sqrt(A.c2 * k[3]);
     }
-    r = wave_max(r);
-    if (lane == 0) {
-        double *o = A.grp + 4 * g;
-        o[0] = c0; o[1] = c1; o[2] = c2;
-        o[3] = r * (1.0 + 1e-9);   // rounding margin: the sphere test only pre-selects
+    for (int o = 1; o < NEAR_GROUP; o <<= 1) r = fmax(r, __shfl_xor(r, o, 64));
+    if (lane == first) {
+        r += 4e-6 * (fabs(c0) + fabs(c1) + fabs(c2) + r);
+        A.sph[s / NEAR_GROUP] = make_float4((float)c0, (float)c1, (float)c2, (float)r);
     }
 }
 
-// One wavefront per group of 64 targets (lane = target).
+// One workgroup per 256 targets (lane = target) and source split
+// (blockIdx.y): the source groups of every instance the workgroup's targets
+// belong to are cut into A.splits contiguous ranges, so that a large volume
+// spreads over many workgroups.  Their spheres and keys are staged in LDS
+// NEAR_CHUNK groups at a time; each target tests its own key against each
+// sphere in FP32 (widened as above by 4e-6 of its magnitudes) and, for the
+// groups some lane of the wavefront hits, the FP64 near rule decides source
+// by source.  Each split keeps its own list per target, in increasing source
+// order.
 __global__ __launch_bounds__(256) void k_near_list(NearArgs A)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t j = w * 64 + lane;
-    if (w * 64 >= A.ns) return;   // whole wavefront
+    __shared__ float4 sh[NEAR_CHUNK];
+    __shared__ double shk[4 * NEAR_GROUP * NEAR_CHUNK];
+    __shared__ long long sh_lo[4], sh_hi[4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int split = blockIdx.y, S = A.splits;
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + tid;
     const bool live = j < A.ns;
     int64_t sb = 0, se = 0;
     double kj[4] = {0, 0, 0, 0};
+    float fj0 = 3e38f, fj1 = 3e38f, fj2 = 3e38f, rj = 0.f;
     if (live) {
         const int64_t inst = inst_of(A, j);
         sb = A.seg_off ? A.seg_off[inst] : 0;
         se = A.seg_off ? A.seg_off[inst + 1] : A.ns;
         for (int c = 0; c < 4; ++c) kj[c] = A.key[4 * j + c];
+        fj0 = (float)kj[0];
+        fj1 = (float)kj[1];
+        fj2 = (float)kj[2];
+        const double r = sqrt(A.c2 * kj[3]);
+        rj = (float)(r + 4e-6 * (fabs(kj[0]) + fabs(kj[1]) + fabs(kj[2]) + r));
     }
-    // source groups of every instance this wavefront's targets belong to
-    const int64_t g_lo = wave_min(live ? sb / 64 : INT64_MAX);
-    const int64_t g_hi = wave_max(live ? (se - 1) / 64 : (int64_t)-1);
-    const double *gt = A.grp + 4 * w;
-    const double tc0 = gt[0], tc1 = gt[1], tc2 = gt[2], tr = gt[3];
+    // source groups of every instance this workgroup's targets belong to
+    const long long glo = wave_min(live ? (long long)(sb / NEAR_GROUP) : (long long)INT64_MAX);
+    const long long ghi = wave_max(live ? (long long)((se - 1) / NEAR_GROUP) : -1LL);
+    if (lane == 0) {
+        sh_lo[wv] = glo;
+        sh_hi[wv] = ghi;
+    }
+    __syncthreads();
+    long long g_lo = sh_lo[0], g_hi = sh_hi[0];
+    for (int k = 1; k < 4; ++k) {
+        g_lo = sh_lo[k] < g_lo ? sh_lo[k] : g_lo;
+        g_hi = sh_hi[k] > g_hi ? sh_hi[k] : g_hi;
+    }
+    // this split's part of [g_lo, g_hi]
+    const long long per = (g_hi - g_lo + S) / S;
+    const long long s_lo = g_lo + split * per;
+    const long long s_hi = s_lo + per - 1 < g_hi ? s_lo + per - 1 : g_hi;
     int32_t cnt = 0;
-    int32_t *out = A.list + j * NEAR_CAP;
-    for (int64_t g0 = g_lo; g0 <= g_hi; g0 += 64) {
-        const int64_t g = g0 + lane;
-        bool hit = false;
-        if (g <= g_hi) {
-            const double *gs = A.grp + 4 * g;
-            const double e0 = gs[0] - tc0, e1 = gs[1] - tc1, e2 = gs[2] - tc2;
-            const double rr = (gs[3] + tr) * (1.0 + 1e-9);
-            hit = e0 * e0 + e1 * e1 + e2 * e2 < rr * rr;
+    int32_t *out = A.list + (j * S + split) * NEAR_CAP;
+    for (long long gc = s_lo; gc <= s_hi; gc += NEAR_CHUNK) {
+        __syncthreads();   // the previous chunk is no longer read
+        const int n_here = (int)(s_hi - gc + 1 < NEAR_CHUNK ? s_hi - gc + 1 : NEAR_CHUNK);
+        if (tid < NEAR_CHUNK) {
+            const long long g = gc + tid;
+            sh[tid] = tid < n_here ? A.sph[g] : make_float4(3e38f, 3e38f, 3e38f, 0.f);
         }
-        uint64_t mask = __ballot(hit);
-        while (mask) {
-            const int b = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            const int64_t i0 = (g0 + b) * 64, i1 = i0 + 64 < A.ns ? i0 + 64 : A.ns;
-            for (int64_t i = i0; i < i1; ++i) {
-                const double *ki = A.key + 4 * i;
-                if (live && i >= sb && i < se && i != j && near_test(ki, kj, A.c2)) {
-                    if (cnt < NEAR_CAP) out[cnt] = (int32_t)i;
-                    ++cnt;
+        // the keys of the chunk's sources, coalesced
+        const int64_t kbase = 4 * gc * NEAR_GROUP, kend = 4 * A.ns;
+        for (int q = tid; q < 4 * NEAR_GROUP * NEAR_CHUNK; q += 256)
+            shk[q] = kbase + q < kend ? A.key[kbase + q] : 0.0;
+        __syncthreads();
+        // four spheres per round (independent tests); entries past n_here hold
+        // a sentinel that no target hits
+        for (int k = 0; k < n_here; k += 4) {
+            bool hit[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 c = sh[k + u];
+                const float e0 = fj0 - c.x, e1 = fj1 - c.y, e2 = fj2 - c.z, rr = c.w + rj;
+                hit[u] = live && e0 * e0 + e1 * e1 + e2 * e2 < rr * rr;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (__ballot(hit[u]) == 0) continue;
+                const int64_t i0 = (gc + k + u) * NEAR_GROUP;
+                const double *kg = shk + 4 * NEAR_GROUP * (k + u);
+#pragma unroll
+                for (int q = 0; q < NEAR_GROUP; ++q) {
+                    const int64_t i = i0 + q;
+                    if (hit[u] && i < A.ns && i >= sb && i < se && i != j && near_test(kg + 4 * q, kj, A.c2)) {
+                        if (cnt < NEAR_CAP) out[cnt] = (int32_t)i;
+                        ++cnt;
+                    }
                 }
             }
         }
     }
+    if (live) A.scnt[j * S + split] = cnt < NEAR_CAP ? cnt : NEAR_CAP;
     if (cnt > NEAR_CAP) atomicOr(A.flags, FLAG_NEAR_FULL);
-    int32_t c = cnt < NEAR_CAP ? cnt : NEAR_CAP;
-    // exclusive prefix of the clamped counts within the wavefront
+}
+
+// One thread per target: the near count over all splits (at most NEAR_CAP
+// kept) and its exclusive prefix within the wavefront, with per-wavefront
+// totals for the scan.
+__global__ __launch_bounds__(256) void k_near_count(NearArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int32_t c = 0;
+    if (j < A.ns) {
+        for (int s = 0; s < A.splits; ++s) c += A.scnt[j * A.splits + s];
+        if (c > NEAR_CAP) {
+            atomicOr(A.flags, FLAG_NEAR_FULL);
+            c = NEAR_CAP;
+        }
+    }
     int32_t incl = c;
     for (int o = 1; o < 64; o <<= 1) {
         const int32_t u = __shfl_up(incl, o, 64);
         if (lane >= o) incl += u;
     }
-    if (live) {
+    if (j < A.ns) {
         A.cnt[j] = c;
         A.loc[j] = incl - c;
     }
-    if (lane == 63) A.wtot[w] = incl;
+    const int64_t w = j >> 6;
+    if (lane == 63 && w < A.n_waves) A.wtot[w] = incl;
 }
 
-// One thread per target: its pairs at woff[wave] + loc[j] in the flat arrays.
+// One thread per target: its pairs at woff[wave] + loc[j] in the flat arrays,
+// the splits' lists concatenated in split order (increasing source index).
 __global__ void k_near_compact(NearArgs A)
 {
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -203,14 +268,19 @@ __global__ void k_near_compact(NearArgs A)
     const int64_t base = (int64_t)A.woff[j >> 6] + A.loc[j];
     const int c = A.cnt[j];
     A.ptr[j] = (int32_t)base;
-    for (int k = 0; k < c; ++k) {
-        const int64_t p = base + k;
-        if (p >= A.pair_cap) {
-            atomicOr(A.flags, FLAG_NEAR_FULL);
-            break;
+    int k = 0;
+    for (int s = 0; s < A.splits && k < c; ++s) {
+        const int32_t *lst = A.list + (j * A.splits + s) * NEAR_CAP;
+        const int m = A.scnt[j * A.splits + s];
+        for (int q = 0; q < m && k < c; ++q, ++k) {
+            const int64_t p = base + k;
+            if (p >= A.pair_cap) {
+                atomicOr(A.flags, FLAG_NEAR_FULL);
+                return;
+            }
+            A.pair_t[p] = (int32_t)j;
+            A.pair_s[p] = lst[q];
         }
-        A.pair_t[p] = (int32_t)j;
-        A.pair_s[p] = A.list[j * NEAR_CAP + k];
     }
 }
 
@@ -229,97 +299,121 @@ __device__ __forceinline__ bool panel_ok(double lo, double hi, const Focus &F)
     return true;
 }
 
-// One thread per near pair (grid-stride).  corr[p] = L_j k2 ((E - G) x t_j)
-// for the two ends, E the exact and G the Q-point weighted integrals of
-// sigma^i b_j / k2, in the units of the epilogue's end forces.
+// Four lanes per near pair (grid-stride over pairs).  The lanes of a pair
+// build the same panels; lane r takes points r, r + 4 and r + 8 of each
+// 12-point panel and the Q-point nodes q = r (mod 4); the four partial sums
+// are combined by a fixed butterfly, so results are reproducible.
+// corr[p] = L_j k2 ((E - G) x t_j) for the two ends, E the exact and G the
+// Q-point weighted integrals of sigma^i b_j / k2, in the units of the
+// epilogue's end forces.
+constexpr int LANES_PER_PAIR = 4;
+
 __global__ __launch_bounds__(256) void k_near_exact(NearArgs A)
 {
     const int64_t ns = A.ns;
     const int64_t P0 = A.woff[A.n_waves];
     const int64_t P = P0 < A.pair_cap ? P0 : A.pair_cap;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int r = threadIdx.x % LANES_PER_PAIR;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x / LANES_PER_PAIR;
     const double *rec = A.rec;
     const double *ra = rec + (int64_t)REC64 * ns;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < P; p += stride) {
-        const int64_t j = A.pair_t[p], i = A.pair_s[p];
-        const double X0 = rec[0 * ns + j], X1 = rec[1 * ns + j], X2 = rec[2 * ns + j];
-        const double t0 = rec[3 * ns + j], t1 = rec[4 * ns + j], t2 = rec[5 * ns + j];
-        const double L = rec[6 * ns + j];
-        const double b0 = rec[7 * ns + j], b1 = rec[8 * ns + j], b2 = rec[9 * ns + j];
-        const double *d = ra + i * RECA;
-        const double iL = 1.0 / L;
-        // the three singular points, in units of the target parameter u
-        Focus F;
-        const double st0 = d[3], st1 = d[4], st2 = d[5], Ls = d[6];
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const double w0 = d[0] + e * Ls * st0 - X0, w1 = d[1] + e * Ls * st1 - X1,
-                         w2 = d[2] + e * Ls * st2 - X2;
-            const double y = w0 * t0 + w1 * t1 + w2 * t2;
-            const double h0 = w0 - y * t0, h1 = w1 - y * t1, h2 = w2 - y * t2;
-            F.p[e] = y * iL;
-            F.d[e] = sqrt(h0 * h0 + h1 * h1 + h2 * h2 + 1.0) * iL;
-        }
-        {
-            // closest approach of the lines X + alpha t and P1 + beta ts
-            const double n0 = t1 * st2 - t2 * st1, n1 = t2 * st0 - t0 * st2, n2 = t0 * st1 - t1 * st0;
-            const double s2 = n0 * n0 + n1 * n1 + n2 * n2;   // sin^2 theta
-            if (s2 > 1e-20) {
-                const double w0 = X0 - d[0], w1 = X1 - d[1], w2 = X2 - d[2];
-                const double ct = t0 * st0 + t1 * st1 + t2 * st2;
-                const double dt = t0 * w0 + t1 * w1 + t2 * w2, ds = st0 * w0 + st1 * w1 + st2 * w2;
-                const double alpha = (ct * ds - dt) / s2;
-                const double e = (w0 * n0 + w1 * n1 + w2 * n2);
-                F.p[2] = alpha * iL;
-                F.d[2] = sqrt((e * e / s2 + 1.0) / s2) * iL;
-            } else {
-                F.p[2] = 0.0;
-                F.d[2] = 1e300;   // parallel lines: the distance to the source line is constant
-            }
-        }
+    // every lane of a wavefront runs the same number of rounds (shuffles below)
+    const int64_t first = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / LANES_PER_PAIR;
+    const int64_t wave_first = first - (threadIdx.x & 63) / LANES_PER_PAIR;
+    for (int64_t pw = wave_first; pw < P; pw += stride) {
+        const int64_t p = pw + (first - wave_first);
+        const bool live = p < P;
         double a10 = 0, a11 = 0, a12 = 0, a20 = 0, a21 = 0, a22 = 0;
-        double lo = 0.0, wd = 1.0;
-        int panels = 0;
-        while (lo < 1.0) {
-            double hi = fmin(lo + wd, 1.0);
-            while (hi - lo > 1e-7 && !panel_ok(lo, hi, F)) hi = lo + 0.5 * (hi - lo);
-            const double h = hi - lo;
-            for (int k = 0; k < PANEL_POINTS; ++k) {
-                const double u = lo + h * A.gp.s[k];
-                const double wk = h * A.gp.w[k];
-                const double uL = u * L;
+        double t0 = 0, t1 = 0, t2 = 0, L = 0;
+        if (live) {
+            const int64_t j = A.pair_t[p], i = A.pair_s[p];
+            const double X0 = rec[0 * ns + j], X1 = rec[1 * ns + j], X2 = rec[2 * ns + j];
+            t0 = rec[3 * ns + j]; t1 = rec[4 * ns + j]; t2 = rec[5 * ns + j];
+            L = rec[6 * ns + j];
+            const double b0 = rec[7 * ns + j], b1 = rec[8 * ns + j], b2 = rec[9 * ns + j];
+            const double *d = ra + i * RECA;
+            const double iL = 1.0 / L;
+            // the three singular points, in units of the target parameter u
+            Focus F;
+            const double st0 = d[3], st1 = d[4], st2 = d[5], Ls = d[6];
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const double w0 = d[0] + e * Ls * st0 - X0, w1 = d[1] + e * Ls * st1 - X1,
+                             w2 = d[2] + e * Ls * st2 - X2;
+                const double y = w0 * t0 + w1 * t1 + w2 * t2;
+                const double h0 = w0 - y * t0, h1 = w1 - y * t1, h2 = w2 - y * t2;
+                F.p[e] = y * iL;
+                F.d[e] = sqrt(h0 * h0 + h1 * h1 + h2 * h2 + 1.0) * iL;
+            }
+            {
+                // closest approach of the lines X + alpha t and P1 + beta ts
+                const double n0 = t1 * st2 - t2 * st1, n1 = t2 * st0 - t0 * st2, n2 = t0 * st1 - t1 * st0;
+                const double s2 = n0 * n0 + n1 * n1 + n2 * n2;   // sin^2 theta
+                if (s2 > 1e-20) {
+                    const double w0 = X0 - d[0], w1 = X1 - d[1], w2 = X2 - d[2];
+                    const double ct = t0 * st0 + t1 * st1 + t2 * st2;
+                    const double dt = t0 * w0 + t1 * w1 + t2 * w2, ds = st0 * w0 + st1 * w1 + st2 * w2;
+                    const double alpha = (ct * ds - dt) / s2;
+                    const double e = (w0 * n0 + w1 * n1 + w2 * n2);
+                    F.p[2] = alpha * iL;
+                    F.d[2] = sqrt((e * e / s2 + 1.0) / s2) * iL;
+                } else {
+                    F.p[2] = 0.0;
+                    F.d[2] = 1e300;   // parallel lines: the distance to the source line is constant
+                }
+            }
+            double lo = 0.0, wd = 1.0;
+            int panels = 0;
+            while (lo < 1.0) {
+                double hi = fmin(lo + wd, 1.0);
+                while (hi - lo > 1e-7 && !panel_ok(lo, hi, F)) hi = lo + 0.5 * (hi - lo);
+                const double h = hi - lo;
+#pragma unroll
+                for (int k = r; k < PANEL_POINTS; k += LANES_PER_PAIR) {
+                    const double u = lo + h * A.gp.s[k];
+                    const double wk = h * A.gp.w[k];
+                    const double uL = u * L;
+                    double g0 = 0, g1 = 0, g2 = 0;
+                    pair_acc_isolated_f64(X0 + uL * t0, X1 + uL * t1, X2 + uL * t2, b0, b1, b2, d, A.kr, A.nu,
+                                          g0, g1, g2);
+                    const double w1 = wk * (1.0 - u), w2 = wk * u;
+                    a10 += w1 * g0; a11 += w1 * g1; a12 += w1 * g2;
+                    a20 += w2 * g0; a21 += w2 * g1; a22 += w2 * g2;
+                }
+                wd = 2.0 * h;
+                lo = hi;
+                if (++panels >= MAX_PANELS) {
+                    atomicOr(A.flags, FLAG_NEAR_PANELS);
+                    break;
+                }
+            }
+            // minus the Q-point rule the all-pairs kernel applied to this pair
+            for (int q = r; q < A.g.n; q += LANES_PER_PAIR) {
+                const double u = A.g.s[q], uL = u * L;
                 double g0 = 0, g1 = 0, g2 = 0;
                 pair_acc_isolated_f64(X0 + uL * t0, X1 + uL * t1, X2 + uL * t2, b0, b1, b2, d, A.kr, A.nu, g0,
                                       g1, g2);
-                const double w1 = wk * (1.0 - u), w2 = wk * u;
-                a10 += w1 * g0; a11 += w1 * g1; a12 += w1 * g2;
-                a20 += w2 * g0; a21 += w2 * g1; a22 += w2 * g2;
-            }
-            wd = 2.0 * h;
-            lo = hi;
-            if (++panels >= MAX_PANELS) {
-                atomicOr(A.flags, FLAG_NEAR_PANELS);
-                break;
+                const double w1 = A.g.w[q] * (1.0 - u), w2 = A.g.w[q] * u;
+                a10 -= w1 * g0; a11 -= w1 * g1; a12 -= w1 * g2;
+                a20 -= w2 * g0; a21 -= w2 * g1; a22 -= w2 * g2;
             }
         }
-        // minus the Q-point rule the all-pairs kernel applied to this pair
-        for (int q = 0; q < A.g.n; ++q) {
-            const double u = A.g.s[q], uL = u * L;
-            double g0 = 0, g1 = 0, g2 = 0;
-            pair_acc_isolated_f64(X0 + uL * t0, X1 + uL * t1, X2 + uL * t2, b0, b1, b2, d, A.kr, A.nu, g0, g1,
-                                  g2);
-            const double w1 = A.g.w[q] * (1.0 - u), w2 = A.g.w[q] * u;
-            a10 -= w1 * g0; a11 -= w1 * g1; a12 -= w1 * g2;
-            a20 -= w2 * g0; a21 -= w2 * g1; a22 -= w2 * g2;
+        // butterfly over the pair's four lanes (every lane of the wavefront takes part)
+#pragma unroll
+        for (int o = 1; o < LANES_PER_PAIR; o <<= 1) {
+            a10 += __shfl_xor(a10, o, 64); a11 += __shfl_xor(a11, o, 64); a12 += __shfl_xor(a12, o, 64);
+            a20 += __shfl_xor(a20, o, 64); a21 += __shfl_xor(a21, o, 64); a22 += __shfl_xor(a22, o, 64);
         }
-        const double sc = L * A.k2;
-        double *o = A.corr + 6 * p;
-        o[0] = sc * (a11 * t2 - a12 * t1);
-        o[1] = sc * (a12 * t0 - a10 * t2);
-        o[2] = sc * (a10 * t1 - a11 * t0);
-        o[3] = sc * (a21 * t2 - a22 * t1);
-        o[4] = sc * (a22 * t0 - a20 * t2);
-        o[5] = sc * (a20 * t1 - a21 * t0);
+        if (live && r == 0) {
+            const double sc = L * A.k2;
+            double *o = A.corr + 6 * p;
+            o[0] = sc * (a11 * t2 - a12 * t1);
+            o[1] = sc * (a12 * t0 - a10 * t2);
+            o[2] = sc * (a10 * t1 - a11 * t0);
+            o[3] = sc * (a21 * t2 - a22 * t1);
+            o[4] = sc * (a22 * t0 - a20 * t2);
+            o[5] = sc * (a20 * t1 - a21 * t0);
+        }
     }
 }
 
@@ -329,13 +423,14 @@ void launch_near(const NearArgs &A, hipStream_t st)
 {
     if (A.ns <= 0) return;
     const int64_t waves = (A.ns + 63) / 64;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    hipLaunchKernelGGL(k_near_groups, dim3(blocks), dim3(256), 0, st, A);
-    hipLaunchKernelGGL(k_near_list, dim3(blocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_near_keys, dim3((unsigned)((A.ns + 255) / 256)), dim3(256), 0, st, A);
+    const unsigned tb = (unsigned)((A.ns + 255) / 256);
+    hipLaunchKernelGGL(k_near_list, dim3(tb, (unsigned)A.splits), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_near_count, dim3(tb), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (const int32_t *)A.wtot, waves, A.woff);
     hipLaunchKernelGGL(k_near_compact, dim3((unsigned)((A.ns + 255) / 256)), dim3(256), 0, st, A);
-    const int64_t cap_blocks = (A.pair_cap + 255) / 256;
-    const unsigned eb = (unsigned)(cap_blocks < 4096 ? (cap_blocks > 0 ? cap_blocks : 1) : 4096);
+    const int64_t cap_blocks = (A.pair_cap * LANES_PER_PAIR + 255) / 256;
+    const unsigned eb = (unsigned)(cap_blocks < 8192 ? (cap_blocks > 0 ? cap_blocks : 1) : 8192);
     hipLaunchKernelGGL(k_near_exact, dim3(eb), dim3(256), 0, st, A);
 }
 
