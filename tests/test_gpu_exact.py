@@ -156,3 +156,51 @@ def test_capacity_exceeded_is_an_error():
         assert ei.value.code == -5
     # a later call without the band is unaffected
     assert normwise(_gpu(inst), _oracle(inst)) < TOL64
+
+
+def test_large_volume_sampled_fp64():
+    """262,144 segments (one source split per target, coordinates up to
+    50,000 b) at eta = 1.5: the loop with the most near pairs (189, up to 34
+    for one segment) and an ordinary one, each against every source, by the
+    oracle.  At eta = 2 one long segment has 68 near sources: the call
+    reports DD_ECAPACITY."""
+    inst = W.config3()
+    with band(1.5):
+        F = _gpu(inst, 2)
+        num = den = 0.0
+        for lp in (7927, 4000):
+            t0, t1 = 32 * lp, 32 * lp + 32
+            ref = O.nodal_forces_sampled(inst.x, inst.seg_nodes, inst.burgers, inst.sigma_app,
+                                         W.MU, W.NU, W.CORE_A, 2, t0, t1)[:, t0:t1]
+            num = max(num, np.linalg.norm(F[:, t0:t1] - ref, axis=0).max())
+            den = max(den, np.linalg.norm(ref, axis=0).max())
+    print(f"large volume sampled eta=1.5: err {num / den:.2e}")
+    assert num / den < TOL64
+    with band(2.0):
+        with pytest.raises(dd.DDError) as ei:
+            _gpu(inst, 2)
+        assert ei.value.code == -5
+
+
+def test_pta_step_with_band():
+    """The PTA step runs its bursts through the same force path: with the band
+    on, the GPU driver takes the oracle driver's decisions and values."""
+    from oracle import pta
+    insts = [W.subset(W.burst_instance(1_000_010 + i), nl) for i, nl in enumerate((2, 1))]
+    rates = np.array([[0, 0, 1e15, 0, 0, 0], [0, 0, 0, 0, 0, 8e14]], float)
+    t = np.array([5e-8, 4e-8])
+    bt = W.pack(insts)
+    d = batch_dev(bt)
+    with band(2.0):
+        got = dd.dd_pta_step(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"], d["normal"],
+                             d["pinned"], d["volume"], rates, t,
+                             dd.PTAParams(dt=W.DT, delta=1e-8, chunk_steps=3, max_chunks=3, lpdot_max=np.inf),
+                             MAT, 2, dd.DD_FP64)
+        torch.cuda.synchronize()
+        OP = pta.PTAParams(dt=W.DT, delta=1e-8, chunk=3, max_chunks=3, lpdot_max=np.inf)
+        refs = [pta.pta_step(inst, t[i], rates[i], W.material(), 2, OP) for i, inst in enumerate(insts)]
+    for i, ref in enumerate(refs):
+        assert got["steps_a"][i] == ref["steps_a"] and got["steps_b"][i] == ref["steps_b"]
+        for k in ("lp_a", "lp_b"):
+            r = np.asarray(ref[k])
+            assert np.abs(got[k][i] - r).max() <= 1e-10 * np.abs(r).max(), k
