@@ -334,6 +334,42 @@ int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off,
                 const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
                 int precision, double near_cutoff_a, double *out, void *stream);
 
+/* Block coupling of the DD boxes to the continuum mesh (Sec. "DD-MFDM
+ * coupling").  The domain is n x n square blocks of side B and thickness h,
+ * one brick through the thickness (one DD box per block); every block is
+ * meshed by m x m x 1 trilinear hexahedra of the continuum calculation, each
+ * with 2 x 2 x 2 Gauss points.  Numbering: element e = ey * (n m) + ex
+ * (ex, ey in [0, n m)); Gauss point 8 e + 4 gz + 2 gy + gx at isoparametric
+ * coordinates ((2 gx - 1), (2 gy - 1), (2 gz - 1)) / sqrt(3); block
+ * r = by * n + bx.  Fields: Gauss-point arrays [n_gp][c] and block arrays
+ * [n * n][c] of float64 (c components, 1..16: a tensor is 9 components in
+ * row-major order ij, a vector 3), device memory owned by the caller.  Valid:
+ * n, m >= 1, n m <= 65536, B, h finite and > 0.  Errors: DD_EINVAL. */
+typedef struct { int32_t n, m; double B, h; } dd_block_mesh;
+
+/* Block averages <f>_r = int_{Omega_r} f dv / |Omega_r| of a Gauss-point field
+ * (the block stress average of Sec. "DD-MFDM coupling"), by the elements'
+ * Gauss rule: on this uniform mesh, the mean of the block's 8 m^2 values. */
+int dd_block_average(const dd_block_mesh *mesh, int c, const double *f_gp, double *f_block, void *stream);
+
+/* The blockwise-constant field f_block (e.g. the DD boxes' L^p or V) at every
+ * Gauss point, as the paper prescribes (subsection "Obtaining L^p, V at
+ * Gauss point of element"): its L2 projection onto the continuous trilinear
+ * finite-element space of the block mesh (consistent mass matrix), then the
+ * two-level isoparametric interpolation, first to the element's nodes with
+ * the block's shape functions, then to the Gauss point with the element's.
+ * Uses the device workspace ((n + 1)^2 c doubles). */
+int dd_block_to_gauss(const dd_block_mesh *mesh, int c, const double *f_block, double *f_gp, void *stream);
+
+/* Non-negative dissipation at n_gp Gauss points (Sec. "Ensuring non-negative
+ * dissipation", Eq. Lp_gauss and Eq. V_gauss), in place: where d = T : Lp < 0,
+ * Lp <- Lp - d T / |T|^2; where beta = V . (X T alpha) < 0, with
+ * (X T alpha)_i = eps_ijk (T alpha)_jk, V <- V - beta (X T alpha) /
+ * |X T alpha|^2.  T, alpha, Lp: [n_gp][9] (row-major), V: [n_gp][3].  Lp or V
+ * may be null (that part is skipped); alpha may be null when V is.  Where T
+ * (or X T alpha) is zero nothing changes. */
+int dd_dissipation_fix(int64_t n_gp, const double *T, const double *alpha, double *Lp, double *V, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Slip-rate surrogate (not in the paper): a 4-member ensemble of MLPs     */
 /* 36 -> 256 -> 256 -> 256 -> 12, ReLU hidden layers, that maps the 36     */

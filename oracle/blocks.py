@@ -121,33 +121,34 @@ def block_to_gauss(f_block, n, m, B, h):
     return interpolate(l2_projection(f_block, n, B, h), n, m, B, h)
 
 
-def interpolate(A, n, m, B, h):
+def interpolate(A, n, m, B, h, elements=None):
     """Two-level isoparametric interpolation of nodal values A [nn][c] of the
-    block mesh to every Gauss point of the element mesh."""
+    block mesh to the Gauss points of the element mesh: all of them
+    ([n_el * 8][c]), or those of the listed elements ([len * 8][c])."""
     A = np.asarray(A, float)
     _, conn = _block_mesh(n, B, h)
     c = A.shape[1]
     ne = n * m
-    out = np.empty((ne * ne * 8, c))
-    for ey in range(ne):
-        for ex in range(ne):
-            bx, by = ex // m, ey // m
-            r = by * n + bx
-            # the element's nodes in the block's isoparametric coordinates
-            A_el = np.empty((8, c))
-            for kz in range(2):
-                for ky in range(2):
-                    for kx in range(2):
-                        xi_b = -1 + 2 * ((ex - bx * m) + kx) / m
-                        et_b = -1 + 2 * ((ey - by * m) + ky) / m
-                        ze_b = 2 * kz - 1
-                        A_el[4 * kz + 2 * ky + kx] = _shape(xi_b, et_b, ze_b) @ A[conn[r]]
-            e = ey * ne + ex
-            for gz in range(2):
-                for gy in range(2):
-                    for gx in range(2):
-                        N = _shape((2 * gx - 1) * GP, (2 * gy - 1) * GP, (2 * gz - 1) * GP)
-                        out[8 * e + 4 * gz + 2 * gy + gx] = N @ A_el
+    els = range(ne * ne) if elements is None else elements
+    out = np.empty((len(els) * 8, c))
+    for slot, e_id in enumerate(els):
+        ey, ex = divmod(int(e_id), ne)
+        bx, by = ex // m, ey // m
+        r = by * n + bx
+        # the element's nodes in the block's isoparametric coordinates
+        A_el = np.empty((8, c))
+        for kz in range(2):
+            for ky in range(2):
+                for kx in range(2):
+                    xi_b = -1 + 2 * ((ex - bx * m) + kx) / m
+                    et_b = -1 + 2 * ((ey - by * m) + ky) / m
+                    ze_b = 2 * kz - 1
+                    A_el[4 * kz + 2 * ky + kx] = _shape(xi_b, et_b, ze_b) @ A[conn[r]]
+        for gz in range(2):
+            for gy in range(2):
+                for gx in range(2):
+                    N = _shape((2 * gx - 1) * GP, (2 * gy - 1) * GP, (2 * gz - 1) * GP)
+                    out[8 * slot + 4 * gz + 2 * gy + gx] = N @ A_el
     return out
 
 

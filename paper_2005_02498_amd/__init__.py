@@ -19,6 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdd.so")
 
 DD_FP64, DD_MIXED = 0, 1
+DD_OK, DD_EINVAL, DD_EHIP, DD_ENOMEM, DD_ENONFINITE, DD_ECAPACITY = 0, -1, -2, -3, -4, -5
 N_SYSTEMS, N_FEATURES = 12, 36
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 
@@ -26,6 +27,7 @@ EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
     "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_exact_band", "dd_set_plan", "dd_last_plan",
     "dd_nodal_forces", "dd_glide_step", "dd_burst_batch", "dd_pta_step",
+    "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
     "dd_surrogate_rates",
@@ -36,6 +38,11 @@ class DDError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libdd error {code}: {msg}")
         self.code = code
+
+
+class BlockMesh(C.Structure):
+    """n x n blocks of side B and thickness h, each meshed by m x m x 1 elements (dd.h)."""
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("B", C.c_double), ("h", C.c_double)]
 
 
 class Material(C.Structure):
@@ -94,6 +101,9 @@ def _declare(L):
                                   C.POINTER(C.c_double), vp]),
         "dd_set_plan": (C.c_int, [i64, C.c_int]),
         "dd_set_exact_band": (C.c_int, [C.c_double]),
+        "dd_block_average": (C.c_int, [C.POINTER(BlockMesh), C.c_int, vp, vp, vp]),
+        "dd_block_to_gauss": (C.c_int, [C.POINTER(BlockMesh), C.c_int, vp, vp, vp]),
+        "dd_dissipation_fix": (C.c_int, [i64, vp, vp, vp, vp, vp]),
         "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
                                       C.POINTER(Material), C.c_int, C.c_int, dbl, vp, vp]),
         "dd_glide_step": (C.c_int, [i64, vp, vp, i64, vp, vp, vp, C.POINTER(Material), dbl,
@@ -190,6 +200,48 @@ def dd_set_exact_band(eta: float = 0.0):
     """Exact target integral for pairs with midpoints closer than
     eta*sqrt((Li^2+Lj^2)/2); 0 turns it off.  Process-wide; see dd.h."""
     _check(lib().dd_set_exact_band(float(eta)))
+
+
+def _block_args(n, m, B, h):
+    return BlockMesh(int(n), int(m), float(B), float(h))
+
+
+def dd_block_average(f_gp, n, m, B, h, out=None, stream=None):
+    """Block averages [n*n][c] of a Gauss-point field [n_gp][c] (float64, device); see dd.h."""
+    ngp = (n * m) ** 2 * 8
+    c = f_gp.shape[1] if f_gp.dim() == 2 else -1
+    pf = _dev(f_gp, torch.float64, (ngp, c), "f_gp")
+    if out is None:
+        out = torch.empty((n * n, c), dtype=torch.float64, device=f_gp.device)
+    po = _dev(out, torch.float64, (n * n, c), "out")
+    mesh = _block_args(n, m, B, h)
+    _check(lib().dd_block_average(C.byref(mesh), c, pf, po, _stream(stream)))
+    return out
+
+
+def dd_block_to_gauss(f_block, n, m, B, h, out=None, stream=None):
+    """Blockwise-constant field [n*n][c] -> L2 projection on the block mesh ->
+    two-level interpolation to every Gauss point [n_gp][c]; see dd.h."""
+    ngp = (n * m) ** 2 * 8
+    c = f_block.shape[1] if f_block.dim() == 2 else -1
+    pf = _dev(f_block, torch.float64, (n * n, c), "f_block")
+    if out is None:
+        out = torch.empty((ngp, c), dtype=torch.float64, device=f_block.device)
+    po = _dev(out, torch.float64, (ngp, c), "out")
+    mesh = _block_args(n, m, B, h)
+    _check(lib().dd_block_to_gauss(C.byref(mesh), c, pf, po, _stream(stream)))
+    return out
+
+
+def dd_dissipation_fix(T, alpha=None, Lp=None, V=None, stream=None):
+    """In place: Eq. Lp_gauss on Lp and Eq. V_gauss on V ([n][9], [n][9], [n][9], [n][3])."""
+    n = T.shape[0]
+    pt = _dev(T, torch.float64, (n, 9), "T")
+    pa = _dev(alpha, torch.float64, (n, 9), "alpha", nullable=True)
+    pl = _dev(Lp, torch.float64, (n, 9), "Lp", nullable=True)
+    pv = _dev(V, torch.float64, (n, 3), "V", nullable=True)
+    _check(lib().dd_dissipation_fix(int(n), pt, pa, pl, pv, _stream(stream)))
+    return Lp, V
 
 
 def dd_set_plan(chunk_len: int = -1, variant: int = 0):

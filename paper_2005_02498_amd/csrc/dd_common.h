@@ -68,6 +68,8 @@ enum Slot {
     WS_NEAR_WAVE,      //   per-wavefront totals and their prefix
     WS_NEAR_PAIR,      //   flat (target, source) pairs
     WS_NEAR_CORR,      //   per-pair end-force corrections
+    WS_BLOCK_A,        // block coupling: nodal values of the projection
+    WS_BLOCK_FAC,      //   tridiagonal factors
     WS_NSLOTS
 };
 

@@ -56,3 +56,16 @@ def test_host_only_calls_without_gpu():
         with pytest.raises(dd.DDError):
             dd.dd_set_exact_band(bad)
     dd.dd_set_exact_band(0.0)
+    # block-coupling argument checks happen before any device work
+    fake = ctypes.c_void_p(256)
+    for bad in ((0, 1, 1.0, 1.0), (1, 0, 1.0, 1.0), (1, 1, 0.0, 1.0), (1, 1, 1.0, float("nan")),
+                (70000, 1, 1.0, 1.0)):
+        mesh = dd.BlockMesh(*bad)
+        assert dd.lib().dd_block_average(ctypes.byref(mesh), 1, fake, fake, None) == dd.DD_EINVAL
+        assert dd.lib().dd_block_to_gauss(ctypes.byref(mesh), 1, fake, fake, None) == dd.DD_EINVAL
+    ok = dd.BlockMesh(1, 1, 1.0, 1.0)
+    for c in (0, 17):
+        assert dd.lib().dd_block_average(ctypes.byref(ok), c, fake, fake, None) == dd.DD_EINVAL
+    assert dd.lib().dd_dissipation_fix(-1, fake, fake, fake, fake, None) == dd.DD_EINVAL
+    assert dd.lib().dd_dissipation_fix(4, None, fake, fake, fake, None) == dd.DD_EINVAL
+    assert dd.lib().dd_dissipation_fix(4, fake, None, None, fake, None) == dd.DD_EINVAL
