@@ -344,7 +344,7 @@ int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off,
  * r = by * n + bx.  Fields: Gauss-point arrays [n_gp][c] and block arrays
  * [n * n][c] of float64 (c components, 1..16: a tensor is 9 components in
  * row-major order ij, a vector 3), device memory owned by the caller.  Valid:
- * n, m >= 1, n m <= 65536, B, h finite and > 0.  Errors: DD_EINVAL. */
+ * n, m >= 1, n m <= 65535, B, h finite and > 0.  Errors: DD_EINVAL. */
 typedef struct { int32_t n, m; double B, h; } dd_block_mesh;
 
 /* Block averages <f>_r = int_{Omega_r} f dv / |Omega_r| of a Gauss-point field
@@ -358,7 +358,7 @@ int dd_block_average(const dd_block_mesh *mesh, int c, const double *f_gp, doubl
  * finite-element space of the block mesh (consistent mass matrix), then the
  * two-level isoparametric interpolation, first to the element's nodes with
  * the block's shape functions, then to the Gauss point with the element's.
- * Uses the device workspace ((n + 1)^2 c doubles). */
+ * Uses the device workspace (2 (n + 1)^2 c doubles). */
 int dd_block_to_gauss(const dd_block_mesh *mesh, int c, const double *f_block, double *f_gp, void *stream);
 
 /* Non-negative dissipation at n_gp Gauss points (Sec. "Ensuring non-negative

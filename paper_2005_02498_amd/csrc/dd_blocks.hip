@@ -20,7 +20,7 @@
 // one tridiagonal solve along x for every row of nodes, then one along y for
 // every column.  K is strictly diagonally dominant, so elimination without
 // pivoting (the Thomas algorithm) is stable; its factors depend only on n and
-// are computed once on the host.
+// are computed on the host when n changes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,30 +43,34 @@ struct BlockGeom {
 };
 
 // Mean of the block's m^2 * 8 Gauss-point values (equal Gauss weights on the
-// uniform affine mesh), one workgroup per block, fixed-order tree reduction.
+// uniform affine mesh), one workgroup per block.  The block's values lie in m
+// contiguous runs (one per row of elements) of m * 8 * c doubles; thread t
+// reads entries t, t + S, t + 2S, ... of each run, S = c * floor(256 / c), so
+// it always holds component t % c (reads are coalesced).  The per-thread
+// sums are then added per component in thread order.
 __global__ __launch_bounds__(256) void k_block_average(BlockGeom G, const double *__restrict__ f,
                                                        double *__restrict__ out)
 {
-    __shared__ double sh[256][MAX_COMP + 1];
+    __shared__ double sh[256];
     const int64_t r = blockIdx.x;
     const int64_t bx = r % G.n, by = r / G.n;
-    const int64_t per = G.m * G.m * 8;
-    double acc[MAX_COMP];
-    for (int k = 0; k < MAX_COMP; ++k) acc[k] = 0.0;
-    for (int64_t q = threadIdx.x; q < per; q += 256) {
-        const int64_t el = q >> 3, g = q & 7;
-        const int64_t ex = bx * G.m + el % G.m, ey = by * G.m + el / G.m;
-        const double *src = f + ((ey * G.ne + ex) * 8 + g) * G.c;
-        for (int k = 0; k < G.c; ++k) acc[k] += src[k];
+    const int t = threadIdx.x;
+    const int S = G.c * (256 / G.c);
+    const int64_t run = G.m * 8 * G.c;
+    double acc = 0.0;
+    if (t < S) {
+        for (int64_t ly = 0; ly < G.m; ++ly) {
+            const double *src = f + ((by * G.m + ly) * G.ne + bx * G.m) * 8 * G.c;
+            for (int64_t q = t; q < run; q += S) acc += src[q];
+        }
     }
-    for (int k = 0; k < G.c; ++k) sh[threadIdx.x][k] = acc[k];
+    sh[t] = acc;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < G.c; ++k) sh[threadIdx.x][k] += sh[threadIdx.x + s][k];
-        __syncthreads();
+    if (t < G.c) {
+        double s = 0.0;
+        for (int u = t; u < S; u += G.c) s += sh[u];
+        out[r * G.c + t] = s / (double)(G.m * G.m * 8);
     }
-    if ((int)threadIdx.x < G.c) out[r * G.c + threadIdx.x] = sh[0][threadIdx.x] / (double)per;
 }
 
 // Load vector of the in-plane system at node (i, j): B^2/4 times the sum of the
@@ -87,11 +91,15 @@ __global__ void k_block_rhs(BlockGeom G, const double *__restrict__ fb, double *
     A[t] = 0.25 * G.B * G.B * s;
 }
 
-// In-place solve K y = scale * d along one line of nodes for every line:
-// line l, entry q at A[base(l) + q * stride].  den[q] and cp[q] are the
-// Thomas factors of K (den_0 = 2, cp_q = 1/den_q, den_q = diag_q - cp_{q-1}).
-__global__ void k_block_tridiag(int64_t lines, int64_t N, int64_t c, int64_t along_y, const double *__restrict__ den,
-                                const double *__restrict__ cp, double scale, double *__restrict__ A)
+// Solve K y = scale * d along one line of nodes for every line: line l,
+// entry q at [base(l) + q * stride] of the arrays.  The forward sweep reads
+// d from `io` and leaves its results in `tmp`; the backward sweep writes y
+// back to `io`.  Reading and writing different arrays lets each sweep keep
+// several loads in flight.  rden[q] = 1/den_q holds the Thomas factors of K
+// (den_0 = 2, den_q = diag_q - 1/den_{q-1}); with unit off-diagonals it is
+// also the back-substitution factor.
+__global__ void k_block_tridiag(int64_t lines, int64_t N, int64_t c, int64_t along_y, const double *__restrict__ rden,
+                                double scale, double *__restrict__ io, double *__restrict__ tmp)
 {
     const int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (l >= lines) return;
@@ -100,49 +108,48 @@ __global__ void k_block_tridiag(int64_t lines, int64_t N, int64_t c, int64_t alo
     const int64_t base = along_y ? line * c + k : line * N * c + k;
     const int64_t stride = along_y ? N * c : c;
     double prev = 0.0;
+#pragma unroll 8
     for (int64_t q = 0; q < N; ++q) {
-        const double d = scale * A[base + q * stride];
-        prev = (d - prev) / den[q];
-        A[base + q * stride] = prev;
+        prev = (scale * io[base + q * stride] - prev) * rden[q];
+        tmp[base + q * stride] = prev;
     }
     double next = 0.0;
+#pragma unroll 8
     for (int64_t q = N - 1; q >= 0; --q) {
-        const double y = A[base + q * stride] - (q + 1 < N ? cp[q] * next : 0.0);
-        A[base + q * stride] = y;
-        next = y;
+        next = tmp[base + q * stride] - rden[q] * next;
+        io[base + q * stride] = next;
     }
 }
 
 // Two-level interpolation: the element's corner nodes from the block's
 // shape functions at their block-isoparametric coordinates, then the Gauss
-// point from the element's shape functions.  The block field does not depend
-// on z, so the z factors of both levels sum to one and drop out.
+// point from the element's shape functions.  Restricted to an element (an
+// axis-aligned sub-box of its block) the block's trilinear field is itself
+// trilinear, so the element's interpolation reproduces it: the two levels
+// compose to the block's shape functions at the Gauss point's block
+// coordinates, which is what is evaluated here (4 weights instead of 16).
+// The block field does not depend on z, so the z factors drop out.  One
+// thread per output value (Gauss point, component), so that writes are
+// coalesced; blockIdx.y is the element row.
 __global__ void k_block_interp(BlockGeom G, const double *__restrict__ A, double *__restrict__ out)
 {
-    const int64_t N = G.n + 1;
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (p >= G.ne * G.ne * 8) return;
-    const int64_t e = p >> 3;
-    const int g = (int)(p & 7);
-    const int64_t ex = e % G.ne, ey = e / G.ne;
-    const int64_t bx = ex / G.m, by = ey / G.m;
+    const int N = (int)G.n + 1, c = G.c, m = (int)G.m;
+    const int row_len = (int)G.ne * 8 * c;
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= row_len) return;
+    const int ey = blockIdx.y;
+    const int k = o % c, p = o / c;
+    const int ex = p >> 3, g = p & 7;
+    const int bx = ex / m, by = ey / m;
     const double xg = (2 * (g & 1) - 1) * ISO_GP, yg = (2 * ((g >> 1) & 1) - 1) * ISO_GP;
-    double val[MAX_COMP];
-    for (int k = 0; k < G.c; ++k) val[k] = 0.0;
-    for (int ky = 0; ky < 2; ++ky)
-        for (int kx = 0; kx < 2; ++kx) {
-            // element corner (kx, ky) in block coordinates
-            const double xb = -1.0 + 2.0 * (double)(ex - bx * G.m + kx) / (double)G.m;
-            const double yb = -1.0 + 2.0 * (double)(ey - by * G.m + ky) / (double)G.m;
-            const double we = 0.25 * (1.0 + (2 * kx - 1) * xg) * (1.0 + (2 * ky - 1) * yg);
-            for (int qy = 0; qy < 2; ++qy)
-                for (int qx = 0; qx < 2; ++qx) {
-                    const double wb = 0.25 * (1.0 + (2 * qx - 1) * xb) * (1.0 + (2 * qy - 1) * yb);
-                    const double *a = A + ((by + qy) * N + bx + qx) * G.c;
-                    for (int k = 0; k < G.c; ++k) val[k] += we * wb * a[k];
-                }
-        }
-    for (int k = 0; k < G.c; ++k) out[p * G.c + k] = val[k];
+    // the Gauss point in its block's isoparametric coordinates
+    const double im = 1.0 / (double)m;
+    const double xb = -1.0 + ((double)(2 * (ex - bx * m) + 1) + xg) * im;
+    const double yb = -1.0 + ((double)(2 * (ey - by * m) + 1) + yg) * im;
+    const double a00 = A[(by * N + bx) * c + k], a10 = A[(by * N + bx + 1) * c + k];
+    const double a01 = A[((by + 1) * N + bx) * c + k], a11 = A[((by + 1) * N + bx + 1) * c + k];
+    out[(int64_t)ey * row_len + o] = 0.25 * ((1.0 - xb) * (1.0 - yb) * a00 + (1.0 + xb) * (1.0 - yb) * a10 +
+                                             (1.0 - xb) * (1.0 + yb) * a01 + (1.0 + xb) * (1.0 + yb) * a11);
 }
 
 // Eq. Lp_gauss: if d = T : Lp < 0, Lp <- Lp - d T / |T|^2.  Eq. V_gauss: with
@@ -191,7 +198,7 @@ int check_mesh(const dd_block_mesh *mesh, int c, BlockGeom &G)
     if (!(mesh->B > 0.0) || !std::isfinite(mesh->B) || !(mesh->h > 0.0) || !std::isfinite(mesh->h))
         return set_error(DD_EINVAL, "block size and thickness must be finite and > 0");
     if (c < 1 || c > MAX_COMP) return set_error(DD_EINVAL, "components must be 1..%d", MAX_COMP);
-    if ((int64_t)mesh->n * mesh->m > 65536) return set_error(DD_EINVAL, "n * m must be at most 65536");
+    if ((int64_t)mesh->n * mesh->m > 65535) return set_error(DD_EINVAL, "n * m must be at most 65535");
     G.n = mesh->n;
     G.m = mesh->m;
     G.ne = G.n * G.m;
@@ -234,30 +241,34 @@ extern "C" int dd_block_to_gauss(const dd_block_mesh *mesh, int c, const double 
     if ((rc = workspace(&ws))) return rc;
     const int64_t N = G.n + 1;
     void *p;
-    if ((rc = ensure(ws, WS_BLOCK_A, sizeof(double) * N * N * c, &p))) return rc;
-    double *A = (double *)p;
-    // Thomas factors of K = tridiag(1, [2, 4, ..., 4, 2], 1), size N
-    std::vector<double> fac(2 * N);
-    double *den = fac.data(), *cp = fac.data() + N;
-    for (int64_t q = 0; q < N; ++q) {
-        const double diag = (q == 0 || q == N - 1) ? 2.0 : 4.0;
-        den[q] = q == 0 ? diag : diag - cp[q - 1];
-        cp[q] = 1.0 / den[q];
+    if ((rc = ensure(ws, WS_BLOCK_A, sizeof(double) * 2 * N * N * c, &p))) return rc;
+    double *A = (double *)p, *tmp = A + N * N * c;
+    // Thomas factors of K = tridiag(1, [2, 4, ..., 4, 2], 1), size N: 1/den_q,
+    // uploaded again only when n changes
+    if ((rc = ensure(ws, WS_BLOCK_FAC, sizeof(double) * N, &p))) return rc;
+    double *rden = (double *)p;
+    if (ws->block_fac_n != N) {
+        std::vector<double> fac(N);
+        double den = 2.0;
+        for (int64_t q = 0; q < N; ++q) {
+            const double diag = (q == 0 || q == N - 1) ? 2.0 : 4.0;
+            den = q == 0 ? diag : diag - 1.0 / den;
+            fac[q] = 1.0 / den;
+        }
+        DD_HIP(hipMemcpyAsync(rden, fac.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+        DD_HIP(hipStreamSynchronize(st));   // fac is pageable and short-lived
+        ws->block_fac_n = N;
     }
-    if ((rc = ensure(ws, WS_BLOCK_FAC, sizeof(double) * 2 * N, &p))) return rc;
-    double *dfac = (double *)p;
-    DD_HIP(hipMemcpyAsync(dfac, fac.data(), sizeof(double) * 2 * N, hipMemcpyHostToDevice, st));
-    DD_HIP(hipStreamSynchronize(st));   // fac is pageable and short-lived
     const int64_t nodes = N * N * c;
     hipLaunchKernelGGL(k_block_rhs, dim3((unsigned)((nodes + 255) / 256)), dim3(256), 0, st, G, f_block, A);
     const int64_t lines = N * c;
     const double scale = 6.0 / G.B;
     hipLaunchKernelGGL(k_block_tridiag, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, st, lines, N,
-                       (int64_t)c, (int64_t)0, (const double *)dfac, (const double *)(dfac + N), scale, A);
+                       (int64_t)c, (int64_t)0, (const double *)rden, scale, A, tmp);
     hipLaunchKernelGGL(k_block_tridiag, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, st, lines, N,
-                       (int64_t)c, (int64_t)1, (const double *)dfac, (const double *)(dfac + N), scale, A);
-    const int64_t gps = G.ne * G.ne * 8;
-    hipLaunchKernelGGL(k_block_interp, dim3((unsigned)((gps + 255) / 256)), dim3(256), 0, st, G,
+                       (int64_t)c, (int64_t)1, (const double *)rden, scale, A, tmp);
+    const int64_t row_len = G.ne * 8 * c;
+    hipLaunchKernelGGL(k_block_interp, dim3((unsigned)((row_len + 255) / 256), (unsigned)G.ne), dim3(256), 0, st, G,
                        (const double *)A, f_gp);
     DD_HIP(hipGetLastError());
     if (validation_on()) DD_HIP(hipStreamSynchronize(st));
