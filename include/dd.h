@@ -264,6 +264,45 @@ int dd_burst_batch(int32_t n_inst, const int64_t *node_off,
                    double near_cutoff_a, int n_steps, double dt,
                    double *rate_avg_out, double *features_out, void *stream);
 
+/* Junctions and their thermally activated breaking (Sec. "Thermal
+ * activation", Eq. tb), for dd_burst_batch_junctions.  A mobile node (not
+ * pinned) that comes closer than capture_radius to a sessile segment (both
+ * its nodes pinned) of its own instance forms a junction: it is held fixed
+ * until t_b = f * max_break_time has passed, f = fractions[node][count mod
+ * n_fractions] (uniform numbers in [0, 1) supplied by the caller; count = the
+ * node's number of junctions so far).  No node is inserted.  The checks run
+ * at the start of every step k, at time t0 + k dt: a held node whose release
+ * time has come is released (and forms no junction in that step); a free node
+ * forgets the segment it last broke from once it is farther than
+ * 2 capture_radius from it, then is captured by the first sessile segment in
+ * index order, other than that one, closer than capture_radius.  Distances
+ * are evaluated in float64 without fused multiply-adds.  State, per node
+ * (device arrays [n_nodes], caller-owned, carried from call to call; start
+ * with junction = ignore = -1, count = 0): junction = index of the holding
+ * segment in the batch's segment arrays or -1, release = its release time,
+ * ignore = the segment it last broke from or -1, count.  Units: lengths as
+ * the positions, times as dt. */
+typedef struct {
+    double capture_radius, max_break_time, t0;
+    int32_t n_fractions;
+    const double *fractions;   /* [n_nodes][n_fractions] */
+    int32_t *junction;         /* [n_nodes] */
+    double *release;           /* [n_nodes] */
+    int32_t *ignore;           /* [n_nodes] */
+    int32_t *count;            /* [n_nodes] */
+} dd_junctions;
+
+/* dd_burst_batch with junctions (see dd_junctions): the same arguments and
+ * outputs; held nodes do not move and contribute no slip rate while held.
+ * DD_EINVAL for a null `junctions`, a negative or non-finite radius or
+ * breaking time, a non-finite t0, n_fractions < 1 or null arrays. */
+int dd_burst_batch_junctions(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                             const int32_t *seg_nodes, const double *burgers, const double *normal,
+                             const uint8_t *pinned, const double *sigma_app, const double *volume,
+                             const dd_material *m, int n_gauss, int precision, double near_cutoff_a,
+                             int n_steps, double dt, const dd_junctions *junctions, double *rate_avg_out,
+                             double *features_out, void *stream);
+
 /* One slow-time step of Practical Time Averaging for a batch of independent
  * DD volumes (Sec. "Application of PTA for coarse-graining DD simulation",
  * subsection "Algorithm", steps 1-7).  Volume i is at slow time t[i] under

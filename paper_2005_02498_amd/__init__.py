@@ -26,7 +26,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
     "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_exact_band", "dd_set_plan", "dd_last_plan",
-    "dd_nodal_forces", "dd_glide_step", "dd_burst_batch", "dd_pta_step",
+    "dd_nodal_forces", "dd_glide_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_pta_step",
     "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -43,6 +43,13 @@ class DDError(RuntimeError):
 class BlockMesh(C.Structure):
     """n x n blocks of side B and thickness h, each meshed by m x m x 1 elements (dd.h)."""
     _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("B", C.c_double), ("h", C.c_double)]
+
+
+class Junctions(C.Structure):
+    """dd_junctions of dd.h (device pointers as integers)."""
+    _fields_ = [("capture_radius", C.c_double), ("max_break_time", C.c_double), ("t0", C.c_double),
+                ("n_fractions", C.c_int32), ("fractions", C.c_void_p), ("junction", C.c_void_p),
+                ("release", C.c_void_p), ("ignore", C.c_void_p), ("count", C.c_void_p)]
 
 
 class Material(C.Structure):
@@ -111,6 +118,9 @@ def _declare(L):
         "dd_burst_batch": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp,
                                      vp, vp, vp, vp, vp, C.POINTER(Material), C.c_int, C.c_int,
                                      dbl, C.c_int, dbl, vp, vp, vp]),
+        "dd_burst_batch_junctions": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp,
+                                               vp, vp, vp, vp, vp, C.POINTER(Material), C.c_int, C.c_int,
+                                               dbl, C.c_int, dbl, C.POINTER(Junctions), vp, vp, vp]),
         "dd_mlp_create": (C.c_int, [C.c_int, C.c_uint64, C.POINTER(vp)]),
         "dd_mlp_destroy": (C.c_int, [vp]),
         "dd_mlp_set_params": (C.c_int, [vp, C.c_int, fp]),
@@ -349,6 +359,46 @@ def dd_burst_batch(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sig
                                 int(n_gauss), _prec(precision), float(near_cutoff_a),
                                 int(n_steps), float(dt), pr, pfe, _stream(stream)))
     return rate_avg_out, features_out
+
+
+def dd_burst_batch_junctions(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume,
+                             mat, state, fractions, capture_radius, max_break_time, t0=0.0, n_gauss=2,
+                             precision=DD_MIXED, near_cutoff_a=20.0, n_steps=200, dt=2e-14,
+                             rate_avg_out=None, stream=None):
+    """Batched bursts with junctions (dd.h, dd_junctions).  state: dict of device
+    tensors junction (int32), release (float64), ignore (int32), count (int32),
+    each [n_nodes], updated in place; fractions [n_nodes][K] float64 (device).
+    Returns rate_avg [n_inst][12]; x advances."""
+    no = (C.c_int64 * len(node_off))(*[int(v) for v in node_off])
+    so = (C.c_int64 * len(seg_off))(*[int(v) for v in seg_off])
+    n_inst = len(node_off) - 1
+    if len(seg_off) != n_inst + 1:
+        raise ValueError("node_off and seg_off must have the same length")
+    nn, ns = int(node_off[-1]), int(seg_off[-1])
+    dev = x.device
+    px = _dev(x, torch.float64, (3, nn), "x")
+    psn = _dev(seg_nodes, torch.int32, (2, ns), "seg_nodes")
+    pb = _dev(burgers, torch.float64, (3, ns), "burgers")
+    pn = _dev(normal, torch.float64, (3, ns), "normal")
+    pp = _dev(pinned, torch.uint8, (nn,), "pinned", nullable=True)
+    ps = _dev(sigma_app, torch.float64, (n_inst, 6), "sigma_app")
+    pv = _dev(volume, torch.float64, (n_inst,), "volume")
+    K = fractions.shape[1] if fractions.dim() == 2 else -1
+    pf = _dev(fractions, torch.float64, (nn, K), "fractions")
+    pj = _dev(state["junction"], torch.int32, (nn,), "junction")
+    prl = _dev(state["release"], torch.float64, (nn,), "release")
+    pig = _dev(state["ignore"], torch.int32, (nn,), "ignore")
+    pc = _dev(state["count"], torch.int32, (nn,), "count")
+    if rate_avg_out is None:
+        rate_avg_out = torch.empty((n_inst, 12), dtype=torch.float64, device=dev)
+    pr = _dev(rate_avg_out, torch.float64, (n_inst, 12), "rate_avg_out")
+    jn = Junctions(float(capture_radius), float(max_break_time), float(t0), int(K), pf.value, pj.value,
+                   prl.value, pig.value, pc.value)
+    m = _mat(mat)
+    _check(lib().dd_burst_batch_junctions(n_inst, no, so, px, psn, pb, pn, pp, ps, pv, C.byref(m),
+                                          int(n_gauss), _prec(precision), float(near_cutoff_a),
+                                          int(n_steps), float(dt), C.byref(jn), pr, None, _stream(stream)))
+    return rate_avg_out
 
 
 def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t,

@@ -70,6 +70,7 @@ enum Slot {
     WS_NEAR_CORR,      //   per-pair end-force corrections
     WS_BLOCK_A,        // block coupling: nodal values of the projection
     WS_BLOCK_FAC,      //   tridiagonal factors
+    WS_HELD,           // junctions: nodes held in this step
     WS_NSLOTS
 };
 

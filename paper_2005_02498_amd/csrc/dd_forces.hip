@@ -390,8 +390,8 @@ __global__ void k_glide(Layout L, const int32_t *__restrict__ ptr, const int32_t
                         const int32_t *__restrict__ seg_nodes, const double *__restrict__ normal,
                         const double *__restrict__ rec, double a, double *x,
                         const double *__restrict__ F, const uint8_t *__restrict__ pinned,
-                        const uint8_t *__restrict__ active, double invB, double dt,
-                        double *__restrict__ vel)
+                        const uint8_t *__restrict__ held, const uint8_t *__restrict__ active, double invB,
+                        double dt, double *__restrict__ vel)
 {
     int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nn = L.nn, ns = L.ns;
@@ -426,7 +426,7 @@ __global__ void k_glide(Layout L, const int32_t *__restrict__ ptr, const int32_t
         }
     }
     double v0 = 0, v1 = 0, v2 = 0;
-    const bool fixed = idle || (pinned && pinned[n]) || !(ell > 0.0) || cnt == 0 || cnt >= 3;
+    const bool fixed = idle || (pinned && pinned[n]) || (held && held[n]) || !(ell > 0.0) || cnt == 0 || cnt >= 3;
     if (!fixed) {
         const double sc = invB / ell;
         v0 = F[n] * sc;
@@ -457,6 +457,104 @@ __global__ void k_glide(Layout L, const int32_t *__restrict__ ptr, const int32_t
         x[nn + n] += v1 * dt;
         x[2 * nn + n] += v2 * dt;
     }
+}
+
+// ----------------------------------- junctions and thermal activation --
+// Squared distance from p to the segment a -> b, written out without fused
+// multiply-adds (the capture decision must match the oracle's bit for bit).
+__device__ __forceinline__ double point_segment_d2(const double *p, const double *a, const double *b)
+{
+#pragma clang fp contract(off)
+    const double d0 = b[0] - a[0], d1 = b[1] - a[1], d2 = b[2] - a[2];
+    const double w0 = p[0] - a[0], w1 = p[1] - a[1], w2 = p[2] - a[2];
+    const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+    double t = (w0 * d0 + w1 * d1 + w2 * d2) / dd;
+    t = fmin(fmax(t, 0.0), 1.0);
+    const double e0 = p[0] - (a[0] + t * d0);
+    const double e1 = p[1] - (a[1] + t * d1);
+    const double e2 = p[2] - (a[2] + t * d2);
+    return e0 * e0 + e1 * e1 + e2 * e2;
+}
+
+__device__ __forceinline__ double release_time(double t, double f, double a)
+{
+#pragma clang fp contract(off)
+    return t + f * a;
+}
+
+struct JunctionArgs {
+    double rc2, rf2, a, t;   // capture radius^2, (2 capture radius)^2, maximum breaking time, time
+    int32_t K;
+    const double *fractions;
+    int32_t *junction, *ignore, *count;
+    double *release;
+};
+
+// Junction checks at the start of a step (Sec. "Thermal activation", Eq. tb),
+// one thread per node: a held node is released once t reaches its release
+// time; a free mobile node forgets the segment it last broke from beyond
+// 2 r_c, then is captured by the first sessile segment of its instance (both
+// nodes pinned), in index order and other than that one, closer than r_c,
+// with release = t + f a, f = fractions[n][count mod K].  held[n] = 1 for the
+// nodes the glide step must keep fixed.
+__global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
+                            const uint8_t *__restrict__ pinned, JunctionArgs J, int n_inst, uint8_t *__restrict__ held)
+{
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t nn = L.nn;
+    if (n >= nn) return;
+    if (!pinned || pinned[n]) {
+        held[n] = 0;
+        return;
+    }
+    const int32_t js = J.junction[n];
+    if (js >= 0) {
+        if (J.t >= J.release[n]) {
+            J.ignore[n] = js;
+            J.junction[n] = -1;
+            held[n] = 0;
+        } else {
+            held[n] = 1;
+        }
+        return;
+    }
+    // the node's instance: last i with node_off[i] <= n
+    int lo = 0, hi = n_inst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (L.node_off[mid] <= n) lo = mid; else hi = mid;
+    }
+    const int64_t sb = L.seg_off[lo], se = L.seg_off[lo + 1];
+    const double p[3] = {x[n], x[nn + n], x[2 * nn + n]};
+    int64_t ig = J.ignore[n];
+    if (ig >= sb && ig < se) {
+        int64_t g1, g2;
+        seg_ends(L, seg_nodes, ig, g1, g2);
+        const double a[3] = {x[g1], x[nn + g1], x[2 * nn + g1]}, b[3] = {x[g2], x[nn + g2], x[2 * nn + g2]};
+        if (point_segment_d2(p, a, b) > J.rf2) {
+            ig = -1;
+            J.ignore[n] = -1;
+        }
+    } else {
+        ig = -1;
+    }
+    for (int64_t s = sb; s < se; ++s) {
+        if (s == ig) continue;
+        int64_t g1, g2;
+        seg_ends(L, seg_nodes, s, g1, g2);
+        if (!(pinned[g1] && pinned[g2])) continue;
+        const double a[3] = {x[g1], x[nn + g1], x[2 * nn + g1]}, b[3] = {x[g2], x[nn + g2], x[2 * nn + g2]};
+        if (point_segment_d2(p, a, b) < J.rc2) {
+            const int32_t c = J.count[n];
+            const int32_t k = ((c % J.K) + J.K) % J.K;
+            J.junction[n] = (int32_t)s;
+            J.release[n] = release_time(J.t, J.fractions[n * J.K + k], J.a);
+            J.count[n] = c + 1;
+            held[n] = 1;
+            return;
+        }
+    }
+    held[n] = 0;
 }
 
 __global__ void k_euler(int64_t nn, double *x, const double *__restrict__ vel, double dt)
@@ -1153,7 +1251,7 @@ int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, con
         launch_forces(C, ws, B.x, B.seg_nodes, B.burgers, B.normal, sigma_dev, sv, F, cs);
         hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L, C.csr_ptr,
                            C.csr_list, B.seg_nodes, B.normal, C.rec64, C.a, B.x, F, B.pinned,
-                           (const uint8_t *)d_act, 1.0 / B.mat.B, B.dt, vel);
+                           (const uint8_t *)nullptr, (const uint8_t *)d_act, 1.0 / B.mat.B, B.dt, vel);
         hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 2, B.seg_nodes, C.rec64, C.sys,
                            vel, B.pinned, B.volume, sigma_dev, C.a, sums_dev);
     }
@@ -1306,7 +1404,7 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
     }
     hipLaunchKernelGGL(k_glide<false>, dim3(grid_for(n_nodes, 256, INT32_MAX)), dim3(256), 0, st, L,
                        C.csr_ptr, C.csr_list, seg_nodes, normal, (const double *)nullptr, 1.0, x, force,
-                       pinned, (const uint8_t *)nullptr, 1.0 / m->B, dt, vel);
+                       pinned, (const uint8_t *)nullptr, (const uint8_t *)nullptr, 1.0 / m->B, dt, vel);
     hipLaunchKernelGGL(k_euler, dim3(grid_for(3 * n_nodes, 256, INT32_MAX)), dim3(256), 0, st, n_nodes, x,
                        vel, dt);
     DD_HIP(hipGetLastError());
@@ -1318,14 +1416,14 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
     return DD_OK;
 }
 
-extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
-                              const int32_t *seg_nodes, const double *burgers, const double *normal,
-                              const uint8_t *pinned, const double *sigma_app, const double *volume,
-                              const dd_material *m, int n_gauss, int precision, double near_cutoff_a,
-                              int n_steps, double dt, double *rate_avg_out, double *features_out,
-                              void *stream)
+namespace dd {
+namespace {
+int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                     const int32_t *seg_nodes, const double *burgers, const double *normal, const uint8_t *pinned,
+                     const double *sigma_app, const double *volume, const dd_material *m, int n_gauss, int precision,
+                     double near_cutoff_a, int n_steps, double dt, const dd_junctions *jn, double *rate_avg_out,
+                     double *features_out, void *stream)
 {
-    clear_error();
     int rc;
     if (n_inst < 0) return set_error(DD_EINVAL, "n_inst < 0");
     if (n_inst == 0) return DD_OK;
@@ -1345,6 +1443,14 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
     if (!sigma_app || !volume || !rate_avg_out) return set_error(DD_EINVAL, "null sigma_app, volume or rate_avg_out");
     if (nn > 0 && !x) return set_error(DD_EINVAL, "null x");
     if (ns > 0 && (!seg_nodes || !burgers || !normal)) return set_error(DD_EINVAL, "null segment array");
+    if (jn) {
+        if (!(jn->capture_radius >= 0.0) || !std::isfinite(jn->capture_radius) || !(jn->max_break_time >= 0.0) ||
+            !std::isfinite(jn->max_break_time) || !std::isfinite(jn->t0))
+            return set_error(DD_EINVAL, "junctions: capture radius and breaking time must be finite and >= 0, t0 finite");
+        if (jn->n_fractions < 1) return set_error(DD_EINVAL, "junctions: n_fractions must be >= 1");
+        if (nn > 0 && (!jn->fractions || !jn->junction || !jn->release || !jn->ignore || !jn->count))
+            return set_error(DD_EINVAL, "junctions: null state or fractions array");
+    }
     hipStream_t st = (hipStream_t)stream;
     Workspace *ws;
     if ((rc = workspace(&ws))) return rc;
@@ -1383,6 +1489,21 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
     double *vel = (double *)p;
     if ((rc = ensure(ws, WS_FORCE, sizeof(double) * 3 * std::max<int64_t>(nn, 1), &p))) return rc;
     double *F = (double *)p;
+    uint8_t *held = nullptr;
+    JunctionArgs J{};
+    if (jn) {
+        if ((rc = ensure(ws, WS_HELD, std::max<int64_t>(nn, 1), &p))) return rc;
+        held = (uint8_t *)p;
+        J.rc2 = jn->capture_radius * jn->capture_radius;
+        J.rf2 = (2.0 * jn->capture_radius) * (2.0 * jn->capture_radius);
+        J.a = jn->max_break_time;
+        J.K = jn->n_fractions;
+        J.fractions = jn->fractions;
+        J.junction = jn->junction;
+        J.ignore = jn->ignore;
+        J.count = jn->count;
+        J.release = jn->release;
+    }
 
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
     launch_csr(C, seg_nodes, st);
@@ -1420,10 +1541,15 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
         DD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
         ws->capturing = true;
         for (int k = 0; k < n_steps; ++k) {
+            if (jn) {
+                J.t = jn->t0 + k * dt;
+                hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L, seg_nodes,
+                                   (const double *)x, pinned, J, n_inst, held);
+            }
             launch_forces(C, ws, x, seg_nodes, burgers, normal, sigma_app, sv, F, cs);
             hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
                                C.csr_ptr, C.csr_list, seg_nodes, normal, C.rec64, C.a, x, F, pinned,
-                               (const uint8_t *)nullptr, 1.0 / m->B, dt, vel);
+                               (const uint8_t *)held, (const uint8_t *)nullptr, 1.0 / m->B, dt, vel);
             hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 0, seg_nodes, C.rec64,
                                C.sys, vel, pinned, volume, sigma_app, C.a, rate_avg_out);
         }
@@ -1457,4 +1583,33 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
     }
     DD_HIP(hipStreamSynchronize(st));
     return DD_OK;
+}
+}  // namespace
+}  // namespace dd
+
+extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                              const int32_t *seg_nodes, const double *burgers, const double *normal,
+                              const uint8_t *pinned, const double *sigma_app, const double *volume,
+                              const dd_material *m, int n_gauss, int precision, double near_cutoff_a,
+                              int n_steps, double dt, double *rate_avg_out, double *features_out,
+                              void *stream)
+{
+    clear_error();
+    return burst_batch_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m,
+                            n_gauss, precision, near_cutoff_a, n_steps, dt, nullptr, rate_avg_out, features_out,
+                            stream);
+}
+
+extern "C" int dd_burst_batch_junctions(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                                        const int32_t *seg_nodes, const double *burgers, const double *normal,
+                                        const uint8_t *pinned, const double *sigma_app, const double *volume,
+                                        const dd_material *m, int n_gauss, int precision, double near_cutoff_a,
+                                        int n_steps, double dt, const dd_junctions *junctions, double *rate_avg_out,
+                                        double *features_out, void *stream)
+{
+    clear_error();
+    if (!junctions) return set_error(DD_EINVAL, "null junction parameters");
+    return burst_batch_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m,
+                            n_gauss, precision, near_cutoff_a, n_steps, dt, junctions, rate_avg_out, features_out,
+                            stream);
 }
