@@ -582,6 +582,27 @@ def main():
                   "steps": args.burst_steps, "seconds": t1 - t0, "pairs": bpairs,
                   "pairs_per_s": bpairs / (t1 - t0),
                   "finite": bool(torch.isfinite(rates).all().item())}
+        # the same bursts with junctions: capture radius 10 b, maximum breaking
+        # time 50 steps, uniform fractions (4 per node)
+        xj = torch.tensor(bt.x, device=dev)
+        nn_b = int(bt.node_off[-1])
+        jstate = {"junction": torch.full((nn_b,), -1, dtype=torch.int32, device=dev),
+                  "release": torch.zeros(nn_b, dtype=torch.float64, device=dev),
+                  "ignore": torch.full((nn_b,), -1, dtype=torch.int32, device=dev),
+                  "count": torch.zeros(nn_b, dtype=torch.int32, device=dev)}
+        frac = torch.rand((nn_b, 4), dtype=torch.float64, device=dev,
+                          generator=torch.Generator(device=dev).manual_seed(3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dd.dd_burst_batch_junctions(bt.node_off, bt.seg_off, xj, d["sn"], d["b"], d["n"], d["p"], d["s"],
+                                    d["v"], mat, jstate, frac, 10.0, 50 * W.DT, 0.0, 2, dd.DD_MIXED, 20.0,
+                                    args.burst_steps, W.DT)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        bursts["with_junctions"] = {"capture_radius_b": 10.0, "max_break_time_steps": 50,
+                                    "seconds": t1 - t0, "pairs_per_s": bpairs / (t1 - t0),
+                                    "junctions_formed": int(jstate["count"].sum().item()),
+                                    "held_at_end": int((jstate["junction"] >= 0).sum().item())}
         if args.only == "burst":
             print(json.dumps(bursts))
             return

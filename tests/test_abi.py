@@ -69,3 +69,8 @@ def test_host_only_calls_without_gpu():
     assert dd.lib().dd_dissipation_fix(-1, fake, fake, fake, fake, None) == dd.DD_EINVAL
     assert dd.lib().dd_dissipation_fix(4, None, fake, fake, fake, None) == dd.DD_EINVAL
     assert dd.lib().dd_dissipation_fix(4, fake, None, None, fake, None) == dd.DD_EINVAL
+    off = (ctypes.c_int64 * 2)(0, 4)
+    m = dd.Material(1.0, 0.3, 1.0, 1.0)
+    assert dd.lib().dd_burst_batch_junctions(1, off, off, fake, fake, fake, fake, fake, fake, fake,
+                                             ctypes.byref(m), 2, 0, 20.0, 1, 1.0, None, fake, None,
+                                             None) == dd.DD_EINVAL
