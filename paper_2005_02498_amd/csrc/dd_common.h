@@ -71,6 +71,8 @@ enum Slot {
     WS_BLOCK_A,        // block coupling: nodal values of the projection
     WS_BLOCK_FAC,      //   tridiagonal factors
     WS_HELD,           // junctions: nodes held in this step
+    WS_SES,            //   sessile-segment flags, positions, indices
+    WS_SES_X,          //   their end points and bounding spheres
     WS_NSLOTS
 };
 

@@ -484,11 +484,70 @@ __device__ __forceinline__ double release_time(double t, double f, double a)
 
 struct JunctionArgs {
     double rc2, rf2, a, t;   // capture radius^2, (2 capture radius)^2, maximum breaking time, time
+    double rc;               // capture radius
     int32_t K;
     const double *fractions;
     int32_t *junction, *ignore, *count;
     double *release;
+    // sessile segments in index order: position in the list of segment s
+    // (valid where s is sessile; pos[seg_off[i]] .. pos[seg_off[i + 1]] are
+    // instance i's), their indices, end points (their nodes never move) and
+    // bounding spheres per JUNC_GROUP consecutive entries
+    const int32_t *pos, *ses_idx;
+    const double *ses_x, *ses_sph;
 };
+constexpr int JUNC_GROUP = 8;
+
+// Sessile segments (both nodes pinned): flags for the scan.
+__global__ void k_ses_flag(Layout L, const int32_t *__restrict__ seg_nodes, const uint8_t *__restrict__ pinned,
+                           int32_t *__restrict__ flag)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= L.ns) return;
+    int64_t g1, g2;
+    seg_ends(L, seg_nodes, s, g1, g2);
+    flag[s] = pinned && pinned[g1] && pinned[g2] ? 1 : 0;
+}
+
+// The compact list of sessile segments and their end points.
+__global__ void k_ses_compact(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
+                              const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
+                              int32_t *__restrict__ idx, double *__restrict__ sx)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= L.ns || !flag[s]) return;
+    int64_t g1, g2;
+    seg_ends(L, seg_nodes, s, g1, g2);
+    const int64_t q = pos[s], nn = L.nn;
+    idx[q] = (int32_t)s;
+    double *o = sx + 6 * q;
+    o[0] = x[g1]; o[1] = x[nn + g1]; o[2] = x[2 * nn + g1];
+    o[3] = x[g2]; o[4] = x[nn + g2]; o[5] = x[2 * nn + g2];
+}
+
+// Bounding sphere of JUNC_GROUP consecutive entries of the list: centre = the
+// first segment's midpoint, radius = max |m_i - C| + L_i / 2, so that a point
+// closer than r to any of them is closer than R + r to C.
+__global__ void k_ses_spheres(int64_t ns, const int32_t *__restrict__ pos, const double *__restrict__ sx,
+                              double *__restrict__ sph)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n_ses = pos[ns];
+    const int64_t q0 = g * JUNC_GROUP;
+    if (q0 >= n_ses) return;
+    const int64_t q1 = q0 + JUNC_GROUP < n_ses ? q0 + JUNC_GROUP : n_ses;
+    const double *f = sx + 6 * q0;
+    const double c0 = 0.5 * (f[0] + f[3]), c1 = 0.5 * (f[1] + f[4]), c2 = 0.5 * (f[2] + f[5]);
+    double r = 0.0;
+    for (int64_t q = q0; q < q1; ++q) {
+        const double *e = sx + 6 * q;
+        const double m0 = 0.5 * (e[0] + e[3]) - c0, m1 = 0.5 * (e[1] + e[4]) - c1, m2 = 0.5 * (e[2] + e[5]) - c2;
+        const double d0 = e[3] - e[0], d1 = e[4] - e[1], d2 = e[5] - e[2];
+        r = fmax(r, sqrt(m0 * m0 + m1 * m1 + m2 * m2) + 0.5 * sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+    }
+    double *o = sph + 4 * g;
+    o[0] = c0; o[1] = c1; o[2] = c2; o[3] = r;
+}
 
 // Junction checks at the start of a step (Sec. "Thermal activation", Eq. tb),
 // one thread per node: a held node is released once t reaches its release
@@ -496,7 +555,8 @@ struct JunctionArgs {
 // 2 r_c, then is captured by the first sessile segment of its instance (both
 // nodes pinned), in index order and other than that one, closer than r_c,
 // with release = t + f a, f = fractions[n][count mod K].  held[n] = 1 for the
-// nodes the glide step must keep fixed.
+// nodes the glide step must keep fixed.  The sessile segments come from the
+// compact list; groups whose sphere is out of reach are skipped.
 __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
                             const uint8_t *__restrict__ pinned, JunctionArgs J, int n_inst, uint8_t *__restrict__ held)
 {
@@ -538,20 +598,28 @@ __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, con
     } else {
         ig = -1;
     }
-    for (int64_t s = sb; s < se; ++s) {
-        if (s == ig) continue;
-        int64_t g1, g2;
-        seg_ends(L, seg_nodes, s, g1, g2);
-        if (!(pinned[g1] && pinned[g2])) continue;
-        const double a[3] = {x[g1], x[nn + g1], x[2 * nn + g1]}, b[3] = {x[g2], x[nn + g2], x[2 * nn + g2]};
-        if (point_segment_d2(p, a, b) < J.rc2) {
-            const int32_t c = J.count[n];
-            const int32_t k = ((c % J.K) + J.K) % J.K;
-            J.junction[n] = (int32_t)s;
-            J.release[n] = release_time(J.t, J.fractions[n * J.K + k], J.a);
-            J.count[n] = c + 1;
-            held[n] = 1;
-            return;
+    // the instance's sessile segments, in index order, sphere by sphere
+    const int64_t q_lo = J.pos[sb], q_hi = J.pos[se];
+    for (int64_t g = q_lo / JUNC_GROUP; g * JUNC_GROUP < q_hi; ++g) {
+        const double *c = J.ses_sph + 4 * g;
+        const double e0 = p[0] - c[0], e1 = p[1] - c[1], e2 = p[2] - c[2];
+        const double rr = (c[3] + J.rc) * (1.0 + 1e-9);
+        if (e0 * e0 + e1 * e1 + e2 * e2 >= rr * rr) continue;
+        const int64_t qa = g * JUNC_GROUP > q_lo ? g * JUNC_GROUP : q_lo;
+        const int64_t qb = (g + 1) * JUNC_GROUP < q_hi ? (g + 1) * JUNC_GROUP : q_hi;
+        for (int64_t q = qa; q < qb; ++q) {
+            const int64_t s = J.ses_idx[q];
+            if (s == ig) continue;
+            const double *e = J.ses_x + 6 * q;
+            if (point_segment_d2(p, e, e + 3) < J.rc2) {
+                const int32_t cn = J.count[n];
+                const int32_t k = ((cn % J.K) + J.K) % J.K;
+                J.junction[n] = (int32_t)s;
+                J.release[n] = release_time(J.t, J.fractions[n * J.K + k], J.a);
+                J.count[n] = cn + 1;
+                held[n] = 1;
+                return;
+            }
         }
     }
     held[n] = 0;
@@ -1503,6 +1571,24 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
         J.ignore = jn->ignore;
         J.count = jn->count;
         J.release = jn->release;
+        J.rc = jn->capture_radius;
+        // the compact list of sessile segments (their nodes do not move during the burst)
+        if ((rc = ensure(ws, WS_SES, sizeof(int32_t) * (3 * ns + 1), &p))) return rc;
+        int32_t *flag = (int32_t *)p, *pos = flag + ns, *idx = pos + ns + 1;
+        if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (6 * ns + 4 * ((ns + JUNC_GROUP - 1) / JUNC_GROUP) + 4), &p)))
+            return rc;
+        double *sx = (double *)p, *sph = sx + 6 * ns;
+        const unsigned gs = grid_for(ns, 256, INT32_MAX);
+        hipLaunchKernelGGL(k_ses_flag, dim3(gs), dim3(256), 0, st, C.L, seg_nodes, pinned, flag);
+        hipLaunchKernelGGL((k_scan<int32_t>), dim3(1), dim3(1024), 0, st, (const int32_t *)flag, ns, pos);
+        hipLaunchKernelGGL(k_ses_compact, dim3(gs), dim3(256), 0, st, C.L, seg_nodes, (const double *)x,
+                           (const int32_t *)flag, (const int32_t *)pos, idx, sx);
+        hipLaunchKernelGGL(k_ses_spheres, dim3(grid_for((ns + JUNC_GROUP - 1) / JUNC_GROUP, 256, INT32_MAX)),
+                           dim3(256), 0, st, ns, (const int32_t *)pos, (const double *)sx, sph);
+        J.pos = pos;
+        J.ses_idx = idx;
+        J.ses_x = sx;
+        J.ses_sph = sph;
     }
 
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
