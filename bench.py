@@ -96,7 +96,7 @@ def parse():
                     help="with --only fp64|mixed: exact target integral for pairs closer than this band")
     ap.add_argument("--burst-instances", type=int, default=512)
     ap.add_argument("--burst-steps", type=int, default=200)
-    ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy", "surrogate"], default=None,
+    ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy", "surrogate", "blocks"], default=None,
                     help="profiling aid: run only one part (no JSON contract)")
     ap.add_argument("--surrogate-study", action="store_true",
                     help="run the surrogate speed-up-at-fixed-error study and write --study-out")
@@ -387,6 +387,50 @@ def main():
         chunk, items, variant = dd.dd_last_plan()
         return (t1 - t0) / steps, kms / 1e3 / launches, (near / launches, quad / launches, variant, chunk, items)
 
+    def block_coupling(sizes=((20, 10), (50, 20)), reps=20):
+        """One continuum increment's block coupling: block stress averages (9
+        components), L^p (9) and V (3) from the blocks to every Gauss point, and
+        the non-negative-dissipation fix."""
+        res = {}
+        for nb, mb in sizes:
+            ngp = (nb * mb) ** 2 * 8
+            gen = torch.Generator(device=dev).manual_seed(5)
+            T_gp = torch.randn((ngp, 9), dtype=torch.float64, device=dev, generator=gen)
+            al_gp = torch.randn((ngp, 9), dtype=torch.float64, device=dev, generator=gen)
+            Lp_b = torch.randn((nb * nb, 9), dtype=torch.float64, device=dev, generator=gen)
+            V_b = torch.randn((nb * nb, 3), dtype=torch.float64, device=dev, generator=gen)
+            T_b = torch.empty((nb * nb, 9), dtype=torch.float64, device=dev)
+            Lp_gp = torch.empty((ngp, 9), dtype=torch.float64, device=dev)
+            V_gp = torch.empty((ngp, 3), dtype=torch.float64, device=dev)
+
+            def coupling():
+                dd.dd_block_average(T_gp, nb, mb, 1.0, 0.2, out=T_b)
+                dd.dd_block_to_gauss(Lp_b, nb, mb, 1.0, 0.2, out=Lp_gp)
+                dd.dd_block_to_gauss(V_b, nb, mb, 1.0, 0.2, out=V_gp)
+                dd.dd_dissipation_fix(T_gp, al_gp, Lp_gp, V_gp)
+
+            for _ in range(3):
+                coupling()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                coupling()
+            torch.cuda.synchronize()
+            tc = (time.perf_counter() - t0) / reps
+            # doubles per Gauss point that must move: average reads T (9); the
+            # interpolations write L^p and V (12); the fix reads T, alpha, L^p, V
+            # (30) and writes L^p, V (12)
+            byts = ngp * 8 * 63
+            res[f"block_coupling_{nb}x{nb}_blocks_{mb}x{mb}_elements"] = {
+                "gauss_points": ngp, "ms_per_increment": tc * 1e3, "min_bytes": byts,
+                "effective_GB_per_s": byts / tc / 1e9}
+            del T_gp, al_gp, Lp_gp, V_gp
+        return res
+
+    if args.only == "blocks":
+        print(json.dumps(block_coupling(((5, 10), (20, 10), (50, 20), (100, 20)), reps=max(1, args.steps))))
+        return
+
     # measured FMA rates: FP64 with a scalar-register operand (the FP64 kernel's
     # form), FP32 with vector-register operands (the FP32 quadrature's form)
     peaks_measured = {k: dd.dd_vector_peak(k, 20) * 1e12 for k in ("fp64", "fp32", "fp64_vec", "fp32_vec")}
@@ -488,41 +532,7 @@ def main():
             extras[name] = {"eta": eta, "near_pairs_per_step": n_near, "ms_per_step": s_b * 1e3,
                             "plain_ms_per_step": base * 1e3, "overhead_ms": (s_b - base) * 1e3,
                             "ns_per_near_pair": (s_b - base) * 1e9 / max(n_near, 1)}
-        # block coupling of one continuum increment: block stress averages (9
-        # components), L^p (9) and V (3) from the blocks to every Gauss point,
-        # and the non-negative-dissipation fix
-        for nb, mb in ((20, 10), (50, 20)):
-            ngp = (nb * mb) ** 2 * 8
-            gen = torch.Generator(device=dev).manual_seed(5)
-            T_gp = torch.randn((ngp, 9), dtype=torch.float64, device=dev, generator=gen)
-            al_gp = torch.randn((ngp, 9), dtype=torch.float64, device=dev, generator=gen)
-            Lp_b = torch.randn((nb * nb, 9), dtype=torch.float64, device=dev, generator=gen)
-            V_b = torch.randn((nb * nb, 3), dtype=torch.float64, device=dev, generator=gen)
-            T_b = torch.empty((nb * nb, 9), dtype=torch.float64, device=dev)
-            Lp_gp = torch.empty((ngp, 9), dtype=torch.float64, device=dev)
-            V_gp = torch.empty((ngp, 3), dtype=torch.float64, device=dev)
-
-            def coupling():
-                dd.dd_block_average(T_gp, nb, mb, 1.0, 0.2, out=T_b)
-                dd.dd_block_to_gauss(Lp_b, nb, mb, 1.0, 0.2, out=Lp_gp)
-                dd.dd_block_to_gauss(V_b, nb, mb, 1.0, 0.2, out=V_gp)
-                dd.dd_dissipation_fix(T_gp, al_gp, Lp_gp, V_gp)
-
-            for _ in range(3):
-                coupling()
-            torch.cuda.synchronize()
-            reps = 20
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                coupling()
-            torch.cuda.synchronize()
-            tc = (time.perf_counter() - t0) / reps
-            # bytes that must move: read T, alpha (twice for T) and write L^p, V at every Gauss point
-            byts = ngp * 8 * (9 + 9 + 9 + 9 + 3 + 9 + 3)
-            extras[f"block_coupling_{nb}x{nb}_blocks_{mb}x{mb}_elements"] = {
-                "gauss_points": ngp, "ms_per_increment": tc * 1e3, "min_bytes": byts,
-                "effective_GB_per_s": byts / tc / 1e9}
-            del T_gp, al_gp, Lp_gp, V_gp
+        extras.update(block_coupling())
         # the 262,144-segment volume (radii 50-2000 b, 50,000 b cube): one step per precision
         big = W.config3()
         vb = resident(big)
