@@ -106,7 +106,7 @@ def parse():
     ap.add_argument("--study-epochs", type=int, default=200)
     ap.add_argument("--study-reuse-train", default=None,
                     help="npz written by an earlier study run: reuse its training bursts")
-    ap.add_argument("--study-out", default=os.path.join(ROOT, "gpurun_out", "surrogate_study.json"))
+    ap.add_argument("--study-out", default=os.path.join(ROOT, "study", "surrogate_study.json"))
     return ap.parse_args()
 
 
