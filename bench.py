@@ -423,7 +423,10 @@ def main():
             byts = ngp * 8 * 63
             res[f"block_coupling_{nb}x{nb}_blocks_{mb}x{mb}_elements"] = {
                 "gauss_points": ngp, "ms_per_increment": tc * 1e3, "min_bytes": byts,
-                "effective_GB_per_s": byts / tc / 1e9}
+                "effective_GB_per_s": byts / tc / 1e9,
+                "roofline": {"bound": "hbm", "achieved": byts / tc / 1e9, "peak": 8000.0, "unit": "GB/s",
+                             "frac": byts / tc / 8e12,
+                             "note": "all calls of one increment together; small meshes are launch-bound"}}
             del T_gp, al_gp, Lp_gp, V_gp
         return res
 
