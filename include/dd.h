@@ -373,6 +373,26 @@ int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off,
                 const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
                 int precision, double near_cutoff_a, double *out, void *stream);
 
+/* dd_pta_step with junctions (see dd_junctions; Sec. "Thermal activation"):
+ * every fast step runs the junction checks first.  The junction state
+ * travels with the microstructure: each fast run carries it on from the state
+ * it starts from, step 5 continues the t - delta run with the state of that
+ * run's own end, and the state at the end of step 2 is what the call leaves
+ * in the junction arrays, as for x.  The clock of the checks is the volume's
+ * fast clock, fast_steps[i] * dt at the first step, one dt per fast step
+ * (junctions->t0 is not used); fast_steps HOST [n_inst] int64, >= 0, in and
+ * out: the fast steps the volume had taken, advanced by those of the run
+ * carried on.  The other arguments as dd_pta_step.
+ * Errors: DD_EINVAL as dd_pta_step, for a null junctions or fast_steps, a
+ *  negative fast_steps entry, or junction parameters dd_burst_batch_junctions
+ *  rejects. */
+int dd_pta_step_junctions(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                          const int32_t *seg_nodes, const double *burgers, const double *normal,
+                          const uint8_t *pinned, const double *volume, const double *stress_rate,
+                          const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
+                          int precision, double near_cutoff_a, const dd_junctions *junctions,
+                          int64_t *fast_steps, double *out, void *stream);
+
 /* Block coupling of the DD boxes to the continuum mesh (Sec. "DD-MFDM
  * coupling").  The domain is n x n square blocks of side B and thickness h,
  * one brick through the thickness (one DD box per block); every block is

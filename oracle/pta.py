@@ -30,6 +30,13 @@ Readings taken where the paper is silent:
   step is the end state of step 2;
 * Lpdot and rhodot are formed after step 5 (the jump test uses the values
   before it); the slow step is h = min(h_max, strain_step / |R^Lp_t|).
+
+With junctions (``Junctions``, the rule of oracle/junctions.py) the junction
+state and the fast clock travel with the microstructure: each fast run
+carries them on from the state it starts from, the fast clock of a step is
+(fast steps taken so far) * dt, and step 5 continues the t - Delta run with
+the junction state and clock of its own end, after which the state of the end
+of step 2 is carried on, as for the positions.
 """
 from __future__ import annotations
 
@@ -39,6 +46,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import burst, fcc_system
+from . import junctions as OJ
 
 
 @dataclass
@@ -70,11 +78,21 @@ def converged(prev, now, tol, norm):
 
 
 @dataclass
+class Junctions:
+    r_c: float                 # capture radius, b
+    a_max: float               # maximum breaking time a, s
+    fractions: np.ndarray      # [nn][K] uniform numbers f of Eq. tb
+    state: dict                # per node junction, release, ignore, count
+    fast: int = 0              # fast steps taken so far (the fast clock)
+
+
+@dataclass
 class Run:
     x: np.ndarray        # state at the end of the run
     sums: np.ndarray     # [13]: sum over the steps of gdot (12) and rho
     steps: int
     converged: bool
+    jn: Junctions | None = None   # junction state and clock at the end of the run
 
     @property
     def rho(self):
@@ -85,29 +103,43 @@ class Run:
         return lp_from_rates(self.sums[:12] / self.steps)
 
 
-def _one_step(inst, x, sigma, mat, Q, dt):
-    """Lambda at state x and the state after one glide step."""
+def _copy_jn(jn):
+    if jn is None:
+        return None
+    return Junctions(jn.r_c, jn.a_max, jn.fractions, {k: v.copy() for k, v in jn.state.items()}, jn.fast)
+
+
+def _one_step(inst, x, sigma, mat, Q, dt, jn=None):
+    """Lambda at state x and the state after one glide step (after the
+    junction checks at the fast clock, with the held nodes fixed, when `jn`
+    is given; its state and clock advance in place)."""
     s = copy.copy(inst)
     s.x = x
     s.sigma_app = np.asarray(sigma, float)
+    if jn is not None:
+        held = OJ.update(x, inst.seg_nodes, inst.pinned, float(jn.fast) * dt, jn.r_c, jn.a_max, jn.fractions,
+                         jn.state)
+        s.pinned = np.maximum(np.asarray(inst.pinned, np.uint8), held)
+        jn.fast += 1
     x1, rate, feat = burst(s, mat, Q, 1, dt)
     return x1, rate, float(np.sum(feat[12:]))
 
 
-def fast_run(inst, x, sigma, mat, Q, P: PTAParams, run: Run | None = None, max_chunks=None):
+def fast_run(inst, x, sigma, mat, Q, P: PTAParams, run: Run | None = None, max_chunks=None, jn=None):
     """Runs chunks of P.chunk steps at fixed load sigma until the running
     averages of rho and L^p converge (or max_chunks checks); continues `run`
-    (same state and sums) when it is given."""
+    (same state, sums and junction state) when it is given, else starts from
+    x and the junction state `jn` (copied)."""
     if run is None:
-        run = Run(np.array(x, float), np.zeros(13), 0, False)
+        run = Run(np.array(x, float), np.zeros(13), 0, False, _copy_jn(jn))
         prev = None
     else:
-        run = Run(run.x.copy(), run.sums.copy(), run.steps, False)
+        run = Run(run.x.copy(), run.sums.copy(), run.steps, False, _copy_jn(run.jn))
         prev = (run.rho, run.lp)
     max_chunks = P.max_chunks if max_chunks is None else max_chunks
     for c in range(max_chunks):
         for _ in range(P.chunk):
-            x1, rate, rho = _one_step(inst, run.x, sigma, mat, Q, P.dt)
+            x1, rate, rho = _one_step(inst, run.x, sigma, mat, Q, P.dt, run.jn)
             run.sums[:12] += rate
             run.sums[12] += rho
             run.steps += 1
@@ -121,20 +153,22 @@ def fast_run(inst, x, sigma, mat, Q, P: PTAParams, run: Run | None = None, max_c
     return run, max_chunks
 
 
-def pta_step(inst, t, sigma_rate, mat, Q, P: PTAParams):
+def pta_step(inst, t, sigma_rate, mat, Q, P: PTAParams, jn: Junctions | None = None):
     """One slow-time step at time t for one volume (its x is the current
-    microstructure).  Returns a dict with the converged averages, rates, the
-    next step size, counters and the microstructure to continue from."""
+    microstructure; `jn` its junction state and fast clock, if any).  Returns
+    a dict with the converged averages, rates, the next step size, counters
+    and the microstructure (and junction state) to continue from."""
     sigma_rate = np.asarray(sigma_rate, float)
     x0 = np.array(inst.x, float)
+    j0 = jn
     jumps = 0
     while True:
-        A, _ = fast_run(inst, x0, (t - P.delta) * sigma_rate, mat, Q, P)       # step 1
-        B, _ = fast_run(inst, A.x, t * sigma_rate, mat, Q, P)                   # step 2
-        lpdot = (B.lp - A.lp) / P.delta                                         # step 3
-        if np.linalg.norm(lpdot) > P.lpdot_max and jumps < P.max_jumps:         # step 4
+        A, _ = fast_run(inst, x0, (t - P.delta) * sigma_rate, mat, Q, P, jn=j0)      # step 1
+        B, _ = fast_run(inst, A.x, t * sigma_rate, mat, Q, P, jn=A.jn)                # step 2
+        lpdot = (B.lp - A.lp) / P.delta                                               # step 3
+        if np.linalg.norm(lpdot) > P.lpdot_max and jumps < P.max_jumps:               # step 4
             jumps += 1
-            x0 = B.x
+            x0, j0 = B.x, B.jn
             continue
         break
     rerun_chunks = 0                                                             # step 5
@@ -148,4 +182,4 @@ def pta_step(inst, t, sigma_rate, mat, Q, P: PTAParams):
     return {"rho_a": A.rho, "rho_b": B.rho, "g_a": A.sums[:12] / A.steps, "g_b": B.sums[:12] / B.steps,
             "lp_a": A.lp, "lp_b": B.lp, "lpdot": lpdot, "rhodot": rhodot, "h": h,
             "steps_a": A.steps, "steps_b": B.steps, "conv_a": A.converged, "conv_b": B.converged,
-            "jumps": jumps, "rerun_chunks": rerun_chunks, "x": B.x}
+            "jumps": jumps, "rerun_chunks": rerun_chunks, "x": B.x, "jn": B.jn}

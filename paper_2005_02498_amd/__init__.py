@@ -26,7 +26,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
     "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_exact_band", "dd_set_plan", "dd_last_plan",
-    "dd_nodal_forces", "dd_glide_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_pta_step",
+    "dd_nodal_forces", "dd_glide_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_pta_step", "dd_pta_step_junctions",
     "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -106,6 +106,11 @@ def _declare(L):
                                   vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(PTAParams), C.POINTER(Material), C.c_int, C.c_int, dbl,
                                   C.POINTER(C.c_double), vp]),
+        "dd_pta_step_junctions": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp, vp,
+                                            vp, vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                            C.POINTER(PTAParams), C.POINTER(Material), C.c_int, C.c_int, dbl,
+                                            C.POINTER(Junctions), C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                            vp]),
         "dd_set_plan": (C.c_int, [i64, C.c_int]),
         "dd_set_exact_band": (C.c_int, [C.c_double]),
         "dd_block_average": (C.c_int, [C.POINTER(BlockMesh), C.c_int, vp, vp, vp]),
@@ -383,17 +388,10 @@ def dd_burst_batch_junctions(node_off, seg_off, x, seg_nodes, burgers, normal, p
     pp = _dev(pinned, torch.uint8, (nn,), "pinned", nullable=True)
     ps = _dev(sigma_app, torch.float64, (n_inst, 6), "sigma_app")
     pv = _dev(volume, torch.float64, (n_inst,), "volume")
-    K = fractions.shape[1] if fractions.dim() == 2 else -1
-    pf = _dev(fractions, torch.float64, (nn, K), "fractions")
-    pj = _dev(state["junction"], torch.int32, (nn,), "junction")
-    prl = _dev(state["release"], torch.float64, (nn,), "release")
-    pig = _dev(state["ignore"], torch.int32, (nn,), "ignore")
-    pc = _dev(state["count"], torch.int32, (nn,), "count")
+    jn = _junction_args(state, fractions, capture_radius, max_break_time, nn, t0)
     if rate_avg_out is None:
         rate_avg_out = torch.empty((n_inst, 12), dtype=torch.float64, device=dev)
     pr = _dev(rate_avg_out, torch.float64, (n_inst, 12), "rate_avg_out")
-    jn = Junctions(float(capture_radius), float(max_break_time), float(t0), int(K), pf.value, pj.value,
-                   prl.value, pig.value, pc.value)
     m = _mat(mat)
     _check(lib().dd_burst_batch_junctions(n_inst, no, so, px, psn, pb, pn, pp, ps, pv, C.byref(m),
                                           int(n_gauss), _prec(precision), float(near_cutoff_a),
@@ -401,11 +399,27 @@ def dd_burst_batch_junctions(node_off, seg_off, x, seg_nodes, burgers, normal, p
     return rate_avg_out
 
 
+def _junction_args(state, fractions, capture_radius, max_break_time, nn, t0=0.0):
+    K = fractions.shape[1] if fractions.dim() == 2 else -1
+    pf = _dev(fractions, torch.float64, (nn, K), "fractions")
+    pj = _dev(state["junction"], torch.int32, (nn,), "junction")
+    prl = _dev(state["release"], torch.float64, (nn,), "release")
+    pig = _dev(state["ignore"], torch.int32, (nn,), "ignore")
+    pc = _dev(state["count"], torch.int32, (nn,), "count")
+    return Junctions(float(capture_radius), float(max_break_time), float(t0), int(K), pf.value, pj.value,
+                     prl.value, pig.value, pc.value)
+
+
 def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t,
-                params, mat, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0, stream=None):
+                params, mat, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0, stream=None, junctions=None):
     """One PTA slow-time step for every instance (see dd.h); x advances to the
     microstructure for the next step.  stress_rate [n_inst][6] (Pa/s) and t
-    [n_inst] (s) are host sequences.  Returns a dict of NumPy arrays."""
+    [n_inst] (s) are host sequences.  Returns a dict of NumPy arrays.
+
+    junctions: None, or a dict with keys state (device tensors as
+    dd_burst_batch_junctions, updated in place), fractions, capture_radius,
+    max_break_time and fast_steps (host int64 array [n_inst], updated in
+    place); then dd_pta_step_junctions runs."""
     import numpy as np
     no = (C.c_int64 * len(node_off))(*[int(v) for v in node_off])
     so = (C.c_int64 * len(seg_off))(*[int(v) for v in seg_off])
@@ -424,16 +438,38 @@ def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume
     out = np.zeros((n_inst, DD_PTA_OUT))
     m = _mat(mat)
     dp = C.POINTER(C.c_double)
-    _check(lib().dd_pta_step(n_inst, no, so, px, psn, pb, pn, pp, pv, sr.ctypes.data_as(dp),
-                             tt.ctypes.data_as(dp), C.byref(params), C.byref(m), int(n_gauss),
-                             _prec(precision), float(near_cutoff_a), out.ctypes.data_as(dp),
-                             _stream(stream)))
+    if junctions is None:
+        _check(lib().dd_pta_step(n_inst, no, so, px, psn, pb, pn, pp, pv, sr.ctypes.data_as(dp),
+                                 tt.ctypes.data_as(dp), C.byref(params), C.byref(m), int(n_gauss),
+                                 _prec(precision), float(near_cutoff_a), out.ctypes.data_as(dp),
+                                 _stream(stream)))
+    else:
+        jn = _junction_args(junctions["state"], junctions["fractions"], junctions["capture_radius"],
+                            junctions["max_break_time"], nn)
+        fs = junctions["fast_steps"]
+        if not (isinstance(fs, np.ndarray) and fs.dtype == np.int64 and fs.shape == (n_inst,)
+                and fs.flags.c_contiguous):
+            raise ValueError("junctions['fast_steps'] must be a contiguous int64 array of length n_inst")
+        _check(lib().dd_pta_step_junctions(n_inst, no, so, px, psn, pb, pn, pp, pv, sr.ctypes.data_as(dp),
+                                           tt.ctypes.data_as(dp), C.byref(params), C.byref(m), int(n_gauss),
+                                           _prec(precision), float(near_cutoff_a), C.byref(jn),
+                                           fs.ctypes.data_as(C.POINTER(C.c_int64)), out.ctypes.data_as(dp),
+                                           _stream(stream)))
     return {"rho_a": out[:, 0], "rho_b": out[:, 1], "g_a": out[:, 2:14], "g_b": out[:, 14:26],
             "lp_a": out[:, 26:35].reshape(n_inst, 3, 3), "lp_b": out[:, 35:44].reshape(n_inst, 3, 3),
             "lpdot": out[:, 44:53].reshape(n_inst, 3, 3), "rhodot": out[:, 53], "h": out[:, 54],
             "steps_a": out[:, 55].astype(int), "steps_b": out[:, 56].astype(int),
             "conv_a": out[:, 57] > 0, "conv_b": out[:, 58] > 0, "jumps": out[:, 59].astype(int),
             "rerun_chunks": out[:, 60].astype(int)}
+
+
+def dd_pta_step_junctions(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t,
+                          params, mat, junctions, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0, stream=None):
+    """dd_pta_step with junctions (dd.h); `junctions` as in dd_pta_step."""
+    if junctions is None:
+        raise ValueError("junctions is required")
+    return dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, params,
+                       mat, n_gauss, precision, near_cutoff_a, stream, junctions)
 
 
 # --------------------------------------------------------------- surrogate --

@@ -61,6 +61,9 @@ enum Slot {
     WS_PTA_XA,         //   saved positions (end of the t - Delta run)
     WS_PTA_XB,         //   saved positions (end of the t run)
     WS_PTA_MASK,       //   per-instance copy mask
+    WS_PTA_FAST,       //   per-instance fast steps (junctions)
+    WS_PTA_JA,         //   saved junction state (end of the t - Delta run)
+    WS_PTA_JB,         //   saved junction state (end of the t run)
     WS_NEAR_KEY,       // exact band: per-segment keys
     WS_NEAR_SPH,       //   per-group bounding spheres
     WS_NEAR_LIST,      //   per-target near sources
@@ -210,6 +213,11 @@ struct BurstBatch {
     int n_gauss = 2, precision = DD_FP64;
     double near_cut = 20.0, dt = 0.0;
     int64_t choice = 0;                       // encoded work split, set by burst_batch_init
+    // junctions (null: none): the caller's parameters and state, and per
+    // instance the fast steps taken so far (device), whose product with dt is
+    // the instance's fast clock
+    const dd_junctions *jn = nullptr;
+    const int64_t *fast_steps_dev = nullptr;
 };
 int burst_batch_init(BurstBatch &B, hipStream_t st);
 int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, const double *sigma_dev,

@@ -558,7 +558,9 @@ __global__ void k_ses_spheres(int64_t ns, const int32_t *__restrict__ pos, const
 // nodes the glide step must keep fixed.  The sessile segments come from the
 // compact list; groups whose sphere is out of reach are skipped.
 __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
-                            const uint8_t *__restrict__ pinned, JunctionArgs J, int n_inst, uint8_t *__restrict__ held)
+                            const uint8_t *__restrict__ pinned, JunctionArgs J, int n_inst,
+                            const uint8_t *__restrict__ active, const int64_t *__restrict__ fast_steps, double dt,
+                            int k, uint8_t *__restrict__ held)
 {
     const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t nn = L.nn;
@@ -567,9 +569,22 @@ __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, con
         held[n] = 0;
         return;
     }
+    // the node's instance: last i with node_off[i] <= n
+    int lo = 0, hi = n_inst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (L.node_off[mid] <= n) lo = mid; else hi = mid;
+    }
+    // an instance left out of this pass keeps its state (and does not move)
+    if (active && !active[lo]) {
+        held[n] = 0;
+        return;
+    }
+    // time: the instance's fast clock (steps taken so far times dt), or the call's
+    const double t = fast_steps ? (double)(fast_steps[lo] + k) * dt : J.t;
     const int32_t js = J.junction[n];
     if (js >= 0) {
-        if (J.t >= J.release[n]) {
+        if (t >= J.release[n]) {
             J.ignore[n] = js;
             J.junction[n] = -1;
             held[n] = 0;
@@ -577,12 +592,6 @@ __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, con
             held[n] = 1;
         }
         return;
-    }
-    // the node's instance: last i with node_off[i] <= n
-    int lo = 0, hi = n_inst;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (L.node_off[mid] <= n) lo = mid; else hi = mid;
     }
     const int64_t sb = L.seg_off[lo], se = L.seg_off[lo + 1];
     const double p[3] = {x[n], x[nn + n], x[2 * nn + n]};
@@ -613,9 +622,9 @@ __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, con
             const double *e = J.ses_x + 6 * q;
             if (point_segment_d2(p, e, e + 3) < J.rc2) {
                 const int32_t cn = J.count[n];
-                const int32_t k = ((cn % J.K) + J.K) % J.K;
+                const int32_t kf = ((cn % J.K) + J.K) % J.K;
                 J.junction[n] = (int32_t)s;
-                J.release[n] = release_time(J.t, J.fractions[n * J.K + k], J.a);
+                J.release[n] = release_time(t, J.fractions[n * J.K + kf], J.a);
                 J.count[n] = cn + 1;
                 held[n] = 1;
                 return;
@@ -623,6 +632,48 @@ __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, con
         }
     }
     held[n] = 0;
+}
+
+// Junction arguments from the caller's parameters, and the compact list of
+// sessile segments (flags, scan, compaction, spheres) for positions x; held
+// receives the per-node hold mask each step.
+int junction_prepare(Workspace *ws, const Layout &L, const int32_t *seg_nodes, const double *x,
+                     const uint8_t *pinned, const dd_junctions *jn, JunctionArgs &J, uint8_t **held,
+                     hipStream_t st)
+{
+    const int64_t nn = L.nn, ns = L.ns;
+    void *p;
+    int rc;
+    if ((rc = ensure(ws, WS_HELD, std::max<int64_t>(nn, 1), &p))) return rc;
+    *held = (uint8_t *)p;
+    J = JunctionArgs{};
+    J.rc2 = jn->capture_radius * jn->capture_radius;
+    J.rf2 = (2.0 * jn->capture_radius) * (2.0 * jn->capture_radius);
+    J.a = jn->max_break_time;
+    J.K = jn->n_fractions;
+    J.fractions = jn->fractions;
+    J.junction = jn->junction;
+    J.ignore = jn->ignore;
+    J.count = jn->count;
+    J.release = jn->release;
+    J.rc = jn->capture_radius;
+    if ((rc = ensure(ws, WS_SES, sizeof(int32_t) * (3 * ns + 1), &p))) return rc;
+    int32_t *flag = (int32_t *)p, *pos = flag + ns, *idx = pos + ns + 1;
+    if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (6 * ns + 4 * ((ns + JUNC_GROUP - 1) / JUNC_GROUP) + 4), &p)))
+        return rc;
+    double *sx = (double *)p, *sph = sx + 6 * ns;
+    const unsigned gs = grid_for(ns, 256, INT32_MAX);
+    hipLaunchKernelGGL(k_ses_flag, dim3(gs), dim3(256), 0, st, L, seg_nodes, pinned, flag);
+    hipLaunchKernelGGL((k_scan<int32_t>), dim3(1), dim3(1024), 0, st, (const int32_t *)flag, ns, pos);
+    hipLaunchKernelGGL(k_ses_compact, dim3(gs), dim3(256), 0, st, L, seg_nodes, x, (const int32_t *)flag,
+                       (const int32_t *)pos, idx, sx);
+    hipLaunchKernelGGL(k_ses_spheres, dim3(grid_for((ns + JUNC_GROUP - 1) / JUNC_GROUP, 256, INT32_MAX)), dim3(256),
+                       0, st, ns, (const int32_t *)pos, (const double *)sx, sph);
+    J.pos = pos;
+    J.ses_idx = idx;
+    J.ses_x = sx;
+    J.ses_sph = sph;
+    return DD_OK;
 }
 
 __global__ void k_euler(int64_t nn, double *x, const double *__restrict__ vel, double dt)
@@ -1309,6 +1360,9 @@ int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, con
     if ((rc = ensure(ws, WS_FORCE, sizeof(double) * 3 * std::max<int64_t>(nn, 1), &p))) return rc;
     double *F = (double *)p;
     launch_csr(C, B.seg_nodes, st);
+    uint8_t *held = nullptr;
+    JunctionArgs J{};
+    if (B.jn && (rc = junction_prepare(ws, C.L, B.seg_nodes, B.x, B.pinned, B.jn, J, &held, st))) return rc;
     DD_HIP(hipGetLastError());
     if (!ws->capture_stream) DD_HIP(hipStreamCreateWithFlags(&ws->capture_stream, hipStreamNonBlocking));
     hipStream_t cs = ws->capture_stream;   // records the steps; the graph then runs on st
@@ -1316,10 +1370,14 @@ int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, con
     ws->capturing = true;
     const Sig6 sv{};
     for (int k = 0; k < n_steps; ++k) {
+        if (B.jn)
+            hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L, B.seg_nodes,
+                               (const double *)B.x, B.pinned, J, n_inst, (const uint8_t *)d_act, B.fast_steps_dev,
+                               B.dt, k, held);
         launch_forces(C, ws, B.x, B.seg_nodes, B.burgers, B.normal, sigma_dev, sv, F, cs);
         hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L, C.csr_ptr,
                            C.csr_list, B.seg_nodes, B.normal, C.rec64, C.a, B.x, F, B.pinned,
-                           (const uint8_t *)nullptr, (const uint8_t *)d_act, 1.0 / B.mat.B, B.dt, vel);
+                           (const uint8_t *)held, (const uint8_t *)d_act, 1.0 / B.mat.B, B.dt, vel);
         hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 2, B.seg_nodes, C.rec64, C.sys,
                            vel, B.pinned, B.volume, sigma_dev, C.a, sums_dev);
     }
@@ -1559,37 +1617,7 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
     double *F = (double *)p;
     uint8_t *held = nullptr;
     JunctionArgs J{};
-    if (jn) {
-        if ((rc = ensure(ws, WS_HELD, std::max<int64_t>(nn, 1), &p))) return rc;
-        held = (uint8_t *)p;
-        J.rc2 = jn->capture_radius * jn->capture_radius;
-        J.rf2 = (2.0 * jn->capture_radius) * (2.0 * jn->capture_radius);
-        J.a = jn->max_break_time;
-        J.K = jn->n_fractions;
-        J.fractions = jn->fractions;
-        J.junction = jn->junction;
-        J.ignore = jn->ignore;
-        J.count = jn->count;
-        J.release = jn->release;
-        J.rc = jn->capture_radius;
-        // the compact list of sessile segments (their nodes do not move during the burst)
-        if ((rc = ensure(ws, WS_SES, sizeof(int32_t) * (3 * ns + 1), &p))) return rc;
-        int32_t *flag = (int32_t *)p, *pos = flag + ns, *idx = pos + ns + 1;
-        if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (6 * ns + 4 * ((ns + JUNC_GROUP - 1) / JUNC_GROUP) + 4), &p)))
-            return rc;
-        double *sx = (double *)p, *sph = sx + 6 * ns;
-        const unsigned gs = grid_for(ns, 256, INT32_MAX);
-        hipLaunchKernelGGL(k_ses_flag, dim3(gs), dim3(256), 0, st, C.L, seg_nodes, pinned, flag);
-        hipLaunchKernelGGL((k_scan<int32_t>), dim3(1), dim3(1024), 0, st, (const int32_t *)flag, ns, pos);
-        hipLaunchKernelGGL(k_ses_compact, dim3(gs), dim3(256), 0, st, C.L, seg_nodes, (const double *)x,
-                           (const int32_t *)flag, (const int32_t *)pos, idx, sx);
-        hipLaunchKernelGGL(k_ses_spheres, dim3(grid_for((ns + JUNC_GROUP - 1) / JUNC_GROUP, 256, INT32_MAX)),
-                           dim3(256), 0, st, ns, (const int32_t *)pos, (const double *)sx, sph);
-        J.pos = pos;
-        J.ses_idx = idx;
-        J.ses_x = sx;
-        J.ses_sph = sph;
-    }
+    if (jn && (rc = junction_prepare(ws, C.L, seg_nodes, x, pinned, jn, J, &held, st))) return rc;
 
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
     launch_csr(C, seg_nodes, st);
@@ -1630,7 +1658,8 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
             if (jn) {
                 J.t = jn->t0 + k * dt;
                 hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L, seg_nodes,
-                                   (const double *)x, pinned, J, n_inst, held);
+                                   (const double *)x, pinned, J, n_inst, (const uint8_t *)nullptr,
+                                   (const int64_t *)nullptr, dt, k, held);
             }
             launch_forces(C, ws, x, seg_nodes, burgers, normal, sigma_app, sv, F, cs);
             hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,

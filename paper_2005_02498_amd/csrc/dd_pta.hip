@@ -39,6 +39,24 @@ __global__ void k_copy_nodes(double *__restrict__ dst, const double *__restrict_
     for (int k = 0; k < 3; ++k) dst[k * nn + n] = src[k * nn + n];
 }
 
+// copies `comps` arrays of nn per-node values (stride nn) of the instances with
+// mask[i] != 0 from src to dst
+template <class T>
+__global__ void k_copy_masked(T *__restrict__ dst, const T *__restrict__ src, int64_t nn, int comps,
+                              const int64_t *__restrict__ node_off, int n_inst, const uint8_t *__restrict__ mask)
+{
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    int lo = 0, hi = n_inst;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (node_off[mid] <= n) lo = mid;
+        else hi = mid;
+    }
+    if (!mask[lo]) return;
+    for (int k = 0; k < comps; ++k) dst[k * nn + n] = src[k * nn + n];
+}
+
 // L^p = sum_alpha gdot_alpha m_alpha (x) n_alpha (row-major 3 x 3)
 void lp_from_rates(const double *g, double Lp[9])
 {
@@ -100,6 +118,9 @@ struct Driver {
     Workspace *ws;
     double *sig_dev = nullptr, *sums_dev = nullptr;
     std::vector<double> sums_h;
+    // junctions: per instance fast steps taken so far (host copy and device)
+    std::vector<int64_t> fast;
+    int64_t *fast_dev = nullptr;
 
     // one chunk of P.chunk_steps for the instances in `act` under `sigma`
     // (host [n][6]); the chunk sums are added to the runs of those instances
@@ -107,6 +128,7 @@ struct Driver {
     {
         const int n = B.n_inst;
         DD_HIP(hipMemcpyAsync(sig_dev, sigma.data(), sizeof(double) * 6 * n, hipMemcpyHostToDevice, st));
+        if (fast_dev) DD_HIP(hipMemcpyAsync(fast_dev, fast.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, st));
         hipLaunchKernelGGL(k_pta_fill, dim3((unsigned)((13 * (int64_t)n + 255) / 256)), dim3(256), 0, st, sums_dev,
                            13 * (int64_t)n, 0.0);
         int rc = burst_batch_run(B, act, sig_dev, P.chunk_steps, sums_dev, st);
@@ -118,6 +140,7 @@ struct Driver {
             for (int k = 0; k < 13; ++k) R.sums[13 * i + k] += sums_h[13 * i + k];
             R.steps[i] += P.chunk_steps;
             R.checks[i] += 1;
+            if (fast_dev) fast[i] += P.chunk_steps;
         }
         return DD_OK;
     }
@@ -170,6 +193,52 @@ struct Driver {
         return DD_OK;
     }
 
+    // Junction state of the masked instances: `to_save` copies the caller's
+    // state (and fast clocks) into save slot `buf`/`fast_saved`, otherwise back.
+    int junction_state(double *buf, std::vector<int64_t> &fast_saved, const std::vector<uint8_t> &mask,
+                       bool to_save)
+    {
+        if (!B.jn) return DD_OK;
+        const int n = B.n_inst;
+        const int64_t nn = B.node_off[n];
+        for (int i = 0; i < n; ++i)
+            if (mask[i]) {
+                if (to_save) fast_saved[i] = fast[i];
+                else fast[i] = fast_saved[i];
+            }
+        if (nn == 0) return DD_OK;
+        uint8_t *d_mask;
+        int rc = upload_mask(mask, &d_mask);
+        if (rc) return rc;
+        // saved layout: release [nn] doubles, then junction, ignore, count [nn] int32 each
+        double *rel = buf;
+        int32_t *ints = (int32_t *)(buf + nn);
+        const int64_t *no = (const int64_t *)ws->ptr[WS_INST_OFFS];
+        const unsigned g = (unsigned)((nn + 255) / 256);
+        const dd_junctions *j = B.jn;
+        if (to_save) {
+            hipLaunchKernelGGL(k_copy_masked<double>, dim3(g), dim3(256), 0, st, rel, (const double *)j->release, nn, 1,
+                               no, n, (const uint8_t *)d_mask);
+            hipLaunchKernelGGL(k_copy_masked<int32_t>, dim3(g), dim3(256), 0, st, ints, (const int32_t *)j->junction,
+                               nn, 1, no, n, (const uint8_t *)d_mask);
+            hipLaunchKernelGGL(k_copy_masked<int32_t>, dim3(g), dim3(256), 0, st, ints + nn, (const int32_t *)j->ignore,
+                               nn, 1, no, n, (const uint8_t *)d_mask);
+            hipLaunchKernelGGL(k_copy_masked<int32_t>, dim3(g), dim3(256), 0, st, ints + 2 * nn,
+                               (const int32_t *)j->count, nn, 1, no, n, (const uint8_t *)d_mask);
+        } else {
+            hipLaunchKernelGGL(k_copy_masked<double>, dim3(g), dim3(256), 0, st, j->release, (const double *)rel, nn, 1,
+                               no, n, (const uint8_t *)d_mask);
+            hipLaunchKernelGGL(k_copy_masked<int32_t>, dim3(g), dim3(256), 0, st, j->junction, (const int32_t *)ints,
+                               nn, 1, no, n, (const uint8_t *)d_mask);
+            hipLaunchKernelGGL(k_copy_masked<int32_t>, dim3(g), dim3(256), 0, st, j->ignore, (const int32_t *)(ints + nn),
+                               nn, 1, no, n, (const uint8_t *)d_mask);
+            hipLaunchKernelGGL(k_copy_masked<int32_t>, dim3(g), dim3(256), 0, st, j->count,
+                               (const int32_t *)(ints + 2 * nn), nn, 1, no, n, (const uint8_t *)d_mask);
+        }
+        DD_HIP(hipGetLastError());
+        return DD_OK;
+    }
+
     int upload_mask(const std::vector<uint8_t> &mask, uint8_t **d)
     {
         void *p;
@@ -187,13 +256,14 @@ struct Driver {
 
 using namespace dd;
 
-extern "C" int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
-                           const int32_t *seg_nodes, const double *burgers, const double *normal,
-                           const uint8_t *pinned, const double *volume, const double *stress_rate,
-                           const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
-                           int precision, double near_cutoff_a, double *out, void *stream)
+namespace dd {
+namespace {
+int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x, const int32_t *seg_nodes,
+             const double *burgers, const double *normal, const uint8_t *pinned, const double *volume,
+             const double *stress_rate, const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
+             int precision, double near_cutoff_a, const dd_junctions *jn, int64_t *fast_steps, double *out,
+             void *stream)
 {
-    clear_error();
     int rc;
     if (n_inst < 0) return set_error(DD_EINVAL, "n_inst < 0");
     if (n_inst == 0) return DD_OK;
@@ -226,6 +296,17 @@ extern "C" int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_
     if (ns > 0 && (!seg_nodes || !burgers || !normal)) return set_error(DD_EINVAL, "null segment array");
     if (nn >= INT32_MAX || 2 * ns >= INT32_MAX) return set_error(DD_EINVAL, "more than 2^31 nodes or 2^30 segments");
     if (precision == DD_MIXED && !(near_cutoff_a > 0.0)) return set_error(DD_EINVAL, "near_cutoff_a must be > 0");
+    if (jn) {
+        if (!(jn->capture_radius >= 0.0) || !std::isfinite(jn->capture_radius) || !(jn->max_break_time >= 0.0) ||
+            !std::isfinite(jn->max_break_time))
+            return set_error(DD_EINVAL, "junctions: capture radius and breaking time must be finite and >= 0");
+        if (jn->n_fractions < 1) return set_error(DD_EINVAL, "junctions: n_fractions must be >= 1");
+        if (nn > 0 && (!jn->fractions || !jn->junction || !jn->release || !jn->ignore || !jn->count))
+            return set_error(DD_EINVAL, "junctions: null state or fractions array");
+        if (!fast_steps) return set_error(DD_EINVAL, "junctions: null fast_steps");
+        for (int i = 0; i < n_inst; ++i)
+            if (fast_steps[i] < 0) return set_error(DD_EINVAL, "junctions: fast_steps must be >= 0");
+    }
     hipStream_t st = (hipStream_t)stream;
     Workspace *ws;
     if ((rc = workspace(&ws))) return rc;
@@ -250,6 +331,21 @@ extern "C" int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_
 
     Driver D{B, P, st, ws};
     void *p;
+    double *jA = nullptr, *jB = nullptr;
+    std::vector<int64_t> fastA(n_inst, 0), fastB(n_inst, 0);
+    if (jn) {
+        if ((rc = ensure(ws, WS_PTA_FAST, sizeof(int64_t) * n_inst, &p))) return rc;
+        D.fast_dev = (int64_t *)p;
+        D.fast.assign(fast_steps, fast_steps + n_inst);
+        B.jn = jn;
+        B.fast_steps_dev = D.fast_dev;
+        // saved junction state: release (double) and junction, ignore, count (int32) per node
+        const size_t jbytes = (sizeof(double) + 3 * sizeof(int32_t)) * (size_t)std::max<int64_t>(nn, 1);
+        if ((rc = ensure(ws, WS_PTA_JA, jbytes, &p))) return rc;
+        jA = (double *)p;
+        if ((rc = ensure(ws, WS_PTA_JB, jbytes, &p))) return rc;
+        jB = (double *)p;
+    }
     if ((rc = ensure(ws, WS_PTA_SIGMA, sizeof(double) * 6 * n_inst, &p))) return rc;
     D.sig_dev = (double *)p;
     if ((rc = ensure(ws, WS_PTA_SUMS, sizeof(double) * 13 * n_inst, &p))) return rc;
@@ -284,6 +380,7 @@ extern "C" int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_
             }
         if ((rc = D.fast_run(todo, sigA, A))) return rc;                  // step 1 at l(t - Delta)
         if ((rc = D.copy_nodes(xA, x, todo))) return rc;                   // its end state
+        if ((rc = D.junction_state(jA, fastA, todo, true))) return rc;
         if ((rc = D.fast_run(todo, sigB, Bv))) return rc;                 // step 2 at l(t)
         for (int i = 0; i < n_inst; ++i) {
             if (!todo[i]) continue;
@@ -314,11 +411,14 @@ extern "C" int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_
         any_rerun = need;
         if ((rc = D.copy_nodes(xB, x, any_rerun))) return rc;
         if ((rc = D.copy_nodes(x, xA, any_rerun))) return rc;
+        if ((rc = D.junction_state(jB, fastB, any_rerun, true))) return rc;
+        if ((rc = D.junction_state(jA, fastA, any_rerun, false))) return rc;
         do {
             if ((rc = D.chunk(need, sigA, A))) return rc;
             for (int i = 0; i < n_inst; ++i) rerun[i] += need[i];
         } while (update_need());
         if ((rc = D.copy_nodes(x, xB, any_rerun))) return rc;   // carry the end of the t run on
+        if ((rc = D.junction_state(jB, fastB, any_rerun, false))) return rc;
         DD_HIP(hipStreamSynchronize(st));
     }
     // outputs, step 6
@@ -362,5 +462,34 @@ extern "C" int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_
                                  "invalid input or non-finite result (flags 0x%x)", fl);
     }
     DD_HIP(hipStreamSynchronize(st));
+    if (jn)
+        for (int i = 0; i < n_inst; ++i) fast_steps[i] = D.fast[i];
     return DD_OK;
 }
+}  // namespace
+}  // namespace dd
+
+extern "C" int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                           const int32_t *seg_nodes, const double *burgers, const double *normal,
+                           const uint8_t *pinned, const double *volume, const double *stress_rate,
+                           const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
+                           int precision, double near_cutoff_a, double *out, void *stream)
+{
+    clear_error();
+    return pta_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, prm, m,
+                    n_gauss, precision, near_cutoff_a, nullptr, nullptr, out, stream);
+}
+
+extern "C" int dd_pta_step_junctions(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                                     const int32_t *seg_nodes, const double *burgers, const double *normal,
+                                     const uint8_t *pinned, const double *volume, const double *stress_rate,
+                                     const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
+                                     int precision, double near_cutoff_a, const dd_junctions *junctions,
+                                     int64_t *fast_steps, double *out, void *stream)
+{
+    clear_error();
+    if (!junctions) return set_error(DD_EINVAL, "null junction parameters");
+    return pta_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, prm, m,
+                    n_gauss, precision, near_cutoff_a, junctions, fast_steps, out, stream);
+}
+

@@ -136,3 +136,144 @@ def test_invalid_junction_parameters():
             dd.dd_burst_batch_junctions(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"],
                                         d["normal"], d["pinned"], d["sigma_app"], d["volume"], MAT, st, fr,
                                         r_c, a, t0, 2, dd.DD_FP64, 20.0, 2, W.DT)
+
+
+# ------------------------------------------------------ PTA with junctions --
+from oracle import pta   # noqa: E402
+
+DELTA = 1e-8
+
+
+def _pta_volumes():
+    insts = []
+    for i, nl in enumerate((4, 3, 5)):
+        inst = W.subset(W.burst_instance(1_000_030 + i), nl)
+        inst.pinned[:] = 0
+        inst.pinned[64:] = 1
+        insts.append(inst)
+    rates = np.array([[0, 0, 1e15, 0, 0, 0], [2e14, -1e14, 0, 3e14, 0, 1e14], [0, 0, 0, 0, 0, 8e14]], float)
+    return insts, rates
+
+
+def _pta_compare(insts, rates, ts, kw, fast0, calls=1, tol=1e-10, r_c=None):
+    """dd_pta_step_junctions against oracle/pta.py with junctions over
+    `calls` consecutive slow steps (times ts[c]); the junction state, fast
+    clocks and microstructure carry over between calls on both sides."""
+    bt = W.pack(insts)
+    d = batch_dev(bt)
+    nn = bt.node_off[-1]
+    st = _state_dev(nn)
+    if r_c is None:
+        r_c = 1.5 * min(_min_capture_distance(inst) for inst in insts)
+    a = 3 * W.DT
+    fr = np.random.default_rng(17).uniform(0.0, 1.0, (nn, 4))
+    fast = np.array(fast0, np.int64)
+    J = {"state": st, "fractions": torch.tensor(fr, device=DEV), "capture_radius": r_c, "max_break_time": a,
+         "fast_steps": fast}
+    P = dd.PTAParams(dt=W.DT, delta=DELTA, **kw)
+    OP = pta.PTAParams(dt=W.DT, delta=DELTA, chunk=kw["chunk_steps"], max_chunks=kw["max_chunks"],
+                       lpdot_max=kw.get("lpdot_max", 0.05), max_jumps=kw.get("max_jumps", 2))
+    ojn = [pta.Junctions(r_c, a, fr[bt.node_off[i]:bt.node_off[i + 1]], OJ.new_state(inst.n_nodes), int(fast0[i]))
+           for i, inst in enumerate(insts)]
+    cur = list(insts)
+    outs = []
+    for c in range(calls):
+        got = dd.dd_pta_step(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"], d["normal"],
+                             d["pinned"], d["volume"], rates, ts[c], P, MAT, 2, dd.DD_FP64, junctions=J)
+        torch.cuda.synchronize()
+        xg = d["x"].cpu().numpy()
+        for i, inst in enumerate(cur):
+            ref = pta.pta_step(inst, ts[c][i], rates[i], W.material(), 2, OP, ojn[i])
+            print(f"call {c} volume {i}: steps {got['steps_a'][i]}/{got['steps_b'][i]}, jumps {got['jumps'][i]}, "
+                  f"rerun {got['rerun_chunks'][i]}, fast clock {fast[i]} (oracle {ref['jn'].fast}), "
+                  f"junctions {int(ref['jn'].state['count'].sum())}")
+            for k in ("steps_a", "steps_b", "jumps", "rerun_chunks", "conv_a", "conv_b"):
+                assert got[k][i] == ref[k], k
+            for k in ("g_a", "g_b", "lp_a", "lp_b"):
+                r = np.asarray(ref[k])
+                assert np.abs(got[k][i] - r).max() <= tol * max(np.abs(r).max(), 1e-300), k
+            n0, n1 = bt.node_off[i], bt.node_off[i + 1]
+            disp_g, disp_o = xg[:, n0:n1] - insts[i].x, ref["x"] - insts[i].x
+            assert np.abs(disp_g - disp_o).max() <= tol * max(np.abs(disp_o).max(), 1e-300)
+            assert fast[i] == ref["jn"].fast
+            s0 = bt.seg_off[i]
+            os_ = ref["jn"].state
+            jg = st["junction"].cpu().numpy()[n0:n1].astype(np.int64)
+            ig = st["ignore"].cpu().numpy()[n0:n1].astype(np.int64)
+            assert np.array_equal(np.where(jg >= 0, jg - s0, -1), os_["junction"])
+            assert np.array_equal(np.where(ig >= 0, ig - s0, -1), os_["ignore"])
+            assert np.array_equal(st["count"].cpu().numpy()[n0:n1], os_["count"])
+            held = os_["junction"] >= 0
+            assert np.array_equal(st["release"].cpu().numpy()[n0:n1][held], os_["release"][held])
+            ojn[i] = ref["jn"]
+            cur[i] = W.Instance(ref["x"], inst.seg_nodes, inst.burgers, inst.normal, inst.pinned, inst.sigma_app,
+                                inst.volume, {})
+        outs.append(got)
+    return outs, [int(j.state["count"].sum()) for j in ojn]
+
+
+def test_pta_junctions_two_slow_steps():
+    insts, rates = _pta_volumes()
+    ts = [np.array([5e-8, 3e-8, 4e-8]), np.array([6e-8, 4e-8, 5e-8])]
+    _, counts = _pta_compare(insts, rates, ts, dict(chunk_steps=3, max_chunks=3, lpdot_max=np.inf), [0, 17, 5],
+                             calls=2)
+    assert sum(counts) > 0
+
+
+def test_pta_junctions_jumps():
+    insts, rates = _pta_volumes()
+    outs, counts = _pta_compare(insts, rates, [np.array([5e-8, 3e-8, 4e-8])],
+                                dict(chunk_steps=2, max_chunks=3, lpdot_max=0.0, max_jumps=2), [3, 0, 9])
+    assert (outs[0]["jumps"] == 2).all() and sum(counts) > 0
+
+
+def test_pta_junctions_rerun_restores_state():
+    """t < delta/2: step 5 continues the t - delta run, with the junction
+    state and clock of its own end; the t run's are carried on."""
+    insts = []
+    for seed in (1_000_072, 1_000_071):
+        inst = W.subset(W.burst_instance(seed), 2)
+        inst.pinned[:] = 0
+        inst.pinned[32:] = 1            # the second loop is sessile
+        insts.append(inst)
+    rates = np.array([[0, 0, 1e15, 0, 0, 0], [0, 0, 0, 0, 0, 8e14]], float)
+    # with this radius the second volume forms junctions and still takes step 5
+    outs, counts = _pta_compare(insts, rates, [np.array([0.1, 0.1]) * DELTA],
+                                dict(chunk_steps=2, max_chunks=3, lpdot_max=np.inf), [0, 4], r_c=421.0)
+    assert outs[0]["rerun_chunks"][1] > 0 and counts[1] > 0
+
+
+def test_pta_junctions_zero_radius_is_the_plain_step():
+    insts, rates = _pta_volumes()
+    bt = W.pack(insts)
+    t = np.array([5e-8, 3e-8, 4e-8])
+    P = dd.PTAParams(dt=W.DT, delta=DELTA, chunk_steps=2, max_chunks=2, lpdot_max=np.inf)
+    d1, d2 = batch_dev(bt), batch_dev(bt)
+    r1 = dd.dd_pta_step(bt.node_off, bt.seg_off, d1["x"], d1["seg_nodes"], d1["burgers"], d1["normal"],
+                        d1["pinned"], d1["volume"], rates, t, P, MAT, 2, dd.DD_FP64)
+    nn = bt.node_off[-1]
+    fast = np.zeros(3, np.int64)
+    J = {"state": _state_dev(nn), "fractions": torch.full((nn, 1), 0.5, dtype=torch.float64, device=DEV),
+         "capture_radius": 0.0, "max_break_time": 1e-12, "fast_steps": fast}
+    r2 = dd.dd_pta_step(bt.node_off, bt.seg_off, d2["x"], d2["seg_nodes"], d2["burgers"], d2["normal"],
+                        d2["pinned"], d2["volume"], rates, t, P, MAT, 2, dd.DD_FP64, junctions=J)
+    torch.cuda.synchronize()
+    assert torch.equal(d1["x"], d2["x"])
+    for k in r1:
+        assert np.array_equal(r1[k], r2[k]), k
+    assert (fast == r1["steps_a"] - 2 * r1["rerun_chunks"] + r1["steps_b"]).all()
+
+
+def test_pta_junctions_invalid():
+    insts, rates = _pta_volumes()
+    bt = W.pack(insts)
+    d = batch_dev(bt)
+    nn = bt.node_off[-1]
+    P = dd.PTAParams(dt=W.DT, delta=DELTA, chunk_steps=2, max_chunks=2, lpdot_max=np.inf)
+    base = {"state": _state_dev(nn), "fractions": torch.full((nn, 1), 0.5, dtype=torch.float64, device=DEV),
+            "capture_radius": 1.0, "max_break_time": 1e-12}
+    for fs, r_c in ((np.array([0, -1, 0], np.int64), 1.0), (np.zeros(3, np.int64), -1.0)):
+        with pytest.raises(dd.DDError):
+            dd.dd_pta_step(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"], d["normal"],
+                           d["pinned"], d["volume"], rates, np.array([5e-8] * 3), P, MAT, 2, dd.DD_FP64,
+                           junctions=dict(base, fast_steps=fs, capture_radius=r_c))

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import junctions as OJ
 from oracle import pta
 from paper_2005_02498_amd import workloads as W
 
@@ -92,3 +93,57 @@ def test_pta_step_rules():
     assert r2["jumps"] == 2
     assert r2["steps_a"] >= 6 and r2["steps_b"] >= 6
     assert np.abs(r2["x"] - r["x"]).max() > 0
+
+
+def _junction_volume():
+    inst = W.subset(W.burst_instance(1_000_030), 4)
+    inst.pinned[:] = 0
+    inst.pinned[64:] = 1                 # loops 3 and 4 are sessile
+    ses = [s for s in range(inst.n_segs) if inst.pinned[inst.seg_nodes[0, s]] and inst.pinned[inst.seg_nodes[1, s]]]
+    d2 = min(OJ._dist2(inst.x[:, n], inst.x[:, inst.seg_nodes[0, s]], inst.x[:, inst.seg_nodes[1, s]])
+             for n in np.nonzero(inst.pinned == 0)[0] for s in ses)
+    return inst, 1.5 * float(np.sqrt(d2))
+
+
+def test_pta_with_zero_capture_radius_is_the_plain_step():
+    inst, _ = _junction_volume()
+    P = pta.PTAParams(dt=W.DT, delta=1e-8, chunk=2, max_chunks=2, lpdot_max=np.inf)
+    rate = np.array([2e14, -1e14, 0, 3e14, 0, 1e14])
+    ref = pta.pta_step(inst, 5e-8, rate, W.material(), Q, P)
+    jn = pta.Junctions(0.0, 3 * W.DT, np.full((inst.n_nodes, 1), 0.5), OJ.new_state(inst.n_nodes), 7)
+    got = pta.pta_step(inst, 5e-8, rate, W.material(), Q, P, jn)
+    assert np.array_equal(got["x"], ref["x"]) and np.array_equal(got["lp_b"], ref["lp_b"])
+    # the clock carried on is that of the end of the t run (step 5 steps excluded)
+    assert got["jn"].fast == 7 + ref["steps_a"] - ref["rerun_chunks"] * P.chunk + ref["steps_b"]
+    assert jn.fast == 7 and (jn.state["count"] == 0).all()      # the caller's state is not touched
+
+
+def test_pta_with_junctions_is_the_step_by_step_junction_burst():
+    """No jump and no step 5: the t - Delta run and the t run are, step for
+    step, the junction burst routine of oracle/junctions.py at the volume's
+    fast clock, one glide step per call; averages, positions and junction
+    state agree exactly."""
+    inst, r_c = _junction_volume()
+    mat = W.material()
+    P = pta.PTAParams(dt=W.DT, delta=1e-8, chunk=2, max_chunks=2, lpdot_max=np.inf)
+    rate = np.array([2e14, -1e14, 0, 3e14, 0, 1e14])
+    fr = np.random.default_rng(5).uniform(0.0, 1.0, (inst.n_nodes, 3))
+    f0 = 11
+    jn = pta.Junctions(r_c, 3 * W.DT, fr, OJ.new_state(inst.n_nodes), f0)
+    got = pta.pta_step(inst, 5e-8, rate, mat, Q, P, jn)
+    assert got["rerun_chunks"] == 0 and got["jumps"] == 0
+    st = OJ.new_state(inst.n_nodes)
+    x = np.array(inst.x, float)
+    k = f0
+    for sig, n_steps, key in ((5e-8 - 1e-8, got["steps_a"], "g_a"), (5e-8, got["steps_b"], "g_b")):
+        acc = np.zeros(12)
+        for _ in range(n_steps):
+            s = W.Instance(x, inst.seg_nodes, inst.burgers, inst.normal, inst.pinned, sig * rate, inst.volume, {})
+            x, r = OJ.burst(s, mat, Q, 1, W.DT, r_c, 3 * W.DT, float(k) * W.DT, fr, st)
+            acc += r
+            k += 1
+        assert np.array_equal(got[key], acc / n_steps)
+    assert np.array_equal(got["x"], x)
+    for key in ("junction", "release", "ignore", "count"):
+        assert np.array_equal(got["jn"].state[key], st[key]), key
+    assert got["jn"].fast == k and st["count"].sum() > 0
