@@ -8,7 +8,8 @@
 namespace dd {
 
 // FP32, far pairs: adds sigma^i b_j / k2 (the regrouped closed form of
-// dd_pair64.h, kr = (1 - nu)/2) to (f0, f1, f2).  y, rho and hh = |rho|^2 are
+// dd_pair64.h, kr = (1 - nu)/2) to (f0, f1, f2) + fk b_j (the b_j term's
+// scalar goes to fk; the caller adds fk b_j once).  y, rho and hh = |rho|^2 are
 // formed by the caller (y and rho in FP64, rounded once).  The endpoint
 // differences are rearranged so that no two nearly equal numbers are
 // subtracted when the target lies far away or on the extension of the segment
@@ -27,7 +28,7 @@ namespace dd {
 __device__ __forceinline__ void pair_acc_f32(
     float y, float h0, float h1, float h2, float hh, float bj0, float bj1, float bj2,
     float t0, float t1, float t2, float L, float b0, float b1, float b2,
-    float c0, float c1, float c2, float kr, float nu, float &f0, float &f1, float &f2)
+    float c0, float c1, float c2, float kr, float nu, float &f0, float &f1, float &f2, float &fk)
 {
     const float d2 = hh + 1.0f;
     const float u2 = L - y;
@@ -54,21 +55,20 @@ __device__ __forceinline__ void pair_acc_f32(
     const float q = fmaf(c2, h2, fmaf(c1, h1, c0 * h0));
     const float A = -kr * g0;
     const float Cc = fmaf(nu, I31, -kr * D51);
-    const float Tt2 = q * P3, Tr = -q * D51, Zr2 = q * E50;
-    const float kd = q * (I30 + E50);
+    fk = fmaf(q, I30 + E50, fk);   // kd
     const float rb0 = fmaf(h1, b2, -h2 * b1), rb1 = fmaf(h2, b0, -h0 * b2), rb2 = fmaf(h0, b1, -h1 * b0);
     // sigma b_j / k2 as coefficients of the five vectors rho x b, c, t, rho and b_j
     const float tb = fmaf(t2, bj2, fmaf(t1, bj1, t0 * bj0));
     const float hb = fmaf(h2, bj2, fmaf(h1, bj1, h0 * bj0));
     const float cb = fmaf(c2, bj2, fmaf(c1, bj1, c0 * bj0));
     const float rbb = fmaf(rb2, bj2, fmaf(rb1, bj1, rb0 * bj0));
-    const float Pt = fmaf(Tt2, tb, fmaf(Tr, hb, fmaf(Cc, cb, A * rbb)));
-    const float Ph = fmaf(Tr, tb, fmaf(Zr2, hb, -I30 * cb));
+    const float Pt = fmaf(q, fmaf(P3, tb, -D51 * hb), fmaf(Cc, cb, A * rbb));
+    const float Ph = fmaf(q, fmaf(E50, hb, -D51 * tb), -I30 * cb);
     const float Pc = fmaf(Cc, tb, -I30 * hb);
     const float Pr = A * tb;
-    f0 = fmaf(kd, bj0, fmaf(Ph, h0, fmaf(Pt, t0, fmaf(Pc, c0, fmaf(Pr, rb0, f0)))));
-    f1 = fmaf(kd, bj1, fmaf(Ph, h1, fmaf(Pt, t1, fmaf(Pc, c1, fmaf(Pr, rb1, f1)))));
-    f2 = fmaf(kd, bj2, fmaf(Ph, h2, fmaf(Pt, t2, fmaf(Pc, c2, fmaf(Pr, rb2, f2)))));
+    f0 = fmaf(Ph, h0, fmaf(Pt, t0, fmaf(Pc, c0, fmaf(Pr, rb0, f0))));
+    f1 = fmaf(Ph, h1, fmaf(Pt, t1, fmaf(Pc, c1, fmaf(Pr, rb1, f1))));
+    f2 = fmaf(Ph, h2, fmaf(Pt, t2, fmaf(Pc, c2, fmaf(Pr, rb2, f2))));
 }
 
 
@@ -95,12 +95,12 @@ __device__ __forceinline__ void pair_acc_f32(
 //   b_j     : q (S3 + 3 S5)
 //   rho     : (c.b_j) Sga + 3 q ((rho.b_j) S5 + (t.b_j) S5v)
 
-// The moments are collected as the coefficients of the five vectors; shared
-// by the 2- and 3-point rules.
+// The moments are collected as the coefficients of the five vectors (that of
+// b_j added to fk); shared by the 2- and 3-point rules.
 __device__ __forceinline__ void quad_moments_acc_f32(float e0, float e1, float e2, float ym, const float *s,
                                                      float S3, float S5, float S3v, float S5v, float S5vv,
                                                      float bj0, float bj1, float bj2, float kr, float nu,
-                                                     float &f0, float &f1, float &f2)
+                                                     float &f0, float &f1, float &f2, float &fk)
 {
     const float t0 = s[6], t1 = s[7], t2 = s[8];
     const float b0 = s[11], b1 = s[12], b2 = s[13], c0 = s[14], c1 = s[15], c2 = s[16];
@@ -117,19 +117,19 @@ __device__ __forceinline__ void quad_moments_acc_f32(float e0, float e1, float e
     const float Cr = tb * Sal;
     const float Cc = fmaf(tb, Sgv, -hb * S3);
     const float Ct = fmaf(rbb, Sal, fmaf(cb, Sgv, q3 * fmaf(hb, S5v, tb * S5vv)));
-    const float Cb = q * fmaf(3.0f, S5, S3);
+    fk = fmaf(q, fmaf(3.0f, S5, S3), fk);
     const float Ch = fmaf(-cb, S3, q3 * fmaf(hb, S5, tb * S5v));
-    f0 = fmaf(Cb, bj0, fmaf(Ch, h0, fmaf(Ct, t0, fmaf(Cc, c0, fmaf(Cr, rb0, f0)))));
-    f1 = fmaf(Cb, bj1, fmaf(Ch, h1, fmaf(Ct, t1, fmaf(Cc, c1, fmaf(Cr, rb1, f1)))));
-    f2 = fmaf(Cb, bj2, fmaf(Ch, h2, fmaf(Ct, t2, fmaf(Cc, c2, fmaf(Cr, rb2, f2)))));
+    f0 = fmaf(Ch, h0, fmaf(Ct, t0, fmaf(Cc, c0, fmaf(Cr, rb0, f0))));
+    f1 = fmaf(Ch, h1, fmaf(Ct, t1, fmaf(Cc, c1, fmaf(Cr, rb1, f1))));
+    f2 = fmaf(Ch, h2, fmaf(Ct, t2, fmaf(Cc, c2, fmaf(Cr, rb2, f2))));
 }
 
 // e = target - source midpoint, ee = |e|^2; s = the source's FP32 record (see
-// REC32A); adds K b_j / k2 to (f0, f1, f2).  2-point rule: points at
+// REC32A); adds K b_j / k2 to (f0, f1, f2) + fk b_j.  2-point rule: points at
 // v = ym -+ hq, weight Wo each.
 __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, float ee, const float *s,
                                               float bj0, float bj1, float bj2, float kr, float nu,
-                                              float &f0, float &f1, float &f2)
+                                              float &f0, float &f1, float &f2, float &fk)
 {
     const float hq = s[10], W = s[18];
     const float ym = fmaf(e2, s[8], fmaf(e1, s[7], e0 * s[6]));
@@ -143,7 +143,7 @@ __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, floa
     const float S3 = W * (iA3 + iB3), S5 = W * (iA5 + iB5);
     const float S3v = W * fmaf(iA3, vA, iB3 * vB), S5v = W * (pA + pB);
     const float S5vv = W * fmaf(pA, vA, pB * vB);
-    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2);
+    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2, fk);
 }
 
 // 3-point rule: points at v = ym -+ hq with weight Wo and at v = ym with
@@ -151,7 +151,7 @@ __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, floa
 // Its error is below 2e-7 relative beyond 6 source lengths from the midpoint.
 __device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, float ee, const float *s,
                                               float bj0, float bj1, float bj2, float kr, float nu,
-                                              float &f0, float &f1, float &f2)
+                                              float &f0, float &f1, float &f2, float &fk)
 {
     const float hq = s[10], Wo = s[18], Wc = s[21];
     const float ym = fmaf(e2, s[8], fmaf(e1, s[7], e0 * s[6]));
@@ -167,7 +167,7 @@ __device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, floa
     const float S3v = fmaf(Wc, iC3 * ym, Wo * fmaf(iA3, vA, iB3 * vB));
     const float S5v = fmaf(Wc, pC, Wo * (pA + pB));
     const float S5vv = fmaf(Wc, pC * ym, Wo * fmaf(pA, vA, pB * vB));
-    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2);
+    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2, fk);
 }
 
 }  // namespace dd

@@ -22,7 +22,8 @@
 //   z/k2  = -I30 c + q E50/2 rho,       kd/k2 = q (I30 + E50)
 // in terms of D51 = 3 I51 = r1^3 - r2^3, P = 3 I52 and E50 = 3 I50, with
 // r = 1/Ra and s = u r at the two endpoints:
-//   I30 = (s2 - s1)/d2,  P = (s2^3 - s1^3)/d2,  E50 = (3 I30 - P)/d2,
+//   I30 = (s2 - s1)/d2,  P = (s2^3 - s1^3)/d2 = I30 (s1^2 + s1 s2 + s2^2),
+//   E50 = (3 I30 - P)/d2,
 //   I31 = r1 - r2,       g0 = 2 I30 + E50.
 #pragma once
 
@@ -51,16 +52,18 @@ __device__ __forceinline__ double rcp64(double x)
 }
 
 // Adds sigma^i b_j / k2 of source (p, t, L, b, c) at target point x to
-// (a0, a1, a2).  r1 and r1c = r1^3 belong to the source's first node and are
-// supplied by the caller; r2 and r2c are returned, so that a source starting
-// where this one ends (same target point) reuses them as its r1, r1c.
-// kr = (1 - nu)/2.
+// (a0, a1, a2) + ak b_j: the kd b_j term is returned as its scalar kd, added
+// to ak, since b_j is the same for every source of a target point (the caller
+// adds ak b_j once).  r1 and r1c = r1^3 belong to the source's first node and
+// are supplied by the caller; r2 and r2c are returned, so that a source
+// starting where this one ends (same target point) reuses them as its r1,
+// r1c.  kr = (1 - nu)/2.
 __device__ __forceinline__ void pair_acc_f64(
     double x0, double x1, double x2, double bj0, double bj1, double bj2,
     double p0, double p1, double p2, double t0, double t1, double t2, double L,
     double b0, double b1, double b2, double c0, double c1, double c2,
     double kr, double nu, double r1, double r1c, double &r2, double &r2c,
-    double &a0, double &a1, double &a2)
+    double &a0, double &a1, double &a2, double &ak)
 {
     const double R0 = x0 - p0, R1 = x1 - p1, R2 = x2 - p2;
     const double y = fma(R2, t2, fma(R1, t1, R0 * t0));
@@ -72,9 +75,8 @@ __device__ __forceinline__ void pair_acc_f64(
     const double id2 = rcp64(d2);
     const double s1 = -y * r1, s2 = u2 * r2;
     const double D1 = s2 - s1;
-    const double D3 = fma(s2 * s2, s2, -(s1 * s1) * s1);
     const double I30 = D1 * id2;
-    const double P = D3 * id2;
+    const double P = I30 * fma(s1, s1 + s2, s2 * s2);   // s2^3 - s1^3 = D1 (s1^2 + s1 s2 + s2^2)
     const double E50 = fma(3.0, I30, -P) * id2;
     const double I31 = r1 - r2;
     const double D51 = r1c - r2c;
@@ -82,23 +84,22 @@ __device__ __forceinline__ void pair_acc_f64(
     const double q = fma(c2, h2, fma(c1, h1, c0 * h0));
     const double A = -kr * g0;
     const double Cc = fma(nu, I31, -kr * D51);
-    // twice the t coefficient of w/k2, its rho coefficient, twice the rho coefficient of z/k2
-    const double Tt2 = q * P, Tr = -q * D51, Zr2 = q * E50;
-    const double kd = q * (I30 + E50);
+    ak = fma(q, I30 + E50, ak);   // kd
     const double rb0 = fma(h1, b2, -h2 * b1), rb1 = fma(h2, b0, -h0 * b2), rb2 = fma(h0, b1, -h1 * b0);
     // sigma b_j = t (w.b_j) + w (t.b_j) + rho (z.b_j) + z (rho.b_j) + kd b_j, with w and z
-    // expanded: coefficients of the five vectors rho x b, c, t, rho and b_j
+    // expanded: coefficients of the four vectors rho x b, c, t, rho (q P/2 and -q D51 are
+    // the t and rho coefficients of w/k2, q E50/2 the rho coefficient of z/k2)
     const double tb = fma(t2, bj2, fma(t1, bj1, t0 * bj0));
     const double hb = fma(h2, bj2, fma(h1, bj1, h0 * bj0));
     const double cb = fma(c2, bj2, fma(c1, bj1, c0 * bj0));
     const double rbb = fma(rb2, bj2, fma(rb1, bj1, rb0 * bj0));
-    const double Pt = fma(Tt2, tb, fma(Tr, hb, fma(Cc, cb, A * rbb)));
-    const double Ph = fma(Tr, tb, fma(Zr2, hb, -I30 * cb));
+    const double Pt = fma(q, fma(P, tb, -D51 * hb), fma(Cc, cb, A * rbb));
+    const double Ph = fma(q, fma(E50, hb, -D51 * tb), -I30 * cb);
     const double Pc = fma(Cc, tb, -I30 * hb);
     const double Pr = A * tb;
-    a0 = fma(kd, bj0, fma(Ph, h0, fma(Pt, t0, fma(Pc, c0, fma(Pr, rb0, a0)))));
-    a1 = fma(kd, bj1, fma(Ph, h1, fma(Pt, t1, fma(Pc, c1, fma(Pr, rb1, a1)))));
-    a2 = fma(kd, bj2, fma(Ph, h2, fma(Pt, t2, fma(Pc, c2, fma(Pr, rb2, a2)))));
+    a0 = fma(Ph, h0, fma(Pt, t0, fma(Pc, c0, fma(Pr, rb0, a0))));
+    a1 = fma(Ph, h1, fma(Pt, t1, fma(Pc, c1, fma(Pr, rb1, a1))));
+    a2 = fma(Ph, h2, fma(Pt, t2, fma(Pc, c2, fma(Pr, rb2, a2))));
 }
 
 // One isolated pair (the near-field branch of the mixed path): adds
@@ -111,9 +112,12 @@ __device__ __forceinline__ void pair_acc_isolated_f64(double x0, double x1, doub
 {
     const double R0 = x0 - d[0], R1 = x1 - d[1], R2 = x2 - d[2];
     const double r1 = rsqrt64(fma(R2, R2, fma(R1, R1, fma(R0, R0, 1.0))));
-    double r2, r2c;
+    double r2, r2c, ak = 0.0;
     pair_acc_f64(x0, x1, x2, bj0, bj1, bj2, d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7], d[8],
-                 d[9], d[10], d[11], d[12], kr, nu, r1, r1 * r1 * r1, r2, r2c, a0, a1, a2);
+                 d[9], d[10], d[11], d[12], kr, nu, r1, r1 * r1 * r1, r2, r2c, a0, a1, a2, ak);
+    a0 = fma(ak, bj0, a0);
+    a1 = fma(ak, bj1, a1);
+    a2 = fma(ak, bj2, a2);
 }
 
 }  // namespace dd

@@ -21,7 +21,7 @@ template <bool SELF>
 __device__ __forceinline__ void pair64_range(const double *__restrict__ ra, int64_t b, int64_t e,
                                              int64_t j, double xq0, double xq1, double xq2, double bj0,
                                              double bj1, double bj2, double kr, double nu, double &a0,
-                                             double &a1, double &a2)
+                                             double &a1, double &a2, double &ak)
 {
     for (int64_t m = b; m < e;) {
         const double *c = ra + m * RECA;
@@ -34,18 +34,19 @@ __device__ __forceinline__ void pair64_range(const double *__restrict__ ra, int6
         for (int k = 0; k < n; ++k, c += RECA) {
             double r2, r2c;
             if (SELF) {
-                double n0 = a0, n1 = a1, n2 = a2;
+                double n0 = a0, n1 = a1, n2 = a2, nk = ak;
                 pair_acc_f64(xq0, xq1, xq2, bj0, bj1, bj2, c[0], c[1], c[2], c[3], c[4], c[5], c[6],
                              c[7], c[8], c[9], c[10], c[11], c[12], kr, nu, r1, r1c, r2, r2c, n0, n1,
-                             n2);
+                             n2, nk);
                 const bool self = m + k == j;
                 a0 = self ? a0 : n0;
                 a1 = self ? a1 : n1;
                 a2 = self ? a2 : n2;
+                ak = self ? ak : nk;
             } else {
                 pair_acc_f64(xq0, xq1, xq2, bj0, bj1, bj2, c[0], c[1], c[2], c[3], c[4], c[5], c[6],
                              c[7], c[8], c[9], c[10], c[11], c[12], kr, nu, r1, r1c, r2, r2c, a0, a1,
-                             a2);
+                             a2, ak);
             }
             r1 = r2;
             r1c = r2c;
@@ -77,15 +78,18 @@ __global__ __launch_bounds__(TILE) void k_pair64(const Item *__restrict__ items,
     const double xq1 = rec[1 * ns + j] + sq * L * rec[4 * ns + j];
     const double xq2 = rec[2 * ns + j] + sq * L * rec[5 * ns + j];
     const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, ak = 0.0;
 
     // the tile's own segments [jlo, jhi] split the range in three parts
     const int64_t jlo = tl.point_begin / Q, jhi = (tl.point_begin + tl.n_points - 1) / Q;
     const int64_t b = it.src_begin, e = it.src_end;
     const int64_t s0 = min(max(b, jlo), e), s1 = min(max(b, jhi + 1), e);
-    pair64_range<false>(ra, b, s0, j, xq0, xq1, xq2, bj0, bj1, bj2, kr, nu, a0, a1, a2);
-    pair64_range<true>(ra, s0, s1, j, xq0, xq1, xq2, bj0, bj1, bj2, kr, nu, a0, a1, a2);
-    pair64_range<false>(ra, s1, e, j, xq0, xq1, xq2, bj0, bj1, bj2, kr, nu, a0, a1, a2);
+    pair64_range<false>(ra, b, s0, j, xq0, xq1, xq2, bj0, bj1, bj2, kr, nu, a0, a1, a2, ak);
+    pair64_range<true>(ra, s0, s1, j, xq0, xq1, xq2, bj0, bj1, bj2, kr, nu, a0, a1, a2, ak);
+    pair64_range<false>(ra, s1, e, j, xq0, xq1, xq2, bj0, bj1, bj2, kr, nu, a0, a1, a2, ak);
+    a0 = fma(ak, bj0, a0);   // the b_j terms of every source at once
+    a1 = fma(ak, bj1, a1);
+    a2 = fma(ak, bj2, a2);
     if (valid) {
         double *o = partial + it.slot * 3 * TILE;
         o[lane] = k2 * a0;

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
 
     for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
         const int n = (int)min(it.src_end - base, (int64_t)TILE);
-        float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+        float f0 = 0.f, f1 = 0.f, f2 = 0.f, fk = 0.f;
         if (QN) {
             __syncthreads();
             if (lane < n) {
@@ -112,9 +112,9 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                 if (__all(ee >= r[17])) {
                     ++n_quad_src;
                     if (QN == 2)
-                        quad2_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2);
+                        quad2_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2, fk);
                     else
-                        quad3_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2);
+                        quad3_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2, fk);
                     continue;
                 }
             }
@@ -135,12 +135,12 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                 }
             } else {
                 pair_acc_f32(y, h0, h1, h2, hh, fb0, fb1, fb2, r[6], r[7], r[8], Ls, r[11], r[12], r[13],
-                             r[14], r[15], r[16], fkr, fnu, f0, f1, f2);
+                             r[14], r[15], r[16], fkr, fnu, f0, f1, f2, fk);
             }
         }
-        a0 += (double)f0;
-        a1 += (double)f1;
-        a2 += (double)f2;
+        a0 += (double)fmaf(fk, fb0, f0);   // the b_j terms of the stage at once
+        a1 += (double)fmaf(fk, fb1, f1);
+        a2 += (double)fmaf(fk, fb2, f2);
     }
     if (valid) {
         double *o = partial + it.slot * 3 * TILE;
