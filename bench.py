@@ -47,12 +47,13 @@ UNIT = "segment-pair evals/s"
 FLOP_F64_EVAL = 126          # FP64 path (pair_acc_f64)
 FLOP_MIX_BAND_F32 = 14       # mixed: offset to the source midpoint and its square (every
                              # pair, variants 0 and 2)
-FLOP_MIX_QUAD_F32 = {0: 129, 2: 147}   # mixed: FP32 2-point (variant 0) and 3-point (variant 2)
+FLOP_MIX_QUAD_F32 = {0: 124, 2: 142}   # mixed: FP32 2-point (variant 0) and 3-point (variant 2)
                                        # source quadrature (quad2/quad3_acc_f32)
 FLOP_MIX_LOC_F64 = 14        # mixed: FP64 offset, axial and perpendicular parts (pairs
                              # that are not evaluated by quadrature)
 FLOP_MIX_CLASS_F32 = 8       # mixed: minimum-distance test (the same pairs)
-FLOP_MIX_FAR_F32 = 144       # mixed: FP32 cancellation-free closed form (pair_acc_f32)
+FLOP_MIX_FAR_F32 = 144       # mixed: FP32 cancellation-free closed form (pair_acc_f32; the
+                             # 4 multiplies that undo the record's quadrature weight not counted)
 FLOP_MIX_NEAR_F64 = 144      # mixed: FP64 closed form of an isolated pair (near field)
 PEAK_F64 = 78.6e12
 PEAK_F32 = 157.3e12

@@ -147,10 +147,12 @@ inline size_t rec64_bytes(int64_t ns)
 // FP32 segment record of the mixed path, REC32A floats per segment (array of
 // structures, read with wavefront-uniform scalar loads or staged in LDS):
 //  0..2 midpoint xm/a rounded to FP32, 3..5 the rounding remainder xm/a - [0..2],
-//  6..8 t, 9 L/a, 11..13 b/a, 14..16 c, and for the source quadrature of the
-//  kernel variant in use (points xm +- hq t with weight Wo each, plus xm with
-//  weight Wc for 3 points): 10 hq, 17 the squared band outside which it is
-//  used, 18 Wo, 19 1 + hq^2, 20 2 hq, 21 Wc, 22..23 zero.
+//  6..8 t, 9 L/a, 11..13 Wo b/a, 14..16 Wo c, and for the source quadrature of
+//  the kernel variant in use (points xm +- hq t with weight Wo each, plus xm
+//  with weight Wc for 3 points): 10 hq, 17 the squared band outside which it
+//  is used, 18 1/Wo, 19 1 + hq^2, 20 2 hq, 21 Wc/Wo, 22..23 zero.  Without a
+//  quadrature Wo = 1.  The field is linear in b (c = b x t), so a rule on the
+//  scaled b and c needs no weight; the closed form unscales them with 1/Wo.
 constexpr int REC32A = 24;
 // Mixed kernel variants: 0 = 2-point source quadrature beyond max(30 L,
 // cutoff + L/2), 1 = no quadrature, 2 = 3-point source quadrature beyond

@@ -203,16 +203,8 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_seg_prep(PrepArgs A)
     }
     if (A.rec32) {
         float *q = A.rec32 + s * REC32A;
-        for (int k = 0; k < 3; ++k) {
-            const double xm = x1[k] + 0.5 * L * t[k];
-            q[k] = (float)xm;
-            q[3 + k] = (float)(xm - (double)q[k]);
-            q[6 + k] = (float)t[k];
-            q[11 + k] = (float)b[k];
-            q[14 + k] = (float)c[k];
-        }
         // source quadrature of the variant: Gauss-Legendre points on the source
-        double hq = 0.0, wo = 0.0, wc = 0.0, band = 0.0;
+        double hq = 0.0, wo = 1.0, wc = 0.0, band = 0.0;
         if (A.quadn == 2) {
             hq = L * 0.28867513459481288225;            // L / (2 sqrt 3)
             wo = 0.5 * L;
@@ -223,13 +215,21 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_seg_prep(PrepArgs A)
             wc = L * (8.0 / 18.0);
             band = fmax(6.0 * L, (double)A.cut + 0.5 * L);
         }
+        for (int k = 0; k < 3; ++k) {
+            const double xm = x1[k] + 0.5 * L * t[k];
+            q[k] = (float)xm;
+            q[3 + k] = (float)(xm - (double)q[k]);
+            q[6 + k] = (float)t[k];
+            q[11 + k] = (float)(wo * b[k]);
+            q[14 + k] = (float)(wo * c[k]);
+        }
         q[9] = (float)L;
         q[10] = (float)hq;
         q[17] = (float)(band * band);
-        q[18] = (float)wo;
+        q[18] = (float)(1.0 / wo);
         q[19] = (float)(1.0 + hq * hq);
         q[20] = (float)(2.0 * hq);
-        q[21] = (float)wc;
+        q[21] = (float)(wc / wo);
         q[22] = 0.f; q[23] = 0.f;
     }
     if (A.sys) {

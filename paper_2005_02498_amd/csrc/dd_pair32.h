@@ -24,11 +24,14 @@ namespace dd {
 //   P3  = 3 I52 = I30 (s1^2 + s1 s2 + s2^2)
 // (from s2^3 - s1^3 = (s2 - s1)(s1^2 + s1 s2 + s2^2), 1 - s^2 = d2 r^2 and
 // u2^2 Ra1^2 - u1^2 Ra2^2 = d2 (u2^2 - u1^2)).  The four reciprocals come in
-// pairs from two: 1/X and 1/Y as Y/(X Y) and X/(X Y).
+// pairs from two: 1/X and 1/Y as Y/(X Y) and X/(X Y).  b and c come scaled by
+// a factor 1/iw (the source record's quadrature weight): the field is linear
+// in them, and iw enters through q, A, Cc and I30 where they meet a scaled
+// quantity.
 __device__ __forceinline__ void pair_acc_f32(
     float y, float h0, float h1, float h2, float hh, float bj0, float bj1, float bj2,
     float t0, float t1, float t2, float L, float b0, float b1, float b2,
-    float c0, float c1, float c2, float kr, float nu, float &f0, float &f1, float &f2, float &fk)
+    float c0, float c1, float c2, float iw, float kr, float nu, float &f0, float &f1, float &f2, float &fk)
 {
     const float d2 = hh + 1.0f;
     const float u2 = L - y;
@@ -52,9 +55,10 @@ __device__ __forceinline__ void pair_acc_f32(
     const float D51 = I31 * (r12 + rr);
     const float P3 = I30 * fmaf(s1, s1 + s2, s2 * s2);
     const float g0 = fmaf(2.0f, I30, E50);
-    const float q = fmaf(c2, h2, fmaf(c1, h1, c0 * h0));
-    const float A = -kr * g0;
-    const float Cc = fmaf(nu, I31, -kr * D51);
+    const float q = iw * fmaf(c2, h2, fmaf(c1, h1, c0 * h0));
+    const float A = -kr * g0 * iw;                      // meets rho x b (scaled)
+    const float Cc = fmaf(nu, I31, -kr * D51) * iw;     // meets c (scaled)
+    const float I30s = I30 * iw;                        // where it meets c
     fk = fmaf(q, I30 + E50, fk);   // kd
     const float rb0 = fmaf(h1, b2, -h2 * b1), rb1 = fmaf(h2, b0, -h0 * b2), rb2 = fmaf(h0, b1, -h1 * b0);
     // sigma b_j / k2 as coefficients of the five vectors rho x b, c, t, rho and b_j
@@ -63,8 +67,8 @@ __device__ __forceinline__ void pair_acc_f32(
     const float cb = fmaf(c2, bj2, fmaf(c1, bj1, c0 * bj0));
     const float rbb = fmaf(rb2, bj2, fmaf(rb1, bj1, rb0 * bj0));
     const float Pt = fmaf(q, fmaf(P3, tb, -D51 * hb), fmaf(Cc, cb, A * rbb));
-    const float Ph = fmaf(q, fmaf(E50, hb, -D51 * tb), -I30 * cb);
-    const float Pc = fmaf(Cc, tb, -I30 * hb);
+    const float Ph = fmaf(q, fmaf(E50, hb, -D51 * tb), -I30s * cb);
+    const float Pc = fmaf(Cc, tb, -I30s * hb);
     const float Pr = A * tb;
     f0 = fmaf(Ph, h0, fmaf(Pt, t0, fmaf(Pc, c0, fmaf(Pr, rb0, f0))));
     f1 = fmaf(Ph, h1, fmaf(Pt, t1, fmaf(Pc, c1, fmaf(Pr, rb1, f1))));
@@ -88,6 +92,7 @@ __device__ __forceinline__ void pair_acc_f32(
 // Summed over the points it depends on them only through
 //   S3 = sum w/Ra^3, S5 = sum w/Ra^5, S3v = sum w v/Ra^3, S5v = sum w v/Ra^5,
 //   S5vv = sum w v^2/Ra^5,
+// with w the weights relative to Wo: Wo itself is carried by b and c,
 // and collects as coefficients of rho x b, c, t, b_j and rho:
 //   rho x b : (t.b_j) Sal                       Sal = -kr (2 S3 + 3 S5)
 //   c       : (rho.b_j) Sga + (t.b_j) Sgv       Sga = -S3, Sgv = -nu S3v + 3 kr S5v
@@ -125,13 +130,13 @@ __device__ __forceinline__ void quad_moments_acc_f32(float e0, float e1, float e
 }
 
 // e = target - source midpoint, ee = |e|^2; s = the source's FP32 record (see
-// REC32A); adds K b_j / k2 to (f0, f1, f2) + fk b_j.  2-point rule: points at
-// v = ym -+ hq, weight Wo each.
+// REC32A), whose b and c carry the weight Wo; adds K b_j / k2 to (f0, f1, f2)
+// + fk b_j.  2-point rule: points at v = ym -+ hq, weight Wo each (in b, c).
 __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, float ee, const float *s,
                                               float bj0, float bj1, float bj2, float kr, float nu,
                                               float &f0, float &f1, float &f2, float &fk)
 {
-    const float hq = s[10], W = s[18];
+    const float hq = s[10];
     const float ym = fmaf(e2, s[8], fmaf(e1, s[7], e0 * s[6]));
     const float base = ee + s[19], tw = s[20] * ym;
     const float vA = ym + hq, vB = ym - hq;
@@ -140,20 +145,21 @@ __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, floa
     const float iA3 = iA2 * iA, iB3 = iB2 * iB;
     const float iA5 = iA3 * iA2, iB5 = iB3 * iB2;
     const float pA = iA5 * vA, pB = iB5 * vB;
-    const float S3 = W * (iA3 + iB3), S5 = W * (iA5 + iB5);
-    const float S3v = W * fmaf(iA3, vA, iB3 * vB), S5v = W * (pA + pB);
-    const float S5vv = W * fmaf(pA, vA, pB * vB);
+    const float S3 = iA3 + iB3, S5 = iA5 + iB5;
+    const float S3v = fmaf(iA3, vA, iB3 * vB), S5v = pA + pB;
+    const float S5vv = fmaf(pA, vA, pB * vB);
     quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2, fk);
 }
 
-// 3-point rule: points at v = ym -+ hq with weight Wo and at v = ym with
-// weight Wc (Gauss-Legendre, hq = (L/2) sqrt(3/5), Wo = 5L/18, Wc = 8L/18).
+// 3-point rule: points at v = ym -+ hq with weight Wo (in b, c) and at v = ym
+// with weight Wc, relative weight Wc/Wo = 8/5 (Gauss-Legendre, hq = (L/2)
+// sqrt(3/5), Wo = 5L/18, Wc = 8L/18).
 // Its error is below 2e-7 relative beyond 6 source lengths from the midpoint.
 __device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, float ee, const float *s,
                                               float bj0, float bj1, float bj2, float kr, float nu,
                                               float &f0, float &f1, float &f2, float &fk)
 {
-    const float hq = s[10], Wo = s[18], Wc = s[21];
+    const float hq = s[10], Wc = s[21];
     const float ym = fmaf(e2, s[8], fmaf(e1, s[7], e0 * s[6]));
     const float base = ee + s[19], tw = s[20] * ym;
     const float vA = ym + hq, vB = ym - hq;
@@ -163,10 +169,10 @@ __device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, floa
     const float iA3 = iA2 * iA, iB3 = iB2 * iB, iC3 = iC2 * iC;
     const float iA5 = iA3 * iA2, iB5 = iB3 * iB2, iC5 = iC3 * iC2;
     const float pA = iA5 * vA, pB = iB5 * vB, pC = iC5 * ym;
-    const float S3 = fmaf(Wc, iC3, Wo * (iA3 + iB3)), S5 = fmaf(Wc, iC5, Wo * (iA5 + iB5));
-    const float S3v = fmaf(Wc, iC3 * ym, Wo * fmaf(iA3, vA, iB3 * vB));
-    const float S5v = fmaf(Wc, pC, Wo * (pA + pB));
-    const float S5vv = fmaf(Wc, pC * ym, Wo * fmaf(pA, vA, pB * vB));
+    const float S3 = fmaf(Wc, iC3, iA3 + iB3), S5 = fmaf(Wc, iC5, iA5 + iB5);
+    const float S3v = fmaf(Wc, iC3 * ym, fmaf(iA3, vA, iB3 * vB));
+    const float S5v = fmaf(Wc, pC, pA + pB);
+    const float S5vv = fmaf(Wc, pC * ym, fmaf(pA, vA, pB * vB));
     quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2, fk);
 }
 

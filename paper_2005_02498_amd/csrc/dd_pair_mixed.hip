@@ -134,8 +134,9 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                     pair_acc_isolated_f64(xq0, xq1, xq2, bj0, bj1, bj2, d, kr, nu, a0, a1, a2);
                 }
             } else {
+                // the record's b and c carry the quadrature weight (1 without a quadrature)
                 pair_acc_f32(y, h0, h1, h2, hh, fb0, fb1, fb2, r[6], r[7], r[8], Ls, r[11], r[12], r[13],
-                             r[14], r[15], r[16], fkr, fnu, f0, f1, f2, fk);
+                             r[14], r[15], r[16], QN ? r[18] : 1.0f, fkr, fnu, f0, f1, f2, fk);
             }
         }
         a0 += (double)fmaf(fk, fb0, f0);   // the b_j terms of the stage at once
