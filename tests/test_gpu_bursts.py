@@ -128,3 +128,28 @@ def test_zero_steps_and_empty_instances():
     xo, ro, _ = O.burst_batch(bt, W.material(), 2, 2, W.DT)
     assert np.all(rg[1] == 0)
     assert normwise(xg - bt.x, xo - bt.x) < 1e-10
+
+
+@pytest.mark.parametrize("prec,steps,tol", [(dd.DD_FP64, 2, 1e-10), (dd.DD_MIXED, 3, 1e-4)])
+def test_full_batch_of_512_sampled(prec, steps, tol):
+    """The benchmark's launch configuration: all 512 burst volumes (256-4096
+    segments each) in one call; eight sampled volumes (the four smallest, two
+    of median size and the two largest of at most 2048 segments, so that the
+    oracle stays fast) against the oracle burst, volume by volume."""
+    insts = W.config2(512)
+    bt = W.pack(insts)
+    xg, rg, _ = _gpu_burst(bt, steps, prec, features=False)
+    ns = np.diff(bt.seg_off)
+    order = np.argsort(ns, kind="stable")
+    small = list(order[:4])
+    mid = list(order[len(order) // 2:len(order) // 2 + 2])
+    big = [i for i in order[::-1] if ns[i] <= 2048][:2]
+    for i in small + mid + big:
+        i = int(i)
+        one = W.pack([insts[i]])
+        xo, ro, _ = O.burst_batch(one, W.material(), 2, steps, W.DT)
+        n0, n1 = bt.node_off[i], bt.node_off[i + 1]
+        e_x = normwise(xg[:, n0:n1] - insts[i].x, xo - insts[i].x)
+        e_r = np.abs(rg[i] - ro[0]).max() / max(np.abs(ro[0]).max(), 1e-300)
+        print(f"volume {i} ({ns[i]} segments): displacement err {e_x:.2e}, rate err {e_r:.2e}")
+        assert e_x < tol and e_r < tol
