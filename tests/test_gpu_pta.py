@@ -105,3 +105,38 @@ def test_pta_invalid_parameters():
         with pytest.raises(dd.DDError):
             dd.dd_pta_step(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"], d["normal"],
                            d["pinned"], d["volume"], rates, np.zeros(3), dd.PTAParams(**kw), MAT, 2, dd.DD_FP64)
+
+
+def test_pta_full_batch_of_512_sampled():
+    """The benchmark's PTA workload (all 512 burst volumes in one call, chunks
+    of 20 steps, at most 10 checks, l(t) = each volume's stress at t = 1e-7 s,
+    delta = 1e-8 s), here in FP64: the four smallest volumes and the smallest
+    one of at least 512 segments against the oracle driver, with the same
+    decisions and values to 1e-10."""
+    insts = W.config2(512)
+    bt = W.pack(insts)
+    d = batch_dev(bt)
+    rates = np.asarray(bt.sigma_app) / 1e-7
+    t = np.full(bt.n_inst, 1e-7)
+    P = dd.PTAParams(dt=W.DT, chunk_steps=20, max_chunks=10, delta=1e-8, lpdot_max=float("inf"))
+    got = dd.dd_pta_step(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"], d["normal"],
+                         d["pinned"], d["volume"], rates, t, P, MAT, 2, dd.DD_FP64)
+    torch.cuda.synchronize()
+    xg = d["x"].cpu().numpy()
+    ns = np.diff(bt.seg_off)
+    order = np.argsort(ns, kind="stable")
+    sample = [int(i) for i in order[:4]] + [int(next(i for i in order if ns[i] >= 512))]
+    OP = pta.PTAParams(dt=W.DT, chunk=20, max_chunks=10, delta=1e-8, lpdot_max=np.inf)
+    tol = 1e-10
+    for i in sample:
+        ref = pta.pta_step(insts[i], 1e-7, rates[i], W.material(), 2, OP)
+        print(f"volume {i} ({ns[i]} segments): steps {got['steps_a'][i]}/{got['steps_b'][i]} "
+              f"(oracle {ref['steps_a']}/{ref['steps_b']}), rerun {got['rerun_chunks'][i]}")
+        for k in ("steps_a", "steps_b", "jumps", "rerun_chunks", "conv_a", "conv_b"):
+            assert got[k][i] == ref[k], k
+        for k in ("g_a", "g_b", "lp_a", "lp_b"):
+            r = np.asarray(ref[k])
+            assert np.abs(got[k][i] - r).max() <= tol * max(np.abs(r).max(), 1e-300), k
+        n0, n1 = bt.node_off[i], bt.node_off[i + 1]
+        disp_g, disp_o = xg[:, n0:n1] - insts[i].x, ref["x"] - insts[i].x
+        assert np.abs(disp_g - disp_o).max() <= tol * max(np.abs(disp_o).max(), 1e-300)
