@@ -492,9 +492,10 @@ struct JunctionArgs {
     // sessile segments in index order: position in the list of segment s
     // (valid where s is sessile; pos[seg_off[i]] .. pos[seg_off[i + 1]] are
     // instance i's), their indices, end points (their nodes never move) and
-    // bounding spheres per JUNC_GROUP consecutive entries
+    // bounding spheres of each (midpoint, half length) and of JUNC_GROUP
+    // consecutive entries
     const int32_t *pos, *ses_idx;
-    const double *ses_x, *ses_sph;
+    const double *ses_x, *ses_ssp, *ses_sph;
 };
 constexpr int JUNC_GROUP = 8;
 
@@ -512,7 +513,7 @@ __global__ void k_ses_flag(Layout L, const int32_t *__restrict__ seg_nodes, cons
 // The compact list of sessile segments and their end points.
 __global__ void k_ses_compact(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
                               const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
-                              int32_t *__restrict__ idx, double *__restrict__ sx)
+                              int32_t *__restrict__ idx, double *__restrict__ sx, double *__restrict__ ssp)
 {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= L.ns || !flag[s]) return;
@@ -523,6 +524,12 @@ __global__ void k_ses_compact(Layout L, const int32_t *__restrict__ seg_nodes, c
     double *o = sx + 6 * q;
     o[0] = x[g1]; o[1] = x[nn + g1]; o[2] = x[2 * nn + g1];
     o[3] = x[g2]; o[4] = x[nn + g2]; o[5] = x[2 * nn + g2];
+    // the segment's own sphere: a point closer than r to it is closer than
+    // L/2 + r to its midpoint
+    const double d0 = o[3] - o[0], d1 = o[4] - o[1], d2 = o[5] - o[2];
+    double *m = ssp + 4 * q;
+    m[0] = 0.5 * (o[0] + o[3]); m[1] = 0.5 * (o[1] + o[4]); m[2] = 0.5 * (o[2] + o[5]);
+    m[3] = 0.5 * sqrt(d0 * d0 + d1 * d1 + d2 * d2);
 }
 
 // Bounding sphere of JUNC_GROUP consecutive entries of the list: centre = the
@@ -556,7 +563,9 @@ __global__ void k_ses_spheres(int64_t ns, const int32_t *__restrict__ pos, const
 // nodes pinned), in index order and other than that one, closer than r_c,
 // with release = t + f a, f = fractions[n][count mod K].  held[n] = 1 for the
 // nodes the glide step must keep fixed.  The sessile segments come from the
-// compact list; groups whose sphere is out of reach are skipped.
+// compact list; groups, and then segments, whose bounding sphere is out of
+// reach are skipped before the exact distance (a division) is formed, which
+// leaves the index order of the tests unchanged.
 __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
                             const uint8_t *__restrict__ pinned, JunctionArgs J, int n_inst,
                             const uint8_t *__restrict__ active, const int64_t *__restrict__ fast_steps, double dt,
@@ -617,6 +626,10 @@ __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, con
         const int64_t qa = g * JUNC_GROUP > q_lo ? g * JUNC_GROUP : q_lo;
         const int64_t qb = (g + 1) * JUNC_GROUP < q_hi ? (g + 1) * JUNC_GROUP : q_hi;
         for (int64_t q = qa; q < qb; ++q) {
+            const double *m = J.ses_ssp + 4 * q;
+            const double g0 = p[0] - m[0], g1 = p[1] - m[1], g2 = p[2] - m[2];
+            const double rs = (m[3] + J.rc) * (1.0 + 1e-9);
+            if (g0 * g0 + g1 * g1 + g2 * g2 >= rs * rs) continue;
             const int64_t s = J.ses_idx[q];
             if (s == ig) continue;
             const double *e = J.ses_x + 6 * q;
@@ -659,19 +672,20 @@ int junction_prepare(Workspace *ws, const Layout &L, const int32_t *seg_nodes, c
     J.rc = jn->capture_radius;
     if ((rc = ensure(ws, WS_SES, sizeof(int32_t) * (3 * ns + 1), &p))) return rc;
     int32_t *flag = (int32_t *)p, *pos = flag + ns, *idx = pos + ns + 1;
-    if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (6 * ns + 4 * ((ns + JUNC_GROUP - 1) / JUNC_GROUP) + 4), &p)))
+    if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (10 * ns + 4 * ((ns + JUNC_GROUP - 1) / JUNC_GROUP) + 4), &p)))
         return rc;
-    double *sx = (double *)p, *sph = sx + 6 * ns;
+    double *sx = (double *)p, *ssp = sx + 6 * ns, *sph = ssp + 4 * ns;
     const unsigned gs = grid_for(ns, 256, INT32_MAX);
     hipLaunchKernelGGL(k_ses_flag, dim3(gs), dim3(256), 0, st, L, seg_nodes, pinned, flag);
     hipLaunchKernelGGL((k_scan<int32_t>), dim3(1), dim3(1024), 0, st, (const int32_t *)flag, ns, pos);
     hipLaunchKernelGGL(k_ses_compact, dim3(gs), dim3(256), 0, st, L, seg_nodes, x, (const int32_t *)flag,
-                       (const int32_t *)pos, idx, sx);
+                       (const int32_t *)pos, idx, sx, ssp);
     hipLaunchKernelGGL(k_ses_spheres, dim3(grid_for((ns + JUNC_GROUP - 1) / JUNC_GROUP, 256, INT32_MAX)), dim3(256),
                        0, st, ns, (const int32_t *)pos, (const double *)sx, sph);
     J.pos = pos;
     J.ses_idx = idx;
     J.ses_x = sx;
+    J.ses_ssp = ssp;
     J.ses_sph = sph;
     return DD_OK;
 }
