@@ -340,18 +340,6 @@ __global__ void k_ensemble(const float *__restrict__ Y, int64_t sY, int members,
 
 
 // ------------------------------------------------- fused inference kernel --
-// One workgroup (4 waves) carries FROWS rows of one member (blockIdx.y)
-// through all four layers in one LDS buffer: the standardised inputs, then
-// each hidden layer's activations overwrite the previous ones (every wave
-// holds its whole output tile in registers until all waves have finished
-// reading the layer's input), so that 4 workgroups fit on a CU.  Rows are
-// padded by 8 bf16 so that the 16-byte fragment reads of 16 consecutive rows
-// fall in distinct banks.  Weight fragments come from global memory
-// (L2-resident), loaded one K step ahead of their use; bias + ReLU are applied
-// when a layer's accumulators are written back.  Hidden layers: each wave owns
-// 64 output columns = 4 x 4 tiles of v_mfma_f32_16x16x32_bf16 over the 64
-// rows.  Output layer: each wave owns 16 rows x 16 (padded) columns.
-constexpr int FROWS = 64;
 constexpr int HSTR = HID + 8;   // LDS row stride of the activations (bf16)
 
 __device__ __forceinline__ bf16x8 lds_frag(const __bf16 *p)
@@ -364,64 +352,118 @@ __device__ __forceinline__ bf16x8 glb_frag(const __bf16 *p)
     return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-// H[FROWS][HSTR] holds the layer input in columns 0..K-1 on entry and the
-// layer output in columns 0..HID-1 on return.
+// One workgroup (RG x CG waves) carries WROWS = 64 RG rows of one member
+// (blockIdx.y) through all four layers in one LDS buffer: the standardised
+// inputs, then each hidden layer's activations overwrite the previous ones
+// (every wave holds its output tile in registers until all waves have read
+// the layer's input).  Rows are padded by 8 bf16 so that the 16-byte fragment
+// reads of 16 consecutive rows fall in distinct banks.  Hidden layers: wave w
+// owns rows 64 (w / CG) .. +63 and output columns 16 JT (w % CG) .. +16 JT - 1
+// (4 x JT tiles of v_mfma_f32_16x16x32_bf16); bias + ReLU are applied when
+// the accumulators are written back.  The layer's weights come through LDS
+// one K step (32 inputs x 256 outputs) at a time, loaded once per workgroup
+// and read by the RG waves of every column group, so each weight reaches the
+// CU once per WROWS rows: the L2-to-CU weight traffic, which bounds a
+// workgroup of 64 rows that streams every wave's own weights, falls by RG.
+// The next slice is fetched into registers one step ahead; two barriers per
+// step guard the one slice buffer (a second does not fit beside the
+// activations).  Output layer: its weights also go through LDS, and the waves
+// split the WROWS rows in tiles of 16.
+constexpr int WRG = 4;                  // row groups of 64
+constexpr int WJT = 4;                  // 16-column tiles per wave
+constexpr int WCG = HID / (16 * WJT);   // column groups
+constexpr int WROWS = 64 * WRG;
+constexpr int WTHREADS = 64 * WRG * WCG;
+constexpr int WSTR = 32;                // LDS row stride of a weight slice (bf16)
+constexpr int WSLICE = HID * WSTR;      // one slice buffer (bf16)
+constexpr int WCHUNKS = HID * 32 / 8;   // 16-byte chunks per slice
+constexpr int WPER = (WCHUNKS + WTHREADS - 1) / WTHREADS;
+
+// Position of 16-byte chunk c (0..3) of output row o in a slice buffer: the
+// chunk index is XOR-ed with bits 1-2 of the row, so that both the fragment
+// reads (16 rows, one chunk) and the stores (4 rows, 4 chunks) of 16 lanes
+// spread over all banks.
+__device__ __forceinline__ int slice_pos(int o, int c)
+{
+    return o * WSTR + ((c ^ ((o >> 1) & 3)) << 3);
+}
+
 template <int K>
-__device__ __forceinline__ void hidden_layer(__bf16 *__restrict__ H, const __bf16 *__restrict__ W,
-                                             const float *__restrict__ bias, int wave, int lane)
+__device__ __forceinline__ void hidden_layer(__bf16 *__restrict__ H, __bf16 *__restrict__ Ws,
+                                             const __bf16 *__restrict__ W, const float *__restrict__ bias,
+                                             int wave, int lane, int tid)
 {
     // W: [HID][K] (out, in), K contiguous
-    f32x4 acc[4][4];
+    constexpr int NS = K / 32;
+    f32x4 acc[4][WJT];
     for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < WJT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int lr = lane & 15, lk = (lane >> 4) * 8;
-    const int n0 = wave * 64;
-    const __bf16 *Wl = W + (int64_t)(n0 + lr) * K + lk;
-    bf16x8 bn[4];
+    const int rg = wave / WCG, cg = wave % WCG;
+    // this thread's chunks of a slice: chunk c = output row c / 4, inputs 8 (c % 4) .. +7
+    bf16x8 pre[WPER];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) bn[j] = glb_frag(Wl + (int64_t)16 * j * K);
+    for (int u = 0; u < WPER; ++u) {
+        const int c = tid + u * WTHREADS;
+        if (c < WCHUNKS) pre[u] = glb_frag(W + (int64_t)(c >> 2) * K + (c & 3) * 8);
+    }
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 b[4], a[4];
+    for (int st = 0; st < NS; ++st) {
+        if (st > 0) __syncthreads();   // slice st - 1 read by every wave
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = bn[j];
-        if (k0 + 32 < K) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bn[j] = glb_frag(Wl + (int64_t)16 * j * K + k0 + 32);
+        for (int u = 0; u < WPER; ++u) {
+            const int c = tid + u * WTHREADS;
+            if (c < WCHUNKS) *reinterpret_cast<bf16x8 *>(Ws + slice_pos(c >> 2, c & 3)) = pre[u];
         }
+        if (st + 1 < NS) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = lds_frag(H + (16 * i + lr) * HSTR + k0 + lk);
+            for (int u = 0; u < WPER; ++u) {
+                const int c = tid + u * WTHREADS;
+                if (c < WCHUNKS) pre[u] = glb_frag(W + (int64_t)(c >> 2) * K + 32 * (st + 1) + (c & 3) * 8);
+            }
+        }
+        __syncthreads();   // slice st (and, at st = 0, the layer input) in place
+        const int k0 = 32 * st;
+        bf16x8 a[4], b[WJT];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = lds_frag(H + (64 * rg + 16 * i + lr) * HSTR + k0 + lk);
+#pragma unroll
+        for (int j = 0; j < WJT; ++j) b[j] = lds_frag(Ws + slice_pos(16 * WJT * cg + 16 * j + lr, lane >> 4));
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < WJT; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    __syncthreads();   // every wave has read the layer input
-    for (int j = 0; j < 4; ++j) {
-        const int n = n0 + 16 * j + lr;
+    __syncthreads();   // every wave has read the layer input and the last slice
+    for (int j = 0; j < WJT; ++j) {
+        const int n = 16 * WJT * cg + 16 * j + lr;
         const float bn_ = bias[n];
         for (int i = 0; i < 4; ++i)
             for (int e = 0; e < 4; ++e) {
-                const int r = 16 * i + (lane >> 4) * 4 + e;
+                const int r = 64 * rg + 16 * i + (lane >> 4) * 4 + e;
                 H[r * HSTR + n] = to_bf16(fmaxf(acc[i][j][e] + bn_, 0.f));
             }
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ feat, int64_t n,
-                                                   const float *__restrict__ scal, const __bf16 *__restrict__ W1p,
-                                                   const __bf16 *__restrict__ W2, const __bf16 *__restrict__ W3,
-                                                   const __bf16 *__restrict__ W4p, const float *__restrict__ w,
-                                                   float *__restrict__ Y, int64_t sY)
+__global__ __launch_bounds__(WTHREADS) void k_mlp_infer(const float *__restrict__ feat, int64_t n,
+                                                             const float *__restrict__ scal,
+                                                             const __bf16 *__restrict__ W1p,
+                                                             const __bf16 *__restrict__ W2,
+                                                             const __bf16 *__restrict__ W3,
+                                                             const __bf16 *__restrict__ W4p,
+                                                             const float *__restrict__ w, float *__restrict__ Y,
+                                                             int64_t sY)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 H[FROWS * HSTR];
+    __shared__ __attribute__((aligned(16))) __bf16 H[WROWS * HSTR];
+    __shared__ __attribute__((aligned(16))) __bf16 Ws[WSLICE];
     const int member = blockIdx.y;
-    const int64_t r0 = (int64_t)blockIdx.x * FROWS;
+    const int64_t r0 = (int64_t)blockIdx.x * WROWS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const float dfloor = scal[2 * IN + 2 * OUT + 1], dscale = scal[2 * IN + 2 * OUT];
     // standardised input tile (rows beyond n and columns beyond IN are zero)
-    for (int i = tid; i < FROWS * INP; i += 256) {
+    for (int i = tid; i < WROWS * INP; i += WTHREADS) {
         const int r = i / INP, k = i % INP;
         float v = 0.f;
         if (k < IN && r0 + r < n) {
@@ -431,31 +473,39 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float *__restrict__ fea
         }
         H[r * HSTR + k] = to_bf16(v);
     }
-    __syncthreads();
     const float *wm = w + member * P;
-    hidden_layer<INP>(H, W1p + (int64_t)member * HID * INP, wm + OB1, wave, lane);
-    __syncthreads();
-    hidden_layer<HID>(H, W2 + (int64_t)member * HID * HID, wm + OB2, wave, lane);
-    __syncthreads();
-    hidden_layer<HID>(H, W3 + (int64_t)member * HID * HID, wm + OB3, wave, lane);
-    __syncthreads();
-    // output layer: wave owns rows 16 wave .. +15, 16 padded columns
+    hidden_layer<INP>(H, Ws, W1p + (int64_t)member * HID * INP, wm + OB1, wave, lane, tid);
+    hidden_layer<HID>(H, Ws, W2 + (int64_t)member * HID * HID, wm + OB2, wave, lane, tid);
+    hidden_layer<HID>(H, Ws, W3 + (int64_t)member * HID * HID, wm + OB3, wave, lane, tid);
+    // the output layer's weights [16][256] to the slice buffer, row stride HSTR
+    // (every wave has finished reading the last slice inside hidden_layer)
+    static_assert(OUTP * HSTR <= WSLICE, "output weights fit the slice buffer");
+    const __bf16 *W4m = W4p + (int64_t)member * OUTP * HID;
+    for (int c = tid; c < OUTP * HID / 8; c += WTHREADS)
+        *reinterpret_cast<bf16x8 *>(Ws + (c / (HID / 8)) * HSTR + (c % (HID / 8)) * 8) = glb_frag(W4m + 8 * c);
+    __syncthreads();   // last hidden activations and output weights in place
+    // output layer: wave owns WROWS / (waves) rows in tiles of 16, 16 padded columns
+    constexpr int OT = WROWS / 16 / (WRG * WCG);   // row tiles per wave
     {
         const int lr = lane & 15, lk = (lane >> 4) * 8;
-        const __bf16 *W4m = W4p + (int64_t)member * OUTP * HID;
-        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 acc[OT];
+        for (int t = 0; t < OT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int k0 = 0; k0 < HID; k0 += 32) {
-            const bf16x8 a = lds_frag(H + (16 * wave + lr) * HSTR + k0 + lk);
-            const bf16x8 b = glb_frag(W4m + lr * HID + k0 + lk);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+            const bf16x8 b = lds_frag(Ws + lr * HSTR + k0 + lk);
+#pragma unroll
+            for (int t = 0; t < OT; ++t) {
+                const bf16x8 a = lds_frag(H + (16 * (OT * wave + t) + lr) * HSTR + k0 + lk);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+            }
         }
         const int o = lr;
         const float bo = o < OUT ? wm[OB4 + o] : 0.f;
-        for (int e = 0; e < 4; ++e) {
-            const int64_t r = r0 + 16 * wave + (lane >> 4) * 4 + e;
-            if (r < n) Y[member * sY + r * OUTP + o] = acc[e] + bo;
-        }
+        for (int t = 0; t < OT; ++t)
+            for (int e = 0; e < 4; ++e) {
+                const int64_t r = r0 + 16 * (OT * wave + t) + (lane >> 4) * 4 + e;
+                if (r < n) Y[member * sY + r * OUTP + o] = acc[t][e] + bo;
+            }
     }
 }
 
@@ -898,9 +948,9 @@ extern "C" int dd_surrogate_rates(const dd_mlp *hc, int64_t n, const float *feat
     if ((rc = ensure_rows(h, chunk, false))) return rc;
     for (int64_t r0 = 0; r0 < n; r0 += chunk) {
         const int64_t m = std::min(chunk, n - r0);
-        dim3 grid((unsigned)((m + FROWS - 1) / FROWS), h->members);
-        hipLaunchKernelGGL(k_mlp_infer, grid, dim3(256), 0, st, feat + r0 * IN, m, h->scal, h->W1p, h->W2, h->W3,
-                           h->W4p, h->w, h->Y, m * OUTP);
+        dim3 grid((unsigned)((m + WROWS - 1) / WROWS), h->members);
+        hipLaunchKernelGGL(k_mlp_infer, grid, dim3(WTHREADS), 0, st, feat + r0 * IN, m, h->scal, h->W1p, h->W2,
+                           h->W3, h->W4p, h->w, h->Y, m * OUTP);
         hipLaunchKernelGGL(k_ensemble, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, h->Y, m * OUTP,
                            h->members, m, h->scal, spread_tol, rates + r0 * OUT, spread + r0, needs_dd + r0);
     }
