@@ -403,7 +403,7 @@ int dd_pta_step_junctions(int32_t n_inst, const int64_t *node_off, const int64_t
  * r = by * n + bx.  Fields: Gauss-point arrays [n_gp][c] and block arrays
  * [n * n][c] of float64 (c components, 1..16: a tensor is 9 components in
  * row-major order ij, a vector 3), device memory owned by the caller.  Valid:
- * n, m >= 1, n m <= 65535, B, h finite and > 0.  Errors: DD_EINVAL. */
+ * n, m >= 1, n m <= 65535, n <= 46340, B, h finite and > 0.  Errors: DD_EINVAL. */
 typedef struct { int32_t n, m; double B, h; } dd_block_mesh;
 
 /* Block averages <f>_r = int_{Omega_r} f dv / |Omega_r| of a Gauss-point field

@@ -146,8 +146,10 @@ __global__ void k_block_interp(BlockGeom G, const double *__restrict__ A, double
     const double im = 1.0 / (double)m;
     const double xb = -1.0 + ((double)(2 * (ex - bx * m) + 1) + xg) * im;
     const double yb = -1.0 + ((double)(2 * (ey - by * m) + 1) + yg) * im;
-    const double a00 = A[(by * N + bx) * c + k], a10 = A[(by * N + bx + 1) * c + k];
-    const double a01 = A[((by + 1) * N + bx) * c + k], a11 = A[((by + 1) * N + bx + 1) * c + k];
+    // block-mesh nodes: (n + 1)^2 c values can pass 2^31, so these indices are 64-bit
+    const int64_t q0 = ((int64_t)by * N + bx) * c + k, q1 = q0 + (int64_t)N * c;
+    const double a00 = A[q0], a10 = A[q0 + c];
+    const double a01 = A[q1], a11 = A[q1 + c];
     out[(int64_t)ey * row_len + o] = 0.25 * ((1.0 - xb) * (1.0 - yb) * a00 + (1.0 + xb) * (1.0 - yb) * a10 +
                                              (1.0 - xb) * (1.0 + yb) * a01 + (1.0 + xb) * (1.0 + yb) * a11);
 }
@@ -199,6 +201,7 @@ int check_mesh(const dd_block_mesh *mesh, int c, BlockGeom &G)
         return set_error(DD_EINVAL, "block size and thickness must be finite and > 0");
     if (c < 1 || c > MAX_COMP) return set_error(DD_EINVAL, "components must be 1..%d", MAX_COMP);
     if ((int64_t)mesh->n * mesh->m > 65535) return set_error(DD_EINVAL, "n * m must be at most 65535");
+    if ((int64_t)mesh->n * mesh->n > INT32_MAX) return set_error(DD_EINVAL, "n must be at most 46340");
     G.n = mesh->n;
     G.m = mesh->m;
     G.ne = G.n * G.m;

@@ -59,7 +59,7 @@ def test_host_only_calls_without_gpu():
     # block-coupling argument checks happen before any device work
     fake = ctypes.c_void_p(256)
     for bad in ((0, 1, 1.0, 1.0), (1, 0, 1.0, 1.0), (1, 1, 0.0, 1.0), (1, 1, 1.0, float("nan")),
-                (70000, 1, 1.0, 1.0)):
+                (70000, 1, 1.0, 1.0), (46341, 1, 1.0, 1.0)):
         mesh = dd.BlockMesh(*bad)
         assert dd.lib().dd_block_average(ctypes.byref(mesh), 1, fake, fake, None) == dd.DD_EINVAL
         assert dd.lib().dd_block_to_gauss(ctypes.byref(mesh), 1, fake, fake, None) == dd.DD_EINVAL
