@@ -3,8 +3,10 @@
 
 A step is one pass of the path over the single-volume workload: segment
 preparation, the all-pairs non-singular stress at every Gauss point, the
-Peach-Koehler contraction, the quadrature to nodal forces (dd_nodal_forces),
-then the glide-constrained mobility and forward-Euler update (dd_glide_step).
+Peach-Koehler contraction, the quadrature to nodal forces, then the
+glide-constrained mobility and forward-Euler update: one dd_step call (the
+same as dd_nodal_forces followed by dd_glide_step, with the node lists built
+once).
 Workload: 16,384 straight segments (512 regular 32-gon glide loops on random
 {111} planes, radii U[100, 500] b, centres in a 10,000 b cube, seed 1), 2 Gauss
 points per segment, FP64, inputs resident in HBM.  value = segment pairs
@@ -371,8 +373,7 @@ def main():
         x, sn, bg, nr, F, V = v["x"].clone(), v["sn"], v["b"], v["n"], v["F"], v["V"]
 
         def step():
-            dd.dd_nodal_forces(x, sn, bg, nr, v["sig"], mat, Q, prec, 20.0, force_out=F)
-            dd.dd_glide_step(x, F, sn, nr, None, mat, W.DT, vel_out=V)
+            dd.dd_step(x, sn, bg, nr, None, v["sig"], mat, W.DT, Q, prec, 20.0, force_out=F, vel_out=V)
 
         for _ in range(warmup):
             step()
@@ -493,7 +494,7 @@ def main():
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
             "data": "synthetic",
             "config": {"workload": "single volume: 16,384 segments (512 glide loops x 32) in a "
-                                   "10,000 b cube, 2 Gauss points, FP64; nodal forces + glide step",
+                                   "10,000 b cube, 2 Gauss points, FP64; nodal forces + glide step (dd_step)",
                        "segments": N, "gauss_points": 2, "precision": "fp64",
                        "pairs_per_step": pairs, "gauss_evals_per_step": 2 * pairs},
             "gauss_evals_per_s": 2 * pairs / step_s,

@@ -228,6 +228,20 @@ int dd_glide_step(int64_t n_nodes, double *x, const double *force,
                   const dd_material *m, double dt, double *vel_out,
                   void *stream);
 
+/* One DD time step: dd_nodal_forces at x, then dd_glide_step with those
+ * forces (Sec. "Discrete Dislocation Dynamics", Eq. DD_evol), in one call
+ * that builds the node-to-segment lists once and takes the segment lengths
+ * of the glide step from the force pass, so the Euler update is fused into
+ * the glide kernel.  Same results as the two calls up to rounding (lengths
+ * are formed in units of a).  Arguments: as the two calls; x [3][n_nodes]
+ * updated in place; pinned nullable; m host (mu, nu, a, B); force_out and
+ * vel_out [3][n_nodes] nullable (then workspace is used).  Errors: as the two
+ * calls. */
+int dd_step(int64_t n_nodes, double *x, int64_t n_segs, const int32_t *seg_nodes, const double *burgers,
+            const double *normal, const uint8_t *pinned, const double *sigma_app, const dd_material *m,
+            int n_gauss, int precision, double near_cutoff_a, double dt, double *force_out, double *vel_out,
+            void *stream);
+
 /* Independent DD bursts at frozen applied stress, all advanced together.
  *  Instance i owns nodes [node_off[i], node_off[i+1]) and segments
  *  [seg_off[i], seg_off[i+1]) of the packed arrays; its seg_nodes are local

@@ -26,7 +26,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
     "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_exact_band", "dd_set_plan", "dd_last_plan",
-    "dd_nodal_forces", "dd_glide_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_pta_step", "dd_pta_step_junctions",
+    "dd_nodal_forces", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_pta_step", "dd_pta_step_junctions",
     "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -120,6 +120,8 @@ def _declare(L):
                                       C.POINTER(Material), C.c_int, C.c_int, dbl, vp, vp]),
         "dd_glide_step": (C.c_int, [i64, vp, vp, i64, vp, vp, vp, C.POINTER(Material), dbl,
                                     vp, vp]),
+        "dd_step": (C.c_int, [i64, vp, i64, vp, vp, vp, vp, C.POINTER(C.c_double), C.POINTER(Material), C.c_int,
+                              C.c_int, dbl, dbl, vp, vp, vp]),
         "dd_burst_batch": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp,
                                      vp, vp, vp, vp, vp, C.POINTER(Material), C.c_int, C.c_int,
                                      dbl, C.c_int, dbl, vp, vp, vp]),
@@ -331,6 +333,28 @@ def dd_glide_step(x, force, seg_nodes, normal, pinned, mat, dt, vel_out=None, st
     _check(lib().dd_glide_step(nn, px, pf, ns, psn, pn, pp, C.byref(m), float(dt), pv,
                                _stream(stream)))
     return vel_out
+
+
+def dd_step(x, seg_nodes, burgers, normal, pinned, sigma_app, mat, dt, n_gauss=2, precision=DD_FP64,
+            near_cutoff_a=20.0, force_out=None, vel_out=None, stream=None):
+    """One DD step (nodal forces, then the glide step) in one call; x advances
+    in place.  Returns (force, vel) [3][n_nodes] (None where the library used
+    its workspace because the output was not requested: pass tensors to keep
+    them)."""
+    nn = x.shape[1] if x.dim() == 2 else -1
+    ns = seg_nodes.shape[1] if seg_nodes.dim() == 2 else -1
+    px = _dev(x, torch.float64, (3, nn), "x")
+    psn = _dev(seg_nodes, torch.int32, (2, ns), "seg_nodes")
+    pb = _dev(burgers, torch.float64, (3, ns), "burgers")
+    pn = _dev(normal, torch.float64, (3, ns), "normal")
+    pp = _dev(pinned, torch.uint8, (nn,), "pinned", nullable=True)
+    pf = _dev(force_out, torch.float64, (3, nn), "force_out", nullable=True)
+    pv = _dev(vel_out, torch.float64, (3, nn), "vel_out", nullable=True)
+    sig = (C.c_double * 6)(*[float(v) for v in sigma_app])
+    m = _mat(mat)
+    _check(lib().dd_step(nn, px, ns, psn, pb, pn, pp, sig, C.byref(m), int(n_gauss), _prec(precision),
+                         float(near_cutoff_a), float(dt), pf, pv, _stream(stream)))
+    return force_out, vel_out
 
 
 def dd_burst_batch(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app,

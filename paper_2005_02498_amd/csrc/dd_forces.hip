@@ -1556,6 +1556,67 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
     return DD_OK;
 }
 
+extern "C" int dd_step(int64_t n_nodes, double *x, int64_t n_segs, const int32_t *seg_nodes,
+                       const double *burgers, const double *normal, const uint8_t *pinned,
+                       const double *sigma_app, const dd_material *m, int n_gauss, int precision,
+                       double near_cutoff_a, double dt, double *force_out, double *vel_out, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a))) return rc;
+    if ((rc = check_material(m, true))) return rc;
+    if (!sigma_app) return set_error(DD_EINVAL, "sigma_app is null");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(DD_EINVAL, "dt must be > 0");
+    if (n_nodes > 0 && !x) return set_error(DD_EINVAL, "null x");
+    if (n_segs > 0 && (!seg_nodes || !burgers || !normal)) return set_error(DD_EINVAL, "null segment array");
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(sigma_app[k])) return set_error(DD_EINVAL, "non-finite sigma_app");
+    if (n_nodes == 0) return DD_OK;
+    hipStream_t st = (hipStream_t)stream;
+    Workspace *ws;
+    if ((rc = workspace(&ws))) return rc;
+    ForceCtx C;
+    std::vector<int64_t> so = {0, n_segs};
+    int64_t choice = 0;
+    Layout flat{};
+    if ((rc = tuned_chunk(ws, st, so, n_nodes, flat, seg_nodes, x, burgers, normal, m, n_gauss, precision,
+                          near_cutoff_a, false, &choice)))
+        return rc;
+    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / MIXED_VARIANTS,
+                    false, C)))
+        return rc;
+    C.variant = (int)(choice % MIXED_VARIANTS);
+    g_last_variant = C.variant;
+    void *p;
+    double *F = force_out, *vel = vel_out;
+    if (!F) {
+        if ((rc = ensure(ws, WS_FORCE, sizeof(double) * 3 * n_nodes, &p))) return rc;
+        F = (double *)p;
+    }
+    if (!vel) {
+        if ((rc = ensure(ws, WS_VEL, sizeof(double) * 3 * n_nodes, &p))) return rc;
+        vel = (double *)p;
+    }
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
+    launch_csr(C, seg_nodes, st);
+    Sig6 sv;
+    for (int k = 0; k < 6; ++k) sv.v[k] = sigma_app[k];
+    launch_forces(C, ws, x, seg_nodes, burgers, normal, nullptr, sv, F, st);
+    // lengths from the segment records of this force pass: x can move in the same kernel
+    hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(n_nodes, 256, INT32_MAX)), dim3(256), 0, st, C.L, C.csr_ptr,
+                       C.csr_list, seg_nodes, normal, (const double *)C.rec64, C.a, x, (const double *)F, pinned,
+                       (const uint8_t *)nullptr, (const uint8_t *)nullptr, 1.0 / m->B, dt, vel);
+    DD_HIP(hipGetLastError());
+    if (validation_on()) {
+        hipLaunchKernelGGL(k_check_finite, dim3(grid_for(3 * n_nodes)), dim3(256), 0, st, (const double *)F,
+                           3 * n_nodes, ws->flags_dev);
+        hipLaunchKernelGGL(k_check_finite, dim3(grid_for(3 * n_nodes)), dim3(256), 0, st, (const double *)x,
+                           3 * n_nodes, ws->flags_dev);
+        return read_flags(ws, st);
+    }
+    return DD_OK;
+}
+
 namespace dd {
 namespace {
 int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,

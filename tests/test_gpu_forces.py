@@ -282,6 +282,52 @@ def test_glide_step_multiple_normals():
         np.testing.assert_allclose(xt.cpu().numpy(), xo, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("prec", [dd.DD_FP64, dd.DD_MIXED])
+def test_step_equals_forces_then_glide(prec):
+    """dd_step = dd_nodal_forces then dd_glide_step.  First step: the same
+    forces bit for bit (same positions), velocities and positions up to the
+    rounding of the segment lengths (formed in units of a in the fused glide).
+    Two more steps from the slightly different positions: within the path's
+    tolerance."""
+    inst = W.burst_instance(1_000_006)
+    d1, d2 = dev(inst), dev(inst)
+    F1 = torch.empty_like(d1["x"])
+    F2, V2 = torch.empty_like(d1["x"]), torch.empty_like(d1["x"])
+    tol = TOL64 if prec == dd.DD_FP64 else TOLMIX
+    for step in range(3):
+        dd.dd_nodal_forces(d1["x"], d1["seg_nodes"], d1["burgers"], d1["normal"], inst.sigma_app, MAT, 2, prec,
+                           20.0, force_out=F1)
+        V1 = dd.dd_glide_step(d1["x"], F1, d1["seg_nodes"], d1["normal"], d1["pinned"], MAT, W.DT)
+        dd.dd_step(d2["x"], d2["seg_nodes"], d2["burgers"], d2["normal"], d2["pinned"], inst.sigma_app, MAT, W.DT,
+                   2, prec, 20.0, force_out=F2, vel_out=V2)
+        torch.cuda.synchronize()
+        f1, f2 = F1.cpu().numpy(), F2.cpu().numpy()
+        v1, v2 = V1.cpu().numpy(), V2.cpu().numpy()
+        if step == 0:
+            assert np.array_equal(f1, f2)
+            np.testing.assert_allclose(v2, v1, rtol=0, atol=1e-13 * np.abs(v1).max())
+            np.testing.assert_allclose(d2["x"].cpu().numpy(), d1["x"].cpu().numpy(), rtol=0, atol=1e-12)
+        else:
+            assert normwise(f2, f1) < tol
+            assert normwise(v2, v1) < tol
+    assert normwise(d2["x"].cpu().numpy() - inst.x, d1["x"].cpu().numpy() - inst.x) < tol
+
+
+def test_step_vs_oracle():
+    """One dd_step against the oracle's forces and glide step."""
+    inst = W.burst_instance(1_000_005)
+    F = _oracle_forces(inst, 2)
+    xo, vo = O.glide_step(inst.x, F, inst.seg_nodes, inst.normal, inst.pinned, W.DRAG_B, W.DT)
+    d = dev(inst)
+    Fg, Vg = torch.empty_like(d["x"]), torch.empty_like(d["x"])
+    dd.dd_step(d["x"], d["seg_nodes"], d["burgers"], d["normal"], d["pinned"], inst.sigma_app, MAT, W.DT, 2,
+               dd.DD_FP64, 20.0, force_out=Fg, vel_out=Vg)
+    torch.cuda.synchronize()
+    assert normwise(Fg.cpu().numpy(), F) < TOL64
+    np.testing.assert_allclose(Vg.cpu().numpy(), vo, rtol=0, atol=1e-12 * np.abs(vo).max())
+    np.testing.assert_allclose(d["x"].cpu().numpy(), xo, rtol=0, atol=1e-11)
+
+
 @functools.lru_cache(maxsize=1)
 def _large_volume_sample():
     """The oracle's nodal forces of 1024 target segments (32 whole loops spread
