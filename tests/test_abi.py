@@ -74,6 +74,10 @@ def test_host_only_calls_without_gpu():
     assert dd.lib().dd_burst_batch_junctions(1, off, off, fake, fake, fake, fake, fake, fake, fake,
                                              ctypes.byref(m), 2, 0, 20.0, 1, 1.0, None, fake, None,
                                              None) == dd.DD_EINVAL
+    sig = (ctypes.c_double * 6)()
+    for args in ((-1, 1.0), (4, 0.0), (4, float("nan"))):   # negative count, dt <= 0, NaN dt
+        assert dd.lib().dd_step(args[0], fake, 4, fake, fake, fake, None, sig, ctypes.byref(m), 2, 0, 20.0,
+                                args[1], None, None, None) == dd.DD_EINVAL
     P = dd.PTAParams(dt=1e-14)
     d1 = (ctypes.c_double * 6)()
     assert dd.lib().dd_pta_step_junctions(1, off, off, fake, fake, fake, fake, fake, fake, d1, d1,
