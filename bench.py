@@ -51,8 +51,8 @@ FLOP_MIX_BAND_F32 = 14       # mixed: offset to the source midpoint and its squa
                              # pair, variants 0 and 2)
 FLOP_MIX_QUAD_F32 = {0: 124, 2: 142}   # mixed: FP32 2-point (variant 0) and 3-point (variant 2)
                                        # source quadrature (quad2/quad3_acc_f32)
-FLOP_MIX_LOC_F64 = 14        # mixed: FP64 offset, axial and perpendicular parts (pairs
-                             # that are not evaluated by quadrature)
+FLOP_MIX_LOC_F32 = 13        # mixed: FP32 axial and perpendicular parts from the midpoint
+                             # offset (pairs that are not evaluated by quadrature)
 FLOP_MIX_CLASS_F32 = 8       # mixed: minimum-distance test (the same pairs)
 FLOP_MIX_FAR_F32 = 144       # mixed: FP32 cancellation-free closed form (pair_acc_f32; the
                              # 4 multiplies that undo the record's quadrature weight not counted)
@@ -449,12 +449,12 @@ def main():
         else:
             near, quad, variant = bands[:3]
             allp = N * N * Q                 # including the (skipped) self pairs
-            other = allp - quad              # pairs located in FP64
+            other = allp - quad              # pairs located in FP32 (not by quadrature)
             closed = pairs * Q - quad - near
             band = allp if variant in (0, 2) else 0
-            f64 = FLOP_MIX_LOC_F64 * other + FLOP_MIX_NEAR_F64 * near
+            f64 = FLOP_MIX_NEAR_F64 * near
             f32 = (FLOP_MIX_BAND_F32 * band + FLOP_MIX_QUAD_F32.get(variant, 0) * quad
-                   + FLOP_MIX_CLASS_F32 * other + FLOP_MIX_FAR_F32 * closed)
+                   + (FLOP_MIX_LOC_F32 + FLOP_MIX_CLASS_F32) * other + FLOP_MIX_FAR_F32 * closed)
         flops = f64 + f32
         t_roof = f64 / PEAK_F64 + f32 / PEAK_F32
         t_meas = f64 / peaks_measured["fp64"] + f32 / peaks_measured["fp32_vec"]

@@ -20,10 +20,10 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // wavefront, the midpoint lies outside the source's band (max(30 L, cutoff +
 // L/2) for 2 points, max(6 L, cutoff + L/2) for 3), the source is evaluated by
 // FP32 quadrature.  With QN = 0 the FP32 records are read with scalar loads.
-// Other pairs get their offset, axial and perpendicular parts in FP64: those
-// closer than the cutoff (minimum distance from the Gauss point to the closed
-// source segment) are evaluated in FP64, the rest by the cancellation-free
-// FP32 closed form.  FP32 contributions are summed in FP32 over TILE sources
+// Other pairs get their axial and perpendicular parts in FP32 from the same
+// midpoint offset: those closer than the cutoff (minimum distance from the
+// Gauss point to the closed source segment) are evaluated in FP64 from the
+// FP64 record, the rest by the cancellation-free FP32 closed form.  FP32 contributions are summed in FP32 over TILE sources
 // at a time, then added to FP64 sums; all sums are in units of k2 and scaled
 // once at the end.
 template <int QN>
@@ -104,10 +104,12 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
 #pragma unroll
                 for (int f = 0; f < 8; ++f) r[16 + f] = vb[f];
             }
+            // offset from the source midpoint, from the split FP32 positions:
+            // accurate to the rounding of its own size
+            const float e0 = (xh0 - r[0]) + (xl0 - r[3]);
+            const float e1 = (xh1 - r[1]) + (xl1 - r[4]);
+            const float e2 = (xh2 - r[2]) + (xl2 - r[5]);
             if (QN) {
-                const float e0 = (xh0 - r[0]) + (xl0 - r[3]);
-                const float e1 = (xh1 - r[1]) + (xl1 - r[4]);
-                const float e2 = (xh2 - r[2]) + (xl2 - r[5]);
                 const float ee = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
                 if (__all(ee >= r[17])) {
                     ++n_quad_src;
@@ -118,20 +120,17 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                     continue;
                 }
             }
-            // offset, axial and perpendicular parts in FP64, rounded once
-            const double *d = ra + m * RECA;
-            const double R0 = xq0 - d[0], R1 = xq1 - d[1], R2 = xq2 - d[2];
-            const double yd = fma(R2, d[5], fma(R1, d[4], R0 * d[3]));
-            const float y = (float)yd;
-            const float h0 = (float)fma(-yd, d[3], R0), h1 = (float)fma(-yd, d[4], R1),
-                        h2 = (float)fma(-yd, d[5], R2);
-            const float hh = fmaf(h2, h2, fmaf(h1, h1, h0 * h0));
+            // axial coordinate from the first node and perpendicular part
             const float Ls = r[9];
+            const float ym = fmaf(e2, r[8], fmaf(e1, r[7], e0 * r[6]));
+            const float y = fmaf(0.5f, Ls, ym);
+            const float h0 = fmaf(-ym, r[6], e0), h1 = fmaf(-ym, r[7], e1), h2 = fmaf(-ym, r[8], e2);
+            const float hh = fmaf(h2, h2, fmaf(h1, h1, h0 * h0));
             const float ya = y - fminf(fmaxf(y, 0.f), Ls);
             if (hh + ya * ya < cut2) {
                 if (m != j) {
                     n_near += valid ? 1u : 0u;
-                    pair_acc_isolated_f64(xq0, xq1, xq2, bj0, bj1, bj2, d, kr, nu, a0, a1, a2);
+                    pair_acc_isolated_f64(xq0, xq1, xq2, bj0, bj1, bj2, ra + m * RECA, kr, nu, a0, a1, a2);
                 }
             } else {
                 // the record's b and c carry the quadrature weight (1 without a quadrature)
