@@ -146,13 +146,17 @@ inline size_t rec64_bytes(int64_t ns)
 }
 // FP32 segment record of the mixed path, REC32A floats per segment (array of
 // structures, read with wavefront-uniform scalar loads or staged in LDS):
-//  0..2 midpoint xm/a rounded to FP32, 3..5 the rounding remainder xm/a - [0..2],
-//  6..8 t, 9 L/a, 11..13 Wo b/a, 14..16 Wo c, and for the source quadrature of
-//  the kernel variant in use (points xm +- hq t with weight Wo each, plus xm
-//  with weight Wc for 3 points): 10 hq, 17 the squared band outside which it
-//  is used, 18 1/Wo, 19 1 + hq^2, 20 2 hq, 21 Wc/Wo, 22..23 zero.  Without a
-//  quadrature Wo = 1.  The field is linear in b (c = b x t), so a rule on the
-//  scaled b and c needs no weight; the closed form unscales them with 1/Wo.
+// the midpoint xm/a rounded to FP32 and its rounding remainder xm/a - [XH],
+// t, and for the source quadrature of the kernel variant in use (points
+// xm +- hq t with weight Wo each, plus xm with weight Wc for 3 points) hq,
+// Wo b/a, Wo c, the squared band outside which it is used, 1 + hq^2, 2 hq and
+// Wc/Wo; then L/a and 1/Wo (read only outside the quadrature) and two zeros.
+// Without a quadrature Wo = 1.  The field is linear in b (c = b x t), so a
+// rule on the scaled b and c needs no weight; the closed form unscales them
+// with 1/Wo.  The quadrature reads the first R32_QUAD_VECS groups of four.
+constexpr int R32_XH = 0, R32_XL = 3, R32_T = 6, R32_HQ = 9, R32_B = 10, R32_C = 13, R32_BAND = 16,
+              R32_RA0 = 17, R32_TW = 18, R32_WC = 19, R32_L = 20, R32_IW = 21;
+constexpr int R32_QUAD_VECS = 5;
 constexpr int REC32A = 24;
 // Mixed kernel variants: 0 = 2-point source quadrature beyond max(30 L,
 // cutoff + L/2), 1 = no quadrature, 2 = 3-point source quadrature beyond

@@ -217,19 +217,19 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_seg_prep(PrepArgs A)
         }
         for (int k = 0; k < 3; ++k) {
             const double xm = x1[k] + 0.5 * L * t[k];
-            q[k] = (float)xm;
-            q[3 + k] = (float)(xm - (double)q[k]);
-            q[6 + k] = (float)t[k];
-            q[11 + k] = (float)(wo * b[k]);
-            q[14 + k] = (float)(wo * c[k]);
+            q[R32_XH + k] = (float)xm;
+            q[R32_XL + k] = (float)(xm - (double)q[k]);
+            q[R32_T + k] = (float)t[k];
+            q[R32_B + k] = (float)(wo * b[k]);
+            q[R32_C + k] = (float)(wo * c[k]);
         }
-        q[9] = (float)L;
-        q[10] = (float)hq;
-        q[17] = (float)(band * band);
-        q[18] = (float)(1.0 / wo);
-        q[19] = (float)(1.0 + hq * hq);
-        q[20] = (float)(2.0 * hq);
-        q[21] = (float)(wc / wo);
+        q[R32_L] = (float)L;
+        q[R32_HQ] = (float)hq;
+        q[R32_BAND] = (float)(band * band);
+        q[R32_IW] = (float)(1.0 / wo);
+        q[R32_RA0] = (float)(1.0 + hq * hq);
+        q[R32_TW] = (float)(2.0 * hq);
+        q[R32_WC] = (float)(wc / wo);
         q[22] = 0.f; q[23] = 0.f;
     }
     if (A.sys) {

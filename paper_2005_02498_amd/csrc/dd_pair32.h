@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "dd_common.h"
+
 namespace dd {
 
 // FP32, far pairs: adds sigma^i b_j / k2 (the regrouped closed form of
@@ -107,8 +109,9 @@ __device__ __forceinline__ void quad_moments_acc_f32(float e0, float e1, float e
                                                      float bj0, float bj1, float bj2, float kr, float nu,
                                                      float &f0, float &f1, float &f2, float &fk)
 {
-    const float t0 = s[6], t1 = s[7], t2 = s[8];
-    const float b0 = s[11], b1 = s[12], b2 = s[13], c0 = s[14], c1 = s[15], c2 = s[16];
+    const float t0 = s[R32_T], t1 = s[R32_T + 1], t2 = s[R32_T + 2];
+    const float b0 = s[R32_B], b1 = s[R32_B + 1], b2 = s[R32_B + 2];
+    const float c0 = s[R32_C], c1 = s[R32_C + 1], c2 = s[R32_C + 2];
     const float h0 = fmaf(-ym, t0, e0), h1 = fmaf(-ym, t1, e1), h2 = fmaf(-ym, t2, e2);
     const float rb0 = fmaf(h1, b2, -h2 * b1), rb1 = fmaf(h2, b0, -h0 * b2), rb2 = fmaf(h0, b1, -h1 * b0);
     const float tb = fmaf(t2, bj2, fmaf(t1, bj1, t0 * bj0));
@@ -136,9 +139,9 @@ __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, floa
                                               float bj0, float bj1, float bj2, float kr, float nu,
                                               float &f0, float &f1, float &f2, float &fk)
 {
-    const float hq = s[10];
-    const float ym = fmaf(e2, s[8], fmaf(e1, s[7], e0 * s[6]));
-    const float base = ee + s[19], tw = s[20] * ym;
+    const float hq = s[R32_HQ];
+    const float ym = fmaf(e2, s[R32_T + 2], fmaf(e1, s[R32_T + 1], e0 * s[R32_T]));
+    const float base = ee + s[R32_RA0], tw = s[R32_TW] * ym;
     const float vA = ym + hq, vB = ym - hq;
     const float iA = __builtin_amdgcn_rsqf(base + tw), iB = __builtin_amdgcn_rsqf(base - tw);
     const float iA2 = iA * iA, iB2 = iB * iB;
@@ -159,9 +162,9 @@ __device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, floa
                                               float bj0, float bj1, float bj2, float kr, float nu,
                                               float &f0, float &f1, float &f2, float &fk)
 {
-    const float hq = s[10], Wc = s[21];
-    const float ym = fmaf(e2, s[8], fmaf(e1, s[7], e0 * s[6]));
-    const float base = ee + s[19], tw = s[20] * ym;
+    const float hq = s[R32_HQ], Wc = s[R32_WC];
+    const float ym = fmaf(e2, s[R32_T + 2], fmaf(e1, s[R32_T + 1], e0 * s[R32_T]));
+    const float base = ee + s[R32_RA0], tw = s[R32_TW] * ym;
     const float vA = ym + hq, vB = ym - hq;
     const float iA = __builtin_amdgcn_rsqf(base + tw), iB = __builtin_amdgcn_rsqf(base - tw);
     const float iC = __builtin_amdgcn_rsqf(ee + 1.0f);

@@ -86,9 +86,10 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
             if (QN) {
                 // from LDS (broadcast reads): the FP32 quadrature then runs on
                 // vector-register operands, which issue faster than FP32
-                // instructions with a scalar operand
+                // instructions with a scalar operand; the fields only the
+                // other pairs use are read below, for those
 #pragma unroll
-                for (int f = 0; f < REC32A / 4; ++f) {
+                for (int f = 0; f < R32_QUAD_VECS; ++f) {
                     const f32x4 v = shr[k][f];
                     r[4 * f] = v[0];
                     r[4 * f + 1] = v[1];
@@ -106,12 +107,12 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
             }
             // offset from the source midpoint, from the split FP32 positions:
             // accurate to the rounding of its own size
-            const float e0 = (xh0 - r[0]) + (xl0 - r[3]);
-            const float e1 = (xh1 - r[1]) + (xl1 - r[4]);
-            const float e2 = (xh2 - r[2]) + (xl2 - r[5]);
+            const float e0 = (xh0 - r[R32_XH]) + (xl0 - r[R32_XL]);
+            const float e1 = (xh1 - r[R32_XH + 1]) + (xl1 - r[R32_XL + 1]);
+            const float e2 = (xh2 - r[R32_XH + 2]) + (xl2 - r[R32_XL + 2]);
             if (QN) {
                 const float ee = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
-                if (__all(ee >= r[17])) {
+                if (__all(ee >= r[R32_BAND])) {
                     ++n_quad_src;
                     if (QN == 2)
                         quad2_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2, fk);
@@ -120,11 +121,21 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                     continue;
                 }
             }
+            if (QN) {
+#pragma unroll
+                for (int f = R32_QUAD_VECS; f < REC32A / 4; ++f) {
+                    const f32x4 v = shr[k][f];
+                    r[4 * f] = v[0];
+                    r[4 * f + 1] = v[1];
+                    r[4 * f + 2] = v[2];
+                    r[4 * f + 3] = v[3];
+                }
+            }
             // axial coordinate from the first node and perpendicular part
-            const float Ls = r[9];
-            const float ym = fmaf(e2, r[8], fmaf(e1, r[7], e0 * r[6]));
+            const float Ls = r[R32_L];
+            const float ym = fmaf(e2, r[R32_T + 2], fmaf(e1, r[R32_T + 1], e0 * r[R32_T]));
             const float y = fmaf(0.5f, Ls, ym);
-            const float h0 = fmaf(-ym, r[6], e0), h1 = fmaf(-ym, r[7], e1), h2 = fmaf(-ym, r[8], e2);
+            const float h0 = fmaf(-ym, r[R32_T], e0), h1 = fmaf(-ym, r[R32_T + 1], e1), h2 = fmaf(-ym, r[R32_T + 2], e2);
             const float hh = fmaf(h2, h2, fmaf(h1, h1, h0 * h0));
             const float ya = y - fminf(fmaxf(y, 0.f), Ls);
             if (hh + ya * ya < cut2) {
@@ -134,8 +145,9 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                 }
             } else {
                 // the record's b and c carry the quadrature weight (1 without a quadrature)
-                pair_acc_f32(y, h0, h1, h2, hh, fb0, fb1, fb2, r[6], r[7], r[8], Ls, r[11], r[12], r[13],
-                             r[14], r[15], r[16], QN ? r[18] : 1.0f, fkr, fnu, f0, f1, f2, fk);
+                pair_acc_f32(y, h0, h1, h2, hh, fb0, fb1, fb2, r[R32_T], r[R32_T + 1], r[R32_T + 2], Ls, r[R32_B],
+                             r[R32_B + 1], r[R32_B + 2], r[R32_C], r[R32_C + 1], r[R32_C + 2], QN ? r[R32_IW] : 1.0f,
+                             fkr, fnu, f0, f1, f2, fk);
             }
         }
         a0 += (double)fmaf(fk, fb0, f0);   // the b_j terms of the stage at once
