@@ -311,7 +311,7 @@ def main():
         surrogate_study(args)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the force path shards by loops across GPUs by design, but no multi-GPU code "
               "path exists)", file=sys.stderr)
         sys.exit(2)
