@@ -370,7 +370,8 @@ def test_P8_two_and_three_normals():
 def test_P8_free_segment_rate_matches_paper_magnitude():
     """One straight segment, applied stress only: |v| = tau |b| / B and the
     distortion rate |b (x) (l x V)| / A with A = |b|^2 is v/|b|: with the
-    paper's b and B at 10 MPa this is 1.59e11 /s, "around 1e11"."""
+    paper's b and B at 10 MPa this is 1.59e11 /s, the order of magnitude
+    (1e11 /s) the paper gives."""
     g = json.load(open(os.path.join(GOLD, "free_segment_rate.json")))
     tau, bm, B = g["applied_stress_pa"], g["b_m"], g["drag_pa_s"]
     n, m = W.PLANE_NORMALS[0], W.SLIP_DIRS[0, 2]
