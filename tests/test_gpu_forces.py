@@ -282,6 +282,27 @@ def test_glide_step_multiple_normals():
         np.testing.assert_allclose(xt.cpu().numpy(), xo, rtol=0, atol=1e-15)
 
 
+def test_step_with_exact_band_equals_forces_then_glide():
+    """With the exact band on, dd_step's forces are dd_nodal_forces' bit for bit."""
+    inst = W.burst_instance(1_000_006)
+    d1, d2 = dev(inst), dev(inst)
+    F1, F2 = torch.empty_like(d1["x"]), torch.empty_like(d1["x"])
+    dd.dd_set_exact_band(2.0)
+    try:
+        dd.dd_nodal_forces(d1["x"], d1["seg_nodes"], d1["burgers"], d1["normal"], inst.sigma_app, MAT, 2,
+                           dd.DD_FP64, 20.0, force_out=F1)
+        V1 = dd.dd_glide_step(d1["x"], F1, d1["seg_nodes"], d1["normal"], d1["pinned"], MAT, W.DT)
+        V2 = torch.empty_like(d2["x"])
+        dd.dd_step(d2["x"], d2["seg_nodes"], d2["burgers"], d2["normal"], d2["pinned"], inst.sigma_app, MAT, W.DT,
+                   2, dd.DD_FP64, 20.0, force_out=F2, vel_out=V2)
+        torch.cuda.synchronize()
+    finally:
+        dd.dd_set_exact_band(0.0)
+    assert torch.equal(F1, F2)
+    v1 = V1.cpu().numpy()
+    np.testing.assert_allclose(V2.cpu().numpy(), v1, rtol=0, atol=1e-13 * np.abs(v1).max())
+
+
 @pytest.mark.parametrize("prec", [dd.DD_FP64, dd.DD_MIXED])
 def test_step_equals_forces_then_glide(prec):
     """dd_step = dd_nodal_forces then dd_glide_step.  First step: the same

@@ -63,9 +63,12 @@ def test_params_roundtrip():
     np.testing.assert_array_equal(p, flat(*params[1]))
 
 
-def test_forward_parity():
+@pytest.mark.parametrize("n", [1, 255, 257, 1000])
+def test_forward_parity(n):
+    """Against the bf16-emulating oracle; n spans one partial, one full plus one
+    row and several 256-row workgroups with a ragged tail."""
     mdl, params, sc = _model()
-    feat = np.random.default_rng(1).normal(size=(1000, 36)).astype(np.float32)
+    feat = np.random.default_rng(1).normal(size=(n, 36)).astype(np.float32)
     r, s, f = dd.dd_surrogate_rates(mdl, torch.tensor(feat, device=DEV), 0.05)
     torch.cuda.synchronize()
     ro, so, fo = M.ensemble_predict(params, feat.astype(np.float64), sc[0], sc[1], sc[2], sc[3],
