@@ -86,8 +86,6 @@ struct Workspace {
     unsigned *flags_dev = nullptr;   // one word
     unsigned *flags_host = nullptr;  // pinned mirror
     hipStream_t capture_stream = nullptr;
-    hipStream_t side_stream = nullptr;           // exact band, overlapping the pair kernel
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int64_t block_fac_n = -1;                    // size of the tridiagonal factors in WS_BLOCK_FAC
     unsigned long long *near_count = nullptr;   // device counter (mixed kernel)
     bool capturing = false;

@@ -1062,9 +1062,6 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
         N.pair_s = N.pair_t + N.pair_cap;
         if ((rc = ensure(ws, WS_NEAR_CORR, sizeof(double) * 6 * N.pair_cap, &p))) return rc;
         N.corr = (double *)p;
-        if (!ws->side_stream) DD_HIP(hipStreamCreateWithFlags(&ws->side_stream, hipStreamNonBlocking));
-        if (!ws->ev_fork) DD_HIP(hipEventCreateWithFlags(&ws->ev_fork, hipEventDisableTiming));
-        if (!ws->ev_join) DD_HIP(hipEventCreateWithFlags(&ws->ev_join, hipEventDisableTiming));
     }
     return DD_OK;
 }
@@ -1106,18 +1103,16 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, PREP_BLOCK, INT32_MAX)), dim3(PREP_BLOCK), 0, st, A);
         if (C.near_on) {
-            // the near-pair work needs only the records: it runs on a side
-            // stream, alongside the pair kernel, and joins before the epilogue
+            // the near-pair work needs only the records; it runs before the
+            // pair kernel on the same stream (alongside it, it slowed the pair
+            // kernel by more than its own duration)
             NearArgs N = C.near;
             N.x = x;
             N.seg_nodes = seg_nodes;
             N.seg_inst = C.L.seg_inst;
             N.seg_off = C.L.seg_off;
             N.node_off = C.L.node_off;
-            (void)hipEventRecord(ws->ev_fork, st);
-            (void)hipStreamWaitEvent(ws->side_stream, ws->ev_fork, 0);
-            launch_near(N, ws->side_stream);
-            (void)hipEventRecord(ws->ev_join, ws->side_stream);
+            launch_near(N, st);
         }
         if (C.n_items > 0) {
             timing_begin(st, ws->capturing);
@@ -1128,7 +1123,6 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
                 launch_pair64(C.items, C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial, C.n_items, st);
             timing_end(st, ws->capturing);
         }
-        if (C.near_on) (void)hipStreamWaitEvent(st, ws->ev_join, 0);
         hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
                            C.tiles, C.partial, C.rec64, C.g, sig_dev, sig_val, C.inv_mu, C.fscale,
                            C.segF, C.near_on ? (const int32_t *)C.near.ptr : nullptr,

@@ -216,9 +216,6 @@ int dd_shutdown(void)
         if (w->flags_dev) (void)hipFree(w->flags_dev);
         if (w->flags_host) (void)hipHostFree(w->flags_host);
         if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
-        if (w->side_stream) (void)hipStreamDestroy(w->side_stream);
-        if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
-        if (w->ev_join) (void)hipEventDestroy(w->ev_join);
         delete w;
         w = nullptr;
     }
