@@ -532,7 +532,7 @@ def main():
                 n_near += int((dd2 < c2 * (K[None, :, 3] + K[j0:j0 + 256, None, 3])).sum()) - min(256, N - j0)
             dd.dd_set_exact_band(eta)
             try:
-                s_b, _, _ = run(prec, 2, max(5, args.steps // 2), 2)
+                s_b, _, _ = run(prec, 2, args.steps, max(3, args.warmup))
             finally:
                 dd.dd_set_exact_band(0.0)
             base = step_s if prec == dd.DD_FP64 else extras["mixed_q2"]["ms_per_step"] / 1e3
