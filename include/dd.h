@@ -78,12 +78,15 @@ typedef struct { double mu, nu, a, B; } dd_material;
 
 /* DD_FP64: every pair in float64.
  * DD_MIXED: pairs whose minimum distance from the target Gauss point to the
- * source segment is below near_cutoff_a * a are evaluated in float64, all
- * others in float32 with float32 accumulation over a source tile: the closed
- * form in a cancellation-free arrangement, or, when the target is at least 30
- * source lengths from the source midpoint, 2-point Gauss-Legendre quadrature
- * of the integrand along the source (error below 2e-7 relative there).  Tile
- * sums, nodal sums and the mobility step stay float64. */
+ * source segment is below near_cutoff_a * a, and nearly collinear pairs (the
+ * target inside a cone of half-angle about 1/16 around the source's axis,
+ * seen from its midpoint: ym^2 > 256 (rho^2 + a^2) for its axial offset ym
+ * and perpendicular distance rho), are evaluated in float64; all others in
+ * float32 with float32 accumulation over a source tile: the closed form in a
+ * cancellation-free arrangement, or, when the target is at least 30 source
+ * lengths from the source midpoint, 2-point Gauss-Legendre quadrature of the
+ * integrand along the source (error below 2e-7 relative there).  Tile sums,
+ * nodal sums and the mobility step stay float64. */
 typedef enum { DD_FP64 = 0, DD_MIXED = 1 } dd_precision;
 
 /* Message of the last error on the calling thread ("" if none). */
@@ -200,8 +203,9 @@ int dd_vector_peak(int kind, int reps, double *tflops, void *stream);
  * Arguments: x [3][n_nodes], seg_nodes [2][n_segs], burgers [3][n_segs];
  *  normal [3][n_segs] is validated (unit length) but unused by the force;
  *  sigma_app host [6]; m host; 1 <= n_gauss <= DD_MAX_GAUSS; precision a
- *  dd_precision; near_cutoff_a > 0 (in units of a, mixed only; the
- *  workload value is 20); force_out [3][n_nodes] (overwritten).
+ *  dd_precision; near_cutoff_a >= 1 (in units of a, mixed only, checked
+ *  only for DD_MIXED; the workload value is 20); force_out [3][n_nodes]
+ *  (overwritten).
  * Errors: DD_EINVAL for null pointers, counts < 0, bad material, n_gauss out
  *  of range, a node index outside [0, n_nodes), a zero-length segment or a
  *  normal of length differing from 1 by more than 1e-6 (validation on);

@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
     global _lib
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wno-unknown-pragmas", "-fPIC", "-shared",
                                _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
         _lib = None
@@ -76,6 +76,8 @@ def _setup(L):
     L.ddo_pair_exact.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, C.c_double, C.c_double,
                                  C.c_double, _dp, _dp]
     L.ddo_set_exact_band.argtypes = [C.c_double]
+    L.ddo_set_source_quadrature.argtypes = [C.c_int, C.c_int]
+    L.ddo_threads.argtypes = []
     L.ddo_glide_step.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _ip, _dp, _up,
                                  C.POINTER(Material), C.c_double, _dp]
     L.ddo_fcc_system.argtypes = [C.c_int, _dp, _dp]
@@ -176,6 +178,23 @@ class exact_band:
 
     def __exit__(self, *exc):
         set_exact_band(0.0)
+
+
+class source_quadrature:
+    """Context manager: inside, the force routines take each source's field by
+    n-point Gauss-Legendre quadrature on `panels` equal panels of the source
+    instead of the closed form (the slow reference where the closed form's
+    endpoint differences lose digits); the closed form again on exit."""
+
+    def __init__(self, n=64, panels=64):
+        self.n, self.panels = n, panels
+
+    def __enter__(self):
+        _check(lib().ddo_set_source_quadrature(self.n, self.panels), "set_source_quadrature")
+        return self
+
+    def __exit__(self, *exc):
+        lib().ddo_set_source_quadrature(0, 0)
 
 
 def fcc_system(alpha: int):

@@ -42,6 +42,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct { double mu, nu, a, B; } ddo_material;
 
@@ -399,6 +402,97 @@ static int near_pair(const double *xa, const double *xb, const double *y1, const
 /*   F[n1(j)] += L_j w_q (1 - s_q) f_jq,  F[n2(j)] += L_j w_q s_q f_jq       */
 /* include_self = 1 also adds the segment's own field (a variant).          */
 /* ------------------------------------------------------------------------- */
+/* Source field used by the force routines: the closed form (default), or,  */
+/* after ddo_set_source_quadrature(n, panels) with n > 0, n-point            */
+/* Gauss-Legendre quadrature of the integrand on `panels` equal panels of    */
+/* the source (ddo_segment_stress_quad).  The quadrature is the slow         */
+/* reference where the closed form's endpoint differences lose digits (a    */
+/* screw source seen from far along its own axis).                          */
+static int g_srcq_n = 0, g_srcq_panels = 0;
+
+int ddo_set_source_quadrature(int n, int panels)
+{
+    if (n < 0 || n > DDO_MAX_Q || (n > 0 && panels < 1)) return -1;
+    g_srcq_n = n;
+    g_srcq_panels = panels;
+    return 0;
+}
+
+static void source_stress(const double xq[3], const double y1[3], const double y2[3], const double bi[3],
+                          const ddo_material *m, double sg[9])
+{
+    if (g_srcq_n > 0)
+        ddo_segment_stress_quad(xq, y1, y2, bi, m->mu, m->nu, m->a, g_srcq_n, g_srcq_panels, sg);
+    else
+        ddo_segment_stress(xq, y1, y2, bi, m->mu, m->nu, m->a, sg);
+}
+
+/* What target segment j sends to its two nodes: out[0..2] to node 1 and     */
+/* out[3..5] to node 2, Gauss points in order, each point's contributions    */
+/* added in the order (w1 f to node 1, w2 f to node 2); then the exact band. */
+static int target_end_forces(int64_t n_nodes, const double *x, int64_t n_segs,
+                             const int32_t *seg_nodes, const double *burgers,
+                             double Sapp[3][3], const ddo_material *m, int n_gauss,
+                             const double *s, const double *w, int include_self, int64_t j,
+                             double *out, double near_out[6])
+{
+    const double *X = x, *Y = x + n_nodes, *Z = x + 2*n_nodes;
+    const int32_t *N1 = seg_nodes, *N2 = seg_nodes + n_segs;
+    int32_t a1 = N1[j], a2 = N2[j];
+    double xa[3] = { X[a1], Y[a1], Z[a1] }, xb[3] = { X[a2], Y[a2], Z[a2] };
+    double d[3] = { xb[0]-xa[0], xb[1]-xa[1], xb[2]-xa[2] };
+    double L = sqrt(dot3(d, d));
+    if (!(L > 0.0)) return -1;
+    double t[3] = { d[0]/L, d[1]/L, d[2]/L };
+    double bj[3] = { burgers[j], burgers[n_segs + j], burgers[2*n_segs + j] };
+    for (int g = 0; g < n_gauss; ++g) {
+        double xq[3] = { xa[0] + s[g]*d[0], xa[1] + s[g]*d[1], xa[2] + s[g]*d[2] };
+        double S[3][3];
+        memcpy(S, Sapp, sizeof S);
+        for (int64_t i = 0; i < n_segs; ++i) {
+            if (i == j && !include_self) continue;
+            int32_t c1 = N1[i], c2 = N2[i];
+            double y1[3] = { X[c1], Y[c1], Z[c1] }, y2[3] = { X[c2], Y[c2], Z[c2] };
+            if (near_pair(xa, xb, y1, y2)) continue;
+            double bi[3] = { burgers[i], burgers[n_segs + i], burgers[2*n_segs + i] };
+            double sg[9];
+            source_stress(xq, y1, y2, bi, m, sg);
+            for (int r = 0; r < 3; ++r)
+                for (int cc = 0; cc < 3; ++cc) S[r][cc] += sg[3*r + cc];
+        }
+        double sb[3], f[3];
+        for (int r = 0; r < 3; ++r) sb[r] = S[r][0]*bj[0] + S[r][1]*bj[1] + S[r][2]*bj[2];
+        cross3(sb, t, f);
+        double w1 = L * w[g] * (1.0 - s[g]), w2 = L * w[g] * s[g];
+        for (int r = 0; r < 3; ++r) {
+            out[6*g + r] = w1 * f[r];
+            out[6*g + 3 + r] = w2 * f[r];
+        }
+    }
+    /* near pairs: the exact target integral, summed over sources in order */
+    for (int k = 0; k < 6; ++k) near_out[k] = 0.0;
+    for (int64_t i = 0; i < n_segs && g_exact_c2 > 0.0; ++i) {
+        if (i == j && !include_self) continue;
+        int32_t c1 = N1[i], c2 = N2[i];
+        double y1[3] = { X[c1], Y[c1], Z[c1] }, y2[3] = { X[c2], Y[c2], Z[c2] };
+        if (!near_pair(xa, xb, y1, y2)) continue;
+        double bi[3] = { burgers[i], burgers[n_segs + i], burgers[2*n_segs + i] };
+        double F1[3], F2[3];
+        if (ddo_pair_exact(xa, xb, bj, y1, y2, bi, m->mu, m->nu, m->a, F1, F2)) return -1;
+        for (int r = 0; r < 3; ++r) {
+            near_out[r] += F1[r];
+            near_out[3 + r] += F2[r];
+        }
+    }
+    return 0;
+}
+
+/* Targets are independent: each computes its own end forces (in parallel   */
+/* when this file is compiled with OpenMP, for the CPU baseline's            */
+/* multi-core leg; the plain build ignores the pragma), then they are added  */
+/* to the nodes in target order, which gives the same sums, bit for bit, as  */
+/* one thread adding each contribution as it is computed.  Near-pair         */
+/* contributions are added after the target's Gauss points.                  */
 static int ddo_forces_impl(int64_t n_nodes, const double *x, int64_t n_segs,
                            const int32_t *seg_nodes, const double *burgers,
                            const double sigma_app[6], const ddo_material *m,
@@ -407,60 +501,55 @@ static int ddo_forces_impl(int64_t n_nodes, const double *x, int64_t n_segs,
 {
     double s[DDO_MAX_Q], w[DDO_MAX_Q];
     if (ddo_gauss_legendre(n_gauss, s, w)) return -1;
-    const double *X = x, *Y = x + n_nodes, *Z = x + 2*n_nodes;
     const int32_t *N1 = seg_nodes, *N2 = seg_nodes + n_segs;
     for (int64_t k = 0; k < 3*n_nodes; ++k) force_out[k] = 0.0;
     double Sapp[3][3];
     voigt_to_full(sigma_app, Sapp);
-
-    for (int64_t j = tgt_begin; j < tgt_end; ++j) {
-        int32_t a1 = N1[j], a2 = N2[j];
-        double xa[3] = { X[a1], Y[a1], Z[a1] }, xb[3] = { X[a2], Y[a2], Z[a2] };
-        double d[3] = { xb[0]-xa[0], xb[1]-xa[1], xb[2]-xa[2] };
-        double L = sqrt(dot3(d, d));
-        if (!(L > 0.0)) return -1;
-        double t[3] = { d[0]/L, d[1]/L, d[2]/L };
-        double bj[3] = { burgers[j], burgers[n_segs + j], burgers[2*n_segs + j] };
-        for (int g = 0; g < n_gauss; ++g) {
-            double xq[3] = { xa[0] + s[g]*d[0], xa[1] + s[g]*d[1], xa[2] + s[g]*d[2] };
-            double S[3][3];
-            memcpy(S, Sapp, sizeof S);
-            for (int64_t i = 0; i < n_segs; ++i) {
-                if (i == j && !include_self) continue;
-                int32_t c1 = N1[i], c2 = N2[i];
-                double y1[3] = { X[c1], Y[c1], Z[c1] }, y2[3] = { X[c2], Y[c2], Z[c2] };
-                if (near_pair(xa, xb, y1, y2)) continue;
-                double bi[3] = { burgers[i], burgers[n_segs + i], burgers[2*n_segs + i] };
-                double sg[9];
-                ddo_segment_stress(xq, y1, y2, bi, m->mu, m->nu, m->a, sg);
-                for (int r = 0; r < 3; ++r)
-                    for (int cc = 0; cc < 3; ++cc) S[r][cc] += sg[3*r + cc];
-            }
-            double sb[3], f[3];
-            for (int r = 0; r < 3; ++r) sb[r] = S[r][0]*bj[0] + S[r][1]*bj[1] + S[r][2]*bj[2];
-            cross3(sb, t, f);
-            double w1 = L * w[g] * (1.0 - s[g]), w2 = L * w[g] * s[g];
-            for (int r = 0; r < 3; ++r) {
-                force_out[r*n_nodes + a1] += w1 * f[r];
-                force_out[r*n_nodes + a2] += w2 * f[r];
-            }
-        }
-        /* near pairs: the exact target integral */
-        for (int64_t i = 0; i < n_segs && g_exact_c2 > 0.0; ++i) {
-            if (i == j && !include_self) continue;
-            int32_t c1 = N1[i], c2 = N2[i];
-            double y1[3] = { X[c1], Y[c1], Z[c1] }, y2[3] = { X[c2], Y[c2], Z[c2] };
-            if (!near_pair(xa, xb, y1, y2)) continue;
-            double bi[3] = { burgers[i], burgers[n_segs + i], burgers[2*n_segs + i] };
-            double F1[3], F2[3];
-            if (ddo_pair_exact(xa, xb, bj, y1, y2, bi, m->mu, m->nu, m->a, F1, F2)) return -1;
-            for (int r = 0; r < 3; ++r) {
-                force_out[r*n_nodes + a1] += F1[r];
-                force_out[r*n_nodes + a2] += F2[r];
-            }
-        }
+    int64_t nt = tgt_end - tgt_begin;
+    if (nt <= 0) return 0;
+    double *ends = malloc(sizeof(double) * 6 * (size_t)n_gauss * (size_t)nt);
+    double (*nears)[6] = malloc(sizeof(*nears) * (size_t)nt);
+    if (!ends || !nears) {
+        free(ends);
+        free(nears);
+        return -1;
     }
-    return 0;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(| : bad)
+    for (int64_t j = tgt_begin; j < tgt_end; ++j)
+        bad |= target_end_forces(n_nodes, x, n_segs, seg_nodes, burgers, Sapp, m, n_gauss, s, w,
+                                 include_self, j, ends + 6 * n_gauss * (j - tgt_begin), nears[j - tgt_begin]) != 0;
+    for (int64_t j = tgt_begin; j < tgt_end && !bad; ++j) {
+        int32_t a1 = N1[j], a2 = N2[j];
+        const double *e = ends + 6 * n_gauss * (j - tgt_begin);
+        for (int g = 0; g < n_gauss; ++g)
+            for (int r = 0; r < 3; ++r) {
+                force_out[r*n_nodes + a1] += e[6*g + r];
+                force_out[r*n_nodes + a2] += e[6*g + 3 + r];
+            }
+        if (g_exact_c2 > 0.0)
+            for (int r = 0; r < 3; ++r) {
+                force_out[r*n_nodes + a1] += nears[j - tgt_begin][r];
+                force_out[r*n_nodes + a2] += nears[j - tgt_begin][3 + r];
+            }
+    }
+    free(ends);
+    free(nears);
+    return bad ? -1 : 0;
+}
+
+/* Number of threads the force routines use (1 for the plain build). */
+int ddo_threads(void)
+{
+#ifdef _OPENMP
+    int n = 1;
+#pragma omp parallel
+#pragma omp master
+    n = omp_get_num_threads();
+    return n;
+#else
+    return 1;
+#endif
 }
 
 static int check_topology(int64_t n_nodes, int64_t n_segs, const int32_t *seg_nodes)

@@ -1306,7 +1306,9 @@ int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, d
     if (n_segs > 0 && n_nodes == 0) return set_error(DD_EINVAL, "segments without nodes");
     if (n_gauss < 1 || n_gauss > DD_MAX_GAUSS) return set_error(DD_EINVAL, "n_gauss must be in 1..16");
     if (precision != DD_FP64 && precision != DD_MIXED) return set_error(DD_EINVAL, "unknown precision");
-    if (precision == DD_MIXED && !(near_cut > 0.0)) return set_error(DD_EINVAL, "near_cutoff_a must be > 0");
+    // at least one core width: a segment's own Gauss points then always take the
+    // FP64 branch of the mixed kernel, which skips the self pair
+    if (precision == DD_MIXED && !(near_cut >= 1.0)) return set_error(DD_EINVAL, "near_cutoff_a must be >= 1");
     return DD_OK;
 }
 

@@ -9,10 +9,22 @@
 
 namespace dd {
 
+// Pairs whose target lies nearly on the source's axis, ym^2 > K^2 (rho^2 + 1)
+// with ym the axial offset from the source midpoint and rho the perpendicular
+// part (units of a), K = 16, leave the FP32 branches for the FP64 closed
+// form.  Outside that cone both FP32 branches stay within about 3e-6 of the
+// pair's own contribution (a CPU emulation of these routines on screw and
+// mixed sources at 20 to 5e4 a); inside it the FP32 rho of a screw source can
+// be off by more than its own size.
+constexpr float COLLINEAR_K2 = 256.0f;
+
 // FP32, far pairs: adds sigma^i b_j / k2 (the regrouped closed form of
 // dd_pair64.h, kr = (1 - nu)/2) to (f0, f1, f2) + fk b_j (the b_j term's
 // scalar goes to fk; the caller adds fk b_j once).  y, rho and hh = |rho|^2 are
-// formed by the caller (y and rho in FP64, rounded once).  The endpoint
+// formed by the caller in FP32 from the offset to the source midpoint, so rho
+// carries an absolute error of order |y - L/2| 6e-8; the caller keeps nearly
+// collinear pairs (COLLINEAR_K2) away from this routine, and for the others
+// that error is small against rho and against the field.  The endpoint
 // differences are rearranged so that no two nearly equal numbers are
 // subtracted when the target lies far away or on the extension of the segment
 // (u1 = -y, u2 = L - y, r = 1/Ra, s = u r):
@@ -132,15 +144,14 @@ __device__ __forceinline__ void quad_moments_acc_f32(float e0, float e1, float e
     f2 = fmaf(Ch, h2, fmaf(Ct, t2, fmaf(Cc, c2, fmaf(Cr, rb2, f2))));
 }
 
-// e = target - source midpoint, ee = |e|^2; s = the source's FP32 record (see
+// e = target - source midpoint, ee = |e|^2, ym = e.t; s = the source's FP32 record (see
 // REC32A), whose b and c carry the weight Wo; adds K b_j / k2 to (f0, f1, f2)
 // + fk b_j.  2-point rule: points at v = ym -+ hq, weight Wo each (in b, c).
-__device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, float ee, const float *s,
+__device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, float ee, float ym, const float *s,
                                               float bj0, float bj1, float bj2, float kr, float nu,
                                               float &f0, float &f1, float &f2, float &fk)
 {
     const float hq = s[R32_HQ];
-    const float ym = fmaf(e2, s[R32_T + 2], fmaf(e1, s[R32_T + 1], e0 * s[R32_T]));
     const float base = ee + s[R32_RA0], tw = s[R32_TW] * ym;
     const float vA = ym + hq, vB = ym - hq;
     const float iA = __builtin_amdgcn_rsqf(base + tw), iB = __builtin_amdgcn_rsqf(base - tw);
@@ -158,12 +169,11 @@ __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, floa
 // with weight Wc, relative weight Wc/Wo = 8/5 (Gauss-Legendre, hq = (L/2)
 // sqrt(3/5), Wo = 5L/18, Wc = 8L/18).
 // Its error is below 2e-7 relative beyond 6 source lengths from the midpoint.
-__device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, float ee, const float *s,
+__device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, float ee, float ym, const float *s,
                                               float bj0, float bj1, float bj2, float kr, float nu,
                                               float &f0, float &f1, float &f2, float &fk)
 {
     const float hq = s[R32_HQ], Wc = s[R32_WC];
-    const float ym = fmaf(e2, s[R32_T + 2], fmaf(e1, s[R32_T + 1], e0 * s[R32_T]));
     const float base = ee + s[R32_RA0], tw = s[R32_TW] * ym;
     const float vA = ym + hq, vB = ym - hq;
     const float iA = __builtin_amdgcn_rsqf(base + tw), iB = __builtin_amdgcn_rsqf(base - tw);

@@ -22,8 +22,14 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // FP32 quadrature.  With QN = 0 the FP32 records are read with scalar loads.
 // Other pairs get their axial and perpendicular parts in FP32 from the same
 // midpoint offset: those closer than the cutoff (minimum distance from the
-// Gauss point to the closed source segment) are evaluated in FP64 from the
-// FP64 record, the rest by the cancellation-free FP32 closed form.  FP32 contributions are summed in FP32 over TILE sources
+// Gauss point to the closed source segment), and nearly collinear ones (the
+// target within an angle of about 1/16 of the source's axis, seen from its
+// midpoint), are evaluated in FP64 from the FP64 record, the rest by the
+// cancellation-free FP32 closed form.  Nearly collinear pairs never take the
+// quadrature either: in FP32 their perpendicular part rho carries an absolute
+// error of order |ym| 6e-8, which is large against rho itself there, and for a
+// screw source (b along t) the field on its axis consists of terms linear in
+// rho alone.  FP32 contributions are summed in FP32 over TILE sources
 // at a time, then added to FP64 sums; all sums are in units of k2 and scaled
 // once at the end.
 template <int QN>
@@ -110,14 +116,20 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
             const float e0 = (xh0 - r[R32_XH]) + (xl0 - r[R32_XL]);
             const float e1 = (xh1 - r[R32_XH + 1]) + (xl1 - r[R32_XL + 1]);
             const float e2 = (xh2 - r[R32_XH + 2]) + (xl2 - r[R32_XL + 2]);
+            // axial coordinate from the midpoint
+            const float ym = fmaf(e2, r[R32_T + 2], fmaf(e1, r[R32_T + 1], e0 * r[R32_T]));
+            const float ym2 = ym * ym;
             if (QN) {
                 const float ee = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
-                if (__all(ee >= r[R32_BAND])) {
+                // outside the band and not nearly collinear (ym^2 > K^2 (rho^2 + 1)
+                // with rho^2 = ee - ym^2, see COLLINEAR_K2)
+                const bool quad = ee >= r[R32_BAND] && ym2 * (1.0f + COLLINEAR_K2) <= fmaf(COLLINEAR_K2, ee, COLLINEAR_K2);
+                if (__all(quad)) {
                     ++n_quad_src;
                     if (QN == 2)
-                        quad2_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2, fk);
+                        quad2_acc_f32(e0, e1, e2, ee, ym, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2, fk);
                     else
-                        quad3_acc_f32(e0, e1, e2, ee, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2, fk);
+                        quad3_acc_f32(e0, e1, e2, ee, ym, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2, fk);
                     continue;
                 }
             }
@@ -133,12 +145,13 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
             }
             // axial coordinate from the first node and perpendicular part
             const float Ls = r[R32_L];
-            const float ym = fmaf(e2, r[R32_T + 2], fmaf(e1, r[R32_T + 1], e0 * r[R32_T]));
             const float y = fmaf(0.5f, Ls, ym);
             const float h0 = fmaf(-ym, r[R32_T], e0), h1 = fmaf(-ym, r[R32_T + 1], e1), h2 = fmaf(-ym, r[R32_T + 2], e2);
             const float hh = fmaf(h2, h2, fmaf(h1, h1, h0 * h0));
             const float ya = y - fminf(fmaxf(y, 0.f), Ls);
-            if (hh + ya * ya < cut2) {
+            // FP64: near pairs, and nearly collinear ones (rho carries an absolute
+            // error of order |ym| eps32 in FP32)
+            if (hh + ya * ya < cut2 || ym2 > fmaf(COLLINEAR_K2, hh, COLLINEAR_K2)) {
                 if (m != j) {
                     n_near += valid ? 1u : 0u;
                     pair_acc_isolated_f64(xq0, xq1, xq2, bj0, bj1, bj2, ra + m * RECA, kr, nu, a0, a1, a2);

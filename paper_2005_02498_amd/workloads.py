@@ -242,3 +242,101 @@ def burst_instance_state(state_seed, micro_seed, box=2000.0, kmin=8, kmax=128) -
     pinned[n_mob * SEGS_PER_LOOP:] = 1
     return Instance(x, seg, bur, nor, pinned, sig, float(box) ** 3,
                     dict(meta, seed=(state_seed, micro_seed), box=box, k=k, f=f, n_mobile_loops=n_mob))
+
+
+# --- edge-case geometries ------------------------------------------------------
+
+def _unit(v):
+    v = np.asarray(v, float)
+    return v / np.linalg.norm(v)
+
+
+def collinear_chains(seed=5, n_targets=24, screw=True) -> Instance:
+    """Nearly collinear far pairs: a straight open chain of 16 segments of
+    50 b along a <110> line starting at an offset point (screw, b along the
+    line, when ``screw``, else a random unit b), and ``n_targets`` short free
+    segments (5-20 b, random unit Burgers vectors) placed on the line's
+    extension at axial distances log-uniform in [100, 10,000] b beyond either
+    end of the chain, 0-2 b off the line, tilted from it by at most 0.01 rad.
+    No applied stress: every force comes from nearly collinear pairs."""
+    rng = np.random.default_rng(seed)
+    u = _unit([1.0, 1.0, 0.0])
+    p = _unit(np.cross(u, [0.0, 0.0, 1.0]))         # two directions normal to the line
+    q = np.cross(u, p)
+    o = np.array([1234.5, -567.75, 910.125])
+    n_chain = 16
+    xs = [o + 50.0 * k * u for k in range(n_chain + 1)]
+    seg = [(k, k + 1) for k in range(n_chain)]
+    bc = u if screw else _unit(rng.normal(size=3))
+    bur = [bc] * n_chain
+    nor = [q] * n_chain
+    length = 50.0 * n_chain
+    for _ in range(n_targets):
+        d = 10.0 ** rng.uniform(2.0, 4.0)
+        s = length + d if rng.random() < 0.5 else -d
+        off = rng.uniform(0.0, 2.0)
+        ang = rng.uniform(0.0, 2.0 * math.pi)
+        c = o + s * u + off * (math.cos(ang) * p + math.sin(ang) * q)
+        tilt = rng.uniform(0.0, 0.01)
+        ta = rng.uniform(0.0, 2.0 * math.pi)
+        t = _unit(u + tilt * (math.cos(ta) * p + math.sin(ta) * q))
+        L = rng.uniform(5.0, 20.0)
+        n0 = len(xs)
+        xs += [c - 0.5 * L * t, c + 0.5 * L * t]
+        seg.append((n0, n0 + 1))
+        bur.append(_unit(rng.normal(size=3)))
+        nn = np.cross(t, p)
+        nor.append(_unit(nn))
+    x = np.ascontiguousarray(np.array(xs).T)
+    return Instance(x, np.ascontiguousarray(np.array(seg, np.int32).T),
+                    np.ascontiguousarray(np.array(bur).T), np.ascontiguousarray(np.array(nor).T),
+                    np.zeros(x.shape[1], np.uint8), np.zeros(6), 1e12, dict(seed=seed, screw=screw))
+
+
+def long_segment_volume(seed=6, n_small=24) -> Instance:
+    """Very long segments: one glide loop of radius 1e5 b (32 segments of
+    about 19,600 b) and ``n_small`` loops of radius 100-500 b whose centres lie
+    50-500 b from a point of one of its segments (near its middle or near an
+    end), same FCC planes and Burgers vectors as the loop workloads; 50 MPa
+    along [001]."""
+    rng = np.random.default_rng(seed)
+    planes = np.concatenate([[0], rng.integers(0, 4, n_small)])
+    dirs = np.concatenate([[0], rng.integers(0, 3, n_small)])
+    signs = rng.integers(0, 2, n_small + 1) * 2 - 1
+    radii = np.concatenate([[1e5], rng.uniform(100.0, 500.0, n_small)])
+    phi0 = rng.uniform(0.0, 2.0 * math.pi, n_small + 1)
+    big_c = np.array([3.0e4, -2.0e4, 1.0e4])
+    n = PLANE_NORMALS[0]
+    e1 = SLIP_DIRS[0, 0]
+    e2 = np.cross(n, e1)
+    centres = [big_c]
+    for _ in range(n_small):
+        k = int(rng.integers(0, SEGS_PER_LOOP))
+        a0 = phi0[0] + 2.0 * math.pi * k / SEGS_PER_LOOP
+        a1 = a0 + 2.0 * math.pi / SEGS_PER_LOOP
+        pa = big_c + 1e5 * (math.cos(a0) * e1 + math.sin(a0) * e2)
+        pb = big_c + 1e5 * (math.cos(a1) * e1 + math.sin(a1) * e2)
+        s = rng.choice([rng.uniform(0.4, 0.6), rng.uniform(0.0, 0.05), rng.uniform(0.95, 1.0)])
+        dirv = _unit(rng.normal(size=3))
+        centres.append(pa + s * (pb - pa) + rng.uniform(50.0, 500.0) * dirv)
+    x, seg, bur, nor, meta = _loop_geometry(planes, dirs, signs, radii, np.array(centres), phi0)
+    return Instance(x, seg, bur, nor, np.zeros(x.shape[1], np.uint8), uniaxial_001(50.0e6),
+                    1e15, dict(meta, seed=seed))
+
+
+def relabel(inst: Instance, seed=7):
+    """The same volume with its segments stored in a random order and its
+    nodes renumbered by a random permutation (so that no run of segments is
+    stored loop by loop).  Returns (instance, node_map) with node_map[n] the
+    new index of old node n: forces on old node n appear at node_map[n]."""
+    rng = np.random.default_rng(seed)
+    nmap = rng.permutation(inst.n_nodes).astype(np.int64)
+    sperm = rng.permutation(inst.n_segs)
+    x = np.empty_like(inst.x)
+    x[:, nmap] = inst.x
+    pinned = np.empty_like(inst.pinned)
+    pinned[nmap] = inst.pinned
+    seg = np.ascontiguousarray(nmap[inst.seg_nodes[:, sperm]].astype(np.int32))
+    return (Instance(x, seg, np.ascontiguousarray(inst.burgers[:, sperm]),
+                     np.ascontiguousarray(inst.normal[:, sperm]), pinned, inst.sigma_app.copy(),
+                     inst.volume, dict(inst.meta, relabel=seed)), nmap)

@@ -75,6 +75,11 @@ def test_host_only_calls_without_gpu():
                                              ctypes.byref(m), 2, 0, 20.0, 1, 1.0, None, fake, None,
                                              None) == dd.DD_EINVAL
     sig = (ctypes.c_double * 6)()
+    # the mixed path's near-field cutoff is at least one core width
+    for cut in (0.5, 0.0, float("nan")):
+        assert dd.lib().dd_nodal_forces(4, fake, 4, fake, fake, fake, sig, ctypes.byref(m), 2, 1, cut,
+                                        fake, None) == dd.DD_EINVAL
+    assert "near_cutoff_a" in dd.dd_last_error()
     for args in ((-1, 1.0), (4, 0.0), (4, float("nan"))):   # negative count, dt <= 0, NaN dt
         assert dd.lib().dd_step(args[0], fake, 4, fake, fake, fake, None, sig, ctypes.byref(m), 2, 0, 20.0,
                                 args[1], None, None, None) == dd.DD_EINVAL

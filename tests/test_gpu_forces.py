@@ -129,12 +129,13 @@ def test_config1_full_sampled(prec, tol, Q):
 
 def test_mixed_cutoff_extremes_agree_with_fp64():
     """A huge cutoff sends every pair to FP64: must equal the FP64 path to
-    rounding; a tiny cutoff sends (almost) everything to FP32."""
+    rounding; the smallest allowed cutoff (one core width) sends nearly
+    everything to FP32."""
     inst = W.subset(W.config1(), 16)
     F64 = _gpu_forces(inst, 2)
     Fbig = _gpu_forces(inst, 2, dd.DD_MIXED, 1e9)
     assert normwise(Fbig, F64) < 1e-13
-    Fsmall = _gpu_forces(inst, 2, dd.DD_MIXED, 1e-3)
+    Fsmall = _gpu_forces(inst, 2, dd.DD_MIXED, 1.0)
     assert normwise(Fsmall, F64) < TOLMIX
 
 
@@ -418,3 +419,79 @@ def test_autotuner_on_off_same_forces():
     bm = _gpu_forces(inst, 2, dd.DD_MIXED)
     assert normwise(a, b) < 1e-13
     assert normwise(am, bm) < 1e-6
+
+
+def _per_node(a, b):
+    """max over nodes of |A_n - B_n| / |B_n|."""
+    return float((np.linalg.norm(a - b, axis=0) / np.linalg.norm(b, axis=0)).max())
+
+
+@pytest.mark.parametrize("screw", [True, False])
+def test_nearly_collinear_far_pairs_per_node(screw):
+    """Nearly collinear far pairs: a straight chain of 16 segments and 24 free
+    short segments on its extension 100-10,000 b beyond its ends, 0-2 b off
+    the line, no applied stress (workloads.collinear_chains).  Node forces span
+    seven decades, each node is compared on its own: mixed path 1e-4 per
+    node, FP64 path 1e-8 per node.  The reference takes every source field by
+    brute-force quadrature along the source, because the closed form loses
+    digits in this geometry (see the oracle pin of nearly collinear points)."""
+    inst = W.collinear_chains(screw=screw)
+    with O.source_quadrature(64, 64):
+        ref = _oracle_forces(inst, 2)
+    for prec, tol in ((dd.DD_MIXED, TOLMIX), (dd.DD_FP64, 1e-8)):
+        for variant in (0, 1, 2):
+            dd.dd_set_plan(0, variant)
+            try:
+                F = _gpu_forces(inst, 2, prec)
+            finally:
+                dd.dd_set_plan(-1)
+            e = _per_node(F, ref)
+            print(f"collinear screw={screw} prec={prec} variant {variant}: per-node err {e:.2e}, "
+                  f"normwise {normwise(F, ref):.2e}")
+            assert e < tol
+            if prec == dd.DD_FP64:
+                break
+
+
+def test_very_long_segments():
+    """Segments of about 19,600 b (one loop of radius 1e5 b) with small loops
+    50-500 b from them, near their middles and near their ends; coordinates
+    up to 1.3e5 b.  Every node against the oracle: FP64 normwise 1e-10, mixed
+    normwise 1e-4 and per node 1e-3 (a few nodes of the small loops carry
+    forces 1e4 times below the largest)."""
+    inst = W.long_segment_volume()
+    ref = _oracle_forces(inst, 2)
+    F64 = _gpu_forces(inst, 2)
+    e64 = normwise(F64, ref)
+    for variant in (0, 1, 2):
+        dd.dd_set_plan(0, variant)
+        try:
+            Fm = _gpu_forces(inst, 2, dd.DD_MIXED)
+        finally:
+            dd.dd_set_plan(-1)
+        em, pn = normwise(Fm, ref), _per_node(Fm, ref)
+        print(f"long segments: fp64 {e64:.2e}; mixed variant {variant} {em:.2e}, per node {pn:.2e}")
+        assert em < TOLMIX and pn < 1e-3
+    assert e64 < TOL64
+
+
+@pytest.mark.parametrize("prec,tol", [(dd.DD_FP64, TOL64), (dd.DD_MIXED, TOLMIX)])
+def test_config1_full_relabelled(prec, tol):
+    """The full 16,384-segment volume with its segments stored in a random
+    order and its nodes renumbered at random (no segment run is stored loop by
+    loop, so the kernels' shared-endpoint reuse and the node lists see a
+    general topology), in the benchmark's launch configuration; four whole
+    loops against the oracle of the original numbering."""
+    base = W.config1()
+    inst, nmap = W.relabel(base)
+    F = _gpu_forces(inst, 2, prec)
+    num = refmax = 0.0
+    for lp in (0, 101, 300, 511):
+        t0, t1 = 32 * lp, 32 * lp + 32
+        ref = O.nodal_forces_sampled(base.x, base.seg_nodes, base.burgers, base.sigma_app,
+                                     W.MU, W.NU, W.CORE_A, 2, t0, t1)[:, t0:t1]
+        got = F[:, nmap[t0:t1]]
+        num = max(num, np.linalg.norm(got - ref, axis=0).max())
+        refmax = max(refmax, np.linalg.norm(ref, axis=0).max())
+    print(f"config1 relabelled prec={prec}: err {num / refmax:.2e}")
+    assert num / refmax < tol

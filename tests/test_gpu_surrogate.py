@@ -63,23 +63,57 @@ def test_params_roundtrip():
     np.testing.assert_array_equal(p, flat(*params[1]))
 
 
-@pytest.mark.parametrize("n", [1, 255, 257, 1000])
+def row_rel(a, b):
+    """Element-wise error relative to each row's largest |value| of b."""
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    den = np.maximum(np.abs(b).max(axis=1, keepdims=True), 1e-300)
+    return np.abs(a - b) / den
+
+
+def check_elementwise(got, ref, what):
+    """Element-by-element agreement with the bf16-emulating oracle.  The
+    oracle rounds at the same points as the kernels, but an activation that
+    lies on a bfloat16 rounding boundary can round either way depending on the
+    order of the float32 sums inside the matrix cores, which the CPU cannot
+    reproduce; one such flip moves that activation by one bfloat16 ulp (2^-7
+    relative).  So: every output column within 1e-3 of its own norm (a column
+    that is systematically off fails), 99.9 % of the elements within 1e-3 of
+    their row's largest value, and none beyond 2e-2 (a few flips at most)."""
+    got = np.asarray(got, np.float64); ref = np.asarray(ref, np.float64)
+    e = row_rel(got, ref)
+    col = np.linalg.norm(got - ref, axis=0) / np.maximum(np.linalg.norm(ref, axis=0), 1e-300)
+    q = float(np.quantile(e, 0.999))
+    print(f"{what}: element max {e.max():.2e}, 99.9% {q:.2e}, worst column {col.max():.2e}")
+    assert col.max() < 1e-3
+    assert q < 1e-3
+    assert e.max() < 2e-2
+
+
+@pytest.mark.parametrize("n", [1, 255, 257, 1000, 65536])
 def test_forward_parity(n):
-    """Against the bf16-emulating oracle; n spans one partial, one full plus one
-    row and several 256-row workgroups with a ragged tail."""
+    """Against the bf16-emulating oracle, element by element (check_elementwise)
+    for the rates and the spread, and the same DD-fallback flag wherever the
+    spread is more than 2e-2 (relative) from the threshold; n spans one
+    partial, one full plus one row, several 256-row workgroups with a ragged
+    tail, and a large batch.  The whole-array norms against the unrounded FP64
+    network stay within the bfloat16 budget."""
     mdl, params, sc = _model()
     feat = np.random.default_rng(1).normal(size=(n, 36)).astype(np.float32)
-    r, s, f = dd.dd_surrogate_rates(mdl, torch.tensor(feat, device=DEV), 0.05)
+    tol_spread = 1.8   # near the median spread of these random members: both flag values occur
+    r, s, f = dd.dd_surrogate_rates(mdl, torch.tensor(feat, device=DEV), tol_spread)
     torch.cuda.synchronize()
+    r, s, f = r.cpu().numpy(), s.cpu().numpy(), f.cpu().numpy()
     ro, so, fo = M.ensemble_predict(params, feat.astype(np.float64), sc[0], sc[1], sc[2], sc[3],
-                                    tol=0.05, bf16=True)
-    e = nrel(r.cpu().numpy(), ro)
-    print(f"surrogate forward rates err {e:.2e}, spread err {nrel(s.cpu().numpy(), so):.2e}")
-    assert e < TOL
-    assert nrel(s.cpu().numpy(), so) < TOL
+                                    tol=tol_spread, bf16=True)
+    print(f"surrogate forward n={n}: normwise rates {nrel(r, ro):.2e}, flagged {int(f.sum())}")
+    check_elementwise(r, ro, "rates")
+    check_elementwise(s[:, None], so[:, None], "spread")
+    clear = np.abs(so - tol_spread) > 2e-2 * tol_spread
+    np.testing.assert_array_equal(f[clear].astype(bool), np.asarray(fo)[clear].astype(bool))
+    assert nrel(r, ro) < TOL and nrel(s, so) < TOL
     # exact (unrounded) FP64 network: still within the bfloat16 budget
     ro64, _, _ = M.ensemble_predict(params, feat.astype(np.float64), sc[0], sc[1], sc[2], sc[3])
-    assert nrel(r.cpu().numpy(), ro64) < TOL
+    assert nrel(r, ro64) < TOL
 
 
 @pytest.mark.parametrize("n", [1, 37, 1024])
@@ -199,6 +233,5 @@ def test_forward_parity_log_densities():
     r, s, f = dd.dd_surrogate_rates(mdl, torch.tensor(feat, device=DEV), 0.05)
     ro, so, fo = M.ensemble_predict(params, feat.astype(np.float64), shift, scale, sc[2], sc[3],
                                     tol=0.05, bf16=True, log_dens=dens)
-    e = nrel(r.cpu().numpy(), ro)
-    print(f"surrogate forward with log densities err {e:.2e}")
-    assert e < TOL
+    check_elementwise(r.cpu().numpy(), ro, "rates with log densities")
+    assert nrel(r.cpu().numpy(), ro) < TOL
