@@ -368,12 +368,13 @@ def main():
 
     vol = resident(inst)
 
-    def run(prec, Q, steps, warmup, v=None):
+    def run(prec, Q, steps, warmup, v=None, eta=0.0):
         v = vol if v is None else v
         x, sn, bg, nr, F, V = v["x"].clone(), v["sn"], v["b"], v["n"], v["F"], v["V"]
 
         def step():
-            dd.dd_step(x, sn, bg, nr, None, v["sig"], mat, W.DT, Q, prec, 20.0, force_out=F, vel_out=V)
+            dd.dd_step(x, sn, bg, nr, None, v["sig"], mat, W.DT, Q, prec, 20.0, force_out=F, vel_out=V,
+                       exact_eta=eta)
 
         for _ in range(warmup):
             step()
@@ -467,9 +468,7 @@ def main():
 
     if args.only in ("fp64", "mixed"):
         prec = dd.DD_FP64 if args.only == "fp64" else dd.DD_MIXED
-        dd.dd_set_exact_band(args.exact_band)
-        s, k, _ = run(prec, 2, args.steps, args.warmup)
-        dd.dd_set_exact_band(0.0)
+        s, k, _ = run(prec, 2, args.steps, args.warmup, eta=args.exact_band)
         print(json.dumps({"part": args.only, "exact_band": args.exact_band, "ms_per_step": s * 1e3,
                           "kernel_ms": k * 1e3}))
         return
@@ -530,11 +529,7 @@ def main():
                 e = K[None, :, :3] - K[j0:j0 + 256, None, :3]
                 dd2 = e[..., 0] * e[..., 0] + e[..., 1] * e[..., 1] + e[..., 2] * e[..., 2]
                 n_near += int((dd2 < c2 * (K[None, :, 3] + K[j0:j0 + 256, None, 3])).sum()) - min(256, N - j0)
-            dd.dd_set_exact_band(eta)
-            try:
-                s_b, _, _ = run(prec, 2, args.steps, max(3, args.warmup))
-            finally:
-                dd.dd_set_exact_band(0.0)
+            s_b, _, _ = run(prec, 2, args.steps, max(3, args.warmup), eta=eta)
             base = step_s if prec == dd.DD_FP64 else extras["mixed_q2"]["ms_per_step"] / 1e3
             extras[name] = {"eta": eta, "near_pairs_per_step": n_near, "ms_per_step": s_b * 1e3,
                             "plain_ms_per_step": base * 1e3, "overhead_ms": (s_b - base) * 1e3,
@@ -558,20 +553,33 @@ def main():
                   b=torch.tensor(sb.burgers, device=dev), n=torch.tensor(sb.normal, device=dev),
                   p=torch.tensor(sb.pinned, device=dev), s=torch.tensor(sb.sigma_app, device=dev),
                   v=torch.tensor(sb.volume, device=dev))
-        dd.dd_burst_batch(sb.node_off, sb.seg_off, ds["x"].clone(), ds["sn"], ds["b"], ds["n"], ds["p"],
-                          ds["s"], ds["v"], mat, 2, dd.DD_FP64, 20.0, 100, W.DT)
+        xs = ds["x"].clone()
+        rs = torch.empty((1, 12), dtype=torch.float64, device=dev)
+
+        def small_call():
+            xs.copy_(ds["x"])   # the same start, in the same buffer: the cached graph applies
+            dd.dd_burst_batch(sb.node_off, sb.seg_off, xs, ds["sn"], ds["b"], ds["n"], ds["p"],
+                              ds["s"], ds["v"], mat, 2, dd.DD_FP64, 20.0, 100, W.DT, rate_avg_out=rs)
+
+        dd.dd_shutdown()   # no cached graph: the first call below captures
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        reps = 5
+        small_call()
+        torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
+        reps = 20
+        t0 = time.perf_counter()
         for _ in range(reps):
-            dd.dd_burst_batch(sb.node_off, sb.seg_off, ds["x"].clone(), ds["sn"], ds["b"], ds["n"],
-                              ds["p"], ds["s"], ds["v"], mat, 2, dd.DD_FP64, 20.0, 100, W.DT)
+            small_call()
         torch.cuda.synchronize()
         t_small = (time.perf_counter() - t0) / reps
         extras["small_volume_100_steps_fp64"] = {
             "segments": 256, "steps": 100, "seconds_per_call": t_small,
-            "us_per_step": t_small / 100 * 1e6,
-            "note": "one call = upload, graph capture of the 100 steps, one launch, synchronise"}
+            "us_per_step": t_small / 100 * 1e6, "first_call_seconds": t_first,
+            "first_call_us_per_step": t_first / 100 * 1e6,
+            "note": "cached: the step graph captured by an earlier call with the same arguments is "
+                    "relaunched, calls enqueued back to back and synchronised once; first call: instance "
+                    "tables, work split, capture and instantiation of the 100 steps, launch"}
         out["extras"] = extras
 
     if (not args.no_extras and args.only is None) or args.only == "burst":
@@ -586,18 +594,24 @@ def main():
         # one short warm-up launch (graph capture path, kernels loaded)
         dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"].clone(), d["sn"], d["b"], d["n"], d["p"],
                           d["s"], d["v"], mat, 2, dd.DD_MIXED, 20.0, 1, W.DT)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rates, _ = dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["sn"], d["b"], d["n"],
-                                     d["p"], d["s"], d["v"], mat, 2, dd.DD_MIXED, 20.0,
-                                     args.burst_steps, W.DT)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        x0 = d["x"].clone()
+        rates = torch.empty((bt.n_inst, 12), dtype=torch.float64, device=dev)
+        t_calls = []
+        for _ in range(2):   # the first call captures the step graph, the second relaunches it
+            d["x"].copy_(x0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["sn"], d["b"], d["n"],
+                              d["p"], d["s"], d["v"], mat, 2, dd.DD_MIXED, 20.0,
+                              args.burst_steps, W.DT, rate_avg_out=rates)
+            torch.cuda.synchronize()
+            t_calls.append(time.perf_counter() - t0)
+        t0, t1 = 0.0, t_calls[1]
         bursts = {"workload": f"{bt.n_inst} independent bursts, 256-4096 segments each, "
                               f"{args.burst_steps} glide steps, 2 Gauss points, mixed, one graph launch",
                   "instances": bt.n_inst, "segments_total": int(bt.seg_off[-1]),
                   "steps": args.burst_steps, "seconds": t1 - t0, "pairs": bpairs,
-                  "pairs_per_s": bpairs / (t1 - t0),
+                  "pairs_per_s": bpairs / (t1 - t0), "first_call_seconds": t_calls[0],
                   "finite": bool(torch.isfinite(rates).all().item())}
         # the same bursts with junctions: capture radius 10 b, maximum breaking
         # time 50 steps, uniform fractions (4 per node)

@@ -118,28 +118,15 @@ int dd_shutdown(void);
  * setting. */
 int dd_set_autotune(int on);
 
-/* Exact band.  The nodal force a source segment i sends to target segment j
- * is L_j int_0^1 N(u) (sigma^i(x_j(u)) b_j) x t_j du for the two linear shape
- * functions N (the Peach-Koehler force of Sec. "Discrete Dislocation
- * Dynamics" integrated along the target).  By default every pair takes the
- * n_gauss-point Gauss-Legendre rule for this integral.  With eta > 0, pairs
- * whose midpoints are closer than eta sqrt((L_i^2 + L_j^2)/2), i.e. with
- * S = x1 + x2 and D = x2 - x1,
- *     |S_i - S_j|^2 < 2 eta^2 (|D_i|^2 + |D_j|^2)
- * (evaluated in float64 without fused multiply-adds, in this order, on the
- * caller's positions), take the integral exactly instead (to ~1e-14 of the
- * pair's contribution: 12-point Gauss-Legendre on panels graded towards the
- * integrand's complex singularities).  This removes the quadrature error of
- * a small n_gauss on adjacent and close segments (several per cent of the
- * net self-force of an irregular loop at n_gauss = 2); eta = 2 to 4 selects
- * about 4 to 16 near sources per segment in dislocation loops.  The self pair
- * is never included.  Process-wide: applies to every later call of
- * dd_nodal_forces, dd_burst_batch and dd_pta_step, with either precision
- * (the correction is always float64).  eta = 0 (the default) turns it off.
- * Limits: at most 64 near sources per segment and 32 per segment on average,
- * else the force call returns DD_ECAPACITY; at most 33,554,431 segments.
- * DD_EINVAL for a negative or non-finite eta. */
-int dd_set_exact_band(double eta);
+/* Report, and clear, the conditions the device-side checks raised since the
+ * last report: synchronises `stream` (hipStream_t, may be null) and returns
+ * DD_OK, or the error code and message of the first condition in the order
+ * DD_EINVAL (bad node index, zero-length segment, normal not of unit
+ * length), DD_ENONFINITE, DD_ECAPACITY (exact band: a captured step's near
+ * pairs outgrew the pair store, see dd_burst_batch).  Calls made with
+ * validation on report them themselves; with validation off they stay
+ * pending until this call or the next validating call. */
+int dd_check(void *stream);
 
 /* Fix the work split instead of letting the autotuner (or its heuristic)
  * choose it, for reproducible benchmarks and for tests of each kernel
@@ -200,21 +187,40 @@ int dd_vector_peak(int kind, int reps, double *tflops, void *stream);
  *  where sigma^i is the closed-form non-singular stress of segment i.  A
  *  segment's own field is excluded (it only redistributes force between its
  *  two nodes: its net force vanishes by symmetry).
+ * Exact band: the force source i sends to target j's nodes is L_j int_0^1
+ *  N(u) (sigma^i(x_j(u)) b_j) x t_j du for the two linear shape functions N
+ *  (the Peach-Koehler force of Sec. "Discrete Dislocation Dynamics"
+ *  integrated along the target); the rule above takes it with n_gauss
+ *  points.  With exact_eta > 0, pairs whose midpoints are closer than
+ *  exact_eta sqrt((L_i^2 + L_j^2)/2), i.e. with S = x1 + x2, D = x2 - x1,
+ *      |S_i - S_j|^2 < 2 exact_eta^2 (|D_i|^2 + |D_j|^2)
+ *  (evaluated in float64 without fused multiply-adds, in this order, on the
+ *  caller's positions), take it exactly instead (to ~1e-14 of the pair's
+ *  contribution: 12-point Gauss-Legendre on panels graded towards the
+ *  integrand's complex singularities).  This removes the quadrature error of
+ *  a small n_gauss on adjacent and close segments (several per cent of the
+ *  net self-force of an irregular loop at n_gauss = 2); exact_eta = 2 to 4
+ *  selects about 4 to 16 near sources per segment in dislocation loops.  The
+ *  self pair is never included; the correction is float64 with either
+ *  precision.  0 turns the band off.  With the band on, the call counts the
+ *  near pairs first and synchronises the stream once to size its pair store
+ *  (any number of near sources per segment; at most 2^31 - 1 near pairs).
  * Arguments: x [3][n_nodes], seg_nodes [2][n_segs], burgers [3][n_segs];
  *  normal [3][n_segs] is validated (unit length) but unused by the force;
  *  sigma_app host [6]; m host; 1 <= n_gauss <= DD_MAX_GAUSS; precision a
  *  dd_precision; near_cutoff_a >= 1 (in units of a, mixed only, checked
- *  only for DD_MIXED; the workload value is 20); force_out [3][n_nodes]
- *  (overwritten).
+ *  only for DD_MIXED; the workload value is 20); exact_eta >= 0 and finite;
+ *  force_out [3][n_nodes] (overwritten).
  * Errors: DD_EINVAL for null pointers, counts < 0, bad material, n_gauss out
- *  of range, a node index outside [0, n_nodes), a zero-length segment or a
- *  normal of length differing from 1 by more than 1e-6 (validation on);
- *  DD_ENONFINITE if a force is NaN/Inf (validation on). */
+ *  of range, a bad exact_eta, a node index outside [0, n_nodes), a
+ *  zero-length segment or a normal of length differing from 1 by more than
+ *  1e-6 (validation on); DD_ENONFINITE if a force is NaN/Inf (validation
+ *  on); DD_ECAPACITY for more than 2^31 - 1 near pairs. */
 int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
                     const int32_t *seg_nodes, const double *burgers,
                     const double *normal, const double *sigma_app,
                     const dd_material *m, int n_gauss, int precision,
-                    double near_cutoff_a, double *force_out, void *stream);
+                    double near_cutoff_a, double exact_eta, double *force_out, void *stream);
 
 /* One glide-constrained forward-Euler step (Eq. DD_evol, lumped, scalar B):
  *    ell_n = 1/2 sum_{s attached to n} L_s
@@ -243,8 +249,8 @@ int dd_glide_step(int64_t n_nodes, double *x, const double *force,
  * calls. */
 int dd_step(int64_t n_nodes, double *x, int64_t n_segs, const int32_t *seg_nodes, const double *burgers,
             const double *normal, const uint8_t *pinned, const double *sigma_app, const dd_material *m,
-            int n_gauss, int precision, double near_cutoff_a, double dt, double *force_out, double *vel_out,
-            void *stream);
+            int n_gauss, int precision, double near_cutoff_a, double exact_eta, double dt, double *force_out,
+            double *vel_out, void *stream);
 
 /* Independent DD bursts at frozen applied stress, all advanced together.
  *  Instance i owns nodes [node_off[i], node_off[i+1]) and segments
@@ -269,9 +275,22 @@ int dd_step(int64_t n_nodes, double *x, int64_t n_segs, const int32_t *seg_nodes
  * Arguments: node_off, seg_off HOST [n_inst+1] int64, non-decreasing, from 0;
  *  x, seg_nodes, burgers, normal, pinned (nullable) packed as above;
  *  sigma_app [n_inst][6] and volume [n_inst] device; m host; n_gauss,
- *  precision, near_cutoff_a as dd_nodal_forces; n_steps >= 0; dt > 0;
- *  rate_avg_out [n_inst][12].  The step loop is captured once into a HIP
- *  graph and launched as one graph.
+ *  precision, near_cutoff_a, exact_eta as dd_nodal_forces; n_steps >= 0;
+ *  dt > 0; rate_avg_out [n_inst][12].
+ * Execution: the step loop is captured into a HIP graph, instantiated and
+ *  kept (up to 4 per device, least recently used dropped): a later call
+ *  with the same arguments (pointers and values), offsets and work split
+ *  relaunches it without capture.  With validation off the call is
+ *  asynchronous on `stream` (outputs valid after the stream is synchronised)
+ *  once the instance tables, work split and graph are cached: the first call
+ *  for new offsets uploads tables and may time the work split
+ *  (synchronising).  With validation on it synchronises and reports errors.
+ *  Exact band: the near-pair store is sized before capture to twice the
+ *  near-pair count of the initial positions plus 8 per segment (a count pass
+ *  and one synchronisation; with validation off only while the store is
+ *  empty); a step whose near pairs outgrow it keeps the n_gauss rule for the
+ *  excess pairs and raises DD_ECAPACITY (reported by this call with
+ *  validation on, else by dd_check).
  * Errors: as dd_nodal_forces, also for inconsistent offsets. */
 int dd_burst_batch(int32_t n_inst, const int64_t *node_off,
                    const int64_t *seg_off, double *x,
@@ -279,7 +298,7 @@ int dd_burst_batch(int32_t n_inst, const int64_t *node_off,
                    const double *normal, const uint8_t *pinned,
                    const double *sigma_app, const double *volume,
                    const dd_material *m, int n_gauss, int precision,
-                   double near_cutoff_a, int n_steps, double dt,
+                   double near_cutoff_a, double exact_eta, int n_steps, double dt,
                    double *rate_avg_out, double *features_out, void *stream);
 
 /* Junctions and their thermally activated breaking (Sec. "Thermal
@@ -318,8 +337,8 @@ int dd_burst_batch_junctions(int32_t n_inst, const int64_t *node_off, const int6
                              const int32_t *seg_nodes, const double *burgers, const double *normal,
                              const uint8_t *pinned, const double *sigma_app, const double *volume,
                              const dd_material *m, int n_gauss, int precision, double near_cutoff_a,
-                             int n_steps, double dt, const dd_junctions *junctions, double *rate_avg_out,
-                             double *features_out, void *stream);
+                             double exact_eta, int n_steps, double dt, const dd_junctions *junctions,
+                             double *rate_avg_out, double *features_out, void *stream);
 
 /* One slow-time step of Practical Time Averaging for a batch of independent
  * DD volumes (Sec. "Application of PTA for coarse-graining DD simulation",
@@ -349,7 +368,7 @@ int dd_burst_batch_junctions(int32_t n_inst, const int64_t *node_off, const int6
  * Arguments: node_off, seg_off HOST; x, seg_nodes, burgers, normal, pinned
  *  (nullable) and volume device, as dd_burst_batch; stress_rate HOST
  *  [n_inst][6] Voigt Pa/s; t HOST [n_inst] s; prm, m host; n_gauss,
- *  precision, near_cutoff_a as dd_nodal_forces; out HOST
+ *  precision, near_cutoff_a, exact_eta as dd_nodal_forces; out HOST
  *  [n_inst][DD_PTA_OUT] doubles laid out by the DD_PTA_* indices below
  *  (L^p row-major).  Synchronises the stream.
  * Errors: DD_EINVAL for inconsistent offsets or parameters (dt, delta,
@@ -389,7 +408,7 @@ int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off,
                 const int32_t *seg_nodes, const double *burgers, const double *normal,
                 const uint8_t *pinned, const double *volume, const double *stress_rate,
                 const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
-                int precision, double near_cutoff_a, double *out, void *stream);
+                int precision, double near_cutoff_a, double exact_eta, double *out, void *stream);
 
 /* dd_pta_step with junctions (see dd_junctions; Sec. "Thermal activation"):
  * every fast step runs the junction checks first.  The junction state
@@ -408,7 +427,7 @@ int dd_pta_step_junctions(int32_t n_inst, const int64_t *node_off, const int64_t
                           const int32_t *seg_nodes, const double *burgers, const double *normal,
                           const uint8_t *pinned, const double *volume, const double *stress_rate,
                           const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
-                          int precision, double near_cutoff_a, const dd_junctions *junctions,
+                          int precision, double near_cutoff_a, double exact_eta, const dd_junctions *junctions,
                           int64_t *fast_steps, double *out, void *stream);
 
 /* Block coupling of the DD boxes to the continuum mesh (Sec. "DD-MFDM

@@ -25,7 +25,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
-    "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_exact_band", "dd_set_plan", "dd_last_plan",
+    "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_check", "dd_set_plan", "dd_last_plan",
     "dd_nodal_forces", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_pta_step", "dd_pta_step_junctions",
     "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
@@ -104,30 +104,30 @@ def _declare(L):
         "dd_vector_peak": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_double), vp]),
         "dd_pta_step": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp, vp, vp,
                                   vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                  C.POINTER(PTAParams), C.POINTER(Material), C.c_int, C.c_int, dbl,
+                                  C.POINTER(PTAParams), C.POINTER(Material), C.c_int, C.c_int, dbl, dbl,
                                   C.POINTER(C.c_double), vp]),
         "dd_pta_step_junctions": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp, vp,
                                             vp, vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                             C.POINTER(PTAParams), C.POINTER(Material), C.c_int, C.c_int, dbl,
-                                            C.POINTER(Junctions), C.POINTER(C.c_int64), C.POINTER(C.c_double),
-                                            vp]),
+                                            dbl, C.POINTER(Junctions), C.POINTER(C.c_int64),
+                                            C.POINTER(C.c_double), vp]),
         "dd_set_plan": (C.c_int, [i64, C.c_int]),
-        "dd_set_exact_band": (C.c_int, [C.c_double]),
+        "dd_check": (C.c_int, [vp]),
         "dd_block_average": (C.c_int, [C.POINTER(BlockMesh), C.c_int, vp, vp, vp]),
         "dd_block_to_gauss": (C.c_int, [C.POINTER(BlockMesh), C.c_int, vp, vp, vp]),
         "dd_dissipation_fix": (C.c_int, [i64, vp, vp, vp, vp, vp]),
         "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
-                                      C.POINTER(Material), C.c_int, C.c_int, dbl, vp, vp]),
+                                      C.POINTER(Material), C.c_int, C.c_int, dbl, dbl, vp, vp]),
         "dd_glide_step": (C.c_int, [i64, vp, vp, i64, vp, vp, vp, C.POINTER(Material), dbl,
                                     vp, vp]),
         "dd_step": (C.c_int, [i64, vp, i64, vp, vp, vp, vp, C.POINTER(C.c_double), C.POINTER(Material), C.c_int,
-                              C.c_int, dbl, dbl, vp, vp, vp]),
+                              C.c_int, dbl, dbl, dbl, vp, vp, vp]),
         "dd_burst_batch": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp,
                                      vp, vp, vp, vp, vp, C.POINTER(Material), C.c_int, C.c_int,
-                                     dbl, C.c_int, dbl, vp, vp, vp]),
+                                     dbl, dbl, C.c_int, dbl, vp, vp, vp]),
         "dd_burst_batch_junctions": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp,
                                                vp, vp, vp, vp, vp, C.POINTER(Material), C.c_int, C.c_int,
-                                               dbl, C.c_int, dbl, C.POINTER(Junctions), vp, vp, vp]),
+                                               dbl, dbl, C.c_int, dbl, C.POINTER(Junctions), vp, vp, vp]),
         "dd_mlp_create": (C.c_int, [C.c_int, C.c_uint64, C.POINTER(vp)]),
         "dd_mlp_destroy": (C.c_int, [vp]),
         "dd_mlp_set_params": (C.c_int, [vp, C.c_int, fp]),
@@ -213,10 +213,10 @@ def dd_set_autotune(on: bool) -> bool:
     return bool(lib().dd_set_autotune(1 if on else 0))
 
 
-def dd_set_exact_band(eta: float = 0.0):
-    """Exact target integral for pairs with midpoints closer than
-    eta*sqrt((Li^2+Lj^2)/2); 0 turns it off.  Process-wide; see dd.h."""
-    _check(lib().dd_set_exact_band(float(eta)))
+def dd_check(stream=None):
+    """Synchronise the stream and raise DDError for conditions the device-side
+    checks raised since the last report (calls made with validation off)."""
+    _check(lib().dd_check(_stream(stream)))
 
 
 def _block_args(n, m, B, h):
@@ -299,8 +299,9 @@ def dd_vector_peak(kind: str = "fp64", reps: int = 20, stream=None) -> float:
 
 # -------------------------------------------------------------- force path --
 def dd_nodal_forces(x, seg_nodes, burgers, normal, sigma_app, mat, n_gauss=2,
-                    precision=DD_FP64, near_cutoff_a=20.0, force_out=None, stream=None):
-    """Nodal forces [3][n_nodes] (float64) of the volume; see dd.h."""
+                    precision=DD_FP64, near_cutoff_a=20.0, force_out=None, stream=None, exact_eta=0.0):
+    """Nodal forces [3][n_nodes] (float64) of the volume; exact_eta > 0 turns
+    the exact band on (see dd.h)."""
     nn = x.shape[1] if x.dim() == 2 else -1
     ns = seg_nodes.shape[1] if seg_nodes.dim() == 2 else -1
     px = _dev(x, torch.float64, (3, nn), "x")
@@ -313,7 +314,7 @@ def dd_nodal_forces(x, seg_nodes, burgers, normal, sigma_app, mat, n_gauss=2,
     sig = (C.c_double * 6)(*[float(v) for v in sigma_app])
     m = _mat(mat)
     _check(lib().dd_nodal_forces(nn, px, ns, psn, pb, pn, sig, C.byref(m), int(n_gauss),
-                                 _prec(precision), float(near_cutoff_a), pf, _stream(stream)))
+                                 _prec(precision), float(near_cutoff_a), float(exact_eta), pf, _stream(stream)))
     return force_out
 
 
@@ -336,7 +337,7 @@ def dd_glide_step(x, force, seg_nodes, normal, pinned, mat, dt, vel_out=None, st
 
 
 def dd_step(x, seg_nodes, burgers, normal, pinned, sigma_app, mat, dt, n_gauss=2, precision=DD_FP64,
-            near_cutoff_a=20.0, force_out=None, vel_out=None, stream=None):
+            near_cutoff_a=20.0, force_out=None, vel_out=None, stream=None, exact_eta=0.0):
     """One DD step (nodal forces, then the glide step) in one call; x advances
     in place.  Returns (force, vel) [3][n_nodes] (None where the library used
     its workspace because the output was not requested: pass tensors to keep
@@ -353,14 +354,14 @@ def dd_step(x, seg_nodes, burgers, normal, pinned, sigma_app, mat, dt, n_gauss=2
     sig = (C.c_double * 6)(*[float(v) for v in sigma_app])
     m = _mat(mat)
     _check(lib().dd_step(nn, px, ns, psn, pb, pn, pp, sig, C.byref(m), int(n_gauss), _prec(precision),
-                         float(near_cutoff_a), float(dt), pf, pv, _stream(stream)))
+                         float(near_cutoff_a), float(exact_eta), float(dt), pf, pv, _stream(stream)))
     return force_out, vel_out
 
 
 def dd_burst_batch(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app,
                    volume, mat, n_gauss=2, precision=DD_MIXED, near_cutoff_a=20.0,
                    n_steps=200, dt=2e-14, rate_avg_out=None, features_out=None,
-                   want_features=False, stream=None):
+                   want_features=False, stream=None, exact_eta=0.0):
     """Batched bursts; node_off/seg_off are host sequences (length n_inst+1).
     Returns (rate_avg [n_inst][12], features [n_inst][36] or None); x advances."""
     no = (C.c_int64 * len(node_off))(*[int(v) for v in node_off])
@@ -385,7 +386,7 @@ def dd_burst_batch(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sig
     pfe = _dev(features_out, torch.float64, (n_inst, 36), "features_out", nullable=True)
     m = _mat(mat)
     _check(lib().dd_burst_batch(n_inst, no, so, px, psn, pb, pn, pp, ps, pv, C.byref(m),
-                                int(n_gauss), _prec(precision), float(near_cutoff_a),
+                                int(n_gauss), _prec(precision), float(near_cutoff_a), float(exact_eta),
                                 int(n_steps), float(dt), pr, pfe, _stream(stream)))
     return rate_avg_out, features_out
 
@@ -393,7 +394,7 @@ def dd_burst_batch(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sig
 def dd_burst_batch_junctions(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume,
                              mat, state, fractions, capture_radius, max_break_time, t0=0.0, n_gauss=2,
                              precision=DD_MIXED, near_cutoff_a=20.0, n_steps=200, dt=2e-14,
-                             rate_avg_out=None, stream=None):
+                             rate_avg_out=None, stream=None, exact_eta=0.0):
     """Batched bursts with junctions (dd.h, dd_junctions).  state: dict of device
     tensors junction (int32), release (float64), ignore (int32), count (int32),
     each [n_nodes], updated in place; fractions [n_nodes][K] float64 (device).
@@ -418,7 +419,7 @@ def dd_burst_batch_junctions(node_off, seg_off, x, seg_nodes, burgers, normal, p
     pr = _dev(rate_avg_out, torch.float64, (n_inst, 12), "rate_avg_out")
     m = _mat(mat)
     _check(lib().dd_burst_batch_junctions(n_inst, no, so, px, psn, pb, pn, pp, ps, pv, C.byref(m),
-                                          int(n_gauss), _prec(precision), float(near_cutoff_a),
+                                          int(n_gauss), _prec(precision), float(near_cutoff_a), float(exact_eta),
                                           int(n_steps), float(dt), C.byref(jn), pr, None, _stream(stream)))
     return rate_avg_out
 
@@ -435,7 +436,8 @@ def _junction_args(state, fractions, capture_radius, max_break_time, nn, t0=0.0)
 
 
 def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t,
-                params, mat, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0, stream=None, junctions=None):
+                params, mat, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0, stream=None, junctions=None,
+                exact_eta=0.0):
     """One PTA slow-time step for every instance (see dd.h); x advances to the
     microstructure for the next step.  stress_rate [n_inst][6] (Pa/s) and t
     [n_inst] (s) are host sequences.  Returns a dict of NumPy arrays.
@@ -465,7 +467,7 @@ def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume
     if junctions is None:
         _check(lib().dd_pta_step(n_inst, no, so, px, psn, pb, pn, pp, pv, sr.ctypes.data_as(dp),
                                  tt.ctypes.data_as(dp), C.byref(params), C.byref(m), int(n_gauss),
-                                 _prec(precision), float(near_cutoff_a), out.ctypes.data_as(dp),
+                                 _prec(precision), float(near_cutoff_a), float(exact_eta), out.ctypes.data_as(dp),
                                  _stream(stream)))
     else:
         jn = _junction_args(junctions["state"], junctions["fractions"], junctions["capture_radius"],
@@ -476,7 +478,7 @@ def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume
             raise ValueError("junctions['fast_steps'] must be a contiguous int64 array of length n_inst")
         _check(lib().dd_pta_step_junctions(n_inst, no, so, px, psn, pb, pn, pp, pv, sr.ctypes.data_as(dp),
                                            tt.ctypes.data_as(dp), C.byref(params), C.byref(m), int(n_gauss),
-                                           _prec(precision), float(near_cutoff_a), C.byref(jn),
+                                           _prec(precision), float(near_cutoff_a), float(exact_eta), C.byref(jn),
                                            fs.ctypes.data_as(C.POINTER(C.c_int64)), out.ctypes.data_as(dp),
                                            _stream(stream)))
     return {"rho_a": out[:, 0], "rho_b": out[:, 1], "g_a": out[:, 2:14], "g_b": out[:, 14:26],
@@ -488,12 +490,13 @@ def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume
 
 
 def dd_pta_step_junctions(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t,
-                          params, mat, junctions, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0, stream=None):
+                          params, mat, junctions, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0, stream=None,
+                          exact_eta=0.0):
     """dd_pta_step with junctions (dd.h); `junctions` as in dd_pta_step."""
     if junctions is None:
         raise ValueError("junctions is required")
     return dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, params,
-                       mat, n_gauss, precision, near_cutoff_a, stream, junctions)
+                       mat, n_gauss, precision, near_cutoff_a, stream, junctions, exact_eta)
 
 
 # --------------------------------------------------------------- surrogate --

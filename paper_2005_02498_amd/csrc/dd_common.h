@@ -79,17 +79,35 @@ enum Slot {
     WS_NSLOTS
 };
 
+// An instantiated step graph and the bytes of everything its kernels'
+// arguments were built from (caller pointers and scalars, instance offsets,
+// work split, workspace addresses): a call with the same key relaunches it.
+struct GraphEntry {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
+constexpr size_t GRAPH_CACHE = 4;   // graphs kept per device (least recently used evicted)
+
 struct Workspace {
     int device = -1;
     void *ptr[WS_NSLOTS] = {};
     size_t cap[WS_NSLOTS] = {};
-    unsigned *flags_dev = nullptr;   // one word
-    unsigned *flags_host = nullptr;  // pinned mirror
+    unsigned *flags_dev = nullptr;   // one word (sticky: cleared only when reported)
+    unsigned *flags_host = nullptr;  // pinned mirror (bytes 64..71: near-pair count read-back)
     hipStream_t capture_stream = nullptr;
     int64_t block_fac_n = -1;                    // size of the tridiagonal factors in WS_BLOCK_FAC
     unsigned long long *near_count = nullptr;   // device counter (mixed kernel)
     bool capturing = false;
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
+    std::vector<int64_t> inst_key;   // offsets whose instance tables WS_SEG_INST / WS_INST_OFFS hold
 };
+
+// Reports (and clears) the flags raised since the last report; synchronises st.
+int read_flags(Workspace *ws, hipStream_t st);
+// Destroys the cached graphs of ws (synchronising the device first).
+void drop_graphs(Workspace *ws);
 
 // Event timing of the all-pairs kernel (dd_timing_enable / dd_timing_read).
 bool timing_on();
@@ -167,10 +185,9 @@ inline __host__ __device__ int quad_points(int variant) { return variant == 0 ? 
 
 GaussRule gauss_rule(int n);
 
-// Exact band (dd_set_exact_band): near-pair lists and the exact target
-// integrals of those pairs, as corrections to the Q-point end forces.
-constexpr int NEAR_CAP = 64;   // near sources kept per target segment
-constexpr int NEAR_AVG = 32;   // pair storage per segment (the mean near count may not exceed it)
+// Exact band (the exact_eta argument of the force calls): near-pair lists and
+// the exact target integrals of those pairs, as corrections to the Q-point
+// end forces.
 constexpr int NEAR_GROUP = 8;  // consecutive segments per bounding sphere of the near search
 struct NearArgs {
     int64_t ns = 0, nn = 0, n_waves = 0, pair_cap = 0;
@@ -186,17 +203,20 @@ struct NearArgs {
     GaussRule g{}, gp{};                 // the Q-point rule and the 12-point panel rule
     double *key = nullptr;               // [ns][4]
     float4 *sph = nullptr;               // [ceil(ns / NEAR_GROUP)] sphere centre, radius
-    int32_t *list = nullptr;             // [ns][splits][NEAR_CAP]
-    int32_t *scnt = nullptr;             // [ns][splits] kept per split
-    int32_t *cnt = nullptr, *loc = nullptr, *ptr = nullptr;   // [ns] each
-    int32_t *wtot = nullptr, *woff = nullptr;                 // [n_waves], [n_waves + 1]
+    int32_t *scnt = nullptr;             // [ns][splits] near sources per split
+    int32_t *cnt = nullptr;              // [ns] near sources per target
+    int64_t *loc = nullptr, *ptr = nullptr;                   // [ns] each: in-wavefront prefix, first slot
+    int64_t *wtot = nullptr, *woff = nullptr;                 // [n_waves], [n_waves + 1] (woff[n_waves] = total)
     int32_t *pair_t = nullptr, *pair_s = nullptr;             // [pair_cap] each
     double *corr = nullptr;                                   // [pair_cap][6]
     unsigned *flags = nullptr;
 };
-void launch_near(const NearArgs &A, hipStream_t st);
-// 2 eta^2 of the current exact band (0: off)
-double exact_band_c2();
+// Keys, counts and the scan (woff[n_waves] then holds the number of near
+// pairs), then, once the pair arrays hold at least that many entries, the
+// fill pass and the exact integrals.  Pairs beyond pair_cap are dropped (they
+// keep the Q-point rule) and FLAG_NEAR_FULL is raised.
+void launch_near_count(const NearArgs &A, hipStream_t st);
+void launch_near_fill(const NearArgs &A, hipStream_t st);
 
 // Glide steps of a batch of independent volumes in which only some instances
 // advance (the PTA driver's fast runs): burst_batch_init uploads the instance
@@ -215,7 +235,7 @@ struct BurstBatch {
     const uint8_t *pinned = nullptr;
     dd_material mat{};
     int n_gauss = 2, precision = DD_FP64;
-    double near_cut = 20.0, dt = 0.0;
+    double near_cut = 20.0, eta = 0.0, dt = 0.0;
     int64_t choice = 0;                       // encoded work split, set by burst_batch_init
     // junctions (null: none): the caller's parameters and state, and per
     // instance the fast steps taken so far (device), whose product with dt is

@@ -298,7 +298,7 @@ __global__ void k_segment_ends(Layout L, const Tile *__restrict__ tiles,
                                const double *__restrict__ rec, GaussRule g,
                                const double *__restrict__ sig_dev, Sig6 sig_val,
                                double inv_mu, double fscale, double *__restrict__ segF,
-                               const int32_t *__restrict__ near_ptr, const int32_t *__restrict__ near_cnt,
+                               const int64_t *__restrict__ near_ptr, const int32_t *__restrict__ near_cnt,
                                const double *__restrict__ near_corr, int64_t pair_cap)
 {
     int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -804,21 +804,34 @@ int check_material(const dd_material *m, bool need_B)
     return DD_OK;
 }
 
+}  // namespace
+
+// The flags word is sticky: kernels OR into it and only a report clears it,
+// so a condition raised by a call made with validation off is reported by the
+// next call that validates (or by dd_check).
 int read_flags(Workspace *ws, hipStream_t st)
 {
     DD_HIP(hipMemcpyAsync(ws->flags_host, ws->flags_dev, sizeof(unsigned), hipMemcpyDeviceToHost, st));
     DD_HIP(hipStreamSynchronize(st));
-    unsigned f = *ws->flags_host;
-    if (f & FLAG_BAD_INDEX) return set_error(DD_EINVAL, "a segment references a node index outside its instance");
-    if (f & FLAG_ZERO_LENGTH) return set_error(DD_EINVAL, "zero-length (or non-finite) segment");
-    if (f & FLAG_BAD_NORMAL) return set_error(DD_EINVAL, "slip-plane normal is not of unit length");
-    if (f & FLAG_NONFINITE) return set_error(DD_ENONFINITE, "non-finite value in an output");
+    const unsigned f = *ws->flags_host;
+    if (!f) return DD_OK;
+    *ws->flags_host = 0u;
+    DD_HIP(hipMemcpyAsync(ws->flags_dev, ws->flags_host, sizeof(unsigned), hipMemcpyHostToDevice, st));
+    DD_HIP(hipStreamSynchronize(st));
+    const char *w = " (this call or an earlier one made with validation off)";
+    if (f & FLAG_BAD_INDEX)
+        return set_error(DD_EINVAL, "a segment references a node index outside its instance%s", w);
+    if (f & FLAG_ZERO_LENGTH) return set_error(DD_EINVAL, "zero-length (or non-finite) segment%s", w);
+    if (f & FLAG_BAD_NORMAL) return set_error(DD_EINVAL, "slip-plane normal is not of unit length%s", w);
+    if (f & FLAG_NONFINITE) return set_error(DD_ENONFINITE, "non-finite value in an output%s", w);
     if (f & FLAG_NEAR_FULL)
-        return set_error(DD_ECAPACITY, "exact band: more than %d near sources for one segment, or more than %d "
-                         "per segment on average; use a narrower band", NEAR_CAP, NEAR_AVG);
-    if (f & FLAG_NEAR_PANELS) return set_error(DD_EINVAL, "exact band: a pair integral did not converge");
+        return set_error(DD_ECAPACITY, "exact band: the near pairs of a captured step outgrew the pair store "
+                         "sized at the start of the burst%s", w);
+    if (f & FLAG_NEAR_PANELS) return set_error(DD_EINVAL, "exact band: a pair integral did not converge%s", w);
     return DD_OK;
 }
+
+namespace {
 
 // Work decomposition for a set of instances (host tables).
 struct Plan {
@@ -827,6 +840,23 @@ struct Plan {
     std::vector<int64_t> tile_begin;   // [n_inst+1]
     int64_t chunk_len = 0;
 };
+
+// Source-range length of a work item when none is given: at least about 2048
+// work items; source ranges of at least MIN_CHUNK_LEN sources (small problems
+// spread over many CUs), in whole TILEs above that, and no longer than
+// max(512, N_max / 16): the largest items set the tail of the schedule, and
+// splitting them further costs only partial sums (on many bursts or one very
+// large volume this is 7-12 % faster than one range per tile).
+int64_t heuristic_chunk(int64_t total_tiles, int64_t max_src)
+{
+    const int64_t want_items = 2048, MIN_CHUNK = MIN_CHUNK_LEN;
+    int64_t chunks = total_tiles > 0 ? (want_items + total_tiles - 1) / total_tiles : 1;
+    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, (max_src + MIN_CHUNK - 1) / MIN_CHUNK));
+    int64_t chunk_len = (max_src + chunks - 1) / chunks;
+    chunk_len = std::min<int64_t>(chunk_len, std::max<int64_t>(512, (max_src + 15) / 16));
+    const int64_t gran = chunk_len > TILE ? TILE : MIN_CHUNK;
+    return std::max<int64_t>(MIN_CHUNK, (chunk_len + gran - 1) / gran * gran);
+}
 
 // chunk_len <= 0: choose so that a single large volume fills the chip.
 void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Plan &P,
@@ -844,19 +874,7 @@ void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Pl
             total_tiles += (N * Q + TILE - 1) / TILE;
             max_src = std::max(max_src, N);
         }
-        // at least about 2048 work items; source ranges of at least MIN_CHUNK
-        // sources (small problems spread over many CUs), in whole TILEs above
-        // that, and no longer than max(512, N_max / 16): the largest items set
-        // the tail of the schedule, and splitting them further costs only
-        // partial sums (on many bursts or one very large volume this is 7-12 %
-        // faster than one range per tile)
-        const int64_t want_items = 2048, MIN_CHUNK = MIN_CHUNK_LEN;
-        int64_t chunks = total_tiles > 0 ? (want_items + total_tiles - 1) / total_tiles : 1;
-        chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, (max_src + MIN_CHUNK - 1) / MIN_CHUNK));
-        chunk_len = (max_src + chunks - 1) / chunks;
-        chunk_len = std::min<int64_t>(chunk_len, std::max<int64_t>(512, (max_src + 15) / 16));
-        const int64_t gran = chunk_len > TILE ? TILE : MIN_CHUNK;
-        chunk_len = std::max<int64_t>(MIN_CHUNK, (chunk_len + gran - 1) / gran * gran);
+        chunk_len = heuristic_chunk(total_tiles, max_src);
     }
     P.chunk_len = chunk_len;
     int64_t slot = 0;
@@ -927,7 +945,7 @@ struct ForceCtx {
     int variant = 0;   // mixed kernel: 0 = FP32 quadrature band test first, 1 = no quadrature
     float cut = 0.f;
     bool near_on = false;   // exact band in use (positions, topology and layout are set per launch)
-    NearArgs near{};
+    NearArgs near{};        // pair store (pair_t, pair_s, corr, pair_cap) sized by size_near_pairs
 };
 
 // Cache of the last uploaded plan (the tables depend only on sizes).
@@ -949,7 +967,7 @@ int g_last_variant = 0;
 
 int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, int64_t nn,
           const int32_t *seg_nodes, const dd_material *m, int n_gauss, int precision,
-          double near_cut, int64_t chunk_len, bool need_sys, ForceCtx &C,
+          double near_cut, double eta, int64_t chunk_len, bool need_sys, ForceCtx &C,
           const std::vector<uint8_t> *active = nullptr)
 {
     const int64_t ns = seg_off_h.back();
@@ -1016,17 +1034,16 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
         return rc;
     C.partial = (double *)p;
     (void)seg_nodes;
-    const double c2 = exact_band_c2();
+    const double c2 = 2.0 * eta * eta;
     C.near_on = c2 > 0.0 && ns > 0;
     if (C.near_on) {
-        if (ns > (int64_t)INT32_MAX / NEAR_CAP)
-            return set_error(DD_EINVAL, "the exact band supports at most %d segments", INT32_MAX / NEAR_CAP);
+        if (ns > (int64_t)INT32_MAX)
+            return set_error(DD_EINVAL, "the exact band supports at most %d segments", INT32_MAX);
         NearArgs &N = C.near;
         N = NearArgs{};
         N.ns = ns;
         N.nn = nn;
         N.n_waves = (ns + 63) / 64;
-        N.pair_cap = ns * NEAR_AVG;
         N.c2 = c2;
         N.kr = C.k1 / C.k2;
         N.nu = m->nu;
@@ -1047,23 +1064,66 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
         const int64_t groups = (max_inst + NEAR_GROUP - 1) / NEAR_GROUP;
         const int64_t want = std::min<int64_t>((groups + 63) / 64, (262144 + ns - 1) / ns);
         N.splits = (int)std::min<int64_t>(32, std::max<int64_t>(1, want));
-        if ((rc = ensure(ws, WS_NEAR_LIST, sizeof(int32_t) * NEAR_CAP * N.splits * ns, &p))) return rc;
-        N.list = (int32_t *)p;
-        if ((rc = ensure(ws, WS_NEAR_IDX, sizeof(int32_t) * (3 + N.splits) * ns, &p))) return rc;
+        // counts: scnt [ns][splits] and cnt [ns] (int32), then loc and ptr [ns] (int64)
+        if ((rc = ensure(ws, WS_NEAR_IDX, sizeof(int32_t) * (1 + N.splits) * ns + 2 * sizeof(int64_t) * ns + 16, &p)))
+            return rc;
         N.cnt = (int32_t *)p;
-        N.loc = N.cnt + ns;
+        N.scnt = N.cnt + ns;
+        N.loc = (int64_t *)(((uintptr_t)(N.scnt + (int64_t)N.splits * ns) + 15) & ~(uintptr_t)15);
         N.ptr = N.loc + ns;
-        N.scnt = N.ptr + ns;
-        if ((rc = ensure(ws, WS_NEAR_WAVE, sizeof(int32_t) * (2 * N.n_waves + 1), &p))) return rc;
-        N.wtot = (int32_t *)p;
+        if ((rc = ensure(ws, WS_NEAR_WAVE, sizeof(int64_t) * (2 * N.n_waves + 1), &p))) return rc;
+        N.wtot = (int64_t *)p;
         N.woff = N.wtot + N.n_waves;
-        if ((rc = ensure(ws, WS_NEAR_PAIR, sizeof(int32_t) * 2 * N.pair_cap, &p))) return rc;
-        N.pair_t = (int32_t *)p;
+        // the pair store as it stands (grown by size_near_pairs)
+        N.pair_cap = (int64_t)std::min(ws->cap[WS_NEAR_PAIR] / (2 * sizeof(int32_t)),
+                                       ws->cap[WS_NEAR_CORR] / (6 * sizeof(double)));
+        N.pair_t = (int32_t *)ws->ptr[WS_NEAR_PAIR];
         N.pair_s = N.pair_t + N.pair_cap;
-        if ((rc = ensure(ws, WS_NEAR_CORR, sizeof(double) * 6 * N.pair_cap, &p))) return rc;
-        N.corr = (double *)p;
+        N.corr = (double *)ws->ptr[WS_NEAR_CORR];
     }
     return DD_OK;
+}
+
+// Makes the near-pair store hold at least `need` pairs (synchronises the
+// device when it grows) and points C.near at it.
+int grow_near_pairs(ForceCtx &C, Workspace *ws, int64_t need)
+{
+    NearArgs &N = C.near;
+    if (need <= N.pair_cap && N.pair_t) return DD_OK;
+    const int64_t cap = std::max<int64_t>(need, 1024);
+    void *p;
+    int rc;
+    if ((rc = ensure(ws, WS_NEAR_PAIR, sizeof(int32_t) * 2 * cap, &p))) return rc;
+    N.pair_t = (int32_t *)p;
+    N.pair_s = N.pair_t + cap;
+    if ((rc = ensure(ws, WS_NEAR_CORR, sizeof(double) * 6 * cap, &p))) return rc;
+    N.corr = (double *)p;
+    N.pair_cap = cap;
+    return DD_OK;
+}
+
+// Counts the near pairs at positions x (the count pass and its scan), reads
+// the total back (synchronising the stream) and grows the pair store to
+// `factor` times it plus `extra` per segment.
+int size_near_pairs(ForceCtx &C, Workspace *ws, const double *x, const int32_t *seg_nodes, double factor,
+                    int64_t extra, hipStream_t st)
+{
+    NearArgs N = C.near;
+    N.x = x;
+    N.seg_nodes = seg_nodes;
+    N.seg_inst = C.L.seg_inst;
+    N.seg_off = C.L.seg_off;
+    N.node_off = C.L.node_off;
+    launch_near_count(N, st);
+    int64_t *host = (int64_t *)((char *)ws->flags_host + 64);
+    DD_HIP(hipMemcpyAsync(host, N.woff + N.n_waves, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    DD_HIP(hipStreamSynchronize(st));
+    const int64_t total = *host;
+    if (total < 0 || total > (int64_t)INT32_MAX)
+        return set_error(DD_ECAPACITY, "exact band: %lld near pairs (at most %d); use a narrower band",
+                         (long long)total, INT32_MAX);
+    return grow_near_pairs(C, ws, std::min<int64_t>((int64_t)INT32_MAX,
+                                                    (int64_t)(factor * (double)total) + extra * C.L.ns));
 }
 
 // Topology-only work: CSR of node -> (segment, end).
@@ -1082,9 +1142,12 @@ void launch_csr(const ForceCtx &C, const int32_t *seg_nodes, hipStream_t st)
 }
 
 // a1..a4 for positions x: segment records, pair kernel, epilogue, gather.
-void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int32_t *seg_nodes,
-                   const double *burgers, const double *normal, const double *sig_dev, Sig6 sig_val,
-                   double *F, hipStream_t st)
+// With the exact band, size_pairs = true counts the near pairs first, reads
+// the count back (one synchronisation) and sizes the pair store to fit;
+// false (graph capture) uses the store as sized beforehand.
+int launch_forces(ForceCtx &C, Workspace *ws, const double *x, const int32_t *seg_nodes,
+                  const double *burgers, const double *normal, const double *sig_dev, Sig6 sig_val,
+                  double *F, hipStream_t st, bool size_pairs)
 {
     const int64_t nn = C.L.nn, ns = C.L.ns;
     if (ns > 0) {
@@ -1106,13 +1169,18 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
             // the near-pair work needs only the records; it runs before the
             // pair kernel on the same stream (alongside it, it slowed the pair
             // kernel by more than its own duration)
+            if (size_pairs) {
+                const int rc = size_near_pairs(C, ws, x, seg_nodes, 1.0, 0, st);
+                if (rc) return rc;
+            }
             NearArgs N = C.near;
             N.x = x;
             N.seg_nodes = seg_nodes;
             N.seg_inst = C.L.seg_inst;
             N.seg_off = C.L.seg_off;
             N.node_off = C.L.node_off;
-            launch_near(N, st);
+            if (!size_pairs) launch_near_count(N, st);
+            launch_near_fill(N, st);
         }
         if (C.n_items > 0) {
             timing_begin(st, ws->capturing);
@@ -1125,11 +1193,12 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
         }
         hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
                            C.tiles, C.partial, C.rec64, C.g, sig_dev, sig_val, C.inv_mu, C.fscale,
-                           C.segF, C.near_on ? (const int32_t *)C.near.ptr : nullptr,
+                           C.segF, C.near_on ? (const int64_t *)C.near.ptr : nullptr,
                            (const int32_t *)C.near.cnt, (const double *)C.near.corr, C.near.pair_cap);
     }
     hipLaunchKernelGGL(k_node_gather, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, st, C.csr_ptr,
                        C.csr_list, nn, ns, C.segF, F);
+    return DD_OK;
 }
 
 // ------------------------------------------------------------- autotuner --
@@ -1144,7 +1213,6 @@ void launch_forces(const ForceCtx &C, Workspace *ws, const double *x, const int3
 // caller's own data, and the fastest is kept for the process (and appended
 // to the file named by DD_AUTOTUNE_CACHE, read back at start-up).
 std::atomic<int> g_autotune{1};
-std::atomic<double> g_exact_c2{0.0};   // dd_set_exact_band: 2 eta^2
 std::atomic<int64_t> g_forced_choice{-1};   // dd_set_plan: encoded split, or -1
 
 struct TuneKey {
@@ -1242,7 +1310,7 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
     for (int64_t cv : cands) {
         const int64_t c = cv / MIXED_VARIANTS;
         ForceCtx C;
-        if ((rc = setup(ws, st, so, nn, seg_nodes, m, Q, prec, cut, c, need_sys, C))) break;
+        if ((rc = setup(ws, st, so, nn, seg_nodes, m, Q, prec, cut, 0.0, c, need_sys, C))) break;
         C.variant = (int)(cv % MIXED_VARIANTS);
         PrepArgs A{};
         A.L = C.L;
@@ -1272,7 +1340,7 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
             // items, so it is part of the cost being compared
             hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, A.L,
                                C.tiles, C.partial, C.rec64, C.g, (const double *)nullptr, Sig6{}, C.inv_mu,
-                               C.fscale, C.segF, (const int32_t *)nullptr, (const int32_t *)nullptr,
+                               C.fscale, C.segF, (const int64_t *)nullptr, (const int32_t *)nullptr,
                                (const double *)nullptr, (int64_t)0);
             (void)hipEventRecord(e1, st);
             if (hipEventSynchronize(e1) != hipSuccess) {
@@ -1298,8 +1366,9 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
     return DD_OK;
 }
 
-int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, double near_cut)
+int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, double near_cut, double eta = 0.0)
 {
+    if (!(eta >= 0.0) || std::isinf(eta)) return set_error(DD_EINVAL, "exact_eta must be finite and >= 0");
     if (n_nodes < 0 || n_segs < 0) return set_error(DD_EINVAL, "negative node or segment count");
     if (n_nodes >= INT32_MAX || 2 * n_segs >= INT32_MAX)
         return set_error(DD_EINVAL, "more than 2^31 nodes or 2^30 segments");
@@ -1312,31 +1381,126 @@ int common_checks(int64_t n_nodes, int64_t n_segs, int n_gauss, int precision, d
     return DD_OK;
 }
 
-}  // namespace
+// ------------------------------------------------------- instance tables --
+// Segment -> instance and the device copies of the offsets, uploaded only
+// when the offsets differ from the last upload (an upload synchronises).
+int instance_tables(Workspace *ws, const std::vector<int64_t> &no, const std::vector<int64_t> &so, Layout &inst,
+                    hipStream_t st)
+{
+    const int n_inst = (int)so.size() - 1;
+    const int64_t ns = so.back();
+    std::vector<int64_t> key(no);
+    key.insert(key.end(), so.begin(), so.end());
+    int rc;
+    if (key != ws->inst_key || !ws->ptr[WS_SEG_INST] || !ws->ptr[WS_INST_OFFS]) {
+        std::vector<int32_t> si((size_t)std::max<int64_t>(ns, 1), 0);
+        for (int i = 0; i < n_inst; ++i)
+            for (int64_t s = so[i]; s < so[i + 1]; ++s) si[s] = i;
+        int32_t *d_si;
+        if ((rc = upload(ws, WS_SEG_INST, si, &d_si, st))) return rc;
+        int64_t *d_offs;
+        if ((rc = upload(ws, WS_INST_OFFS, key, &d_offs, st))) return rc;
+        ws->inst_key = key;
+    }
+    inst.seg_inst = (const int32_t *)ws->ptr[WS_SEG_INST];
+    inst.node_off = (const int64_t *)ws->ptr[WS_INST_OFFS];
+    inst.seg_off = inst.node_off + (n_inst + 1);
+    return DD_OK;
+}
 
-double exact_band_c2() { return g_exact_c2.load(); }
+// ------------------------------------------------------------ step graphs --
+struct KeyBuf {
+    std::vector<unsigned char> b;
+    template <class T>
+    KeyBuf &add(const T &v)
+    {
+        const unsigned char *p = reinterpret_cast<const unsigned char *>(&v);
+        b.insert(b.end(), p, p + sizeof(T));
+        return *this;
+    }
+    template <class T>
+    KeyBuf &add_vec(const std::vector<T> &v)
+    {
+        add(v.size());
+        const unsigned char *p = reinterpret_cast<const unsigned char *>(v.data());
+        b.insert(b.end(), p, p + v.size() * sizeof(T));
+        return *this;
+    }
+    // every workspace address a captured kernel can be handed
+    KeyBuf &add_workspace(const Workspace *ws)
+    {
+        for (int s = 0; s < WS_NSLOTS; ++s) add(ws->ptr[s]);
+        return add(ws->flags_dev);
+    }
+};
+
+// Launches on st the graph cached under `key`, or records one with
+// record(capture_stream), instantiates it, caches it and launches it.  No
+// synchronisation unless a cached graph has to be evicted.
+template <class F>
+int launch_cached_graph(Workspace *ws, const KeyBuf &key, F &&record, hipStream_t st)
+{
+    for (auto &g : ws->graphs)
+        if (g.key == key.b) {
+            g.last_use = ++ws->graph_clock;
+            DD_HIP(hipGraphLaunch(g.exec, st));
+            return DD_OK;
+        }
+    if (!ws->capture_stream) DD_HIP(hipStreamCreateWithFlags(&ws->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = ws->capture_stream;
+    DD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    ws->capturing = true;
+    const int rc = record(cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    ws->capturing = false;
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return set_error(DD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return set_error(DD_EHIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+    if (ws->graphs.size() >= GRAPH_CACHE) {
+        size_t lru = 0;
+        for (size_t k = 1; k < ws->graphs.size(); ++k)
+            if (ws->graphs[k].last_use < ws->graphs[lru].last_use) lru = k;
+        DD_HIP(hipDeviceSynchronize());   // it may still be running
+        (void)hipGraphExecDestroy(ws->graphs[lru].exec);
+        ws->graphs.erase(ws->graphs.begin() + (std::ptrdiff_t)lru);
+    }
+    ws->graphs.push_back(GraphEntry{key.b, exec, ++ws->graph_clock});
+    DD_HIP(hipGraphLaunch(exec, st));
+    return DD_OK;
+}
+
+// Before a captured burst with the exact band: a pair store of twice the
+// current near-pair count plus 8 per segment (count pass, one
+// synchronisation).  Done whenever validation is on (the call synchronises
+// anyway) and, with validation off, only while the store is still empty, so
+// that repeated asynchronous calls stay asynchronous; a step whose pairs
+// outgrow the store raises FLAG_NEAR_FULL.
+int presize_near(ForceCtx &C, Workspace *ws, const double *x, const int32_t *seg_nodes, hipStream_t st)
+{
+    if (!C.near_on) return DD_OK;
+    if (!validation_on() && C.near.pair_t) return DD_OK;
+    return size_near_pairs(C, ws, x, seg_nodes, 2.0, 8, st);
+}
+
+}  // namespace
 
 // ------------------------------------------------ bursts of an active subset --
 int burst_batch_init(BurstBatch &B, hipStream_t st)
 {
     int rc;
     const int n_inst = B.n_inst;
-    const int64_t nn = B.node_off[n_inst], ns = B.seg_off[n_inst];
+    const int64_t nn = B.node_off[n_inst];
     Workspace *ws;
     if ((rc = workspace(&ws))) return rc;
-    std::vector<int32_t> si((size_t)std::max<int64_t>(ns, 1), 0);
-    for (int i = 0; i < n_inst; ++i)
-        for (int64_t s = B.seg_off[i]; s < B.seg_off[i + 1]; ++s) si[s] = i;
-    int32_t *d_si;
-    if ((rc = upload(ws, WS_SEG_INST, si, &d_si, st))) return rc;
-    std::vector<int64_t> offs(B.node_off);
-    offs.insert(offs.end(), B.seg_off.begin(), B.seg_off.end());
-    int64_t *d_offs;
-    if ((rc = upload(ws, WS_INST_OFFS, offs, &d_offs, st))) return rc;
     Layout inst{};
-    inst.seg_inst = d_si;
-    inst.node_off = d_offs;
-    inst.seg_off = d_offs + (n_inst + 1);
+    if ((rc = instance_tables(ws, B.node_off, B.seg_off, inst, st))) return rc;
     return tuned_chunk(ws, st, B.seg_off, nn, inst, B.seg_nodes, B.x, B.burgers, B.normal, &B.mat, B.n_gauss,
                        B.precision, B.near_cut, true, &B.choice);
 }
@@ -1353,15 +1517,17 @@ int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, con
     if (!any) return DD_OK;
     Workspace *ws;
     if ((rc = workspace(&ws))) return rc;
+    Layout inst{};
+    if ((rc = instance_tables(ws, B.node_off, B.seg_off, inst, st))) return rc;
     ForceCtx C;
-    if ((rc = setup(ws, st, B.seg_off, nn, B.seg_nodes, &B.mat, B.n_gauss, B.precision, B.near_cut,
+    if ((rc = setup(ws, st, B.seg_off, nn, B.seg_nodes, &B.mat, B.n_gauss, B.precision, B.near_cut, B.eta,
                     B.choice / MIXED_VARIANTS, true, C, &active)))
         return rc;
     C.variant = (int)(B.choice % MIXED_VARIANTS);
     g_last_variant = C.variant;
-    C.L.seg_inst = (const int32_t *)ws->ptr[WS_SEG_INST];
-    C.L.node_off = (const int64_t *)ws->ptr[WS_INST_OFFS];
-    C.L.seg_off = C.L.node_off + (n_inst + 1);
+    C.L.seg_inst = inst.seg_inst;
+    C.L.node_off = inst.node_off;
+    C.L.seg_off = inst.seg_off;
     uint8_t *d_act;
     if ((rc = upload(ws, WS_ACTIVE, active, &d_act, st))) return rc;
     void *p;
@@ -1373,40 +1539,33 @@ int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, con
     uint8_t *held = nullptr;
     JunctionArgs J{};
     if (B.jn && (rc = junction_prepare(ws, C.L, B.seg_nodes, B.x, B.pinned, B.jn, J, &held, st))) return rc;
+    if ((rc = presize_near(C, ws, B.x, B.seg_nodes, st))) return rc;
     DD_HIP(hipGetLastError());
-    if (!ws->capture_stream) DD_HIP(hipStreamCreateWithFlags(&ws->capture_stream, hipStreamNonBlocking));
-    hipStream_t cs = ws->capture_stream;   // records the steps; the graph then runs on st
-    DD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    ws->capturing = true;
+    KeyBuf key;
+    key.add('r').add(n_inst).add_vec(B.node_off).add_vec(B.seg_off).add_vec(active).add(B.x).add(B.seg_nodes);
+    key.add(B.burgers).add(B.normal).add(B.volume).add(B.pinned).add(B.mat).add(B.n_gauss).add(B.precision);
+    key.add(B.near_cut).add(B.eta).add(B.dt).add(B.choice).add(sigma_dev).add(sums_dev).add(n_steps);
+    key.add(B.jn != nullptr).add(B.fast_steps_dev).add(C.near.pair_cap).add_workspace(ws);
+    if (B.jn) key.add(*B.jn);
     const Sig6 sv{};
-    for (int k = 0; k < n_steps; ++k) {
-        if (B.jn)
-            hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L, B.seg_nodes,
-                               (const double *)B.x, B.pinned, J, n_inst, (const uint8_t *)d_act, B.fast_steps_dev,
-                               B.dt, k, held);
-        launch_forces(C, ws, B.x, B.seg_nodes, B.burgers, B.normal, sigma_dev, sv, F, cs);
-        hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L, C.csr_ptr,
-                           C.csr_list, B.seg_nodes, B.normal, C.rec64, C.a, B.x, F, B.pinned,
-                           (const uint8_t *)held, (const uint8_t *)d_act, 1.0 / B.mat.B, B.dt, vel);
-        hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 2, B.seg_nodes, C.rec64, C.sys,
-                           vel, B.pinned, B.volume, sigma_dev, C.a, sums_dev);
-    }
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(cs, &graph);
-    ws->capturing = false;
-    if (e != hipSuccess) return set_error(DD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return set_error(DD_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
-    }
-    e = hipGraphLaunch(exec, st);
-    hipError_t e2 = hipStreamSynchronize(st);
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return set_error(DD_EHIP, "graph launch failed: %s", hipGetErrorString(e));
-    if (e2 != hipSuccess) return set_error(DD_EHIP, "burst execution failed: %s", hipGetErrorString(e2));
+    rc = launch_cached_graph(ws, key, [&](hipStream_t cs) -> int {
+        for (int k = 0; k < n_steps; ++k) {
+            if (B.jn)
+                hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
+                                   B.seg_nodes, (const double *)B.x, B.pinned, J, n_inst, (const uint8_t *)d_act,
+                                   B.fast_steps_dev, B.dt, k, held);
+            const int r = launch_forces(C, ws, B.x, B.seg_nodes, B.burgers, B.normal, sigma_dev, sv, F, cs, false);
+            if (r) return r;
+            hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
+                               C.csr_ptr, C.csr_list, B.seg_nodes, B.normal, C.rec64, C.a, B.x, F, B.pinned,
+                               (const uint8_t *)held, (const uint8_t *)d_act, 1.0 / B.mat.B, B.dt, vel);
+            hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 2, B.seg_nodes, C.rec64,
+                               C.sys, vel, B.pinned, B.volume, sigma_dev, C.a, sums_dev);
+        }
+        return DD_OK;
+    }, st);
+    if (rc) return rc;
+    DD_HIP(hipGetLastError());
     return DD_OK;
 }
 
@@ -1416,12 +1575,13 @@ using namespace dd;
 
 extern "C" int dd_set_autotune(int on) { return dd::g_autotune.exchange(on ? 1 : 0); }
 
-extern "C" int dd_set_exact_band(double eta)
+extern "C" int dd_check(void *stream)
 {
-    dd::clear_error();
-    if (!(eta >= 0.0) || std::isinf(eta)) return dd::set_error(DD_EINVAL, "eta must be finite and >= 0");
-    dd::g_exact_c2.store(2.0 * eta * eta);
-    return DD_OK;
+    clear_error();
+    Workspace *ws;
+    int rc;
+    if ((rc = workspace(&ws))) return rc;
+    return read_flags(ws, (hipStream_t)stream);
 }
 
 extern "C" int dd_set_plan(int64_t chunk_len, int variant)
@@ -1450,11 +1610,11 @@ extern "C" int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
                                const int32_t *seg_nodes, const double *burgers,
                                const double *normal, const double *sigma_app,
                                const dd_material *m, int n_gauss, int precision,
-                               double near_cutoff_a, double *force_out, void *stream)
+                               double near_cutoff_a, double exact_eta, double *force_out, void *stream)
 {
     clear_error();
     int rc;
-    if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a))) return rc;
+    if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a, exact_eta))) return rc;
     if ((rc = check_material(m, false))) return rc;
     if (!sigma_app) return set_error(DD_EINVAL, "sigma_app is null");
     if (n_nodes > 0 && (!x || !force_out)) return set_error(DD_EINVAL, "null x or force_out");
@@ -1472,15 +1632,15 @@ extern "C" int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
     if ((rc = tuned_chunk(ws, st, so, n_nodes, flat, seg_nodes, x, burgers, normal, m, n_gauss, precision,
                           near_cutoff_a, false, &choice)))
         return rc;
-    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / MIXED_VARIANTS, false, C)))
+    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, exact_eta,
+                    choice / MIXED_VARIANTS, false, C)))
         return rc;
     C.variant = (int)(choice % MIXED_VARIANTS);
     g_last_variant = C.variant;
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
     launch_csr(C, seg_nodes, st);
     Sig6 sv;
     for (int k = 0; k < 6; ++k) sv.v[k] = sigma_app[k];
-    launch_forces(C, ws, x, seg_nodes, burgers, normal, nullptr, sv, force_out, st);
+    if ((rc = launch_forces(C, ws, x, seg_nodes, burgers, normal, nullptr, sv, force_out, st, true))) return rc;
     DD_HIP(hipGetLastError());
     if (validation_on()) {
         hipLaunchKernelGGL(k_check_finite, dim3(grid_for(3 * n_nodes)), dim3(256), 0, st, force_out,
@@ -1522,7 +1682,6 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
         if ((rc = ensure(ws, WS_VEL, sizeof(double) * 3 * n_nodes, &p))) return rc;
         vel = (double *)p;
     }
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
     launch_csr(C, seg_nodes, st);
     if (validation_on() && n_segs > 0) {
         // index and normal checks (the prep kernel also computes lengths)
@@ -1555,11 +1714,12 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
 extern "C" int dd_step(int64_t n_nodes, double *x, int64_t n_segs, const int32_t *seg_nodes,
                        const double *burgers, const double *normal, const uint8_t *pinned,
                        const double *sigma_app, const dd_material *m, int n_gauss, int precision,
-                       double near_cutoff_a, double dt, double *force_out, double *vel_out, void *stream)
+                       double near_cutoff_a, double exact_eta, double dt, double *force_out, double *vel_out,
+                       void *stream)
 {
     clear_error();
     int rc;
-    if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a))) return rc;
+    if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a, exact_eta))) return rc;
     if ((rc = check_material(m, true))) return rc;
     if (!sigma_app) return set_error(DD_EINVAL, "sigma_app is null");
     if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(DD_EINVAL, "dt must be > 0");
@@ -1578,8 +1738,8 @@ extern "C" int dd_step(int64_t n_nodes, double *x, int64_t n_segs, const int32_t
     if ((rc = tuned_chunk(ws, st, so, n_nodes, flat, seg_nodes, x, burgers, normal, m, n_gauss, precision,
                           near_cutoff_a, false, &choice)))
         return rc;
-    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / MIXED_VARIANTS,
-                    false, C)))
+    if ((rc = setup(ws, st, so, n_nodes, seg_nodes, m, n_gauss, precision, near_cutoff_a, exact_eta,
+                    choice / MIXED_VARIANTS, false, C)))
         return rc;
     C.variant = (int)(choice % MIXED_VARIANTS);
     g_last_variant = C.variant;
@@ -1593,11 +1753,10 @@ extern "C" int dd_step(int64_t n_nodes, double *x, int64_t n_segs, const int32_t
         if ((rc = ensure(ws, WS_VEL, sizeof(double) * 3 * n_nodes, &p))) return rc;
         vel = (double *)p;
     }
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
     launch_csr(C, seg_nodes, st);
     Sig6 sv;
     for (int k = 0; k < 6; ++k) sv.v[k] = sigma_app[k];
-    launch_forces(C, ws, x, seg_nodes, burgers, normal, nullptr, sv, F, st);
+    if ((rc = launch_forces(C, ws, x, seg_nodes, burgers, normal, nullptr, sv, F, st, true))) return rc;
     // lengths from the segment records of this force pass: x can move in the same kernel
     hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(n_nodes, 256, INT32_MAX)), dim3(256), 0, st, C.L, C.csr_ptr,
                        C.csr_list, seg_nodes, normal, (const double *)C.rec64, C.a, x, (const double *)F, pinned,
@@ -1618,8 +1777,8 @@ namespace {
 int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
                      const int32_t *seg_nodes, const double *burgers, const double *normal, const uint8_t *pinned,
                      const double *sigma_app, const double *volume, const dd_material *m, int n_gauss, int precision,
-                     double near_cutoff_a, int n_steps, double dt, const dd_junctions *jn, double *rate_avg_out,
-                     double *features_out, void *stream)
+                     double near_cutoff_a, double exact_eta, int n_steps, double dt, const dd_junctions *jn,
+                     double *rate_avg_out, double *features_out, void *stream)
 {
     int rc;
     if (n_inst < 0) return set_error(DD_EINVAL, "n_inst < 0");
@@ -1633,7 +1792,7 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
         if (seg_off[i + 1] > seg_off[i] && node_off[i + 1] == node_off[i])
             return set_error(DD_EINVAL, "instance %d has segments but no nodes", i);
     const int64_t nn = node_off[n_inst], ns = seg_off[n_inst];
-    if ((rc = common_checks(nn, ns, n_gauss, precision, near_cutoff_a))) return rc;
+    if ((rc = common_checks(nn, ns, n_gauss, precision, near_cutoff_a, exact_eta))) return rc;
     if ((rc = check_material(m, true))) return rc;
     if (n_steps < 0) return set_error(DD_EINVAL, "n_steps < 0");
     if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(DD_EINVAL, "dt must be > 0");
@@ -1653,27 +1812,15 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
     if ((rc = workspace(&ws))) return rc;
 
     std::vector<int64_t> so(seg_off, seg_off + n_inst + 1), no(node_off, node_off + n_inst + 1);
-    // instance tables: segment -> instance, node offsets then segment offsets
-    std::vector<int32_t> si((size_t)std::max<int64_t>(ns, 1), 0);
-    for (int i = 0; i < n_inst; ++i)
-        for (int64_t s = so[i]; s < so[i + 1]; ++s) si[s] = i;
-    int32_t *d_si;
-    if ((rc = upload(ws, WS_SEG_INST, si, &d_si, st))) return rc;
-    std::vector<int64_t> offs;
-    offs.insert(offs.end(), no.begin(), no.end());
-    offs.insert(offs.end(), so.begin(), so.end());
-    int64_t *d_offs;
-    if ((rc = upload(ws, WS_INST_OFFS, offs, &d_offs, st))) return rc;
     Layout inst{};
-    inst.seg_inst = d_si;
-    inst.node_off = d_offs;
-    inst.seg_off = d_offs + (n_inst + 1);
+    if ((rc = instance_tables(ws, no, so, inst, st))) return rc;
     ForceCtx C;
     int64_t choice = 0;
     if ((rc = tuned_chunk(ws, st, so, nn, inst, seg_nodes, x, burgers, normal, m, n_gauss, precision,
                           near_cutoff_a, true, &choice)))
         return rc;
-    if ((rc = setup(ws, st, so, nn, seg_nodes, m, n_gauss, precision, near_cutoff_a, choice / MIXED_VARIANTS, true, C)))
+    if ((rc = setup(ws, st, so, nn, seg_nodes, m, n_gauss, precision, near_cutoff_a, exact_eta,
+                    choice / MIXED_VARIANTS, true, C)))
         return rc;
     C.variant = (int)(choice % MIXED_VARIANTS);
     g_last_variant = C.variant;
@@ -1690,7 +1837,6 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
     JunctionArgs J{};
     if (jn && (rc = junction_prepare(ws, C.L, seg_nodes, x, pinned, jn, J, &held, st))) return rc;
 
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, ws->flags_dev, (int64_t)1, 0u);
     launch_csr(C, seg_nodes, st);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(12 * (int64_t)n_inst)), dim3(256), 0, st, rate_avg_out,
                        12 * (int64_t)n_inst, 0.0);
@@ -1720,41 +1866,33 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
     DD_HIP(hipGetLastError());
 
     if (n_steps > 0 && ns > 0) {
-        // capture the whole step loop once, launch it as one graph
-        if (!ws->capture_stream) DD_HIP(hipStreamCreateWithFlags(&ws->capture_stream, hipStreamNonBlocking));
-        hipStream_t cs = ws->capture_stream;
-        DD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        ws->capturing = true;
-        for (int k = 0; k < n_steps; ++k) {
-            if (jn) {
-                J.t = jn->t0 + k * dt;
-                hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L, seg_nodes,
-                                   (const double *)x, pinned, J, n_inst, (const uint8_t *)nullptr,
-                                   (const int64_t *)nullptr, dt, k, held);
+        if ((rc = presize_near(C, ws, x, seg_nodes, st))) return rc;
+        // the whole step loop as one graph, cached for calls with the same key
+        KeyBuf key;
+        key.add('b').add(n_inst).add_vec(no).add_vec(so).add(x).add(seg_nodes).add(burgers).add(normal);
+        key.add(pinned).add(sigma_app).add(volume).add(*m).add(n_gauss).add(precision).add(near_cutoff_a);
+        key.add(exact_eta).add(n_steps).add(dt).add(choice).add(rate_avg_out).add(jn != nullptr);
+        key.add(C.near.pair_cap).add_workspace(ws);
+        if (jn) key.add(*jn);
+        rc = launch_cached_graph(ws, key, [&](hipStream_t cs) -> int {
+            for (int k = 0; k < n_steps; ++k) {
+                if (jn) {
+                    J.t = jn->t0 + k * dt;
+                    hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
+                                       seg_nodes, (const double *)x, pinned, J, n_inst, (const uint8_t *)nullptr,
+                                       (const int64_t *)nullptr, dt, k, held);
+                }
+                const int r = launch_forces(C, ws, x, seg_nodes, burgers, normal, sigma_app, sv, F, cs, false);
+                if (r) return r;
+                hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
+                                   C.csr_ptr, C.csr_list, seg_nodes, normal, C.rec64, C.a, x, F, pinned,
+                                   (const uint8_t *)held, (const uint8_t *)nullptr, 1.0 / m->B, dt, vel);
+                hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 0, seg_nodes, C.rec64,
+                                   C.sys, vel, pinned, volume, sigma_app, C.a, rate_avg_out);
             }
-            launch_forces(C, ws, x, seg_nodes, burgers, normal, sigma_app, sv, F, cs);
-            hipLaunchKernelGGL(k_glide<true>, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
-                               C.csr_ptr, C.csr_list, seg_nodes, normal, C.rec64, C.a, x, F, pinned,
-                               (const uint8_t *)held, (const uint8_t *)nullptr, 1.0 / m->B, dt, vel);
-            hipLaunchKernelGGL(k_instance_sums, dim3(n_inst), dim3(256), 0, cs, C.L, 0, seg_nodes, C.rec64,
-                               C.sys, vel, pinned, volume, sigma_app, C.a, rate_avg_out);
-        }
-        hipGraph_t graph = nullptr;
-        hipError_t e = hipStreamEndCapture(cs, &graph);
-        ws->capturing = false;
-        if (e != hipSuccess) return set_error(DD_EHIP, "graph capture failed: %s", hipGetErrorString(e));
-        hipGraphExec_t exec = nullptr;
-        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(graph);
-            return set_error(DD_EHIP, "graph instantiation failed: %s", hipGetErrorString(e));
-        }
-        e = hipGraphLaunch(exec, st);
-        hipError_t e2 = hipStreamSynchronize(st);
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) return set_error(DD_EHIP, "graph launch failed: %s", hipGetErrorString(e));
-        if (e2 != hipSuccess) return set_error(DD_EHIP, "burst execution failed: %s", hipGetErrorString(e2));
+            return DD_OK;
+        }, st);
+        if (rc) return rc;
         hipLaunchKernelGGL(k_scale_rates, dim3(grid_for(12 * (int64_t)n_inst, 256, INT32_MAX)), dim3(256), 0,
                            st, rate_avg_out, 12 * (int64_t)n_inst, 1.0 / n_steps);
     }
@@ -1767,7 +1905,6 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
                                ws->flags_dev);
         return read_flags(ws, st);
     }
-    DD_HIP(hipStreamSynchronize(st));
     return DD_OK;
 }
 }  // namespace
@@ -1777,25 +1914,26 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
                               const int32_t *seg_nodes, const double *burgers, const double *normal,
                               const uint8_t *pinned, const double *sigma_app, const double *volume,
                               const dd_material *m, int n_gauss, int precision, double near_cutoff_a,
-                              int n_steps, double dt, double *rate_avg_out, double *features_out,
-                              void *stream)
+                              double exact_eta, int n_steps, double dt, double *rate_avg_out,
+                              double *features_out, void *stream)
 {
     clear_error();
     return burst_batch_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m,
-                            n_gauss, precision, near_cutoff_a, n_steps, dt, nullptr, rate_avg_out, features_out,
-                            stream);
+                            n_gauss, precision, near_cutoff_a, exact_eta, n_steps, dt, nullptr, rate_avg_out,
+                            features_out, stream);
 }
 
 extern "C" int dd_burst_batch_junctions(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
                                         const int32_t *seg_nodes, const double *burgers, const double *normal,
                                         const uint8_t *pinned, const double *sigma_app, const double *volume,
                                         const dd_material *m, int n_gauss, int precision, double near_cutoff_a,
-                                        int n_steps, double dt, const dd_junctions *junctions, double *rate_avg_out,
-                                        double *features_out, void *stream)
+                                        double exact_eta, int n_steps, double dt, const dd_junctions *junctions,
+                                        double *rate_avg_out, double *features_out, void *stream)
 {
     clear_error();
     if (!junctions) return set_error(DD_EINVAL, "null junction parameters");
     return burst_batch_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m,
-                            n_gauss, precision, near_cutoff_a, n_steps, dt, junctions, rate_avg_out, features_out,
-                            stream);
+                            n_gauss, precision, near_cutoff_a, exact_eta, n_steps, dt, junctions, rate_avg_out,
+                            features_out, stream);
 }
+

@@ -9,13 +9,17 @@
 //   k_near_keys     per segment its key (x1 + x2, |x2 - x1|^2, physical
 //                   units), per NEAR_GROUP consecutive segments a bounding
 //                   sphere;
-//   k_near_list     one thread per target and source split: source groups
+//   k_near_list<0>  one thread per target and source split: source groups
 //                   whose sphere can hold a near pair are scanned and every
-//                   target keeps its near sources in increasing index order;
-//   k_near_count    per-target totals over the splits (at most NEAR_CAP) and
-//                   per-wavefront totals;
-//   k_scan          prefix of the per-wavefront totals;
-//   k_near_compact  one flat array of (target, source) pairs;
+//                   target counts its near sources per split;
+//   k_near_count    per-target totals over the splits, their prefix within
+//                   the wavefront and per-wavefront totals;
+//   k_scan          prefix of the per-wavefront totals: every target's first
+//                   slot in one flat array of (target, source) pairs, and the
+//                   total, from which the caller sizes that array;
+//   k_near_list<1>  the same search again, each split writing its sources in
+//                   increasing index order straight into the target's slots
+//                   (pairs past the array's capacity are dropped and flagged);
 //   k_near_exact    four lanes per pair: the exact integral on panels graded
 //                   towards the integrand's complex singularities, minus the
 //                   Q-point rule, as two end-force vectors.
@@ -145,8 +149,12 @@ __global__ __launch_bounds__(256) void k_near_keys(NearArgs A)
 // NEAR_CHUNK groups at a time; each target tests its own key against each
 // sphere in FP32 (widened as above by 4e-6 of its magnitudes) and, for the
 // groups some lane of the wavefront hits, the FP64 near rule decides source
-// by source.  Each split keeps its own list per target, in increasing source
-// order.
+// by source.  FILL = 0 counts each split's near sources (scnt); FILL = 1
+// repeats the same search and writes them, in increasing source order, to
+// the target's slots of the flat pair arrays: slot woff[wave] + loc[j] plus
+// the counts of the splits before this one.  Split 0 also records the
+// target's first slot (ptr).
+template <int FILL>
 __global__ __launch_bounds__(256) void k_near_list(NearArgs A)
 {
     __shared__ float4 sh[NEAR_CHUNK];
@@ -170,6 +178,13 @@ __global__ __launch_bounds__(256) void k_near_list(NearArgs A)
         const double r = sqrt(A.c2 * kj[3]);
         rj = (float)(r + 4e-6 * (fabs(kj[0]) + fabs(kj[1]) + fabs(kj[2]) + r));
     }
+    // first slot of this split's sources (fill pass)
+    int64_t slot = 0;
+    if (FILL && live) {
+        slot = A.woff[j >> 6] + A.loc[j];
+        if (split == 0) A.ptr[j] = slot;
+        for (int s2 = 0; s2 < split; ++s2) slot += A.scnt[j * S + s2];
+    }
     // source groups of every instance this workgroup's targets belong to
     const long long glo = wave_min(live ? (long long)(sb / NEAR_GROUP) : (long long)INT64_MAX);
     const long long ghi = wave_max(live ? (long long)((se - 1) / NEAR_GROUP) : -1LL);
@@ -188,7 +203,7 @@ __global__ __launch_bounds__(256) void k_near_list(NearArgs A)
     const long long s_lo = g_lo + split * per;
     const long long s_hi = s_lo + per - 1 < g_hi ? s_lo + per - 1 : g_hi;
     int32_t cnt = 0;
-    int32_t *out = A.list + (j * S + split) * NEAR_CAP;
+    bool full = false;
     for (long long gc = s_lo; gc <= s_hi; gc += NEAR_CHUNK) {
         __syncthreads();   // the previous chunk is no longer read
         const int n_here = (int)(s_hi - gc + 1 < NEAR_CHUNK ? s_hi - gc + 1 : NEAR_CHUNK);
@@ -220,68 +235,45 @@ __global__ __launch_bounds__(256) void k_near_list(NearArgs A)
                 for (int q = 0; q < NEAR_GROUP; ++q) {
                     const int64_t i = i0 + q;
                     if (hit[u] && i < A.ns && i >= sb && i < se && i != j && near_test(kg + 4 * q, kj, A.c2)) {
-                        if (cnt < NEAR_CAP) out[cnt] = (int32_t)i;
+                        if (FILL) {
+                            const int64_t p = slot + cnt;
+                            if (p < A.pair_cap) {
+                                A.pair_t[p] = (int32_t)j;
+                                A.pair_s[p] = (int32_t)i;
+                            } else {
+                                full = true;
+                            }
+                        }
                         ++cnt;
                     }
                 }
             }
         }
     }
-    if (live) A.scnt[j * S + split] = cnt < NEAR_CAP ? cnt : NEAR_CAP;
-    if (cnt > NEAR_CAP) atomicOr(A.flags, FLAG_NEAR_FULL);
+    if (!FILL && live) A.scnt[j * S + split] = cnt;
+    if (full) atomicOr(A.flags, FLAG_NEAR_FULL);
 }
 
-// One thread per target: the near count over all splits (at most NEAR_CAP
-// kept) and its exclusive prefix within the wavefront, with per-wavefront
-// totals for the scan.
+// One thread per target: the near count over all splits, its exclusive
+// prefix within the wavefront, and per-wavefront totals for the scan.
 __global__ __launch_bounds__(256) void k_near_count(NearArgs A)
 {
     const int lane = threadIdx.x & 63;
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int32_t c = 0;
-    if (j < A.ns) {
+    int64_t c = 0;
+    if (j < A.ns)
         for (int s = 0; s < A.splits; ++s) c += A.scnt[j * A.splits + s];
-        if (c > NEAR_CAP) {
-            atomicOr(A.flags, FLAG_NEAR_FULL);
-            c = NEAR_CAP;
-        }
-    }
-    int32_t incl = c;
+    int64_t incl = c;
     for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(incl, o, 64);
+        const int64_t u = __shfl_up(incl, o, 64);
         if (lane >= o) incl += u;
     }
     if (j < A.ns) {
-        A.cnt[j] = c;
+        A.cnt[j] = (int32_t)c;
         A.loc[j] = incl - c;
     }
     const int64_t w = j >> 6;
     if (lane == 63 && w < A.n_waves) A.wtot[w] = incl;
-}
-
-// One thread per target: its pairs at woff[wave] + loc[j] in the flat arrays,
-// the splits' lists concatenated in split order (increasing source index).
-__global__ void k_near_compact(NearArgs A)
-{
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= A.ns) return;
-    const int64_t base = (int64_t)A.woff[j >> 6] + A.loc[j];
-    const int c = A.cnt[j];
-    A.ptr[j] = (int32_t)base;
-    int k = 0;
-    for (int s = 0; s < A.splits && k < c; ++s) {
-        const int32_t *lst = A.list + (j * A.splits + s) * NEAR_CAP;
-        const int m = A.scnt[j * A.splits + s];
-        for (int q = 0; q < m && k < c; ++q, ++k) {
-            const int64_t p = base + k;
-            if (p >= A.pair_cap) {
-                atomicOr(A.flags, FLAG_NEAR_FULL);
-                return;
-            }
-            A.pair_t[p] = (int32_t)j;
-            A.pair_s[p] = lst[q];
-        }
-    }
 }
 
 struct Focus {
@@ -419,16 +411,21 @@ __global__ __launch_bounds__(256) void k_near_exact(NearArgs A)
 
 }  // namespace
 
-void launch_near(const NearArgs &A, hipStream_t st)
+void launch_near_count(const NearArgs &A, hipStream_t st)
 {
     if (A.ns <= 0) return;
-    const int64_t waves = (A.ns + 63) / 64;
-    hipLaunchKernelGGL(k_near_keys, dim3((unsigned)((A.ns + 255) / 256)), dim3(256), 0, st, A);
     const unsigned tb = (unsigned)((A.ns + 255) / 256);
-    hipLaunchKernelGGL(k_near_list, dim3(tb, (unsigned)A.splits), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_near_keys, dim3(tb), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_near_list<0>, dim3(tb, (unsigned)A.splits), dim3(256), 0, st, A);
     hipLaunchKernelGGL(k_near_count, dim3(tb), dim3(256), 0, st, A);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (const int32_t *)A.wtot, waves, A.woff);
-    hipLaunchKernelGGL(k_near_compact, dim3((unsigned)((A.ns + 255) / 256)), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (const int64_t *)A.wtot, A.n_waves, A.woff);
+}
+
+void launch_near_fill(const NearArgs &A, hipStream_t st)
+{
+    if (A.ns <= 0) return;
+    const unsigned tb = (unsigned)((A.ns + 255) / 256);
+    hipLaunchKernelGGL(k_near_list<1>, dim3(tb, (unsigned)A.splits), dim3(256), 0, st, A);
     const int64_t cap_blocks = (A.pair_cap * LANES_PER_PAIR + 255) / 256;
     const unsigned eb = (unsigned)(cap_blocks < 8192 ? (cap_blocks > 0 ? cap_blocks : 1) : 8192);
     hipLaunchKernelGGL(k_near_exact, dim3(eb), dim3(256), 0, st, A);

@@ -261,8 +261,8 @@ namespace {
 int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x, const int32_t *seg_nodes,
              const double *burgers, const double *normal, const uint8_t *pinned, const double *volume,
              const double *stress_rate, const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
-             int precision, double near_cutoff_a, const dd_junctions *jn, int64_t *fast_steps, double *out,
-             void *stream)
+             int precision, double near_cutoff_a, double exact_eta, const dd_junctions *jn, int64_t *fast_steps,
+             double *out, void *stream)
 {
     int rc;
     if (n_inst < 0) return set_error(DD_EINVAL, "n_inst < 0");
@@ -295,7 +295,8 @@ int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, do
     if (nn > 0 && !x) return set_error(DD_EINVAL, "null x");
     if (ns > 0 && (!seg_nodes || !burgers || !normal)) return set_error(DD_EINVAL, "null segment array");
     if (nn >= INT32_MAX || 2 * ns >= INT32_MAX) return set_error(DD_EINVAL, "more than 2^31 nodes or 2^30 segments");
-    if (precision == DD_MIXED && !(near_cutoff_a > 0.0)) return set_error(DD_EINVAL, "near_cutoff_a must be > 0");
+    if (precision == DD_MIXED && !(near_cutoff_a >= 1.0)) return set_error(DD_EINVAL, "near_cutoff_a must be >= 1");
+    if (!(exact_eta >= 0.0) || std::isinf(exact_eta)) return set_error(DD_EINVAL, "exact_eta must be finite and >= 0");
     if (jn) {
         if (!(jn->capture_radius >= 0.0) || !std::isfinite(jn->capture_radius) || !(jn->max_break_time >= 0.0) ||
             !std::isfinite(jn->max_break_time))
@@ -311,7 +312,6 @@ int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, do
     Workspace *ws;
     if ((rc = workspace(&ws))) return rc;
 
-    DD_HIP(hipMemsetAsync(ws->flags_dev, 0, sizeof(unsigned), st));   // not captured: plain stream work
     BurstBatch B;
     B.n_inst = n_inst;
     B.node_off.assign(node_off, node_off + n_inst + 1);
@@ -326,6 +326,7 @@ int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, do
     B.n_gauss = n_gauss;
     B.precision = precision;
     B.near_cut = near_cutoff_a;
+    B.eta = exact_eta;
     B.dt = P.dt;
     if ((rc = burst_batch_init(B, st))) return rc;
 
@@ -455,11 +456,7 @@ int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, do
         if (nn > 0)
             hipLaunchKernelGGL(k_pta_flags, dim3((unsigned)((3 * nn + 255) / 256)), dim3(256), 0, st, x, 3 * nn,
                                ws->flags_dev);
-        DD_HIP(hipStreamSynchronize(st));
-        unsigned fl = 0;
-        DD_HIP(hipMemcpy(&fl, ws->flags_dev, sizeof(unsigned), hipMemcpyDeviceToHost));
-        if (fl) return set_error(fl & FLAG_NONFINITE ? DD_ENONFINITE : DD_EINVAL,
-                                 "invalid input or non-finite result (flags 0x%x)", fl);
+        if ((rc = read_flags(ws, st))) return rc;
     }
     DD_HIP(hipStreamSynchronize(st));
     if (jn)
@@ -473,23 +470,23 @@ extern "C" int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_
                            const int32_t *seg_nodes, const double *burgers, const double *normal,
                            const uint8_t *pinned, const double *volume, const double *stress_rate,
                            const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
-                           int precision, double near_cutoff_a, double *out, void *stream)
+                           int precision, double near_cutoff_a, double exact_eta, double *out, void *stream)
 {
     clear_error();
     return pta_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, prm, m,
-                    n_gauss, precision, near_cutoff_a, nullptr, nullptr, out, stream);
+                    n_gauss, precision, near_cutoff_a, exact_eta, nullptr, nullptr, out, stream);
 }
 
 extern "C" int dd_pta_step_junctions(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
                                      const int32_t *seg_nodes, const double *burgers, const double *normal,
                                      const uint8_t *pinned, const double *volume, const double *stress_rate,
                                      const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
-                                     int precision, double near_cutoff_a, const dd_junctions *junctions,
-                                     int64_t *fast_steps, double *out, void *stream)
+                                     int precision, double near_cutoff_a, double exact_eta,
+                                     const dd_junctions *junctions, int64_t *fast_steps, double *out, void *stream)
 {
     clear_error();
     if (!junctions) return set_error(DD_EINVAL, "null junction parameters");
     return pta_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, prm, m,
-                    n_gauss, precision, near_cutoff_a, junctions, fast_steps, out, stream);
+                    n_gauss, precision, near_cutoff_a, exact_eta, junctions, fast_steps, out, stream);
 }
 

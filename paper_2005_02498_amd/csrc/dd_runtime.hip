@@ -157,6 +157,15 @@ GaussRule gauss_rule(int n)
     return g;
 }
 
+void drop_graphs(Workspace *ws)
+{
+    if (ws->graphs.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto &g : ws->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    ws->graphs.clear();
+}
+
 }  // namespace dd
 
 extern "C" {
@@ -211,6 +220,7 @@ int dd_shutdown(void)
         if (!w) continue;
         (void)hipSetDevice(w->device);
         (void)hipDeviceSynchronize();
+        dd::drop_graphs(w);
         for (int s = 0; s < dd::WS_NSLOTS; ++s)
             if (w->ptr[s]) (void)hipFree(w->ptr[s]);
         if (w->flags_dev) (void)hipFree(w->flags_dev);

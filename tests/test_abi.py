@@ -52,10 +52,6 @@ def test_host_only_calls_without_gpu():
         with pytest.raises(dd.DDError):
             dd.dd_set_plan(*bad)
     dd.dd_set_plan(-1)
-    for bad in (-1.0, float("nan"), float("inf")):
-        with pytest.raises(dd.DDError):
-            dd.dd_set_exact_band(bad)
-    dd.dd_set_exact_band(0.0)
     # block-coupling argument checks happen before any device work
     fake = ctypes.c_void_p(256)
     for bad in ((0, 1, 1.0, 1.0), (1, 0, 1.0, 1.0), (1, 1, 0.0, 1.0), (1, 1, 1.0, float("nan")),
@@ -72,19 +68,29 @@ def test_host_only_calls_without_gpu():
     off = (ctypes.c_int64 * 2)(0, 4)
     m = dd.Material(1.0, 0.3, 1.0, 1.0)
     assert dd.lib().dd_burst_batch_junctions(1, off, off, fake, fake, fake, fake, fake, fake, fake,
-                                             ctypes.byref(m), 2, 0, 20.0, 1, 1.0, None, fake, None,
+                                             ctypes.byref(m), 2, 0, 20.0, 0.0, 1, 1.0, None, fake, None,
                                              None) == dd.DD_EINVAL
     sig = (ctypes.c_double * 6)()
     # the mixed path's near-field cutoff is at least one core width
     for cut in (0.5, 0.0, float("nan")):
-        assert dd.lib().dd_nodal_forces(4, fake, 4, fake, fake, fake, sig, ctypes.byref(m), 2, 1, cut,
+        assert dd.lib().dd_nodal_forces(4, fake, 4, fake, fake, fake, sig, ctypes.byref(m), 2, 1, cut, 0.0,
                                         fake, None) == dd.DD_EINVAL
     assert "near_cutoff_a" in dd.dd_last_error()
+    # the exact band's eta is finite and >= 0, for every call that takes it
+    for eta in (-1.0, float("nan"), float("inf")):
+        assert dd.lib().dd_nodal_forces(4, fake, 4, fake, fake, fake, sig, ctypes.byref(m), 2, 0, 20.0, eta,
+                                        fake, None) == dd.DD_EINVAL
+        assert "exact_eta" in dd.dd_last_error()
+        assert dd.lib().dd_step(4, fake, 4, fake, fake, fake, None, sig, ctypes.byref(m), 2, 0, 20.0, eta,
+                                1.0, None, None, None) == dd.DD_EINVAL
+        assert dd.lib().dd_burst_batch(1, off, off, fake, fake, fake, fake, fake, fake, fake,
+                                       ctypes.byref(m), 2, 0, 20.0, eta, 1, 1.0, fake, None,
+                                       None) == dd.DD_EINVAL
     for args in ((-1, 1.0), (4, 0.0), (4, float("nan"))):   # negative count, dt <= 0, NaN dt
-        assert dd.lib().dd_step(args[0], fake, 4, fake, fake, fake, None, sig, ctypes.byref(m), 2, 0, 20.0,
+        assert dd.lib().dd_step(args[0], fake, 4, fake, fake, fake, None, sig, ctypes.byref(m), 2, 0, 20.0, 0.0,
                                 args[1], None, None, None) == dd.DD_EINVAL
     P = dd.PTAParams(dt=1e-14)
     d1 = (ctypes.c_double * 6)()
     assert dd.lib().dd_pta_step_junctions(1, off, off, fake, fake, fake, fake, fake, fake, d1, d1,
-                                          ctypes.byref(P), ctypes.byref(m), 2, 0, 20.0, None, None, d1,
+                                          ctypes.byref(P), ctypes.byref(m), 2, 0, 20.0, 0.0, None, None, d1,
                                           None) == dd.DD_EINVAL

@@ -153,3 +153,46 @@ def test_full_batch_of_512_sampled(prec, steps, tol):
         e_r = np.abs(rg[i] - ro[0]).max() / max(np.abs(ro[0]).max(), 1e-300)
         print(f"volume {i} ({ns[i]} segments): displacement err {e_x:.2e}, rate err {e_r:.2e}")
         assert e_x < tol and e_r < tol
+
+
+def test_async_two_calls_one_sync():
+    """With validation off, dd_burst_batch is asynchronous once its instance
+    tables, work split and step graph are cached.  Two calls enqueued back to
+    back on one output (the second relaunches the first's cached graph, and
+    resumes from its end state), a clone of the rates enqueued between them,
+    and one synchronisation: the same rates and positions, bit for bit, as the
+    same two calls made with validation on; the stream is still busy when the
+    second call returns."""
+    insts = [W.subset(W.burst_instance(1_000_020 + i), 32) for i in range(8)]
+    bt = W.pack(insts)
+    ref = batch_dev(bt)
+    out = []
+    for _ in range(2):
+        r, _ = dd.dd_burst_batch(bt.node_off, bt.seg_off, ref["x"], ref["seg_nodes"], ref["burgers"],
+                                 ref["normal"], ref["pinned"], ref["sigma_app"], ref["volume"], MAT, 2,
+                                 dd.DD_MIXED, 20.0, 100, W.DT)
+        out.append(r.cpu().numpy())
+    d = batch_dev(bt)
+    rate = torch.empty((bt.n_inst, 12), dtype=torch.float64, device="cuda:0")
+    args = (bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"], d["normal"], d["pinned"],
+            d["sigma_app"], d["volume"], MAT, 2, dd.DD_MIXED, 20.0, 100, W.DT)
+    prev = dd.dd_set_validation(False)
+    try:
+        # one call to cache tables and graph for this argument set
+        dd.dd_burst_batch(*args, rate_avg_out=rate)
+        torch.cuda.synchronize()
+        d["x"].copy_(torch.tensor(bt.x, device="cuda:0"))
+        torch.cuda.synchronize()
+        dd.dd_burst_batch(*args, rate_avg_out=rate)
+        first = rate.clone()
+        dd.dd_burst_batch(*args, rate_avg_out=rate)
+        busy = not torch.cuda.current_stream().query()
+        torch.cuda.synchronize()
+    finally:
+        dd.dd_set_validation(prev)
+    print(f"stream busy after the second call returned: {busy}")
+    assert busy
+    np.testing.assert_array_equal(first.cpu().numpy(), out[0])
+    np.testing.assert_array_equal(rate.cpu().numpy(), out[1])
+    np.testing.assert_array_equal(d["x"].cpu().numpy(), ref["x"].cpu().numpy())
+    dd.dd_check()

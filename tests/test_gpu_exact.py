@@ -1,8 +1,8 @@
-"""GPU parity of the exact band (dd_set_exact_band) against the oracle with the
-same band: near pairs take the exact target integral, all others the Q-point
-rule.  Tolerances as for the plain force path: FP64 1e-10, mixed 1e-4
-(normwise over nodes).  The near decision is the same arithmetic on both
-sides, so the same pairs are corrected."""
+"""GPU parity of the exact band (the exact_eta argument of the force calls)
+against the oracle with the same band: near pairs take the exact target
+integral, all others the Q-point rule.  Tolerances as for the plain force
+path: FP64 1e-10, mixed 1e-4 (normwise over nodes).  The near decision is the
+same arithmetic on both sides, so the same pairs are corrected."""
 import numpy as np
 import pytest
 import torch
@@ -18,24 +18,29 @@ pytestmark = pytest.mark.gpu
 TOL64, TOLMIX = 1e-10, 1e-4
 
 
+_ETA = [0.0]   # the band the GPU calls below pass (set by `band`)
+
+
 class band:
-    """The same exact band on the GPU library and in the oracle, 0 on exit."""
+    """The same exact band for the GPU calls of this module (their exact_eta
+    argument) and in the oracle (process-wide there); 0 on exit."""
 
     def __init__(self, eta):
         self.eta = eta
 
     def __enter__(self):
-        dd.dd_set_exact_band(self.eta)
+        _ETA[0] = self.eta
         O.set_exact_band(self.eta)
 
     def __exit__(self, *exc):
-        dd.dd_set_exact_band(0.0)
+        _ETA[0] = 0.0
         O.set_exact_band(0.0)
 
 
 def _gpu(inst, Q=2, prec=dd.DD_FP64):
     d = dev(inst)
-    F = dd.dd_nodal_forces(d["x"], d["seg_nodes"], d["burgers"], d["normal"], inst.sigma_app, MAT, Q, prec)
+    F = dd.dd_nodal_forces(d["x"], d["seg_nodes"], d["burgers"], d["normal"], inst.sigma_app, MAT, Q, prec,
+                           exact_eta=_ETA[0])
     torch.cuda.synchronize()
     return F.cpu().numpy()
 
@@ -108,7 +113,7 @@ def test_closed_loop_net_force_vanishes_with_wide_band():
             torch.tensor(nrm, device=d), np.zeros(6), MAT, 2)
     Fq = dd.dd_nodal_forces(*args).cpu().numpy()
     with band(100.0):   # every pair of the loop (31 near sources per segment)
-        Fe = dd.dd_nodal_forces(*args).cpu().numpy()
+        Fe = dd.dd_nodal_forces(*args, exact_eta=100.0).cpu().numpy()
         ref = O.nodal_forces(x, sn, b, np.zeros(6), W.MU, W.NU, W.CORE_A, 2)
     ratio_q = np.abs(Fq.sum(1)).max() / np.abs(Fq).sum(1).max()
     ratio_e = np.abs(Fe.sum(1)).max() / np.abs(Fe).sum(1).max()
@@ -126,7 +131,8 @@ def test_small_batch_bursts_fp64():
     d = batch_dev(bt)
     with band(2.0):
         rate, _ = dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"], d["normal"],
-                                    d["pinned"], d["sigma_app"], d["volume"], MAT, 2, dd.DD_FP64, 20.0, 4, W.DT)
+                                    d["pinned"], d["sigma_app"], d["volume"], MAT, 2, dd.DD_FP64, 20.0, 4, W.DT,
+                                    exact_eta=2.0)
         torch.cuda.synchronize()
         xo, ro, _ = O.burst_batch(bt, W.material(), 2, 4, W.DT)
     xg = d["x"].cpu().numpy()
@@ -148,38 +154,59 @@ def test_deterministic_and_off_again():
     assert not np.array_equal(F0, F1)
 
 
-def test_capacity_exceeded_is_an_error():
-    inst = W.config0()
-    with band(60.0):   # every one of the 255 other segments is near
-        with pytest.raises(dd.DDError) as ei:
-            _gpu(inst)
-        assert ei.value.code == -5
-    # a later call without the band is unaffected
+def test_every_pair_near():
+    """A band that makes every one of the 127 other segments near for each
+    segment of four loops: the pair store is sized from the count, with no
+    cap on near sources per segment; a later call without the band is
+    unaffected."""
+    inst = W.subset(W.config0(), 4)
+    with band(60.0):
+        e = normwise(_gpu(inst), _oracle(inst))
+    print(f"every pair near: err {e:.2e}")
+    assert e < TOL64
     assert normwise(_gpu(inst), _oracle(inst)) < TOL64
 
 
-def test_large_volume_sampled_fp64():
+def test_pending_flags_reported_by_check():
+    """With validation off a bad node index is not reported by the call (its
+    results are unspecified, the kernels stay in bounds); dd_check reports it
+    afterwards, once, and the library works again."""
+    inst = W.subset(W.config0(), 1)
+    d = dev(inst)
+    bad = d["seg_nodes"].clone()
+    bad[1, 3] = 99
+    prev = dd.dd_set_validation(False)
+    try:
+        dd.dd_nodal_forces(d["x"], bad, d["burgers"], d["normal"], inst.sigma_app, MAT, 2)
+    finally:
+        dd.dd_set_validation(prev)
+    with pytest.raises(dd.DDError) as ei:
+        dd.dd_check()
+    assert ei.value.code == -1
+    dd.dd_check()
+    assert normwise(_gpu(inst), _oracle(inst)) < TOL64
+
+
+@pytest.mark.parametrize("eta,loops", [(1.5, (7927, 4000)), (2.0, (2410, 2116, 4000))])
+def test_large_volume_sampled_fp64(eta, loops):
     """262,144 segments (one source split per target, coordinates up to
-    50,000 b) at eta = 1.5: the loop with the most near pairs (189, up to 34
-    for one segment) and an ordinary one, each against every source, by the
-    oracle.  At eta = 2 one long segment has 68 near sources: the call
-    reports DD_ECAPACITY."""
+    50,000 b), each sampled loop against every source by the oracle.  At
+    eta = 1.5: the loop with the most near pairs (189, up to 40 for one
+    segment) and an ordinary one.  At eta = 2 (1,121,914 near pairs): the
+    loop holding the segment with the most near sources (68) and the loop
+    with the most near pairs (324)."""
     inst = W.config3()
-    with band(1.5):
+    with band(eta):
         F = _gpu(inst, 2)
         num = den = 0.0
-        for lp in (7927, 4000):
+        for lp in loops:
             t0, t1 = 32 * lp, 32 * lp + 32
             ref = O.nodal_forces_sampled(inst.x, inst.seg_nodes, inst.burgers, inst.sigma_app,
                                          W.MU, W.NU, W.CORE_A, 2, t0, t1)[:, t0:t1]
             num = max(num, np.linalg.norm(F[:, t0:t1] - ref, axis=0).max())
             den = max(den, np.linalg.norm(ref, axis=0).max())
-    print(f"large volume sampled eta=1.5: err {num / den:.2e}")
+    print(f"large volume sampled eta={eta}: err {num / den:.2e}")
     assert num / den < TOL64
-    with band(2.0):
-        with pytest.raises(dd.DDError) as ei:
-            _gpu(inst, 2)
-        assert ei.value.code == -5
 
 
 def test_pta_step_with_band():
@@ -195,7 +222,7 @@ def test_pta_step_with_band():
         got = dd.dd_pta_step(bt.node_off, bt.seg_off, d["x"], d["seg_nodes"], d["burgers"], d["normal"],
                              d["pinned"], d["volume"], rates, t,
                              dd.PTAParams(dt=W.DT, delta=1e-8, chunk_steps=3, max_chunks=3, lpdot_max=np.inf),
-                             MAT, 2, dd.DD_FP64)
+                             MAT, 2, dd.DD_FP64, exact_eta=2.0)
         torch.cuda.synchronize()
         OP = pta.PTAParams(dt=W.DT, delta=1e-8, chunk=3, max_chunks=3, lpdot_max=np.inf)
         refs = [pta.pta_step(inst, t[i], rates[i], W.material(), 2, OP) for i, inst in enumerate(insts)]

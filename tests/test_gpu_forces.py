@@ -219,7 +219,8 @@ def test_size_limits_rejected():
     F = torch.empty_like(d["x"])
     p = [C.c_void_p(t.data_ptr()) for t in (d["x"], d["seg_nodes"], d["burgers"], d["normal"], F)]
     for nn, ns in ((2 ** 31, inst.n_segs), (inst.n_nodes, 2 ** 30)):
-        rc = dd.lib().dd_nodal_forces(nn, p[0], ns, p[1], p[2], p[3], sig, C.byref(m), 2, 0, 20.0, p[4], None)
+        rc = dd.lib().dd_nodal_forces(nn, p[0], ns, p[1], p[2], p[3], sig, C.byref(m), 2, 0, 20.0, 0.0, p[4],
+                                      None)
         assert rc == -1, rc
         assert "2^31" in dd.dd_last_error() or "2^30" in dd.dd_last_error()
 
@@ -288,17 +289,13 @@ def test_step_with_exact_band_equals_forces_then_glide():
     inst = W.burst_instance(1_000_006)
     d1, d2 = dev(inst), dev(inst)
     F1, F2 = torch.empty_like(d1["x"]), torch.empty_like(d1["x"])
-    dd.dd_set_exact_band(2.0)
-    try:
-        dd.dd_nodal_forces(d1["x"], d1["seg_nodes"], d1["burgers"], d1["normal"], inst.sigma_app, MAT, 2,
-                           dd.DD_FP64, 20.0, force_out=F1)
-        V1 = dd.dd_glide_step(d1["x"], F1, d1["seg_nodes"], d1["normal"], d1["pinned"], MAT, W.DT)
-        V2 = torch.empty_like(d2["x"])
-        dd.dd_step(d2["x"], d2["seg_nodes"], d2["burgers"], d2["normal"], d2["pinned"], inst.sigma_app, MAT, W.DT,
-                   2, dd.DD_FP64, 20.0, force_out=F2, vel_out=V2)
-        torch.cuda.synchronize()
-    finally:
-        dd.dd_set_exact_band(0.0)
+    dd.dd_nodal_forces(d1["x"], d1["seg_nodes"], d1["burgers"], d1["normal"], inst.sigma_app, MAT, 2,
+                       dd.DD_FP64, 20.0, force_out=F1, exact_eta=2.0)
+    V1 = dd.dd_glide_step(d1["x"], F1, d1["seg_nodes"], d1["normal"], d1["pinned"], MAT, W.DT)
+    V2 = torch.empty_like(d2["x"])
+    dd.dd_step(d2["x"], d2["seg_nodes"], d2["burgers"], d2["normal"], d2["pinned"], inst.sigma_app, MAT, W.DT,
+               2, dd.DD_FP64, 20.0, force_out=F2, vel_out=V2, exact_eta=2.0)
+    torch.cuda.synchronize()
     assert torch.equal(F1, F2)
     v1 = V1.cpu().numpy()
     np.testing.assert_allclose(V2.cpu().numpy(), v1, rtol=0, atol=1e-13 * np.abs(v1).max())
