@@ -18,8 +18,10 @@ Printed as one JSON line, with
   average launch time from HIP events on the launch stream, against the FP64
   vector peak; traffic from the committed rocprofv3 counter summary when it
   was taken on the current kernel source;
-* cpu_baseline: the FP64 C oracle, single-threaded, on a bounded sample of the
-  same workload (the first --cpu-targets target segments against all sources);
+* cpu_baseline: the FP64 C oracle on this machine's host CPU: its OpenMP build
+  on the full force pass of the same workload (the reported value, with the
+  thread count), the single-threaded oracle on a sample of it, and the other
+  workloads in full or sampled with labelled extrapolations (cpu_baseline());
 * extras: the mixed FP32/FP64 path and 4 Gauss points on the same volume, one
   step of the 262,144-segment volume in both precisions, 100 graph-captured
   steps of the 256-segment volume, 512 batched bursts (200 glide steps each)
@@ -47,13 +49,15 @@ UNIT = "segment-pair evals/s"
 # scalar is summed per target point and its vector added once, which the
 # per-evaluation counts leave out.
 FLOP_F64_EVAL = 126          # FP64 path (pair_acc_f64)
-FLOP_MIX_BAND_F32 = 14       # mixed: offset to the source midpoint and its square (every
-                             # pair, variants 0 and 2)
-FLOP_MIX_QUAD_F32 = {0: 124, 2: 142}   # mixed: FP32 2-point (variant 0) and 3-point (variant 2)
+FLOP_MIX_EVERY_F32 = {0: 23, 1: 15, 2: 23}   # mixed, every pair: offset to the source midpoint
+                             # (9), its axial part (5) and square (1); variants 0 and 2 also its
+                             # squared length (5) and the band/collinearity test (3)
+FLOP_MIX_QUAD_F32 = {0: 119, 2: 137}   # mixed: FP32 2-point (variant 0) and 3-point (variant 2)
                                        # source quadrature (quad2/quad3_acc_f32)
-FLOP_MIX_LOC_F32 = 13        # mixed: FP32 axial and perpendicular parts from the midpoint
-                             # offset (pairs that are not evaluated by quadrature)
-FLOP_MIX_CLASS_F32 = 8       # mixed: minimum-distance test (the same pairs)
+FLOP_MIX_LOC_F32 = 8         # mixed: FP32 axial coordinate from the first node and
+                             # perpendicular part (pairs that are not evaluated by quadrature)
+FLOP_MIX_CLASS_F32 = 10      # mixed: |rho|^2, axial excess, near-field and collinearity tests
+                             # (the same pairs)
 FLOP_MIX_FAR_F32 = 144       # mixed: FP32 cancellation-free closed form (pair_acc_f32; the
                              # 4 multiplies that undo the record's quadrature weight not counted)
 FLOP_MIX_NEAR_F64 = 144      # mixed: FP64 closed form of an isolated pair (near field)
@@ -64,7 +68,8 @@ PEAK_BF16_MFMA = 2.5e15
 # surrogate: 36-256-256-256-12, multiply-adds per point and member
 MLP_MACS = 36 * 256 + 256 * 256 * 2 + 256 * 12
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pair64_volume16384_q2_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "k_pair64_volume16384_q2_traffic.json")
 KERNEL_SOURCES = ["paper_2005_02498_amd/csrc/dd_pair64.hip", "paper_2005_02498_amd/csrc/dd_pair64.h"]
 
 
@@ -97,11 +102,15 @@ def parse():
     ap.add_argument("--cpu-targets", type=int, default=4096,
                     help="target segments in the CPU oracle sample (0: skip)")
     ap.add_argument("--no-extras", action="store_true", help="skip mixed / Q=4 / burst extras")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the single-threaded oracle on the full 16,384-segment pass and on 1024 "
+                         "targets of the large volume; store every CPU leg in --cpu-full-out")
+    ap.add_argument("--cpu-full-out", default=os.path.join(PROFILES, "cpu_baseline_full.json"))
     ap.add_argument("--exact-band", type=float, default=0.0,
                     help="with --only fp64|mixed: exact target integral for pairs closer than this band")
     ap.add_argument("--burst-instances", type=int, default=512)
     ap.add_argument("--burst-steps", type=int, default=200)
-    ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy", "surrogate", "blocks"], default=None,
+    ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy", "surrogate", "blocks", "cpu"], default=None,
                     help="profiling aid: run only one part (no JSON contract)")
     ap.add_argument("--surrogate-study", action="store_true",
                     help="run the surrogate speed-up-at-fixed-error study and write --study-out")
@@ -305,6 +314,107 @@ def surrogate_study(args):
     print(json.dumps(res))
 
 
+def cpu_baseline(args, inst):
+    """The FP64 C oracle, as it stands, on the host CPU of this machine: the
+    OpenMP build of the same source (targets over all host cores, the same
+    sums) on the full force pass of the 16,384-segment volume, which is the
+    reported value; beside it the single-threaded oracle on a sample of it,
+    the 256-segment volume's 100-step burst in full (both builds), 16 of the
+    512 burst volumes (one step) and 1024 target segments of the 262,144-segment
+    volume against all its sources, each with the time the whole workload
+    would take at that rate (extrapolated linearly: the work is proportional
+    to target points x sources, so the rate carries over).  --cpu-full adds
+    the single-threaded full pass of the 16,384-segment volume (about 35 s)
+    and stores every leg in profiles/cpu_baseline_full.json."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2005_02498_amd import workloads as W
+
+    N = inst.n_segs
+    pairs = N * (N - 1)
+    legs = {}
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        return time.perf_counter() - t0
+
+    def forces(v, t0=0, t1=None):
+        t1 = v.n_segs if t1 is None else t1
+        return O.nodal_forces_sampled(v.x, v.seg_nodes, v.burgers, v.sigma_app, W.MU, W.NU, W.CORE_A, 2, t0, t1)
+
+    with O.openmp():
+        thr = O.threads()
+        t = timed(lambda: forces(inst))
+    legs["volume16384_full_openmp"] = {"pairs_per_s": pairs / t, "seconds": t, "threads": thr,
+                                       "what": "all 16,384 targets x all sources, Q = 2"}
+    nt = min(args.cpu_targets, N)
+    t = timed(lambda: forces(inst, 0, nt))
+    legs["volume16384_sample_1thread"] = {
+        "pairs_per_s": nt * (N - 1) / t, "seconds": t, "threads": 1,
+        "what": f"first {nt} of {N} targets x all sources, Q = 2",
+        "full_pass_seconds_extrapolated": pairs / (nt * (N - 1) / t)}
+    if args.cpu_full:
+        t = timed(lambda: forces(inst))
+        legs["volume16384_full_1thread"] = {"pairs_per_s": pairs / t, "seconds": t, "threads": 1,
+                                            "what": "all 16,384 targets x all sources, Q = 2"}
+    # the 256-segment volume: the whole 100-step FP64 burst
+    c0 = W.config0()
+    c0p = c0.n_segs * (c0.n_segs - 1) * 100
+    for name, ctx in (("volume256_burst100_1thread", None), ("volume256_burst100_openmp", O.openmp())):
+        if ctx is None:
+            t = timed(lambda: O.burst(c0, W.material(), 2, 100, W.DT))
+            th = 1
+        else:
+            with ctx:
+                th = O.threads()
+                t = timed(lambda: O.burst(c0, W.material(), 2, 100, W.DT))
+        legs[name] = {"pairs_per_s": c0p / t, "seconds": t, "threads": th, "what": "256 segments, 100 steps, Q = 2"}
+    # 16 of the 512 burst volumes, one step; extrapolated to 512 volumes x 200 steps
+    bts = W.pack(W.config2(16))
+    Ns = np.diff(bts.seg_off)
+    p16 = int(np.sum(Ns * (Ns - 1)))
+    all512 = np.diff(W.pack(W.config2(512)).seg_off)
+    p512 = int(np.sum(all512 * (all512 - 1))) * 200
+    with O.openmp():
+        th = O.threads()
+        t = timed(lambda: O.burst_batch(bts, W.material(), 2, 1, W.DT))
+    legs["bursts16_1step_openmp"] = {"pairs_per_s": p16 / t, "seconds": t, "threads": th,
+                                     "what": "16 burst volumes (seeds 1,000,000-1,000,015), one step, FP64, Q = 2",
+                                     "bursts512x200_seconds_extrapolated": p512 / (p16 / t)}
+    # 1024 target segments of the 262,144-segment volume against all sources
+    big = W.config3()
+    NB = big.n_segs
+    with O.openmp():
+        th = O.threads()
+        t = timed(lambda: forces(big, 0, 1024))
+    legs["volume262144_1024targets_openmp"] = {
+        "pairs_per_s": 1024 * (NB - 1) / t, "seconds": t, "threads": th,
+        "what": "first 1024 of 262,144 targets x all sources, Q = 2",
+        "full_pass_seconds_extrapolated": NB * (NB - 1) / (1024 * (NB - 1) / t)}
+    nt3 = 1024 if args.cpu_full else 128
+    t = timed(lambda: forces(big, 0, nt3))
+    legs[f"volume262144_{nt3}targets_1thread"] = {
+        "pairs_per_s": nt3 * (NB - 1) / t, "seconds": t, "threads": 1,
+        "what": f"first {nt3} of 262,144 targets x all sources, Q = 2",
+        "full_pass_seconds_extrapolated": NB * (NB - 1) / (nt3 * (NB - 1) / t)}
+    main_leg = legs["volume16384_full_openmp"]
+    res = {"value": main_leg["pairs_per_s"], "unit": UNIT, "cores": main_leg["threads"], "kind": "oracle",
+           "sample": "the full force pass of the 16,384-segment volume (every target against every source, "
+                     "2 Gauss points), FP64 C oracle compiled with OpenMP over target segments, on this "
+                     f"machine's host CPU ({os.cpu_count()} logical CPUs visible)",
+           "seconds": main_leg["seconds"], "legs": legs}
+    if args.cpu_full:
+        os.makedirs(os.path.dirname(os.path.abspath(args.cpu_full_out)), exist_ok=True)
+        with open(args.cpu_full_out, "w") as f:
+            json.dump({"command": "python bench.py --only cpu --cpu-full", "cpu_baseline": res}, f, indent=1)
+    elif os.path.exists(os.path.join(PROFILES, "cpu_baseline_full.json")):
+        with open(os.path.join(PROFILES, "cpu_baseline_full.json")) as f:
+            res["stored_full_run"] = json.load(f)["cpu_baseline"]["legs"]
+    return res
+
+
 def main():
     args = parse()
     if args.surrogate_study:
@@ -325,6 +435,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     mat = {"mu": W.MU, "nu": W.NU, "a": W.CORE_A, "B": W.DRAG_B}
+
+    if args.only == "cpu":
+        from paper_2005_02498_amd import workloads as W
+        print(json.dumps({"part": "cpu", "cpu_baseline": cpu_baseline(args, W.config1())}))
+        return
 
     if args.only == "surrogate":
         # surrogate inference only: 1,048,576 points, 4-member ensemble
@@ -452,9 +567,8 @@ def main():
             allp = N * N * Q                 # including the (skipped) self pairs
             other = allp - quad              # pairs located in FP32 (not by quadrature)
             closed = pairs * Q - quad - near
-            band = allp if variant in (0, 2) else 0
             f64 = FLOP_MIX_NEAR_F64 * near
-            f32 = (FLOP_MIX_BAND_F32 * band + FLOP_MIX_QUAD_F32.get(variant, 0) * quad
+            f32 = (FLOP_MIX_EVERY_F32[variant] * allp + FLOP_MIX_QUAD_F32.get(variant, 0) * quad
                    + (FLOP_MIX_LOC_F32 + FLOP_MIX_CLASS_F32) * other + FLOP_MIX_FAR_F32 * closed)
         flops = f64 + f32
         t_roof = f64 / PEAK_F64 + f32 / PEAK_F32
@@ -705,18 +819,7 @@ def main():
                             "source": "profiles/surrogate_study.json (python bench.py --surrogate-study)"}
 
     if args.cpu_targets > 0:
-        import oracle as O
-        nt = min(args.cpu_targets, N)
-        t0 = time.perf_counter()
-        O.nodal_forces_sampled(inst.x, inst.seg_nodes, inst.burgers, inst.sigma_app,
-                               W.MU, W.NU, W.CORE_A, 2, 0, nt)
-        t1 = time.perf_counter()
-        out["cpu_baseline"] = {
-            "value": nt * (N - 1) / (t1 - t0), "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"first {nt} of {N} target segments against all {N} sources, 2 Gauss "
-                      f"points, FP64 C oracle single-threaded ({t1 - t0:.1f} s); host has "
-                      f"{os.cpu_count()} logical CPUs",
-            "seconds": t1 - t0}
+        out["cpu_baseline"] = cpu_baseline(args, inst)
 
     print(json.dumps(out))
 

@@ -21,33 +21,74 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ddo.c")
 _LIB = os.path.join(_HERE, "libddoracle.so")
+_LIB_OMP = os.path.join(_HERE, "libddoracle_omp.so")   # the same source with OpenMP over targets
 _lib = None
+_lib_omp = None
+_use_omp = False
 
 
 class Material(C.Structure):
     _fields_ = [("mu", C.c_double), ("nu", C.c_double), ("a", C.c_double), ("B", C.c_double)]
 
 
+def _compile(out, extra):
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wno-unknown-pragmas", "-fPIC", "-shared",
+                           *extra, _SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
-    """Compile ddo.c into libddoracle.so next to it."""
-    global _lib
+    """Compile ddo.c into libddoracle.so (single-threaded, the oracle) and
+    libddoracle_omp.so (the same code with its target loop spread over
+    OpenMP threads: identical sums, used only to time the oracle on all host
+    cores)."""
+    global _lib, _lib_omp
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wno-unknown-pragmas", "-fPIC", "-shared",
-                               _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
+        _compile(_LIB, [])
         _lib = None
+    if force or not os.path.exists(_LIB_OMP):
+        _compile(_LIB_OMP, ["-fopenmp"])
+        _lib_omp = None
     return _LIB
 
 
 def lib():
-    global _lib
+    """The single-threaded oracle library (the OpenMP build inside `openmp()`)."""
+    global _lib, _lib_omp
+    if _use_omp:
+        if _lib_omp is None:
+            if not os.path.exists(_LIB_OMP) or os.path.getmtime(_LIB_OMP) < os.path.getmtime(_SRC):
+                _compile(_LIB_OMP, ["-fopenmp"])
+            _lib_omp = C.CDLL(_LIB_OMP)
+            _setup(_lib_omp)
+        return _lib_omp
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
+            _compile(_LIB, [])
         _lib = C.CDLL(_LIB)
         _setup(_lib)
     return _lib
+
+
+class openmp:
+    """Context manager: inside, the wrappers below call the OpenMP build of
+    the same source (targets in parallel, sums in the same order, so the same
+    numbers); used to time the oracle on every host core."""
+
+    def __enter__(self):
+        global _use_omp
+        _use_omp = True
+        return self
+
+    def __exit__(self, *exc):
+        global _use_omp
+        _use_omp = False
+
+
+def threads() -> int:
+    """Threads the force routines of the current build use."""
+    return int(lib().ddo_threads())
 
 
 _dp = C.POINTER(C.c_double)
@@ -78,6 +119,7 @@ def _setup(L):
     L.ddo_set_exact_band.argtypes = [C.c_double]
     L.ddo_set_source_quadrature.argtypes = [C.c_int, C.c_int]
     L.ddo_threads.argtypes = []
+    L.ddo_threads.restype = C.c_int
     L.ddo_glide_step.argtypes = [C.c_int64, _dp, _dp, C.c_int64, _ip, _dp, _up,
                                  C.POINTER(Material), C.c_double, _dp]
     L.ddo_fcc_system.argtypes = [C.c_int, _dp, _dp]
