@@ -222,6 +222,31 @@ int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
                     const dd_material *m, int n_gauss, int precision,
                     double near_cutoff_a, double exact_eta, double *force_out, void *stream);
 
+/* dd_nodal_forces for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, layouts and results as dd_nodal_forces without
+ * the exact band (the same numbers bit for bit when both use the same work
+ * split: the built-in heuristic, or what dd_set_plan fixes; this call never
+ * runs the autotuner).  Every buffer beyond the caller's arrays comes from a
+ * fixed device array of 64 MiB that each GPU holds from the library's first
+ * use until the process ends, so the call allocates nothing, never
+ * synchronises and may be captured in a graph.  Limit: the pass's scratch
+ * (about 400 bytes per segment, 6 KiB per work item of 256 Gauss points x one
+ * source range, and the node lists) must fit in 64 MiB, e.g. 16,384 segments
+ * at 2 or 4 Gauss points; larger problems return DD_ECAPACITY before any
+ * device work.  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one device (two streams, two threads) race and give wrong
+ * results; calls in one stream are ordered and safe.  Input errors are not
+ * reported (as with validation off, results are then unspecified; kernels
+ * stay in bounds).
+ * Errors: DD_EINVAL as dd_nodal_forces for host-side argument checks;
+ *  DD_ECAPACITY as above; DD_EHIP if the array's address cannot be taken. */
+int dd_nodal_forces_noalloc(int64_t n_nodes, const double *x, int64_t n_segs,
+                            const int32_t *seg_nodes, const double *burgers,
+                            const double *normal, const double *sigma_app,
+                            const dd_material *m, int n_gauss, int precision,
+                            double near_cutoff_a, double *force_out, void *stream);
+
 /* One glide-constrained forward-Euler step (Eq. DD_evol, lumped, scalar B):
  *    ell_n = 1/2 sum_{s attached to n} L_s
  *    v_n   = P_n F_n / (B ell_n),   x_n <- x_n + v_n dt

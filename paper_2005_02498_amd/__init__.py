@@ -26,7 +26,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
     "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_check", "dd_set_plan", "dd_last_plan",
-    "dd_nodal_forces", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_pta_step", "dd_pta_step_junctions",
+    "dd_nodal_forces", "dd_nodal_forces_noalloc", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_pta_step", "dd_pta_step_junctions",
     "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -118,6 +118,8 @@ def _declare(L):
         "dd_dissipation_fix": (C.c_int, [i64, vp, vp, vp, vp, vp]),
         "dd_nodal_forces": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
                                       C.POINTER(Material), C.c_int, C.c_int, dbl, dbl, vp, vp]),
+        "dd_nodal_forces_noalloc": (C.c_int, [i64, vp, i64, vp, vp, vp, C.POINTER(C.c_double),
+                                              C.POINTER(Material), C.c_int, C.c_int, dbl, vp, vp]),
         "dd_glide_step": (C.c_int, [i64, vp, vp, i64, vp, vp, vp, C.POINTER(Material), dbl,
                                     vp, vp]),
         "dd_step": (C.c_int, [i64, vp, i64, vp, vp, vp, vp, C.POINTER(C.c_double), C.POINTER(Material), C.c_int,
@@ -315,6 +317,24 @@ def dd_nodal_forces(x, seg_nodes, burgers, normal, sigma_app, mat, n_gauss=2,
     m = _mat(mat)
     _check(lib().dd_nodal_forces(nn, px, ns, psn, pb, pn, sig, C.byref(m), int(n_gauss),
                                  _prec(precision), float(near_cutoff_a), float(exact_eta), pf, _stream(stream)))
+    return force_out
+
+
+def dd_nodal_forces_noalloc(x, seg_nodes, burgers, normal, sigma_app, mat, force_out, n_gauss=2,
+                            precision=DD_FP64, near_cutoff_a=20.0, stream=None):
+    """dd_nodal_forces from the library's fixed scratch array (no allocation,
+    no synchronisation; see dd.h).  force_out [3][n_nodes] is required."""
+    nn = x.shape[1] if x.dim() == 2 else -1
+    ns = seg_nodes.shape[1] if seg_nodes.dim() == 2 else -1
+    px = _dev(x, torch.float64, (3, nn), "x")
+    psn = _dev(seg_nodes, torch.int32, (2, ns), "seg_nodes")
+    pb = _dev(burgers, torch.float64, (3, ns), "burgers")
+    pn = _dev(normal, torch.float64, (3, ns), "normal")
+    pf = _dev(force_out, torch.float64, (3, nn), "force_out")
+    sig = (C.c_double * 6)(*[float(v) for v in sigma_app])
+    m = _mat(mat)
+    _check(lib().dd_nodal_forces_noalloc(nn, px, ns, psn, pb, pn, sig, C.byref(m), int(n_gauss),
+                                         _prec(precision), float(near_cutoff_a), pf, _stream(stream)))
     return force_out
 
 

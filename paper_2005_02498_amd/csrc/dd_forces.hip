@@ -1937,3 +1937,161 @@ extern "C" int dd_burst_batch_junctions(int32_t n_inst, const int64_t *node_off,
                             features_out, stream);
 }
 
+// ======================================================= no-allocation call --
+// dd_nodal_forces_noalloc: dd_nodal_forces for callers that cannot allocate
+// (code under graph capture, serving loops).  Every buffer the force pass
+// needs beyond the caller's arrays comes from `scratch`, a file-scope device
+// array of NOALLOC_BYTES that each GPU holds from the library's load until
+// the process ends.  Host code never uses the array's name as an address:
+// its device address is taken once per device with hipGetSymbolAddress.
+namespace dd {
+namespace {
+
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};   // device address of `scratch` per device
+
+int scratch_address(void **out)
+{
+    int dev = 0;
+    DD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return set_error(DD_EINVAL, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(DD_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DD_OK;
+}
+
+// Tiles of TILE consecutive Gauss points of one volume and, per tile, C items
+// over consecutive source ranges of chunk_len; item i = tile (i / C), range
+// (i % C), partial slot i.
+__global__ void k_plan_flat(Tile *tiles, Item *items, int64_t ns, int Q, int64_t chunk_len, int64_t n_tiles,
+                            int64_t C)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_tiles * C) return;
+    const int64_t t = i / C, c = i - t * C;
+    Item it;
+    it.tile = (int32_t)t;
+    it.pad = 0;
+    it.src_begin = c * chunk_len;
+    it.src_end = min(ns, it.src_begin + chunk_len);
+    it.slot = i;
+    items[i] = it;
+    if (c == 0) {
+        Tile tl;
+        tl.point_begin = t * TILE;
+        tl.n_points = (int32_t)min((int64_t)TILE, ns * Q - t * TILE);
+        tl.n_chunks = (int32_t)C;
+        tl.slot_begin = t * C;
+        tiles[t] = tl;
+    }
+}
+
+// Carves the force pass's buffers out of the scratch array; returns the bytes
+// needed in *need (whether or not they fit).
+struct Carve {
+    unsigned char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count)
+    {
+        T *p = reinterpret_cast<T *>(base + off);
+        off += (count * sizeof(T) + 255) & ~size_t(255);
+        return p;
+    }
+};
+
+}  // namespace
+}  // namespace dd
+
+extern "C" int dd_nodal_forces_noalloc(int64_t n_nodes, const double *x, int64_t n_segs,
+                                       const int32_t *seg_nodes, const double *burgers, const double *normal,
+                                       const double *sigma_app, const dd_material *m, int n_gauss,
+                                       int precision, double near_cutoff_a, double *force_out, void *stream)
+{
+    clear_error();
+    int rc;
+    if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a))) return rc;
+    if ((rc = check_material(m, false))) return rc;
+    if (!sigma_app) return set_error(DD_EINVAL, "sigma_app is null");
+    if (n_nodes > 0 && (!x || !force_out)) return set_error(DD_EINVAL, "null x or force_out");
+    if (n_segs > 0 && (!seg_nodes || !burgers || !normal)) return set_error(DD_EINVAL, "null segment array");
+    for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(sigma_app[k])) return set_error(DD_EINVAL, "non-finite sigma_app");
+    // the work split: as dd_set_plan fixes it, else the built-in heuristic
+    // (the autotuner would allocate and synchronise)
+    const int64_t forced = g_forced_choice.load();
+    const int64_t n_tiles = (n_segs * n_gauss + TILE - 1) / TILE;
+    int64_t chunk_len = forced > 0 ? forced / MIXED_VARIANTS : 0;
+    const int variant = forced >= 0 ? (int)(forced % MIXED_VARIANTS) : 0;
+    if (chunk_len <= 0) chunk_len = heuristic_chunk(n_tiles, n_segs);
+    const int64_t n_chunks = n_segs > 0 ? (n_segs + chunk_len - 1) / chunk_len : 0;
+    const int64_t n_items = n_tiles * n_chunks;
+    // what the pass needs, in the order it is carved below
+    Carve sz{nullptr};
+    sz.take<unsigned char>(256);                                   // flags word, mixed-kernel counters
+    sz.take<double>((size_t)REC64_TOTAL * (size_t)std::max<int64_t>(n_segs, 1));
+    if (precision == DD_MIXED) sz.take<float>((size_t)REC32A * (size_t)std::max<int64_t>(n_segs, 1));
+    sz.take<double>(6 * (size_t)std::max<int64_t>(n_segs, 1));    // end forces
+    sz.take<int32_t>((size_t)n_nodes + 1);                          // node lists: offsets
+    sz.take<int32_t>(2 * (size_t)std::max<int64_t>(n_segs, 1));   //   entries
+    sz.take<int32_t>((size_t)std::max<int64_t>(n_nodes, 1));      //   counters
+    sz.take<Tile>((size_t)std::max<int64_t>(n_tiles, 1));
+    sz.take<Item>((size_t)std::max<int64_t>(n_items, 1));
+    sz.take<double>(3 * (size_t)TILE * (size_t)std::max<int64_t>(n_items, 1));   // partial sums
+    if (sz.off > NOALLOC_BYTES)
+        return set_error(DD_ECAPACITY, "dd_nodal_forces_noalloc: this problem needs %zu bytes of scratch, more "
+                         "than the %zu it has (%lld segments, %d Gauss points, %lld work items)", sz.off,
+                         NOALLOC_BYTES, (long long)n_segs, n_gauss, (long long)n_items);
+    if (n_nodes == 0) return DD_OK;
+    void *base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    Carve cv{(unsigned char *)base};
+    Workspace ws;   // addresses only: nothing here is allocated
+    ws.flags_dev = cv.take<unsigned>(64);
+    ws.near_count = (unsigned long long *)(ws.flags_dev + 32);
+    ws.capturing = true;   // no event timing (events would be created on first use)
+    ForceCtx C;
+    C.g = gauss_rule(n_gauss);
+    C.k1 = 1.0 / (8.0 * M_PI);
+    C.k2 = 1.0 / (4.0 * M_PI * (1.0 - m->nu));
+    C.a = m->a;
+    C.inv_a = 1.0 / m->a;
+    C.inv_mu = 1.0 / m->mu;
+    C.fscale = m->mu * m->a * m->a;
+    C.precision = precision;
+    C.variant = variant;
+    C.cut = (float)near_cutoff_a;
+    C.L.nn = n_nodes;
+    C.L.ns = n_segs;
+    C.rec64 = cv.take<double>((size_t)REC64_TOTAL * (size_t)std::max<int64_t>(n_segs, 1));
+    if (precision == DD_MIXED) C.rec32 = cv.take<float>((size_t)REC32A * (size_t)std::max<int64_t>(n_segs, 1));
+    C.segF = cv.take<double>(6 * (size_t)std::max<int64_t>(n_segs, 1));
+    C.csr_ptr = cv.take<int32_t>((size_t)n_nodes + 1);
+    C.csr_list = cv.take<int32_t>(2 * (size_t)std::max<int64_t>(n_segs, 1));
+    C.csr_cnt = cv.take<int32_t>((size_t)std::max<int64_t>(n_nodes, 1));
+    C.tiles = cv.take<Tile>((size_t)std::max<int64_t>(n_tiles, 1));
+    C.items = cv.take<Item>((size_t)std::max<int64_t>(n_items, 1));
+    C.partial = cv.take<double>(3 * (size_t)TILE * (size_t)std::max<int64_t>(n_items, 1));
+    C.n_items = n_items;
+    if (n_items > 0)
+        hipLaunchKernelGGL(k_plan_flat, dim3(grid_for(n_items, 256, INT32_MAX)), dim3(256), 0, st, C.tiles,
+                           C.items, n_segs, n_gauss, chunk_len, n_tiles, n_chunks);
+    launch_csr(C, seg_nodes, st);
+    Sig6 sv;
+    for (int k = 0; k < 6; ++k) sv.v[k] = sigma_app[k];
+    if ((rc = launch_forces(C, &ws, x, seg_nodes, burgers, normal, nullptr, sv, force_out, st, false))) return rc;
+    DD_HIP(hipGetLastError());
+    return DD_OK;
+}
