@@ -166,6 +166,11 @@ static void gemm(const GemmArgs &g, int members, hipStream_t st)
 // 12..35 when dens_floor > 0, f = feat otherwise.
 constexpr int SCAL = 2 * IN + 2 * OUT + 3;   // shifts/scales, dens_scale, dens_floor, spread floor
 
+// log10 of a density input (x >= dens_floor > 0): v_log_f32 (base 2, the
+// hardware's transcendental) times log10(2).  Shared by training and
+// inference so both standardize alike.
+__device__ __forceinline__ float dens_log10(float x) { return __builtin_amdgcn_logf(x) * 0.30102999566398120f; }
+
 __global__ void k_standardize(const float *__restrict__ feat, int64_t n, const float *__restrict__ scal,
                               __bf16 *__restrict__ X0)
 {
@@ -177,7 +182,7 @@ __global__ void k_standardize(const float *__restrict__ feat, int64_t n, const f
     if (k < IN) {
         float f = feat[r * IN + k];
         const float dfloor = scal[2 * IN + 2 * OUT + 1];
-        if (k >= 12 && dfloor > 0.f) f = log10f(fmaxf(f, 0.f) * scal[2 * IN + 2 * OUT] + dfloor);
+        if (k >= 12 && dfloor > 0.f) f = dens_log10(fmaxf(f, 0.f) * scal[2 * IN + 2 * OUT] + dfloor);
         v = (f - scal[k]) * scal[IN + k];
     }
     X0[i] = to_bf16(v);
@@ -308,204 +313,494 @@ __global__ void k_refresh(const float *__restrict__ w, int members, __bf16 *__re
 }
 
 // Ensemble reduction per point: rates = member mean (unstandardised),
-// spread = |population std|_2 / max(|mean|_2, 1e-30), needs_dd = spread > tol.
-__global__ void k_ensemble(const float *__restrict__ Y, int64_t sY, int members, int64_t n,
-                           const float *__restrict__ scal, float tol, float *__restrict__ rates,
-                           float *__restrict__ spread, uint8_t *__restrict__ needs_dd)
+// spread = |population std|_2 / max(|mean|_2, spread floor), needs_dd =
+// spread > tol.  A member's 12 outputs are the first three float4s of its
+// 64-byte row of Y; VEC: rates rows as float4s too (16-byte aligned rates).
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_ensemble(const float *__restrict__ Y, int64_t sY, int members, int64_t n,
+                                                  const float *__restrict__ scal, float tol,
+                                                  float *__restrict__ rates, float *__restrict__ spread,
+                                                  uint8_t *__restrict__ needs_dd)
 {
-    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (r >= n) return;
     float mean[OUT], var[OUT];
+#pragma unroll
     for (int o = 0; o < OUT; ++o) mean[o] = var[o] = 0.f;
-    for (int m = 0; m < members; ++m)
-        for (int o = 0; o < OUT; ++o)
-            mean[o] += Y[m * sY + r * OUTP + o] * scal[2 * IN + OUT + o] + scal[2 * IN + o];
-    const float im = 1.f / members;
-    for (int o = 0; o < OUT; ++o) mean[o] *= im;
-    for (int m = 0; m < members; ++m)
-        for (int o = 0; o < OUT; ++o) {
-            const float d = Y[m * sY + r * OUTP + o] * scal[2 * IN + OUT + o] + scal[2 * IN + o] - mean[o];
-            var[o] += d * d;
+    const float *osh = scal + 2 * IN, *osc = scal + 2 * IN + OUT;
+    for (int m = 0; m < members; ++m) {
+        const float4 *y = reinterpret_cast<const float4 *>(Y + m * sY + r * OUTP);
+#pragma unroll
+        for (int q = 0; q < OUT / 4; ++q) {
+            const float4 v = y[q];
+            mean[4 * q] += v.x * osc[4 * q] + osh[4 * q];
+            mean[4 * q + 1] += v.y * osc[4 * q + 1] + osh[4 * q + 1];
+            mean[4 * q + 2] += v.z * osc[4 * q + 2] + osh[4 * q + 2];
+            mean[4 * q + 3] += v.w * osc[4 * q + 3] + osh[4 * q + 3];
         }
+    }
+    const float im = 1.f / members;
+#pragma unroll
+    for (int o = 0; o < OUT; ++o) mean[o] *= im;
+    for (int m = 0; m < members; ++m) {
+        const float4 *y = reinterpret_cast<const float4 *>(Y + m * sY + r * OUTP);
+#pragma unroll
+        for (int q = 0; q < OUT / 4; ++q) {
+            const float4 v = y[q];
+            const float d[4] = {v.x * osc[4 * q] + osh[4 * q] - mean[4 * q],
+                                v.y * osc[4 * q + 1] + osh[4 * q + 1] - mean[4 * q + 1],
+                                v.z * osc[4 * q + 2] + osh[4 * q + 2] - mean[4 * q + 2],
+                                v.w * osc[4 * q + 3] + osh[4 * q + 3] - mean[4 * q + 3]};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) var[4 * q + e] += d[e] * d[e];
+        }
+    }
     float s2 = 0.f, m2 = 0.f;
+#pragma unroll
     for (int o = 0; o < OUT; ++o) {
         s2 += var[o] * im;
         m2 += mean[o] * mean[o];
-        rates[r * OUT + o] = mean[o];
+    }
+    if (VEC) {
+        float4 *ro = reinterpret_cast<float4 *>(rates + r * OUT);
+#pragma unroll
+        for (int q = 0; q < OUT / 4; ++q) ro[q] = float4{mean[4 * q], mean[4 * q + 1], mean[4 * q + 2], mean[4 * q + 3]};
+    } else {
+#pragma unroll
+        for (int o = 0; o < OUT; ++o) rates[r * OUT + o] = mean[o];
     }
     const float sp = sqrtf(s2) / fmaxf(sqrtf(m2), scal[2 * IN + 2 * OUT + 2]);
     spread[r] = sp;
     needs_dd[r] = sp > tol ? 1 : 0;
 }
 
-
 // ------------------------------------------------- fused inference kernel --
-constexpr int HSTR = HID + 8;   // LDS row stride of the activations (bf16)
+// A persistent workgroup of four waves carries tiles of IP = 128 points of
+// one member (blockIdx.y) through all four layers; workgroup x of G takes the
+// tiles x, x + G, ...  The hidden-layer products are taken transposed,
+// out^T = W x^T, on v_mfma_f32_32x32x16_bf16: the weights are the A operand
+// (32 output features x 16 inputs per tile), the activations the B operand
+// (16 inputs x 32 points).  Operand layout of that instruction: lane l holds
+// row (A) or column (B) l % 32 and the eight k values 8 (l / 32) .. +7; the
+// accumulator of lane l holds column (point) l % 32 and the 16 rows
+// (features) 8 (i / 4) + 4 (l / 32) + (i % 4), i = 0..15.
+//
+// * Weights stay in registers: wave w computes the output features 64 w ..
+//   64 w + 63 (two 32-row tiles) of every hidden layer for all the tile's
+//   points, so it holds its 2 x 16 weight fragments of a layer (128 VGPRs)
+//   and, as soon as a K step's fragments have been used, loads the next
+//   layer's fragments for that K step into them: each layer's weights arrive
+//   while the previous layer computes, and layer 2's of the next tile while
+//   layer 3 and the output layer compute.  Layer 1's fragments (24 KB per
+//   member) stay in LDS.
+// * Activations go through LDS in the B-operand layout [K step][point tile]
+//   [lane][8 bf16] (128 KB for two buffers): every wave reads each 16-byte
+//   fragment once per layer, 64 B per clock per CU at the matrix cores' rate.
+// * No data movement between layers beyond that: a lane's accumulator holds
+//   16 features of one point, exactly the 8 + 8 bf16 a lane supplies as the
+//   B operand of two K steps of the next layer, provided the next layer's
+//   weight columns are stored in the matching order.  So the layer inputs of
+//   layers 2-4 use the K order
+//     K step t, lane half h, slot s  <->  input 32 (t / 2) + 16 (t % 2) + 8 (s / 4) + 4 h + (s % 4)
+//   (the sum over K does not depend on the order), and k_refresh_infer
+//   writes the weights in it; layer 1 reads the 36 inputs in natural order,
+//   padded to 48.
+// * The bias enters as the accumulator's initial value (the C operand of a
+//   layer's first K step); the epilogue is conversion to bf16 and ReLU only.
+// * The output layer (12 outputs padded to 16) runs on
+//   v_mfma_f32_16x16x32_bf16, wave w taking point tile w as two halves of 16
+//   points.  Meanwhile the next tile's inputs, loaded into registers during
+//   layer 3, are standardized and written to LDS.
+constexpr int IP = 128;                  // points per tile
+constexpr int IWAVES = 4;
+constexpr int IK1 = 3;                   // K steps of 16 of the first layer (36 inputs)
+constexpr int IKS = HID / 16;            // K steps of 16 of layers 2 and 3
+constexpr int IK4 = HID / 32;            // K steps of 32 of the output layer
+constexpr int IMT = HID / 32 / IWAVES;   // 32-row tiles per wave in the hidden layers (2)
+constexpr int INT = IP / 32;             // point tiles (4)
+// bf16 fragments of one member's inference weights, per layer
+constexpr int64_t WI1 = (int64_t)IWAVES * IK1 * IMT * 64 * 8;
+constexpr int64_t WI2 = (int64_t)IWAVES * IKS * IMT * 64 * 8;
+constexpr int64_t WI4 = (int64_t)IK4 * 64 * 8;
+constexpr int64_t WI_PER = WI1 + 2 * WI2 + WI4;
+static_assert(WI2 == (int64_t)HID * HID, "hidden-layer fragments cover the matrix");
+static_assert(WI4 == (int64_t)OUTP * HID, "output fragments cover the padded rows");
+static_assert(IK4 <= IKS, "output fragments fit in the hidden-layer weight registers");
 
-__device__ __forceinline__ bf16x8 lds_frag(const __bf16 *p)
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Input index of slot s in lane half h of K step t, for layers 2-4.
+__host__ __device__ __forceinline__ int perm_k(int t, int h, int s)
 {
-    return *reinterpret_cast<const bf16x8 *>(p);
+    return 32 * (t / 2) + 16 * (t % 2) + 8 * (s / 4) + 4 * h + (s % 4);
 }
 
-__device__ __forceinline__ bf16x8 glb_frag(const __bf16 *p)
+// Inference weight fragments from the float32 master weights: element e of
+// the member's copy, laid out [wave][K step][row tile][lane][slot] (layers
+// 1-3; row = 64 wave + 32 tile + lane % 32) and [K step of 32][lane][slot]
+// (layer 4, the A operand of v_mfma_f32_16x16x32_bf16: row lane % 16, k
+// values 8 (lane / 16) + slot, which are the B fragments of K steps
+// 2 T + (lane / 32) and lane half (lane / 16) % 2 of the 32 x 32 layout; rows
+// 12..15 zero).
+__global__ void k_refresh_infer(const float *__restrict__ w, int members, __bf16 *__restrict__ Wi)
 {
-    return *reinterpret_cast<const bf16x8 *>(p);
-}
-
-// One workgroup (RG x CG waves) carries WROWS = 64 RG rows of one member
-// (blockIdx.y) through all four layers in one LDS buffer: the standardised
-// inputs, then each hidden layer's activations overwrite the previous ones
-// (every wave holds its output tile in registers until all waves have read
-// the layer's input).  Rows are padded by 8 bf16 so that the 16-byte fragment
-// reads of 16 consecutive rows fall in distinct banks.  Hidden layers: wave w
-// owns rows 64 (w / CG) .. +63 and output columns 16 JT (w % CG) .. +16 JT - 1
-// (4 x JT tiles of v_mfma_f32_16x16x32_bf16); bias + ReLU are applied when
-// the accumulators are written back.  The layer's weights come through LDS
-// one K step (32 inputs x 256 outputs) at a time, loaded once per workgroup
-// and read by the RG waves of every column group, so each weight reaches the
-// CU once per WROWS rows: the L2-to-CU weight traffic, which bounds a
-// workgroup of 64 rows that streams every wave's own weights, falls by RG.
-// The next slice is fetched into registers one step ahead; two barriers per
-// step guard the one slice buffer (a second does not fit beside the
-// activations).  Output layer: its weights also go through LDS, and the waves
-// split the WROWS rows in tiles of 16.
-constexpr int WRG = 4;                  // row groups of 64
-constexpr int WJT = 4;                  // 16-column tiles per wave
-constexpr int WCG = HID / (16 * WJT);   // column groups
-constexpr int WROWS = 64 * WRG;
-constexpr int WTHREADS = 64 * WRG * WCG;
-constexpr int WSTR = 32;                // LDS row stride of a weight slice (bf16)
-constexpr int WSLICE = HID * WSTR;      // one slice buffer (bf16)
-constexpr int WCHUNKS = HID * 32 / 8;   // 16-byte chunks per slice
-constexpr int WPER = (WCHUNKS + WTHREADS - 1) / WTHREADS;
-
-// Position of 16-byte chunk c (0..3) of output row o in a slice buffer: the
-// chunk index is XOR-ed with bits 1-2 of the row, so that both the fragment
-// reads (16 rows, one chunk) and the stores (4 rows, 4 chunks) of 16 lanes
-// spread over all banks.
-__device__ __forceinline__ int slice_pos(int o, int c)
-{
-    return o * WSTR + ((c ^ ((o >> 1) & 3)) << 3);
-}
-
-template <int K>
-__device__ __forceinline__ void hidden_layer(__bf16 *__restrict__ H, __bf16 *__restrict__ Ws,
-                                             const __bf16 *__restrict__ W, const float *__restrict__ bias,
-                                             int wave, int lane, int tid)
-{
-    // W: [HID][K] (out, in), K contiguous
-    constexpr int NS = K / 32;
-    f32x4 acc[4][WJT];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < WJT; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int lr = lane & 15, lk = (lane >> 4) * 8;
-    const int rg = wave / WCG, cg = wave % WCG;
-    // this thread's chunks of a slice: chunk c = output row c / 4, inputs 8 (c % 4) .. +7
-    bf16x8 pre[WPER];
-#pragma unroll
-    for (int u = 0; u < WPER; ++u) {
-        const int c = tid + u * WTHREADS;
-        if (c < WCHUNKS) pre[u] = glb_frag(W + (int64_t)(c >> 2) * K + (c & 3) * 8);
-    }
-#pragma unroll
-    for (int st = 0; st < NS; ++st) {
-        if (st > 0) __syncthreads();   // slice st - 1 read by every wave
-#pragma unroll
-        for (int u = 0; u < WPER; ++u) {
-            const int c = tid + u * WTHREADS;
-            if (c < WCHUNKS) *reinterpret_cast<bf16x8 *>(Ws + slice_pos(c >> 2, c & 3)) = pre[u];
-        }
-        if (st + 1 < NS) {
-#pragma unroll
-            for (int u = 0; u < WPER; ++u) {
-                const int c = tid + u * WTHREADS;
-                if (c < WCHUNKS) pre[u] = glb_frag(W + (int64_t)(c >> 2) * K + 32 * (st + 1) + (c & 3) * 8);
-            }
-        }
-        __syncthreads();   // slice st (and, at st = 0, the layer input) in place
-        const int k0 = 32 * st;
-        bf16x8 a[4], b[WJT];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = lds_frag(H + (64 * rg + 16 * i + lr) * HSTR + k0 + lk);
-#pragma unroll
-        for (int j = 0; j < WJT; ++j) b[j] = lds_frag(Ws + slice_pos(16 * WJT * cg + 16 * j + lr, lane >> 4));
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < WJT; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    }
-    __syncthreads();   // every wave has read the layer input and the last slice
-    for (int j = 0; j < WJT; ++j) {
-        const int n = 16 * WJT * cg + 16 * j + lr;
-        const float bn_ = bias[n];
-        for (int i = 0; i < 4; ++i)
-            for (int e = 0; e < 4; ++e) {
-                const int r = 64 * rg + 16 * i + (lane >> 4) * 4 + e;
-                H[r * HSTR + n] = to_bf16(fmaxf(acc[i][j][e] + bn_, 0.f));
-            }
-    }
-}
-
-__global__ __launch_bounds__(WTHREADS) void k_mlp_infer(const float *__restrict__ feat, int64_t n,
-                                                             const float *__restrict__ scal,
-                                                             const __bf16 *__restrict__ W1p,
-                                                             const __bf16 *__restrict__ W2,
-                                                             const __bf16 *__restrict__ W3,
-                                                             const __bf16 *__restrict__ W4p,
-                                                             const float *__restrict__ w, float *__restrict__ Y,
-                                                             int64_t sY)
-{
-    __shared__ __attribute__((aligned(16))) __bf16 H[WROWS * HSTR];
-    __shared__ __attribute__((aligned(16))) __bf16 Ws[WSLICE];
-    const int member = blockIdx.y;
-    const int64_t r0 = (int64_t)blockIdx.x * WROWS;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const float dfloor = scal[2 * IN + 2 * OUT + 1], dscale = scal[2 * IN + 2 * OUT];
-    // standardised input tile (rows beyond n and columns beyond IN are zero)
-    for (int i = tid; i < WROWS * INP; i += WTHREADS) {
-        const int r = i / INP, k = i % INP;
-        float v = 0.f;
-        if (k < IN && r0 + r < n) {
-            float f = feat[(r0 + r) * IN + k];
-            if (k >= 12 && dfloor > 0.f) f = log10f(fmaxf(f, 0.f) * dscale + dfloor);
-            v = (f - scal[k]) * scal[IN + k];
-        }
-        H[r * HSTR + k] = to_bf16(v);
-    }
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= members * WI_PER) return;
+    const int member = (int)(i / WI_PER);
+    int64_t e = i % WI_PER;
     const float *wm = w + member * P;
-    hidden_layer<INP>(H, Ws, W1p + (int64_t)member * HID * INP, wm + OB1, wave, lane, tid);
-    hidden_layer<HID>(H, Ws, W2 + (int64_t)member * HID * HID, wm + OB2, wave, lane, tid);
-    hidden_layer<HID>(H, Ws, W3 + (int64_t)member * HID * HID, wm + OB3, wave, lane, tid);
-    // the output layer's weights [16][256] to the slice buffer, row stride HSTR
-    // (every wave has finished reading the last slice inside hidden_layer)
-    static_assert(OUTP * HSTR <= WSLICE, "output weights fit the slice buffer");
-    const __bf16 *W4m = W4p + (int64_t)member * OUTP * HID;
-    for (int c = tid; c < OUTP * HID / 8; c += WTHREADS)
-        *reinterpret_cast<bf16x8 *>(Ws + (c / (HID / 8)) * HSTR + (c % (HID / 8)) * 8) = glb_frag(W4m + 8 * c);
-    __syncthreads();   // last hidden activations and output weights in place
-    // output layer: wave owns WROWS / (waves) rows in tiles of 16, 16 padded columns
-    constexpr int OT = WROWS / 16 / (WRG * WCG);   // row tiles per wave
-    {
-        const int lr = lane & 15, lk = (lane >> 4) * 8;
-        f32x4 acc[OT];
-        for (int t = 0; t < OT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float v = 0.f;
+    if (e < WI1 + 2 * WI2) {
+        int layer = 1, T = IK1;
+        int64_t base = 0;
+        if (e >= WI1) {
+            layer = e < WI1 + WI2 ? 2 : 3;
+            base = layer == 2 ? WI1 : WI1 + WI2;
+            T = IKS;
+        }
+        int64_t q = e - base;
+        const int s = (int)(q % 8); q /= 8;
+        const int lane = (int)(q % 64); q /= 64;
+        const int jj = (int)(q % IMT); q /= IMT;
+        const int t = (int)(q % T); q /= T;
+        const int wv = (int)q;
+        const int row = 64 * wv + 32 * jj + lane % 32, h = lane / 32;
+        if (layer == 1) {
+            const int k = 16 * t + 8 * h + s;
+            v = k < IN ? wm[OW1 + row * IN + k] : 0.f;
+        } else {
+            v = wm[(layer == 2 ? OW2 : OW3) + row * HID + perm_k(t, h, s)];
+        }
+    } else {
+        int64_t q = e - (WI1 + 2 * WI2);
+        const int s = (int)(q % 8); q /= 8;
+        const int lane = (int)(q % 64); q /= 64;
+        const int T = (int)q;
+        const int o = lane % 16, c = lane / 16;
+        v = o < OUT ? wm[OW4 + o * HID + perm_k(2 * T + c / 2, c % 2, s)] : 0.f;
+    }
+    Wi[i] = to_bf16(v);
+}
+
+// Fragment f (1 KB) of the weight block starting at element `block` of a
+// member's fragments, through a buffer descriptor of them (scalar registers):
+// the lane's byte offset 16 lane is the one vector register all these loads
+// share, the block and fragment offset a scalar one.
+typedef __attribute__((address_space(3))) bf16x8 lds_frag;
+
+// The LDS address of p as a base register of its own: the empty asm hides
+// the constant part from the compiler, so that accesses p[c] take c as the
+// instruction's offset (up to 64 KB) instead of one address add per access.
+__device__ __forceinline__ lds_frag *lds_base(bf16x8 *p)
+{
+    unsigned a = (unsigned)(uintptr_t)(lds_frag *)p;
+    asm volatile("" : "+v"(a));
+    return (lds_frag *)(uintptr_t)a;
+}
+
+__device__ __forceinline__ bf16x8 ldfrag(__amdgpu_buffer_rsrc_t rs, int block, int f, unsigned lane16)
+{
+    return __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)lane16, 2 * (block + 512 * f), 0));
+}
+
+// The bias of a hidden layer in the accumulator layout of row tile J:
+// element i of lane half h is feature 32 J + 8 (i / 4) + 4 h + i % 4.
+__device__ __forceinline__ void load_bias(f32x16 &bc, const float *bias, int J, int h)
+{
 #pragma unroll
-        for (int k0 = 0; k0 < HID; k0 += 32) {
-            const bf16x8 b = lds_frag(Ws + lr * HSTR + k0 + lk);
+    for (int g = 0; g < 4; ++g) {
+        const float4 b = *reinterpret_cast<const float4 *>(bias + 32 * J + 8 * g + 4 * h);
+        bc[4 * g] = b.x;
+        bc[4 * g + 1] = b.y;
+        bc[4 * g + 2] = b.z;
+        bc[4 * g + 3] = b.w;
+    }
+}
+
+// bf16(max(a, 0)), bf16(max(b, 0)) as one packed pair: rounded to bf16 first,
+// then an integer max with 0 clears the negative values (sign bit set, so
+// negative as int16).  Rounding is monotonic and keeps the sign, so this is
+// the same pair (a negative zero becomes +0).
+__device__ __forceinline__ unsigned relu_pk(float a, float b)
+{
+    const bf16x2 p = __builtin_convertvector(f32x2{a, b}, bf16x2);
+    const s16x2 q = __builtin_elementwise_max(__builtin_bit_cast(s16x2, p), s16x2{0, 0});
+    return __builtin_bit_cast(unsigned, q);
+}
+
+// Unit u (0..15) of the epilogue of one phase's accumulators ga[jj][i]
+// (point tile 2 gph + i): features 32 J + 8 g + 4 h + e, J = J0 + jj, of
+// accumulator a = u / 4 (jj = a / 2, i = a % 2), register group g = u % 4:
+// ReLU and bf16, collected in frag; groups 0-1 form the B fragment of the
+// next layer's K step 2 J and groups 2-3 that of K step 2 J + 1, each
+// written to LDS once complete.
+// dst: the fragment of K step 2 J0, point tile 2 gph and this lane.
+__device__ __forceinline__ void epi_unit(const f32x16 (&ga)[IMT][2], int u, lds_frag *dst, u32x4 &frag)
+{
+    const int a = u / 4, jj = a / 2, i = a % 2, g = u % 4;
+    frag[2 * (g % 2)] = relu_pk(ga[jj][i][4 * g], ga[jj][i][4 * g + 1]);
+    frag[2 * (g % 2) + 1] = relu_pk(ga[jj][i][4 * g + 2], ga[jj][i][4 * g + 3]);
+    if (g % 2 == 1) dst[((2 * jj + g / 2) * INT + i) * 64] = __builtin_bit_cast(bf16x8, frag);
+}
+
+// One phase of a layer: its NK K steps for point tiles 2 ph and 2 ph + 1 into
+// acc, starting from the bias bc.  Every step, in this order (kept by a
+// scheduling barrier): the LDS reads of the next step's B fragments, this
+// step's four MFMAs, one unit of the guest epilogue (GUEST: the other phase's
+// accumulators ga, of this or the previous layer; VALU work that runs while
+// the matrix core works), and loads into the weight registers the step has
+// used:
+//   NEXT = 1: the next hidden layer's fragments of this step (both row tiles,
+//             from block wn of the descriptor rs);
+//   NEXT = 2: row tile 1 <- layer 2 (block wn2); row tile 0 <- the output
+//             layer's fragment t (block wn) for t < IK4, layer 2 after that.
+// At the last step, bc <- the bias of the next phase (nbias), which its step
+// 0 reads.
+// Units of the guest epilogue beyond NK are done after the loop.
+template <int NK, bool GUEST, int NEXT, int NW>
+__device__ __forceinline__ void run_phase(bf16x8 (&Wr)[NW][IMT], bf16x8 (*src)[INT][64], int ph, int lane,
+                                          f32x16 (&acc)[IMT][2], f32x16 (&bc)[IMT], const float *nbias,
+                                          const f32x16 (&ga)[IMT][2], bf16x8 (*gdst)[INT][64], int gph, int J0,
+                                          int h, __amdgpu_buffer_rsrc_t rs, int wn, int wn2)
+{
+    bf16x8 b[NK][2];
+    u32x4 frag{};
+    lds_frag *sb = lds_base(&src[0][2 * ph][lane]);
+    lds_frag *db = GUEST ? lds_base(&gdst[2 * J0][2 * gph][lane]) : nullptr;
+    b[0][0] = sb[0];
+    b[0][1] = sb[64];
 #pragma unroll
-            for (int t = 0; t < OT; ++t) {
-                const bf16x8 a = lds_frag(H + (16 * (OT * wave + t) + lr) * HSTR + k0 + lk);
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+    for (int t = 0; t < NK; ++t) {
+        if (t + 1 < NK) {
+            b[t + 1][0] = sb[(t + 1) * INT * 64];
+            b[t + 1][1] = sb[(t + 1) * INT * 64 + 64];
+        }
+#pragma unroll
+        for (int jj = 0; jj < IMT; ++jj)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                acc[jj][i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wr[t][jj], b[t][i], t == 0 ? bc[jj] : acc[jj][i],
+                                                                      0, 0, 0);
+        if (GUEST && t < 16) epi_unit(ga, t, db, frag);
+        if (t == NK - 1) {
+#pragma unroll
+            for (int jj = 0; jj < IMT; ++jj) load_bias(bc[jj], nbias, J0 + jj, h);
+        }
+        if (NEXT == 1) {
+#pragma unroll
+            for (int jj = 0; jj < IMT; ++jj) Wr[t][jj] = ldfrag(rs, wn, t * IMT + jj, 16u * lane);
+        } else if (NEXT == 2) {
+            Wr[t][1] = ldfrag(rs, wn2, t * IMT + 1, 16u * lane);
+            Wr[t][0] = t < IK4 ? ldfrag(rs, wn, t, 16u * lane) : ldfrag(rs, wn2, t * IMT, 16u * lane);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (GUEST) {
+#pragma unroll
+        for (int u = NK; u < 16; ++u) epi_unit(ga, u, db, frag);
+    }
+}
+
+// Inputs of one tile, loaded a tile ahead: thread tid takes point p = tid %
+// IP of the tile and the groups of eight inputs g = g0, g0 + 2, g0 + 4 (g0 =
+// tid / IP): group g holds inputs 8 g .. 8 g + 7 (group 4: 32..35 and
+// padding; group 5: padding only).  Two float4s per group (one for group 4);
+// a row of 36 floats is nine float4s.  Rows at or beyond n read row n - 1
+// instead (their outputs are not stored); threads with g0 = 1 read a fifth
+// float4 of their own row that they do not use.
+__device__ __forceinline__ void load_inputs(float4 (&fv)[5], const float4 *__restrict__ f4, int64_t row, int64_t n,
+                                            int g0)
+{
+    const float4 *q = f4 + (row < n ? row : n - 1) * 9 + 2 * g0;
+    fv[0] = q[0];
+    fv[1] = q[1];
+    fv[2] = q[4];
+    fv[3] = q[5];
+    fv[4] = q[8 - 8 * g0];
+}
+
+// Group G0 + 2 j (j = 0..2) of the point's inputs to LDS: standardized
+// (f - shift[k]) * scale[k], with f = log10(max(f, 0) dens_scale + dens_floor)
+// for k >= 12 when the density transform is on, as the bf16 fragment
+// act0[g / 2][p / 32][32 (g % 2) + p % 32] (inputs 36..47 zero).
+template <int G0>
+__device__ __forceinline__ void scatter_inputs(const float4 (&fv)[5], bf16x8 (*act0)[INT][64], int p,
+                                               const float *scal_s, bool dlog, float dscale, float dfloor)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int g = G0 + 2 * j;
+        bf16x8 o{};
+        if (g < 5) {
+            const float v[8] = {fv[2 * j].x, fv[2 * j].y, fv[2 * j].z, fv[2 * j].w,
+                                fv[2 * j + 1].x, fv[2 * j + 1].y, fv[2 * j + 1].z, fv[2 * j + 1].w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * g + e;
+                if (k < IN) {
+                    float f = j == 2 ? (&fv[4].x)[e & 3] : v[e];
+                    if (k >= 12) f = dlog ? dens_log10(fmaxf(f, 0.f) * dscale + dfloor) : f;
+                    o[e] = to_bf16((f - scal_s[k]) * scal_s[IN + k]);
+                }
             }
         }
-        const int o = lr;
-        const float bo = o < OUT ? wm[OB4 + o] : 0.f;
-        for (int t = 0; t < OT; ++t)
-            for (int e = 0; e < 4; ++e) {
-                const int64_t r = r0 + 16 * (OT * wave + t) + (lane >> 4) * 4 + e;
-                if (r < n) Y[member * sY + r * OUTP + o] = acc[t][e] + bo;
+        act0[g / 2][p / 32][32 * (g % 2) + p % 32] = o;
+    }
+}
+
+__global__ __launch_bounds__(64 * IWAVES, 1) void k_mlp_infer(const float *__restrict__ feat, int64_t n,
+                                                              int ntiles, const float *__restrict__ scal,
+                                                              const __bf16 *__restrict__ Wi,
+                                                              const float *__restrict__ w, float *__restrict__ Y,
+                                                              int64_t sY)
+{
+    // activations: [buffer][K step][point tile][lane] of 8 bf16
+    __shared__ bf16x8 act[2][IKS][INT][64];
+    // the biases of layers 1-3 and of the output layer (padded to 16)
+    __shared__ __attribute__((aligned(16))) float bias_s[3 * HID + OUTP];
+    // input shifts and scales
+    __shared__ __attribute__((aligned(16))) float scal_s[2 * IN];
+    // layer 1's weight fragments [wave][K step][row tile][lane] (24 KB)
+    __shared__ bf16x8 w1s[IWAVES][IK1][IMT][64];
+    static_assert(HID == 64 * IWAVES, "one bias of each layer per thread");
+    static_assert(IP == 128 && 64 * IWAVES == 2 * IP, "two threads per point for the inputs");
+    static_assert(WI1 % (8 * 64 * IWAVES) == 0, "whole fragments per thread");
+    const int member = blockIdx.y, G = gridDim.x;
+    const int tid = threadIdx.x, lane = tid & 63, h = lane >> 5;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform in the wave
+    const unsigned lane16 = 16u * lane;
+    const int p_in = tid % IP, g0 = __builtin_amdgcn_readfirstlane(tid / IP);   // uniform in the wave
+    const __bf16 *wi = Wi + member * WI_PER;
+    const float *wm = w + member * P;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16 *>(wi), 0,
+                                                                         (int)(2 * WI_PER), 0x00020000);
+    // element offsets of this wave's weight blocks of layers 2 and 3 and of the output layer's
+    const int w2 = (int)(WI1 + wv * IKS * IMT * 512), w3 = (int)(WI1 + WI2 + wv * IKS * IMT * 512);
+    const int w4 = (int)(WI1 + 2 * WI2);
+    const float4 *f4 = reinterpret_cast<const float4 *>(feat);
+    const float dfloor = scal[2 * IN + 2 * OUT + 1], dscale = scal[2 * IN + 2 * OUT];
+    const bool dlog = dfloor > 0.f;
+    bf16x8 Wr[IKS][IMT];   // weight fragments of layers 2-4 in registers
+    float4 fv[5];          // the next tile's inputs
+    // Start: the first tile's inputs, the input shift and scale, the biases
+    // and layer 1's weights to LDS; then layer 2's weights (arriving while the
+    // inputs are standardized).
+    int tile = blockIdx.x;
+    load_inputs(fv, f4, (int64_t)tile * IP + p_in, n, g0);
+    const float sc = tid < 2 * IN ? scal[tid] : 0.f;
+    const float bl1 = wm[OB1 + tid], bl2 = wm[OB2 + tid], bl3 = wm[OB3 + tid];
+    const float bl4 = tid < OUT ? wm[OB4 + tid] : 0.f;
+    constexpr int W1PT = (int)(WI1 / (8 * 64 * IWAVES));   // fragments of 16 B per thread
+    bf16x8 w1v[W1PT];
+#pragma unroll
+    for (int u = 0; u < W1PT; ++u) w1v[u] = ldfrag(rs, 0, u * IWAVES + wv, lane16);
+    if (tid < 2 * IN) scal_s[tid] = sc;
+    bias_s[tid] = bl1;
+    bias_s[HID + tid] = bl2;
+    bias_s[2 * HID + tid] = bl3;
+    if (tid < OUTP) bias_s[3 * HID + tid] = bl4;
+#pragma unroll
+    for (int u = 0; u < W1PT; ++u) (&w1s[0][0][0][0])[(u * IWAVES + wv) * 64 + lane] = w1v[u];
+    __syncthreads();
+    if (g0 == 0)
+        scatter_inputs<0>(fv, act[0], p_in, scal_s, dlog, dscale, dfloor);
+    else
+        scatter_inputs<1>(fv, act[0], p_in, scal_s, dlog, dscale, dfloor);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < IKS; ++t)
+#pragma unroll
+        for (int jj = 0; jj < IMT; ++jj) Wr[t][jj] = ldfrag(rs, w2, t * IMT + jj, lane16);
+    f32x16 bc[IMT];   // the bias of the layer being computed, in accumulator layout
+    const int J0 = IMT * wv;
+#pragma unroll
+    for (int jj = 0; jj < IMT; ++jj) load_bias(bc[jj], bias_s, J0 + jj, h);
+    __syncthreads();
+    // Per tile, layers 1-3 in two phases each (point tiles 0-1, then 2-3),
+    // one barrier between phases.  Layer l + 1's phase p needs only layer l's
+    // phase-p outputs, so each phase's epilogue runs inside the next phase:
+    //   L1.0 | L1.1 + epi L1.0 | bar | L2.0 + epi L1.1 | bar | L2.1 + epi L2.0 | bar
+    //   L3.0 + epi L2.1 | bar | L3.1 + epi L3.0, epi L3.1 | bar | output layer + next inputs | bar
+    // Buffers: layer 1 reads 0 and writes 1, layer 2 reads 1 and writes 0,
+    // layer 3 reads 0 and writes 1, the output layer reads 1 while the next
+    // tile's inputs go to 0; an epilogue writes point tiles of its own phase
+    // only, which no wave reads until the next barrier, and the tiles it
+    // overwrites were last read two barriers earlier.
+    f32x16 acc[2][IMT][2];   // [phase][row tile][point tile within the phase]
+    for (; tile < ntiles; tile += G) {
+        const bool more = tile + G < ntiles;
+        {
+            bf16x8 W1r[IK1][IMT];   // layer 1's fragments, from LDS for this layer only
+#pragma unroll
+            for (int t = 0; t < IK1; ++t)
+#pragma unroll
+                for (int jj = 0; jj < IMT; ++jj) W1r[t][jj] = w1s[wv][t][jj][lane];
+            run_phase<IK1, false, 0>(W1r, act[0], 0, lane, acc[0], bc, bias_s, acc[1], act[1], 1, J0, h, rs, 0, 0);
+            run_phase<IK1, true, 0>(W1r, act[0], 1, lane, acc[1], bc, bias_s + HID, acc[0], act[1], 0, J0, h,
+                                    rs, 0, 0);
+        }
+        __syncthreads();
+        run_phase<IKS, true, 0>(Wr, act[1], 0, lane, acc[0], bc, bias_s + HID, acc[1], act[1], 1, J0, h, rs, 0, 0);
+        __syncthreads();
+        run_phase<IKS, true, 1>(Wr, act[1], 1, lane, acc[1], bc, bias_s + 2 * HID, acc[0], act[0], 0, J0, h, rs, w3, 0);
+        __syncthreads();
+        // the next tile's inputs, two phases ahead of their use
+        if (more) load_inputs(fv, f4, (int64_t)(tile + G) * IP + p_in, n, g0);
+        run_phase<IKS, true, 0>(Wr, act[0], 0, lane, acc[0], bc, bias_s + 2 * HID, acc[1], act[0], 1, J0, h,
+                                rs, 0, 0);
+        __syncthreads();
+        run_phase<IKS, true, 2>(Wr, act[0], 1, lane, acc[1], bc, bias_s, acc[0], act[1], 0, J0, h, rs, w4, w2);
+        {
+            u32x4 frag{};
+            lds_frag *db = lds_base(&act[1][2 * J0][2][lane]);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) epi_unit(acc[1], u, db, frag);
+        }
+        __syncthreads();
+        // ---- output layer: wave wv takes point tile wv (reads buffer 1) as
+        // two halves of 16 points on v_mfma_f32_16x16x32_bf16; lane l reads
+        // the fragment of K step 2 T + l / 32, lane half (l / 16) % 2
+        {
+            const int c = lane >> 4;
+            bf16x8 *ob = &act[1][c >> 1][wv][32 * (c & 1) + (lane & 15)];
+            f32x4 o0 = {}, o1 = {};
+            bf16x8 b[IK4][2];
+#pragma unroll
+            for (int T = 0; T < 2; ++T) {
+                b[T][0] = ob[2 * T * INT * 64];
+                b[T][1] = ob[2 * T * INT * 64 + 16];
             }
+#pragma unroll
+            for (int T = 0; T < IK4; ++T) {
+                if (T + 2 < IK4) {
+                    b[T + 2][0] = ob[2 * (T + 2) * INT * 64];
+                    b[T + 2][1] = ob[2 * (T + 2) * INT * 64 + 16];
+                }
+                o0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wr[T][0], b[T][0], o0, 0, 0, 0);
+                o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wr[T][0], b[T][1], o1, 0, 0, 0);
+                if (T == 0) {   // (after the last tile: stale inputs, never read)
+                    if (g0 == 0)
+                        scatter_inputs<0>(fv, act[0], p_in, scal_s, dlog, dscale, dfloor);
+                    else
+                        scatter_inputs<1>(fv, act[0], p_in, scal_s, dlog, dscale, dfloor);
+                }
+                Wr[T][0] = ldfrag(rs, w2, T * IMT, lane16);   // (after the last tile: unused)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // accumulator of lane l: point l % 16 of the half, outputs 4 c .. 4 c + 3
+            const float4 bb = *reinterpret_cast<const float4 *>(bias_s + 3 * HID + 4 * c);
+            const int64_t r = (int64_t)tile * IP + 32 * wv + (lane & 15);
+            float *y = Y + member * sY + r * OUTP + 4 * c;
+            if (r < n) *reinterpret_cast<float4 *>(y) = float4{o0[0] + bb.x, o0[1] + bb.y, o0[2] + bb.z, o0[3] + bb.w};
+            if (r + 16 < n)
+                *reinterpret_cast<float4 *>(y + 16 * OUTP) =
+                    float4{o1[0] + bb.x, o1[1] + bb.y, o1[2] + bb.z, o1[3] + bb.w};
+        }
+        __syncthreads();
     }
 }
 
@@ -519,9 +814,11 @@ using namespace dd::mlp;
 struct dd_mlp {
     int members = 0;
     int device = -1;
+    int cus = 1;                                          // compute units of that device
     float *w = nullptr, *m1 = nullptr, *m2 = nullptr;   // [members][P]
     int64_t t = 0;                                        // Adam steps taken
     __bf16 *W1p = nullptr, *W2 = nullptr, *W3 = nullptr, *W4p = nullptr;
+    __bf16 *Wi = nullptr;                                 // inference fragments [members][WI_PER]
     float *scal = nullptr;                                // device [2*36 + 2*12]
     float h_scal[SCAL];                                   // host copy
     float *dW1 = nullptr, *dW2 = nullptr, *dW3 = nullptr, *dW4 = nullptr, *db = nullptr;
@@ -602,6 +899,9 @@ int refresh(dd_mlp *h, hipStream_t st)
     const int64_t tot = per * h->members;
     hipLaunchKernelGGL(k_refresh, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, h->w, h->members,
                        h->W1p, h->W2, h->W3, h->W4p);
+    const int64_t ti = WI_PER * h->members;
+    hipLaunchKernelGGL(k_refresh_infer, dim3((unsigned)((ti + 255) / 256)), dim3(256), 0, st, h->w, h->members,
+                       h->Wi);
     DD_HIP(hipGetLastError());
     return DD_OK;
 }
@@ -749,6 +1049,8 @@ extern "C" int dd_mlp_create(int n_members, uint64_t seed, dd_mlp **out)
     h->members = n_members;
     int rc = DD_OK;
     if (hipGetDevice(&h->device) != hipSuccess) rc = set_error(DD_EHIP, "hipGetDevice failed");
+    if (!rc && hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess)
+        rc = set_error(DD_EHIP, "hipDeviceGetAttribute failed");
     const int64_t M = n_members;
     if (!rc) rc = dev_alloc((void **)&h->w, sizeof(float) * M * P);
     if (!rc) rc = dev_alloc((void **)&h->m1, sizeof(float) * M * P);
@@ -757,6 +1059,7 @@ extern "C" int dd_mlp_create(int n_members, uint64_t seed, dd_mlp **out)
     if (!rc) rc = dev_alloc((void **)&h->W2, sizeof(__bf16) * M * HID * HID);
     if (!rc) rc = dev_alloc((void **)&h->W3, sizeof(__bf16) * M * HID * HID);
     if (!rc) rc = dev_alloc((void **)&h->W4p, sizeof(__bf16) * M * OUTP * HID);
+    if (!rc) rc = dev_alloc((void **)&h->Wi, sizeof(__bf16) * M * WI_PER);
     if (!rc) rc = dev_alloc((void **)&h->scal, sizeof(float) * SCAL);
     if (!rc) rc = dev_alloc((void **)&h->dW1, sizeof(float) * M * HID * INP);
     if (!rc) rc = dev_alloc((void **)&h->dW2, sizeof(float) * M * HID * HID);
@@ -809,7 +1112,8 @@ extern "C" int dd_mlp_destroy(dd_mlp *h)
     if (!h) return DD_OK;
     (void)hipDeviceSynchronize();
     free_rows(h);
-    void *ps[] = {h->w, h->m1, h->m2, h->W1p, h->W2, h->W3, h->W4p, h->scal, h->dW1, h->dW2, h->dW3, h->dW4, h->db};
+    void *ps[] = {h->w, h->m1, h->m2, h->W1p, h->W2, h->W3, h->W4p, h->Wi, h->scal, h->dW1, h->dW2, h->dW3, h->dW4,
+                  h->db};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     delete h;
@@ -943,16 +1247,23 @@ extern "C" int dd_surrogate_rates(const dd_mlp *hc, int64_t n, const float *feat
     if (n == 0) return DD_OK;
     if (!feat || !rates || !spread || !needs_dd) return set_error(DD_EINVAL, "null array");
     if (!(spread_tol >= 0.f)) return set_error(DD_EINVAL, "spread_tol must be >= 0");
+    if ((uintptr_t)feat % 16 != 0) return set_error(DD_EINVAL, "feat must be 16-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     const int64_t chunk = std::min<int64_t>(n, INFER_CHUNK);
     if ((rc = ensure_rows(h, chunk, false))) return rc;
     for (int64_t r0 = 0; r0 < n; r0 += chunk) {
         const int64_t m = std::min(chunk, n - r0);
-        dim3 grid((unsigned)((m + WROWS - 1) / WROWS), h->members);
-        hipLaunchKernelGGL(k_mlp_infer, grid, dim3(WTHREADS), 0, st, feat + r0 * IN, m, h->scal, h->W1p, h->W2,
-                           h->W3, h->W4p, h->w, h->Y, m * OUTP);
-        hipLaunchKernelGGL(k_ensemble, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, h->Y, m * OUTP,
-                           h->members, m, h->scal, spread_tol, rates + r0 * OUT, spread + r0, needs_dd + r0);
+        const int ntiles = (int)((m + IP - 1) / IP);
+        dim3 grid((unsigned)std::min(ntiles, std::max(1, h->cus / h->members)), h->members);
+        hipLaunchKernelGGL(k_mlp_infer, grid, dim3(64 * IWAVES), 0, st, feat + r0 * IN, m, ntiles, h->scal, h->Wi,
+                           h->w, h->Y, m * OUTP);
+        float *ro = rates + r0 * OUT;
+        if ((uintptr_t)ro % 16 == 0)
+            hipLaunchKernelGGL(k_ensemble<true>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, h->Y,
+                               m * OUTP, h->members, m, h->scal, spread_tol, ro, spread + r0, needs_dd + r0);
+        else
+            hipLaunchKernelGGL(k_ensemble<false>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, h->Y,
+                               m * OUTP, h->members, m, h->scal, spread_tol, ro, spread + r0, needs_dd + r0);
     }
     DD_HIP(hipGetLastError());
     return DD_OK;
