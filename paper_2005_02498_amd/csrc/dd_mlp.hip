@@ -165,11 +165,18 @@ static void gemm(const GemmArgs &g, int members, hipStream_t st)
 // f = log10(max(feat, 0) * dens_scale + dens_floor) for the density features
 // 12..35 when dens_floor > 0, f = feat otherwise.
 constexpr int SCAL = 2 * IN + 2 * OUT + 3;   // shifts/scales, dens_scale, dens_floor, spread floor
+constexpr float LOG10_2 = 0.30102999566398120f;
 
-// log10 of a density input (x >= dens_floor > 0): v_log_f32 (base 2, the
-// hardware's transcendental) times log10(2).  Shared by training and
-// inference so both standardize alike.
-__device__ __forceinline__ float dens_log10(float x) { return __builtin_amdgcn_logf(x) * 0.30102999566398120f; }
+// The standardization as one multiply-add, identical in training and
+// inference: bf16(std_in(f, a, b)) with a = scale[k] (times log10(2) for a
+// density input, whose f is then log2 of its argument) and b = -shift[k]
+// scale[k].  log2 is v_log_f32, the hardware's transcendental; its argument
+// max(feat, 0) dens_scale + dens_floor is at least dens_floor > 0.
+__device__ __forceinline__ float dens_log2(float f, float dscale, float dfloor)
+{
+    return __builtin_amdgcn_logf(fmaf(fmaxf(f, 0.f), dscale, dfloor));
+}
+__device__ __forceinline__ float std_in(float f, float a, float b) { return fmaf(f, a, b); }
 
 __global__ void k_standardize(const float *__restrict__ feat, int64_t n, const float *__restrict__ scal,
                               __bf16 *__restrict__ X0)
@@ -181,9 +188,13 @@ __global__ void k_standardize(const float *__restrict__ feat, int64_t n, const f
     float v = 0.f;
     if (k < IN) {
         float f = feat[r * IN + k];
-        const float dfloor = scal[2 * IN + 2 * OUT + 1];
-        if (k >= 12 && dfloor > 0.f) f = dens_log10(fmaxf(f, 0.f) * scal[2 * IN + 2 * OUT] + dfloor);
-        v = (f - scal[k]) * scal[IN + k];
+        const float dfloor = scal[2 * IN + 2 * OUT + 1], sc = scal[IN + k];
+        float a = sc;
+        if (k >= 12 && dfloor > 0.f) {
+            f = dens_log2(f, scal[2 * IN + 2 * OUT], dfloor);
+            a = sc * LOG10_2;
+        }
+        v = std_in(f, a, -scal[k] * sc);
     }
     X0[i] = to_bf16(v);
 }
@@ -391,8 +402,7 @@ __global__ __launch_bounds__(256) void k_ensemble(const float *__restrict__ Y, i
 //   and, as soon as a K step's fragments have been used, loads the next
 //   layer's fragments for that K step into them: each layer's weights arrive
 //   while the previous layer computes, and layer 2's of the next tile while
-//   layer 3 and the output layer compute.  Layer 1's fragments (24 KB per
-//   member) stay in LDS.
+//   layer 3 and the output layer compute.  Layer 1's 24 registers stay.
 // * Activations go through LDS in the B-operand layout [K step][point tile]
 //   [lane][8 bf16] (128 KB for two buffers): every wave reads each 16-byte
 //   fragment once per layer, 64 B per clock per CU at the matrix cores' rate.
@@ -409,8 +419,9 @@ __global__ __launch_bounds__(256) void k_ensemble(const float *__restrict__ Y, i
 //   layer's first K step); the epilogue is conversion to bf16 and ReLU only.
 // * The output layer (12 outputs padded to 16) runs on
 //   v_mfma_f32_16x16x32_bf16, wave w taking point tile w as two halves of 16
-//   points.  Meanwhile the next tile's inputs, loaded into registers during
-//   layer 3, are standardized and written to LDS.
+//   points.
+// * The next tile's inputs are loaded into registers during layer 2 and
+//   standardized into an LDS buffer of their own during layer 3.
 constexpr int IP = 128;                  // points per tile
 constexpr int IWAVES = 4;
 constexpr int IK1 = 3;                   // K steps of 16 of the first layer (36 inputs)
@@ -550,22 +561,26 @@ __device__ __forceinline__ void epi_unit(const f32x16 (&ga)[IMT][2], int u, lds_
 // One phase of a layer: its NK K steps for point tiles 2 ph and 2 ph + 1 into
 // acc, starting from the bias bc.  Every step, in this order (kept by a
 // scheduling barrier): the LDS reads of the next step's B fragments, this
-// step's four MFMAs, one unit of the guest epilogue (GUEST: the other phase's
-// accumulators ga, of this or the previous layer; VALU work that runs while
-// the matrix core works), and loads into the weight registers the step has
-// used:
+// step's four MFMAs, 16 / NK units of the guest epilogue (GUEST: the other
+// phase's accumulators ga, of this or the previous layer; VALU work that runs
+// while the matrix core works), and loads into the weight registers the step
+// has used:
 //   NEXT = 1: the next hidden layer's fragments of this step (both row tiles,
 //             from block wn of the descriptor rs);
 //   NEXT = 2: row tile 1 <- layer 2 (block wn2); row tile 0 <- the output
 //             layer's fragment t (block wn) for t < IK4, layer 2 after that.
 // At the last step, bc <- the bias of the next phase (nbias), which its step
-// 0 reads.
-// Units of the guest epilogue beyond NK are done after the loop.
-template <int NK, bool GUEST, int NEXT, int NW>
+// 0 reads.  extra(t) runs after the step's epilogue units (more VALU work
+// under the MFMAs).
+struct NoExtra {
+    __device__ void operator()(int) const {}
+};
+template <int NK, bool GUEST, int NEXT, int NW, class Extra = NoExtra>
 __device__ __forceinline__ void run_phase(bf16x8 (&Wr)[NW][IMT], bf16x8 (*src)[INT][64], int ph, int lane,
                                           f32x16 (&acc)[IMT][2], f32x16 (&bc)[IMT], const float *nbias,
                                           const f32x16 (&ga)[IMT][2], bf16x8 (*gdst)[INT][64], int gph, int J0,
-                                          int h, __amdgpu_buffer_rsrc_t rs, int wn, int wn2)
+                                          int h, __amdgpu_buffer_rsrc_t rs, int wn, int wn2,
+                                          const Extra &extra = Extra())
 {
     bf16x8 b[NK][2];
     u32x4 frag{};
@@ -585,7 +600,11 @@ __device__ __forceinline__ void run_phase(bf16x8 (&Wr)[NW][IMT], bf16x8 (*src)[I
             for (int i = 0; i < 2; ++i)
                 acc[jj][i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Wr[t][jj], b[t][i], t == 0 ? bc[jj] : acc[jj][i],
                                                                       0, 0, 0);
-        if (GUEST && t < 16) epi_unit(ga, t, db, frag);
+        if (GUEST) {   // units t 16 / NK .. (t + 1) 16 / NK - 1 of the guest epilogue
+#pragma unroll
+            for (int u = t * 16 / NK; u < (t + 1) * 16 / NK; ++u) epi_unit(ga, u, db, frag);
+        }
+        extra(t);
         if (t == NK - 1) {
 #pragma unroll
             for (int jj = 0; jj < IMT; ++jj) load_bias(bc[jj], nbias, J0 + jj, h);
@@ -599,19 +618,15 @@ __device__ __forceinline__ void run_phase(bf16x8 (&Wr)[NW][IMT], bf16x8 (*src)[I
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    if (GUEST) {
-#pragma unroll
-        for (int u = NK; u < 16; ++u) epi_unit(ga, u, db, frag);
-    }
 }
 
-// Inputs of one tile, loaded a tile ahead: thread tid takes point p = tid %
-// IP of the tile and the groups of eight inputs g = g0, g0 + 2, g0 + 4 (g0 =
-// tid / IP): group g holds inputs 8 g .. 8 g + 7 (group 4: 32..35 and
-// padding; group 5: padding only).  Two float4s per group (one for group 4);
-// a row of 36 floats is nine float4s.  Rows at or beyond n read row n - 1
-// instead (their outputs are not stored); threads with g0 = 1 read a fifth
-// float4 of their own row that they do not use.
+// Inputs of one tile, loaded during the previous tile: thread tid takes point
+// p = tid % IP of the tile and the groups of eight inputs g = g0, g0 + 2,
+// g0 + 4 (g0 = tid / IP): group g holds inputs 8 g .. 8 g + 7 (group 4:
+// 32..35 and padding; group 5: padding only).  Two float4s per group (one for
+// group 4); a row of 36 floats is nine float4s.  Rows at or beyond n read row
+// n - 1 instead (their outputs are not stored); threads with g0 = 1 read a
+// fifth float4 of their own row that they do not use.
 __device__ __forceinline__ void load_inputs(float4 (&fv)[5], const float4 *__restrict__ f4, int64_t row, int64_t n,
                                             int g0)
 {
@@ -623,34 +638,66 @@ __device__ __forceinline__ void load_inputs(float4 (&fv)[5], const float4 *__res
     fv[4] = q[8 - 8 * g0];
 }
 
-// Group G0 + 2 j (j = 0..2) of the point's inputs to LDS: standardized
-// (f - shift[k]) * scale[k], with f = log10(max(f, 0) dens_scale + dens_floor)
-// for k >= 12 when the density transform is on, as the bf16 fragment
-// act0[g / 2][p / 32][32 (g % 2) + p % 32] (inputs 36..47 zero).
-template <int G0>
-__device__ __forceinline__ void scatter_inputs(const float4 (&fv)[5], bf16x8 (*act0)[INT][64], int p,
-                                               const float *scal_s, bool dlog, float dscale, float dfloor)
+// Group G of the point's inputs, standardized (std_in with the coefficients
+// a = coef[k], b = coef[IN + k]), to LDS as one bf16 fragment: dst is the
+// fragment of group 0 of the point (K step 0, lane p % 32 of point tile
+// p / 32); group G is K step G / 2, lane half G % 2.  Inputs 36..47 are zero.
+template <int G>
+__device__ __forceinline__ void scatter_group(float4 f0, float4 f1, lds_frag *dst, const float *coef, bool dlog,
+                                              float dscale, float dfloor)
 {
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const int g = G0 + 2 * j;
-        bf16x8 o{};
-        if (g < 5) {
-            const float v[8] = {fv[2 * j].x, fv[2 * j].y, fv[2 * j].z, fv[2 * j].w,
-                                fv[2 * j + 1].x, fv[2 * j + 1].y, fv[2 * j + 1].z, fv[2 * j + 1].w};
+    bf16x8 o{};
+    if (G < 5) {
+        const float v[8] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+        if (dlog && G >= 1) {   // groups holding density inputs (k >= 12)
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
-                const int k = 8 * g + e;
-                if (k < IN) {
-                    float f = j == 2 ? (&fv[4].x)[e & 3] : v[e];
-                    if (k >= 12) f = dlog ? dens_log10(fmaxf(f, 0.f) * dscale + dfloor) : f;
-                    o[e] = to_bf16((f - scal_s[k]) * scal_s[IN + k]);
-                }
+                const int k = 8 * G + e;
+                if (k < IN) o[e] = to_bf16(std_in(k >= 12 ? dens_log2(v[e], dscale, dfloor) : v[e], coef[k], coef[IN + k]));
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * G + e;
+                if (k < IN) o[e] = to_bf16(std_in(v[e], coef[k], coef[IN + k]));
             }
         }
-        act0[g / 2][p / 32][32 * (g % 2) + p % 32] = o;
+    }
+    dst[(G / 2) * INT * 64 + 32 * (G % 2)] = o;
+}
+
+// Group j (0..2) of this thread's inputs: g = g0 + 2 j.
+__device__ __forceinline__ void scatter_item(int j, int g0, const float4 (&fv)[5], lds_frag *dst, const float *coef,
+                                             bool dlog, float dscale, float dfloor)
+{
+    const float4 z = {0.f, 0.f, 0.f, 0.f};
+    if (g0 == 0) {
+        if (j == 0) scatter_group<0>(fv[0], fv[1], dst, coef, dlog, dscale, dfloor);
+        if (j == 1) scatter_group<2>(fv[2], fv[3], dst, coef, dlog, dscale, dfloor);
+        if (j == 2) scatter_group<4>(fv[4], z, dst, coef, dlog, dscale, dfloor);
+    } else {
+        if (j == 0) scatter_group<1>(fv[0], fv[1], dst, coef, dlog, dscale, dfloor);
+        if (j == 1) scatter_group<3>(fv[2], fv[3], dst, coef, dlog, dscale, dfloor);
+        if (j == 2) scatter_group<5>(z, z, dst, coef, dlog, dscale, dfloor);
     }
 }
+
+// The scatter of the next tile's inputs as extra work of a layer-3 phase:
+// items 0 and 1 at steps 5 and 11 of the first phase, item 2 at step 5 of
+// the second.
+struct ScatterExtra {
+    int first_item, g0;
+    const float4 (&fv)[5];
+    lds_frag *dst;
+    const float *coef;
+    bool dlog;
+    float dscale, dfloor;
+    __device__ void operator()(int t) const
+    {
+        if (t == 5) scatter_item(first_item, g0, fv, dst, coef, dlog, dscale, dfloor);
+        if (t == 11 && first_item == 0) scatter_item(1, g0, fv, dst, coef, dlog, dscale, dfloor);
+    }
+};
 
 __global__ __launch_bounds__(64 * IWAVES, 1) void k_mlp_infer(const float *__restrict__ feat, int64_t n,
                                                               int ntiles, const float *__restrict__ scal,
@@ -660,15 +707,14 @@ __global__ __launch_bounds__(64 * IWAVES, 1) void k_mlp_infer(const float *__res
 {
     // activations: [buffer][K step][point tile][lane] of 8 bf16
     __shared__ bf16x8 act[2][IKS][INT][64];
+    // the standardized inputs of a tile, layer 1's B operand (12 KB)
+    __shared__ bf16x8 xin[IK1][INT][64];
     // the biases of layers 1-3 and of the output layer (padded to 16)
     __shared__ __attribute__((aligned(16))) float bias_s[3 * HID + OUTP];
-    // input shifts and scales
-    __shared__ __attribute__((aligned(16))) float scal_s[2 * IN];
-    // layer 1's weight fragments [wave][K step][row tile][lane] (24 KB)
-    __shared__ bf16x8 w1s[IWAVES][IK1][IMT][64];
+    // standardization coefficients a[k], b[k] (std_in)
+    __shared__ __attribute__((aligned(16))) float coef_s[2 * IN];
     static_assert(HID == 64 * IWAVES, "one bias of each layer per thread");
     static_assert(IP == 128 && 64 * IWAVES == 2 * IP, "two threads per point for the inputs");
-    static_assert(WI1 % (8 * 64 * IWAVES) == 0, "whole fragments per thread");
     const int member = blockIdx.y, G = gridDim.x;
     const int tid = threadIdx.x, lane = tid & 63, h = lane >> 5;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform in the wave
@@ -678,43 +724,48 @@ __global__ __launch_bounds__(64 * IWAVES, 1) void k_mlp_infer(const float *__res
     const float *wm = w + member * P;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<__bf16 *>(wi), 0,
                                                                          (int)(2 * WI_PER), 0x00020000);
-    // element offsets of this wave's weight blocks of layers 2 and 3 and of the output layer's
+    // element offsets of this wave's weight blocks of layers 1-3 and of the output layer's
+    const int w1 = (int)(wv * IK1 * IMT * 512);
     const int w2 = (int)(WI1 + wv * IKS * IMT * 512), w3 = (int)(WI1 + WI2 + wv * IKS * IMT * 512);
     const int w4 = (int)(WI1 + 2 * WI2);
     const float4 *f4 = reinterpret_cast<const float4 *>(feat);
     const float dfloor = scal[2 * IN + 2 * OUT + 1], dscale = scal[2 * IN + 2 * OUT];
     const bool dlog = dfloor > 0.f;
-    bf16x8 Wr[IKS][IMT];   // weight fragments of layers 2-4 in registers
-    float4 fv[5];          // the next tile's inputs
-    // Start: the first tile's inputs, the input shift and scale, the biases
-    // and layer 1's weights to LDS; then layer 2's weights (arriving while the
-    // inputs are standardized).
+    bf16x8 W1r[IK1][IMT], Wr[IKS][IMT];   // weight fragments in registers (layer 1; layers 2-4)
+    float4 fv[5];                         // the next tile's inputs
+    // Start: the first tile's inputs, the standardization coefficients and
+    // the biases to LDS; then the weights of layers 1 and 2 (arriving while
+    // the inputs are standardized).
     int tile = blockIdx.x;
     load_inputs(fv, f4, (int64_t)tile * IP + p_in, n, g0);
-    const float sc = tid < 2 * IN ? scal[tid] : 0.f;
+    float ca = 0.f, cb = 0.f;
+    if (tid < IN) {
+        const float sh = scal[tid], sc = scal[IN + tid];
+        ca = tid >= 12 && dlog ? sc * LOG10_2 : sc;
+        cb = -sh * sc;
+    }
     const float bl1 = wm[OB1 + tid], bl2 = wm[OB2 + tid], bl3 = wm[OB3 + tid];
     const float bl4 = tid < OUT ? wm[OB4 + tid] : 0.f;
-    constexpr int W1PT = (int)(WI1 / (8 * 64 * IWAVES));   // fragments of 16 B per thread
-    bf16x8 w1v[W1PT];
-#pragma unroll
-    for (int u = 0; u < W1PT; ++u) w1v[u] = ldfrag(rs, 0, u * IWAVES + wv, lane16);
-    if (tid < 2 * IN) scal_s[tid] = sc;
+    if (tid < IN) {
+        coef_s[tid] = ca;
+        coef_s[IN + tid] = cb;
+    }
     bias_s[tid] = bl1;
     bias_s[HID + tid] = bl2;
     bias_s[2 * HID + tid] = bl3;
     if (tid < OUTP) bias_s[3 * HID + tid] = bl4;
-#pragma unroll
-    for (int u = 0; u < W1PT; ++u) (&w1s[0][0][0][0])[(u * IWAVES + wv) * 64 + lane] = w1v[u];
     __syncthreads();
-    if (g0 == 0)
-        scatter_inputs<0>(fv, act[0], p_in, scal_s, dlog, dscale, dfloor);
-    else
-        scatter_inputs<1>(fv, act[0], p_in, scal_s, dlog, dscale, dfloor);
-    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < IK1; ++t)
+#pragma unroll
+        for (int jj = 0; jj < IMT; ++jj) W1r[t][jj] = ldfrag(rs, w1, t * IMT + jj, lane16);
 #pragma unroll
     for (int t = 0; t < IKS; ++t)
 #pragma unroll
         for (int jj = 0; jj < IMT; ++jj) Wr[t][jj] = ldfrag(rs, w2, t * IMT + jj, lane16);
+    lds_frag *xdst = lds_base(&xin[0][p_in / 32][p_in % 32]);   // this thread's group-0 fragment
+#pragma unroll
+    for (int j = 0; j < 3; ++j) scatter_item(j, g0, fv, xdst, coef_s, dlog, dscale, dfloor);
     f32x16 bc[IMT];   // the bias of the layer being computed, in accumulator layout
     const int J0 = IMT * wv;
 #pragma unroll
@@ -724,36 +775,33 @@ __global__ __launch_bounds__(64 * IWAVES, 1) void k_mlp_infer(const float *__res
     // one barrier between phases.  Layer l + 1's phase p needs only layer l's
     // phase-p outputs, so each phase's epilogue runs inside the next phase:
     //   L1.0 | L1.1 + epi L1.0 | bar | L2.0 + epi L1.1 | bar | L2.1 + epi L2.0 | bar
-    //   L3.0 + epi L2.1 | bar | L3.1 + epi L3.0, epi L3.1 | bar | output layer + next inputs | bar
-    // Buffers: layer 1 reads 0 and writes 1, layer 2 reads 1 and writes 0,
-    // layer 3 reads 0 and writes 1, the output layer reads 1 while the next
-    // tile's inputs go to 0; an epilogue writes point tiles of its own phase
-    // only, which no wave reads until the next barrier, and the tiles it
-    // overwrites were last read two barriers earlier.
+    //   L3.0 + epi L2.1 | bar | L3.1 + epi L3.0, epi L3.1 | bar | output layer | bar
+    // Buffers: layer 1 reads xin and writes act 1, layer 2 reads 1 and writes
+    // 0, layer 3 reads 0 and writes 1, the output layer reads 1.  An epilogue
+    // writes point tiles of its own phase only, which no wave reads until the
+    // next barrier, and the tiles it overwrites were last read two barriers
+    // earlier.  The next tile's inputs are loaded during layer 2 and written
+    // to xin during layer 3 (layer 1 has read xin two barriers before).
     f32x16 acc[2][IMT][2];   // [phase][row tile][point tile within the phase]
     for (; tile < ntiles; tile += G) {
-        const bool more = tile + G < ntiles;
-        {
-            bf16x8 W1r[IK1][IMT];   // layer 1's fragments, from LDS for this layer only
-#pragma unroll
-            for (int t = 0; t < IK1; ++t)
-#pragma unroll
-                for (int jj = 0; jj < IMT; ++jj) W1r[t][jj] = w1s[wv][t][jj][lane];
-            run_phase<IK1, false, 0>(W1r, act[0], 0, lane, acc[0], bc, bias_s, acc[1], act[1], 1, J0, h, rs, 0, 0);
-            run_phase<IK1, true, 0>(W1r, act[0], 1, lane, acc[1], bc, bias_s + HID, acc[0], act[1], 0, J0, h,
-                                    rs, 0, 0);
-        }
+        run_phase<IK1, false, 0>(W1r, xin, 0, lane, acc[0], bc, bias_s, acc[1], act[1], 1, J0, h, rs, 0, 0);
+        run_phase<IK1, true, 0>(W1r, xin, 1, lane, acc[1], bc, bias_s + HID, acc[0], act[1], 0, J0, h, rs, 0, 0);
         __syncthreads();
+        // the next tile's inputs, two phases ahead of their standardization;
+        // loaded after the last tile too (rows clamped to n - 1), so that the
+        // waits for the weights can count the loads issued after them exactly
+        load_inputs(fv, f4, (int64_t)(tile + G) * IP + p_in, n, g0);
         run_phase<IKS, true, 0>(Wr, act[1], 0, lane, acc[0], bc, bias_s + HID, acc[1], act[1], 1, J0, h, rs, 0, 0);
         __syncthreads();
-        run_phase<IKS, true, 1>(Wr, act[1], 1, lane, acc[1], bc, bias_s + 2 * HID, acc[0], act[0], 0, J0, h, rs, w3, 0);
+        run_phase<IKS, true, 1>(Wr, act[1], 1, lane, acc[1], bc, bias_s + 2 * HID, acc[0], act[0], 0, J0, h, rs,
+                                w3, 0);
         __syncthreads();
-        // the next tile's inputs, two phases ahead of their use
-        if (more) load_inputs(fv, f4, (int64_t)(tile + G) * IP + p_in, n, g0);
-        run_phase<IKS, true, 0>(Wr, act[0], 0, lane, acc[0], bc, bias_s + 2 * HID, acc[1], act[0], 1, J0, h,
-                                rs, 0, 0);
+        // (after the last tile the scatter writes stale inputs that are never read)
+        run_phase<IKS, true, 0>(Wr, act[0], 0, lane, acc[0], bc, bias_s + 2 * HID, acc[1], act[0], 1, J0, h, rs, 0,
+                                0, ScatterExtra{0, g0, fv, xdst, coef_s, dlog, dscale, dfloor});
         __syncthreads();
-        run_phase<IKS, true, 2>(Wr, act[0], 1, lane, acc[1], bc, bias_s, acc[0], act[1], 0, J0, h, rs, w4, w2);
+        run_phase<IKS, true, 2>(Wr, act[0], 1, lane, acc[1], bc, bias_s, acc[0], act[1], 0, J0, h, rs, w4, w2,
+                                ScatterExtra{2, g0, fv, xdst, coef_s, dlog, dscale, dfloor});
         {
             u32x4 frag{};
             lds_frag *db = lds_base(&act[1][2 * J0][2][lane]);
@@ -766,7 +814,7 @@ __global__ __launch_bounds__(64 * IWAVES, 1) void k_mlp_infer(const float *__res
         // the fragment of K step 2 T + l / 32, lane half (l / 16) % 2
         {
             const int c = lane >> 4;
-            bf16x8 *ob = &act[1][c >> 1][wv][32 * (c & 1) + (lane & 15)];
+            lds_frag *ob = lds_base(&act[1][c >> 1][wv][32 * (c & 1) + (lane & 15)]);
             f32x4 o0 = {}, o1 = {};
             bf16x8 b[IK4][2];
 #pragma unroll
@@ -782,12 +830,6 @@ __global__ __launch_bounds__(64 * IWAVES, 1) void k_mlp_infer(const float *__res
                 }
                 o0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wr[T][0], b[T][0], o0, 0, 0, 0);
                 o1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Wr[T][0], b[T][1], o1, 0, 0, 0);
-                if (T == 0) {   // (after the last tile: stale inputs, never read)
-                    if (g0 == 0)
-                        scatter_inputs<0>(fv, act[0], p_in, scal_s, dlog, dscale, dfloor);
-                    else
-                        scatter_inputs<1>(fv, act[0], p_in, scal_s, dlog, dscale, dfloor);
-                }
                 Wr[T][0] = ldfrag(rs, w2, T * IMT, lane16);   // (after the last tile: unused)
                 __builtin_amdgcn_sched_barrier(0);
             }
