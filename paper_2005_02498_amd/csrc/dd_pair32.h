@@ -115,10 +115,13 @@ __device__ __forceinline__ void pair_acc_f32(
 //   rho     : (c.b_j) Sga + 3 q ((rho.b_j) S5 + (t.b_j) S5v)
 
 // The moments are collected as the coefficients of the five vectors (that of
-// b_j added to fk); shared by the 2- and 3-point rules.
+// b_j added to fk); shared by the 2- and 3-point rules.  three = 3, passed in
+// a vector register by the caller: an FP32 instruction with a literal or
+// scalar-register operand issues at half the rate of one whose operands are
+// all vector registers.
 __device__ __forceinline__ void quad_moments_acc_f32(float e0, float e1, float e2, float ym, const float *s,
                                                      float S3, float S5, float S3v, float S5v, float S5vv,
-                                                     float bj0, float bj1, float bj2, float kr, float nu,
+                                                     float bj0, float bj1, float bj2, float kr, float nu, float three,
                                                      float &f0, float &f1, float &f2, float &fk)
 {
     const float t0 = s[R32_T], t1 = s[R32_T + 1], t2 = s[R32_T + 2];
@@ -131,13 +134,13 @@ __device__ __forceinline__ void quad_moments_acc_f32(float e0, float e1, float e
     const float cb = fmaf(c2, bj2, fmaf(c1, bj1, c0 * bj0));
     const float rbb = fmaf(rb2, bj2, fmaf(rb1, bj1, rb0 * bj0));
     const float q = fmaf(c2, h2, fmaf(c1, h1, c0 * h0));
-    const float q3 = 3.0f * q;
-    const float Sal = -kr * fmaf(2.0f, S3, 3.0f * S5);
-    const float Sgv = fmaf(-nu, S3v, 3.0f * kr * S5v);
+    const float q3 = three * q;
+    const float Sal = -kr * fmaf(2.0f, S3, three * S5);
+    const float Sgv = fmaf(-nu, S3v, three * kr * S5v);
     const float Cr = tb * Sal;
     const float Cc = fmaf(tb, Sgv, -hb * S3);
     const float Ct = fmaf(rbb, Sal, fmaf(cb, Sgv, q3 * fmaf(hb, S5v, tb * S5vv)));
-    fk = fmaf(q, fmaf(3.0f, S5, S3), fk);
+    fk = fmaf(q, fmaf(three, S5, S3), fk);
     const float Ch = fmaf(-cb, S3, q3 * fmaf(hb, S5, tb * S5v));
     f0 = fmaf(Ch, h0, fmaf(Ct, t0, fmaf(Cc, c0, fmaf(Cr, rb0, f0))));
     f1 = fmaf(Ch, h1, fmaf(Ct, t1, fmaf(Cc, c1, fmaf(Cr, rb1, f1))));
@@ -148,7 +151,7 @@ __device__ __forceinline__ void quad_moments_acc_f32(float e0, float e1, float e
 // REC32A), whose b and c carry the weight Wo; adds K b_j / k2 to (f0, f1, f2)
 // + fk b_j.  2-point rule: points at v = ym -+ hq, weight Wo each (in b, c).
 __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, float ee, float ym, const float *s,
-                                              float bj0, float bj1, float bj2, float kr, float nu,
+                                              float bj0, float bj1, float bj2, float kr, float nu, float three,
                                               float &f0, float &f1, float &f2, float &fk)
 {
     const float hq = s[R32_HQ];
@@ -162,7 +165,7 @@ __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, floa
     const float S3 = iA3 + iB3, S5 = iA5 + iB5;
     const float S3v = fmaf(iA3, vA, iB3 * vB), S5v = pA + pB;
     const float S5vv = fmaf(pA, vA, pB * vB);
-    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2, fk);
+    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, three, f0, f1, f2, fk);
 }
 
 // 3-point rule: points at v = ym -+ hq with weight Wo (in b, c) and at v = ym
@@ -170,7 +173,7 @@ __device__ __forceinline__ void quad2_acc_f32(float e0, float e1, float e2, floa
 // sqrt(3/5), Wo = 5L/18, Wc = 8L/18).
 // Its error is below 2e-7 relative beyond 6 source lengths from the midpoint.
 __device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, float ee, float ym, const float *s,
-                                              float bj0, float bj1, float bj2, float kr, float nu,
+                                              float bj0, float bj1, float bj2, float kr, float nu, float three,
                                               float &f0, float &f1, float &f2, float &fk)
 {
     const float hq = s[R32_HQ], Wc = s[R32_WC];
@@ -186,7 +189,7 @@ __device__ __forceinline__ void quad3_acc_f32(float e0, float e1, float e2, floa
     const float S3v = fmaf(Wc, iC3 * ym, fmaf(iA3, vA, iB3 * vB));
     const float S5v = fmaf(Wc, pC, pA + pB);
     const float S5vv = fmaf(Wc, pC * ym, fmaf(pA, vA, pB * vB));
-    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, f0, f1, f2, fk);
+    quad_moments_acc_f32(e0, e1, e2, ym, s, S3, S5, S3v, S5v, S5vv, bj0, bj1, bj2, kr, nu, three, f0, f1, f2, fk);
 }
 
 }  // namespace dd

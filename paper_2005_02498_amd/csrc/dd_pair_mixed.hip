@@ -65,6 +65,10 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
     const double bj0 = rec[7 * ns + j], bj1 = rec[8 * ns + j], bj2 = rec[9 * ns + j];
     const float fb0 = (float)bj0, fb1 = (float)bj1, fb2 = (float)bj2;
     const float fkr = (float)kr, fnu = (float)nu, cut2 = cut * cut;
+    // constants of the FP32 arithmetic in vector registers (the empty asm keeps
+    // them there): an FP32 instruction with a literal operand issues at half rate
+    float three = 3.0f, ck2 = COLLINEAR_K2, ck21 = 1.0f + COLLINEAR_K2;
+    asm volatile("" : "+v"(three), "+v"(ck2), "+v"(ck21));
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     unsigned n_near = 0, n_quad_src = 0;
     if (lane == 0) {
@@ -75,6 +79,8 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
 
     for (int64_t base = it.src_begin; base < it.src_end; base += TILE) {
         const int n = (int)min(it.src_end - base, (int64_t)TILE);
+        // the target's own segment as a source index of this stage (-1: not in it)
+        const int self = j >= base && j < base + n ? (int)(j - base) : -1;
         float f0 = 0.f, f1 = 0.f, f2 = 0.f, fk = 0.f;
         if (QN) {
             __syncthreads();
@@ -87,7 +93,6 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
         }
         const float *s = rf + base * REC32A;
         for (int k = 0; k < n; ++k, s += REC32A) {
-            const int64_t m = base + k;
             float r[REC32A];
             if (QN) {
                 // from LDS (broadcast reads): the FP32 quadrature then runs on
@@ -123,13 +128,13 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                 const float ee = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
                 // outside the band and not nearly collinear (ym^2 > K^2 (rho^2 + 1)
                 // with rho^2 = ee - ym^2, see COLLINEAR_K2)
-                const bool quad = ee >= r[R32_BAND] && ym2 * (1.0f + COLLINEAR_K2) <= fmaf(COLLINEAR_K2, ee, COLLINEAR_K2);
+                const bool quad = ee >= r[R32_BAND] && ym2 * ck21 <= fmaf(ck2, ee, ck2);
                 if (__all(quad)) {
                     ++n_quad_src;
                     if (QN == 2)
-                        quad2_acc_f32(e0, e1, e2, ee, ym, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2, fk);
+                        quad2_acc_f32(e0, e1, e2, ee, ym, r, fb0, fb1, fb2, fkr, fnu, three, f0, f1, f2, fk);
                     else
-                        quad3_acc_f32(e0, e1, e2, ee, ym, r, fb0, fb1, fb2, fkr, fnu, f0, f1, f2, fk);
+                        quad3_acc_f32(e0, e1, e2, ee, ym, r, fb0, fb1, fb2, fkr, fnu, three, f0, f1, f2, fk);
                     continue;
                 }
             }
@@ -151,10 +156,10 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
             const float ya = y - fminf(fmaxf(y, 0.f), Ls);
             // FP64: near pairs, and nearly collinear ones (rho carries an absolute
             // error of order |ym| eps32 in FP32)
-            if (hh + ya * ya < cut2 || ym2 > fmaf(COLLINEAR_K2, hh, COLLINEAR_K2)) {
-                if (m != j) {
+            if (hh + ya * ya < cut2 || ym2 > fmaf(ck2, hh, ck2)) {
+                if (k != self) {
                     n_near += valid ? 1u : 0u;
-                    pair_acc_isolated_f64(xq0, xq1, xq2, bj0, bj1, bj2, ra + m * RECA, kr, nu, a0, a1, a2);
+                    pair_acc_isolated_f64(xq0, xq1, xq2, bj0, bj1, bj2, ra + (base + k) * RECA, kr, nu, a0, a1, a2);
                 }
             } else {
                 // the record's b and c carry the quadrature weight (1 without a quadrature)
