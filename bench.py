@@ -114,12 +114,14 @@ def parse():
                     help="profiling aid: run only one part (no JSON contract)")
     ap.add_argument("--surrogate-study", action="store_true",
                     help="run the surrogate speed-up-at-fixed-error study and write --study-out")
-    ap.add_argument("--study-train", type=int, default=65536)
+    ap.add_argument("--study-train-states", type=int, default=32768)
+    ap.add_argument("--study-train-seeds", type=int, default=2,
+                    help="microstructures per training state (rows per burst, and per-state means)")
     ap.add_argument("--study-states", type=int, default=256)
     ap.add_argument("--study-seeds", type=int, default=16)
     ap.add_argument("--study-epochs", type=int, default=200)
-    ap.add_argument("--study-reuse-train", default=None,
-                    help="npz written by an earlier study run: reuse its training bursts")
+    ap.add_argument("--no-live-study", action="store_true",
+                    help="skip the reduced surrogate study of the default run")
     ap.add_argument("--study-out", default=os.path.join(ROOT, "study", "surrogate_study.json"))
     return ap.parse_args()
 
@@ -128,191 +130,23 @@ SURROGATE_FILE = os.path.join(ROOT, "profiles", "surrogate_study.json")
 
 
 def surrogate_study(args):
-    """Surrogate speed-up at fixed error.
-
-    Data: one 200-step mixed-precision burst per training state (states drawn
-    like the batched-burst workload from seeds 2,000,000 + i: k ~ U{8..128}
-    loops, mobile fraction, applied stress), features = resolved shear stress
-    and mobile/sessile line densities per system of the initial state,
-    targets = the 12 burst-averaged slip rates.  Held out: S states (seeds
-    3,000,000 + s) x M microstructures each; reference = the M-burst mean
-    Rbar_s.  The network: 4 members, densities as log10 of m^-2 (floor 1e10),
-    standardised, Adam.  Errors are (sum_s |pred_s - Rbar_s|^2 / sum_s
-    |Rbar_s|^2)^(1/2).  DD at error e needs n(e) = E1^2 / e^2 bursts per state
-    (E1: the single-burst error, from the per-state sample covariance); its
-    cost is n(e) times the measured mean burst time.  The surrogate (one
-    inference per state) is judged against Rbar_s with the reference's own
-    noise E1^2 / M removed in quadrature.  Its cost per state is its
-    measured inference time per point plus, for the fraction of points whose
-    ensemble spread exceeds 5 % (spread floor: 10 % of the training RMS rate),
-    the DD cost at the same error.
-    """
-    import numpy as np
-    import torch
-
+    """The full surrogate study (paper_2005_02498_amd/surrogate_study.py):
+    written to --study-out."""
+    from paper_2005_02498_amd import surrogate_study as S
     import paper_2005_02498_amd as dd
-    from paper_2005_02498_amd import workloads as W
-
-    dev = torch.device("cuda:0")
-    mat = {"mu": W.MU, "nu": W.NU, "a": W.CORE_A, "B": W.DRAG_B}
     dd.dd_set_validation(False)
-    t_start = time.perf_counter()
-
-    def bursts(instances):
-        bt = W.pack(instances)
-        d = dict(x=torch.tensor(bt.x, device=dev), sn=torch.tensor(bt.seg_nodes, device=dev),
-                 b=torch.tensor(bt.burgers, device=dev), n=torch.tensor(bt.normal, device=dev),
-                 p=torch.tensor(bt.pinned, device=dev), s=torch.tensor(bt.sigma_app, device=dev),
-                 v=torch.tensor(bt.volume, device=dev))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r, f = dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["sn"], d["b"], d["n"], d["p"],
-                                 d["s"], d["v"], mat, 2, dd.DD_MIXED, 20.0, 200, W.DT,
-                                 want_features=True)
-        torch.cuda.synchronize()
-        return r.cpu().numpy(), f.cpu().numpy(), time.perf_counter() - t0
-
-    def log(msg):
-        print(f"[{time.perf_counter() - t_start:7.1f}s] {msg}", file=sys.stderr, flush=True)
-
-    B = 512
-    Xtr, Ytr, sec, n_b = [], [], 0.0, 0
-    if args.study_reuse_train:
-        z = np.load(args.study_reuse_train)
-        Xtr, Ytr = [z["Xtr"].astype(np.float64)], [z["Ytr"].astype(np.float64)]
-        log(f"reusing {len(Xtr[0])} training bursts from {args.study_reuse_train}")
-    for b0 in range(0, args.study_train if not args.study_reuse_train else 0, B):
-        ins = [W.burst_instance(2_000_000 + i) for i in range(b0, min(b0 + B, args.study_train))]
-        r, f, t = bursts(ins)
-        Xtr.append(f); Ytr.append(r); sec += t; n_b += len(ins)
-        log(f"training bursts {n_b}/{args.study_train} ({t:.2f} s for {len(ins)})")
-    Xtr = np.concatenate(Xtr); Ytr = np.concatenate(Ytr)
-    S, M = args.study_states, args.study_seeds
-    pairs_ho = [(s, k) for s in range(S) for k in range(M)]
-    Xho, Yho = [], []
-    for b0 in range(0, len(pairs_ho), B):
-        ins = [W.burst_instance_state(3_000_000 + s, 4_000_000 + M * s + k) for s, k in pairs_ho[b0:b0 + B]]
-        r, f, t = bursts(ins)
-        Xho.append(f); Yho.append(r); sec += t; n_b += len(ins)
-        log(f"held-out bursts {min(b0 + B, len(pairs_ho))}/{len(pairs_ho)}")
-    Xho = np.concatenate(Xho).reshape(S, M, 36); Yho = np.concatenate(Yho).reshape(S, M, 12)
-    t_burst = sec / n_b
-
-    # ---- training (all device work in the library's kernels)
-    dens_scale, dens_floor = 1.0 / W.B_SI ** 2, 1e10
-    Xt = Xtr.copy()
-    Xt[:, 12:] = np.log10(np.maximum(Xt[:, 12:], 0) * dens_scale + dens_floor)
-    in_shift = Xt.mean(0); in_scale = 1.0 / np.maximum(Xt.std(0), 1e-6)
-    out_shift = Ytr.mean(0); out_scale = np.maximum(Ytr.std(0), 1e-30)
-    model = dd.SurrogateModel(4, 12345)
-    model.set_log_densities(dens_scale, dens_floor)
-    model.set_scaling(in_shift, in_scale, out_shift, out_scale)
-    # 10 % of the training bursts are a validation split for early stopping
-    rng = np.random.default_rng(0)
-    order = rng.permutation(len(Xtr))
-    n_val = len(Xtr) // 10
-    val, trn = order[:n_val], order[n_val:]
-    Xd = torch.tensor(Xtr[trn], dtype=torch.float32, device=dev)
-    Yd = torch.tensor(Ytr[trn], dtype=torch.float32, device=dev)
-    Xv = torch.tensor(Xtr[val], dtype=torch.float32, device=dev)
-    Yv = Ytr[val]
-    nb = 1024
-    steps_per_epoch = max(1, len(trn) // nb)
     t0 = time.perf_counter()
-    losses, best, best_ep, best_params = [], float("inf"), -1, None
-    for ep in range(args.study_epochs):
-        lr = 1e-3 if ep < 0.6 * args.study_epochs else (3e-4 if ep < 0.85 * args.study_epochs else 1e-4)
-        perm = torch.tensor(rng.permutation(len(trn)), device=dev)
-        for k in range(steps_per_epoch):
-            idx = perm[k * nb:(k + 1) * nb]
-            loss = dd.dd_mlp_train_step(model, Xd[idx].contiguous(), Yd[idx].contiguous(), lr)
-        if ep % 5 == 4 or ep == args.study_epochs - 1:
-            losses.append(loss.cpu().numpy().tolist())
-            pv, _, _ = dd.dd_surrogate_rates(model, Xv, 0.05)
-            vloss = float(np.mean(((pv.cpu().numpy() - Yv) / out_scale) ** 2))
-            if vloss < best:
-                best, best_ep = vloss, ep
-                best_params = [model.get_params(m) for m in range(4)]
-            log(f"epoch {ep}: train loss {np.round(losses[-1], 4).tolist()}, validation {vloss:.4f}")
-    for m in range(4):
-        model.set_params(m, best_params[m])
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-
-    # ---- evaluation on the held-out states: a state fixes the features
-    # exactly (stress, and every loop's system, radius and mobility), its M
-    # microstructures differ only in loop centres, phases and signs.  The
-    # reference is the M-burst mean; its own noise E1^2 / M is removed in
-    # quadrature from the surrogate's error.
-    floor_rate = 0.1 * float(np.sqrt(np.mean(Ytr ** 2)))     # spread floor, rate units
-    model.set_spread_floor(floor_rate)
-    Fho = torch.tensor(Xho[:, 0], dtype=torch.float32, device=dev)
-    pr, sp, fl = dd.dd_surrogate_rates(model, Fho, 0.05)
-    pred = pr.cpu().numpy().astype(np.float64)
-    spread = sp.cpu().numpy()
-    feat_spread = float(np.abs(Xho - Xho[:, :1]).max() / max(np.abs(Xho).max(), 1e-300))
-    Rbar = Yho.mean(1)
-    den = float(np.sum(Rbar ** 2))
-    cov_tr = np.sum(Yho.var(1, ddof=1), axis=1)              # trace of the per-state covariance
-    E1 = float(np.sqrt(np.sum(cov_tr) / den))                # one burst vs the state mean
-    ref2 = E1 ** 2 / M                                       # noise of the M-burst reference
-    raw = float(np.sum((pred - Rbar) ** 2) / den)
-    E_sur1 = float(np.sqrt(max(raw - ref2, 0.0)))
-    E_sur_raw = float(np.sqrt(raw))
-    E_const = float(np.sqrt(max(np.sum((out_shift[None, :] - Rbar) ** 2) / den - ref2, 0.0)))
-    flagged = spread > 0.05
-
-    # ---- inference cost: 1,048,576 points per call
-    n_inf = 1 << 20
-    Fin = Fho[torch.tensor(rng.integers(0, len(Fho), n_inf), device=dev)].contiguous()
-    for _ in range(2):
-        dd.dd_surrogate_rates(model, Fin, 0.05)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = 5
-    for _ in range(reps):
-        dd.dd_surrogate_rates(model, Fin, 0.05)
-    torch.cuda.synchronize()
-    t_inf_call = (time.perf_counter() - t0) / reps
-    t_inf = t_inf_call / n_inf
-
-    def n_needed(e):
-        return max(1, int(np.ceil((E1 / e) ** 2)))
-
-    f_flag = float(flagged.mean())
-    res = {"study": "surrogate speed-up at fixed error",
-           "training_states": int(len(Xtr)), "heldout_states": S, "microstructures_per_state": M,
-           "burst": "200 glide steps, mixed precision, 2 Gauss points, one graph launch per 512",
-           "mean_burst_seconds": t_burst, "data_generation_seconds": sec, "training_seconds": t_train,
-           "epochs": args.study_epochs, "best_epoch": best_ep, "validation_loss": best,
-           "final_losses": losses[-1],
-           "inference_seconds_per_call": t_inf_call, "inference_points_per_call": n_inf,
-           "inference_tflops": 1.20e12 * n_inf / (1 << 20) / t_inf_call / 1e12,
-           "error_single_burst": E1, "error_reference_noise": float(np.sqrt(ref2)),
-           "error_surrogate": E_sur1, "error_surrogate_vs_reference_raw": E_sur_raw,
-           "error_mean_rate_predictor": E_const, "spread_floor_rate": floor_rate,
-           "heldout_feature_variation_within_state": feat_spread,
-           "fallback_fraction": f_flag,
-           "fallback_fraction_at_tol": {str(t): float((spread > t).mean())
-                                        for t in (0.05, 0.1, 0.2, 0.5)},
-           "spread_median": float(np.median(spread))}
-    for name, e in (("at_surrogate_error", E_sur1), ("at_5_percent", 0.05)):
-        n = n_needed(e)
-        dd_cost = n * t_burst
-        sur_cost = t_inf + f_flag * dd_cost
-        res[name] = {"error": e, "dd_bursts_per_state": n, "dd_seconds_per_state": dd_cost,
-                     "surrogate_seconds_per_state": sur_cost, "speedup": dd_cost / sur_cost,
-                     "speedup_without_fallback": dd_cost / t_inf,
-                     "surrogate_reaches_it": bool(E_sur1 <= e + 1e-12)}
-    res["total_seconds"] = time.perf_counter() - t_start
+    res = S.study(args.study_train_states, args.study_train_seeds, args.study_states, args.study_seeds,
+                  args.study_epochs, learning_curve=True,
+                  log=lambda m: print(f"[{time.perf_counter() - t0:7.1f}s] {m}", file=sys.stderr, flush=True))
+    res["command"] = ("python bench.py --surrogate-study --study-train-states %d --study-train-seeds %d "
+                      "--study-states %d --study-seeds %d --study-epochs %d"
+                      % (args.study_train_states, args.study_train_seeds, args.study_states, args.study_seeds,
+                         args.study_epochs))
     os.makedirs(os.path.dirname(args.study_out), exist_ok=True)
     with open(args.study_out, "w") as f:
         json.dump(res, f, indent=1)
-    np.savez_compressed(os.path.splitext(args.study_out)[0] + "_data.npz", Xtr=Xtr.astype(np.float32),
-                        Ytr=Ytr.astype(np.float32), Xho=Xho.astype(np.float32), Yho=Yho.astype(np.float32),
-                        pred=pred.astype(np.float32), spread=spread.astype(np.float32))
-    print(json.dumps(res))
-
+    print(json.dumps({"study": args.study_out, "seconds": res["total_seconds"]}))
 
 def cpu_baseline(args, inst):
     """The FP64 C oracle, as it stands, on the host CPU of this machine: the
@@ -811,16 +645,39 @@ def main():
         out["extras"]["surrogate_train_step"] = {"batch": 1024, "members": 4, "ms_per_step": t_train * 1e3}
         model.close()
 
-    if os.path.exists(SURROGATE_FILE) and args.only is None:
-        with open(SURROGATE_FILE) as f:
-            sur = json.load(f)
-        out["surrogate"] = {"speedup_at_fixed_error": sur["at_surrogate_error"]["speedup"],
-                            "speedup_without_fallback": sur["at_surrogate_error"]["speedup_without_fallback"],
-                            "error": sur["at_surrogate_error"]["error"],
-                            "dd_bursts_for_same_error": sur["at_surrogate_error"]["dd_bursts_per_state"],
-                            "fallback_fraction_at_5_percent_spread": sur["fallback_fraction"],
-                            "reaches_5_percent": sur["at_5_percent"]["surrogate_reaches_it"],
-                            "source": "profiles/surrogate_study.json (python bench.py --surrogate-study)"}
+    if args.only is None and not args.no_live_study:
+        # reduced study, measured in this run: 4,096 training states x 2
+        # microstructures (8,192 bursts), 64 held-out states x 8, 100 epochs
+        from paper_2005_02498_amd import surrogate_study as S
+        dd.dd_set_validation(False)
+        st = S.study(4096, 2, 64, 8, 100, learning_curve=False)
+        dd.dd_set_validation(True)
+        best = min(("per_burst_targets", "per_state_mean_targets"),
+                   key=lambda k: st[k]["error_surrogate_evaluation_half"])
+        b = st[best]
+        out["surrogate"] = {
+            "workload": "reduced live study: 4,096 training states x 2 microstructures of 200-step mixed bursts, "
+                        "64 held-out states x 8, 100 epochs; threshold calibrated on half the held-out states",
+            "targets": best, "error": b["at_surrogate_error"]["error"],
+            "error_single_burst": b["error_single_burst"],
+            "speedup_at_fixed_error": b["at_surrogate_error"]["speedup"],
+            "fallback_fraction": b["at_surrogate_error"]["fallback_fraction"],
+            "dd_bursts_for_same_error": b["at_surrogate_error"]["dd_bursts_per_state"],
+            "speedup_without_fallback": b["at_surrogate_error"]["speedup_without_fallback"],
+            "at_5_percent": b["at_0.05"], "seconds": st["total_seconds"]}
+        if os.path.exists(SURROGATE_FILE):
+            with open(SURROGATE_FILE) as f:
+                sur = json.load(f)
+            out["surrogate"]["full_study"] = {
+                "source": "profiles/surrogate_study.json (" + sur.get("command", "python bench.py --surrogate-study")
+                          + ")"}
+            for k in ("per_burst_targets", "per_state_mean_targets"):
+                if k in sur:
+                    out["surrogate"]["full_study"][k] = {"error": sur[k]["at_surrogate_error"]["error"],
+                                                         "speedup": sur[k]["at_surrogate_error"]["speedup"],
+                                                         "fallback": sur[k]["at_surrogate_error"]["fallback_fraction"]}
+            if "learning_curve" in sur:
+                out["surrogate"]["full_study"]["bursts_for_5_percent"] = sur["learning_curve"]["bursts_for_5_percent"]
 
     if args.cpu_targets > 0:
         out["cpu_baseline"] = cpu_baseline(args, inst)

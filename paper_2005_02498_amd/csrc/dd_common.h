@@ -123,6 +123,28 @@ int ensure(Workspace *ws, Slot s, size_t bytes, void **out);
 // Work decomposition of the pair kernel: a tile is up to TILE consecutive
 // target Gauss points of one instance; an item is one tile against one
 // contiguous range of that instance's sources.
+// FCC slip system alpha = 3 p + d (the order dd.h documents): unit plane
+// normal n = P[p] / sqrt(3) and slip direction m = D[p][d] / sqrt(2).  Used by
+// the slip-rate kernels (device) and the PTA driver's L^p (host).
+__host__ __device__ inline void fcc(int alpha, double n[3], double m[3])
+{
+    const double r3 = 0.57735026918962576451, r2 = 0.70710678118654752440;
+    // plane normals
+    const signed char P[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
+    // directions, per plane: zero x, zero y, zero z
+    const signed char D[4][3][3] = {
+        {{0, 1, -1}, {1, 0, -1}, {1, -1, 0}},
+        {{0, 1, -1}, {1, 0, 1}, {1, 1, 0}},
+        {{0, 1, 1}, {1, 0, -1}, {1, 1, 0}},
+        {{0, 1, 1}, {1, 0, 1}, {1, -1, 0}},
+    };
+    const int p = alpha / 3, d = alpha % 3;
+    for (int k = 0; k < 3; ++k) {
+        n[k] = P[p][k] * r3;
+        m[k] = D[p][d][k] * r2;
+    }
+}
+
 constexpr int TILE = 256;
 
 struct Tile {

@@ -100,26 +100,6 @@ __device__ __forceinline__ bool seg_ends(const Layout &L, const int32_t *seg_nod
     return ok;
 }
 
-// FCC slip systems, alpha = 3 p + d (see dd.h).
-__device__ __forceinline__ void fcc(int alpha, double n[3], double m[3])
-{
-    const double r3 = 0.57735026918962576451, r2 = 0.70710678118654752440;
-    // plane normals
-    const signed char P[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
-    // directions, per plane: zero x, zero y, zero z
-    const signed char D[4][3][3] = {
-        {{0, 1, -1}, {1, 0, -1}, {1, -1, 0}},
-        {{0, 1, -1}, {1, 0, 1}, {1, 1, 0}},
-        {{0, 1, 1}, {1, 0, -1}, {1, 1, 0}},
-        {{0, 1, 1}, {1, 0, 1}, {1, -1, 0}},
-    };
-    int p = alpha / 3, d = alpha % 3;
-    for (int k = 0; k < 3; ++k) {
-        n[k] = P[p][k] * r3;
-        m[k] = D[p][d][k] * r2;
-    }
-}
-
 // -------------------------------------------------------- a1: preparation --
 struct PrepArgs {
     Layout L;

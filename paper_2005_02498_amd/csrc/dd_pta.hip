@@ -60,19 +60,12 @@ __global__ void k_copy_masked(T *__restrict__ dst, const T *__restrict__ src, in
 // L^p = sum_alpha gdot_alpha m_alpha (x) n_alpha (row-major 3 x 3)
 void lp_from_rates(const double *g, double Lp[9])
 {
-    static const int P[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
-    static const int D[4][3][3] = {
-        {{0, 1, -1}, {1, 0, -1}, {1, -1, 0}},
-        {{0, 1, -1}, {1, 0, 1}, {1, 1, 0}},
-        {{0, 1, 1}, {1, 0, -1}, {1, 1, 0}},
-        {{0, 1, 1}, {1, 0, 1}, {1, -1, 0}},
-    };
-    const double r3 = 0.57735026918962576451, r2 = 0.70710678118654752440;
     for (int k = 0; k < 9; ++k) Lp[k] = 0.0;
     for (int al = 0; al < 12; ++al) {
-        const int p = al / 3, d = al % 3;
+        double n[3], m[3];
+        fcc(al, n, m);
         for (int r = 0; r < 3; ++r)
-            for (int c = 0; c < 3; ++c) Lp[3 * r + c] += g[al] * (D[p][d][r] * r2) * (P[p][c] * r3);
+            for (int c = 0; c < 3; ++c) Lp[3 * r + c] += g[al] * m[r] * n[c];
     }
 }
 
