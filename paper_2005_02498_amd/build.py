@@ -3,7 +3,8 @@
     python -m paper_2005_02498_amd.build          # compile every source
     python -m paper_2005_02498_amd.build --isa    # also keep the AMD assembly
 
-Each csrc/*.hip is compiled with hipcc for gfx950 into _build/, then linked into
+Each csrc/*.hip is compiled with hipcc for gfx950 and each csrc/*.cpp (host-only
+planning code) with the host C++ compiler into _build/, then linked into
 paper_2005_02498_amd/libdd.so.  Packed FP32 instructions are disabled for all
 device code (-packed-fp32-ops); the host pass prints a harmless warning that it
 does not know that feature.
@@ -26,6 +27,7 @@ LIB = os.path.join(PKG, "libdd.so")
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CXX", shutil.which("g++") or "g++")
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
@@ -43,14 +45,18 @@ EXTRA = {
 
 def _compile(src: str, isa: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
-    if isa:
-        cmd += ["-save-temps=obj"]
+    if src.endswith(".cpp"):
+        cmd = [CXX, "-O2", "-fPIC", "-std=c++17", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+               "-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
+        if isa:
+            cmd += ["-save-temps=obj"]
     r = subprocess.run(cmd, capture_output=True, text=True, cwd=BUILD)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
                      if "packed-fp32-ops" not in l)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed for {src}:\n{msgs}")
+        raise RuntimeError(f"compiling {src} failed:\n{msgs}")
     if msgs.strip():
         print(msgs, file=sys.stderr)
     return obj
@@ -58,7 +64,7 @@ def _compile(src: str, isa: bool) -> str:
 
 def build(isa: bool = False, verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, isa), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "dd.h"
+#include "dd_host.h"
 
 namespace dd {
 
@@ -145,28 +146,6 @@ __host__ __device__ inline void fcc(int alpha, double n[3], double m[3])
     }
 }
 
-constexpr int TILE = 256;
-
-struct Tile {
-    int64_t point_begin;   // global Gauss-point index (segment * Q + q)
-    int32_t n_points;      // <= TILE
-    int32_t n_chunks;      // items covering this tile, slots slot_begin..+n_chunks
-    int64_t slot_begin;
-};
-
-struct Item {
-    int32_t tile;
-    int32_t pad;
-    int64_t src_begin;     // global segment indices [src_begin, src_end)
-    int64_t src_end;
-    int64_t slot;          // partial-sum slot
-};
-
-struct GaussRule {
-    double s[DD_MAX_GAUSS];
-    double w[DD_MAX_GAUSS];
-    int n;
-};
 
 // FP64 segment records, structure of arrays with stride n_segs:
 //  0..2 x1/a, 3..5 t, 6 L/a, 7..9 b/a, 10..12 c = (b/a) x t, 13 length of the
@@ -201,11 +180,8 @@ constexpr int REC32A = 24;
 // max(6 L, cutoff + L/2).  A work split is encoded as MIXED_VARIANTS *
 // (source-range length) + variant.
 constexpr int MIXED_VARIANTS = 3;
-// shortest source range of a work item
-constexpr int MIN_CHUNK_LEN = 16;
 inline __host__ __device__ int quad_points(int variant) { return variant == 0 ? 2 : (variant == 2 ? 3 : 0); }
 
-GaussRule gauss_rule(int n);
 
 // Exact band (the exact_eta argument of the force calls): near-pair lists and
 // the exact target integrals of those pairs, as corrections to the Q-point

@@ -813,86 +813,6 @@ int read_flags(Workspace *ws, hipStream_t st)
 
 namespace {
 
-// Work decomposition for a set of instances (host tables).
-struct Plan {
-    std::vector<Tile> tiles;
-    std::vector<Item> items;
-    std::vector<int64_t> tile_begin;   // [n_inst+1]
-    int64_t chunk_len = 0;
-};
-
-// Source-range length of a work item when none is given: at least about 2048
-// work items; source ranges of at least MIN_CHUNK_LEN sources (small problems
-// spread over many CUs), in whole TILEs above that, and no longer than
-// max(512, N_max / 16): the largest items set the tail of the schedule, and
-// splitting them further costs only partial sums (on many bursts or one very
-// large volume this is 7-12 % faster than one range per tile).
-int64_t heuristic_chunk(int64_t total_tiles, int64_t max_src)
-{
-    const int64_t want_items = 2048, MIN_CHUNK = MIN_CHUNK_LEN;
-    int64_t chunks = total_tiles > 0 ? (want_items + total_tiles - 1) / total_tiles : 1;
-    chunks = std::max<int64_t>(1, std::min<int64_t>(chunks, (max_src + MIN_CHUNK - 1) / MIN_CHUNK));
-    int64_t chunk_len = (max_src + chunks - 1) / chunks;
-    chunk_len = std::min<int64_t>(chunk_len, std::max<int64_t>(512, (max_src + 15) / 16));
-    const int64_t gran = chunk_len > TILE ? TILE : MIN_CHUNK;
-    return std::max<int64_t>(MIN_CHUNK, (chunk_len + gran - 1) / gran * gran);
-}
-
-// chunk_len <= 0: choose so that a single large volume fills the chip.
-void make_plan(const std::vector<int64_t> &seg_off, int Q, int64_t chunk_len, Plan &P,
-               const std::vector<uint8_t> *active = nullptr)
-{
-    const int n_inst = (int)seg_off.size() - 1;
-    P.tiles.clear();
-    P.items.clear();
-    P.tile_begin.assign(n_inst + 1, 0);
-    if (chunk_len <= 0) {
-        int64_t total_tiles = 0, max_src = 0;
-        for (int i = 0; i < n_inst; ++i) {
-            if (active && !(*active)[i]) continue;
-            int64_t N = seg_off[i + 1] - seg_off[i];
-            total_tiles += (N * Q + TILE - 1) / TILE;
-            max_src = std::max(max_src, N);
-        }
-        chunk_len = heuristic_chunk(total_tiles, max_src);
-    }
-    P.chunk_len = chunk_len;
-    int64_t slot = 0;
-    for (int i = 0; i < n_inst; ++i) {
-        const int64_t s0 = seg_off[i], N = seg_off[i + 1] - s0;
-        P.tile_begin[i] = (int64_t)P.tiles.size();
-        if (active && !(*active)[i]) continue;   // an idle instance gets no tiles
-        const int64_t npts = N * Q;
-        const int nchunks = N > 0 ? (int)((N + chunk_len - 1) / chunk_len) : 0;
-        for (int64_t pb = 0; pb < npts; pb += TILE) {
-            Tile t;
-            t.point_begin = s0 * Q + pb;
-            t.n_points = (int32_t)std::min<int64_t>(TILE, npts - pb);
-            t.n_chunks = nchunks;
-            t.slot_begin = slot;
-            const int32_t tidx = (int32_t)P.tiles.size();
-            P.tiles.push_back(t);
-            for (int c = 0; c < nchunks; ++c) {
-                Item it;
-                it.tile = tidx;
-                it.pad = 0;
-                it.src_begin = s0 + c * chunk_len;
-                it.src_end = std::min(s0 + N, it.src_begin + chunk_len);
-                it.slot = slot++;
-                P.items.push_back(it);
-            }
-        }
-    }
-    P.tile_begin[n_inst] = (int64_t)P.tiles.size();
-    // longest items first: the dispatcher hands out workgroups in index order,
-    // which makes this a longest-processing-time-first schedule
-    std::stable_sort(P.items.begin(), P.items.end(), [&](const Item &a, const Item &b) {
-        const int64_t ca = (int64_t)P.tiles[a.tile].n_points * (a.src_end - a.src_begin);
-        const int64_t cb = (int64_t)P.tiles[b.tile].n_points * (b.src_end - b.src_begin);
-        return ca > cb;
-    });
-}
-
 template <class T>
 int upload(Workspace *ws, Slot s, const std::vector<T> &v, T **dev, hipStream_t st)
 {

@@ -119,44 +119,6 @@ int ensure(Workspace *ws, Slot s, size_t bytes, void **out)
     return DD_OK;
 }
 
-// Gauss-Legendre rule on [0, 1]: the roots z of P_n are found by Newton's
-// method on the Legendre recurrence (k P_k = (2k-1) z P_{k-1} - (k-1) P_{k-2})
-// from the guess cos(pi (4i + 3) / (4n + 2)); P_n'(z) = n (z P_n - P_{n-1}) /
-// (z^2 - 1) and the weight on [-1, 1] is 2 / ((1 - z^2) P_n'(z)^2).
-GaussRule gauss_rule(int n)
-{
-    GaussRule g{};
-    g.n = n;
-    for (int i = 0; i < n; ++i) {
-        double z = std::cos(M_PI * (4.0 * i + 3.0) / (4.0 * n + 2.0));
-        double p = 0, q = 0, dp = 1;
-        for (int it = 0; it < 60; ++it) {
-            q = 1.0;   // P_{k-1}
-            p = z;     // P_k
-            for (int k = 2; k <= n; ++k) {
-                double r = ((2 * k - 1) * z * p - (k - 1) * q) / k;
-                q = p;
-                p = r;
-            }
-            dp = n * (z * p - q) / (z * z - 1.0);
-            double step = p / dp;
-            z -= step;
-            if (std::fabs(step) < 1e-17) break;
-        }
-        q = 1.0; p = z;
-        for (int k = 2; k <= n; ++k) {
-            double r = ((2 * k - 1) * z * p - (k - 1) * q) / k;
-            q = p;
-            p = r;
-        }
-        dp = n * (z * p - q) / (z * z - 1.0);
-        // i = 0 is the largest root
-        g.s[n - 1 - i] = 0.5 * (1.0 + z);
-        g.w[n - 1 - i] = 1.0 / ((1.0 - z * z) * dp * dp);
-    }
-    return g;
-}
-
 void drop_graphs(Workspace *ws)
 {
     if (ws->graphs.empty()) return;

@@ -1,6 +1,7 @@
 """AddressSanitizer + UndefinedBehaviorSanitizer builds on the CPU: the oracle
 (oracle/ddo.c, plain and OpenMP builds) driven through every routine by
-tests/asan/oracle_driver.c.  Each build must exit 0 with no sanitizer report.
+tests/asan/oracle_driver.c, and the library's host planning code
+(csrc/dd_host.cpp) driven by tests/asan/host_driver.cpp.  Each build must exit 0 with no sanitizer report.
 Only host compilers are used (gcc / g++); nothing here runs on a GPU."""
 import os
 import shutil
@@ -35,3 +36,16 @@ def test_oracle_under_sanitizers(openmp, tmp_path):
            "-lm", "-o", exe]
     out = _run(cmd, exe, tmp_path)
     assert "0 failures" in out
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="g++ not available")
+def test_host_planning_under_sanitizers(tmp_path):
+    """The library's host-only planning code (csrc/dd_host.cpp: work split and
+    Gauss-Legendre rule) driven by tests/asan/host_driver.cpp, which checks
+    the plan invariants on many instance layouts."""
+    exe = str(tmp_path / "host_asan")
+    csrc = os.path.join(ROOT, "paper_2005_02498_amd", "csrc")
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-Wall", *SAN, "-I", os.path.join(ROOT, "include"), "-I", csrc,
+           os.path.join(csrc, "dd_host.cpp"), os.path.join(ROOT, "tests", "asan", "host_driver.cpp"), "-o", exe]
+    out = _run(cmd, exe, tmp_path)
+    assert " 0 failures" in out
