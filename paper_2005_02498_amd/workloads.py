@@ -340,3 +340,26 @@ def relabel(inst: Instance, seed=7):
     return (Instance(x, seg, np.ascontiguousarray(inst.burgers[:, sperm]),
                      np.ascontiguousarray(inst.normal[:, sperm]), pinned, inst.sigma_app.copy(),
                      inst.volume, dict(inst.meta, relabel=seed)), nmap)
+
+
+def with_junction_slots(inst: Instance, n_slots: int) -> Instance:
+    """The instance with room for n_slots junction nodes: after its own nodes,
+    n_slots node slots and two dummy nodes D1, D2, all pinned; after its own
+    segments, n_slots free segment slots D1 -> D2 with Burgers vector 0 (they
+    add no stress, feel no force and belong to no slip system).  D1 lies ten
+    box widths off the volume on the x axis and D2 ten b beyond it; the free
+    node slots sit at D1."""
+    nn, ns = inst.n_nodes, inst.n_segs
+    span = float(np.ptp(inst.x)) if nn else 1.0
+    d1 = np.array([inst.x[0].min() - 10.0 * max(span, 1.0), 0.0, 0.0])
+    d2 = d1 + np.array([10.0, 0.0, 0.0])
+    x = np.concatenate([inst.x, np.tile(d1[:, None], (1, n_slots)), d1[:, None], d2[:, None]], axis=1)
+    pinned = np.concatenate([np.asarray(inst.pinned, np.uint8), np.ones(n_slots + 2, np.uint8)])
+    D1, D2 = nn + n_slots, nn + n_slots + 1
+    sn = np.concatenate([inst.seg_nodes, np.tile(np.array([[D1], [D2]], np.int32), (1, n_slots))], axis=1)
+    bur = np.concatenate([inst.burgers, np.zeros((3, n_slots))], axis=1)
+    nrm = np.concatenate([inst.normal, np.tile(np.array([[0.0], [0.0], [1.0]]), (1, n_slots))], axis=1)
+    meta = dict(inst.meta)
+    meta["junction_slots"] = n_slots
+    return Instance(x=x, seg_nodes=sn.astype(np.int32), burgers=bur, normal=nrm, pinned=pinned,
+                    sigma_app=np.array(inst.sigma_app, float), volume=inst.volume, meta=meta)
