@@ -365,6 +365,75 @@ int dd_burst_batch_junctions(int32_t n_inst, const int64_t *node_off, const int6
                              double exact_eta, int n_steps, double dt, const dd_junctions *junctions,
                              double *rate_avg_out, double *features_out, void *stream);
 
+/* Junction nodes (Sec. "Thermal activation", Eq. tb), for
+ * dd_burst_batch_junction_nodes: a mobile dislocation that meets a sessile one
+ * is held at their intersection until the junction breaks after
+ * t_b = f * max_break_time, and bows around it meanwhile.
+ *  - Capture: a mobile segment (not sessile, not a free slot) that comes
+ *    closer than capture_radius to a sessile segment of its instance (an
+ *    instance's own segment between two of its own pinned nodes) is split at
+ *    its point of closest approach (segment-to-segment) by a pinned junction
+ *    node: a -> b becomes a -> j and j -> b (same Burgers vector and normal).
+ *    The node keeps at least min_length from both ends (parameter clamped to
+ *    [min_length / L, 1 - min_length / L]); a segment no longer than
+ *    2 min_length forms no junction.
+ *  - A segment forms no junction while it is within 2 capture_radius of the
+ *    point of its last junction (point-to-segment distance): both halves of
+ *    a split keep the junction point (junctions do not nest), and so does
+ *    the merged segment after the release.
+ *  - Release: at t >= its release time the node is removed: its in-segment
+ *    takes the end node of its out-segment, which is freed.
+ *  - Order, each step k at time t0 + k dt: releases (node slots in index
+ *    order); then captures found on the positions at the start of the step
+ *    (per segment the first sessile segment in index order), applied in
+ *    segment index order; a capture takes the lowest
+ *    free node slot and the lowest free segment slot, and without one it is
+ *    not made and counted in missed.  f = fractions[inst][count mod
+ *    n_fractions], count = the instance's number of junctions so far.
+ *    Distances and the junction point are computed in float64 without fused
+ *    multiply-adds.
+ *  - Slots: every instance ends its nodes with n_slots node slots and two
+ *    dummy nodes D1, D2 (all pinned), and its segments with n_slots segment
+ *    slots; a free segment slot is D1 -> D2 with Burgers vector 0 and a unit
+ *    normal (it adds no stress, feels no force and belongs to no slip
+ *    system).  The caller sets up the free slots; seg_nodes, burgers, normal
+ *    and the positions of node slots change in place.
+ *  - State (device arrays, caller-owned, carried from call to call; start
+ *    with ses = -1, ignore = count = missed = 0): release [n_nodes] (release
+ *    time of an active junction node), ses [n_nodes] (batch index of its
+ *    sessile segment, -1: the node slot is free), ignore [n_segs] (1 while
+ *    the segment keeps the point of its last junction), point [3][n_segs]
+ *    (that point), count and missed [n_inst].
+ * Units: lengths as the positions, times as dt. */
+typedef struct {
+    double capture_radius, max_break_time, t0, min_length;
+    int32_t n_slots, n_fractions;
+    const double *fractions;   /* [n_inst][n_fractions] */
+    double *release;           /* [n_nodes] */
+    int32_t *ses;              /* [n_nodes] */
+    int32_t *ignore;           /* [n_segs] */
+    double *point;             /* [3][n_segs] */
+    int32_t *count, *missed;   /* [n_inst] */
+} dd_junction_nodes;
+
+/* dd_burst_batch with junction nodes (see dd_junction_nodes): the arguments
+ * and outputs of dd_burst_batch except exact_eta (no exact band: the
+ * topology changes during the call); seg_nodes, burgers and normal are
+ * changed in place.  Rates are averaged over the steps; features_out
+ * (nullable) describes the state at the start of the call.
+ * Errors: DD_EINVAL as dd_burst_batch, and for a null `junctions` or state
+ * array, n_slots < 1, n_fractions < 1, a negative or non-finite radius,
+ * breaking time or min_length, a non-finite t0, or an instance with fewer
+ * than n_slots + 2 nodes or n_slots segments; an inconsistent slot state
+ * (a junction node without its two segments) is reported as DD_EINVAL by
+ * the call, or by dd_check when validation is off. */
+int dd_burst_batch_junction_nodes(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                                  int32_t *seg_nodes, double *burgers, double *normal, const uint8_t *pinned,
+                                  const double *sigma_app, const double *volume, const dd_material *m,
+                                  int n_gauss, int precision, double near_cutoff_a, int n_steps, double dt,
+                                  const dd_junction_nodes *junctions, double *rate_avg_out, double *features_out,
+                                  void *stream);
+
 /* One slow-time step of Practical Time Averaging for a batch of independent
  * DD volumes (Sec. "Application of PTA for coarse-graining DD simulation",
  * subsection "Algorithm", steps 1-7).  Volume i is at slow time t[i] under

@@ -14,15 +14,16 @@ here (the paper states the rule, not the DD code's mechanics):
   * the inserted node keeps at least l_min from both ends (its parameter on
     the segment is clamped to [l_min / L, 1 - l_min / L]); a segment no longer
     than 2 l_min forms no junction;
-  * both halves ignore that sessile segment (they touch it at the junction
-    node); at release the node is removed: its in-segment takes the
-    out-segment's end node, and the merged segment keeps ignoring the
-    sessile segment it broke from until it is farther than 2 r_c from it
-    (the segment-to-segment distance);
+  * a segment forms no junction while it is within 2 r_c of the point of its
+    last junction (point-to-segment distance): both halves of a split get the
+    junction point, so they are never captured while the node holds them
+    (junctions do not nest), and at release the node is removed (its
+    in-segment takes the out-segment's end node) and the merged segment keeps
+    the point until it has moved 2 r_c away from it;
   * every step, at time t_k = t0 + k dt, in this order: releases (node slots
     in index order, t_k >= release time), then captures found on the
     positions at the start of the step (one per mobile segment, the first
-    sessile segment in index order other than the ignored one), applied in
+    sessile segment in index order), applied in
     segment index order; a capture needs a free node slot and a free segment
     slot (the lowest of each); without one it is not made and counted as
     missed;
@@ -81,12 +82,25 @@ class Params:
         self.rc, self.a, self.l_min, self.K, self.t0 = capture_radius, max_break_time, l_min, n_slots, t0
 
 
+def point_segment_d2(p, a, b):
+    """Squared distance from p to the segment a -> b (the clamped projection)."""
+    d0, d1, d2 = b[0] - a[0], b[1] - a[1], b[2] - a[2]
+    w0, w1, w2 = p[0] - a[0], p[1] - a[1], p[2] - a[2]
+    dd = d0 * d0 + d1 * d1 + d2 * d2
+    t = min(max((w0 * d0 + w1 * d1 + w2 * d2) / dd, 0.0), 1.0)
+    e0 = p[0] - (a[0] + t * d0)
+    e1 = p[1] - (a[1] + t * d1)
+    e2 = p[2] - (a[2] + t * d2)
+    return e0 * e0 + e1 * e1 + e2 * e2
+
+
 def new_state(nn, ns, fractions):
     """Per node: release time and the sessile segment of an active junction
-    node (-1: none); per segment: the ignored sessile segment (-1: none); the
-    volume's junction count and missed captures; its fractions [Kf]."""
-    return {"release": np.zeros(nn), "ses": np.full(nn, -1, np.int64), "ignore": np.full(ns, -1, np.int64),
-            "count": 0, "missed": 0, "fractions": np.asarray(fractions, float)}
+    node (-1: none); per segment: whether it keeps a junction point and the
+    point [3][ns]; the volume's junction count and missed captures; its
+    fractions [Kf]."""
+    return {"release": np.zeros(nn), "ses": np.full(nn, -1, np.int64), "ignore": np.zeros(ns, bool),
+            "point": np.zeros((3, ns)), "count": 0, "missed": 0, "fractions": np.asarray(fractions, float)}
 
 
 def _layout(nn, ns, K):
@@ -109,8 +123,9 @@ def topology_step(x, sn, bur, nrm, pinned, t, P: Params, st):
             sn[0, s_out], sn[1, s_out] = d1, d2
             bur[:, s_out] = 0.0
             nrm[:, s_out] = (0.0, 0.0, 1.0)
-            st["ignore"][s_in] = st["ses"][j]
-            st["ignore"][s_out] = -1
+            st["ignore"][s_in] = True
+            st["point"][:, s_in] = x[:, j]
+            st["ignore"][s_out] = False
             st["ses"][j] = -1
     # candidates on the positions at the start of the step
     def free_seg(s):
@@ -126,13 +141,12 @@ def topology_step(x, sn, bur, nrm, pinned, t, P: Params, st):
         if free_seg(s) or sessile(s):
             continue
         p, p2 = x[:, sn[0, s]], x[:, sn[1, s]]
-        ig = int(st["ignore"][s])
-        if ig >= 0 and segment_closest(p, p2, x[:, sn[0, ig]], x[:, sn[1, ig]])[0] > rf2:
-            ig = -1
-            st["ignore"][s] = -1
-        for k in ses:
-            if k == ig:
+        if st["ignore"][s]:
+            if point_segment_d2(st["point"][:, s], p, p2) > rf2:
+                st["ignore"][s] = False
+            else:
                 continue
+        for k in ses:
             dd2, u = segment_closest(p, p2, x[:, sn[0, k]], x[:, sn[1, k]])
             if dd2 < rc2:
                 cand.append((s, k, u))
@@ -159,8 +173,10 @@ def topology_step(x, sn, bur, nrm, pinned, t, P: Params, st):
         sn[0, s2], sn[1, s2] = j, b
         bur[:, s2] = bur[:, s]
         nrm[:, s2] = nrm[:, s]
-        st["ignore"][s] = k
-        st["ignore"][s2] = k
+        st["ignore"][s] = True
+        st["ignore"][s2] = True
+        st["point"][:, s] = x[:, j]
+        st["point"][:, s2] = x[:, j]
         c = int(st["count"])
         st["release"][j] = t + st["fractions"][c % len(st["fractions"])] * P.a
         st["ses"][j] = k

@@ -26,7 +26,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
     "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_check", "dd_set_plan", "dd_last_plan",
-    "dd_nodal_forces", "dd_nodal_forces_noalloc", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_pta_step", "dd_pta_step_junctions",
+    "dd_nodal_forces", "dd_nodal_forces_noalloc", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_burst_batch_junction_nodes", "dd_pta_step", "dd_pta_step_junctions",
     "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -50,6 +50,14 @@ class Junctions(C.Structure):
     _fields_ = [("capture_radius", C.c_double), ("max_break_time", C.c_double), ("t0", C.c_double),
                 ("n_fractions", C.c_int32), ("fractions", C.c_void_p), ("junction", C.c_void_p),
                 ("release", C.c_void_p), ("ignore", C.c_void_p), ("count", C.c_void_p)]
+
+
+class JunctionNodes(C.Structure):
+    """dd_junction_nodes of dd.h (device pointers as integers)."""
+    _fields_ = [("capture_radius", C.c_double), ("max_break_time", C.c_double), ("t0", C.c_double),
+                ("min_length", C.c_double), ("n_slots", C.c_int32), ("n_fractions", C.c_int32),
+                ("fractions", C.c_void_p), ("release", C.c_void_p), ("ses", C.c_void_p), ("ignore", C.c_void_p),
+                ("point", C.c_void_p), ("count", C.c_void_p), ("missed", C.c_void_p)]
 
 
 class Material(C.Structure):
@@ -130,6 +138,9 @@ def _declare(L):
         "dd_burst_batch_junctions": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp,
                                                vp, vp, vp, vp, vp, C.POINTER(Material), C.c_int, C.c_int,
                                                dbl, dbl, C.c_int, dbl, C.POINTER(Junctions), vp, vp, vp]),
+        "dd_burst_batch_junction_nodes": (C.c_int, [i32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp,
+                                                    vp, vp, vp, vp, vp, C.POINTER(Material), C.c_int, C.c_int,
+                                                    dbl, C.c_int, dbl, C.POINTER(JunctionNodes), vp, vp, vp]),
         "dd_mlp_create": (C.c_int, [C.c_int, C.c_uint64, C.POINTER(vp)]),
         "dd_mlp_destroy": (C.c_int, [vp]),
         "dd_mlp_set_params": (C.c_int, [vp, C.c_int, fp]),
@@ -442,6 +453,65 @@ def dd_burst_batch_junctions(node_off, seg_off, x, seg_nodes, burgers, normal, p
                                           int(n_gauss), _prec(precision), float(near_cutoff_a), float(exact_eta),
                                           int(n_steps), float(dt), C.byref(jn), pr, None, _stream(stream)))
     return rate_avg_out
+
+
+def junction_node_state(n_nodes, n_segs, n_inst, device):
+    """Initial state of dd_burst_batch_junction_nodes (no junctions): release
+    [n_nodes] float64, ses [n_nodes] int32 = -1, ignore [n_segs] int32 = 0,
+    point [3][n_segs] float64, count and missed [n_inst] int32 = 0."""
+    return {"release": torch.zeros(n_nodes, dtype=torch.float64, device=device),
+            "ses": torch.full((n_nodes,), -1, dtype=torch.int32, device=device),
+            "ignore": torch.zeros(n_segs, dtype=torch.int32, device=device),
+            "point": torch.zeros((3, n_segs), dtype=torch.float64, device=device),
+            "count": torch.zeros(n_inst, dtype=torch.int32, device=device),
+            "missed": torch.zeros(n_inst, dtype=torch.int32, device=device)}
+
+
+def dd_burst_batch_junction_nodes(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume,
+                                  mat, state, fractions, capture_radius, max_break_time, min_length, n_slots,
+                                  t0=0.0, n_gauss=2, precision=DD_MIXED, near_cutoff_a=20.0, n_steps=200,
+                                  dt=2e-14, rate_avg_out=None, features_out=None, want_features=False,
+                                  stream=None):
+    """Batched bursts with junction nodes (dd.h, dd_junction_nodes): every
+    instance ends with n_slots node slots, two dummy nodes and n_slots segment
+    slots (workloads.with_junction_slots).  x, seg_nodes, burgers, normal and
+    the state (junction_node_state) change in place; fractions [n_inst][K]
+    float64 (device).  Returns (rate_avg [n_inst][12], features or None)."""
+    no = (C.c_int64 * len(node_off))(*[int(v) for v in node_off])
+    so = (C.c_int64 * len(seg_off))(*[int(v) for v in seg_off])
+    n_inst = len(node_off) - 1
+    if len(seg_off) != n_inst + 1:
+        raise ValueError("node_off and seg_off must have the same length")
+    nn, ns = int(node_off[-1]), int(seg_off[-1])
+    dev = x.device
+    px = _dev(x, torch.float64, (3, nn), "x")
+    psn = _dev(seg_nodes, torch.int32, (2, ns), "seg_nodes")
+    pb = _dev(burgers, torch.float64, (3, ns), "burgers")
+    pn = _dev(normal, torch.float64, (3, ns), "normal")
+    pp = _dev(pinned, torch.uint8, (nn,), "pinned", nullable=True)
+    ps = _dev(sigma_app, torch.float64, (n_inst, 6), "sigma_app")
+    pv = _dev(volume, torch.float64, (n_inst,), "volume")
+    K = fractions.shape[1] if fractions.dim() == 2 else -1
+    pf = _dev(fractions, torch.float64, (n_inst, K), "fractions")
+    jn = JunctionNodes(float(capture_radius), float(max_break_time), float(t0), float(min_length), int(n_slots),
+                       int(K), pf.value,
+                       _dev(state["release"], torch.float64, (nn,), "release").value,
+                       _dev(state["ses"], torch.int32, (nn,), "ses").value,
+                       _dev(state["ignore"], torch.int32, (ns,), "ignore").value,
+                       _dev(state["point"], torch.float64, (3, ns), "point").value,
+                       _dev(state["count"], torch.int32, (n_inst,), "count").value,
+                       _dev(state["missed"], torch.int32, (n_inst,), "missed").value)
+    if rate_avg_out is None:
+        rate_avg_out = torch.empty((n_inst, 12), dtype=torch.float64, device=dev)
+    pr = _dev(rate_avg_out, torch.float64, (n_inst, 12), "rate_avg_out")
+    if features_out is None and want_features:
+        features_out = torch.empty((n_inst, 36), dtype=torch.float64, device=dev)
+    pfe = _dev(features_out, torch.float64, (n_inst, 36), "features_out", nullable=True)
+    m = _mat(mat)
+    _check(lib().dd_burst_batch_junction_nodes(n_inst, no, so, px, psn, pb, pn, pp, ps, pv, C.byref(m),
+                                               int(n_gauss), _prec(precision), float(near_cutoff_a), int(n_steps),
+                                               float(dt), C.byref(jn), pr, pfe, _stream(stream)))
+    return rate_avg_out, features_out
 
 
 def _junction_args(state, fractions, capture_radius, max_break_time, nn, t0=0.0):

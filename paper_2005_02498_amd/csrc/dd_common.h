@@ -77,6 +77,7 @@ enum Slot {
     WS_HELD,           // junctions: nodes held in this step
     WS_SES,            //   sessile-segment flags, positions, indices
     WS_SES_X,          //   their end points and bounding spheres
+    WS_JN_CAND,        // junction nodes: per-segment candidates and parameters
     WS_NSLOTS
 };
 

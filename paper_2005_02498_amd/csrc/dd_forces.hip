@@ -670,6 +670,307 @@ int junction_prepare(Workspace *ws, const Layout &L, const int32_t *seg_nodes, c
     return DD_OK;
 }
 
+// ---------------------------------------------------------- junction nodes --
+// Junction nodes (Sec. "Thermal activation", Eq. tb): a mobile segment that
+// comes closer than the capture radius to a sessile segment of its instance
+// is split at its point of closest approach by a pinned node taken from the
+// instance's node slots, with the out-half in a segment slot; the node is
+// removed when its junction breaks (the rules and the slot layout are those
+// of dd_junction_nodes in dd.h).  Decisions and the junction point are formed
+// in FP64 without fused multiply-adds, in the same order of operations as the
+// oracle, so that both take the same decisions.
+
+// Closest approach of the segments p -> p2 and q -> q2: the squared distance,
+// and in u the parameter of the closest point on the first.  The unclamped
+// parameter on the first line is (b f - c e) / (a e - b^2) (a = d1.d1,
+// b = d1.d2, c = d1.r, e = d2.d2, f = d2.r, r = p - q), clamped to [0, 1];
+// the second parameter v = (b u + f) / e follows, and when v leaves [0, 1]
+// it is clamped and u recomputed for that end of the second segment.
+__device__ __forceinline__ double seg_seg_closest(const double *p, const double *p2, const double *q,
+                                                  const double *q2, double &u_out)
+{
+#pragma clang fp contract(off)
+    const double d10 = p2[0] - p[0], d11 = p2[1] - p[1], d12 = p2[2] - p[2];
+    const double d20 = q2[0] - q[0], d21 = q2[1] - q[1], d22 = q2[2] - q[2];
+    const double r0 = p[0] - q[0], r1 = p[1] - q[1], r2 = p[2] - q[2];
+    const double a = d10 * d10 + d11 * d11 + d12 * d12;
+    const double e = d20 * d20 + d21 * d21 + d22 * d22;
+    const double f = d20 * r0 + d21 * r1 + d22 * r2;
+    const double c = d10 * r0 + d11 * r1 + d12 * r2;
+    const double b = d10 * d20 + d11 * d21 + d12 * d22;
+    const double den = a * e - b * b;
+    double u = den > 0.0 ? fmin(fmax((b * f - c * e) / den, 0.0), 1.0) : 0.0;
+    double v = (b * u + f) / e;
+    if (v < 0.0) {
+        v = 0.0;
+        u = fmin(fmax(-c / a, 0.0), 1.0);
+    } else if (v > 1.0) {
+        v = 1.0;
+        u = fmin(fmax((b - c) / a, 0.0), 1.0);
+    }
+    const double w0 = (p[0] + u * d10) - (q[0] + v * d20);
+    const double w1 = (p[1] + u * d11) - (q[1] + v * d21);
+    const double w2 = (p[2] + u * d12) - (q[2] + v * d22);
+    u_out = u;
+    return w0 * w0 + w1 * w1 + w2 * w2;
+}
+
+struct JNodeArgs {
+    double rc, rc2, rf2, a, lmin, t;   // capture radius, its square, (2 r_c)^2, max breaking time, l_min, time
+    int32_t K, Kf;                     // slots per instance, fractions per instance
+    const double *fractions;           // [n_inst][Kf]
+    double *release;                   // [nn]
+    int32_t *ses;                      // [nn] batch index of the sessile segment, -1: free slot
+    int32_t *ignore;                   // [ns] 1 while the segment keeps the point of its last junction
+    double *point;                     // [3][ns] that point
+    int32_t *count, *missed;           // [n_inst]
+    const int32_t *flag;               // [ns] sessile
+    const int32_t *pos, *ses_idx;      // the compact sessile list (as for JunctionArgs)
+    const double *ses_x, *ses_ssp, *ses_sph;
+    int32_t *cand;                     // [ns] sessile candidate of a segment, -1: none
+    double *cand_u;                    // [ns] its parameter on the segment
+};
+
+// Sessile segments for junction nodes: an instance's own segment (not a
+// segment slot) between two of its own nodes (not node slots or dummies),
+// both pinned.
+__global__ void k_jn_ses_flag(Layout L, const int32_t *__restrict__ seg_nodes, const uint8_t *__restrict__ pinned,
+                              int32_t K, int32_t *__restrict__ flag)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= L.ns) return;
+    const int inst = seg_instance(L, s);
+    const int64_t sl = s - L.seg_off[inst], n_s = L.seg_off[inst + 1] - L.seg_off[inst];
+    const int64_t n_n = node_count(L, inst);
+    int64_t g1, g2;
+    const bool ok = seg_ends(L, seg_nodes, s, g1, g2);
+    const int64_t a = seg_nodes[s], b = seg_nodes[L.ns + s];
+    flag[s] = ok && sl < n_s - K && a < n_n - K - 2 && b < n_n - K - 2 && pinned[g1] && pinned[g2] ? 1 : 0;
+}
+
+// Releases (one workgroup per instance): node slots in index order whose
+// junction has broken at time t are removed; the node's in-segment takes the
+// end node of its out-segment, which becomes a free segment slot (D1 -> D2,
+// Burgers vector 0); the merged segment keeps the junction point.
+__global__ __launch_bounds__(256) void k_jn_release(Layout L, int32_t *__restrict__ seg_nodes,
+                                                    const double *__restrict__ x, double *__restrict__ burgers,
+                                                    double *__restrict__ normal, JNodeArgs J,
+                                                    const uint8_t *__restrict__ active, uint32_t *__restrict__ flags)
+{
+    const int inst = blockIdx.x, tid = threadIdx.x;
+    if (active && !active[inst]) return;
+    const int64_t n0 = L.node_off[inst], n_n = L.node_off[inst + 1] - n0;
+    const int64_t s0 = L.seg_off[inst], n_s = L.seg_off[inst + 1] - s0, ns = L.ns;
+    if (n_n < J.K + 2 || n_s < J.K) return;
+    const int32_t d1 = (int32_t)(n_n - 2), d2 = (int32_t)(n_n - 1);
+    __shared__ int64_t s_in, s_out;
+    for (int64_t jl = n_n - J.K - 2; jl < n_n - 2; ++jl) {
+        const int64_t j = n0 + jl;
+        if (!(J.ses[j] >= 0 && J.t >= J.release[j])) continue;   // the same for every thread
+        if (tid == 0) {
+            s_in = -1;
+            s_out = -1;
+        }
+        __syncthreads();
+        for (int64_t q = tid; q < n_s; q += blockDim.x) {
+            if (seg_nodes[ns + s0 + q] == jl) s_in = q;
+            if (seg_nodes[s0 + q] == jl) s_out = q;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (s_in >= 0 && s_out >= 0) {
+                const int64_t a = s0 + s_in, b = s0 + s_out;
+                seg_nodes[ns + a] = seg_nodes[ns + b];
+                seg_nodes[b] = d1;
+                seg_nodes[ns + b] = d2;
+                for (int c = 0; c < 3; ++c) {
+                    burgers[c * ns + b] = 0.0;
+                    normal[c * ns + b] = c == 2 ? 1.0 : 0.0;
+                }
+                J.ignore[a] = 1;   // the merged segment keeps the junction point
+                for (int c = 0; c < 3; ++c) J.point[c * ns + a] = x[c * L.nn + j];
+                J.ignore[b] = 0;
+            } else {
+                atomicOr(flags, FLAG_BAD_INDEX);   // inconsistent slot state: the node is dropped
+            }
+            J.ses[j] = -1;
+        }
+        __syncthreads();
+    }
+}
+
+// Candidates (one thread per segment): a mobile segment (not sessile, not a
+// free slot) that keeps the point of its last junction forgets it once
+// farther than 2 r_c from it and is no candidate before; then it takes the
+// first sessile segment of its instance in index order closer than r_c.
+// Groups and segments whose bounding spheres are out of reach
+// (|m_s - m_k| >= h_s + h_k + r_c) are skipped, which leaves the order of the
+// exact tests unchanged.
+__global__ void k_jn_candidates(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
+                                JNodeArgs J, const uint8_t *__restrict__ active)
+{
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= L.ns) return;
+    J.cand[s] = -1;
+    const int inst = seg_instance(L, s);
+    if (active && !active[inst]) return;
+    const int64_t n_n = node_count(L, inst), nn = L.nn;
+    int64_t g1, g2;
+    if (!seg_ends(L, seg_nodes, s, g1, g2) || J.flag[s]) return;
+    if (seg_nodes[s] == n_n - 2 && seg_nodes[L.ns + s] == n_n - 1) return;   // a free segment slot
+    const double p[3] = {x[g1], x[nn + g1], x[2 * nn + g1]}, p2[3] = {x[g2], x[nn + g2], x[2 * nn + g2]};
+    const int64_t sb = L.seg_off[inst], se = L.seg_off[inst + 1];
+    if (J.ignore[s]) {
+        const double pt[3] = {J.point[s], J.point[L.ns + s], J.point[2 * L.ns + s]};
+        if (point_segment_d2(pt, p, p2) > J.rf2)
+            J.ignore[s] = 0;
+        else
+            return;
+    }
+    double u;
+    const double m0 = 0.5 * (p[0] + p2[0]), m1 = 0.5 * (p[1] + p2[1]), m2 = 0.5 * (p[2] + p2[2]);
+    const double t0 = p2[0] - p[0], t1 = p2[1] - p[1], t2 = p2[2] - p[2];
+    const double hs = 0.5 * sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+    const int64_t q_lo = J.pos[sb], q_hi = J.pos[se];
+    for (int64_t g = q_lo / JUNC_GROUP; g * JUNC_GROUP < q_hi; ++g) {
+        const double *c = J.ses_sph + 4 * g;
+        const double e0 = m0 - c[0], e1 = m1 - c[1], e2 = m2 - c[2];
+        const double rr = (c[3] + hs + J.rc) * (1.0 + 1e-9);
+        if (e0 * e0 + e1 * e1 + e2 * e2 >= rr * rr) continue;
+        const int64_t qa = g * JUNC_GROUP > q_lo ? g * JUNC_GROUP : q_lo;
+        const int64_t qb = (g + 1) * JUNC_GROUP < q_hi ? (g + 1) * JUNC_GROUP : q_hi;
+        for (int64_t q = qa; q < qb; ++q) {
+            const double *mk = J.ses_ssp + 4 * q;
+            const double f0 = m0 - mk[0], f1 = m1 - mk[1], f2 = m2 - mk[2];
+            const double rs = (mk[3] + hs + J.rc) * (1.0 + 1e-9);
+            if (f0 * f0 + f1 * f1 + f2 * f2 >= rs * rs) continue;
+            const int64_t k = J.ses_idx[q];
+            const double *e = J.ses_x + 6 * q;
+            if (seg_seg_closest(p, p2, e, e + 3, u) < J.rc2) {
+                J.cand[s] = (int32_t)k;
+                J.cand_u[s] = u;
+                return;
+            }
+        }
+    }
+}
+
+// Captures (one workgroup per instance), in segment index order: a candidate
+// segment a -> b longer than 2 l_min gets a junction node j in the lowest
+// free node slot at the clamped parameter u in [l_min / L, 1 - l_min / L],
+// becomes a -> j, and the lowest free segment slot becomes j -> b with its
+// Burgers vector and normal; both halves keep the junction point; the node
+// is released at t + f a, f = fractions[instance][count mod Kf].  Without a
+// free slot the capture is counted in missed.
+__global__ __launch_bounds__(256) void k_jn_capture(Layout L, int32_t *__restrict__ seg_nodes, double *__restrict__ x,
+                                                    double *__restrict__ burgers, double *__restrict__ normal,
+                                                    JNodeArgs J, const uint8_t *__restrict__ active)
+{
+#pragma clang fp contract(off)
+    const int inst = blockIdx.x, tid = threadIdx.x;
+    if (active && !active[inst]) return;
+    const int64_t n0 = L.node_off[inst], n_n = L.node_off[inst + 1] - n0;
+    const int64_t s0 = L.seg_off[inst], n_s = L.seg_off[inst + 1] - s0, ns = L.ns, nn = L.nn;
+    if (n_n < J.K + 2 || n_s < J.K) return;
+    const int32_t d1 = (int32_t)(n_n - 2), d2 = (int32_t)(n_n - 1);
+    __shared__ uint8_t has[256];
+    for (int64_t base = 0; base < n_s; base += blockDim.x) {
+        const int64_t q = base + tid;
+        const bool c = q < n_s && J.cand[s0 + q] >= 0;
+        has[tid] = c ? 1 : 0;
+        if (__syncthreads_count(c) && tid == 0) {
+            for (int i = 0; i < (int)blockDim.x && base + i < n_s; ++i) {
+                if (!has[i]) continue;
+                const int64_t s = s0 + base + i;
+                const int32_t k = J.cand[s];
+                const int64_t a = seg_nodes[s], b = seg_nodes[ns + s];
+                if (a < 0 || a >= n_n || b < 0 || b >= n_n) continue;
+                const int64_t ga = n0 + a, gb = n0 + b;
+                const double e0 = x[gb] - x[ga], e1 = x[nn + gb] - x[nn + ga], e2 = x[2 * nn + gb] - x[2 * nn + ga];
+                const double Ls = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                if (!(Ls > 2.0 * J.lmin)) continue;
+                const double u = fmin(fmax(J.cand_u[s], J.lmin / Ls), 1.0 - J.lmin / Ls);
+                int64_t jl = -1, s2l = -1;
+                for (int64_t r = n_n - J.K - 2; r < n_n - 2 && jl < 0; ++r)
+                    if (J.ses[n0 + r] < 0) jl = r;
+                for (int64_t r = n_s - J.K; r < n_s && s2l < 0; ++r)
+                    if (seg_nodes[s0 + r] == d1 && seg_nodes[ns + s0 + r] == d2) s2l = r;
+                if (jl < 0 || s2l < 0) {
+                    J.missed[inst] += 1;
+                    continue;
+                }
+                const int64_t j = n0 + jl, s2 = s0 + s2l;
+                x[j] = x[ga] + u * e0;
+                x[nn + j] = x[nn + ga] + u * e1;
+                x[2 * nn + j] = x[2 * nn + ga] + u * e2;
+                seg_nodes[ns + s] = (int32_t)jl;
+                seg_nodes[s2] = (int32_t)jl;
+                seg_nodes[ns + s2] = (int32_t)b;
+                for (int cc = 0; cc < 3; ++cc) {
+                    burgers[cc * ns + s2] = burgers[cc * ns + s];
+                    normal[cc * ns + s2] = normal[cc * ns + s];
+                }
+                J.ignore[s] = 1;
+                J.ignore[s2] = 1;
+                for (int cc = 0; cc < 3; ++cc) J.point[cc * ns + s] = J.point[cc * ns + s2] = x[cc * nn + j];
+                const int32_t cn = J.count[inst];
+                const int32_t kf = ((cn % J.Kf) + J.Kf) % J.Kf;
+                J.release[j] = release_time(J.t, J.fractions[(int64_t)inst * J.Kf + kf], J.a);
+                J.ses[j] = k;
+                J.count[inst] = cn + 1;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Junction-node arguments from the caller's parameters, and the compact list
+// of sessile segments (they never change: their nodes are pinned).
+int jnode_prepare(Workspace *ws, const Layout &L, const int32_t *seg_nodes, const double *x, const uint8_t *pinned,
+                  const dd_junction_nodes *jn, JNodeArgs &J, hipStream_t st)
+{
+    const int64_t ns = L.ns;
+    void *p;
+    int rc;
+    J = JNodeArgs{};
+    J.rc = jn->capture_radius;
+    J.rc2 = jn->capture_radius * jn->capture_radius;
+    J.rf2 = (2.0 * jn->capture_radius) * (2.0 * jn->capture_radius);
+    J.a = jn->max_break_time;
+    J.lmin = jn->min_length;
+    J.K = jn->n_slots;
+    J.Kf = jn->n_fractions;
+    J.fractions = jn->fractions;
+    J.release = jn->release;
+    J.ses = jn->ses;
+    J.ignore = jn->ignore;
+    J.point = jn->point;
+    J.count = jn->count;
+    J.missed = jn->missed;
+    if ((rc = ensure(ws, WS_SES, sizeof(int32_t) * (3 * ns + 1), &p))) return rc;
+    int32_t *flag = (int32_t *)p, *pos = flag + ns, *idx = pos + ns + 1;
+    if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (10 * ns + 4 * ((ns + JUNC_GROUP - 1) / JUNC_GROUP) + 4), &p)))
+        return rc;
+    double *sx = (double *)p, *ssp = sx + 6 * ns, *sph = ssp + 4 * ns;
+    if ((rc = ensure(ws, WS_JN_CAND, (sizeof(int32_t) + sizeof(double)) * std::max<int64_t>(ns, 1), &p))) return rc;
+    J.cand_u = (double *)p;
+    J.cand = (int32_t *)(J.cand_u + std::max<int64_t>(ns, 1));
+    const unsigned gs = grid_for(ns, 256, INT32_MAX);
+    hipLaunchKernelGGL(k_jn_ses_flag, dim3(gs), dim3(256), 0, st, L, seg_nodes, pinned, J.K, flag);
+    hipLaunchKernelGGL((k_scan<int32_t>), dim3(1), dim3(1024), 0, st, (const int32_t *)flag, ns, pos);
+    hipLaunchKernelGGL(k_ses_compact, dim3(gs), dim3(256), 0, st, L, seg_nodes, x, (const int32_t *)flag,
+                       (const int32_t *)pos, idx, sx, ssp);
+    hipLaunchKernelGGL(k_ses_spheres, dim3(grid_for((ns + JUNC_GROUP - 1) / JUNC_GROUP, 256, INT32_MAX)), dim3(256),
+                       0, st, ns, (const int32_t *)pos, (const double *)sx, sph);
+    J.flag = flag;
+    J.pos = pos;
+    J.ses_idx = idx;
+    J.ses_x = sx;
+    J.ses_ssp = ssp;
+    J.ses_sph = sph;
+    return DD_OK;
+}
+
 __global__ void k_euler(int64_t nn, double *x, const double *__restrict__ vel, double dt)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1040,6 +1341,22 @@ void launch_csr(const ForceCtx &C, const int32_t *seg_nodes, hipStream_t st)
     hipLaunchKernelGGL(k_csr_sort, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, st, C.csr_ptr, nn,
                        C.csr_list);
 }
+
+// The topology kernels of one step at time t (releases, candidates,
+// captures) and the node -> segment lists they change.
+void launch_jnode_step(const ForceCtx &C, JNodeArgs J, double t, int n_inst, int32_t *seg_nodes, double *x,
+                       double *burgers, double *normal, uint32_t *flags, hipStream_t st)
+{
+    J.t = t;
+    hipLaunchKernelGGL(k_jn_release, dim3(n_inst), dim3(256), 0, st, C.L, seg_nodes, (const double *)x, burgers,
+                       normal, J, (const uint8_t *)nullptr, flags);
+    hipLaunchKernelGGL(k_jn_candidates, dim3(grid_for(C.L.ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
+                       (const int32_t *)seg_nodes, (const double *)x, J, (const uint8_t *)nullptr);
+    hipLaunchKernelGGL(k_jn_capture, dim3(n_inst), dim3(256), 0, st, C.L, seg_nodes, x, burgers, normal, J,
+                       (const uint8_t *)nullptr);
+    launch_csr(C, seg_nodes, st);
+}
+
 
 // a1..a4 for positions x: segment records, pair kernel, epilogue, gather.
 // With the exact band, size_pairs = true counts the near pairs first, reads
@@ -1678,7 +1995,8 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
                      const int32_t *seg_nodes, const double *burgers, const double *normal, const uint8_t *pinned,
                      const double *sigma_app, const double *volume, const dd_material *m, int n_gauss, int precision,
                      double near_cutoff_a, double exact_eta, int n_steps, double dt, const dd_junctions *jn,
-                     double *rate_avg_out, double *features_out, void *stream)
+                     double *rate_avg_out, double *features_out, void *stream,
+                     const dd_junction_nodes *jnodes = nullptr)
 {
     int rc;
     if (n_inst < 0) return set_error(DD_EINVAL, "n_inst < 0");
@@ -1706,6 +2024,23 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
         if (jn->n_fractions < 1) return set_error(DD_EINVAL, "junctions: n_fractions must be >= 1");
         if (nn > 0 && (!jn->fractions || !jn->junction || !jn->release || !jn->ignore || !jn->count))
             return set_error(DD_EINVAL, "junctions: null state or fractions array");
+    }
+    if (jnodes) {
+        const dd_junction_nodes *J = jnodes;
+        if (!(J->capture_radius >= 0.0) || !std::isfinite(J->capture_radius) || !(J->max_break_time >= 0.0) ||
+            !std::isfinite(J->max_break_time) || !std::isfinite(J->t0) || !(J->min_length >= 0.0) ||
+            !std::isfinite(J->min_length))
+            return set_error(DD_EINVAL, "junction nodes: capture radius, breaking time and min_length must be "
+                                        "finite and >= 0, t0 finite");
+        if (J->n_slots < 1 || J->n_fractions < 1)
+            return set_error(DD_EINVAL, "junction nodes: n_slots and n_fractions must be >= 1");
+        if (!J->fractions || !J->release || !J->ses || !J->ignore || !J->point || !J->count || !J->missed)
+            return set_error(DD_EINVAL, "junction nodes: null state or fractions array");
+        if (exact_eta != 0.0) return set_error(DD_EINVAL, "junction nodes: no exact band (exact_eta must be 0)");
+        for (int i = 0; i < n_inst; ++i)
+            if (node_off[i + 1] - node_off[i] < (int64_t)J->n_slots + 2 || seg_off[i + 1] - seg_off[i] < J->n_slots)
+                return set_error(DD_EINVAL, "junction nodes: instance %d has fewer than n_slots + 2 nodes or n_slots "
+                                            "segments", i);
     }
     hipStream_t st = (hipStream_t)stream;
     Workspace *ws;
@@ -1736,6 +2071,8 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
     uint8_t *held = nullptr;
     JunctionArgs J{};
     if (jn && (rc = junction_prepare(ws, C.L, seg_nodes, x, pinned, jn, J, &held, st))) return rc;
+    JNodeArgs JN{};
+    if (jnodes && (rc = jnode_prepare(ws, C.L, seg_nodes, x, pinned, jnodes, JN, st))) return rc;
 
     launch_csr(C, seg_nodes, st);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(12 * (int64_t)n_inst)), dim3(256), 0, st, rate_avg_out,
@@ -1774,8 +2111,14 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
         key.add(exact_eta).add(n_steps).add(dt).add(choice).add(rate_avg_out).add(jn != nullptr);
         key.add(C.near.pair_cap).add_workspace(ws);
         if (jn) key.add(*jn);
+        key.add(jnodes != nullptr);
+        if (jnodes) key.add(*jnodes);
         rc = launch_cached_graph(ws, key, [&](hipStream_t cs) -> int {
             for (int k = 0; k < n_steps; ++k) {
+                if (jnodes)   // (the public call passes these arrays as writable)
+                    launch_jnode_step(C, JN, jnodes->t0 + k * dt, n_inst, const_cast<int32_t *>(seg_nodes), x,
+                                      const_cast<double *>(burgers), const_cast<double *>(normal), ws->flags_dev,
+                                      cs);
                 if (jn) {
                     J.t = jn->t0 + k * dt;
                     hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
@@ -1835,6 +2178,20 @@ extern "C" int dd_burst_batch_junctions(int32_t n_inst, const int64_t *node_off,
     return burst_batch_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m,
                             n_gauss, precision, near_cutoff_a, exact_eta, n_steps, dt, junctions, rate_avg_out,
                             features_out, stream);
+}
+
+extern "C" int dd_burst_batch_junction_nodes(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off,
+                                             double *x, int32_t *seg_nodes, double *burgers, double *normal,
+                                             const uint8_t *pinned, const double *sigma_app, const double *volume,
+                                             const dd_material *m, int n_gauss, int precision, double near_cutoff_a,
+                                             int n_steps, double dt, const dd_junction_nodes *junctions,
+                                             double *rate_avg_out, double *features_out, void *stream)
+{
+    clear_error();
+    if (!junctions) return set_error(DD_EINVAL, "null junction-node parameters");
+    return burst_batch_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m,
+                            n_gauss, precision, near_cutoff_a, 0.0, n_steps, dt, nullptr, rate_avg_out, features_out,
+                            stream, junctions);
 }
 
 // ======================================================= no-allocation call --

@@ -363,3 +363,45 @@ def with_junction_slots(inst: Instance, n_slots: int) -> Instance:
     meta["junction_slots"] = n_slots
     return Instance(x=x, seg_nodes=sn.astype(np.int32), burgers=bur, normal=nrm, pinned=pinned,
                     sigma_app=np.array(inst.sigma_app, float), volume=inst.volume, meta=meta)
+
+
+def junction_forest(seed, n_loops=2, n_chains=4, near=10.0, chain_segs=4, chain_len=150.0, box=2000.0,
+                    sigma_app=None) -> Instance:
+    """Mobile loops and a forest of sessile lines (straight chains of pinned
+    nodes) that pass close to them: chain c runs through a point at distance
+    near * U[0.2, 0.8] from the midpoint of a random loop segment, along a
+    random direction, so that mobile-sessile approaches closer than `near`
+    exist from the start.  Sessile lines carry a random Burgers vector and
+    plane of the FCC set.  Stress: uniaxial 200 MPa along [001] unless given."""
+    rng = np.random.default_rng(seed)
+    x, seg, bur, nor, meta = _loops(rng, n_loops, box, 100.0, 300.0)
+    nn, ns = x.shape[1], seg.shape[1]
+    xs, sns, bs, ns_ = [x], [seg], [bur], [nor]
+    node = nn
+    for c in range(n_chains):
+        s = int(rng.integers(0, ns))
+        a, b = x[:, seg[0, s]], x[:, seg[1, s]]
+        m = 0.5 * (a + b)
+        t = (b - a) / np.linalg.norm(b - a)
+        # a direction not along the segment, and an offset perpendicular to both
+        u = rng.normal(size=3)
+        u -= u.dot(t) * t
+        u /= np.linalg.norm(u)
+        w = np.cross(t, u)
+        p0 = m + near * rng.uniform(0.2, 0.8) * w
+        k = np.arange(chain_segs + 1) - chain_segs / 2.0
+        pts = p0[:, None] + (chain_len * k)[None, :] * u[:, None]
+        xs.append(pts)
+        sns.append(np.stack([np.arange(chain_segs) + node, np.arange(chain_segs) + node + 1]).astype(np.int32))
+        pl, di = int(rng.integers(0, 4)), int(rng.integers(0, 3))
+        bs.append(np.tile(SLIP_DIRS[pl, di][:, None], (1, chain_segs)))
+        ns_.append(np.tile(PLANE_NORMALS[pl][:, None], (1, chain_segs)))
+        node += chain_segs + 1
+    x = np.concatenate(xs, axis=1)
+    pinned = np.zeros(x.shape[1], np.uint8)
+    pinned[nn:] = 1
+    sig = uniaxial_001(200e6) if sigma_app is None else np.asarray(sigma_app, float)
+    return Instance(x=np.ascontiguousarray(x), seg_nodes=np.ascontiguousarray(np.concatenate(sns, axis=1)),
+                    burgers=np.ascontiguousarray(np.concatenate(bs, axis=1)),
+                    normal=np.ascontiguousarray(np.concatenate(ns_, axis=1)), pinned=pinned, sigma_app=sig,
+                    volume=box ** 3, meta=meta)

@@ -94,3 +94,17 @@ def test_host_only_calls_without_gpu():
     assert dd.lib().dd_pta_step_junctions(1, off, off, fake, fake, fake, fake, fake, fake, d1, d1,
                                           ctypes.byref(P), ctypes.byref(m), 2, 0, 20.0, 0.0, None, None, d1,
                                           None) == dd.DD_EINVAL
+    # junction nodes: parameters are checked before any device work
+    assert dd.lib().dd_burst_batch_junction_nodes(1, off, off, fake, fake, fake, fake, fake, fake, fake,
+                                                  ctypes.byref(m), 2, 0, 20.0, 1, 1.0, None, fake, None,
+                                                  None) == dd.DD_EINVAL
+    for bad in (dict(n_slots=0), dict(n_fractions=0), dict(capture_radius=-1.0), dict(min_length=float("nan")),
+                dict(t0=float("inf")), dict(n_slots=4)):   # n_slots = 4: the instance has 4 nodes, needs 6
+        kw = dict(capture_radius=5.0, max_break_time=1.0, t0=0.0, min_length=1.0, n_slots=1, n_fractions=1)
+        kw.update(bad)
+        jn = dd.JunctionNodes(kw["capture_radius"], kw["max_break_time"], kw["t0"], kw["min_length"],
+                              kw["n_slots"], kw["n_fractions"], 256, 256, 256, 256, 256, 256, 256)
+        assert dd.lib().dd_burst_batch_junction_nodes(1, off, off, fake, fake, fake, fake, fake, fake, fake,
+                                                      ctypes.byref(m), 2, 0, 20.0, 1, 1.0, ctypes.byref(jn), fake,
+                                                      None, None) == dd.DD_EINVAL, bad
+        assert "junction nodes" in dd.dd_last_error()

@@ -40,17 +40,23 @@ def test_closest_approach_closed_form_and_brute_force():
         assert d2 <= b2 + 1e-9 and b2 - d2 < 5e-3 * (1 + b2)
 
 
-def crossing(d=3.0, K=2, shift=0.0):
-    """A pinned sessile segment on the x axis (nodes 0, 1) and a mobile chain
-    along y at x = 30, height d (nodes 2-5, ends pinned): its middle segment
-    (3 -> 4) passes over the sessile one at y = shift."""
-    x = np.array([[-100.0, 100.0, 30.0, 30.0, 30.0, 30.0],
+def crossing(d=3.0, K=2, shift=0.0, cx=30.0, continued=False):
+    """A pinned sessile segment on the x axis (nodes 0, 1; with `continued` a
+    second one from x = 100 to 300, node 6) and a mobile chain along y at
+    x = cx, height d (nodes 2-5, ends pinned): its middle segment (3 -> 4)
+    passes over the sessile line at y = shift."""
+    x = np.array([[-100.0, 100.0, cx, cx, cx, cx],
                   [0.0, 0.0, -150.0 + shift, -50.0 + shift, 50.0 + shift, 150.0 + shift],
                   [0.0, 0.0, d, d, d, d]])
     sn = np.array([[0, 2, 3, 4], [1, 3, 4, 5]], np.int32)
-    b = np.array([[1.0, 0.0, 0.0, 0.0], [0.0, 1.0, 1.0, 1.0], [0.0, 0.0, 0.0, 0.0]]) / 1.0
-    nrm = np.tile(np.array([[0.0], [0.0], [1.0]]), (1, 4))
+    b = np.array([[1.0, 0.0, 0.0, 0.0], [0.0, 1.0, 1.0, 1.0], [0.0, 0.0, 0.0, 0.0]])
     pinned = np.array([1, 1, 1, 0, 0, 1], np.uint8)
+    if continued:
+        x = np.concatenate([x, [[300.0], [0.0], [0.0]]], axis=1)
+        sn = np.concatenate([sn, [[1], [6]]], axis=1).astype(np.int32)
+        b = np.concatenate([b, [[1.0], [0.0], [0.0]]], axis=1)
+        pinned = np.concatenate([pinned, [1]]).astype(np.uint8)
+    nrm = np.tile(np.array([[0.0], [0.0], [1.0]]), (1, sn.shape[1]))
     inst = W.Instance(x=x, seg_nodes=sn, burgers=b, normal=nrm, pinned=pinned, sigma_app=np.zeros(6),
                       volume=1e9)
     return W.with_junction_slots(inst, K)
@@ -73,23 +79,24 @@ def test_crossing_capture_release_merge_and_ignore():
     assert list(sn[:, 2]) == [3, 6] and list(sn[:, 4]) == [6, 4]
     assert list(bu[:, 4]) == list(bu[:, 2]) and list(nr[:, 4]) == list(nr[:, 2])
     assert st["release"][6] == 0.0 + 0.25 * 8.0 and st["ses"][6] == 0 and st["count"] == 1
-    assert st["ignore"][2] == 0 and st["ignore"][4] == 0   # both halves touch the sessile segment
+    # both halves keep the junction point: never captured while the node holds them
+    assert st["ignore"][2] and st["ignore"][4] and list(st["point"][:, 4]) == [30.0, 0.0, 3.0]
     # held until t = 2 (the other segments are farther than r_c: no capture)
     assert JN.topology_step(x, sn, bu, nr, inst.pinned, 1.5, P, st) == []
     assert list(sn[:, 2]) == [3, 6]
     # released at t = 2: the in-segment takes the out-segment's end, the slot is free again
     assert JN.topology_step(x, sn, bu, nr, inst.pinned, 2.0, P, st) == []
     assert list(sn[:, 2]) == [3, 4] and list(sn[:, 4]) == [8, 9] and not bu[:, 4].any()
-    assert st["ses"][6] == -1 and st["ignore"][2] == 0
-    # still within r_c, but the segment ignores the sessile one it broke from
+    assert st["ses"][6] == -1 and st["ignore"][2] and not st["ignore"][4]
+    # still within r_c, but the segment keeps the point of the junction it broke from
     assert JN.topology_step(x, sn, bu, nr, inst.pinned, 3.0, P, st) == []
-    # moved to 8 (within 2 r_c): still ignored; to 11 (beyond): forgotten
+    # moved to z = 8 (5 from the point, within 2 r_c): kept; to z = 14 (11, beyond): forgotten
     x[2, 2:6] = 8.0
     JN.topology_step(x, sn, bu, nr, inst.pinned, 4.0, P, st)
-    assert st["ignore"][2] == 0
-    x[2, 2:6] = 11.0
+    assert st["ignore"][2]
+    x[2, 2:6] = 14.0
     JN.topology_step(x, sn, bu, nr, inst.pinned, 5.0, P, st)
-    assert st["ignore"][2] == -1
+    assert not st["ignore"][2]
     # back within r_c: captured again, with the next fraction
     x[2, 2:6] = 3.0
     assert JN.topology_step(x, sn, bu, nr, inst.pinned, 6.0, P, st) == [(2, 0, 6, 4)]
@@ -111,6 +118,24 @@ def test_junction_point_clamped_near_an_end_and_short_segments():
     P2 = JN.Params(capture_radius=5.0, max_break_time=8.0, l_min=50.0, n_slots=2)
     x, sn, bu, nr = (np.array(a) for a in (inst.x, inst.seg_nodes, inst.burgers, inst.normal))
     assert JN.topology_step(x, sn, bu, nr, inst.pinned, 0.0, P2, _state(inst)) == []
+
+
+def test_adjacent_sessile_segment_does_not_recapture():
+    """The crossing at x = 97, 3 b from the shared node of two sessile
+    segments of one line: the first in index order forms the junction, and
+    the halves of the split segment are not captured by the second while the
+    node holds them."""
+    inst = crossing(cx=97.0, continued=True)
+    P = JN.Params(capture_radius=8.0, max_break_time=8.0, l_min=1.0, n_slots=2)
+    x, sn, bu, nr = (np.array(a) for a in (inst.x, inst.seg_nodes, inst.burgers, inst.normal))
+    st = _state(inst)
+    assert [m[:2] for m in JN.topology_step(x, sn, bu, nr, inst.pinned, 0.0, P, st)] == [(2, 0)]
+    # the second sessile segment (4) is within r_c of both halves
+    for s_half in (2, 5):
+        a, b = x[:, sn[0, s_half]], x[:, sn[1, s_half]]
+        assert JN.segment_closest(a, b, x[:, 1], x[:, 6])[0] < 64.0
+    for t in (0.5, 1.0, 1.5):
+        assert JN.topology_step(x, sn, bu, nr, inst.pinned, t, P, st) == []
 
 
 def test_no_free_slot_means_no_junction():
