@@ -676,8 +676,11 @@ def main():
                     out["surrogate"]["full_study"][k] = {"error": sur[k]["at_surrogate_error"]["error"],
                                                          "speedup": sur[k]["at_surrogate_error"]["speedup"],
                                                          "fallback": sur[k]["at_surrogate_error"]["fallback_fraction"]}
-            if "learning_curve" in sur:
-                out["surrogate"]["full_study"]["bursts_for_5_percent"] = sur["learning_curve"]["bursts_for_5_percent"]
+            lc = sur.get("learning_curve", {})
+            if "variance_law" in lc:
+                out["surrogate"]["full_study"]["bursts_for_5_percent"] = {
+                    "variance_law": lc["variance_law"]["bursts_for_5_percent"],
+                    "power_law": lc["power_law"]["bursts_for_5_percent"]}
 
     if args.cpu_targets > 0:
         out["cpu_baseline"] = cpu_baseline(args, inst)
