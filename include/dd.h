@@ -66,6 +66,8 @@ extern "C" {
 #define DD_ENOMEM     (-3)   /* device workspace allocation failed        */
 #define DD_ENONFINITE (-4)   /* a NaN or Inf reached an output            */
 #define DD_ECAPACITY  (-5)   /* a fixed-size device list ran out of room  */
+#define DD_EIO        (-6)   /* a file could not be opened, read or written,
+                                or is not a valid file of the expected kind */
 
 #define DD_MAX_GAUSS  16
 #define DD_N_SYSTEMS  12
@@ -588,6 +590,23 @@ int dd_mlp_destroy(dd_mlp *model);
 int dd_mlp_set_params(dd_mlp *model, int member, const float *host_params);
 /* Copy one member's float32 master parameters out to host memory. */
 int dd_mlp_get_params(const dd_mlp *model, int member, float *host_params);
+
+/* Persistence.  dd_mlp_save writes the whole ensemble to `path`: member
+ * count, network shape, Adam step count, the scaling of dd_mlp_set_scaling,
+ * dd_mlp_set_log_densities and dd_mlp_set_spread_floor, and per member the
+ * float32 master parameters and both Adam moments, followed by an FNV-1a
+ * checksum.  It writes `path`.tmp first and renames it, so `path` never holds
+ * a partial file.  dd_mlp_load reads and checks such a file (magic and
+ * version, shape, checksum, no trailing bytes, finite values) before any
+ * device call, then creates the ensemble on the current device; *out
+ * receives the handle, which the caller releases with dd_mlp_destroy.  A
+ * loaded model infers bit for bit as the saved one did, and training resumes
+ * where it stopped (same Adam state).  File errors return DD_EIO with the
+ * reason in dd_last_error(); *out stays NULL on any error. */
+int dd_mlp_save(const dd_mlp *model, const char *path);
+int dd_mlp_load(const char *path, dd_mlp **out);
+/* Member count and Adam steps taken (host outputs, each nullable). */
+int dd_mlp_info(const dd_mlp *model, int *n_members, int64_t *adam_steps);
 
 /* Feature and target standardisation (host arrays): the network sees
  * (feat - in_shift) * in_scale and predicts (rate - out_shift) / out_scale. */

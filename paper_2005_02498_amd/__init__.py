@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdd.so")
 
 DD_FP64, DD_MIXED = 0, 1
-DD_OK, DD_EINVAL, DD_EHIP, DD_ENOMEM, DD_ENONFINITE, DD_ECAPACITY = 0, -1, -2, -3, -4, -5
+DD_OK, DD_EINVAL, DD_EHIP, DD_ENOMEM, DD_ENONFINITE, DD_ECAPACITY, DD_EIO = 0, -1, -2, -3, -4, -5, -6
 N_SYSTEMS, N_FEATURES = 12, 36
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 
@@ -28,7 +28,7 @@ EXPORTS = [
     "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_check", "dd_set_plan", "dd_last_plan",
     "dd_nodal_forces", "dd_nodal_forces_noalloc", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_burst_batch_junction_nodes", "dd_pta_step", "dd_pta_step_junctions",
     "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
-    "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
+    "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params", "dd_mlp_save", "dd_mlp_load", "dd_mlp_info",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
     "dd_surrogate_rates",
 ]
@@ -145,6 +145,9 @@ def _declare(L):
         "dd_mlp_destroy": (C.c_int, [vp]),
         "dd_mlp_set_params": (C.c_int, [vp, C.c_int, fp]),
         "dd_mlp_get_params": (C.c_int, [vp, C.c_int, fp]),
+        "dd_mlp_save": (C.c_int, [vp, C.c_char_p]),
+        "dd_mlp_load": (C.c_int, [C.c_char_p, C.POINTER(vp)]),
+        "dd_mlp_info": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(i64)]),
         "dd_mlp_set_scaling": (C.c_int, [vp, fp, fp, fp, fp]),
         "dd_mlp_set_log_densities": (C.c_int, [vp, C.c_float, C.c_float]),
         "dd_mlp_set_spread_floor": (C.c_int, [vp, C.c_float]),
@@ -601,11 +604,31 @@ def _host_f32(a, n, name):
 class SurrogateModel:
     """Owns a dd_mlp handle (ensemble of MLPs on the current device)."""
 
-    def __init__(self, n_members=4, seed=0):
-        h = C.c_void_p()
-        _check(lib().dd_mlp_create(int(n_members), C.c_uint64(int(seed)), C.byref(h)))
-        self.handle = h
+    def __init__(self, n_members=4, seed=0, _handle=None):
+        if _handle is None:
+            h = C.c_void_p()
+            _check(lib().dd_mlp_create(int(n_members), C.c_uint64(int(seed)), C.byref(h)))
+            _handle = h
+        self.handle = _handle
         self.n_members = n_members
+
+    def save(self, path):
+        """Write the ensemble (parameters, Adam state, scaling) to `path`."""
+        _check(lib().dd_mlp_save(self.handle, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path):
+        """An ensemble read from a file written by save(), on the current device."""
+        h = C.c_void_p()
+        _check(lib().dd_mlp_load(os.fsencode(path), C.byref(h)))
+        m = C.c_int()
+        _check(lib().dd_mlp_info(h, C.byref(m), None))
+        return cls(m.value, _handle=h)
+
+    def adam_steps(self):
+        t = C.c_int64()
+        _check(lib().dd_mlp_info(self.handle, None, C.byref(t)))
+        return t.value
 
     def close(self):
         if self.handle:

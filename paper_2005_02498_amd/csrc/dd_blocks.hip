@@ -219,6 +219,7 @@ using namespace dd;
 
 extern "C" int dd_block_average(const dd_block_mesh *mesh, int c, const double *f_gp, double *f_block, void *stream)
 {
+    ::dd::Range range_("dd_block_average");
     clear_error();
     BlockGeom G;
     int rc;
@@ -234,6 +235,7 @@ extern "C" int dd_block_average(const dd_block_mesh *mesh, int c, const double *
 extern "C" int dd_block_to_gauss(const dd_block_mesh *mesh, int c, const double *f_block, double *f_gp,
                                  void *stream)
 {
+    ::dd::Range range_("dd_block_to_gauss");
     clear_error();
     BlockGeom G;
     int rc;
@@ -281,6 +283,7 @@ extern "C" int dd_block_to_gauss(const dd_block_mesh *mesh, int c, const double 
 extern "C" int dd_dissipation_fix(int64_t n_gp, const double *T, const double *alpha, double *Lp, double *V,
                                   void *stream)
 {
+    ::dd::Range range_("dd_dissipation_fix");
     clear_error();
     if (n_gp < 0) return set_error(DD_EINVAL, "n_gp must be >= 0");
     if (n_gp == 0) return DD_OK;

@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "dd.h"
 #include "dd_host.h"
 
@@ -17,6 +19,16 @@ namespace dd {
 int set_error(int code, const char *fmt, ...);
 void clear_error();
 bool validation_on();
+
+// Named roctx range over a host scope (rocprofv3 --marker-trace shows the
+// library's calls, graph captures and tuner passes on the timeline; without a
+// tool attached each range costs two library calls).
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 #define DD_HIP(call)                                                           \
     do {                                                                       \

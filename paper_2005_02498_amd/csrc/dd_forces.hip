@@ -1509,6 +1509,7 @@ int tuned_chunk(Workspace *ws, hipStream_t st, const std::vector<int64_t> &so, i
         *out = itk->second;
         return DD_OK;
     }
+    Range range_("dd autotune");
     // a choice is encoded as MIXED_VARIANTS * chunk_length + mixed-kernel variant
     std::vector<int64_t> chunks = {0};
     // short ranges spread small batches over more CUs; long ones need fewer partial sums
@@ -1663,6 +1664,7 @@ int launch_cached_graph(Workspace *ws, const KeyBuf &key, F &&record, hipStream_
             DD_HIP(hipGraphLaunch(g.exec, st));
             return DD_OK;
         }
+    Range range_("dd graph capture");
     if (!ws->capture_stream) DD_HIP(hipStreamCreateWithFlags(&ws->capture_stream, hipStreamNonBlocking));
     hipStream_t cs = ws->capture_stream;
     DD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -1829,6 +1831,7 @@ extern "C" int dd_nodal_forces(int64_t n_nodes, const double *x, int64_t n_segs,
                                const dd_material *m, int n_gauss, int precision,
                                double near_cutoff_a, double exact_eta, double *force_out, void *stream)
 {
+    ::dd::Range range_("dd_nodal_forces");
     clear_error();
     int rc;
     if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a, exact_eta))) return rc;
@@ -1871,6 +1874,7 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
                              const int32_t *seg_nodes, const double *normal, const uint8_t *pinned,
                              const dd_material *m, double dt, double *vel_out, void *stream)
 {
+    ::dd::Range range_("dd_glide_step");
     clear_error();
     int rc;
     if ((rc = common_checks(n_nodes, n_segs, 1, DD_FP64, 1.0))) return rc;
@@ -1934,6 +1938,7 @@ extern "C" int dd_step(int64_t n_nodes, double *x, int64_t n_segs, const int32_t
                        double near_cutoff_a, double exact_eta, double dt, double *force_out, double *vel_out,
                        void *stream)
 {
+    ::dd::Range range_("dd_step");
     clear_error();
     int rc;
     if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a, exact_eta))) return rc;
@@ -2160,6 +2165,7 @@ extern "C" int dd_burst_batch(int32_t n_inst, const int64_t *node_off, const int
                               double exact_eta, int n_steps, double dt, double *rate_avg_out,
                               double *features_out, void *stream)
 {
+    ::dd::Range range_("dd_burst_batch");
     clear_error();
     return burst_batch_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m,
                             n_gauss, precision, near_cutoff_a, exact_eta, n_steps, dt, nullptr, rate_avg_out,
@@ -2173,6 +2179,7 @@ extern "C" int dd_burst_batch_junctions(int32_t n_inst, const int64_t *node_off,
                                         double exact_eta, int n_steps, double dt, const dd_junctions *junctions,
                                         double *rate_avg_out, double *features_out, void *stream)
 {
+    ::dd::Range range_("dd_burst_batch_junctions");
     clear_error();
     if (!junctions) return set_error(DD_EINVAL, "null junction parameters");
     return burst_batch_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m,
@@ -2187,6 +2194,7 @@ extern "C" int dd_burst_batch_junction_nodes(int32_t n_inst, const int64_t *node
                                              int n_steps, double dt, const dd_junction_nodes *junctions,
                                              double *rate_avg_out, double *features_out, void *stream)
 {
+    ::dd::Range range_("dd_burst_batch_junction_nodes");
     clear_error();
     if (!junctions) return set_error(DD_EINVAL, "null junction-node parameters");
     return burst_batch_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m,
@@ -2276,6 +2284,7 @@ extern "C" int dd_nodal_forces_noalloc(int64_t n_nodes, const double *x, int64_t
                                        const double *sigma_app, const dd_material *m, int n_gauss,
                                        int precision, double near_cutoff_a, double *force_out, void *stream)
 {
+    ::dd::Range range_("dd_nodal_forces_noalloc");
     clear_error();
     int rc;
     if ((rc = common_checks(n_nodes, n_segs, n_gauss, precision, near_cutoff_a))) return rc;

@@ -10,7 +10,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "dd_common.h"
@@ -1193,6 +1195,152 @@ extern "C" int dd_mlp_get_params(const dd_mlp *h, int member, float *host_params
     return DD_OK;
 }
 
+// ---------------------------------------------------------- persistence --
+// File layout (host byte order, which is little-endian on every ROCm host):
+//   char   magic[8]           "DDMLP\0\0\1" (the last byte is the version)
+//   int32  members, in, hidden, out, params per member, scaling entries
+//   int64  Adam steps taken
+//   float  scaling[SCAL]      shifts, scales, dens_scale, dens_floor, spread floor
+//   float  w[members][P], m1[members][P], m2[members][P]
+//   uint64 FNV-1a hash of every byte before it
+namespace {
+
+constexpr char MAGIC[8] = {'D', 'D', 'M', 'L', 'P', 0, 0, 1};
+constexpr int HDR_INTS = 6;
+
+struct Fnv {
+    uint64_t h = 0xcbf29ce484222325ull;
+    void add(const void *p, size_t n)
+    {
+        const unsigned char *c = (const unsigned char *)p;
+        for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 0x100000001b3ull;
+    }
+};
+
+struct File {
+    FILE *f = nullptr;
+    ~File()
+    {
+        if (f) std::fclose(f);
+    }
+};
+
+bool put(FILE *f, Fnv &fnv, const void *p, size_t n)
+{
+    fnv.add(p, n);
+    return std::fwrite(p, 1, n, f) == n;
+}
+
+bool get(FILE *f, Fnv &fnv, void *p, size_t n)
+{
+    if (std::fread(p, 1, n, f) != n) return false;
+    fnv.add(p, n);
+    return true;
+}
+
+}  // namespace
+
+extern "C" int dd_mlp_save(const dd_mlp *h, const char *path)
+{
+    ::dd::Range range_("dd_mlp_save");
+    clear_error();
+    int rc;
+    if ((rc = check_model(h))) return rc;
+    if (!path || !*path) return set_error(DD_EINVAL, "null or empty path");
+    const int64_t MP = h->members * P;
+    std::vector<float> buf((size_t)(3 * MP));
+    DD_HIP(hipDeviceSynchronize());
+    DD_HIP(hipMemcpy(buf.data(), h->w, sizeof(float) * MP, hipMemcpyDeviceToHost));
+    DD_HIP(hipMemcpy(buf.data() + MP, h->m1, sizeof(float) * MP, hipMemcpyDeviceToHost));
+    DD_HIP(hipMemcpy(buf.data() + 2 * MP, h->m2, sizeof(float) * MP, hipMemcpyDeviceToHost));
+    // written to a temporary name and renamed, so that a reader never sees a
+    // partial file under `path`
+    const std::string tmp = std::string(path) + ".tmp";
+    File out;
+    if (!(out.f = std::fopen(tmp.c_str(), "wb"))) return set_error(DD_EIO, "cannot open %s for writing", tmp.c_str());
+    Fnv fnv;
+    const int32_t hdr[HDR_INTS] = {h->members, IN, HID, OUT, (int32_t)P, SCAL};
+    bool ok = put(out.f, fnv, MAGIC, sizeof MAGIC) && put(out.f, fnv, hdr, sizeof hdr) &&
+              put(out.f, fnv, &h->t, sizeof h->t) && put(out.f, fnv, h->h_scal, sizeof h->h_scal) &&
+              put(out.f, fnv, buf.data(), sizeof(float) * buf.size());
+    const uint64_t sum = fnv.h;
+    ok = ok && std::fwrite(&sum, 1, sizeof sum, out.f) == sizeof sum;
+    ok = (std::fclose(out.f) == 0) && ok;
+    out.f = nullptr;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return set_error(DD_EIO, "writing %s failed", path);
+    }
+    return DD_OK;
+}
+
+extern "C" int dd_mlp_load(const char *path, dd_mlp **out)
+{
+    ::dd::Range range_("dd_mlp_load");
+    clear_error();
+    if (!out) return set_error(DD_EINVAL, "null output handle pointer");
+    *out = nullptr;
+    if (!path || !*path) return set_error(DD_EINVAL, "null or empty path");
+    // the whole file is read and checked before any device call
+    File in;
+    if (!(in.f = std::fopen(path, "rb"))) return set_error(DD_EIO, "cannot open %s", path);
+    Fnv fnv;
+    char magic[8];
+    int32_t hdr[HDR_INTS];
+    int64_t t = 0;
+    float scal[SCAL];
+    if (!get(in.f, fnv, magic, sizeof magic) || std::memcmp(magic, MAGIC, sizeof magic) != 0)
+        return set_error(DD_EIO, "%s is not a surrogate file of this version", path);
+    if (!get(in.f, fnv, hdr, sizeof hdr)) return set_error(DD_EIO, "%s: truncated header", path);
+    if (hdr[0] < 1 || hdr[0] > 8 || hdr[1] != IN || hdr[2] != HID || hdr[3] != OUT || hdr[4] != (int32_t)P ||
+        hdr[5] != SCAL)
+        return set_error(DD_EIO, "%s: network shape (%d members, %d-%d-%d, %d parameters, %d scaling) does not "
+                                 "match this library's", path, hdr[0], hdr[1], hdr[2], hdr[3], hdr[4], hdr[5]);
+    const int64_t MP = (int64_t)hdr[0] * P;
+    std::vector<float> buf((size_t)(3 * MP));
+    if (!get(in.f, fnv, &t, sizeof t) || !get(in.f, fnv, scal, sizeof scal) ||
+        !get(in.f, fnv, buf.data(), sizeof(float) * buf.size()))
+        return set_error(DD_EIO, "%s: truncated", path);
+    uint64_t sum = 0;
+    char extra;
+    if (std::fread(&sum, 1, sizeof sum, in.f) != sizeof sum || sum != fnv.h)
+        return set_error(DD_EIO, "%s: checksum mismatch (corrupted or truncated)", path);
+    if (std::fread(&extra, 1, 1, in.f) != 0) return set_error(DD_EIO, "%s: trailing bytes", path);
+    if (t < 0) return set_error(DD_EIO, "%s: negative Adam step count", path);
+    for (float v : scal)
+        if (!std::isfinite(v)) return set_error(DD_EIO, "%s: non-finite scaling value", path);
+    for (float v : buf)
+        if (!std::isfinite(v)) return set_error(DD_EIO, "%s: non-finite parameter or moment", path);
+
+    dd_mlp *h = nullptr;
+    int rc = dd_mlp_create(hdr[0], 0, &h);
+    if (rc) return rc;
+    auto fail = [&](int code) {
+        dd_mlp_destroy(h);
+        return code;
+    };
+    if (hipMemcpy(h->w, buf.data(), sizeof(float) * MP, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->m1, buf.data() + MP, sizeof(float) * MP, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->m2, buf.data() + 2 * MP, sizeof(float) * MP, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->scal, scal, sizeof scal, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(set_error(DD_EHIP, "copying the loaded surrogate to the device failed"));
+    std::memcpy(h->h_scal, scal, sizeof scal);
+    h->t = t;
+    if ((rc = refresh(h, nullptr))) return fail(rc);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(set_error(DD_EHIP, "loading the surrogate failed"));
+    *out = h;
+    return DD_OK;
+}
+
+extern "C" int dd_mlp_info(const dd_mlp *h, int *n_members, int64_t *adam_steps)
+{
+    clear_error();
+    if (!h) return set_error(DD_EINVAL, "null surrogate handle");
+    if (n_members) *n_members = h->members;
+    if (adam_steps) *adam_steps = h->t;
+    return DD_OK;
+}
+
 extern "C" int dd_mlp_set_scaling(dd_mlp *h, const float *in_shift, const float *in_scale,
                                   const float *out_shift, const float *out_scale)
 {
@@ -1245,6 +1393,7 @@ extern "C" int dd_mlp_set_spread_floor(dd_mlp *h, float floor)
 extern "C" int dd_mlp_gradients(dd_mlp *h, int64_t n, const float *feat, const float *target,
                                 float *grad_out, float *loss_out, void *stream)
 {
+    ::dd::Range range_("dd_mlp_gradients");
     clear_error();
     int rc;
     if ((rc = train_checks(h, n, feat, target))) return rc;
@@ -1261,6 +1410,7 @@ extern "C" int dd_mlp_gradients(dd_mlp *h, int64_t n, const float *feat, const f
 extern "C" int dd_mlp_train_step(dd_mlp *h, int64_t n, const float *feat, const float *target, float lr,
                                  float *loss_out, void *stream)
 {
+    ::dd::Range range_("dd_mlp_train_step");
     clear_error();
     int rc;
     if ((rc = train_checks(h, n, feat, target))) return rc;
@@ -1281,6 +1431,7 @@ extern "C" int dd_mlp_train_step(dd_mlp *h, int64_t n, const float *feat, const 
 extern "C" int dd_surrogate_rates(const dd_mlp *hc, int64_t n, const float *feat, float *rates, float *spread,
                                   uint8_t *needs_dd, float spread_tol, void *stream)
 {
+    ::dd::Range range_("dd_surrogate_rates");
     clear_error();
     dd_mlp *h = const_cast<dd_mlp *>(hc);   // the handle's workspace grows; the model is unchanged
     int rc;

@@ -70,6 +70,7 @@ int probe(int reps, double *tflops, hipStream_t st)
 
 extern "C" int dd_vector_peak(int kind, int reps, double *tflops, void *stream)
 {
+    ::dd::Range range_("dd_vector_peak");
     dd::clear_error();
     if (!tflops) return dd::set_error(DD_EINVAL, "tflops is null");
     if (reps < 1 || reps > 1000) return dd::set_error(DD_EINVAL, "reps must be in 1..1000");

@@ -465,6 +465,7 @@ extern "C" int dd_pta_step(int32_t n_inst, const int64_t *node_off, const int64_
                            const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
                            int precision, double near_cutoff_a, double exact_eta, double *out, void *stream)
 {
+    ::dd::Range range_("dd_pta_step");
     clear_error();
     return pta_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, prm, m,
                     n_gauss, precision, near_cutoff_a, exact_eta, nullptr, nullptr, out, stream);
@@ -477,6 +478,7 @@ extern "C" int dd_pta_step_junctions(int32_t n_inst, const int64_t *node_off, co
                                      int precision, double near_cutoff_a, double exact_eta,
                                      const dd_junctions *junctions, int64_t *fast_steps, double *out, void *stream)
 {
+    ::dd::Range range_("dd_pta_step_junctions");
     clear_error();
     if (!junctions) return set_error(DD_EINVAL, "null junction parameters");
     return pta_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, prm, m,

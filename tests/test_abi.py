@@ -36,7 +36,8 @@ def test_binding_covers_header():
     assert sorted(dd.EXPORTS) == declared()
     for n in declared():
         if n in ("dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params",
-                 "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor"):
+                 "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor",
+                 "dd_mlp_save", "dd_mlp_load", "dd_mlp_info"):
             continue   # wrapped as SurrogateModel methods
         assert hasattr(dd, n), n
 
@@ -108,3 +109,58 @@ def test_host_only_calls_without_gpu():
                                                       ctypes.byref(m), 2, 0, 20.0, 1, 1.0, ctypes.byref(jn), fake,
                                                       None, None) == dd.DD_EINVAL, bad
         assert "junction nodes" in dd.dd_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdd.so not built")
+def test_surrogate_file_checks_without_gpu(tmp_path):
+    """dd_mlp_load checks the whole file before any device call: a missing
+    file, a wrong magic, a foreign shape, a truncated file, a flipped byte
+    and trailing bytes are each DD_EIO, and the handle stays NULL."""
+    import struct
+    import paper_2005_02498_amd as dd
+    P, SCAL = dd.MLP_PARAMS, 2 * dd.MLP_IN + 2 * dd.MLP_OUT + 3
+
+    def fnv(b):
+        h = 0xcbf29ce484222325
+        for c in b:
+            h = ((h ^ c) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+        return h
+
+    def body(members=1, shape=(36, 256, 12)):
+        b = b"DDMLP\0\0\x01" + struct.pack("<6i", members, *shape, P, SCAL) + struct.pack("<q", 3)
+        return b + struct.pack(f"<{SCAL}f", *([0.5] * SCAL)) + bytes(4 * 3 * members * P)
+
+    def load(path):
+        h = ctypes.c_void_p(1234)
+        rc = dd.lib().dd_mlp_load(os.fsencode(str(path)), ctypes.byref(h))
+        return rc, h.value
+
+    cases = {}
+    good = body()
+    cases["missing"] = None
+    cases["magic"] = b"XXMLP\0\0\x01" + good[8:]
+    cases["shape"] = body(shape=(36, 128, 12))
+    cases["truncated"] = good[:-100]
+    flipped = bytearray(good)
+    flipped[5000] ^= 1
+    cases["checksum"] = bytes(flipped) + struct.pack("<Q", fnv(good))
+    cases["trailing"] = good + struct.pack("<Q", fnv(good)) + b"\0"
+    for name, data in cases.items():
+        path = tmp_path / f"{name}.ddmlp"
+        if data is not None:
+            path.write_bytes(data)
+        rc, h = load(path)
+        assert rc == dd.DD_EIO and h is None, (name, rc, dd.lib().dd_last_error())
+    # a null output pointer or path is DD_EINVAL
+    assert dd.lib().dd_mlp_load(b"x", None) == dd.DD_EINVAL
+    h = ctypes.c_void_p()
+    assert dd.lib().dd_mlp_load(None, ctypes.byref(h)) == dd.DD_EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdd.so not built")
+def test_library_links_roctx():
+    """The host runtime's roctx ranges come from the rocprofiler-sdk roctx
+    library, which libdd.so records as a dependency."""
+    import subprocess
+    out = subprocess.run(["readelf", "-d", LIB], capture_output=True, text=True).stdout
+    assert "librocprofiler-sdk-roctx" in out

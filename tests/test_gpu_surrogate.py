@@ -240,3 +240,34 @@ def test_forward_parity_log_densities():
                                     tol=0.05, bf16=True, log_dens=dens)
     check_elementwise(r.cpu().numpy(), ro, "rates with log densities")
     assert nrel(r.cpu().numpy(), ro) < TOL
+
+
+def test_save_load_resumes_bit_for_bit(tmp_path):
+    """A saved and loaded ensemble infers bit for bit as the original, and
+    training resumes with the same Adam state: after one more step on the
+    same batch both hold identical parameters."""
+    mdl = dd.SurrogateModel(3, 21)
+    rng = np.random.default_rng(8)
+    mdl.set_scaling(rng.normal(size=36), rng.uniform(0.5, 2, 36), rng.normal(size=12), rng.uniform(0.5, 2, 12))
+    mdl.set_log_densities(1.5e19, 1e10)
+    mdl.set_spread_floor(0.3)
+    X = torch.tensor(rng.normal(size=(512, 36)).astype(np.float32), device=DEV)
+    Y = torch.tensor(rng.normal(size=(512, 12)).astype(np.float32), device=DEV)
+    for _ in range(3):
+        dd.dd_mlp_train_step(mdl, X, Y, 1e-3)
+    path = tmp_path / "ensemble.ddmlp"
+    mdl.save(path)
+    assert not (tmp_path / "ensemble.ddmlp.tmp").exists()
+    ld = dd.SurrogateModel.load(path)
+    assert ld.n_members == 3 and ld.adam_steps() == mdl.adam_steps() == 3
+    for m in range(3):
+        np.testing.assert_array_equal(ld.get_params(m), mdl.get_params(m))
+    feat = torch.tensor(rng.normal(size=(1000, 36)).astype(np.float32), device=DEV)
+    for a, b in zip(dd.dd_surrogate_rates(mdl, feat, 0.05), dd.dd_surrogate_rates(ld, feat, 0.05)):
+        np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+    la = dd.dd_mlp_train_step(mdl, X, Y, 1e-3)
+    lb = dd.dd_mlp_train_step(ld, X, Y, 1e-3)
+    np.testing.assert_array_equal(la.cpu().numpy(), lb.cpu().numpy())
+    for m in range(3):
+        np.testing.assert_array_equal(ld.get_params(m), mdl.get_params(m))
+    ld.close()
