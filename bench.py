@@ -585,6 +585,38 @@ def main():
                                     "seconds": t1 - t0, "pairs_per_s": bpairs / (t1 - t0),
                                     "junctions_formed": int(jstate["count"].sum().item()),
                                     "held_at_end": int((jstate["junction"] >= 0).sum().item())}
+        # the same bursts with junction nodes: 16 node and segment slots per
+        # volume, capture radius 10 b, maximum breaking time 50 steps, l_min
+        # 2 b; two calls of the burst length (the first records the graph, the
+        # second continues from its end state with the cached one)
+        K_SLOTS = 16
+        bj = W.pack([W.with_junction_slots(i, K_SLOTS) for i in insts])
+        dj = dict(x=torch.tensor(bj.x, device=dev), sn=torch.tensor(bj.seg_nodes, device=dev),
+                  b=torch.tensor(bj.burgers, device=dev), n=torch.tensor(bj.normal, device=dev),
+                  p=torch.tensor(bj.pinned, device=dev), s=torch.tensor(bj.sigma_app, device=dev),
+                  v=torch.tensor(bj.volume, device=dev))
+        jn_state = dd.junction_node_state(int(bj.node_off[-1]), int(bj.seg_off[-1]), bj.n_inst, dev)
+        jn_frac = torch.rand((bj.n_inst, 4), dtype=torch.float64, device=dev,
+                             generator=torch.Generator(device=dev).manual_seed(4))
+        t_jn = []
+        for c in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            dd.dd_burst_batch_junction_nodes(bj.node_off, bj.seg_off, dj["x"], dj["sn"], dj["b"], dj["n"], dj["p"],
+                                             dj["s"], dj["v"], mat, jn_state, jn_frac, 10.0, 50 * W.DT, 2.0,
+                                             K_SLOTS, t0=c * args.burst_steps * W.DT, n_gauss=2,
+                                             precision=dd.DD_MIXED, near_cutoff_a=20.0, n_steps=args.burst_steps,
+                                             dt=W.DT)
+            torch.cuda.synchronize()
+            t_jn.append(time.perf_counter() - t0)
+        bursts["with_junction_nodes"] = {
+            "slots_per_volume": K_SLOTS, "capture_radius_b": 10.0, "max_break_time_steps": 50, "min_length_b": 2.0,
+            "seconds": t_jn[1], "first_call_seconds": t_jn[0], "pairs_per_s": bpairs / t_jn[1],
+            "pairs_note": "pairs of the volumes' own segments (free slot segments are evaluated too, not counted)",
+            "junctions_formed": int(jn_state["count"].sum().item()),
+            "missed_for_want_of_a_slot": int(jn_state["missed"].sum().item()),
+            "held_at_end": int((jn_state["ses"] >= 0).sum().item()),
+            "finite": bool(torch.isfinite(dj["x"]).all().item())}
         if args.only == "burst":
             print(json.dumps(bursts))
             return

@@ -90,6 +90,7 @@ enum Slot {
     WS_SES,            //   sessile-segment flags, positions, indices
     WS_SES_X,          //   their end points and bounding spheres
     WS_JN_CAND,        // junction nodes: per-segment candidates and parameters
+    WS_T0,             // junction bursts: the call's start time (one double)
     WS_NSLOTS
 };
 

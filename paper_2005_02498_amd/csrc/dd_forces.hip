@@ -463,7 +463,9 @@ __device__ __forceinline__ double release_time(double t, double f, double a)
 }
 
 struct JunctionArgs {
-    double rc2, rf2, a, t;   // capture radius^2, (2 capture radius)^2, maximum breaking time, time
+    double rc2, rf2, a;      // capture radius^2, (2 capture radius)^2, maximum breaking time
+    double tk;               // this step's offset k dt from the call's start time
+    const double *t0;        // the call's start time (device, written before the step graph runs)
     double rc;               // capture radius
     int32_t K;
     const double *fractions;
@@ -570,7 +572,7 @@ __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, con
         return;
     }
     // time: the instance's fast clock (steps taken so far times dt), or the call's
-    const double t = fast_steps ? (double)(fast_steps[lo] + k) * dt : J.t;
+    const double t = fast_steps ? (double)(fast_steps[lo] + k) * dt : *J.t0 + J.tk;
     const int32_t js = J.junction[n];
     if (js >= 0) {
         if (t >= J.release[n]) {
@@ -716,7 +718,9 @@ __device__ __forceinline__ double seg_seg_closest(const double *p, const double 
 }
 
 struct JNodeArgs {
-    double rc, rc2, rf2, a, lmin, t;   // capture radius, its square, (2 r_c)^2, max breaking time, l_min, time
+    double rc, rc2, rf2, a, lmin;      // capture radius, its square, (2 r_c)^2, max breaking time, l_min
+    double tk;                         // this step's offset k dt from the call's start time
+    const double *t0;                  // the call's start time (device, written before the step graph runs)
     int32_t K, Kf;                     // slots per instance, fractions per instance
     const double *fractions;           // [n_inst][Kf]
     double *release;                   // [nn]
@@ -763,10 +767,11 @@ __global__ __launch_bounds__(256) void k_jn_release(Layout L, int32_t *__restric
     const int64_t s0 = L.seg_off[inst], n_s = L.seg_off[inst + 1] - s0, ns = L.ns;
     if (n_n < J.K + 2 || n_s < J.K) return;
     const int32_t d1 = (int32_t)(n_n - 2), d2 = (int32_t)(n_n - 1);
+    const double t = *J.t0 + J.tk;   // t0 + k dt, as the oracle forms it
     __shared__ int64_t s_in, s_out;
     for (int64_t jl = n_n - J.K - 2; jl < n_n - 2; ++jl) {
         const int64_t j = n0 + jl;
-        if (!(J.ses[j] >= 0 && J.t >= J.release[j])) continue;   // the same for every thread
+        if (!(J.ses[j] >= 0 && t >= J.release[j])) continue;   // the same for every thread
         if (tid == 0) {
             s_in = -1;
             s_out = -1;
@@ -915,7 +920,7 @@ __global__ __launch_bounds__(256) void k_jn_capture(Layout L, int32_t *__restric
                 for (int cc = 0; cc < 3; ++cc) J.point[cc * ns + s] = J.point[cc * ns + s2] = x[cc * nn + j];
                 const int32_t cn = J.count[inst];
                 const int32_t kf = ((cn % J.Kf) + J.Kf) % J.Kf;
-                J.release[j] = release_time(J.t, J.fractions[(int64_t)inst * J.Kf + kf], J.a);
+                J.release[j] = release_time(*J.t0 + J.tk, J.fractions[(int64_t)inst * J.Kf + kf], J.a);
                 J.ses[j] = k;
                 J.count[inst] = cn + 1;
             }
@@ -1342,12 +1347,13 @@ void launch_csr(const ForceCtx &C, const int32_t *seg_nodes, hipStream_t st)
                        C.csr_list);
 }
 
-// The topology kernels of one step at time t (releases, candidates,
-// captures) and the node -> segment lists they change.
-void launch_jnode_step(const ForceCtx &C, JNodeArgs J, double t, int n_inst, int32_t *seg_nodes, double *x,
+// The topology kernels of one step at time t0 + tk, t0 read from the device
+// (releases, candidates, captures), and the node -> segment lists they
+// change.
+void launch_jnode_step(const ForceCtx &C, JNodeArgs J, double tk, int n_inst, int32_t *seg_nodes, double *x,
                        double *burgers, double *normal, uint32_t *flags, hipStream_t st)
 {
-    J.t = t;
+    J.tk = tk;
     hipLaunchKernelGGL(k_jn_release, dim3(n_inst), dim3(256), 0, st, C.L, seg_nodes, (const double *)x, burgers,
                        normal, J, (const uint8_t *)nullptr, flags);
     hipLaunchKernelGGL(k_jn_candidates, dim3(grid_for(C.L.ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
@@ -1758,6 +1764,10 @@ int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, con
     uint8_t *held = nullptr;
     JunctionArgs J{};
     if (B.jn && (rc = junction_prepare(ws, C.L, B.seg_nodes, B.x, B.pinned, B.jn, J, &held, st))) return rc;
+    // (the PTA path times junctions by the per-instance fast clock; t0 is
+    // never read there, but points at valid memory all the same)
+    if ((rc = ensure(ws, WS_T0, sizeof(double), &p))) return rc;
+    J.t0 = (const double *)p;
     if ((rc = presize_near(C, ws, B.x, B.seg_nodes, st))) return rc;
     DD_HIP(hipGetLastError());
     KeyBuf key;
@@ -2074,10 +2084,14 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
     if ((rc = ensure(ws, WS_FORCE, sizeof(double) * 3 * std::max<int64_t>(nn, 1), &p))) return rc;
     double *F = (double *)p;
     uint8_t *held = nullptr;
+    if ((rc = ensure(ws, WS_T0, sizeof(double), &p))) return rc;
+    double *t0_dev = (double *)p;
     JunctionArgs J{};
     if (jn && (rc = junction_prepare(ws, C.L, seg_nodes, x, pinned, jn, J, &held, st))) return rc;
+    J.t0 = t0_dev;
     JNodeArgs JN{};
     if (jnodes && (rc = jnode_prepare(ws, C.L, seg_nodes, x, pinned, jnodes, JN, st))) return rc;
+    JN.t0 = t0_dev;
 
     launch_csr(C, seg_nodes, st);
     hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(12 * (int64_t)n_inst)), dim3(256), 0, st, rate_avg_out,
@@ -2115,17 +2129,30 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
         key.add(pinned).add(sigma_app).add(volume).add(*m).add(n_gauss).add(precision).add(near_cutoff_a);
         key.add(exact_eta).add(n_steps).add(dt).add(choice).add(rate_avg_out).add(jn != nullptr);
         key.add(C.near.pair_cap).add_workspace(ws);
-        if (jn) key.add(*jn);
+        // the start time is not part of the key: the step kernels read it from
+        // the device, where it is stored on the caller's stream before the
+        // graph is launched, so that consecutive calls share one graph
+        if (jn) {
+            dd_junctions kj = *jn;
+            kj.t0 = 0.0;
+            key.add(kj);
+        }
         key.add(jnodes != nullptr);
-        if (jnodes) key.add(*jnodes);
+        if (jnodes) {
+            dd_junction_nodes kj = *jnodes;
+            kj.t0 = 0.0;
+            key.add(kj);
+        }
+        if (jn || jnodes)
+            hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, t0_dev, (int64_t)1, jn ? jn->t0 : jnodes->t0);
         rc = launch_cached_graph(ws, key, [&](hipStream_t cs) -> int {
             for (int k = 0; k < n_steps; ++k) {
                 if (jnodes)   // (the public call passes these arrays as writable)
-                    launch_jnode_step(C, JN, jnodes->t0 + k * dt, n_inst, const_cast<int32_t *>(seg_nodes), x,
+                    launch_jnode_step(C, JN, k * dt, n_inst, const_cast<int32_t *>(seg_nodes), x,
                                       const_cast<double *>(burgers), const_cast<double *>(normal), ws->flags_dev,
                                       cs);
                 if (jn) {
-                    J.t = jn->t0 + k * dt;
+                    J.tk = k * dt;
                     hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
                                        seg_nodes, (const double *)x, pinned, J, n_inst, (const uint8_t *)nullptr,
                                        (const int64_t *)nullptr, dt, k, held);

@@ -128,8 +128,12 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                 const float ee = fmaf(e2, e2, fmaf(e1, e1, e0 * e0));
                 // outside the band and not nearly collinear (ym^2 > K^2 (rho^2 + 1)
                 // with rho^2 = ee - ym^2, see COLLINEAR_K2)
-                const bool quad = ee >= r[R32_BAND] && ym2 * ck21 <= fmaf(ck2, ee, ck2);
-                if (__all(quad)) {
+                // every active lane passes both tests: the two comparison masks
+                // against exec, in scalar registers (a ballot of their
+                // conjunction would select and re-compare per lane)
+                const uint64_t quad = __builtin_amdgcn_ballot_w64(ee >= r[R32_BAND]) &
+                                      __builtin_amdgcn_ballot_w64(ym2 * ck21 <= fmaf(ck2, ee, ck2));
+                if (quad == __builtin_amdgcn_read_exec()) {
                     ++n_quad_src;
                     if (QN == 2)
                         quad2_acc_f32(e0, e1, e2, ee, ym, r, fb0, fb1, fb2, fkr, fnu, three, f0, f1, f2, fk);
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
             const float y = fmaf(0.5f, Ls, ym);
             const float h0 = fmaf(-ym, r[R32_T], e0), h1 = fmaf(-ym, r[R32_T + 1], e1), h2 = fmaf(-ym, r[R32_T + 2], e2);
             const float hh = fmaf(h2, h2, fmaf(h1, h1, h0 * h0));
-            const float ya = y - fminf(fmaxf(y, 0.f), Ls);
+            const float ya = y - __builtin_amdgcn_fmed3f(y, 0.f, Ls);   // y clamped to [0, L]: one instruction
             // FP64: near pairs, and nearly collinear ones (rho carries an absolute
             // error of order |ym| eps32 in FP32)
             if (hh + ya * ya < cut2 || ym2 > fmaf(ck2, hh, ck2)) {
