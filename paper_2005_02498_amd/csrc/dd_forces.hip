@@ -477,9 +477,16 @@ struct JunctionArgs {
     // bounding spheres of each (midpoint, half length) and of JUNC_GROUP
     // consecutive entries
     const int32_t *pos, *ses_idx;
-    const double *ses_x, *ses_ssp, *ses_sph;
+    const double *ses_x, *ses_ssp, *ses_sph, *ses_sup;
 };
 constexpr int JUNC_GROUP = 8;
+constexpr int JUNC_SUPER = 8;   // groups per second-level sphere (64 list entries)
+
+// Bounding spheres of the compact sessile list (centre, radius each): per
+// entry, per JUNC_GROUP entries and per JUNC_SUPER groups.
+struct JunctionSpheres {
+    const double *ssp, *sph, *sup;
+};
 
 // Sessile segments (both nodes pinned): flags for the scan.
 __global__ void k_ses_flag(Layout L, const int32_t *__restrict__ seg_nodes, const uint8_t *__restrict__ pinned,
@@ -538,6 +545,86 @@ __global__ void k_ses_spheres(int64_t ns, const int32_t *__restrict__ pos, const
     o[0] = c0; o[1] = c1; o[2] = c2; o[3] = r;
 }
 
+// Bounding sphere of JUNC_SUPER consecutive group spheres (centre = the
+// first one's), so that the searches skip 64 list entries with one test.
+__global__ void k_ses_super(int64_t ns, const int32_t *__restrict__ pos, const double *__restrict__ sph,
+                            double *__restrict__ sup)
+{
+    const int64_t G = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t n_grp = (pos[ns] + JUNC_GROUP - 1) / JUNC_GROUP;
+    const int64_t g0 = G * JUNC_SUPER;
+    if (g0 >= n_grp) return;
+    const int64_t g1 = g0 + JUNC_SUPER < n_grp ? g0 + JUNC_SUPER : n_grp;
+    const double *f = sph + 4 * g0;
+    const double c0 = f[0], c1 = f[1], c2 = f[2];
+    double r = 0.0;
+    for (int64_t g = g0; g < g1; ++g) {
+        const double *e = sph + 4 * g;
+        const double m0 = e[0] - c0, m1 = e[1] - c1, m2 = e[2] - c2;
+        r = fmax(r, sqrt(m0 * m0 + m1 * m1 + m2 * m2) + e[3]);
+    }
+    double *o = sup + 4 * G;
+    o[0] = c0; o[1] = c1; o[2] = c2; o[3] = r;
+}
+
+// Search of the sessile list entries [q_lo, q_hi) in index order for the
+// first one that test(q) accepts, skipping second-level and group spheres
+// (centre c, radius r) with |m - c| >= r + reach (m: the searcher's centre).
+// Returns the entry or -1.  When every active lane of the wavefront searches
+// the same range, the bounds are taken wave-uniform, so that the sphere
+// loads are the same address across the wavefront (scalar loads, one per
+// wavefront instead of one per lane).
+template <class Test>
+__device__ __forceinline__ int64_t sessile_search(const JunctionSpheres &S, int64_t q_lo, int64_t q_hi,
+                                                  const double m[3], double reach, Test &&test)
+{
+    // sphere j of 8 consecutive ones starting at base (indices clamped to
+    // last, so that every load stays inside the list) tested at once: the
+    // loads are issued together, one wait for all eight
+    auto hits8 = [&](const double *sp, int64_t base, int64_t first, int64_t last) -> unsigned {
+        double c[8][4];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t i = base + j < last ? base + j : last;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) c[j][d] = sp[4 * i + d];
+        }
+        unsigned mask = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const double e0 = m[0] - c[j][0], e1 = m[1] - c[j][1], e2 = m[2] - c[j][2];
+            const double rr = (c[j][3] + reach) * (1.0 + 1e-9);
+            if (base + j >= first && base + j <= last && e0 * e0 + e1 * e1 + e2 * e2 < rr * rr) mask |= 1u << j;
+        }
+        return mask;
+    };
+    auto run = [&](const int64_t qa0, const int64_t qb0) -> int64_t {
+        if (qa0 >= qb0) return -1;
+        const int64_t g_lo = qa0 / JUNC_GROUP, g_hi = (qb0 + JUNC_GROUP - 1) / JUNC_GROUP;
+        const int64_t G_lo = g_lo / JUNC_SUPER, G_hi = (g_hi + JUNC_SUPER - 1) / JUNC_SUPER;
+        for (int64_t G0 = G_lo; G0 < G_hi; G0 += 8) {
+            for (unsigned mG = hits8(S.sup, G0, G_lo, G_hi - 1); mG; mG &= mG - 1) {
+                const int64_t G = G0 + __builtin_ctz(mG);
+                for (unsigned mg = hits8(S.sph, G * JUNC_SUPER, g_lo, g_hi - 1); mg; mg &= mg - 1) {
+                    const int64_t g = G * JUNC_SUPER + __builtin_ctz(mg);
+                    const int64_t qa = g * JUNC_GROUP > qa0 ? g * JUNC_GROUP : qa0;
+                    const int64_t qb = (g + 1) * JUNC_GROUP < qb0 ? (g + 1) * JUNC_GROUP : qb0;
+                    for (unsigned mq = hits8(S.ssp, g * JUNC_GROUP, qa, qb - 1); mq; mq &= mq - 1) {
+                        const int64_t q = g * JUNC_GROUP + __builtin_ctz(mq);
+                        if (test(q)) return q;
+                    }
+                }
+            }
+        }
+        return -1;
+    };
+    const int32_t lo0 = __builtin_amdgcn_readfirstlane((int32_t)q_lo);
+    const int32_t hi0 = __builtin_amdgcn_readfirstlane((int32_t)q_hi);
+    if (__builtin_amdgcn_ballot_w64(q_lo == lo0 && q_hi == hi0) == __builtin_amdgcn_read_exec())
+        return run(lo0, hi0);
+    return run(q_lo, q_hi);
+}
+
 // Junction checks at the start of a step (Sec. "Thermal activation", Eq. tb),
 // one thread per node: a held node is released once t reaches its release
 // time; a free mobile node forgets the segment it last broke from beyond
@@ -548,7 +635,7 @@ __global__ void k_ses_spheres(int64_t ns, const int32_t *__restrict__ pos, const
 // compact list; groups, and then segments, whose bounding sphere is out of
 // reach are skipped before the exact distance (a division) is formed, which
 // leaves the index order of the tests unchanged.
-__global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
+__global__ __launch_bounds__(256) void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
                             const uint8_t *__restrict__ pinned, JunctionArgs J, int n_inst,
                             const uint8_t *__restrict__ active, const int64_t *__restrict__ fast_steps, double dt,
                             int k, uint8_t *__restrict__ held)
@@ -599,32 +686,20 @@ __global__ void k_junctions(Layout L, const int32_t *__restrict__ seg_nodes, con
         ig = -1;
     }
     // the instance's sessile segments, in index order, sphere by sphere
-    const int64_t q_lo = J.pos[sb], q_hi = J.pos[se];
-    for (int64_t g = q_lo / JUNC_GROUP; g * JUNC_GROUP < q_hi; ++g) {
-        const double *c = J.ses_sph + 4 * g;
-        const double e0 = p[0] - c[0], e1 = p[1] - c[1], e2 = p[2] - c[2];
-        const double rr = (c[3] + J.rc) * (1.0 + 1e-9);
-        if (e0 * e0 + e1 * e1 + e2 * e2 >= rr * rr) continue;
-        const int64_t qa = g * JUNC_GROUP > q_lo ? g * JUNC_GROUP : q_lo;
-        const int64_t qb = (g + 1) * JUNC_GROUP < q_hi ? (g + 1) * JUNC_GROUP : q_hi;
-        for (int64_t q = qa; q < qb; ++q) {
-            const double *m = J.ses_ssp + 4 * q;
-            const double g0 = p[0] - m[0], g1 = p[1] - m[1], g2 = p[2] - m[2];
-            const double rs = (m[3] + J.rc) * (1.0 + 1e-9);
-            if (g0 * g0 + g1 * g1 + g2 * g2 >= rs * rs) continue;
-            const int64_t s = J.ses_idx[q];
-            if (s == ig) continue;
-            const double *e = J.ses_x + 6 * q;
-            if (point_segment_d2(p, e, e + 3) < J.rc2) {
-                const int32_t cn = J.count[n];
-                const int32_t kf = ((cn % J.K) + J.K) % J.K;
-                J.junction[n] = (int32_t)s;
-                J.release[n] = release_time(t, J.fractions[n * J.K + kf], J.a);
-                J.count[n] = cn + 1;
-                held[n] = 1;
-                return;
-            }
-        }
+    const JunctionSpheres S{J.ses_ssp, J.ses_sph, J.ses_sup};
+    const int64_t qf = sessile_search(S, J.pos[sb], J.pos[se], p, J.rc, [&](const int64_t q) {
+        if (J.ses_idx[q] == ig) return false;
+        const double *e = J.ses_x + 6 * q;
+        return point_segment_d2(p, e, e + 3) < J.rc2;
+    });
+    if (qf >= 0) {
+        const int32_t cn = J.count[n];
+        const int32_t kf = ((cn % J.K) + J.K) % J.K;
+        J.junction[n] = J.ses_idx[qf];
+        J.release[n] = release_time(t, J.fractions[n * J.K + kf], J.a);
+        J.count[n] = cn + 1;
+        held[n] = 1;
+        return;
     }
     held[n] = 0;
 }
@@ -652,23 +727,26 @@ int junction_prepare(Workspace *ws, const Layout &L, const int32_t *seg_nodes, c
     J.count = jn->count;
     J.release = jn->release;
     J.rc = jn->capture_radius;
-    if ((rc = ensure(ws, WS_SES, sizeof(int32_t) * (3 * ns + 1), &p))) return rc;
-    int32_t *flag = (int32_t *)p, *pos = flag + ns, *idx = pos + ns + 1;
-    if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (10 * ns + 4 * ((ns + JUNC_GROUP - 1) / JUNC_GROUP) + 4), &p)))
-        return rc;
-    double *sx = (double *)p, *ssp = sx + 6 * ns, *sph = ssp + 4 * ns;
+    if ((rc = ensure(ws, WS_SES, sizeof(int32_t) * (3 * ns + 1 + scan_scratch_len(ns)), &p))) return rc;
+    int32_t *flag = (int32_t *)p, *pos = flag + ns, *idx = pos + ns + 1, *scan_tmp = idx + ns;
+    const int64_t n_grp = (ns + JUNC_GROUP - 1) / JUNC_GROUP, n_sup = (n_grp + JUNC_SUPER - 1) / JUNC_SUPER;
+    if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (10 * ns + 4 * n_grp + 4 * n_sup + 8), &p))) return rc;
+    double *sx = (double *)p, *ssp = sx + 6 * ns, *sph = ssp + 4 * ns, *sup = sph + 4 * n_grp + 4;
     const unsigned gs = grid_for(ns, 256, INT32_MAX);
     hipLaunchKernelGGL(k_ses_flag, dim3(gs), dim3(256), 0, st, L, seg_nodes, pinned, flag);
-    hipLaunchKernelGGL((k_scan<int32_t>), dim3(1), dim3(1024), 0, st, (const int32_t *)flag, ns, pos);
+    launch_scan<int32_t>(flag, ns, pos, scan_tmp, st);
     hipLaunchKernelGGL(k_ses_compact, dim3(gs), dim3(256), 0, st, L, seg_nodes, x, (const int32_t *)flag,
                        (const int32_t *)pos, idx, sx, ssp);
-    hipLaunchKernelGGL(k_ses_spheres, dim3(grid_for((ns + JUNC_GROUP - 1) / JUNC_GROUP, 256, INT32_MAX)), dim3(256),
-                       0, st, ns, (const int32_t *)pos, (const double *)sx, sph);
+    hipLaunchKernelGGL(k_ses_spheres, dim3(grid_for(n_grp, 256, INT32_MAX)), dim3(256), 0, st, ns,
+                       (const int32_t *)pos, (const double *)sx, sph);
+    hipLaunchKernelGGL(k_ses_super, dim3(grid_for(n_sup, 256, INT32_MAX)), dim3(256), 0, st, ns,
+                       (const int32_t *)pos, (const double *)sph, sup);
     J.pos = pos;
     J.ses_idx = idx;
     J.ses_x = sx;
     J.ses_ssp = ssp;
     J.ses_sph = sph;
+    J.ses_sup = sup;
     return DD_OK;
 }
 
@@ -730,7 +808,7 @@ struct JNodeArgs {
     int32_t *count, *missed;           // [n_inst]
     const int32_t *flag;               // [ns] sessile
     const int32_t *pos, *ses_idx;      // the compact sessile list (as for JunctionArgs)
-    const double *ses_x, *ses_ssp, *ses_sph;
+    const double *ses_x, *ses_ssp, *ses_sph, *ses_sup;
     int32_t *cand;                     // [ns] sessile candidate of a segment, -1: none
     double *cand_u;                    // [ns] its parameter on the segment
 };
@@ -811,7 +889,7 @@ __global__ __launch_bounds__(256) void k_jn_release(Layout L, int32_t *__restric
 // Groups and segments whose bounding spheres are out of reach
 // (|m_s - m_k| >= h_s + h_k + r_c) are skipped, which leaves the order of the
 // exact tests unchanged.
-__global__ void k_jn_candidates(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
+__global__ __launch_bounds__(256) void k_jn_candidates(Layout L, const int32_t *__restrict__ seg_nodes, const double *__restrict__ x,
                                 JNodeArgs J, const uint8_t *__restrict__ active)
 {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -832,31 +910,18 @@ __global__ void k_jn_candidates(Layout L, const int32_t *__restrict__ seg_nodes,
         else
             return;
     }
-    double u;
-    const double m0 = 0.5 * (p[0] + p2[0]), m1 = 0.5 * (p[1] + p2[1]), m2 = 0.5 * (p[2] + p2[2]);
+    const double m[3] = {0.5 * (p[0] + p2[0]), 0.5 * (p[1] + p2[1]), 0.5 * (p[2] + p2[2])};
     const double t0 = p2[0] - p[0], t1 = p2[1] - p[1], t2 = p2[2] - p[2];
     const double hs = 0.5 * sqrt(t0 * t0 + t1 * t1 + t2 * t2);
-    const int64_t q_lo = J.pos[sb], q_hi = J.pos[se];
-    for (int64_t g = q_lo / JUNC_GROUP; g * JUNC_GROUP < q_hi; ++g) {
-        const double *c = J.ses_sph + 4 * g;
-        const double e0 = m0 - c[0], e1 = m1 - c[1], e2 = m2 - c[2];
-        const double rr = (c[3] + hs + J.rc) * (1.0 + 1e-9);
-        if (e0 * e0 + e1 * e1 + e2 * e2 >= rr * rr) continue;
-        const int64_t qa = g * JUNC_GROUP > q_lo ? g * JUNC_GROUP : q_lo;
-        const int64_t qb = (g + 1) * JUNC_GROUP < q_hi ? (g + 1) * JUNC_GROUP : q_hi;
-        for (int64_t q = qa; q < qb; ++q) {
-            const double *mk = J.ses_ssp + 4 * q;
-            const double f0 = m0 - mk[0], f1 = m1 - mk[1], f2 = m2 - mk[2];
-            const double rs = (mk[3] + hs + J.rc) * (1.0 + 1e-9);
-            if (f0 * f0 + f1 * f1 + f2 * f2 >= rs * rs) continue;
-            const int64_t k = J.ses_idx[q];
-            const double *e = J.ses_x + 6 * q;
-            if (seg_seg_closest(p, p2, e, e + 3, u) < J.rc2) {
-                J.cand[s] = (int32_t)k;
-                J.cand_u[s] = u;
-                return;
-            }
-        }
+    const JunctionSpheres S{J.ses_ssp, J.ses_sph, J.ses_sup};
+    double u = 0.0;
+    const int64_t qf = sessile_search(S, J.pos[sb], J.pos[se], m, hs + J.rc, [&](const int64_t q) {
+        const double *e = J.ses_x + 6 * q;
+        return seg_seg_closest(p, p2, e, e + 3, u) < J.rc2;
+    });
+    if (qf >= 0) {
+        J.cand[s] = J.ses_idx[qf];
+        J.cand_u[s] = u;
     }
 }
 
@@ -952,27 +1017,30 @@ int jnode_prepare(Workspace *ws, const Layout &L, const int32_t *seg_nodes, cons
     J.point = jn->point;
     J.count = jn->count;
     J.missed = jn->missed;
-    if ((rc = ensure(ws, WS_SES, sizeof(int32_t) * (3 * ns + 1), &p))) return rc;
-    int32_t *flag = (int32_t *)p, *pos = flag + ns, *idx = pos + ns + 1;
-    if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (10 * ns + 4 * ((ns + JUNC_GROUP - 1) / JUNC_GROUP) + 4), &p)))
-        return rc;
-    double *sx = (double *)p, *ssp = sx + 6 * ns, *sph = ssp + 4 * ns;
+    if ((rc = ensure(ws, WS_SES, sizeof(int32_t) * (3 * ns + 1 + scan_scratch_len(ns)), &p))) return rc;
+    int32_t *flag = (int32_t *)p, *pos = flag + ns, *idx = pos + ns + 1, *scan_tmp = idx + ns;
+    const int64_t n_grp = (ns + JUNC_GROUP - 1) / JUNC_GROUP, n_sup = (n_grp + JUNC_SUPER - 1) / JUNC_SUPER;
+    if ((rc = ensure(ws, WS_SES_X, sizeof(double) * (10 * ns + 4 * n_grp + 4 * n_sup + 8), &p))) return rc;
+    double *sx = (double *)p, *ssp = sx + 6 * ns, *sph = ssp + 4 * ns, *sup = sph + 4 * n_grp + 4;
     if ((rc = ensure(ws, WS_JN_CAND, (sizeof(int32_t) + sizeof(double)) * std::max<int64_t>(ns, 1), &p))) return rc;
     J.cand_u = (double *)p;
     J.cand = (int32_t *)(J.cand_u + std::max<int64_t>(ns, 1));
     const unsigned gs = grid_for(ns, 256, INT32_MAX);
     hipLaunchKernelGGL(k_jn_ses_flag, dim3(gs), dim3(256), 0, st, L, seg_nodes, pinned, J.K, flag);
-    hipLaunchKernelGGL((k_scan<int32_t>), dim3(1), dim3(1024), 0, st, (const int32_t *)flag, ns, pos);
+    launch_scan<int32_t>(flag, ns, pos, scan_tmp, st);
     hipLaunchKernelGGL(k_ses_compact, dim3(gs), dim3(256), 0, st, L, seg_nodes, x, (const int32_t *)flag,
                        (const int32_t *)pos, idx, sx, ssp);
-    hipLaunchKernelGGL(k_ses_spheres, dim3(grid_for((ns + JUNC_GROUP - 1) / JUNC_GROUP, 256, INT32_MAX)), dim3(256),
-                       0, st, ns, (const int32_t *)pos, (const double *)sx, sph);
+    hipLaunchKernelGGL(k_ses_spheres, dim3(grid_for(n_grp, 256, INT32_MAX)), dim3(256), 0, st, ns,
+                       (const int32_t *)pos, (const double *)sx, sph);
+    hipLaunchKernelGGL(k_ses_super, dim3(grid_for(n_sup, 256, INT32_MAX)), dim3(256), 0, st, ns,
+                       (const int32_t *)pos, (const double *)sph, sup);
     J.flag = flag;
     J.pos = pos;
     J.ses_idx = idx;
     J.ses_x = sx;
     J.ses_ssp = ssp;
     J.ses_sph = sph;
+    J.ses_sup = sup;
     return DD_OK;
 }
 
@@ -1142,6 +1210,7 @@ struct ForceCtx {
     double *partial = nullptr;
     double *segF = nullptr;
     int32_t *csr_ptr = nullptr, *csr_list = nullptr, *csr_cnt = nullptr;
+    int32_t *scan_tmp = nullptr;   // scratch of the node-list scan (after csr_cnt)
     Tile *tiles = nullptr;
     Item *items = nullptr;
     int64_t n_items = 0;
@@ -1207,8 +1276,10 @@ int setup(Workspace *ws, hipStream_t st, const std::vector<int64_t> &seg_off_h, 
     C.csr_ptr = (int32_t *)p;
     if ((rc = ensure(ws, WS_CSR_LIST, sizeof(int32_t) * std::max<int64_t>(2 * ns, 1), &p))) return rc;
     C.csr_list = (int32_t *)p;
-    if ((rc = ensure(ws, WS_CSR_CNT, sizeof(int32_t) * std::max<int64_t>(nn, 1), &p))) return rc;
+    if ((rc = ensure(ws, WS_CSR_CNT, sizeof(int32_t) * (std::max<int64_t>(nn, 1) + scan_scratch_len(nn)), &p)))
+        return rc;
     C.csr_cnt = (int32_t *)p;
+    C.scan_tmp = C.csr_cnt + std::max<int64_t>(nn, 1);
 
     // plan tables (cached by size)
     PlanKey key;
@@ -1339,8 +1410,7 @@ void launch_csr(const ForceCtx &C, const int32_t *seg_nodes, hipStream_t st)
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(nn)), dim3(256), 0, st, (unsigned *)C.csr_cnt, nn, 0u);
     hipLaunchKernelGGL(k_csr_count, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L, seg_nodes,
                        C.csr_cnt);
-    hipLaunchKernelGGL((k_scan<int32_t>), dim3(1), dim3(1024), 0, st, (const int32_t *)C.csr_cnt, nn,
-                       C.csr_ptr);
+    launch_scan<int32_t>(C.csr_cnt, nn, C.csr_ptr, C.scan_tmp, st);
     hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L, seg_nodes,
                        C.csr_ptr, C.csr_cnt, C.csr_list);
     hipLaunchKernelGGL(k_csr_sort, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, st, C.csr_ptr, nn,
@@ -1906,8 +1976,9 @@ extern "C" int dd_glide_step(int64_t n_nodes, double *x, const double *force, in
     C.csr_ptr = (int32_t *)p;
     if ((rc = ensure(ws, WS_CSR_LIST, sizeof(int32_t) * std::max<int64_t>(2 * n_segs, 1), &p))) return rc;
     C.csr_list = (int32_t *)p;
-    if ((rc = ensure(ws, WS_CSR_CNT, sizeof(int32_t) * n_nodes, &p))) return rc;
+    if ((rc = ensure(ws, WS_CSR_CNT, sizeof(int32_t) * (n_nodes + scan_scratch_len(n_nodes)), &p))) return rc;
     C.csr_cnt = (int32_t *)p;
+    C.scan_tmp = C.csr_cnt + n_nodes;
     double *vel = vel_out;
     if (!vel) {
         if ((rc = ensure(ws, WS_VEL, sizeof(double) * 3 * n_nodes, &p))) return rc;
@@ -2338,7 +2409,7 @@ extern "C" int dd_nodal_forces_noalloc(int64_t n_nodes, const double *x, int64_t
     sz.take<double>(6 * (size_t)std::max<int64_t>(n_segs, 1));    // end forces
     sz.take<int32_t>((size_t)n_nodes + 1);                          // node lists: offsets
     sz.take<int32_t>(2 * (size_t)std::max<int64_t>(n_segs, 1));   //   entries
-    sz.take<int32_t>((size_t)std::max<int64_t>(n_nodes, 1));      //   counters
+    sz.take<int32_t>((size_t)(std::max<int64_t>(n_nodes, 1) + scan_scratch_len(n_nodes)));   //   counters, scan
     sz.take<Tile>((size_t)std::max<int64_t>(n_tiles, 1));
     sz.take<Item>((size_t)std::max<int64_t>(n_items, 1));
     sz.take<double>(3 * (size_t)TILE * (size_t)std::max<int64_t>(n_items, 1));   // partial sums
@@ -2373,7 +2444,8 @@ extern "C" int dd_nodal_forces_noalloc(int64_t n_nodes, const double *x, int64_t
     C.segF = cv.take<double>(6 * (size_t)std::max<int64_t>(n_segs, 1));
     C.csr_ptr = cv.take<int32_t>((size_t)n_nodes + 1);
     C.csr_list = cv.take<int32_t>(2 * (size_t)std::max<int64_t>(n_segs, 1));
-    C.csr_cnt = cv.take<int32_t>((size_t)std::max<int64_t>(n_nodes, 1));
+    C.csr_cnt = cv.take<int32_t>((size_t)(std::max<int64_t>(n_nodes, 1) + scan_scratch_len(n_nodes)));
+    C.scan_tmp = C.csr_cnt + std::max<int64_t>(n_nodes, 1);
     C.tiles = cv.take<Tile>((size_t)std::max<int64_t>(n_tiles, 1));
     C.items = cv.take<Item>((size_t)std::max<int64_t>(n_items, 1));
     C.partial = cv.take<double>(3 * (size_t)TILE * (size_t)std::max<int64_t>(n_items, 1));
