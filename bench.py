@@ -512,25 +512,37 @@ def main():
             dd.dd_burst_batch(sb.node_off, sb.seg_off, xs, ds["sn"], ds["b"], ds["n"], ds["p"],
                               ds["s"], ds["v"], mat, 2, dd.DD_FP64, 20.0, 100, W.DT, rate_avg_out=rs)
 
-        dd.dd_shutdown()   # no cached graph: the first call below captures
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        small_call()
-        torch.cuda.synchronize()
-        t_first = time.perf_counter() - t0
-        reps = 20
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            small_call()
-        torch.cuda.synchronize()
-        t_small = (time.perf_counter() - t0) / reps
-        extras["small_volume_100_steps_fp64"] = {
-            "segments": 256, "steps": 100, "seconds_per_call": t_small,
-            "us_per_step": t_small / 100 * 1e6, "first_call_seconds": t_first,
-            "first_call_us_per_step": t_first / 100 * 1e6,
-            "note": "cached: the step graph captured by an earlier call with the same arguments is "
-                    "relaunched, calls enqueued back to back and synchronised once; first call: instance "
-                    "tables, work split, capture and instantiation of the 100 steps, launch"}
+        def small_timing(mode):
+            prev = dd.dd_set_burst_mode(mode)
+            try:
+                dd.dd_shutdown()   # nothing cached: the first call below builds tables (and captures)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                small_call()
+                torch.cuda.synchronize()
+                t_first = time.perf_counter() - t0
+                reps = 20
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    small_call()
+                torch.cuda.synchronize()
+                t_small = (time.perf_counter() - t0) / reps
+            finally:
+                dd.dd_set_burst_mode(prev)
+            return {"seconds_per_call": t_small, "us_per_step": t_small / 100 * 1e6,
+                    "first_call_seconds": t_first, "first_call_us_per_step": t_first / 100 * 1e6}
+
+        graph = small_timing(dd.BURST_GRAPH)
+        one_wg = small_timing(dd.BURST_PERSISTENT_ONE)
+        auto = small_timing(dd.BURST_AUTO)
+        extras["small_volume_100_steps_fp64"] = dict(
+            auto, segments=256, steps=100,
+            step_graph=dict(graph, note="the 100 steps as one cached graph of per-step kernels, relaunched; first "
+                                        "call: instance tables, work split, capture and instantiation"),
+            persistent_one_workgroup=dict(one_wg, note="all 100 steps in one persistent launch, one workgroup"),
+            persistent=dict(auto, workgroups=128, note="all 100 steps in one cooperative launch, 128 workgroups "
+                                                       "of 2 nodes each, one barrier per step (the default)"),
+            note="calls enqueued back to back and synchronised once")
         out["extras"] = extras
 
     if (not args.no_extras and args.only is None) or args.only == "burst":

@@ -120,6 +120,20 @@ int dd_shutdown(void);
  * setting. */
 int dd_set_autotune(int on);
 
+/* How dd_burst_batch runs its steps.  0 (default): batches of small FP64
+ * bursts (every instance at most 512 segments and 512 nodes; no exact band)
+ * run all their steps in one persistent launch, several co-resident
+ * workgroups per instance meeting at one barrier per step (about 2 nodes per
+ * workgroup, at most 128 per instance), when all of them fit on the device at
+ * once; other bursts replay a cached graph of per-step kernels.  1: always the step graph.  2: the persistent launch with one
+ * workgroup per instance (a reference point for the split).  The persistent
+ * launch's results do not depend on the split; they differ from the step
+ * graph's only in the order of floating-point sums.  Returns the previous
+ * mode, or DD_EINVAL for a mode other than 0, 1 and 2.  A persistent burst
+ * whose workgroups wait too long at a step barrier raises DD_EHIP (reported
+ * as the device-side checks are). */
+int dd_set_burst_mode(int mode);
+
 /* Report, and clear, the conditions the device-side checks raised since the
  * last report: synchronises `stream` (hipStream_t, may be null) and returns
  * DD_OK, or the error code and message of the first condition in the order

@@ -25,7 +25,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
-    "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_check", "dd_set_plan", "dd_last_plan",
+    "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_burst_mode", "dd_check", "dd_set_plan", "dd_last_plan",
     "dd_nodal_forces", "dd_nodal_forces_noalloc", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_burst_batch_junction_nodes", "dd_pta_step", "dd_pta_step_junctions",
     "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params", "dd_mlp_save", "dd_mlp_load", "dd_mlp_info",
@@ -106,6 +106,7 @@ def _declare(L):
         "dd_shutdown": (C.c_int, []),
         "dd_timing_enable": (C.c_int, [C.c_int]),
         "dd_set_autotune": (C.c_int, [C.c_int]),
+        "dd_set_burst_mode": (C.c_int, [C.c_int]),
         "dd_last_plan": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
         "dd_timing_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int]),
@@ -227,6 +228,18 @@ def dd_last_error() -> str:
 
 def dd_set_autotune(on: bool) -> bool:
     return bool(lib().dd_set_autotune(1 if on else 0))
+
+
+BURST_AUTO, BURST_GRAPH, BURST_PERSISTENT_ONE = 0, 1, 2
+
+
+def dd_set_burst_mode(mode: int) -> int:
+    """How dd_burst_batch runs its steps (dd.h): 0 automatic, 1 step graph,
+    2 persistent with one workgroup per instance.  Returns the previous mode."""
+    rc = lib().dd_set_burst_mode(int(mode))
+    if rc < 0:
+        _check(rc)
+    return rc
 
 
 def dd_check(stream=None):

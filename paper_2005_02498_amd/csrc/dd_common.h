@@ -46,6 +46,7 @@ enum : unsigned {
     FLAG_NONFINITE = 8u,
     FLAG_NEAR_FULL = 16u,     // a near-pair list or the pair store ran out of room
     FLAG_NEAR_PANELS = 32u,   // an exact-band integral needed more panels than allowed
+    FLAG_BARRIER = 64u,       // a persistent burst's barrier wait ran out of polls
 };
 
 // -------------------------------------------------------------- workspace --
@@ -91,6 +92,9 @@ enum Slot {
     WS_SES_X,          //   their end points and bounding spheres
     WS_JN_CAND,        // junction nodes: per-segment candidates and parameters
     WS_T0,             // junction bursts: the call's start time (one double)
+    WS_PB,             // persistent bursts: second position buffer, velocities, per-workgroup sums
+    WS_PB_INT,         //   workgroup tables
+    WS_PB_BAR,         //   barrier arrival words
     WS_NSLOTS
 };
 
@@ -117,6 +121,7 @@ struct Workspace {
     std::vector<GraphEntry> graphs;
     uint64_t graph_clock = 0;
     std::vector<int64_t> inst_key;   // offsets whose instance tables WS_SEG_INST / WS_INST_OFFS hold
+    std::vector<int32_t> pb_tab;     // the persistent-burst workgroup table WS_PB_INT holds
 };
 
 // Reports (and clears) the flags raised since the last report; synchronises st.

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "dd_common.h"
+#include "dd_pair64.h"
 #include "dd_scan.h"
 
 namespace dd {
@@ -118,6 +119,43 @@ struct PrepArgs {
 
 constexpr int PREP_BLOCK = 256;   // threads per workgroup of k_seg_prep
 
+// FP64 record of segment s with nodes g1 -> g2, in units of a: x1, the unit
+// tangent t, the length L, b and c = b x t (r[0..12]).  Returns L.
+__device__ __forceinline__ double seg_record(const double *x, int64_t nn, int64_t g1, int64_t g2,
+                                             const double *burgers, int64_t ns, int64_t s, double inv_a, double *r)
+{
+    double d[3];
+    for (int k = 0; k < 3; ++k) {
+        r[k] = x[k * nn + g1] * inv_a;
+        d[k] = x[k * nn + g2] * inv_a - r[k];
+        r[7 + k] = burgers[k * ns + s] * inv_a;
+    }
+    const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double iL = 1.0 / L;
+    for (int k = 0; k < 3; ++k) r[3 + k] = d[k] * iL;
+    r[6] = L;
+    r[10] = r[8] * r[5] - r[9] * r[4];
+    r[11] = r[9] * r[3] - r[7] * r[5];
+    r[12] = r[7] * r[4] - r[8] * r[3];
+    return L;
+}
+
+// Slip system of a segment (FCC table): the system whose plane normal and
+// slip direction match its normal and Burgers vector up to sign, or -1.
+__device__ __forceinline__ int seg_system(const double *b, const double *nv)
+{
+    int found = -1;
+    const double bl = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+    for (int al = 0; al < 12 && found < 0; ++al) {
+        double n[3], m[3];
+        fcc(al, n, m);
+        const double cn = fabs(n[0] * nv[0] + n[1] * nv[1] + n[2] * nv[2]);
+        const double cb = fabs(m[0] * b[0] + m[1] * b[1] + m[2] * b[2]);
+        if (cn > 1.0 - 1e-6 && bl > 0.0 && cb > (1.0 - 1e-6) * bl) found = al;
+    }
+    return found;
+}
+
 __global__ __launch_bounds__(PREP_BLOCK) void k_seg_prep(PrepArgs A)
 {
     __shared__ int64_t sh_g1[PREP_BLOCK], sh_g2[PREP_BLOCK];
@@ -142,19 +180,11 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_seg_prep(PrepArgs A)
     sh_chain[tid] = live && tid + 1 < PREP_BLOCK && sh_inst[tid + 1] == inst && sh_g1[tid + 1] == g2;
     __syncthreads();
     if (!live) return;
-    double x1[3], d[3], b[3], t[3], c[3];
-    for (int k = 0; k < 3; ++k) {
-        x1[k] = A.x[k * nn + g1] * A.inv_a;
-        d[k] = A.x[k * nn + g2] * A.inv_a - x1[k];
-        b[k] = A.burgers[k * ns + s] * A.inv_a;
-    }
-    double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double rr[13];
+    const double L = seg_record(A.x, nn, g1, g2, A.burgers, ns, s, A.inv_a, rr);
     if (!(L > 0.0) || !isfinite(L)) fl |= FLAG_ZERO_LENGTH;
-    double iL = 1.0 / L;
-    for (int k = 0; k < 3; ++k) t[k] = d[k] * iL;
-    c[0] = b[1] * t[2] - b[2] * t[1];
-    c[1] = b[2] * t[0] - b[0] * t[2];
-    c[2] = b[0] * t[1] - b[1] * t[0];
+    const double x1[3] = {rr[0], rr[1], rr[2]}, t[3] = {rr[3], rr[4], rr[5]};
+    const double b[3] = {rr[7], rr[8], rr[9]}, c[3] = {rr[10], rr[11], rr[12]};
     double nv[3] = {A.normal[s], A.normal[ns + s], A.normal[2 * ns + s]};
     double nl = nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2];
     if (!(fabs(nl - 1.0) <= 2e-6)) fl |= FLAG_BAD_NORMAL;
@@ -212,18 +242,7 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_seg_prep(PrepArgs A)
         q[R32_WC] = (float)(wc / wo);
         q[22] = 0.f; q[23] = 0.f;
     }
-    if (A.sys) {
-        int found = -1;
-        double bl = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
-        for (int al = 0; al < 12 && found < 0; ++al) {
-            double n[3], m[3];
-            fcc(al, n, m);
-            double cn = fabs(n[0] * nv[0] + n[1] * nv[1] + n[2] * nv[2]);
-            double cb = fabs(m[0] * b[0] + m[1] * b[1] + m[2] * b[2]);
-            if (cn > 1.0 - 1e-6 && bl > 0.0 && cb > (1.0 - 1e-6) * bl) found = al;
-        }
-        A.sys[s] = found;
-    }
+    if (A.sys) A.sys[s] = seg_system(b, nv);
     if (fl) atomicOr(A.flags, fl);
 }
 
@@ -360,6 +379,48 @@ __global__ void k_node_gather(const int32_t *__restrict__ ptr, const int32_t *__
 }
 
 // ---------------------------------------------- a5 + a6: glide and Euler --
+// Collects the distinct slip-plane normals (up to sign) of a node's
+// segments: the first three in nrm, their number in cnt.
+__device__ __forceinline__ void add_normal(double ns0, double ns1, double ns2, double (&nrm)[3][3], int &cnt)
+{
+    bool dup = false;
+    for (int c = 0; c < 3; ++c)
+        if (c < cnt && fabs(nrm[c][0] * ns0 + nrm[c][1] * ns1 + nrm[c][2] * ns2) > 1.0 - 1e-12) dup = true;
+    if (!dup) {
+        if (cnt < 3) {
+            nrm[cnt][0] = ns0; nrm[cnt][1] = ns1; nrm[cnt][2] = ns2;
+        }
+        ++cnt;
+    }
+}
+
+// Glide velocity v = P F / (B ell) of a free node with cnt distinct normals:
+// one normal -> its component removed; two -> projected on their
+// intersection line (cnt >= 3 and fixed nodes are handled by the caller).
+__device__ __forceinline__ void glide_velocity(double F0, double F1, double F2, double ell, double invB,
+                                               const double (&nrm)[3][3], int cnt, double &v0, double &v1,
+                                               double &v2)
+{
+    const double sc = invB / ell;
+    v0 = F0 * sc;
+    v1 = F1 * sc;
+    v2 = F2 * sc;
+    if (cnt == 1) {
+        const double vn = v0 * nrm[0][0] + v1 * nrm[0][1] + v2 * nrm[0][2];
+        v0 -= vn * nrm[0][0];
+        v1 -= vn * nrm[0][1];
+        v2 -= vn * nrm[0][2];
+    } else {
+        double l0 = nrm[0][1] * nrm[1][2] - nrm[0][2] * nrm[1][1];
+        double l1 = nrm[0][2] * nrm[1][0] - nrm[0][0] * nrm[1][2];
+        double l2 = nrm[0][0] * nrm[1][1] - nrm[0][1] * nrm[1][0];
+        const double il = 1.0 / sqrt(l0 * l0 + l1 * l1 + l2 * l2);
+        l0 *= il; l1 *= il; l2 *= il;
+        const double vl = v0 * l0 + v1 * l1 + v2 * l2;
+        v0 = vl * l0; v1 = vl * l1; v2 = vl * l2;
+    }
+}
+
 // Per node: ell = 1/2 sum L_s over attached segments, v = P F / (B ell), with
 // P from the distinct slip-plane normals among them.  FROM_REC: lengths from
 // the segment records (x unchanged since they were made), so the node can be
@@ -393,40 +454,11 @@ __global__ void k_glide(Layout L, const int32_t *__restrict__ ptr, const int32_t
             Ls = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
         }
         ell += 0.5 * Ls;
-        const double ns0 = normal[s], ns1 = normal[ns + s], ns2 = normal[2 * ns + s];
-        bool dup = false;
-        for (int c = 0; c < 3; ++c)
-            if (c < cnt && fabs(nrm[c][0] * ns0 + nrm[c][1] * ns1 + nrm[c][2] * ns2) > 1.0 - 1e-12)
-                dup = true;
-        if (!dup) {
-            if (cnt < 3) {
-                nrm[cnt][0] = ns0; nrm[cnt][1] = ns1; nrm[cnt][2] = ns2;
-            }
-            ++cnt;
-        }
+        add_normal(normal[s], normal[ns + s], normal[2 * ns + s], nrm, cnt);
     }
     double v0 = 0, v1 = 0, v2 = 0;
     const bool fixed = idle || (pinned && pinned[n]) || (held && held[n]) || !(ell > 0.0) || cnt == 0 || cnt >= 3;
-    if (!fixed) {
-        const double sc = invB / ell;
-        v0 = F[n] * sc;
-        v1 = F[nn + n] * sc;
-        v2 = F[2 * nn + n] * sc;
-        if (cnt == 1) {
-            const double vn = v0 * nrm[0][0] + v1 * nrm[0][1] + v2 * nrm[0][2];
-            v0 -= vn * nrm[0][0];
-            v1 -= vn * nrm[0][1];
-            v2 -= vn * nrm[0][2];
-        } else {
-            double l0 = nrm[0][1] * nrm[1][2] - nrm[0][2] * nrm[1][1];
-            double l1 = nrm[0][2] * nrm[1][0] - nrm[0][0] * nrm[1][2];
-            double l2 = nrm[0][0] * nrm[1][1] - nrm[0][1] * nrm[1][0];
-            const double il = 1.0 / sqrt(l0 * l0 + l1 * l1 + l2 * l2);
-            l0 *= il; l1 *= il; l2 *= il;
-            const double vl = v0 * l0 + v1 * l1 + v2 * l2;
-            v0 = vl * l0; v1 = vl * l1; v2 = vl * l2;
-        }
-    }
+    if (!fixed) glide_velocity(F[n], F[nn + n], F[2 * nn + n], ell, invB, nrm, cnt, v0, v1, v2);
     if (vel) {
         vel[n] = v0;
         vel[nn + n] = v1;
@@ -1057,6 +1089,21 @@ __global__ void k_euler(int64_t nn, double *x, const double *__restrict__ vel, d
 // features (resolved shear, mobile and sessile densities) written to
 // out[inst][36]; mode 2: gdot_alpha(k) and the line density of the segments
 // that belong to a slip system, added to out[inst][13].
+// Slip-rate contribution of a segment with unit tangent t, Burgers vector b
+// (units of a) and length Ls on its system (n, m): (b.m) Ls ((t x vbar).n) / V,
+// vbar the mean velocity of its nodes g1, g2.
+__device__ __forceinline__ double seg_rate(const double *t, const double *b, double Ls, const double *vel,
+                                           int64_t nn, int64_t g1, int64_t g2, const double *n, const double *m,
+                                           double a, double invV)
+{
+    const double vb0 = 0.5 * (vel[g1] + vel[g2]);
+    const double vb1 = 0.5 * (vel[nn + g1] + vel[nn + g2]);
+    const double vb2 = 0.5 * (vel[2 * nn + g1] + vel[2 * nn + g2]);
+    const double c0 = t[1] * vb2 - t[2] * vb1, c1 = t[2] * vb0 - t[0] * vb2, c2 = t[0] * vb1 - t[1] * vb0;
+    const double bm = (b[0] * m[0] + b[1] * m[1] + b[2] * m[2]) * a;
+    return bm * Ls * (c0 * n[0] + c1 * n[1] + c2 * n[2]) * invV;
+}
+
 __global__ __launch_bounds__(256) void k_instance_sums(Layout L, int mode,
                                                        const int32_t *__restrict__ seg_nodes,
                                                        const double *__restrict__ rec,
@@ -1085,13 +1132,9 @@ __global__ __launch_bounds__(256) void k_instance_sums(Layout L, int mode,
         if (mode == 0 || mode == 2) {
             int64_t g1, g2;
             seg_ends(L, seg_nodes, s, g1, g2);
-            const double t0 = rec[3 * ns + s], t1 = rec[4 * ns + s], t2 = rec[5 * ns + s];
-            const double vb0 = 0.5 * (vel[g1] + vel[g2]);
-            const double vb1 = 0.5 * (vel[nn + g1] + vel[nn + g2]);
-            const double vb2 = 0.5 * (vel[2 * nn + g1] + vel[2 * nn + g2]);
-            const double c0 = t1 * vb2 - t2 * vb1, c1 = t2 * vb0 - t0 * vb2, c2 = t0 * vb1 - t1 * vb0;
-            const double bm = (rec[7 * ns + s] * m[0] + rec[8 * ns + s] * m[1] + rec[9 * ns + s] * m[2]) * a;
-            const double val = bm * Ls * (c0 * n[0] + c1 * n[1] + c2 * n[2]) * invV;
+            const double t[3] = {rec[3 * ns + s], rec[4 * ns + s], rec[5 * ns + s]};
+            const double b[3] = {rec[7 * ns + s], rec[8 * ns + s], rec[9 * ns + s]};
+            const double val = seg_rate(t, b, Ls, vel, nn, g1, g2, n, m, a, invV);
             for (int k = 0; k < 12; ++k)
                 if (k == al) acc[k] += val;
         } else {
@@ -1145,6 +1188,280 @@ __global__ void k_scale_rates(double *acc, int64_t n, double inv_steps)
     if (i < n) acc[i] *= inv_steps;
 }
 
+// ------------------------------------------------ persistent small bursts --
+// Every step of a batch of small bursts (FP64, no junctions, no exact band)
+// in one launch: G_i co-resident workgroups per instance i (a cooperative
+// launch) that meet at one barrier per step.  Each workgroup rebuilds its
+// instance's segment records in LDS from the positions of the step; it owns
+// a contiguous range of the instance's nodes and evaluates, for every
+// segment incident to them (a segment whose nodes lie in two ranges is
+// evaluated by both owners), the stress at its Gauss points from every other
+// segment, summed over fixed chunks of PB_CHUNK sources in chunk order, then
+// the end forces, the nodal forces in node-list order and the glide step of
+// its nodes.  No sum depends on G_i, so the results do not depend on how the
+// instances are split.  Positions and velocities alternate between two
+// buffers from step to step.  The slip-rate sums of a step are formed after
+// the next barrier (every velocity is then written; the step's records are
+// still in LDS), per workgroup over the segments that start at its nodes, in
+// index order, and summed over the workgroups in order at the end.
+constexpr int PB_THREADS = 512;
+constexpr int PB_MAX_SEGS = 512;    // segments and nodes per instance
+constexpr int PB_CHUNK = 8;         // sources per partial sum
+constexpr int PB_ITEMS = 1024;      // (target point, chunk) partial sums held at once
+constexpr int PB_NODES_PER_WG = 2;  // nodes per workgroup aimed at
+constexpr int PB_MAX_G = 128;       // workgroups per instance at most
+constexpr uint64_t PB_WAIT_TICKS = 200000000ull;   // longest barrier wait: 2 s of the 100 MHz wall clock
+
+struct PBArgs {
+    Layout L;
+    const int32_t *seg_nodes;
+    const double *burgers, *normal;
+    const uint8_t *pinned;
+    const double *sigma_app;   // [n_inst][6]
+    const double *volume;      // [n_inst]
+    const int32_t *csr_ptr, *csr_list;
+    const int32_t *wg;         // [4][n_wg]: instance, rank in it, the instance's G, its first workgroup
+    int n_wg;
+    double *xa, *xb;           // positions: the caller's array and the second buffer [3][nn]
+    double *vel;               // [2][3][nn]
+    double *wpart;             // [n_wg][12]
+    unsigned *arrive;          // [n_wg][16] barrier arrival words (one per 64 bytes), zero at launch
+    unsigned *flags;
+    double *rate_out;          // [n_inst][12], added to
+    GaussRule g;
+    double kr, nu, k2, inv_a, a, inv_mu, fscale, invB, dt;
+    int n_steps;
+};
+
+// Barrier of the G workgroups of one instance (workgroups first ..
+// first + G - 1), the step-th since the launch: each workgroup publishes step
+// in its own arrival word (one per 64-byte line, after a release fence) and
+// waits, one thread per workgroup, until every word of the instance holds at
+// least step; then one acquire fence for the workgroup.  A wait longer than
+// PB_WAIT_TICKS raises FLAG_BARRIER and returns false (the caller then
+// leaves the kernel, and so, after their own wait, do the other workgroups).
+__device__ __forceinline__ bool pb_barrier(unsigned *arrive, int wg, int first, int G, unsigned step,
+                                           unsigned *flags)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_store(arrive + 16 * wg, step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int ok = 1;
+    if ((int)threadIdx.x < G) {
+        const unsigned *f = arrive + 16 * (first + (int)threadIdx.x);
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < step) {
+            if (wall_clock64() - t0 > PB_WAIT_TICKS) {
+                atomicOr(flags, FLAG_BARRIER);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    ok = __syncthreads_and(ok);
+    if (threadIdx.x == 0) __threadfence();
+    __syncthreads();
+    return ok != 0;
+}
+
+__global__ __launch_bounds__(PB_THREADS) void k_burst_persistent(PBArgs A)
+{
+    __shared__ double s_rec[PB_MAX_SEGS][16];   // x1, t, L, b, c (units of a)
+    __shared__ double s_part[PB_ITEMS][3];
+    __shared__ double s_segF[PB_MAX_SEGS][6];   // end forces of the listed segments
+    __shared__ double s_wacc[12];
+    __shared__ int32_t s_list[PB_MAX_SEGS];     // the workgroup's segments (instance-local), index order
+    __shared__ int16_t s_loc[PB_MAX_SEGS];      // segment -> list position, -1: not listed
+    __shared__ int8_t s_sys[PB_MAX_SEGS];
+    __shared__ uint8_t s_own[PB_MAX_SEGS];      // listed segment starts at an owned node
+    __shared__ int s_nl;
+    const int tid = threadIdx.x, wg = blockIdx.x;
+    const int inst = A.wg[wg], w = A.wg[A.n_wg + wg], G = A.wg[2 * A.n_wg + wg], first = A.wg[3 * A.n_wg + wg];
+    const Layout &L = A.L;
+    const int64_t nn = L.nn, ns = L.ns;
+    const int64_t n0 = L.node_off[inst], nn_i = L.node_off[inst + 1] - n0;
+    const int64_t s0 = L.seg_off[inst], ns_i = L.seg_off[inst + 1] - s0;
+    const int64_t o_lo = n0 + nn_i * w / G, o_hi = n0 + nn_i * (w + 1) / G;   // owned nodes
+    const double invV = 1.0 / A.volume[inst];
+    unsigned step_no = 0;   // barriers passed
+
+    // the list of segments incident to owned nodes, their slip systems
+    if (tid == 0) {
+        int nl = 0;
+        for (int64_t sl = 0; sl < ns_i; ++sl) {
+            int64_t g1, g2;
+            seg_ends(L, A.seg_nodes, s0 + sl, g1, g2);
+            const bool own1 = g1 >= o_lo && g1 < o_hi, own2 = g2 >= o_lo && g2 < o_hi;
+            s_loc[sl] = -1;
+            if (own1 || own2) {
+                s_loc[sl] = (int16_t)nl;
+                s_list[nl] = (int32_t)sl;
+                s_own[nl] = own1;
+                ++nl;
+            }
+        }
+        s_nl = nl;
+        for (int k = 0; k < 12; ++k) s_wacc[k] = 0.0;
+    }
+    for (int64_t sl = tid; sl < ns_i; sl += PB_THREADS) {
+        const int64_t sg = s0 + sl;
+        int64_t g1, g2;
+        unsigned fl = seg_ends(L, A.seg_nodes, sg, g1, g2) ? 0u : FLAG_BAD_INDEX;
+        const double b[3] = {A.burgers[sg], A.burgers[ns + sg], A.burgers[2 * ns + sg]};
+        const double nv[3] = {A.normal[sg], A.normal[ns + sg], A.normal[2 * ns + sg]};
+        if (!(fabs(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2] - 1.0) <= 2e-6)) fl |= FLAG_BAD_NORMAL;
+        s_sys[sl] = (int8_t)seg_system(b, nv);
+        if (fl) atomicOr(A.flags, fl);
+    }
+    __syncthreads();
+    const int nl = s_nl;
+    const int Q = A.g.n;
+    const int nch = (int)((ns_i + PB_CHUNK - 1) / PB_CHUNK);
+    const int per_batch = nch > 0 ? (PB_ITEMS / (Q * nch) > 0 ? PB_ITEMS / (Q * nch) : 1) : 1;
+    double S6[6];
+    for (int k = 0; k < 6; ++k) S6[k] = A.sigma_app[6 * inst + k] * A.inv_mu;
+
+    for (int k = 0; k <= A.n_steps; ++k) {
+        const double *xc = (k & 1) ? A.xb : A.xa;   // positions at the start of step k
+        if (k > 0) {
+            if (!pb_barrier(A.arrive, wg, first, G, ++step_no, A.flags)) return;
+            // slip-rate sums of step k - 1 (its records are still in LDS)
+            const double *vk = A.vel + (int64_t)((k - 1) & 1) * 3 * nn;
+            for (int l = tid; l < nl; l += PB_THREADS) {
+                s_part[l][0] = 0.0;
+                const int sl = s_list[l], al = s_sys[sl];
+                if (!s_own[l] || al < 0) continue;
+                int64_t g1, g2;
+                seg_ends(L, A.seg_nodes, s0 + sl, g1, g2);
+                double n[3], m[3];
+                fcc(al, n, m);
+                const double *r = s_rec[sl];
+                s_part[l][0] = seg_rate(r + 3, r + 7, r[6] * A.a, vk, nn, g1, g2, n, m, A.a, invV);
+            }
+            __syncthreads();
+            if (tid == 0)
+                for (int l = 0; l < nl; ++l) {
+                    const int al = s_sys[s_list[l]];
+                    if (s_own[l] && al >= 0) s_wacc[al] += s_part[l][0];
+                }
+            __syncthreads();
+        }
+        if (k == A.n_steps) break;
+        // records of step k
+        for (int64_t sl = tid; sl < ns_i; sl += PB_THREADS) {
+            int64_t g1, g2;
+            seg_ends(L, A.seg_nodes, s0 + sl, g1, g2);
+            const double Ls = seg_record(xc, nn, g1, g2, A.burgers, ns, s0 + sl, A.inv_a, s_rec[sl]);
+            if (!(Ls > 0.0) || !isfinite(Ls)) atomicOr(A.flags, FLAG_ZERO_LENGTH);
+        }
+        __syncthreads();
+        // Gauss-point stresses of the listed segments, in batches of whole segments
+        for (int l0 = 0; l0 < nl; l0 += per_batch) {
+            const int l1 = l0 + per_batch < nl ? l0 + per_batch : nl;
+            const int items = (l1 - l0) * Q * nch;
+            for (int it = tid; it < items; it += PB_THREADS) {
+                const int c = it % nch, tq = it / nch;
+                const int sj = s_list[l0 + tq / Q], q = tq % Q;
+                const double *rj = s_rec[sj];
+                double sq = A.g.s[0];
+                for (int i = 1; i < DD_MAX_GAUSS; ++i)
+                    if (i == q) sq = A.g.s[i];
+                const double xq0 = rj[0] + sq * rj[6] * rj[3];
+                const double xq1 = rj[1] + sq * rj[6] * rj[4];
+                const double xq2 = rj[2] + sq * rj[6] * rj[5];
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, ak = 0.0;
+                const int c1 = (c + 1) * PB_CHUNK < ns_i ? (c + 1) * PB_CHUNK : (int)ns_i;
+                for (int src = c * PB_CHUNK; src < c1; ++src) {
+                    if (src == sj) continue;
+                    const double *d = s_rec[src];
+                    const double R0 = xq0 - d[0], R1 = xq1 - d[1], R2 = xq2 - d[2];
+                    const double r1 = rsqrt64(fma(R2, R2, fma(R1, R1, fma(R0, R0, 1.0))));
+                    double r2, r2c;
+                    pair_acc_f64(xq0, xq1, xq2, rj[7], rj[8], rj[9], d[0], d[1], d[2], d[3], d[4], d[5], d[6],
+                                 d[7], d[8], d[9], d[10], d[11], d[12], A.kr, A.nu, r1, r1 * r1 * r1, r2, r2c, a0,
+                                 a1, a2, ak);
+                }
+                s_part[it][0] = A.k2 * fma(ak, rj[7], a0);
+                s_part[it][1] = A.k2 * fma(ak, rj[8], a1);
+                s_part[it][2] = A.k2 * fma(ak, rj[9], a2);
+            }
+            __syncthreads();
+            // end forces: per listed segment, Gauss points in order, chunks in order
+            for (int l = l0 + tid; l < l1; l += PB_THREADS) {
+                const double *rj = s_rec[s_list[l]];
+                const double t0 = rj[3], t1 = rj[4], t2 = rj[5], Ls = rj[6];
+                const double b0 = rj[7], b1 = rj[8], b2 = rj[9];
+                const double ab0 = S6[0] * b0 + S6[5] * b1 + S6[4] * b2;
+                const double ab1 = S6[5] * b0 + S6[1] * b1 + S6[3] * b2;
+                const double ab2 = S6[4] * b0 + S6[3] * b1 + S6[2] * b2;
+                double F1[3] = {0, 0, 0}, F2[3] = {0, 0, 0};
+                for (int q = 0; q < Q; ++q) {
+                    const int base = ((l - l0) * Q + q) * nch;
+                    double sa = 0, sb = 0, sc = 0;
+                    for (int c = 0; c < nch; ++c) {
+                        sa += s_part[base + c][0];
+                        sb += s_part[base + c][1];
+                        sc += s_part[base + c][2];
+                    }
+                    sa += ab0;
+                    sb += ab1;
+                    sc += ab2;
+                    const double f0 = sb * t2 - sc * t1, f1 = sc * t0 - sa * t2, f2 = sa * t1 - sb * t0;
+                    const double w1 = Ls * A.g.w[q] * (1.0 - A.g.s[q]), w2 = Ls * A.g.w[q] * A.g.s[q];
+                    F1[0] += w1 * f0; F1[1] += w1 * f1; F1[2] += w1 * f2;
+                    F2[0] += w2 * f0; F2[1] += w2 * f1; F2[2] += w2 * f2;
+                }
+                for (int c = 0; c < 3; ++c) {
+                    s_segF[l][c] = F1[c] * A.fscale;
+                    s_segF[l][3 + c] = F2[c] * A.fscale;
+                }
+            }
+            __syncthreads();
+        }
+        // owned nodes: nodal force in node-list order, glide step into the other buffers
+        double *xn = (k & 1) ? A.xa : A.xb;
+        double *vn = A.vel + (int64_t)(k & 1) * 3 * nn;
+        for (int64_t n = o_lo + tid; n < o_hi; n += PB_THREADS) {
+            double F0 = 0, F1 = 0, F2 = 0, ell = 0.0, nrm[3][3];
+            int cnt = 0;
+            for (int32_t e = A.csr_ptr[n]; e < A.csr_ptr[n + 1]; ++e) {
+                const int32_t v = A.csr_list[e];
+                const int64_t sg = v >> 1;
+                const int end = v & 1, l = s_loc[sg - s0];
+                F0 += s_segF[l][3 * end];
+                F1 += s_segF[l][3 * end + 1];
+                F2 += s_segF[l][3 * end + 2];
+                ell += 0.5 * (s_rec[sg - s0][6] * A.a);
+                add_normal(A.normal[sg], A.normal[ns + sg], A.normal[2 * ns + sg], nrm, cnt);
+            }
+            double v0 = 0, v1 = 0, v2 = 0;
+            const bool fixed = (A.pinned && A.pinned[n]) || !(ell > 0.0) || cnt == 0 || cnt >= 3;
+            if (!fixed) glide_velocity(F0, F1, F2, ell, A.invB, nrm, cnt, v0, v1, v2);
+            vn[n] = v0;
+            vn[nn + n] = v1;
+            vn[2 * nn + n] = v2;
+            xn[n] = xc[n] + v0 * A.dt;
+            xn[nn + n] = xc[nn + n] + v1 * A.dt;
+            xn[2 * nn + n] = xc[2 * nn + n] + v2 * A.dt;
+        }
+    }
+    // an odd number of steps leaves the positions in the second buffer: owned
+    // nodes back to the caller's array (every read of it ended at the last barrier)
+    if (A.n_steps & 1)
+        for (int64_t n = o_lo + tid; n < o_hi; n += PB_THREADS)
+            for (int c = 0; c < 3; ++c) A.xa[c * nn + n] = A.xb[c * nn + n];
+    if (tid < 12) A.wpart[12 * (int64_t)wg + tid] = s_wacc[tid];
+    if (!pb_barrier(A.arrive, wg, first, G, ++step_no, A.flags)) return;
+    if (w == 0 && tid < 12) {
+        double sum = 0.0;
+        for (int v = 0; v < G; ++v) sum += A.wpart[12 * (int64_t)(first + v) + tid];
+        A.rate_out[12 * (int64_t)inst + tid] += sum;
+    }
+}
+
 // =================================================================== host ==
 namespace {
 
@@ -1182,6 +1499,8 @@ int read_flags(Workspace *ws, hipStream_t st)
         return set_error(DD_ECAPACITY, "exact band: the near pairs of a captured step outgrew the pair store "
                          "sized at the start of the burst%s", w);
     if (f & FLAG_NEAR_PANELS) return set_error(DD_EINVAL, "exact band: a pair integral did not converge%s", w);
+    if (f & FLAG_BARRIER)
+        return set_error(DD_EHIP, "persistent burst: a workgroup waited too long at a step barrier%s", w);
     return DD_OK;
 }
 
@@ -1506,6 +1825,7 @@ int launch_forces(ForceCtx &C, Workspace *ws, const double *x, const int32_t *se
 // caller's own data, and the fastest is kept for the process (and appended
 // to the file named by DD_AUTOTUNE_CACHE, read back at start-up).
 std::atomic<int> g_autotune{1};
+std::atomic<int> g_burst_mode{0};   // dd_set_burst_mode: 0 automatic, 1 step graphs, 2 persistent, one workgroup each
 std::atomic<int64_t> g_forced_choice{-1};   // dd_set_plan: encoded split, or -1
 
 struct TuneKey {
@@ -1874,6 +2194,13 @@ using namespace dd;
 
 extern "C" int dd_set_autotune(int on) { return dd::g_autotune.exchange(on ? 1 : 0); }
 
+extern "C" int dd_set_burst_mode(int mode)
+{
+    clear_error();
+    if (mode < 0 || mode > 2) return set_error(DD_EINVAL, "burst mode must be 0, 1 or 2");
+    return dd::g_burst_mode.exchange(mode);
+}
+
 extern "C" int dd_check(void *stream)
 {
     clear_error();
@@ -2077,6 +2404,107 @@ extern "C" int dd_step(int64_t n_nodes, double *x, int64_t n_segs, const int32_t
 
 namespace dd {
 namespace {
+// The persistent kernel for a batch of small FP64 bursts, when every
+// instance fits (at most PB_MAX_SEGS segments and nodes) and all the
+// workgroups fit on the device at once; *used = false leaves the call to the
+// step graph.  G_i: about PB_NODES_PER_WG nodes per workgroup, at most
+// PB_MAX_G; one workgroup per instance in burst mode 2.  The node lists must
+// be built.
+int launch_persistent(const ForceCtx &C, Workspace *ws, const std::vector<int64_t> &no,
+                      const std::vector<int64_t> &so, double *x, const int32_t *seg_nodes, const double *burgers,
+                      const double *normal, const uint8_t *pinned, const double *sigma_app, const double *volume,
+                      const dd_material *m, int n_steps, double dt, double *rate_avg_out, hipStream_t st,
+                      bool *used)
+{
+    *used = false;
+    const int mode = g_burst_mode.load();
+    if (mode == 1) return DD_OK;
+    const int n_inst = (int)no.size() - 1;
+    for (int i = 0; i < n_inst; ++i)
+        if (no[i + 1] - no[i] > PB_MAX_SEGS || so[i + 1] - so[i] > PB_MAX_SEGS) return DD_OK;
+    int per_cu = 0, cus = 0;
+    DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_burst_persistent, PB_THREADS, 0));
+    DD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ws->device));
+    const int64_t cap = (int64_t)per_cu * cus;
+    if (n_inst > cap) return DD_OK;
+    std::vector<int> G(n_inst);
+    int64_t total = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        const int64_t want = (no[i + 1] - no[i] + PB_NODES_PER_WG - 1) / PB_NODES_PER_WG;
+        G[i] = mode == 2 ? 1 : (int)std::max<int64_t>(1, std::min<int64_t>(want, PB_MAX_G));
+        total += G[i];
+    }
+    // with fewer workgroups each would carry more nodes, and the step graph is
+    // then the faster of the two (measured): only a batch that fits as split
+    if (total > cap) return DD_OK;
+    const int n_wg = (int)total;
+    std::vector<int32_t> tab(4 * (size_t)n_wg);
+    for (int i = 0, k = 0; i < n_inst; ++i) {
+        const int first = k;
+        for (int w = 0; w < G[i]; ++w, ++k) {
+            tab[k] = i;
+            tab[n_wg + k] = w;
+            tab[2 * n_wg + k] = G[i];
+            tab[3 * n_wg + k] = first;
+        }
+    }
+    const int64_t nn = no.back();
+    void *p;
+    int rc;
+    if ((rc = ensure(ws, WS_PB, sizeof(double) * (9 * (size_t)std::max<int64_t>(nn, 1) + 12 * (size_t)n_wg), &p)))
+        return rc;
+    double *xb = (double *)p, *vel2 = xb + 3 * std::max<int64_t>(nn, 1), *wpart = vel2 + 6 * std::max<int64_t>(nn, 1);
+    int32_t *wgtab = (int32_t *)ws->ptr[WS_PB_INT];
+    if (tab != ws->pb_tab || !wgtab) {   // uploaded (one synchronisation) only when the table changes
+        if ((rc = upload(ws, WS_PB_INT, tab, &wgtab, st))) return rc;
+        ws->pb_tab = tab;
+    }
+    // barrier arrival words, zeroed on the stream
+    void *pb;
+    if ((rc = ensure(ws, WS_PB_BAR, sizeof(unsigned) * 16 * (size_t)n_wg, &pb))) return rc;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(16 * (int64_t)n_wg)), dim3(256), 0, st, (unsigned *)pb,
+                       16 * (int64_t)n_wg, 0u);
+    PBArgs A{};
+    A.L = C.L;
+    A.seg_nodes = seg_nodes;
+    A.burgers = burgers;
+    A.normal = normal;
+    A.pinned = pinned;
+    A.sigma_app = sigma_app;
+    A.volume = volume;
+    A.csr_ptr = C.csr_ptr;
+    A.csr_list = C.csr_list;
+    A.wg = wgtab;
+    A.n_wg = n_wg;
+    A.xa = x;
+    A.xb = xb;
+    A.vel = vel2;
+    A.wpart = wpart;
+    A.arrive = (unsigned *)pb;
+    A.flags = ws->flags_dev;
+    A.rate_out = rate_avg_out;
+    A.g = C.g;
+    A.kr = C.k1 / C.k2;
+    A.nu = 1.0 - 2.0 * A.kr;
+    A.k2 = C.k2;
+    A.inv_a = C.inv_a;
+    A.a = C.a;
+    A.inv_mu = C.inv_mu;
+    A.fscale = C.fscale;
+    A.invB = 1.0 / m->B;
+    A.dt = dt;
+    A.n_steps = n_steps;
+    void *args[] = {&A};
+    const hipError_t e = hipLaunchCooperativeKernel((const void *)k_burst_persistent, dim3((unsigned)n_wg),
+                                                    dim3(PB_THREADS), args, 0, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();   // not launched: the step graph runs instead
+        return DD_OK;
+    }
+    *used = true;
+    return DD_OK;
+}
+
 int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
                      const int32_t *seg_nodes, const double *burgers, const double *normal, const uint8_t *pinned,
                      const double *sigma_app, const double *volume, const dd_material *m, int n_gauss, int precision,
@@ -2192,7 +2620,16 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
     }
     DD_HIP(hipGetLastError());
 
-    if (n_steps > 0 && ns > 0) {
+    // small FP64 bursts: every step in one persistent launch, when it fits
+    bool persistent = false;
+    if (n_steps > 0 && ns > 0 && !jn && !jnodes && exact_eta == 0.0 && precision == DD_FP64 &&
+        (rc = launch_persistent(C, ws, no, so, x, seg_nodes, burgers, normal, pinned, sigma_app, volume, m, n_steps,
+                                dt, rate_avg_out, st, &persistent)))
+        return rc;
+    if (persistent) {
+        hipLaunchKernelGGL(k_scale_rates, dim3(grid_for(12 * (int64_t)n_inst, 256, INT32_MAX)), dim3(256), 0,
+                           st, rate_avg_out, 12 * (int64_t)n_inst, 1.0 / n_steps);
+    } else if (n_steps > 0 && ns > 0) {
         if ((rc = presize_near(C, ws, x, seg_nodes, st))) return rc;
         // the whole step loop as one graph, cached for calls with the same key
         KeyBuf key;

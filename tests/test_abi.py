@@ -53,6 +53,9 @@ def test_host_only_calls_without_gpu():
         with pytest.raises(dd.DDError):
             dd.dd_set_plan(*bad)
     dd.dd_set_plan(-1)
+    assert dd.dd_set_burst_mode(1) == 0 and dd.dd_set_burst_mode(0) == 1
+    with pytest.raises(dd.DDError):
+        dd.dd_set_burst_mode(3)
     # block-coupling argument checks happen before any device work
     fake = ctypes.c_void_p(256)
     for bad in ((0, 1, 1.0, 1.0), (1, 0, 1.0, 1.0), (1, 1, 0.0, 1.0), (1, 1, 1.0, float("nan")),

@@ -196,3 +196,54 @@ def test_async_two_calls_one_sync():
     np.testing.assert_array_equal(rate.cpu().numpy(), out[1])
     np.testing.assert_array_equal(d["x"].cpu().numpy(), ref["x"].cpu().numpy())
     dd.dd_check()
+
+
+def _in_mode(mode, fn):
+    prev = dd.dd_set_burst_mode(mode)
+    try:
+        return fn()
+    finally:
+        dd.dd_set_burst_mode(prev)
+
+
+def test_persistent_config0_against_graph_and_oracle():
+    """The 256-segment volume, 100 FP64 steps: the persistent launch (128
+    workgroups, and one workgroup) against the step graph and the oracle.
+    The split does not change the positions (bit for bit); the slip rates
+    differ between splits only in the order of the workgroups' sums."""
+    inst = W.config0()
+    bt = W.pack([inst])
+    xa, ra, fa = _in_mode(dd.BURST_AUTO, lambda: _gpu_burst(bt, 100))
+    x1, r1, _ = _in_mode(dd.BURST_PERSISTENT_ONE, lambda: _gpu_burst(bt, 100, features=False))
+    xg, rg, fg = _in_mode(dd.BURST_GRAPH, lambda: _gpu_burst(bt, 100))
+    xo, ro, fo = O.burst(inst, W.material(), 2, 100, W.DT)
+    np.testing.assert_array_equal(xa, x1)
+    np.testing.assert_allclose(ra, r1, rtol=1e-13, atol=1e-13 * np.abs(ra).max())
+    e_graph = normwise(xa - inst.x, xg - inst.x)
+    e_disp = normwise(xa - inst.x, xo - inst.x)
+    e_rate = np.abs(ra[0] - ro).max() / np.abs(ro).max()
+    print(f"persistent config0: vs graph {e_graph:.2e}, vs oracle displacement {e_disp:.2e}, rate {e_rate:.2e}")
+    assert e_graph < 1e-12
+    assert e_disp < 1e-9 and e_rate < 1e-9
+    np.testing.assert_array_equal(fa, fg)
+
+
+@pytest.mark.parametrize("Q", [1, 4])
+def test_persistent_batch_against_oracle(Q):
+    """A batch with an empty instance, instances of 1 to 4 loops with mobile
+    and pinned loops, an odd number of steps (the positions end in the second
+    buffer), Q = 1 and 4: against the oracle, and the same positions with one
+    workgroup per instance."""
+    insts = [W.subset(W.burst_instance(1_000_030 + i), nl) for i, nl in enumerate((2, 1, 4, 3))]
+    insts[2].pinned[:] = 0
+    insts[2].pinned[64:] = 1
+    e = W.Instance(np.zeros((3, 0)), np.zeros((2, 0), np.int32), np.zeros((3, 0)), np.zeros((3, 0)),
+                   np.zeros(0, np.uint8), np.zeros(6), 1.0)
+    bt = W.pack(insts[:2] + [e] + insts[2:])
+    xa, ra, _ = _in_mode(dd.BURST_AUTO, lambda: _gpu_burst(bt, 7, Q=Q, features=False))
+    x1, _, _ = _in_mode(dd.BURST_PERSISTENT_ONE, lambda: _gpu_burst(bt, 7, Q=Q, features=False))
+    xo, ro, _ = O.burst_batch(bt, W.material(), Q, 7, W.DT)
+    np.testing.assert_array_equal(xa, x1)
+    assert normwise(xa - bt.x, xo - bt.x) < 1e-10
+    assert np.abs(ra - ro).max() / np.abs(ro).max() < 1e-10
+    assert np.all(ra[2] == 0)
