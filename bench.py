@@ -81,9 +81,10 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_bytes():
-    """HBM bytes per launch of k_pair64 from the committed counter summary,
-    or None when the kernel source changed since the counters were taken."""
+def traffic_bytes(work_items):
+    """HBM bytes per launch of k_pair64 under a work split of `work_items`
+    items, from the committed counter summary; None when the kernel source
+    changed since the counters were taken or that split was not measured."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -91,7 +92,8 @@ def traffic_bytes():
         return None
     if t.get("kernel_source_sha") != kernel_source_sha():
         return None
-    return t.get("bytes_per_launch")
+    entry = t.get("by_work_items", {}).get(str(int(work_items)))
+    return entry["bytes_per_launch"] if entry else None
 
 
 def parse():
@@ -108,6 +110,8 @@ def parse():
     ap.add_argument("--cpu-full-out", default=os.path.join(PROFILES, "cpu_baseline_full.json"))
     ap.add_argument("--exact-band", type=float, default=0.0,
                     help="with --only fp64|mixed: exact target integral for pairs closer than this band")
+    ap.add_argument("--plan", type=int, default=0,
+                    help="profiling aid: fix the work split's source-range length (dd_set_plan); 0: automatic")
     ap.add_argument("--burst-instances", type=int, default=512)
     ap.add_argument("--burst-steps", type=int, default=200)
     ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy", "surrogate", "blocks", "cpu"], default=None,
@@ -308,6 +312,8 @@ def main():
     N = inst.n_segs
     pairs = N * (N - 1)
     dd.dd_set_validation(False)
+    if args.plan > 0:
+        dd.dd_set_plan(args.plan, 0)
 
     def resident(v):
         return {"x": torch.tensor(v.x, device=dev), "sn": torch.tensor(v.seg_nodes, device=dev),
@@ -426,7 +432,7 @@ def main():
         step_s, ker_s, bands64 = run(dd.DD_FP64, 2, args.steps, args.warmup)
         plan64 = bands64[3:5]
         r = roof(dd.DD_FP64, 2, ker_s, None)
-        tb = traffic_bytes()
+        tb = traffic_bytes(plan64[1])
         rl = {"bound": "alu", "achieved": r["achieved"], "peak": r["peak"], "unit": "TFLOP/s",
               "frac": r["frac"], "traffic": tb, "kernel": "k_pair64",
               "kernel_ms": r["kernel_ms"], "flop_per_launch": r["flop_per_launch"],
