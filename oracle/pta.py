@@ -36,7 +36,11 @@ state and the fast clock travel with the microstructure: each fast run
 carries them on from the state it starts from, the fast clock of a step is
 (fast steps taken so far) * dt, and step 5 continues the t - Delta run with
 the junction state and clock of its own end, after which the state of the end
-of step 2 is carried on, as for the positions.
+of step 2 is carried on, as for the positions.  With junction nodes
+(``JunctionNodes``, the rule of oracle/junction_nodes.py) the microstructure
+also holds the topology (segment nodes, Burgers vectors, normals, which
+captures and releases change): it travels the same way, with the node state
+and the fast clock.
 """
 from __future__ import annotations
 
@@ -46,6 +50,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import burst, fcc_system
+from . import junction_nodes as JN
 from . import junctions as OJ
 
 
@@ -87,6 +92,16 @@ class Junctions:
 
 
 @dataclass
+class JunctionNodes:
+    params: JN.Params          # capture radius, maximum breaking time, l_min, slots (its t0 unused)
+    state: dict                # oracle.junction_nodes.new_state
+    seg_nodes: np.ndarray      # the topology the node state refers to
+    burgers: np.ndarray
+    normal: np.ndarray
+    fast: int = 0              # fast steps taken so far (the fast clock)
+
+
+@dataclass
 class Run:
     x: np.ndarray        # state at the end of the run
     sums: np.ndarray     # [13]: sum over the steps of gdot (12) and rho
@@ -106,17 +121,27 @@ class Run:
 def _copy_jn(jn):
     if jn is None:
         return None
+    if isinstance(jn, JunctionNodes):
+        st = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in jn.state.items()}
+        return JunctionNodes(jn.params, st, jn.seg_nodes.copy(), jn.burgers.copy(), jn.normal.copy(), jn.fast)
     return Junctions(jn.r_c, jn.a_max, jn.fractions, {k: v.copy() for k, v in jn.state.items()}, jn.fast)
 
 
 def _one_step(inst, x, sigma, mat, Q, dt, jn=None):
     """Lambda at state x and the state after one glide step (after the
     junction checks at the fast clock, with the held nodes fixed, when `jn`
-    is given; its state and clock advance in place)."""
+    is given; its state and clock advance in place).  With junction nodes the
+    releases and captures at the fast clock change x (in place) and the
+    topology of `jn` first."""
     s = copy.copy(inst)
     s.x = x
     s.sigma_app = np.asarray(sigma, float)
-    if jn is not None:
+    if isinstance(jn, JunctionNodes):
+        JN.topology_step(x, jn.seg_nodes, jn.burgers, jn.normal, inst.pinned, float(jn.fast) * dt, jn.params,
+                         jn.state)
+        s.seg_nodes, s.burgers, s.normal = jn.seg_nodes, jn.burgers, jn.normal
+        jn.fast += 1
+    elif jn is not None:
         held = OJ.update(x, inst.seg_nodes, inst.pinned, float(jn.fast) * dt, jn.r_c, jn.a_max, jn.fractions,
                          jn.state)
         s.pinned = np.maximum(np.asarray(inst.pinned, np.uint8), held)

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from oracle import junction_nodes as JN
 from oracle import junctions as OJ
 from oracle import pta
 from paper_2005_02498_amd import workloads as W
@@ -147,3 +148,66 @@ def test_pta_with_junctions_is_the_step_by_step_junction_burst():
     for key in ("junction", "release", "ignore", "count"):
         assert np.array_equal(got["jn"].state[key], st[key]), key
     assert got["jn"].fast == k and st["count"].sum() > 0
+
+
+def _forest(K=4, seed=2):
+    inst = W.with_junction_slots(W.junction_forest(seed), K)
+    return inst, JN.Params(capture_radius=10.0, max_break_time=3 * W.DT, l_min=2.0, n_slots=K)
+
+
+def _nodes(inst, Pj, fast=0, seed=5):
+    fr = np.random.default_rng(seed).uniform(0.0, 1.0, 3)
+    return pta.JunctionNodes(Pj, JN.new_state(inst.n_nodes, inst.n_segs, fr), np.array(inst.seg_nodes),
+                             np.array(inst.burgers), np.array(inst.normal), fast)
+
+
+def test_pta_with_junction_nodes_and_zero_radius_is_the_plain_step():
+    """A zero capture radius: the step is the plain PTA step of the slotted
+    volume bit for bit (free slot segments add nothing), the topology is
+    unchanged, and the fast clock advances by the steps of the carried path."""
+    inst, Pj = _forest()
+    Pj = JN.Params(0.0, Pj.a, Pj.l_min, Pj.K)
+    P = pta.PTAParams(dt=W.DT, delta=1e-8, chunk=2, max_chunks=2, lpdot_max=np.inf)
+    rate = np.array([0.0, 0.0, 4e15, 0.0, 0.0, 0.0])
+    ref = pta.pta_step(inst, 5e-8, rate, W.material(), Q, P)
+    jn = _nodes(inst, Pj, fast=7)
+    got = pta.pta_step(inst, 5e-8, rate, W.material(), Q, P, jn)
+    assert np.array_equal(got["x"], ref["x"]) and np.array_equal(got["lp_b"], ref["lp_b"])
+    assert np.array_equal(got["jn"].seg_nodes, inst.seg_nodes)
+    assert got["jn"].fast == 7 + ref["steps_a"] - ref["rerun_chunks"] * P.chunk + ref["steps_b"]
+    assert jn.fast == 7 and jn.state["count"] == 0   # the caller's state is not touched
+
+
+def test_pta_with_junction_nodes_is_the_step_by_step_node_burst():
+    """No jump and no step 5: the t - Delta run and the t run are, step for
+    step, the junction-node topology step of oracle/junction_nodes.py at the
+    volume's fast clock followed by one glide step; averages, positions,
+    topology and node state agree exactly, and junctions form."""
+    inst, Pj = _forest()
+    mat = W.material()
+    P = pta.PTAParams(dt=W.DT, delta=1e-8, chunk=2, max_chunks=2, lpdot_max=np.inf)
+    rate = np.array([0.0, 0.0, 4e15, 0.0, 0.0, 0.0])
+    f0 = 11
+    jn = _nodes(inst, Pj, fast=f0)
+    got = pta.pta_step(inst, 5e-8, rate, mat, Q, P, jn)
+    assert got["rerun_chunks"] == 0 and got["jumps"] == 0
+    ref = _nodes(inst, Pj, fast=f0)
+    x = np.array(inst.x, float)
+    k = f0
+    for sig, n_steps, key in ((5e-8 - 1e-8, got["steps_a"], "g_a"), (5e-8, got["steps_b"], "g_b")):
+        acc = np.zeros(12)
+        for _ in range(n_steps):
+            JN.topology_step(x, ref.seg_nodes, ref.burgers, ref.normal, inst.pinned, float(k) * W.DT, Pj, ref.state)
+            s = W.Instance(x, ref.seg_nodes, ref.burgers, ref.normal, inst.pinned, sig * rate, inst.volume, {})
+            x, r, _ = O.burst(s, mat, Q, 1, W.DT)
+            acc += r
+            k += 1
+        assert np.array_equal(got[key], acc / n_steps)
+    assert np.array_equal(got["x"], x)
+    for a, b in ((got["jn"].seg_nodes, ref.seg_nodes), (got["jn"].burgers, ref.burgers),
+                 (got["jn"].normal, ref.normal)):
+        assert np.array_equal(a, b)
+    for key in ("release", "ses", "ignore", "point"):
+        assert np.array_equal(got["jn"].state[key], ref.state[key]), key
+    assert got["jn"].state["count"] == ref.state["count"] > 0
+    assert got["jn"].fast == k
