@@ -540,6 +540,28 @@ int dd_pta_step_junctions(int32_t n_inst, const int64_t *node_off, const int64_t
                           int precision, double near_cutoff_a, double exact_eta, const dd_junctions *junctions,
                           int64_t *fast_steps, double *out, void *stream);
 
+/* dd_pta_step with junction nodes (see dd_junction_nodes; Sec. "Thermal
+ * activation"): every fast step runs the releases and captures first, which
+ * change x, seg_nodes, burgers and normal in place (every instance carries
+ * n_slots node and segment slots as dd_burst_batch_junction_nodes needs).
+ * The topology and the junction-node state travel with the microstructure as
+ * the positions do: each fast run carries them on from the state it starts
+ * from, step 5 continues the t - delta run from that run's own end, and the
+ * topology, node state and positions at the end of step 2 are what the call
+ * leaves in the caller's arrays.  The clock of a step is the volume's fast
+ * clock, (fast_steps[i] + steps taken in this run) * dt (junctions->t0 is not
+ * used); fast_steps HOST [n_inst] int64, >= 0, in and out as for
+ * dd_pta_step_junctions.  No exact band.  The other arguments as
+ * dd_pta_step.
+ * Errors: DD_EINVAL as dd_pta_step, for a null junctions or fast_steps, a
+ *  negative fast_steps entry, or what dd_burst_batch_junction_nodes rejects. */
+int dd_pta_step_junction_nodes(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                               int32_t *seg_nodes, double *burgers, double *normal, const uint8_t *pinned,
+                               const double *volume, const double *stress_rate, const double *t,
+                               const dd_pta_params *prm, const dd_material *m, int n_gauss, int precision,
+                               double near_cutoff_a, const dd_junction_nodes *junctions, int64_t *fast_steps,
+                               double *out, void *stream);
+
 /* Block coupling of the DD boxes to the continuum mesh (Sec. "DD-MFDM
  * coupling").  The domain is n x n square blocks of side B and thickness h,
  * one brick through the thickness (one DD box per block); every block is

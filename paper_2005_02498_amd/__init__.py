@@ -26,7 +26,7 @@ MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 36, 256, 12, 144140
 EXPORTS = [
     "dd_last_error", "dd_version", "dd_set_validation", "dd_shutdown",
     "dd_timing_enable", "dd_timing_read", "dd_vector_peak", "dd_set_autotune", "dd_set_burst_mode", "dd_check", "dd_set_plan", "dd_last_plan",
-    "dd_nodal_forces", "dd_nodal_forces_noalloc", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_burst_batch_junction_nodes", "dd_pta_step", "dd_pta_step_junctions",
+    "dd_nodal_forces", "dd_nodal_forces_noalloc", "dd_glide_step", "dd_step", "dd_burst_batch", "dd_burst_batch_junctions", "dd_burst_batch_junction_nodes", "dd_pta_step", "dd_pta_step_junctions", "dd_pta_step_junction_nodes",
     "dd_block_average", "dd_block_to_gauss", "dd_dissipation_fix",
     "dd_mlp_create", "dd_mlp_destroy", "dd_mlp_set_params", "dd_mlp_get_params", "dd_mlp_save", "dd_mlp_load", "dd_mlp_info",
     "dd_mlp_set_scaling", "dd_mlp_set_log_densities", "dd_mlp_set_spread_floor", "dd_mlp_train_step", "dd_mlp_gradients",
@@ -120,6 +120,11 @@ def _declare(L):
                                             C.POINTER(PTAParams), C.POINTER(Material), C.c_int, C.c_int, dbl,
                                             dbl, C.POINTER(Junctions), C.POINTER(C.c_int64),
                                             C.POINTER(C.c_double), vp]),
+        "dd_pta_step_junction_nodes": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64), vp, vp,
+                                                 vp, vp, vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                                 C.POINTER(PTAParams), C.POINTER(Material), C.c_int, C.c_int, dbl,
+                                                 C.POINTER(JunctionNodes), C.POINTER(C.c_int64),
+                                                 C.POINTER(C.c_double), vp]),
         "dd_set_plan": (C.c_int, [i64, C.c_int]),
         "dd_check": (C.c_int, [vp]),
         "dd_block_average": (C.c_int, [C.POINTER(BlockMesh), C.c_int, vp, vp, vp]),
@@ -507,16 +512,7 @@ def dd_burst_batch_junction_nodes(node_off, seg_off, x, seg_nodes, burgers, norm
     pp = _dev(pinned, torch.uint8, (nn,), "pinned", nullable=True)
     ps = _dev(sigma_app, torch.float64, (n_inst, 6), "sigma_app")
     pv = _dev(volume, torch.float64, (n_inst,), "volume")
-    K = fractions.shape[1] if fractions.dim() == 2 else -1
-    pf = _dev(fractions, torch.float64, (n_inst, K), "fractions")
-    jn = JunctionNodes(float(capture_radius), float(max_break_time), float(t0), float(min_length), int(n_slots),
-                       int(K), pf.value,
-                       _dev(state["release"], torch.float64, (nn,), "release").value,
-                       _dev(state["ses"], torch.int32, (nn,), "ses").value,
-                       _dev(state["ignore"], torch.int32, (ns,), "ignore").value,
-                       _dev(state["point"], torch.float64, (3, ns), "point").value,
-                       _dev(state["count"], torch.int32, (n_inst,), "count").value,
-                       _dev(state["missed"], torch.int32, (n_inst,), "missed").value)
+    jn = _jnode_args(state, fractions, capture_radius, max_break_time, min_length, n_slots, t0, nn, ns, n_inst)
     if rate_avg_out is None:
         rate_avg_out = torch.empty((n_inst, 12), dtype=torch.float64, device=dev)
     pr = _dev(rate_avg_out, torch.float64, (n_inst, 12), "rate_avg_out")
@@ -528,6 +524,19 @@ def dd_burst_batch_junction_nodes(node_off, seg_off, x, seg_nodes, burgers, norm
                                                int(n_gauss), _prec(precision), float(near_cutoff_a), int(n_steps),
                                                float(dt), C.byref(jn), pr, pfe, _stream(stream)))
     return rate_avg_out, features_out
+
+
+def _jnode_args(state, fractions, capture_radius, max_break_time, min_length, n_slots, t0, nn, ns, n_inst):
+    K = fractions.shape[1] if fractions.dim() == 2 else -1
+    pf = _dev(fractions, torch.float64, (n_inst, K), "fractions")
+    return JunctionNodes(float(capture_radius), float(max_break_time), float(t0), float(min_length), int(n_slots),
+                         int(K), pf.value,
+                         _dev(state["release"], torch.float64, (nn,), "release").value,
+                         _dev(state["ses"], torch.int32, (nn,), "ses").value,
+                         _dev(state["ignore"], torch.int32, (ns,), "ignore").value,
+                         _dev(state["point"], torch.float64, (3, ns), "point").value,
+                         _dev(state["count"], torch.int32, (n_inst,), "count").value,
+                         _dev(state["missed"], torch.int32, (n_inst,), "missed").value)
 
 
 def _junction_args(state, fractions, capture_radius, max_break_time, nn, t0=0.0):
@@ -543,7 +552,7 @@ def _junction_args(state, fractions, capture_radius, max_break_time, nn, t0=0.0)
 
 def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t,
                 params, mat, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0, stream=None, junctions=None,
-                exact_eta=0.0):
+                exact_eta=0.0, junction_nodes=None):
     """One PTA slow-time step for every instance (see dd.h); x advances to the
     microstructure for the next step.  stress_rate [n_inst][6] (Pa/s) and t
     [n_inst] (s) are host sequences.  Returns a dict of NumPy arrays.
@@ -551,7 +560,13 @@ def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume
     junctions: None, or a dict with keys state (device tensors as
     dd_burst_batch_junctions, updated in place), fractions, capture_radius,
     max_break_time and fast_steps (host int64 array [n_inst], updated in
-    place); then dd_pta_step_junctions runs."""
+    place); then dd_pta_step_junctions runs.
+
+    junction_nodes: None, or a dict with keys state (junction_node_state),
+    fractions (device [n_inst][K]), capture_radius, max_break_time,
+    min_length, n_slots and fast_steps (host int64 [n_inst], updated in
+    place); then dd_pta_step_junction_nodes runs, and seg_nodes, burgers and
+    normal change in place with the topology."""
     import numpy as np
     no = (C.c_int64 * len(node_off))(*[int(v) for v in node_off])
     so = (C.c_int64 * len(seg_off))(*[int(v) for v in seg_off])
@@ -570,7 +585,20 @@ def dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume
     out = np.zeros((n_inst, DD_PTA_OUT))
     m = _mat(mat)
     dp = C.POINTER(C.c_double)
-    if junctions is None:
+    if junction_nodes is not None:
+        J = junction_nodes
+        jn = _jnode_args(J["state"], J["fractions"], J["capture_radius"], J["max_break_time"], J["min_length"],
+                         J["n_slots"], 0.0, nn, ns, n_inst)
+        fs = J["fast_steps"]
+        if not (isinstance(fs, np.ndarray) and fs.dtype == np.int64 and fs.shape == (n_inst,)
+                and fs.flags.c_contiguous):
+            raise ValueError("junction_nodes['fast_steps'] must be a contiguous int64 array of length n_inst")
+        _check(lib().dd_pta_step_junction_nodes(n_inst, no, so, px, psn, pb, pn, pp, pv, sr.ctypes.data_as(dp),
+                                                tt.ctypes.data_as(dp), C.byref(params), C.byref(m), int(n_gauss),
+                                                _prec(precision), float(near_cutoff_a), C.byref(jn),
+                                                fs.ctypes.data_as(C.POINTER(C.c_int64)), out.ctypes.data_as(dp),
+                                                _stream(stream)))
+    elif junctions is None:
         _check(lib().dd_pta_step(n_inst, no, so, px, psn, pb, pn, pp, pv, sr.ctypes.data_as(dp),
                                  tt.ctypes.data_as(dp), C.byref(params), C.byref(m), int(n_gauss),
                                  _prec(precision), float(near_cutoff_a), float(exact_eta), out.ctypes.data_as(dp),
@@ -603,6 +631,16 @@ def dd_pta_step_junctions(node_off, seg_off, x, seg_nodes, burgers, normal, pinn
         raise ValueError("junctions is required")
     return dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, params,
                        mat, n_gauss, precision, near_cutoff_a, stream, junctions, exact_eta)
+
+
+def dd_pta_step_junction_nodes(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t,
+                               params, mat, junction_nodes, n_gauss=2, precision=DD_FP64, near_cutoff_a=20.0,
+                               stream=None):
+    """dd_pta_step with junction nodes (dd.h); `junction_nodes` as in dd_pta_step."""
+    if junction_nodes is None:
+        raise ValueError("junction_nodes is required")
+    return dd_pta_step(node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, params,
+                       mat, n_gauss, precision, near_cutoff_a, stream, junction_nodes=junction_nodes)
 
 
 # --------------------------------------------------------------- surrogate --

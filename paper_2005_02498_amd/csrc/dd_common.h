@@ -259,6 +259,11 @@ struct BurstBatch {
     // the instance's fast clock
     const dd_junctions *jn = nullptr;
     const int64_t *fast_steps_dev = nullptr;
+    // junction nodes (null: none): parameters and state, timed by the same
+    // fast clock; captures and releases change the topology in place
+    const dd_junction_nodes *jnodes = nullptr;
+    int32_t *seg_nodes_w = nullptr;
+    double *burgers_w = nullptr, *normal_w = nullptr;
 };
 int burst_batch_init(BurstBatch &B, hipStream_t st);
 int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, const double *sigma_dev,

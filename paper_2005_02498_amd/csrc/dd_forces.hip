@@ -831,6 +831,9 @@ struct JNodeArgs {
     double rc, rc2, rf2, a, lmin;      // capture radius, its square, (2 r_c)^2, max breaking time, l_min
     double tk;                         // this step's offset k dt from the call's start time
     const double *t0;                  // the call's start time (device, written before the step graph runs)
+    const int64_t *fast;               // or per instance the fast steps taken so far (PTA), null: t0 + tk
+    double fdt;                        //   the fast step dt
+    int fk;                            //   and this step's index in the run
     int32_t K, Kf;                     // slots per instance, fractions per instance
     const double *fractions;           // [n_inst][Kf]
     double *release;                   // [nn]
@@ -844,6 +847,15 @@ struct JNodeArgs {
     int32_t *cand;                     // [ns] sessile candidate of a segment, -1: none
     double *cand_u;                    // [ns] its parameter on the segment
 };
+
+// Time of a topology step of instance inst: its fast clock, (fast steps
+// taken so far + this step's index) dt, when the caller keeps one (the PTA
+// driver), else the call's start time plus k dt (both as the oracle forms
+// them).
+__device__ __forceinline__ double jn_time(const JNodeArgs &J, int inst)
+{
+    return J.fast ? (double)(J.fast[inst] + J.fk) * J.fdt : *J.t0 + J.tk;
+}
 
 // Sessile segments for junction nodes: an instance's own segment (not a
 // segment slot) between two of its own nodes (not node slots or dummies),
@@ -877,7 +889,7 @@ __global__ __launch_bounds__(256) void k_jn_release(Layout L, int32_t *__restric
     const int64_t s0 = L.seg_off[inst], n_s = L.seg_off[inst + 1] - s0, ns = L.ns;
     if (n_n < J.K + 2 || n_s < J.K) return;
     const int32_t d1 = (int32_t)(n_n - 2), d2 = (int32_t)(n_n - 1);
-    const double t = *J.t0 + J.tk;   // t0 + k dt, as the oracle forms it
+    const double t = jn_time(J, inst);
     __shared__ int64_t s_in, s_out;
     for (int64_t jl = n_n - J.K - 2; jl < n_n - 2; ++jl) {
         const int64_t j = n0 + jl;
@@ -1017,7 +1029,7 @@ __global__ __launch_bounds__(256) void k_jn_capture(Layout L, int32_t *__restric
                 for (int cc = 0; cc < 3; ++cc) J.point[cc * ns + s] = J.point[cc * ns + s2] = x[cc * nn + j];
                 const int32_t cn = J.count[inst];
                 const int32_t kf = ((cn % J.Kf) + J.Kf) % J.Kf;
-                J.release[j] = release_time(*J.t0 + J.tk, J.fractions[(int64_t)inst * J.Kf + kf], J.a);
+                J.release[j] = release_time(jn_time(J, inst), J.fractions[(int64_t)inst * J.Kf + kf], J.a);
                 J.ses[j] = k;
                 J.count[inst] = cn + 1;
             }
@@ -1739,16 +1751,16 @@ void launch_csr(const ForceCtx &C, const int32_t *seg_nodes, hipStream_t st)
 // The topology kernels of one step at time t0 + tk, t0 read from the device
 // (releases, candidates, captures), and the node -> segment lists they
 // change.
-void launch_jnode_step(const ForceCtx &C, JNodeArgs J, double tk, int n_inst, int32_t *seg_nodes, double *x,
-                       double *burgers, double *normal, uint32_t *flags, hipStream_t st)
+void launch_jnode_step(const ForceCtx &C, JNodeArgs J, double tk, int k, int n_inst, int32_t *seg_nodes, double *x,
+                       double *burgers, double *normal, uint32_t *flags, const uint8_t *active, hipStream_t st)
 {
     J.tk = tk;
+    J.fk = k;
     hipLaunchKernelGGL(k_jn_release, dim3(n_inst), dim3(256), 0, st, C.L, seg_nodes, (const double *)x, burgers,
-                       normal, J, (const uint8_t *)nullptr, flags);
+                       normal, J, active, flags);
     hipLaunchKernelGGL(k_jn_candidates, dim3(grid_for(C.L.ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
-                       (const int32_t *)seg_nodes, (const double *)x, J, (const uint8_t *)nullptr);
-    hipLaunchKernelGGL(k_jn_capture, dim3(n_inst), dim3(256), 0, st, C.L, seg_nodes, x, burgers, normal, J,
-                       (const uint8_t *)nullptr);
+                       (const int32_t *)seg_nodes, (const double *)x, J, active);
+    hipLaunchKernelGGL(k_jn_capture, dim3(n_inst), dim3(256), 0, st, C.L, seg_nodes, x, burgers, normal, J, active);
     launch_csr(C, seg_nodes, st);
 }
 
@@ -2158,6 +2170,14 @@ int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, con
     // never read there, but points at valid memory all the same)
     if ((rc = ensure(ws, WS_T0, sizeof(double), &p))) return rc;
     J.t0 = (const double *)p;
+    // junction nodes, timed by the per-instance fast clock
+    JNodeArgs JN{};
+    if (B.jnodes) {
+        if ((rc = jnode_prepare(ws, C.L, B.seg_nodes, B.x, B.pinned, B.jnodes, JN, st))) return rc;
+        JN.t0 = (const double *)p;
+        JN.fast = B.fast_steps_dev;
+        JN.fdt = B.dt;
+    }
     if ((rc = presize_near(C, ws, B.x, B.seg_nodes, st))) return rc;
     DD_HIP(hipGetLastError());
     KeyBuf key;
@@ -2166,9 +2186,18 @@ int burst_batch_run(const BurstBatch &B, const std::vector<uint8_t> &active, con
     key.add(B.near_cut).add(B.eta).add(B.dt).add(B.choice).add(sigma_dev).add(sums_dev).add(n_steps);
     key.add(B.jn != nullptr).add(B.fast_steps_dev).add(C.near.pair_cap).add_workspace(ws);
     if (B.jn) key.add(*B.jn);
+    key.add(B.jnodes != nullptr);
+    if (B.jnodes) {
+        dd_junction_nodes kj = *B.jnodes;
+        kj.t0 = 0.0;
+        key.add(kj);
+    }
     const Sig6 sv{};
     rc = launch_cached_graph(ws, key, [&](hipStream_t cs) -> int {
         for (int k = 0; k < n_steps; ++k) {
+            if (B.jnodes)
+                launch_jnode_step(C, JN, 0.0, k, n_inst, B.seg_nodes_w, B.x, B.burgers_w, B.normal_w, ws->flags_dev,
+                                  (const uint8_t *)d_act, cs);
             if (B.jn)
                 hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,
                                    B.seg_nodes, (const double *)B.x, B.pinned, J, n_inst, (const uint8_t *)d_act,
@@ -2656,9 +2685,9 @@ int burst_batch_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg
         rc = launch_cached_graph(ws, key, [&](hipStream_t cs) -> int {
             for (int k = 0; k < n_steps; ++k) {
                 if (jnodes)   // (the public call passes these arrays as writable)
-                    launch_jnode_step(C, JN, k * dt, n_inst, const_cast<int32_t *>(seg_nodes), x,
+                    launch_jnode_step(C, JN, k * dt, k, n_inst, const_cast<int32_t *>(seg_nodes), x,
                                       const_cast<double *>(burgers), const_cast<double *>(normal), ws->flags_dev,
-                                      cs);
+                                      nullptr, cs);
                 if (jn) {
                     J.tk = k * dt;
                     hipLaunchKernelGGL(k_junctions, dim3(grid_for(nn, 256, INT32_MAX)), dim3(256), 0, cs, C.L,

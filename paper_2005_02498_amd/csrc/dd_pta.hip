@@ -4,6 +4,7 @@
 // them (burst_batch_run).  Per-chunk sums come back to the host (13 doubles
 // per volume); positions stay in device memory.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "dd_common.h"
@@ -55,6 +56,14 @@ __global__ void k_copy_masked(T *__restrict__ dst, const T *__restrict__ src, in
     }
     if (!mask[lo]) return;
     for (int k = 0; k < comps; ++k) dst[k * nn + n] = src[k * nn + n];
+}
+
+// copies per-instance values of the instances with mask[i] != 0
+template <class T>
+__global__ void k_copy_inst(T *__restrict__ dst, const T *__restrict__ src, int n_inst, const uint8_t *__restrict__ mask)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_inst && mask[i]) dst[i] = src[i];
 }
 
 // L^p = sum_alpha gdot_alpha m_alpha (x) n_alpha (row-major 3 x 3)
@@ -186,11 +195,73 @@ struct Driver {
         return DD_OK;
     }
 
+    // Junction-node state and topology of the masked instances (saved layout:
+    // release [nn], burgers, normal, point [3][ns] doubles, then ses [nn],
+    // seg_nodes [2][ns], ignore [ns], count, missed [n_inst] int32).
+    int node_state(double *buf, const std::vector<uint8_t> &mask, bool to_save)
+    {
+        const int n = B.n_inst;
+        const int64_t nn = B.node_off[n], ns = B.seg_off[n];
+        uint8_t *d_mask;
+        int rc = upload_mask(mask, &d_mask);
+        if (rc) return rc;
+        const dd_junction_nodes *J = B.jnodes;
+        double *rel = buf, *bur = rel + nn, *nrm = bur + 3 * ns, *pt = nrm + 3 * ns;
+        int32_t *ses = (int32_t *)(pt + 3 * ns), *sn = ses + nn, *ig = sn + 2 * ns, *cnt = ig + ns, *mis = cnt + n;
+        const int64_t *no = (const int64_t *)ws->ptr[WS_INST_OFFS], *so = no + (n + 1);
+        const unsigned gn = (unsigned)((nn + 255) / 256), gs = (unsigned)((ns + 255) / 256);
+        const unsigned gi = (unsigned)((n + 255) / 256);
+        auto nodes = [&](auto *dst, const auto *src, int comps) {
+            if (nn > 0)
+                hipLaunchKernelGGL(k_copy_masked<std::remove_cv_t<std::remove_reference_t<decltype(*dst)>>>, dim3(gn),
+                                   dim3(256), 0, st, dst, src, nn, comps, no, n, (const uint8_t *)d_mask);
+        };
+        auto segs = [&](auto *dst, const auto *src, int comps) {
+            if (ns > 0)
+                hipLaunchKernelGGL(k_copy_masked<std::remove_cv_t<std::remove_reference_t<decltype(*dst)>>>, dim3(gs),
+                                   dim3(256), 0, st, dst, src, ns, comps, so, n, (const uint8_t *)d_mask);
+        };
+        auto insts = [&](int32_t *dst, const int32_t *src) {
+            hipLaunchKernelGGL(k_copy_inst<int32_t>, dim3(gi), dim3(256), 0, st, dst, src, n, (const uint8_t *)d_mask);
+        };
+        if (to_save) {
+            nodes(rel, (const double *)J->release, 1);
+            nodes(ses, (const int32_t *)J->ses, 1);
+            segs(bur, (const double *)B.burgers_w, 3);
+            segs(nrm, (const double *)B.normal_w, 3);
+            segs(pt, (const double *)J->point, 3);
+            segs(sn, (const int32_t *)B.seg_nodes_w, 2);
+            segs(ig, (const int32_t *)J->ignore, 1);
+            insts(cnt, J->count);
+            insts(mis, J->missed);
+        } else {
+            nodes(J->release, (const double *)rel, 1);
+            nodes(J->ses, (const int32_t *)ses, 1);
+            segs(B.burgers_w, (const double *)bur, 3);
+            segs(B.normal_w, (const double *)nrm, 3);
+            segs(J->point, (const double *)pt, 3);
+            segs(B.seg_nodes_w, (const int32_t *)sn, 2);
+            segs(J->ignore, (const int32_t *)ig, 1);
+            insts(J->count, cnt);
+            insts(J->missed, mis);
+        }
+        DD_HIP(hipGetLastError());
+        return DD_OK;
+    }
+
     // Junction state of the masked instances: `to_save` copies the caller's
     // state (and fast clocks) into save slot `buf`/`fast_saved`, otherwise back.
     int junction_state(double *buf, std::vector<int64_t> &fast_saved, const std::vector<uint8_t> &mask,
                        bool to_save)
     {
+        if (B.jnodes) {
+            for (int i = 0; i < B.n_inst; ++i)
+                if (mask[i]) {
+                    if (to_save) fast_saved[i] = fast[i];
+                    else fast[i] = fast_saved[i];
+                }
+            return node_state(buf, mask, to_save);
+        }
         if (!B.jn) return DD_OK;
         const int n = B.n_inst;
         const int64_t nn = B.node_off[n];
@@ -255,7 +326,7 @@ int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, do
              const double *burgers, const double *normal, const uint8_t *pinned, const double *volume,
              const double *stress_rate, const double *t, const dd_pta_params *prm, const dd_material *m, int n_gauss,
              int precision, double near_cutoff_a, double exact_eta, const dd_junctions *jn, int64_t *fast_steps,
-             double *out, void *stream)
+             double *out, void *stream, const dd_junction_nodes *jnodes = nullptr)
 {
     int rc;
     if (n_inst < 0) return set_error(DD_EINVAL, "n_inst < 0");
@@ -301,6 +372,25 @@ int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, do
         for (int i = 0; i < n_inst; ++i)
             if (fast_steps[i] < 0) return set_error(DD_EINVAL, "junctions: fast_steps must be >= 0");
     }
+    if (jnodes) {
+        const dd_junction_nodes *J = jnodes;
+        if (!(J->capture_radius >= 0.0) || !std::isfinite(J->capture_radius) || !(J->max_break_time >= 0.0) ||
+            !std::isfinite(J->max_break_time) || !(J->min_length >= 0.0) || !std::isfinite(J->min_length))
+            return set_error(DD_EINVAL, "junction nodes: capture radius, breaking time and min_length must be "
+                                        "finite and >= 0");
+        if (J->n_slots < 1 || J->n_fractions < 1)
+            return set_error(DD_EINVAL, "junction nodes: n_slots and n_fractions must be >= 1");
+        if (!J->fractions || !J->release || !J->ses || !J->ignore || !J->point || !J->count || !J->missed)
+            return set_error(DD_EINVAL, "junction nodes: null state or fractions array");
+        if (exact_eta != 0.0) return set_error(DD_EINVAL, "junction nodes: no exact band (exact_eta must be 0)");
+        for (int i = 0; i < n_inst; ++i)
+            if (node_off[i + 1] - node_off[i] < (int64_t)J->n_slots + 2 || seg_off[i + 1] - seg_off[i] < J->n_slots)
+                return set_error(DD_EINVAL, "junction nodes: instance %d has fewer than n_slots + 2 nodes or n_slots "
+                                            "segments", i);
+        if (!fast_steps) return set_error(DD_EINVAL, "junction nodes: null fast_steps");
+        for (int i = 0; i < n_inst; ++i)
+            if (fast_steps[i] < 0) return set_error(DD_EINVAL, "junction nodes: fast_steps must be >= 0");
+    }
     hipStream_t st = (hipStream_t)stream;
     Workspace *ws;
     if ((rc = workspace(&ws))) return rc;
@@ -327,7 +417,21 @@ int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, do
     void *p;
     double *jA = nullptr, *jB = nullptr;
     std::vector<int64_t> fastA(n_inst, 0), fastB(n_inst, 0);
-    if (jn) {
+    if (jnodes) {
+        if ((rc = ensure(ws, WS_PTA_FAST, sizeof(int64_t) * n_inst, &p))) return rc;
+        D.fast_dev = (int64_t *)p;
+        D.fast.assign(fast_steps, fast_steps + n_inst);
+        B.jnodes = jnodes;
+        B.seg_nodes_w = const_cast<int32_t *>(seg_nodes);
+        B.burgers_w = const_cast<double *>(burgers);
+        B.normal_w = const_cast<double *>(normal);
+        B.fast_steps_dev = D.fast_dev;
+        const size_t jbytes = sizeof(double) * (size_t)(nn + 9 * ns) + sizeof(int32_t) * (size_t)(nn + 3 * ns + 2 * n_inst);
+        if ((rc = ensure(ws, WS_PTA_JA, jbytes, &p))) return rc;
+        jA = (double *)p;
+        if ((rc = ensure(ws, WS_PTA_JB, jbytes, &p))) return rc;
+        jB = (double *)p;
+    } else if (jn) {
         if ((rc = ensure(ws, WS_PTA_FAST, sizeof(int64_t) * n_inst, &p))) return rc;
         D.fast_dev = (int64_t *)p;
         D.fast.assign(fast_steps, fast_steps + n_inst);
@@ -452,7 +556,7 @@ int pta_impl(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, do
         if ((rc = read_flags(ws, st))) return rc;
     }
     DD_HIP(hipStreamSynchronize(st));
-    if (jn)
+    if (jn || jnodes)
         for (int i = 0; i < n_inst; ++i) fast_steps[i] = D.fast[i];
     return DD_OK;
 }
@@ -485,3 +589,17 @@ extern "C" int dd_pta_step_junctions(int32_t n_inst, const int64_t *node_off, co
                     n_gauss, precision, near_cutoff_a, exact_eta, junctions, fast_steps, out, stream);
 }
 
+
+extern "C" int dd_pta_step_junction_nodes(int32_t n_inst, const int64_t *node_off, const int64_t *seg_off, double *x,
+                                          int32_t *seg_nodes, double *burgers, double *normal, const uint8_t *pinned,
+                                          const double *volume, const double *stress_rate, const double *t,
+                                          const dd_pta_params *prm, const dd_material *m, int n_gauss, int precision,
+                                          double near_cutoff_a, const dd_junction_nodes *junctions,
+                                          int64_t *fast_steps, double *out, void *stream)
+{
+    ::dd::Range range_("dd_pta_step_junction_nodes");
+    clear_error();
+    if (!junctions) return set_error(DD_EINVAL, "null junction-node parameters");
+    return pta_impl(n_inst, node_off, seg_off, x, seg_nodes, burgers, normal, pinned, volume, stress_rate, t, prm, m,
+                    n_gauss, precision, near_cutoff_a, 0.0, nullptr, fast_steps, out, stream, junctions);
+}

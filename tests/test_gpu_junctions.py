@@ -110,11 +110,17 @@ def test_batch_with_captures_over_two_calls():
 
 
 def test_zero_radius_is_the_plain_burst():
+    """A zero capture radius: bit for bit the plain burst of the same step
+    graph (the persistent launch of small FP64 bursts sums in another order)."""
     insts = [W.subset(W.burst_instance(1_000_040 + i), nl) for i, nl in enumerate((2, 3))]
     bt = W.pack(insts)
     d1, d2 = batch_dev(bt), batch_dev(bt)
-    r1, _ = dd.dd_burst_batch(bt.node_off, bt.seg_off, d1["x"], d1["seg_nodes"], d1["burgers"], d1["normal"],
-                              d1["pinned"], d1["sigma_app"], d1["volume"], MAT, 2, dd.DD_FP64, 20.0, 5, W.DT)
+    prev = dd.dd_set_burst_mode(dd.BURST_GRAPH)
+    try:
+        r1, _ = dd.dd_burst_batch(bt.node_off, bt.seg_off, d1["x"], d1["seg_nodes"], d1["burgers"], d1["normal"],
+                                  d1["pinned"], d1["sigma_app"], d1["volume"], MAT, 2, dd.DD_FP64, 20.0, 5, W.DT)
+    finally:
+        dd.dd_set_burst_mode(prev)
     st = _state_dev(bt.node_off[-1])
     fr = torch.full((bt.node_off[-1], 1), 0.5, dtype=torch.float64, device=DEV)
     r2 = dd.dd_burst_batch_junctions(bt.node_off, bt.seg_off, d2["x"], d2["seg_nodes"], d2["burgers"],
