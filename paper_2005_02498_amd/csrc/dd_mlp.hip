@@ -62,6 +62,24 @@ struct GemmArgs {
 
 constexpr int BM = 64, BN = 64, BK = 32, LDSK = BK + 8;
 
+// Eight consecutive bf16 of a row of P (elements c .. c + 7 of row `row`,
+// leading dimension ld), zero where c + i >= lim or the row is out of range:
+// one 16-byte load when the eight lie inside and the address is 16-byte
+// aligned, else element by element.
+__device__ __forceinline__ bf16x8 load8(const __bf16 *P, int64_t ld, int row, bool row_ok, int c, int lim)
+{
+    bf16x8 v;
+    const __bf16 zero = to_bf16(0.f);
+    const __bf16 *q = P + (int64_t)row * ld + c;
+    if (row_ok && c + 8 <= lim && ((uintptr_t)q & 15) == 0) {
+        v = *reinterpret_cast<const bf16x8 *>(q);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (row_ok && c + i < lim) ? q[i] : zero;
+    }
+    return v;
+}
+
 template <bool TA, bool TB>
 __device__ __forceinline__ void stage(const GemmArgs &g, int member, int m0, int n0, int k0,
                                       __bf16 (*As)[LDSK], __bf16 (*Bs)[LDSK])
@@ -69,40 +87,36 @@ __device__ __forceinline__ void stage(const GemmArgs &g, int member, int m0, int
     const int t = threadIdx.x;
     const __bf16 *A = g.A + member * g.sA;
     const __bf16 *B = g.B + member * g.sB;
-    const __bf16 zero = to_bf16(0.f);
-    if (!TA) {   // row r, k offset 8 (t % 4)
+    if (!TA) {   // row r, k offset 8 (t % 4): eight k of one row
         const int r = t / 4, kk = (t % 4) * 8, m = m0 + r;
-        for (int i = 0; i < 8; ++i) {
-            const int k = k0 + kk + i;
-            As[r][kk + i] = (m < g.M && k < g.K) ? A[(int64_t)m * g.lda + k] : zero;
-        }
-    } else {     // k row t / 8, m offset 8 (t % 8)
+        const bf16x8 v = load8(A, g.lda, m, m < g.M, k0 + kk, g.K);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) As[r][kk + i] = v[i];
+    } else {     // k row t / 8, m offset 8 (t % 8): eight m of one k row, stored transposed
         const int kr = t / 8, mm = (t % 8) * 8, k = k0 + kr;
-        for (int i = 0; i < 8; ++i) {
-            const int m = m0 + mm + i;
-            As[mm + i][kr] = (m < g.M && k < g.K) ? A[(int64_t)k * g.lda + m] : zero;
-        }
+        const bf16x8 v = load8(A, g.lda, k, k < g.K, m0 + mm, g.M);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) As[mm + i][kr] = v[i];
     }
     if (!TB) {
         const int r = t / 4, kk = (t % 4) * 8, n = n0 + r;
-        for (int i = 0; i < 8; ++i) {
-            const int k = k0 + kk + i;
-            Bs[r][kk + i] = (n < g.N && k < g.K) ? B[(int64_t)n * g.ldb + k] : zero;
-        }
+        const bf16x8 v = load8(B, g.ldb, n, n < g.N, k0 + kk, g.K);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Bs[r][kk + i] = v[i];
     } else {
         const int kr = t / 8, nn = (t % 8) * 8, k = k0 + kr;
-        for (int i = 0; i < 8; ++i) {
-            const int n = n0 + nn + i;
-            Bs[nn + i][kr] = (n < g.N && k < g.K) ? B[(int64_t)k * g.ldb + n] : zero;
-        }
+        const bf16x8 v = load8(B, g.ldb, k, k < g.K, n0 + nn, g.N);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Bs[nn + i][kr] = v[i];
     }
 }
 
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
 {
-    __shared__ __bf16 As[BM][LDSK];
-    __shared__ __bf16 Bs[BN][LDSK];
+    // rows of LDSK = 40 bf16 (80 bytes): every 16-byte fragment at k = 8 q is aligned
+    __shared__ __attribute__((aligned(16))) __bf16 As[BM][LDSK];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][LDSK];
     const int member = blockIdx.z;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -117,10 +131,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
         stage<TA, TB>(g, member, m0, n0, k0, As, Bs);
         __syncthreads();
         bf16x8 a[2], b[2];
-        for (int i = 0; i < 2; ++i)
-            for (int e = 0; e < 8; ++e) a[i][e] = As[wm + 16 * i + lr][lk + e];
-        for (int j = 0; j < 2; ++j)
-            for (int e = 0; e < 8; ++e) b[j][e] = Bs[wn + 16 * j + lr][lk + e];
+        for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + lr][lk]);
+        for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 16 * j + lr][lk]);
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
