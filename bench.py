@@ -114,7 +114,8 @@ def parse():
                     help="profiling aid: fix the work split's source-range length (dd_set_plan); 0: automatic")
     ap.add_argument("--burst-instances", type=int, default=512)
     ap.add_argument("--burst-steps", type=int, default=200)
-    ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy", "surrogate", "blocks", "cpu"], default=None,
+    ap.add_argument("--only", choices=["fp64", "mixed", "burst", "copy", "surrogate", "blocks", "cpu", "small"],
+                    default=None,
                     help="profiling aid: run only one part (no JSON contract)")
     ap.add_argument("--surrogate-study", action="store_true",
                     help="run the surrogate speed-up-at-fixed-error study and write --study-out")
@@ -306,6 +307,59 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "launches": 5}))
+        return
+
+    def small_volume():
+        """The 256-segment volume, 100 FP64 glide steps per call, in the three
+        burst modes: the cached step graph, the persistent launch with one
+        workgroup, and the default (the persistent launch, 128 workgroups)."""
+        sb = W.pack([W.config0()])
+        ds = dict(x=torch.tensor(sb.x, device=dev), sn=torch.tensor(sb.seg_nodes, device=dev),
+                  b=torch.tensor(sb.burgers, device=dev), n=torch.tensor(sb.normal, device=dev),
+                  p=torch.tensor(sb.pinned, device=dev), s=torch.tensor(sb.sigma_app, device=dev),
+                  v=torch.tensor(sb.volume, device=dev))
+        xs = ds["x"].clone()
+        rs = torch.empty((1, 12), dtype=torch.float64, device=dev)
+
+        def small_call():
+            xs.copy_(ds["x"])   # the same start, in the same buffer: the cached graph applies
+            dd.dd_burst_batch(sb.node_off, sb.seg_off, xs, ds["sn"], ds["b"], ds["n"], ds["p"],
+                              ds["s"], ds["v"], mat, 2, dd.DD_FP64, 20.0, 100, W.DT, rate_avg_out=rs)
+
+        def small_timing(mode):
+            prev = dd.dd_set_burst_mode(mode)
+            try:
+                dd.dd_shutdown()   # nothing cached: the first call below builds tables (and captures)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                small_call()
+                torch.cuda.synchronize()
+                t_first = time.perf_counter() - t0
+                reps = 20
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    small_call()
+                torch.cuda.synchronize()
+                t_small = (time.perf_counter() - t0) / reps
+            finally:
+                dd.dd_set_burst_mode(prev)
+            return {"seconds_per_call": t_small, "us_per_step": t_small / 100 * 1e6,
+                    "first_call_seconds": t_first, "first_call_us_per_step": t_first / 100 * 1e6}
+
+        graph = small_timing(dd.BURST_GRAPH)
+        one_wg = small_timing(dd.BURST_PERSISTENT_ONE)
+        auto = small_timing(dd.BURST_AUTO)
+        return dict(
+            auto, segments=256, steps=100,
+            step_graph=dict(graph, note="the 100 steps as one cached graph of per-step kernels, relaunched; first "
+                                        "call: instance tables, work split, capture and instantiation"),
+            persistent_one_workgroup=dict(one_wg, note="all 100 steps in one persistent launch, one workgroup"),
+            persistent=dict(auto, workgroups=128, note="all 100 steps in one cooperative launch, 128 workgroups "
+                                                       "of 2 nodes each, one barrier per step (the default)"),
+            note="calls enqueued back to back and synchronised once")
+
+    if args.only == "small":
+        print(json.dumps(small_volume()))
         return
 
     inst = W.config1()
@@ -504,51 +558,7 @@ def main():
                             "plan": {"chunk_len": bands[3], "work_items": bands[4],
                                      "mixed_variant": bands[2]}}
         del vb
-        # the 256-segment volume: 100 FP64 glide steps captured in one graph launch
-        sb = W.pack([W.config0()])
-        ds = dict(x=torch.tensor(sb.x, device=dev), sn=torch.tensor(sb.seg_nodes, device=dev),
-                  b=torch.tensor(sb.burgers, device=dev), n=torch.tensor(sb.normal, device=dev),
-                  p=torch.tensor(sb.pinned, device=dev), s=torch.tensor(sb.sigma_app, device=dev),
-                  v=torch.tensor(sb.volume, device=dev))
-        xs = ds["x"].clone()
-        rs = torch.empty((1, 12), dtype=torch.float64, device=dev)
-
-        def small_call():
-            xs.copy_(ds["x"])   # the same start, in the same buffer: the cached graph applies
-            dd.dd_burst_batch(sb.node_off, sb.seg_off, xs, ds["sn"], ds["b"], ds["n"], ds["p"],
-                              ds["s"], ds["v"], mat, 2, dd.DD_FP64, 20.0, 100, W.DT, rate_avg_out=rs)
-
-        def small_timing(mode):
-            prev = dd.dd_set_burst_mode(mode)
-            try:
-                dd.dd_shutdown()   # nothing cached: the first call below builds tables (and captures)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                small_call()
-                torch.cuda.synchronize()
-                t_first = time.perf_counter() - t0
-                reps = 20
-                t0 = time.perf_counter()
-                for _ in range(reps):
-                    small_call()
-                torch.cuda.synchronize()
-                t_small = (time.perf_counter() - t0) / reps
-            finally:
-                dd.dd_set_burst_mode(prev)
-            return {"seconds_per_call": t_small, "us_per_step": t_small / 100 * 1e6,
-                    "first_call_seconds": t_first, "first_call_us_per_step": t_first / 100 * 1e6}
-
-        graph = small_timing(dd.BURST_GRAPH)
-        one_wg = small_timing(dd.BURST_PERSISTENT_ONE)
-        auto = small_timing(dd.BURST_AUTO)
-        extras["small_volume_100_steps_fp64"] = dict(
-            auto, segments=256, steps=100,
-            step_graph=dict(graph, note="the 100 steps as one cached graph of per-step kernels, relaunched; first "
-                                        "call: instance tables, work split, capture and instantiation"),
-            persistent_one_workgroup=dict(one_wg, note="all 100 steps in one persistent launch, one workgroup"),
-            persistent=dict(auto, workgroups=128, note="all 100 steps in one cooperative launch, 128 workgroups "
-                                                       "of 2 nodes each, one barrier per step (the default)"),
-            note="calls enqueued back to back and synchronised once")
+        extras["small_volume_100_steps_fp64"] = small_volume()
         out["extras"] = extras
 
     if (not args.no_extras and args.only is None) or args.only == "burst":
@@ -660,6 +670,25 @@ def main():
                            "converged_fraction": float(np.mean(res["conv_a"] & res["conv_b"])),
                            "rerun_chunks": int(np.sum(res["rerun_chunks"])),
                            "pairs_per_s": pair_steps / (t1 - t0)}
+        # the same step with junction nodes (the volumes with 16 slots each, as
+        # in the burst leg): topology and node state travel with the microstructure
+        xj = torch.tensor(bj.x, device=dev)
+        snj, buj, nrj = (torch.tensor(a, device=dev) for a in (bj.seg_nodes, bj.burgers, bj.normal))
+        stj = dd.junction_node_state(int(bj.node_off[-1]), int(bj.seg_off[-1]), bj.n_inst, dev)
+        J = {"state": stj, "fractions": jn_frac, "capture_radius": 10.0, "max_break_time": 50 * W.DT,
+             "min_length": 2.0, "n_slots": K_SLOTS, "fast_steps": np.zeros(bj.n_inst, np.int64)}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rj = dd.dd_pta_step_junction_nodes(bj.node_off, bj.seg_off, xj, snj, buj, nrj, dj["p"], dj["v"], rate,
+                                           np.full(bj.n_inst, 1e-7), P, mat, J, 2, dd.DD_MIXED, 20.0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pair_steps = int(np.sum((rj["steps_a"] + rj["steps_b"]) * Ns * (Ns - 1)))
+        out["pta_step"]["with_junction_nodes"] = {
+            "seconds": t1 - t0, "fast_steps": int(np.sum(rj["steps_a"] + rj["steps_b"])),
+            "converged_fraction": float(np.mean(rj["conv_a"] & rj["conv_b"])),
+            "junctions_formed": int(stj["count"].sum().item()), "pairs_per_s": pair_steps / (t1 - t0),
+            "pairs_note": "pairs of the volumes' own segments"}
 
     if not args.no_extras and args.only is None:
         # surrogate inference (row a9): 1,048,576 points, 4-member ensemble
