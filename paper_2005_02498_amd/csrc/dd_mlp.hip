@@ -58,6 +58,11 @@ struct GemmArgs {
     const float *bias; int64_t sbias; int nbias;
     const __bf16 *mask; int64_t ldmask, smask;
     __bf16 *out_h; float *out_f; int64_t ldo, so_h, so_f;
+    // split K (EPI_F32 only): nsp splits, blockIdx.z = split * members +
+    // member; split s covers k in [s kc, min(K, (s + 1) kc)) and writes its
+    // partial product at out_f + s ssplit.  kc is a multiple of BK; one
+    // split: kc >= K.
+    int kc, nsp; int64_t ssplit;
 };
 
 constexpr int BM = 64, BN = 64, BK = 32, LDSK = BK + 8;
@@ -81,7 +86,7 @@ __device__ __forceinline__ bf16x8 load8(const __bf16 *P, int64_t ld, int row, bo
 }
 
 template <bool TA, bool TB>
-__device__ __forceinline__ void stage(const GemmArgs &g, int member, int m0, int n0, int k0,
+__device__ __forceinline__ void stage(const GemmArgs &g, int member, int m0, int n0, int k0, int ke,
                                       __bf16 (*As)[LDSK], __bf16 (*Bs)[LDSK])
 {
     const int t = threadIdx.x;
@@ -89,23 +94,23 @@ __device__ __forceinline__ void stage(const GemmArgs &g, int member, int m0, int
     const __bf16 *B = g.B + member * g.sB;
     if (!TA) {   // row r, k offset 8 (t % 4): eight k of one row
         const int r = t / 4, kk = (t % 4) * 8, m = m0 + r;
-        const bf16x8 v = load8(A, g.lda, m, m < g.M, k0 + kk, g.K);
+        const bf16x8 v = load8(A, g.lda, m, m < g.M, k0 + kk, ke);
 #pragma unroll
         for (int i = 0; i < 8; ++i) As[r][kk + i] = v[i];
     } else {     // k row t / 8, m offset 8 (t % 8): eight m of one k row, stored transposed
         const int kr = t / 8, mm = (t % 8) * 8, k = k0 + kr;
-        const bf16x8 v = load8(A, g.lda, k, k < g.K, m0 + mm, g.M);
+        const bf16x8 v = load8(A, g.lda, k, k < ke, m0 + mm, g.M);
 #pragma unroll
         for (int i = 0; i < 8; ++i) As[mm + i][kr] = v[i];
     }
     if (!TB) {
         const int r = t / 4, kk = (t % 4) * 8, n = n0 + r;
-        const bf16x8 v = load8(B, g.ldb, n, n < g.N, k0 + kk, g.K);
+        const bf16x8 v = load8(B, g.ldb, n, n < g.N, k0 + kk, ke);
 #pragma unroll
         for (int i = 0; i < 8; ++i) Bs[r][kk + i] = v[i];
     } else {
         const int kr = t / 8, nn = (t % 8) * 8, k = k0 + kr;
-        const bf16x8 v = load8(B, g.ldb, k, k < g.K, n0 + nn, g.N);
+        const bf16x8 v = load8(B, g.ldb, k, k < ke, n0 + nn, g.N);
 #pragma unroll
         for (int i = 0; i < 8; ++i) Bs[nn + i][kr] = v[i];
     }
@@ -117,7 +122,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
     // rows of LDSK = 40 bf16 (80 bytes): every 16-byte fragment at k = 8 q is aligned
     __shared__ __attribute__((aligned(16))) __bf16 As[BM][LDSK];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][LDSK];
-    const int member = blockIdx.z;
+    const int members = (int)gridDim.z / g.nsp;
+    const int member = (int)blockIdx.z % members, split = (int)blockIdx.z / members;
+    const int kb = split * g.kc, ke = min(g.K, kb + g.kc);
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -126,9 +133,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
+    for (int k0 = kb; k0 < ke; k0 += BK) {
         __syncthreads();
-        stage<TA, TB>(g, member, m0, n0, k0, As, Bs);
+        stage<TA, TB>(g, member, m0, n0, k0, ke, As, Bs);
         __syncthreads();
         bf16x8 a[2], b[2];
         for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wm + 16 * i + lr][lk]);
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
                 } else if (EPI == EPI_BIAS_F32) {
                     g.out_f[member * g.so_f + o] = v + bias;
                 } else if (EPI == EPI_F32) {
-                    g.out_f[member * g.so_f + o] = v;
+                    g.out_f[split * g.ssplit + member * g.so_f + o] = v;
                 } else {
                     const float h = from_bf16(g.mask[member * g.smask + (int64_t)m * g.ldmask + n]);
                     const float d = h > 0.f ? v : 0.f;
@@ -167,11 +174,32 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g)
         }
 }
 
+// Returns the number of K splits launched (at most `splits`).
 template <bool TA, bool TB, int EPI>
-static void gemm(const GemmArgs &g, int members, hipStream_t st)
+static int gemm(const GemmArgs &g0, int members, hipStream_t st, int splits = 1)
 {
-    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, members);
+    GemmArgs g = g0;
+    g.kc = splits <= 1 ? std::max(g.K, 1) : (g.K + splits * BK - 1) / (splits * BK) * BK;
+    g.nsp = std::max(1, (g.K + g.kc - 1) / g.kc);
+    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, members * g.nsp);
     hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, st, g);
+    return g.nsp;
+}
+
+// K splits of a weight-gradient GEMM (K = batch rows) with `tiles` output
+// tiles per member: enough workgroups for two per compute unit of a 256-CU
+// device, at least four BK steps per split, at most KSPLIT_MAX splits.  A
+// function of the shapes alone, so the summation order does not depend on
+// the device.
+constexpr int KSPLIT_MAX = 32;
+// output tiles per member of the weight-gradient GEMMs: dW1 [256][64],
+// dW2 and dW3 [256][256], dW4 [16][256]
+constexpr int TILES_W1 = (HID / BM) * (INP / BN), TILES_W23 = (HID / BM) * (HID / BN), TILES_W4 = HID / BN;
+static int ksplit(int tiles, int members, int64_t K)
+{
+    const int64_t want = (512 + (int64_t)tiles * members - 1) / ((int64_t)tiles * members);
+    const int64_t most = std::max<int64_t>(1, K / (4 * BK));
+    return (int)std::max<int64_t>(1, std::min<int64_t>({want, most, (int64_t)KSPLIT_MAX}));
 }
 
 // ------------------------------------------------------- small kernels --
@@ -213,26 +241,33 @@ __global__ void k_standardize(const float *__restrict__ feat, int64_t n, const f
     X0[i] = to_bf16(v);
 }
 
-// Loss and output gradient, one workgroup per member:
+// Loss and output gradient on one block of LOSS_ROWS rows of one member:
 //   T'[r][o] = (target[r][o] - out_shift[o]) / out_scale[o]
 //   dY[r][o] = 2 (Y[r][o] - T'[r][o]) / (n 12) (0 in the padding columns)
-//   loss = mean over r, o of (Y - T')^2, summed in a fixed tree order.
+// in f32 and bf16, and the block's sum of (Y - T')^2 in fp64 into
+// lpart[member][block]; k_loss_fin turns the block sums into the mean.
+constexpr int LOSS_ROWS = 64;
 __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ Y, int64_t sY, const float *__restrict__ target,
                                               int64_t n, const float *__restrict__ scal, float *__restrict__ dYf,
-                                              __bf16 *__restrict__ dYh, int64_t sdY, float *loss_out)
+                                              __bf16 *__restrict__ dYh, int64_t sdY, double *__restrict__ lpart,
+                                              int64_t slp)
 {
     __shared__ double red[256];
-    const int member = blockIdx.x;
+    const int member = blockIdx.y;
     const float *Ym = Y + member * sY;
     double acc = 0.0;
     const float inv = 2.f / (float)(n * OUT);
-    for (int64_t i = threadIdx.x; i < n * OUTP; i += blockDim.x) {
+    const int64_t i0 = (int64_t)blockIdx.x * LOSS_ROWS * OUTP, i1 = min(i0 + LOSS_ROWS * OUTP, n * OUTP);
+#pragma unroll
+    for (int k = 0; k < LOSS_ROWS * OUTP / 256; ++k) {
+        const int64_t i = i0 + threadIdx.x + 256 * k;
+        if (i >= i1) break;
         const int64_t r = i / OUTP;
         const int o = (int)(i % OUTP);
         float d = 0.f;
         if (o < OUT) {
             const float tt = (target[r * OUT + o] - scal[2 * IN + o]) / scal[2 * IN + OUT + o];
-            const float e = Ym[r * OUTP + o] - tt;
+            const float e = Ym[i] - tt;
             acc += (double)e * e;
             d = inv * e;
         }
@@ -245,46 +280,108 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ Y, int64
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0 && loss_out) loss_out[member] = (float)(red[0] / (double)(n * OUT));
+    if (threadIdx.x == 0) lpart[member * slp + blockIdx.x] = red[0];
 }
 
-// Column sums (bias gradients): out[member][c] = sum_r G[member][r][c].
-// Workgroup = 64 columns x 4 row lanes of one member; each lane sums rows
-// r = lane_row, lane_row + 4, ... in order, then the 4 partials are added in
-// a fixed order.
-__global__ __launch_bounds__(256) void k_colsum(const float *__restrict__ G, int64_t sG, int64_t n, int ld,
-                                                int ncols, float *__restrict__ out, int64_t sout)
+// Per-member loss = (sum of the nb block sums) / (n OUT); lanes take blocks
+// lane, lane + 64, ... in order, then a fixed tree adds the 64 lanes.
+__global__ __launch_bounds__(64) void k_loss_fin(const double *__restrict__ lpart, int64_t slp, int nb, int64_t n,
+                                                 float *__restrict__ loss_out)
 {
-    __shared__ float part[4][64];
+    __shared__ double red[64];
+    const int member = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 64) s += lpart[member * slp + b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_out[member] = (float)(red[0] / (double)(n * OUT));
+}
+
+// Column sums (bias gradients): out[member][c] = sum_r G[member][r][c], in
+// two passes so that the whole device takes part.  k_colsum_part: workgroup
+// = 64 columns x 4 row lanes over one block of CS_ROWS rows; lane l adds rows
+// l, l + 4, ... of the block in order, the 4 lanes are added in a fixed order
+// into part[member][block][c].  k_colsum_fin then adds the blocks of each
+// column: lane l takes blocks l, l + 4, ... in order, again 4 lanes in a
+// fixed order.  The result depends on n only, not on the launch.
+constexpr int CS_ROWS = 64;
+__global__ __launch_bounds__(256) void k_colsum_part(const float *__restrict__ G, int64_t sG, int64_t n, int ld,
+                                                     int ncols, float *__restrict__ part, int64_t spm)
+{
+    __shared__ float p4[4][64];
     const int member = blockIdx.y;
     const int c = blockIdx.x * 64 + (threadIdx.x & 63), rl = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.z * CS_ROWS;
     const float *g = G + member * sG;
     float s = 0.f;
-    if (c < ncols)
-        for (int64_t r = rl; r < n; r += 4) s += g[r * ld + c];
-    part[rl][threadIdx.x & 63] = s;
+    if (c < ncols) {
+        float v[CS_ROWS / 4];
+#pragma unroll
+        for (int k = 0; k < CS_ROWS / 4; ++k) {
+            const int64_t r = r0 + rl + 4 * k;
+            v[k] = r < n ? g[r * ld + c] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < CS_ROWS / 4; ++k) s += v[k];
+    }
+    p4[rl][threadIdx.x & 63] = s;
     __syncthreads();
     if (rl == 0 && c < ncols)
-        out[member * sout + c] = ((part[0][threadIdx.x] + part[1][threadIdx.x]) + part[2][threadIdx.x]) +
-                                 part[3][threadIdx.x];
+        part[member * spm + blockIdx.z * (int64_t)ncols + c] =
+            ((p4[0][threadIdx.x] + p4[1][threadIdx.x]) + p4[2][threadIdx.x]) + p4[3][threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_colsum_fin(const float *__restrict__ part, int64_t spm, int nb, int ncols,
+                                                    float *__restrict__ out, int64_t sout)
+{
+    __shared__ float p4[4][64];
+    const int member = blockIdx.y;
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63), rl = threadIdx.x >> 6;
+    const float *p = part + member * spm;
+    float s = 0.f;
+    if (c < ncols)
+        for (int b = rl; b < nb; b += 4) s += p[(int64_t)b * ncols + c];
+    p4[rl][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (rl == 0 && c < ncols)
+        out[member * sout + c] = ((p4[0][threadIdx.x] + p4[1][threadIdx.x]) + p4[2][threadIdx.x]) +
+                                 p4[3][threadIdx.x];
 }
 
 // Adam on the flat master parameters; gradients are read from the padded
 // GEMM layouts (dW1 [256][64], dW4 [16][256], biases).
+// A weight gradient is the sum of its K-split partial products, added in
+// split order.
 struct GradPtrs {
     const float *dW1, *dW2, *dW3, *dW4, *db1, *db2, *db3, *db4;
     int64_t s1, s2, s3, s4, sb;   // member strides
+    int k1, k2, k3, k4;           // K splits of dW1 .. dW4
+    int64_t ss1, ss2, ss3, ss4;   // split strides
 };
+
+__device__ __forceinline__ float split_sum(const float *q, int k, int64_t ss)
+{
+    float v = q[0];
+    for (int s = 1; s < k; ++s) v += q[s * ss];
+    return v;
+}
 
 __device__ __forceinline__ float grad_at(const GradPtrs &G, int member, int64_t p)
 {
-    if (p < OB1) { int64_t o = p / IN, i = p % IN; return G.dW1[member * G.s1 + o * INP + i]; }
+    if (p < OB1) {
+        const int64_t o = p / IN, i = p % IN;
+        return split_sum(G.dW1 + member * G.s1 + o * INP + i, G.k1, G.ss1);
+    }
     if (p < OW2) return G.db1[member * G.sb + (p - OB1)];
-    if (p < OB2) return G.dW2[member * G.s2 + (p - OW2)];
+    if (p < OB2) return split_sum(G.dW2 + member * G.s2 + (p - OW2), G.k2, G.ss2);
     if (p < OW3) return G.db2[member * G.sb + (p - OB2)];
-    if (p < OB3) return G.dW3[member * G.s3 + (p - OW3)];
+    if (p < OB3) return split_sum(G.dW3 + member * G.s3 + (p - OW3), G.k3, G.ss3);
     if (p < OW4) return G.db3[member * G.sb + (p - OB3)];
-    if (p < OB4) return G.dW4[member * G.s4 + (p - OW4)];
+    if (p < OB4) return split_sum(G.dW4 + member * G.s4 + (p - OW4), G.k4, G.ss4);
     return G.db4[member * G.sb + (p - OB4)];
 }
 
@@ -878,6 +975,7 @@ struct dd_mlp {
     float *scal = nullptr;                                // device [2*36 + 2*12]
     float h_scal[SCAL];                                   // host copy
     float *dW1 = nullptr, *dW2 = nullptr, *dW3 = nullptr, *dW4 = nullptr, *db = nullptr;
+    int ks[4] = {1, 1, 1, 1};                             // K splits of dW1 .. dW4 in the last backward
     // row workspace, sized for `cap` rows
     int64_t cap = 0;
     bool cap_train = false;
@@ -885,6 +983,8 @@ struct dd_mlp {
     __bf16 *Dh[2] = {nullptr, nullptr};
     float *Y = nullptr, *dYf = nullptr;
     float *Df[2] = {nullptr, nullptr};
+    float *part = nullptr;                                // column-sum block partials
+    double *lpart = nullptr;                              // loss block partials
 };
 
 namespace {
@@ -894,11 +994,13 @@ constexpr int64_t TRAIN_MAX = 65536;
 
 void free_rows(dd_mlp *h)
 {
-    void *ps[] = {h->X0, h->H1, h->H2, h->H3, h->dYh, h->Dh[0], h->Dh[1], h->Y, h->dYf, h->Df[0], h->Df[1]};
+    void *ps[] = {h->X0, h->H1, h->H2, h->H3, h->dYh, h->Dh[0], h->Dh[1], h->Y, h->dYf, h->Df[0], h->Df[1],
+                  h->part, h->lpart};
     for (void *p : ps)
         if (p) (void)hipFree(p);
     h->X0 = h->H1 = h->H2 = h->H3 = h->dYh = h->Dh[0] = h->Dh[1] = nullptr;
-    h->Y = h->dYf = h->Df[0] = h->Df[1] = nullptr;
+    h->Y = h->dYf = h->Df[0] = h->Df[1] = h->part = nullptr;
+    h->lpart = nullptr;
     h->cap = 0;
     h->cap_train = false;
 }
@@ -934,6 +1036,9 @@ int ensure_rows(dd_mlp *h, int64_t rows, bool training)
             if ((rc = dev_alloc((void **)&h->Dh[k], sizeof(__bf16) * M * rows * HID))) return rc;
             if ((rc = dev_alloc((void **)&h->Df[k], sizeof(float) * M * rows * HID))) return rc;
         }
+        const int64_t nb = (rows + CS_ROWS - 1) / CS_ROWS, nbl = (rows + LOSS_ROWS - 1) / LOSS_ROWS;
+        if ((rc = dev_alloc((void **)&h->part, sizeof(float) * M * nb * HID))) return rc;
+        if ((rc = dev_alloc((void **)&h->lpart, sizeof(double) * M * nbl))) return rc;
     }
     h->cap = rows;
     h->cap_train = train;
@@ -1011,12 +1116,20 @@ GradPtrs grad_ptrs(const dd_mlp *h)
     G.db1 = h->db; G.db2 = h->db + HID; G.db3 = h->db + 2 * HID; G.db4 = h->db + 3 * HID;
     G.s1 = (int64_t)HID * INP; G.s2 = G.s3 = (int64_t)HID * HID; G.s4 = (int64_t)OUTP * HID;
     G.sb = 4 * HID;
+    G.k1 = h->ks[0]; G.k2 = h->ks[1]; G.k3 = h->ks[2]; G.k4 = h->ks[3];
+    G.ss1 = h->members * G.s1; G.ss2 = h->members * G.s2; G.ss3 = h->members * G.s3; G.ss4 = h->members * G.s4;
     return G;
 }
 
-void colsum(const float *G, int64_t sG, int64_t n, int ld, int ncols, float *out, int members, hipStream_t st)
+// Two passes; part holds members x ceil(n / CS_ROWS) x ncols floats.
+void colsum(const float *G, int64_t sG, int64_t n, int ld, int ncols, float *out, int members, float *part,
+            hipStream_t st)
 {
-    hipLaunchKernelGGL(k_colsum, dim3((ncols + 63) / 64, members), dim3(256), 0, st, G, sG, n, ld, ncols, out,
+    const int nb = (int)((n + CS_ROWS - 1) / CS_ROWS);
+    const int64_t spm = (int64_t)nb * ncols;
+    hipLaunchKernelGGL(k_colsum_part, dim3((ncols + 63) / 64, members, nb), dim3(256), 0, st, G, sG, n, ld, ncols,
+                       part, spm);
+    hipLaunchKernelGGL(k_colsum_fin, dim3((ncols + 63) / 64, members), dim3(256), 0, st, part, spm, nb, ncols, out,
                        (int64_t)4 * HID);
 }
 
@@ -1030,16 +1143,19 @@ int gradients(dd_mlp *h, int64_t n, const float *feat, const float *target, floa
     hipLaunchKernelGGL(k_standardize, dim3((unsigned)((n * INP + 255) / 256)), dim3(256), 0, st, feat, n,
                        h->scal, h->X0);
     forward(h, n, st);
-    hipLaunchKernelGGL(k_loss, dim3(M), dim3(256), 0, st, h->Y, n * OUTP, target, n, h->scal, h->dYf, h->dYh,
-                       n * OUTP, loss_out);
+    const int nbl = (int)((n + LOSS_ROWS - 1) / LOSS_ROWS);
+    hipLaunchKernelGGL(k_loss, dim3(nbl, M), dim3(256), 0, st, h->Y, n * OUTP, target, n, h->scal, h->dYf,
+                       h->dYh, n * OUTP, h->lpart, (int64_t)nbl);
+    if (loss_out)
+        hipLaunchKernelGGL(k_loss_fin, dim3(M), dim3(64), 0, st, h->lpart, (int64_t)nbl, nbl, n, loss_out);
     GemmArgs g{};
     // output layer: dW4 [16][256] = dY^T H3, db4 = colsum(dY)
     g.A = h->dYh; g.lda = OUTP; g.sA = n * OUTP;
     g.B = h->H3; g.ldb = HID; g.sB = n * HID;
     g.M = OUTP; g.N = HID; g.K = (int)n;
-    g.out_f = h->dW4; g.ldo = HID; g.so_f = (int64_t)OUTP * HID;
-    gemm<true, true, EPI_F32>(g, M, st);
-    colsum(h->dYf, n * OUTP, n, OUTP, OUTP, h->db + 3 * HID, M, st);
+    g.out_f = h->dW4; g.ldo = HID; g.so_f = (int64_t)OUTP * HID; g.ssplit = M * g.so_f;
+    h->ks[3] = gemm<true, true, EPI_F32>(g, M, st, ksplit(TILES_W4, M, n));
+    colsum(h->dYf, n * OUTP, n, OUTP, OUTP, h->db + 3 * HID, M, h->part, st);
     // dZ3 = (dY W4p) * (H3 > 0)  -> buffer 0
     g = GemmArgs{};
     g.A = h->dYh; g.lda = OUTP; g.sA = n * OUTP;
@@ -1060,9 +1176,9 @@ int gradients(dd_mlp *h, int64_t n, const float *feat, const float *target, floa
         g.A = h->Dh[cur]; g.lda = HID; g.sA = n * HID;
         g.B = Hprev[l]; g.ldb = HID; g.sB = n * HID;
         g.M = HID; g.N = HID; g.K = (int)n;
-        g.out_f = dWs[l]; g.ldo = HID; g.so_f = (int64_t)HID * HID;
-        gemm<true, true, EPI_F32>(g, M, st);
-        colsum(h->Df[cur], n * HID, n, HID, HID, h->db + dbo[l], M, st);
+        g.out_f = dWs[l]; g.ldo = HID; g.so_f = (int64_t)HID * HID; g.ssplit = M * g.so_f;
+        h->ks[2 - l] = gemm<true, true, EPI_F32>(g, M, st, ksplit(TILES_W23, M, n));
+        colsum(h->Df[cur], n * HID, n, HID, HID, h->db + dbo[l], M, h->part, st);
         g = GemmArgs{};
         g.A = h->Dh[cur]; g.lda = HID; g.sA = n * HID;
         g.B = Ws[l]; g.ldb = HID; g.sB = (int64_t)HID * HID;   // B(n = i, k = o) = W[o][i]
@@ -1077,9 +1193,9 @@ int gradients(dd_mlp *h, int64_t n, const float *feat, const float *target, floa
     g.A = h->Dh[cur]; g.lda = HID; g.sA = n * HID;
     g.B = h->X0; g.ldb = INP; g.sB = 0;
     g.M = HID; g.N = INP; g.K = (int)n;
-    g.out_f = h->dW1; g.ldo = INP; g.so_f = (int64_t)HID * INP;
-    gemm<true, true, EPI_F32>(g, M, st);
-    colsum(h->Df[cur], n * HID, n, HID, HID, h->db, M, st);
+    g.out_f = h->dW1; g.ldo = INP; g.so_f = (int64_t)HID * INP; g.ssplit = M * g.so_f;
+    h->ks[0] = gemm<true, true, EPI_F32>(g, M, st, ksplit(TILES_W1, M, n));
+    colsum(h->Df[cur], n * HID, n, HID, HID, h->db, M, h->part, st);
     DD_HIP(hipGetLastError());
     return DD_OK;
 }
@@ -1117,10 +1233,13 @@ extern "C" int dd_mlp_create(int n_members, uint64_t seed, dd_mlp **out)
     if (!rc) rc = dev_alloc((void **)&h->W4p, sizeof(__bf16) * M * OUTP * HID);
     if (!rc) rc = dev_alloc((void **)&h->Wi, sizeof(__bf16) * M * WI_PER);
     if (!rc) rc = dev_alloc((void **)&h->scal, sizeof(float) * SCAL);
-    if (!rc) rc = dev_alloc((void **)&h->dW1, sizeof(float) * M * HID * INP);
-    if (!rc) rc = dev_alloc((void **)&h->dW2, sizeof(float) * M * HID * HID);
-    if (!rc) rc = dev_alloc((void **)&h->dW3, sizeof(float) * M * HID * HID);
-    if (!rc) rc = dev_alloc((void **)&h->dW4, sizeof(float) * M * OUTP * HID);
+    // weight gradients hold one partial product per K split
+    const int64_t k1 = ksplit(TILES_W1, n_members, TRAIN_MAX), k23 = ksplit(TILES_W23, n_members, TRAIN_MAX),
+                  k4 = ksplit(TILES_W4, n_members, TRAIN_MAX);
+    if (!rc) rc = dev_alloc((void **)&h->dW1, sizeof(float) * k1 * M * HID * INP);
+    if (!rc) rc = dev_alloc((void **)&h->dW2, sizeof(float) * k23 * M * HID * HID);
+    if (!rc) rc = dev_alloc((void **)&h->dW3, sizeof(float) * k23 * M * HID * HID);
+    if (!rc) rc = dev_alloc((void **)&h->dW4, sizeof(float) * k4 * M * OUTP * HID);
     if (!rc) rc = dev_alloc((void **)&h->db, sizeof(float) * M * 4 * HID);
     if (rc) {
         dd_mlp_destroy(h);

@@ -121,7 +121,9 @@ def test_forward_parity(n):
     assert nrel(r, ro64) < TOL
 
 
-@pytest.mark.parametrize("n", [1, 37, 1024])
+# 1000 and 4133 rows: the weight-gradient products are split along the
+# batch into 7 and up to 26 pieces of unequal length
+@pytest.mark.parametrize("n", [1, 37, 1000, 1024, 4133])
 def test_gradient_parity(n):
     mdl, params, sc = _model()
     rng = np.random.default_rng(n)
