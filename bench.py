@@ -476,9 +476,11 @@ def main():
 
     if args.only in ("fp64", "mixed"):
         prec = dd.DD_FP64 if args.only == "fp64" else dd.DD_MIXED
-        s, k, _ = run(prec, 2, args.steps, args.warmup, eta=args.exact_band)
+        s, k, b = run(prec, 2, args.steps, args.warmup, eta=args.exact_band)
         print(json.dumps({"part": args.only, "exact_band": args.exact_band, "ms_per_step": s * 1e3,
-                          "kernel_ms": k * 1e3}))
+                          "kernel_ms": k * 1e3, "near_fp64_evals_per_launch": b[0],
+                          "quad_fp32_evals_per_launch": b[1],
+                          "plan": {"chunk_len": b[3], "work_items": b[4], "mixed_variant": b[2]}}))
         return
 
     out = {}
