@@ -128,6 +128,10 @@ def parse():
     ap.add_argument("--no-live-study", action="store_true",
                     help="skip the reduced surrogate study of the default run")
     ap.add_argument("--study-out", default=os.path.join(ROOT, "study", "surrogate_study.json"))
+    ap.add_argument("--surrogate-noise", action="store_true",
+                    help="only the single-burst scatter of 64 held-out states x 8 microstructures against "
+                         "the burst length (200, 600, 2000 steps), written to --noise-out")
+    ap.add_argument("--noise-out", default=os.path.join(ROOT, "study", "surrogate_noise_vs_burst_length.json"))
     return ap.parse_args()
 
 
@@ -152,6 +156,22 @@ def surrogate_study(args):
     with open(args.study_out, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps({"study": args.study_out, "seconds": res["total_seconds"]}))
+
+def surrogate_noise(args):
+    """noise_vs_length of paper_2005_02498_amd/surrogate_study.py, written to --noise-out."""
+    from paper_2005_02498_amd import surrogate_study as S
+    import paper_2005_02498_amd as dd
+    dd.dd_set_validation(False)
+    t0 = time.perf_counter()
+    res = S.noise_vs_length(64, 8, (200, 600, 2000),
+                            log=lambda m: print(f"[{time.perf_counter() - t0:7.1f}s] {m}", file=sys.stderr,
+                                                flush=True))
+    res["command"] = "python bench.py --surrogate-noise"
+    os.makedirs(os.path.dirname(args.noise_out), exist_ok=True)
+    with open(args.noise_out, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps({"noise": args.noise_out, "rows": res["rows"]}))
+
 
 def cpu_baseline(args, inst):
     """The FP64 C oracle, as it stands, on the host CPU of this machine: the
@@ -258,6 +278,9 @@ def main():
     args = parse()
     if args.surrogate_study:
         surrogate_study(args)
+        return
+    if args.surrogate_noise:
+        surrogate_noise(args)
         return
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "

@@ -50,10 +50,11 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def burst_data(states, seeds, state_base, micro_base, log=None):
-    """One 200-step mixed-precision burst per (state, microstructure):
-    features X [states][seeds][36] and rates Y [states][seeds][12] (float64),
-    the seconds spent in the burst calls and the number of bursts."""
+def burst_data(states, seeds, state_base, micro_base, log=None, n_steps=N_STEPS):
+    """One mixed-precision burst of n_steps glide steps per (state,
+    microstructure): features X [states][seeds][36] and rates Y
+    [states][seeds][12] (float64), the seconds spent in the burst calls and
+    the number of bursts."""
     import torch
 
     import paper_2005_02498_amd as dd
@@ -73,7 +74,7 @@ def burst_data(states, seeds, state_base, micro_base, log=None):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r, f = dd.dd_burst_batch(bt.node_off, bt.seg_off, d["x"], d["sn"], d["b"], d["n"], d["p"], d["s"], d["v"],
-                                 mat, 2, dd.DD_MIXED, 20.0, N_STEPS, W.DT, want_features=True)
+                                 mat, 2, dd.DD_MIXED, 20.0, n_steps, W.DT, want_features=True)
         torch.cuda.synchronize()
         sec += time.perf_counter() - t0
         X.append(f.cpu().numpy())
@@ -83,6 +84,28 @@ def burst_data(states, seeds, state_base, micro_base, log=None):
     X = np.concatenate(X).reshape(states, seeds, 36)
     Y = np.concatenate(Y).reshape(states, seeds, 12)
     return X, Y, sec, len(pairs)
+
+
+def noise_vs_length(states, seeds, lengths, log=None):
+    """The single-burst scatter E1 against the burst length: the same
+    held-out states and microstructures, run for each number of glide steps
+    in `lengths`.  A scatter that comes from the finite time average falls
+    as the bursts get longer; one that comes from the microstructures (the
+    spread of the time averages of different microstructures of one state)
+    does not."""
+    rows = []
+    for n in lengths:
+        _, Y, sec, nb = burst_data(states, seeds, STATE_BASE_HELD, MICRO_BASE_HELD, log, n_steps=n)
+        Rbar = Y.mean(1)
+        _, E1 = state_errors(Rbar, Y)
+        rel = np.sqrt(Y.var(1, ddof=1).sum(1)) / np.maximum(np.linalg.norm(Rbar, axis=1), 1e-300)
+        rows.append({"steps": n, "error_single_burst": E1, "median_state_scatter": float(np.median(rel)),
+                     "mean_state_rate_norm": float(np.mean(np.linalg.norm(Rbar, axis=1))),
+                     "bursts": nb, "seconds": sec})
+        if log:
+            log(f"{n} steps: E1 = {E1:.3f}")
+    return {"study": "single-burst scatter against burst length", "states": states,
+            "microstructures_per_state": seeds, "rows": rows}
 
 
 def train(X, Y, epochs, members=4, seed=12345, log=None):
