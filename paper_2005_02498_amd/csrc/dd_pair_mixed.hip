@@ -67,8 +67,10 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
     const float fkr = (float)kr, fnu = (float)nu, cut2 = cut * cut;
     // constants of the FP32 arithmetic in vector registers (the empty asm keeps
     // them there): an FP32 instruction with a literal operand issues at half rate
-    float three = 3.0f, ck2 = COLLINEAR_K2, ck21 = 1.0f + COLLINEAR_K2;
-    asm volatile("" : "+v"(three), "+v"(ck2), "+v"(ck21));
+    // kap = K^2 / (1 + K^2): the collinear test ym^2 (1 + K^2) <= K^2 (ee + 1)
+    // as ym^2 <= kap (ee + 1), one instruction fewer
+    float three = 3.0f, ck2 = COLLINEAR_K2, kap = COLLINEAR_K2 / (1.0f + COLLINEAR_K2);
+    asm volatile("" : "+v"(three), "+v"(ck2), "+v"(kap));
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     unsigned n_near = 0, n_quad_src = 0;
     if (lane == 0) {
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
                 // against exec, in scalar registers (a ballot of their
                 // conjunction would select and re-compare per lane)
                 const uint64_t quad = __builtin_amdgcn_ballot_w64(ee >= r[R32_BAND]) &
-                                      __builtin_amdgcn_ballot_w64(ym2 * ck21 <= fmaf(ck2, ee, ck2));
+                                      __builtin_amdgcn_ballot_w64(ym2 <= fmaf(kap, ee, kap));
                 if (quad == __builtin_amdgcn_read_exec()) {
                     ++n_quad_src;
                     if (QN == 2)
@@ -161,7 +163,11 @@ __global__ __launch_bounds__(TILE) void k_pair_mixed(const Item *__restrict__ it
             // FP64: near pairs, and nearly collinear ones (rho carries an absolute
             // error of order |ym| eps32 in FP32)
             if (hh + ya * ya < cut2 || ym2 > fmaf(ck2, hh, ck2)) {
-                if (k != self) {
+                // k through an empty asm: the comparison stays in this branch
+                // instead of becoming a per-lane counter stepped every source
+                int ks = k;
+                asm volatile("" : "+s"(ks));
+                if (ks != self) {
                     n_near += valid ? 1u : 0u;
                     pair_acc_isolated_f64(xq0, xq1, xq2, bj0, bj1, bj2, ra + (base + k) * RECA, kr, nu, a0, a1, a2);
                 }
