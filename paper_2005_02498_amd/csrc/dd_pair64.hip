@@ -31,7 +31,23 @@ __device__ __forceinline__ void pair64_range(const double *__restrict__ ra, int6
         const double R0 = xq0 - c[0], R1 = xq1 - c[1], R2 = xq2 - c[2];
         double r1 = rsqrt64(fma(R2, R2, fma(R1, R1, fma(R0, R0, 1.0))));
         double r1c = r1 * r1 * r1;
-        for (int k = 0; k < n; ++k, c += RECA) {
+        int k = 0;
+        if (!SELF) {
+            // two sources per iteration: the second takes the first's far-end
+            // values and leaves its own where the first's near-end values were,
+            // so no register copy is made per source
+            for (; k + 2 <= n; k += 2, c += 2 * RECA) {
+                double r2, r2c;
+                pair_acc_f64(xq0, xq1, xq2, bj0, bj1, bj2, c[0], c[1], c[2], c[3], c[4], c[5], c[6],
+                             c[7], c[8], c[9], c[10], c[11], c[12], kr, nu, r1, r1c, r2, r2c, a0, a1,
+                             a2, ak);
+                const double *d = c + RECA;
+                pair_acc_f64(xq0, xq1, xq2, bj0, bj1, bj2, d[0], d[1], d[2], d[3], d[4], d[5], d[6],
+                             d[7], d[8], d[9], d[10], d[11], d[12], kr, nu, r2, r2c, r1, r1c, a0, a1,
+                             a2, ak);
+            }
+        }
+        for (; k < n; ++k, c += RECA) {
             double r2, r2c;
             if (SELF) {
                 double n0 = a0, n1 = a1, n2 = a2, nk = ak;
