@@ -45,9 +45,12 @@ struct BlockGeom {
 // Mean of the block's m^2 * 8 Gauss-point values (equal Gauss weights on the
 // uniform affine mesh), one workgroup per block.  The block's values lie in m
 // contiguous runs (one per row of elements) of m * 8 * c doubles; thread t
-// reads entries t, t + S, t + 2S, ... of each run, S = c * floor(256 / c), so
-// it always holds component t % c (reads are coalesced).  The per-thread
-// sums are then added per component in thread order.
+// reads entries q = t, t + S, t + 2S, ... of every run, S = c * floor(256 / c),
+// so it always holds component t % c (reads are coalesced).  For each q the
+// runs are read eight at a time into eight partial sums (run ly into sum
+// ly % 8, the last m % 8 runs into sum 0), so that eight loads are in flight;
+// the eight sums are added in order, then the per-thread sums per component
+// in thread order.
 __global__ __launch_bounds__(256) void k_block_average(BlockGeom G, const double *__restrict__ f,
                                                        double *__restrict__ out)
 {
@@ -56,13 +59,21 @@ __global__ __launch_bounds__(256) void k_block_average(BlockGeom G, const double
     const int64_t bx = r % G.n, by = r / G.n;
     const int t = threadIdx.x;
     const int S = G.c * (256 / G.c);
-    const int64_t run = G.m * 8 * G.c;
     double acc = 0.0;
     if (t < S) {
-        for (int64_t ly = 0; ly < G.m; ++ly) {
-            const double *src = f + ((by * G.m + ly) * G.ne + bx * G.m) * 8 * G.c;
-            for (int64_t q = t; q < run; q += S) acc += src[q];
+        const int m = (int)G.m, run = (int)(G.m * 8 * G.c);
+        const int64_t rs = G.ne * 8 * G.c;   // doubles from one run (element row) to the next
+        const double *src = f + (by * G.m * G.ne + bx * G.m) * 8 * G.c;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int q = t; q < run; q += S) {
+            int ly = 0;
+            for (; ly + 8 <= m; ly += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] += src[(int64_t)(ly + u) * rs + q];
+            }
+            for (; ly < m; ++ly) a[0] += src[(int64_t)ly * rs + q];
         }
+        acc = ((((((a[0] + a[1]) + a[2]) + a[3]) + a[4]) + a[5]) + a[6]) + a[7];
     }
     sh[t] = acc;
     __syncthreads();
@@ -129,29 +140,40 @@ __global__ void k_block_tridiag(int64_t lines, int64_t N, int64_t c, int64_t alo
 // compose to the block's shape functions at the Gauss point's block
 // coordinates, which is what is evaluated here (4 weights instead of 16).
 // The block field does not depend on z, so the z factors drop out.  One
-// thread per output value (Gauss point, component), so that writes are
-// coalesced; blockIdx.y is the element row.
-__global__ void k_block_interp(BlockGeom G, const double *__restrict__ A, double *__restrict__ out)
+// thread per Gauss point of an element row (blockIdx.y): its four weights
+// once, then its CT components (CT = 0: G.c of them) into LDS, from where
+// the workgroup writes its 256 points' values as one contiguous run.  im =
+// 1/m, formed once on the host.
+template <int CT>
+__global__ __launch_bounds__(256) void k_block_interp(BlockGeom G, const double *__restrict__ A,
+                                                      double *__restrict__ out, double im)
 {
-    const int N = (int)G.n + 1, c = G.c, m = (int)G.m;
-    const int row_len = (int)G.ne * 8 * c;
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= row_len) return;
-    const int ey = blockIdx.y;
-    const int k = o % c, p = o / c;
-    const int ex = p >> 3, g = p & 7;
-    const int bx = ex / m, by = ey / m;
-    const double xg = (2 * (g & 1) - 1) * ISO_GP, yg = (2 * ((g >> 1) & 1) - 1) * ISO_GP;
-    // the Gauss point in its block's isoparametric coordinates
-    const double im = 1.0 / (double)m;
-    const double xb = -1.0 + ((double)(2 * (ex - bx * m) + 1) + xg) * im;
-    const double yb = -1.0 + ((double)(2 * (ey - by * m) + 1) + yg) * im;
-    // block-mesh nodes: (n + 1)^2 c values can pass 2^31, so these indices are 64-bit
-    const int64_t q0 = ((int64_t)by * N + bx) * c + k, q1 = q0 + (int64_t)N * c;
-    const double a00 = A[q0], a10 = A[q0 + c];
-    const double a01 = A[q1], a11 = A[q1 + c];
-    out[(int64_t)ey * row_len + o] = 0.25 * ((1.0 - xb) * (1.0 - yb) * a00 + (1.0 + xb) * (1.0 - yb) * a10 +
-                                             (1.0 - xb) * (1.0 + yb) * a01 + (1.0 + xb) * (1.0 + yb) * a11);
+    __shared__ double sh[256 * (CT ? CT : MAX_COMP)];
+    const int C = CT ? CT : G.c;
+    const int N = (int)G.n + 1, m = (int)G.m;
+    const int row_gp = (int)G.ne * 8;
+    const int p0 = blockIdx.x * 256, p = p0 + (int)threadIdx.x;
+    const int ey = blockIdx.y, by = ey / m;
+    if (p < row_gp) {
+        const int ex = p >> 3, g = p & 7;
+        const int bx = ex / m;
+        const double xg = (2 * (g & 1) - 1) * ISO_GP, yg = (2 * ((g >> 1) & 1) - 1) * ISO_GP;
+        // the Gauss point in its block's isoparametric coordinates
+        const double xb = -1.0 + ((double)(2 * (ex - bx * m) + 1) + xg) * im;
+        const double yb = -1.0 + ((double)(2 * (ey - by * m) + 1) + yg) * im;
+        const double f00 = (1.0 - xb) * (1.0 - yb), f10 = (1.0 + xb) * (1.0 - yb);
+        const double f01 = (1.0 - xb) * (1.0 + yb), f11 = (1.0 + xb) * (1.0 + yb);
+        // block-mesh nodes: (n + 1)^2 c values can pass 2^31, so these indices are 64-bit
+        const int64_t q0 = ((int64_t)by * N + bx) * C, q1 = q0 + (int64_t)N * C;
+#pragma unroll
+        for (int k = 0; k < C; ++k)
+            sh[threadIdx.x * C + k] =
+                0.25 * (f00 * A[q0 + k] + f10 * A[q0 + C + k] + f01 * A[q1 + k] + f11 * A[q1 + C + k]);
+    }
+    __syncthreads();
+    const int nv = min(256, row_gp - p0) * C;
+    double *o = out + ((int64_t)ey * row_gp + p0) * C;
+    for (int i = threadIdx.x; i < nv; i += 256) o[i] = sh[i];
 }
 
 // Eq. Lp_gauss: if d = T : Lp < 0, Lp <- Lp - d T / |T|^2.  Eq. V_gauss: with
@@ -272,9 +294,14 @@ extern "C" int dd_block_to_gauss(const dd_block_mesh *mesh, int c, const double 
                        (int64_t)c, (int64_t)0, (const double *)rden, scale, A, tmp);
     hipLaunchKernelGGL(k_block_tridiag, dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, st, lines, N,
                        (int64_t)c, (int64_t)1, (const double *)rden, scale, A, tmp);
-    const int64_t row_len = G.ne * 8 * c;
-    hipLaunchKernelGGL(k_block_interp, dim3((unsigned)((row_len + 255) / 256), (unsigned)G.ne), dim3(256), 0, st, G,
-                       (const double *)A, f_gp);
+    const dim3 grid((unsigned)((G.ne * 8 + 255) / 256), (unsigned)G.ne);
+    const double im = 1.0 / (double)G.m;
+    if (c == 9)
+        hipLaunchKernelGGL(k_block_interp<9>, grid, dim3(256), 0, st, G, (const double *)A, f_gp, im);
+    else if (c == 3)
+        hipLaunchKernelGGL(k_block_interp<3>, grid, dim3(256), 0, st, G, (const double *)A, f_gp, im);
+    else
+        hipLaunchKernelGGL(k_block_interp<0>, grid, dim3(256), 0, st, G, (const double *)A, f_gp, im);
     DD_HIP(hipGetLastError());
     if (validation_on()) DD_HIP(hipStreamSynchronize(st));
     return DD_OK;
