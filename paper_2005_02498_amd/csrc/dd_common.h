@@ -115,6 +115,7 @@ struct Workspace {
     unsigned *flags_dev = nullptr;   // one word (sticky: cleared only when reported)
     unsigned *flags_host = nullptr;  // pinned mirror (bytes 64..71: near-pair count read-back)
     hipStream_t capture_stream = nullptr;
+    hipEvent_t near_ev = nullptr;    // marks the near-pair count's read-back on the caller's stream
     int64_t block_fac_n = -1;                    // size of the tridiagonal factors in WS_BLOCK_FAC
     unsigned long long *near_count = nullptr;   // device counter (mixed kernel)
     bool capturing = false;

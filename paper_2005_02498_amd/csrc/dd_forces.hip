@@ -1789,22 +1789,28 @@ int launch_forces(ForceCtx &C, Workspace *ws, const double *x, const int32_t *se
         A.sys = C.sys;
         A.flags = ws->flags_dev;
         hipLaunchKernelGGL(k_seg_prep, dim3(grid_for(ns, PREP_BLOCK, INT32_MAX)), dim3(PREP_BLOCK), 0, st, A);
+        // The near-pair work needs only the records and runs on the same
+        // stream as the pair kernel (alongside it, on a second stream, it
+        // slowed the pair kernel by more than its own duration): the count
+        // pass before the pair kernel, the list and the exact integrals after
+        // it.  With size_pairs the count is read back behind the pair kernel:
+        // the host waits for the count (an event), not for the pair kernel, and
+        // sizes the pair store before the list is written.
+        NearArgs N = C.near;
+        int64_t *count_host = nullptr;
         if (C.near_on) {
-            // the near-pair work needs only the records; it runs before the
-            // pair kernel on the same stream (alongside it, it slowed the pair
-            // kernel by more than its own duration)
-            if (size_pairs) {
-                const int rc = size_near_pairs(C, ws, x, seg_nodes, 1.0, 0, st);
-                if (rc) return rc;
-            }
-            NearArgs N = C.near;
             N.x = x;
             N.seg_nodes = seg_nodes;
             N.seg_inst = C.L.seg_inst;
             N.seg_off = C.L.seg_off;
             N.node_off = C.L.node_off;
-            if (!size_pairs) launch_near_count(N, st);
-            launch_near_fill(N, st);
+            launch_near_count(N, st);
+            if (size_pairs) {
+                if (!ws->near_ev) DD_HIP(hipEventCreateWithFlags(&ws->near_ev, hipEventDisableTiming));
+                count_host = (int64_t *)((char *)ws->flags_host + 64);
+                DD_HIP(hipMemcpyAsync(count_host, N.woff + N.n_waves, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+                DD_HIP(hipEventRecord(ws->near_ev, st));
+            }
         }
         if (C.n_items > 0) {
             timing_begin(st, ws->capturing);
@@ -1814,6 +1820,22 @@ int launch_forces(ForceCtx &C, Workspace *ws, const double *x, const int32_t *se
             else
                 launch_pair64(C.items, C.tiles, C.rec64, ns, C.g, C.k1, C.k2, C.partial, C.n_items, st);
             timing_end(st, ws->capturing);
+        }
+        if (C.near_on) {
+            if (size_pairs) {
+                DD_HIP(hipEventSynchronize(ws->near_ev));
+                const int64_t total = *count_host;
+                if (total < 0 || total > (int64_t)INT32_MAX)
+                    return set_error(DD_ECAPACITY, "exact band: %lld near pairs (at most %d); use a narrower band",
+                                     (long long)total, INT32_MAX);
+                int rc;
+                if ((rc = grow_near_pairs(C, ws, total))) return rc;
+                N.pair_t = C.near.pair_t;
+                N.pair_s = C.near.pair_s;
+                N.corr = C.near.corr;
+                N.pair_cap = C.near.pair_cap;
+            }
+            launch_near_fill(N, st);
         }
         hipLaunchKernelGGL(k_segment_ends, dim3(grid_for(ns, 256, INT32_MAX)), dim3(256), 0, st, C.L,
                            C.tiles, C.partial, C.rec64, C.g, sig_dev, sig_val, C.inv_mu, C.fscale,

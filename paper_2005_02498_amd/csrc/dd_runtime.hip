@@ -188,6 +188,7 @@ int dd_shutdown(void)
         if (w->flags_dev) (void)hipFree(w->flags_dev);
         if (w->flags_host) (void)hipHostFree(w->flags_host);
         if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
+        if (w->near_ev) (void)hipEventDestroy(w->near_ev);
         delete w;
         w = nullptr;
     }
