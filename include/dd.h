@@ -219,8 +219,11 @@ int dd_vector_peak(int kind, int reps, double *tflops, void *stream);
  *  selects about 4 to 16 near sources per segment in dislocation loops.  The
  *  self pair is never included; the correction is float64 with either
  *  precision.  0 turns the band off.  With the band on, the call counts the
- *  near pairs first and synchronises the stream once to size its pair store
- *  (any number of near sources per segment; at most 2^31 - 1 near pairs).
+ *  near pairs first and waits once for that count (an event recorded on the
+ *  stream after the count pass; the pair kernel is already queued behind it)
+ *  to size its pair store, so the call returns only once the count pass has
+ *  finished (any number of near sources per segment; at most 2^31 - 1 near
+ *  pairs).
  * Arguments: x [3][n_nodes], seg_nodes [2][n_segs], burgers [3][n_segs];
  *  normal [3][n_segs] is validated (unit length) but unused by the force;
  *  sigma_app host [6]; m host; 1 <= n_gauss <= DD_MAX_GAUSS; precision a
