@@ -231,3 +231,20 @@ def test_pta_step_with_band():
         for k in ("lp_a", "lp_b"):
             r = np.asarray(ref[k])
             assert np.abs(got[k][i] - r).max() <= 1e-10 * np.abs(r).max(), k
+
+
+def test_band_with_validation_off_same_result():
+    """With validation off the call waits only for the near-pair count (an
+    event behind which the pair kernel is already queued) before sizing the
+    pair store and writing the list: the forces equal those of the
+    synchronised call, bit for bit, for two bands in a row."""
+    inst = W.subset(W.config1(), 20)
+    for eta in (2.0, 5.0):
+        with band(eta):
+            F_on = _gpu(inst)
+            prev = dd.dd_set_validation(False)
+            try:
+                F_off = _gpu(inst)
+            finally:
+                dd.dd_set_validation(prev)
+        assert np.array_equal(F_on, F_off), eta
